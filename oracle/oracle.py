@@ -1,0 +1,228 @@
+"""ctypes binding of the C oracle (oracle/soup_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+leg of the benchmark call it; the product path never does.
+
+All functions take a ``workloads.Scene`` and a ``workloads.View`` (plain
+numpy containers) and return numpy arrays. Gradients come back as float64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsoup_oracle.so")
+
+BG_KEY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+class _Scene(C.Structure):
+    _fields_ = [("T", C.c_int32), ("G", C.c_int32), ("C", C.c_int32), ("n_layers", C.c_int32),
+                ("dims", C.POINTER(C.c_int32)), ("verts", C.c_void_p), ("feats", C.c_void_p),
+                ("mlp", C.c_void_p)]
+
+
+class _View(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("view_id", C.c_uint32), ("M", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("mode", C.c_int32),
+                ("background", C.c_float * 3), ("edge_pairs", C.c_int32), ("near_w", C.c_float),
+                ("analysis", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("covered_pixels", C.c_int64), ("covering_fragments", C.c_int64),
+                ("decodes", C.c_int64), ("winners", C.c_int64), ("front_fragments", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.orc_forward.argtypes = [P, P, P, P, P, P, P]
+        L.orc_backward.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        L.orc_forward_pixels.argtypes = [P, P, P, C.c_int64, P, P, P, P]
+        L.orc_backward_pixels.argtypes = [P, P, P, C.c_int64, P, P, P, P, P, P]
+        L.orc_pixel_fragments.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_color_f64.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P]
+        L.orc_exp.argtypes = [C.c_float]
+        L.orc_exp.restype = C.c_float
+        L.orc_sigmoid.argtypes = [C.c_float]
+        L.orc_sigmoid.restype = C.c_float
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.orc_uniform.restype = C.c_float
+        L.orc_count_valid.argtypes = [P, P, P]
+        L.orc_count_valid.restype = C.c_int64
+        L.orc_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class _Keep:
+    """Holds the numpy buffers the C structs point to."""
+
+    def __init__(self, scene, view, opts):
+        self.verts = np.ascontiguousarray(scene.verts, dtype=np.float32)
+        self.feats = np.ascontiguousarray(scene.feats, dtype=np.float32)
+        self.mlp = np.ascontiguousarray(scene.mlp, dtype=np.float32)
+        self.dims = np.ascontiguousarray(np.asarray(scene.dims, dtype=np.int32))
+        self.M = np.ascontiguousarray(view.M, dtype=np.float32)
+        self.s = _Scene(self.verts.shape[0], self.feats.shape[1], self.feats.shape[3],
+                        len(scene.dims) - 1, self.dims.ctypes.data_as(C.POINTER(C.c_int32)),
+                        self.verts.ctypes.data, self.feats.ctypes.data, self.mlp.ctypes.data)
+        self.v = _View(view.width, view.height, view.view_id, self.M.ctypes.data)
+        self.o = _Opts(opts.seed, opts.step, opts.mode, (C.c_float * 3)(*opts.background),
+                       opts.edge_pairs, opts.near_w, opts.analysis)
+
+    def args(self):
+        return C.byref(self.s), C.byref(self.v), C.byref(self.o)
+
+
+class Opts:
+    def __init__(self, seed: int = 0, step: int = 0, mode: int = 0, background=(0.0, 0.0, 0.0),
+                 edge_pairs: int = 0, near_w: float = 0.1, analysis: int = 0):
+        self.seed, self.step, self.mode = int(seed), int(step), int(mode)
+        self.background = tuple(float(b) for b in background)
+        self.edge_pairs, self.near_w, self.analysis = int(edge_pairs), float(near_w), int(analysis)
+
+
+def n_params(dims: Sequence[int]) -> int:
+    return int(sum(o * i + o for i, o in zip(dims[:-1], dims[1:])))
+
+
+def forward(scene, view, opts: Opts, want_logp: bool = True):
+    k = _Keep(scene, view, opts)
+    H, W = view.height, view.width
+    vis = np.empty(H * W, np.uint64)
+    color = np.empty(H * W * 3, np.float32)
+    logp = np.empty(H * W, np.float64) if want_logp else None
+    st = _Stats()
+    rc = lib().orc_forward(*k.args(), _ptr(vis), _ptr(color), _ptr(logp) if want_logp else None,
+                           C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle forward rejected its arguments")
+    stats = {f: int(getattr(st, f)) for f, _ in _Stats._fields_}
+    return (vis.reshape(H, W), color.reshape(H, W, 3),
+            logp.reshape(H, W) if want_logp else None, stats)
+
+
+def backward(scene, view, opts: Opts, vis, color, grad_color, grad_logp=None):
+    k = _Keep(scene, view, opts)
+    T, G, Cc = scene.verts.shape[0], scene.feats.shape[1], scene.feats.shape[3]
+    gv = np.zeros(T * 9, np.float64)
+    gf = np.zeros(T * G * G * Cc, np.float64)
+    gm = np.zeros(n_params(scene.dims), np.float64)
+    vis = np.ascontiguousarray(vis, dtype=np.uint64).ravel()
+    color = np.ascontiguousarray(color, dtype=np.float32).ravel()
+    gc = np.ascontiguousarray(grad_color, dtype=np.float32).ravel()
+    gl = None if grad_logp is None else np.ascontiguousarray(grad_logp, dtype=np.float32).ravel()
+    rc = lib().orc_backward(*k.args(), _ptr(vis), _ptr(color), _ptr(gc),
+                            _ptr(gl) if gl is not None else None, _ptr(gv), _ptr(gf), _ptr(gm))
+    if rc != 0:
+        raise ValueError("oracle backward rejected its arguments")
+    return gv.reshape(T, 3, 3), gf.reshape(T, G, G, Cc), gm
+
+
+def forward_pixels(scene, view, opts: Opts, xy: np.ndarray):
+    k = _Keep(scene, view, opts)
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    vis = np.empty(n, np.uint64)
+    color = np.empty(n * 3, np.float32)
+    logp = np.empty(n, np.float64)
+    rc = lib().orc_forward_pixels(*k.args(), n, _ptr(xy), _ptr(vis), _ptr(color), _ptr(logp))
+    if rc != 0:
+        raise ValueError("oracle forward_pixels rejected its arguments")
+    return vis, color.reshape(n, 3), logp
+
+
+def backward_pixels(scene, view, opts: Opts, xy, grad_color, grad_logp=None):
+    k = _Keep(scene, view, opts)
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    T, G, Cc = scene.verts.shape[0], scene.feats.shape[1], scene.feats.shape[3]
+    gv = np.zeros(T * 9, np.float64)
+    gf = np.zeros(T * G * G * Cc, np.float64)
+    gm = np.zeros(n_params(scene.dims), np.float64)
+    gc = np.ascontiguousarray(grad_color, dtype=np.float32).reshape(-1)
+    gl = None if grad_logp is None else np.ascontiguousarray(grad_logp, dtype=np.float32).reshape(-1)
+    rc = lib().orc_backward_pixels(*k.args(), n, _ptr(xy), _ptr(gc),
+                                   _ptr(gl) if gl is not None else None, _ptr(gv), _ptr(gf), _ptr(gm))
+    if rc != 0:
+        raise ValueError("oracle backward_pixels rejected its arguments")
+    return gv.reshape(T, 3, 3), gf.reshape(T, G, G, Cc), gm
+
+
+def pixel_fragments(scene, view, opts: Opts, x: int, y: int, cap: int = 4096):
+    k = _Keep(scene, view, opts)
+    tri = np.zeros(cap, np.uint32)
+    key = np.zeros(cap, np.uint64)
+    alpha = np.zeros(cap, np.float32)
+    o3 = np.zeros(cap, np.float32)
+    u = np.zeros(cap, np.float32)
+    dl = np.zeros(cap, np.float64)
+    win = C.c_int32(0)
+    n = lib().orc_pixel_fragments(*k.args(), x, y, cap, _ptr(tri), _ptr(key), _ptr(alpha), _ptr(o3),
+                                  _ptr(u), _ptr(dl), C.byref(win))
+    if n < 0:
+        raise ValueError("oracle pixel_fragments rejected its arguments")
+    m = min(n, cap)
+    return dict(n=n, tri=tri[:m], key=key[:m], alpha=alpha[:m], o3=o3[:m], u=u[:m],
+                dlogit=dl[:m], winner=int(win.value))
+
+
+def color_f64(scene, view, opts: Opts, tri: int, x: int, y: int):
+    k = _Keep(scene, view, opts)
+    rgb = np.zeros(3, np.float64)
+    a = C.c_double(0)
+    rc = lib().orc_color_f64(*k.args(), tri, x, y, _ptr(rgb), C.byref(a))
+    if rc < 0:
+        raise ValueError("bad arguments")
+    return (rgb, a.value) if rc == 1 else (None, None)
+
+
+def exp(x: float) -> float:
+    return float(lib().orc_exp(x))
+
+
+def sigmoid(x: float) -> float:
+    return float(lib().orc_sigmoid(x))
+
+
+def philox(ctr, key):
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(seed: int, pixel: int, tri: int, view_id: int, step: int) -> float:
+    return float(lib().orc_uniform(seed, pixel, tri, view_id, step))
+
+
+def count_valid(scene, view, opts: Opts) -> int:
+    k = _Keep(scene, view, opts)
+    return int(lib().orc_count_valid(*k.args()))
+
+
+def threads() -> int:
+    return int(lib().orc_threads())

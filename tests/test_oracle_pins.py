@@ -1,0 +1,678 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU. None of them retypes the oracle's own
+formulas: each compares the oracle with an independent statement (exact
+rational geometry, ray casting, closed forms of Eq. (6), (8), (9) and
+(A2)-(A9), finite differences, a library routine, published known answers).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_27151_amd import workloads as W
+from tests import geometry as geo
+from tests import scenes as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 and the uniform draw (Eq. (5): tau ~ U[0,1] per fragment)
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = O.philox(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_uniform_draws_are_uniform_and_independent():
+    n = 1 << 16
+    u = np.array([O.uniform(0x5EED0001, i, 7, 3, 0) for i in range(n)])
+    assert u.min() >= 0.0 and u.max() <= 1.0 - 2.0 ** -24
+    assert np.all(u * 2 ** 24 == np.floor(u * 2 ** 24))            # 24-bit grid
+    hist, _ = np.histogram(u, bins=64, range=(0, 1))
+    chi2 = ((hist - n / 64) ** 2 / (n / 64)).sum()
+    assert chi2 < 63 + 6 * math.sqrt(2 * 63)                      # ~6 sigma
+    r = np.corrcoef(u[:-1], u[1:])[0, 1]
+    assert abs(r) < 6 / math.sqrt(n)
+    # a different triangle, view or step gives an unrelated stream
+    v = np.array([O.uniform(0x5EED0001, i, 8, 3, 0) for i in range(4096)])
+    assert abs(np.corrcoef(u[:4096], v)[0, 1]) < 6 / math.sqrt(4096)
+
+
+# --------------------------------------------------------------------------
+# exp / sigmoid of the float32 contract
+# --------------------------------------------------------------------------
+
+def _ulp_err(got, ref):
+    ref32 = np.float32(ref)
+    sp = np.spacing(np.abs(ref32)).astype(np.float64)
+    return abs(float(got) - ref) / sp
+
+
+def test_exp_within_two_ulp_of_double_exp():
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([np.linspace(-87.0, 88.0, 20001), rng.uniform(-87, 88, 20000),
+                         rng.uniform(-1, 1, 20000)]).astype(np.float32)
+    worst = 0.0
+    for x in xs:
+        ref = math.exp(float(x))
+        if ref < 1.1754944e-38:       # denormal results: absolute check
+            assert abs(O.exp(float(x)) - ref) < 2 * 1.4e-45 * 4
+            continue
+        worst = max(worst, _ulp_err(O.exp(float(x)), ref))
+    assert worst <= 2.0, worst
+
+
+def test_exp_and_sigmoid_special_values():
+    assert O.exp(0.0) == 1.0
+    assert O.exp(100.0) == math.inf
+    assert O.exp(-100.0) == 0.0
+    assert math.isnan(O.exp(float("nan")))
+    assert O.sigmoid(0.0) == 0.5
+    assert O.sigmoid(30.0) == 1.0       # alpha rounds to exactly one
+    assert O.sigmoid(-200.0) == 0.0
+    xs = np.linspace(-20, 20, 4001).astype(np.float32)
+    s = np.array([O.sigmoid(float(x)) for x in xs])
+    assert np.all(np.diff(s) >= 0)
+    ref = 1 / (1 + np.exp(-xs.astype(np.float64)))
+    assert np.max(np.abs(s - ref) / ref) < 4e-7
+
+
+# --------------------------------------------------------------------------
+# Coverage: pixel-centre samples of Eq. (1)
+# --------------------------------------------------------------------------
+
+def _oracle_coverage(scene, view, t):
+    """Pixels whose sorted fragment list contains triangle t."""
+    vis, _, _, _ = O.forward(scene, view, O.Opts(mode=1))
+    out = set()
+    for y in range(view.height):
+        for x in range(view.width):
+            fr = O.pixel_fragments(scene, view, O.Opts(mode=1), x, y)
+            if t in set(int(v) for v in fr["tri"]):
+                out.add((x, y))
+    return out
+
+
+def _rand_snapped_tris(rng, n, Wd, Hd, lo=-2, hi=None, grid=False):
+    hi = hi if hi is not None else Wd + 2
+    tris = []
+    while len(tris) < n:
+        if grid:     # vertices exactly on pixel centres / half pixels: many ties
+            v = rng.integers(lo * 2, hi * 2, (3, 2)) * 128
+        else:
+            v = rng.integers(lo * 256, hi * 256, (3, 2))
+        a = (v[1, 0] - v[0, 0]) * (v[2, 1] - v[0, 1]) - (v[1, 1] - v[0, 1]) * (v[2, 0] - v[0, 0])
+        if a != 0:
+            tris.append(v)
+    return tris
+
+
+@pytest.mark.parametrize("grid", [False, True])
+def test_coverage_matches_exact_rational_point_in_triangle(grid):
+    rng = np.random.default_rng(11 + grid)
+    Wd = Hd = 12
+    view = S.ortho_view(Wd, Hd)
+    for v in _rand_snapped_tris(rng, 12, Wd, Hd, grid=grid):
+        tri = S.tri_world([(x / 256.0, y / 256.0) for x, y in v], 0.0, Wd, Hd)
+        scene = S.passthrough_scene([tri], logit=[40.0])
+        want = geo.coverage_rational([tuple(p) for p in v], Wd, Hd)
+        vis, _, _, _ = O.forward(scene, view, O.Opts(mode=1))
+        got = {(x, y) for y in range(Hd) for x in range(Wd) if vis[y, x] != O.BG_KEY}
+        assert got == want
+
+
+def test_watertight_mesh_covers_each_centre_once():
+    rng = np.random.default_rng(5)
+    Wd = Hd = 24
+    view = S.ortho_view(Wd, Hd)
+    n = 4
+    # jittered grid of shared vertices, some exactly on pixel centres
+    gx = np.linspace(2, 22, n + 1)
+    P = np.zeros((n + 1, n + 1, 2))
+    for i in range(n + 1):
+        for j in range(n + 1):
+            jit = rng.integers(-200, 200, 2) if 0 < i < n and 0 < j < n else (0, 0)
+            P[i, j] = (gx[j] * 256 + jit[0], gx[i] * 256 + jit[1])
+    P[2, 2] = (10.5 * 256, 10.5 * 256)   # a vertex on a pixel centre
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = P[i, j], P[i, j + 1], P[i + 1, j + 1], P[i + 1, j]
+            tris.append([a, b, c])
+            tris.append([a, c, d])
+    world = [S.tri_world([(p[0] / 256, p[1] / 256) for p in t], 0.0, Wd, Hd) for t in tris]
+    scene = S.passthrough_scene(world, logit=[40.0] * len(world))
+    cover = np.zeros((Hd, Wd), int)
+    for t in range(len(world)):
+        cov = geo.coverage_rational([tuple(int(c) for c in p) for p in tris[t]], Wd, Hd)
+        for (x, y) in cov:
+            cover[y, x] += 1
+    # rational classification: each centre of the union at most once
+    assert cover.max() == 1
+    # the oracle covers exactly the same pixels, each by exactly one fragment
+    for y in range(Hd):
+        for x in range(Wd):
+            fr = O.pixel_fragments(scene, view, O.Opts(mode=1), x, y)
+            assert fr["n"] == cover[y, x], (x, y)
+    # interior pixel centres of the square [2,22)^2 are all covered
+    assert cover[3:21, 3:21].min() == 1
+
+
+def test_rectangle_lattice_count():
+    Wd, Hd = 20, 16
+    view = S.ortho_view(Wd, Hd)
+    x0, y0, x1, y1 = 3, 2, 15, 11
+    a = (x0 + 0.5, y0 + 0.5)
+    b = (x1 + 0.5, y0 + 0.5)
+    c = (x1 + 0.5, y1 + 0.5)
+    d = (x0 + 0.5, y1 + 0.5)
+    tris = [S.tri_world([a, b, c], 0.0, Wd, Hd), S.tri_world([a, c, d], 0.0, Wd, Hd)]
+    scene = S.passthrough_scene(tris, logit=[40.0, 40.0])
+    vis, _, _, _ = O.forward(scene, view, O.Opts(mode=1))
+    cov = vis != O.BG_KEY
+    # half-open rectangle [x0, x1) x [y0, y1) under the (1, +eps) tie rule
+    want = np.zeros_like(cov)
+    want[y0:y1, x0:x1] = True
+    assert np.array_equal(cov, want)
+    assert cov.sum() == (x1 - x0) * (y1 - y0)
+
+
+def test_full_screen_quad_and_offscreen_culling():
+    Wd, Hd = 16, 9
+    view = S.ortho_view(Wd, Hd)
+    q = [(-1, -1), (1, -1), (1, 1), (-1, 1)]
+    mk = lambda p: np.array([[p[0][0], p[0][1], 0], [p[1][0], p[1][1], 0], [p[2][0], p[2][1], 0]], np.float32)
+    tris = [mk([q[0], q[1], q[2]]), mk([q[0], q[2], q[3]]),
+            mk([(3, 3), (4, 3), (3, 4)]),                     # entirely off screen
+            mk([(0, 0), (0.5, 0.5), (1, 1)])]                 # degenerate
+    scene = S.passthrough_scene(tris, logit=[40.0] * 4)
+    vis, _, _, st = O.forward(scene, view, O.Opts(mode=1))
+    assert st["covering_fragments"] == Wd * Hd
+    assert np.all(vis != O.BG_KEY)
+    assert O.count_valid(scene, view, O.Opts()) == 2
+
+
+# --------------------------------------------------------------------------
+# Visibility: Eq. (2) (alpha = 1 reduces masking to a z-buffer) and Eq. (3)
+# --------------------------------------------------------------------------
+
+def test_alpha_one_is_an_ordinary_z_buffer():
+    rng = np.random.default_rng(3)
+    Wd = Hd = 24
+    view = S.ortho_view(Wd, Hd)
+    n = 10
+    zs = rng.permutation(np.linspace(-0.75, 0.75, n))
+    tris, verts = [], []
+    for (v, z) in zip(_rand_snapped_tris(rng, n, Wd, Hd, lo=0, hi=Wd), zs):
+        tris.append(v)
+        verts.append(S.tri_world([(x / 256.0, y / 256.0) for x, y in v], z, Wd, Hd))
+    scene = S.passthrough_scene(verts, logit=[30.0] * n)      # sigmoid(30) == 1.0f
+    vis, _, _, _ = O.forward(scene, view, O.Opts(seed=99))
+    covers = [geo.coverage_rational([tuple(p) for p in v], Wd, Hd) for v in tris]
+    for y in range(Hd):
+        for x in range(Wd):
+            cand = [t for t in range(n) if (x, y) in covers[t]]
+            if not cand:
+                assert vis[y, x] == O.BG_KEY
+                continue
+            t = min(cand, key=lambda t: zs[t])
+            assert int(vis[y, x]) & 0xFFFFFFFF == t
+            z01 = np.float32(np.float32(zs[t]) * np.float32(0.5) + np.float32(0.5))
+            # depth = sum of beta_i z01 with float rounding: within a few ulp
+            assert abs((int(vis[y, x]) >> 32) - int(z01.view(np.uint32))) <= 4
+
+
+def test_threshold_mode_is_eq3_argmin():
+    w = W.tiny(with_targets=False)
+    view = w.views[0]
+    vis, color, _, _ = O.forward(w.scene, view, O.Opts(mode=1))
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        x, y = int(rng.integers(0, 128)), int(rng.integers(0, 128))
+        fr = O.pixel_fragments(w.scene, view, O.Opts(mode=1), x, y)
+        keys = [int(k) for k, o3 in zip(fr["key"], fr["o3"]) if o3 > 0]
+        want = min(keys) if keys else int(O.BG_KEY)
+        assert int(vis[y, x]) == want
+        assert fr["n"] == 0 or np.all(np.diff(fr["key"].astype(np.float64)) >= 0)
+
+
+def test_stochastic_winner_is_first_passing_fragment():
+    w = W.tiny(with_targets=False)
+    view = w.views[0]
+    o = O.Opts(seed=w.seed)
+    vis, _, logp, _ = O.forward(w.scene, view, o)
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        x, y = int(rng.integers(0, 128)), int(rng.integers(0, 128))
+        fr = O.pixel_fragments(w.scene, view, o, x, y)
+        # Eq. (5): argmin of D over fragments with alpha > tau
+        passing = [int(k) for k, a, u in zip(fr["key"], fr["alpha"], fr["u"]) if u < a]
+        want = min(passing) if passing else int(O.BG_KEY)
+        assert int(vis[y, x]) == want
+        # log p(f*) of Eq. (6)/(A2)
+        if fr["n"]:
+            wi = fr["winner"]
+            a = fr["alpha"].astype(np.float64)
+            lp = np.log1p(-a[:wi]).sum() + np.log(a[wi]) if wi >= 0 else np.log1p(-a).sum()
+            assert abs(logp[y, x] - lp) < 1e-12 * max(1, abs(lp))
+        # independent of every other pixel: draws depend on (pixel, tri, view, step) only
+        u2 = [O.uniform(w.seed, y * 128 + x, int(t), 0, 0) for t in fr["tri"]]
+        assert np.array_equal(np.array(u2, np.float32), fr["u"])
+
+
+# --------------------------------------------------------------------------
+# Depth, barycentrics, bilinear fetch, MLP
+# --------------------------------------------------------------------------
+
+def _ray_bary(M, verts, x, y, Wd, Hd):
+    """Barycentric coordinates (of v1, v2) of the world point seen at the
+    centre of pixel (x, y), by intersecting the pixel ray with the plane."""
+    Minv = np.linalg.inv(M.astype(np.float64))
+    ndc_x = (x + 0.5) / (Wd / 2) - 1
+    ndc_y = 1 - (y + 0.5) / (Hd / 2)
+    p0 = Minv @ np.array([ndc_x, ndc_y, -1, 1.0])
+    p1 = Minv @ np.array([ndc_x, ndc_y, 1, 1.0])
+    p0, p1 = p0[:3] / p0[3], p1[:3] / p1[3]
+    v = verts.astype(np.float64)
+    n = np.cross(v[1] - v[0], v[2] - v[0])
+    t = np.dot(n, v[0] - p0) / np.dot(n, p1 - p0)
+    q = p0 + t * (p1 - p0)
+    A = np.stack([v[1] - v[0], v[2] - v[0]], 1)
+    l, *_ = np.linalg.lstsq(A, q - v[0], rcond=None)
+    return l
+
+
+@pytest.mark.parametrize("which", [1, 2])
+def test_perspective_correct_barycentrics_match_ray_casting(which):
+    Wd = Hd = 96
+    M = W.view_proj((0.3, 0.2, 3.0), Wd, Hd)
+    view = W.View(Wd, Hd, 0, M)
+    # a strongly slanted triangle: screen-linear interpolation would be far off
+    tri = np.array([[-1.2, -0.9, 0.8], [1.1, -0.7, -1.6], [-0.2, 1.0, -0.4]], np.float32)
+    G, C = 4, 8
+    feats = np.zeros((1, G, G, C), np.float32)
+    for iy in range(G):
+        for ix in range(G):
+            feats[0, iy, ix, 0] = ix if which == 1 else iy     # linear field: bilinear is exact
+    scene = W.Scene(tri[None], feats, W.passthrough_mlp(C, 16), [C, 16, 4])
+    rng = np.random.default_rng(4)
+    checked = 0
+    for _ in range(400):
+        x, y = int(rng.integers(0, Wd)), int(rng.integers(0, Hd))
+        fr = O.pixel_fragments(scene, view, O.Opts(mode=1), x, y)
+        if fr["n"] == 0:
+            continue
+        l = _ray_bary(M, tri, x, y, Wd, Hd)
+        got = float(fr["o3"][0]) / (G - 1)
+        assert abs(got - l[which - 1]) < 2e-4, (x, y, got, l)
+        checked += 1
+    assert checked > 50
+
+
+def test_mlp_decode_matches_float64_matmul():
+    rng = np.random.default_rng(8)
+    Wd = Hd = 16
+    view = S.ortho_view(Wd, Hd)
+    dims = [16, 32, 32, 4]
+    mlp = W.glorot_mlp(rng, dims)
+    mlp += rng.normal(0, 0.1, mlp.shape).astype(np.float32)           # nonzero biases too
+    x = rng.normal(0, 1, 16).astype(np.float32)
+    G = 5
+    feats = np.broadcast_to(x, (1, G, G, 16)).copy()
+    tri = S.tri_world([(0, 0), (16, 0), (0, 16)], 0.0, Wd, Hd)
+    scene = W.Scene(tri[None], feats, mlp, dims)
+    # float64 reference with numpy's matmul
+    h = x.astype(np.float64)
+    off = 0
+    for l, (i, o) in enumerate(zip(dims[:-1], dims[1:])):
+        Wl = mlp[off:off + o * i].reshape(o, i).astype(np.float64)
+        bl = mlp[off + o * i:off + o * i + o].astype(np.float64)
+        off += o * i + o
+        h = Wl @ h + bl
+        if l < len(dims) - 2:
+            h = np.maximum(h, 0)
+    vis, color, _, _ = O.forward(scene, view, O.Opts(mode=1, background=(0.25, 0.25, 0.25)))
+    for (px, py) in [(1, 1), (5, 2), (3, 7)]:
+        fr = O.pixel_fragments(scene, view, O.Opts(mode=1), px, py)
+        assert abs(fr["o3"][0] - h[3]) < 1e-5 * max(1, abs(h[3]))
+        if h[3] > 0:
+            assert np.allclose(color[py, px], 1 / (1 + np.exp(-h[:3])), rtol=2e-6)
+        else:
+            assert np.all(color[py, px] == 0.25)
+
+
+# --------------------------------------------------------------------------
+# Stochastic opacity masking: Eq. (6)/(A2), Eq. (8)/(A3-A6), Eq. (9)/(A7-A9)
+# --------------------------------------------------------------------------
+
+def _stack(alphas, rgb_logits, Wd=8, Hd=8, zs=None):
+    """Full-screen fronto-parallel squares (two triangles each) stacked at
+    increasing depth; returns scene (2 triangles per layer)."""
+    n = len(alphas)
+    zs = np.linspace(-0.5, 0.5, n) if zs is None else zs
+    tris, logits, rgbs = [], [], []
+    for k in range(n):
+        z = zs[k]
+        q = [(-1, -1), (1, -1), (1, 1), (-1, 1)]
+        for (a, b, c) in [(0, 1, 2), (0, 2, 3)]:
+            tris.append(np.array([[*q[a], z], [*q[b], z], [*q[c], z]], np.float32))
+            logits.append(S.logit(alphas[k]))
+            rgbs.append(rgb_logits[k])
+    return S.passthrough_scene(tris, logit=logits, rgb_logits=rgbs)
+
+
+def _layer_alpha(scene):
+    return np.array([O.sigmoid(float(l)) for l in scene.feats[::2, 0, 0, 0]], np.float64)
+
+
+def test_selection_probability_matches_eq6_chi2():
+    alphas = [0.3, 0.55, 0.7, 0.2]
+    scene = _stack(alphas, [(0, 0, 0)] * 4)
+    view = S.ortho_view(16, 16)
+    a = _layer_alpha(scene)
+    p = [np.prod(1 - a[:k]) * a[k] for k in range(4)] + [np.prod(1 - a)]
+    counts = np.zeros(5)
+    n_steps = 80
+    for step in range(n_steps):
+        vis, _, _, _ = O.forward(scene, view, O.Opts(seed=1234, step=step))
+        tri = (vis & np.uint64(0xFFFFFFFF)).astype(np.int64).ravel()
+        bg = vis.ravel() == O.BG_KEY
+        counts[4] += bg.sum()
+        layer = tri[~bg] // 2
+        for k in range(4):
+            counts[k] += (layer == k).sum()
+    N = counts.sum()
+    exp_ = N * np.array(p)
+    chi2 = ((counts - exp_) ** 2 / exp_).sum()
+    assert abs(sum(p) - 1) < 1e-12
+    assert chi2 < 4 + 6 * math.sqrt(8), (counts, exp_)
+
+
+def test_score_values_are_eq9():
+    alphas = [0.35, 0.3, 0.45, 0.25]      # background has probability 0.19
+    scene = _stack(alphas, [(0, 0, 0)] * 4, Wd=4, Hd=4)
+    view = S.ortho_view(4, 4)
+    a = _layer_alpha(scene)
+    seen_bg = seen_win = False
+    for step in range(40):
+        o = O.Opts(seed=77, step=step, edge_pairs=2)
+        vis, color, _, _ = O.forward(scene, view, o)
+        x, y = 1, 2
+        gl = np.zeros((4, 4), np.float32)
+        gl[y, x] = 1.0
+        _, gf, _ = O.backward(scene, view, o, vis, color, np.zeros((4, 4, 3), np.float32), gl)
+        d = gf[:, :, :, 0].sum(axis=(1, 2))            # d logit per triangle
+        key = int(vis[y, x])
+        win_layer = None if key == int(O.BG_KEY) else (key & 0xFFFFFFFF) // 2
+        tri_here = [int(t) for t in O.pixel_fragments(scene, view, o, x, y)["tri"]]
+        want = np.zeros(len(d))
+        for k in range(4):
+            t = [tt for tt in tri_here if tt // 2 == k][0]
+            if win_layer is None or k < win_layer:
+                want[t] = -1.0 / (1 - a[k]) * a[k] * (1 - a[k])     # Eq. (9), f' in front
+            elif k == win_layer:
+                want[t] = 1.0 / a[k] * a[k] * (1 - a[k])            # Eq. (9), f' = f
+        assert np.allclose(d, want, rtol=1e-12, atol=1e-15)
+        seen_bg |= win_layer is None
+        seen_win |= win_layer is not None
+    assert seen_win and seen_bg
+
+
+def test_estimator_is_unbiased_for_expected_loss():
+    """Mean of the estimator over independent draws vs the exact derivative
+    of E_p[L] = sum_f p(f) L(C_f) (Eq. (7)-(8), (A3)-(A6))."""
+    alphas = [0.4, 0.6, 0.55]      # logit 0 would sit on the ReLU kink of the pass-through MLP
+    rgb_l = [(1.0, -0.5, 0.2), (-1.0, 0.8, 0.1), (0.3, 0.3, -1.2)]   # no logit on the ReLU kink
+    scene = _stack(alphas, rgb_l)
+    Wd = Hd = 32
+    view = S.ortho_view(Wd, Hd)
+    a = _layer_alpha(scene)
+    col = np.array([[O.sigmoid(float(v)) for v in r] for r in rgb_l], np.float64)
+    target = np.array([0.2, 0.7, 0.4])
+    bg = np.zeros(3)
+    Lf = list(((col - target) ** 2).sum(1)) + [float(((bg - target) ** 2).sum())]
+    n = 3
+    p = [np.prod(1 - a[:k]) * a[k] for k in range(n)] + [np.prod(1 - a)]
+    # exact gradients of E[L] with respect to each layer's opacity logit
+    dlogit = np.zeros(n)
+    for t in range(n):
+        dE = 0.0
+        for f in range(n + 1):
+            if f == t:
+                dE += Lf[f] * p[f] / a[t]
+            elif f > t:                        # t in front of f (or of the background)
+                dE -= Lf[f] * p[f] / (1 - a[t])
+        dlogit[t] = dE * a[t] * (1 - a[t])
+    # and with respect to each layer's RGB logits (colour path)
+    drgb = np.array([p[t] * 2 * (col[t] - target) * col[t] * (1 - col[t]) for t in range(n)])
+
+    samples_l, samples_c = [], []
+    for step in range(24):
+        o = O.Opts(seed=4242, step=step, edge_pairs=2)
+        vis, color, _, _ = O.forward(scene, view, o)
+        c = color.astype(np.float64)
+        gC = (2 * (c - target)).astype(np.float32)
+        gL = ((c - target) ** 2).sum(-1).astype(np.float32)
+        # one pixel at a time would be slow: every pixel is an independent
+        # sample, and the backward sums them; per-pixel variance is estimated
+        # from the per-step sums
+        _, gf, _ = O.backward(scene, view, o, vis, color, gC, gL)
+        per_layer_l = gf[:, :, :, 0].sum(axis=(1, 2)).reshape(n, 2).sum(1) / (Wd * Hd)
+        per_layer_c = gf[:, :, :, 1:4].sum(axis=(1, 2)).reshape(n, 2, 3).sum(1) / (Wd * Hd)
+        samples_l.append(per_layer_l)
+        samples_c.append(per_layer_c)
+    sl = np.array(samples_l)
+    sc = np.array(samples_c)
+    se_l = sl.std(0, ddof=1) / math.sqrt(len(sl))
+    se_c = sc.std(0, ddof=1) / math.sqrt(len(sc))
+    assert np.all(np.abs(sl.mean(0) - dlogit) < 5 * se_l + 1e-9), (sl.mean(0), dlogit, se_l)
+    assert np.all(np.abs(sc.mean(0) - drgb) < 5 * se_c + 1e-9), (sc.mean(0), drgb, se_c)
+
+
+# --------------------------------------------------------------------------
+# Colour-path gradients (Algorithm A1, 2(a)) by finite differences
+# --------------------------------------------------------------------------
+
+def _fd_scene():
+    rng = np.random.default_rng(21)
+    dims = [8, 16, 4]
+    mlp = W.glorot_mlp(rng, dims)
+    mlp[-1] = 40.0                                   # opacity bias: alpha == 1
+    mlp[-4:-1] = rng.normal(0, 0.3, 3).astype(np.float32)
+    tris = np.array([[[-0.9, -0.8, 0.2], [0.8, -0.6, -0.5], [-0.1, 0.9, 0.1]],
+                     [[-0.5, -0.2, 0.9], [0.6, 0.1, 0.7], [0.0, 0.7, 1.1]]], np.float32)
+    feats = rng.normal(0, 0.5, (2, 4, 4, 8)).astype(np.float32)
+    return W.Scene(tris, feats, mlp, dims)
+
+
+def test_colour_gradients_match_finite_differences():
+    scene = _fd_scene()
+    Wd = Hd = 48
+    view = W.View(Wd, Hd, 0, W.view_proj((0.2, 0.1, 3.0), Wd, Hd))
+    o = O.Opts(seed=5, edge_pairs=2, analysis=1)
+    vis, color, _, _ = O.forward(scene, view, o)
+    rng = np.random.default_rng(6)
+    g = np.array([0.7, -0.4, 1.1])
+    tested = 0
+    for (x, y) in [(24, 24), (20, 30), (30, 18), (14, 26), (27, 27)]:
+        key = int(vis[y, x])
+        if key == int(O.BG_KEY):
+            continue
+        t = key & 0xFFFFFFFF
+        gc = np.zeros((Hd, Wd, 3), np.float32)
+        gc[y, x] = g
+        gv, gf, gm = O.backward(scene, view, o, vis, color, gc, None)
+
+        def f(sc):
+            rgb, _ = O.color_f64(sc, view, o, t, x, y)
+            return float(np.dot(g, rgb))
+
+        def fd(arr_name, idx, h):
+            sc = W.Scene(scene.verts.copy(), scene.feats.copy(), scene.mlp.copy(), scene.dims)
+            arr = getattr(sc, arr_name)
+            base = float(arr[idx])
+            arr[idx] = np.float32(base + h)
+            hp = float(arr[idx]) - base
+            fp = f(sc)
+            arr[idx] = np.float32(base - h)
+            hm = base - float(arr[idx])
+            fm = f(sc)
+            return (fp - fm) / (hp + hm)
+
+        # float32 parameters: the step is what float32 can represent; the
+        # colour is float64 in the analysis path
+        for i in range(3):
+            for k in range(3):
+                num = fd("verts", (t, i, k), 2e-3)
+                assert abs(num - gv[t, i, k]) < 2e-3 * (abs(num) + 1e-3), ("v", t, i, k, num, gv[t, i, k])
+        fi = np.argwhere(np.abs(gf[t]) > 0)
+        for idx in fi[rng.choice(len(fi), min(12, len(fi)), replace=False)]:
+            num = fd("feats", (t, *idx), 1e-4)
+            assert abs(num - gf[(t, *idx)]) < 1e-4 * (abs(num) + 1e-3)
+        for j in rng.choice(len(scene.mlp), 25, replace=False):
+            num = fd("mlp", (int(j),), 1e-4)     # small step: stays off the ReLU kinks
+            assert abs(num - gm[j]) < 1e-4 * (abs(num) + 1e-3), ("mlp", j, num, gm[j])
+        tested += 1
+    assert tested >= 3
+
+
+def test_snapped_gradients_are_close_to_unsnapped():
+    """Straight-through snapping: the default backward evaluates at snapped
+    positions; it differs from the float64 unsnapped derivative only by the
+    1/256 px snap."""
+    scene = _fd_scene()
+    Wd = Hd = 48
+    view = W.View(Wd, Hd, 0, W.view_proj((0.2, 0.1, 3.0), Wd, Hd))
+    o0 = O.Opts(seed=5, edge_pairs=2, analysis=0)
+    o1 = O.Opts(seed=5, edge_pairs=2, analysis=1)
+    vis, color, _, _ = O.forward(scene, view, o0)
+    rng = np.random.default_rng(1)
+    gc = rng.normal(0, 1, (Hd, Wd, 3)).astype(np.float32)
+    a = O.backward(scene, view, o0, vis, color, gc, None)
+    b = O.backward(scene, view, o1, vis, color, gc, None)
+    for x, y in zip(a, b):
+        assert np.linalg.norm(x - y) <= 2e-2 * np.linalg.norm(y)
+
+
+# --------------------------------------------------------------------------
+# Edge term (Section 3.2) against the box-filtered image
+# --------------------------------------------------------------------------
+
+def _edge_grad_vs_area_fd(pts, Wd, Hd, rgb_logit, logit_fn=None, halfplane=None, seed=0):
+    """Compare the edge-term vertex gradient with finite differences of the
+    exact box-filtered image L = sum_p g_p . I_p, I_p = covered area x colour.
+    halfplane(pts) -> (a, b, c) keeps a x + b y + c >= 0 inside the triangle
+    (an opacity-induced boundary that moves with the triangle)."""
+    rng = np.random.default_rng(seed)
+    # smooth random gradient field
+    yy, xx = np.mgrid[0:Hd, 0:Wd] + 0.5
+    g = np.zeros((Hd, Wd))
+    for _ in range(4):
+        kx, ky, ph = rng.normal(0, 0.12), rng.normal(0, 0.12), rng.uniform(0, 6.3)
+        g += rng.normal() * np.cos(kx * xx + ky * yy + ph)
+    chan = np.array([1.0, -0.5, 0.25])
+    view = S.ortho_view(Wd, Hd)
+    tri = S.tri_world(pts, 0.0, Wd, Hd)
+    G = 4
+    scene = S.passthrough_scene([tri], G=G, logit=[40.0], rgb_logits=[rgb_logit])
+    if logit_fn is not None:
+        for iy in range(G):
+            for ix in range(G):
+                scene.feats[0, iy, ix, 0] = logit_fn(ix / (G - 1), iy / (G - 1))
+    col = np.array([O.sigmoid(float(v)) for v in rgb_logit])
+    o = O.Opts(seed=3, mode=1, edge_pairs=0)
+    vis, color, _, _ = O.forward(scene, view, o)
+    gc = (g[..., None] * chan).astype(np.float32)
+    gv, _, _ = O.backward(scene, view, o, vis, color, gc, None)
+
+    def L(p):
+        poly = [tuple(q) for q in p]
+        if halfplane is not None:
+            poly = geo.clip_halfplane(poly, *halfplane(p))
+        img = geo.pixel_area(poly, Wd, Hd)
+        return float((img * g).sum() * np.dot(col, chan))
+
+    h = 1e-3
+    num = np.zeros((3, 2))
+    for i in range(3):
+        for k in range(2):
+            pp = [list(q) for q in pts]
+            pm = [list(q) for q in pts]
+            pp[i][k] += h
+            pm[i][k] -= h
+            num[i, k] = (L(pp) - L(pm)) / (2 * h)
+    # screen-space FD -> world: x_w = sx/(W/2) - 1, y_w = 1 - sy/(H/2)
+    est = np.stack([gv[0, :, 0] * (2 / Wd), -gv[0, :, 1] * (2 / Hd)], 1)
+    cos = float((num * est).sum() / (np.linalg.norm(num) * np.linalg.norm(est)))
+    rel = float(np.linalg.norm(num - est) / np.linalg.norm(num))
+    return cos, rel
+
+
+@pytest.mark.parametrize("pts", [
+    [(8.3, 10.1), (52.7, 14.2), (21.4, 49.6)],
+    [(40.2, 6.6), (55.1, 50.3), (9.7, 36.9)],
+])
+def test_edge_term_matches_box_filter_derivative(pts):
+    cos, rel = _edge_grad_vs_area_fd(pts, 64, 64, (0.8, -0.3, 0.5))
+    assert cos > 0.995 and rel < 0.08, (cos, rel)      # measured 0.9998 / 0.046
+
+
+def test_edge_term_covers_opacity_induced_boundaries():
+    """A triangle whose opacity is ~1 on one side of b1 = 0.45 and ~0 on the
+    other: the visible region is the triangle clipped by that line, which moves
+    with the triangle. The all-pairs edge term sees the implicit boundary."""
+    pts = [(6.2, 8.9), (57.3, 12.4), (18.8, 55.1)]
+
+    def logit_fn(u, v):       # bilinear in the grid: positive where b1 > 0.45
+        return 400.0 * (u - 0.45)
+
+    def halfplane(p):
+        # b1 >= 0.45 on the ortho camera: affine in screen space
+        (x0, y0), (x1, y1), (x2, y2) = p
+        det = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0)
+        # b1 = ((y2 - y0)(x - x0) - (x2 - x0)(y - y0)) / det
+        a = (y2 - y0) / det
+        b = -(x2 - x0) / det
+        c = -(a * x0 + b * y0) - 0.45
+        return a, b, c
+
+    cos, rel = _edge_grad_vs_area_fd(pts, 64, 64, (0.8, -0.3, 0.5), logit_fn, halfplane)
+    assert cos > 0.995 and rel < 0.05, (cos, rel)      # measured 0.99995 / 0.011
+
+
+# --------------------------------------------------------------------------
+# Sparse-pixel oracle entry points agree with the full-image ones
+# --------------------------------------------------------------------------
+
+def test_pixel_entry_points_agree_with_full_image():
+    w = W.tiny()
+    view = w.views[0]
+    o = O.Opts(seed=w.seed)
+    vis, color, logp, _ = O.forward(w.scene, view, o)
+    rng = np.random.default_rng(0)
+    xy = np.stack([rng.integers(0, 128, 200), rng.integers(0, 128, 200)], 1)
+    xy = np.unique(xy, axis=0)
+    v2, c2, l2 = O.forward_pixels(w.scene, view, o, xy)
+    assert np.array_equal(v2, vis[xy[:, 1], xy[:, 0]])
+    assert np.array_equal(c2, color[xy[:, 1], xy[:, 0]])
+    assert np.allclose(l2, logp[xy[:, 1], xy[:, 0]], rtol=0, atol=1e-12)
+    gc = rng.normal(0, 1, (len(xy), 3)).astype(np.float32)
+    gl = rng.normal(0, 1, len(xy)).astype(np.float32)
+    dense_c = np.zeros((128, 128, 3), np.float32)
+    dense_l = np.zeros((128, 128), np.float32)
+    dense_c[xy[:, 1], xy[:, 0]] = gc
+    dense_l[xy[:, 1], xy[:, 0]] = gl
+    a = O.backward(w.scene, view, o, vis, color, dense_c, dense_l)
+    b = O.backward_pixels(w.scene, view, o, xy, gc, gl)
+    for x, y in zip(a, b):
+        assert np.allclose(x, y, rtol=1e-10, atol=1e-13)
