@@ -1,0 +1,188 @@
+/*
+ * diffsoup.h -- C ABI of the MI355X (gfx950) differentiable triangle-soup
+ * rasterizer: one rasterization step of an opaque triangle soup under
+ * stochastic opacity masking (DiffSoup, arXiv 2603.27151).
+ *
+ * The problem statement follows Section 3.1 and Supplement B.6 of the paper:
+ * a soup of |T| independent triangles (nine floats each), per-triangle
+ * textures, a shared MLP decoder (Section 3.3) and pinhole cameras in; an
+ * image of colours out; gradients for vertices, textures and the MLP back,
+ * as a custom differentiable operator (Supplement A.1).
+ *
+ * Conventions
+ *  - Every pointer marked "device" is a device pointer owned by the caller;
+ *    every pointer marked "host" is read during the call only.
+ *  - All compute calls are ordered on the given stream (a hipStream_t, passed
+ *    as void*; NULL = the default stream). A call returns once its work is
+ *    enqueued, except where noted; it synchronises the stream once to size
+ *    its tile lists (see soup_rasterize_fwd).
+ *  - Argument errors are detected before any work is enqueued: the call
+ *    returns SOUP_ERR_INVALID (or SOUP_ERR_UNSUPPORTED) and soup_last_error()
+ *    describes the problem. No C++ exception crosses this interface.
+ *  - Views of one call are concatenated in the output buffers: view v owns
+ *    pixels [sum_{u<v} W_u H_u, sum_{u<=v} W_u H_u), row-major (y * W + x),
+ *    row 0 at the top of the image.
+ *  - A context is not thread safe; use one context per host thread/stream.
+ */
+#ifndef DIFFSOUP_H
+#define DIFFSOUP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct soup_ctx soup_ctx;
+
+typedef enum {
+    SOUP_OK = 0,
+    SOUP_ERR_INVALID = 1,      /* bad argument (message via soup_last_error) */
+    SOUP_ERR_OOM = 2,          /* device allocation failed */
+    SOUP_ERR_CAPACITY = 3,     /* a fixed workspace capacity was exceeded */
+    SOUP_ERR_HIP = 4,          /* a HIP runtime call failed */
+    SOUP_ERR_UNSUPPORTED = 5   /* valid but not compiled in (e.g. an MLP shape) */
+} soup_status;
+
+/* A triangle soup with its neural texture (Section 3.1; Section 3.3 in the
+ * form of a G x G feature grid per triangle, sampled bilinearly at the
+ * perspective-correct barycentrics (b1, b2) -> grid (b1 (G-1), b2 (G-1)),
+ * and a shared MLP C -> h ... -> 4 with ReLU hidden layers whose outputs are
+ * the RGB logits and the opacity logit; colour = sigmoid(o0..o2),
+ * alpha = sigmoid(o3)). */
+typedef struct {
+    int32_t T;                 /* triangles, >= 0 */
+    int32_t G;                 /* feature grid side, >= 2 */
+    int32_t C;                 /* feature channels = dims[0] */
+    int32_t n_layers;          /* MLP layers (linear maps), >= 1 */
+    const int32_t* dims;       /* host [n_layers+1]; dims[0] == C, dims[n_layers] == 4 */
+    const float* verts;        /* device [T,3,3] world positions, float32 */
+    const float* feats;        /* device [T,G,G,C], texel [t][iy][ix][c] */
+    const float* mlp;          /* device, per layer: W[d_out][d_in] row-major, then b[d_out] */
+} soup_scene;
+
+/* Pinhole views. clip = M [x, y, z, 1]; screen x = W/2 (c_x/c_w + 1),
+ * screen y = H/2 (1 - c_y/c_w), depth = (c_z/c_w + 1)/2 clamped to [0, 1]. */
+typedef struct {
+    int32_t V;                 /* number of views, >= 1 */
+    const int32_t* width;      /* host [V], 1..16384 */
+    const int32_t* height;     /* host [V], 1..16384 */
+    const uint32_t* view_id;   /* host [V]: enters the random draws (not the batch position) */
+    const float* view_proj;    /* host [V,4,4] row-major float32 */
+} soup_views;
+
+typedef struct {
+    uint64_t seed;             /* Philox4x32-10 key (low word, high word) */
+    uint32_t step;             /* fourth counter word (e.g. the iteration) */
+    int32_t mode;              /* 0: stochastic masking, Eq. (5); 1: threshold alpha > 1/2, Eq. (3) */
+    float background[3];       /* colour where no fragment passes */
+    int32_t edge_pairs;        /* 0: every adjacent pixel pair (Section 3.2); 1: only pairs whose
+                                  triangle id differs; 2: no edge term */
+    float near_w;              /* triangles with any vertex at clip w < near_w are culled (0.1) */
+} soup_opts;
+
+/* Work counts of the last compute call on a context (filled on request). */
+typedef struct {
+    int64_t pixels;            /* pixels of all views */
+    int64_t tiles;             /* screen tiles of all views */
+    int64_t bin_entries;       /* (tile, triangle) pairs after binning */
+    int64_t visible_tris;      /* (view, triangle) records that survived culling */
+    int64_t decodes;           /* texture + MLP decodes performed by the raster kernel */
+} soup_stats;
+
+/* Create a context on HIP device `device`. Owns the workspaces (triangle
+ * records, tile lists, partial sums), grown on demand and freed by
+ * soup_ctx_destroy. Returns SOUP_ERR_HIP if the device cannot be used. */
+soup_status soup_ctx_create(soup_ctx** out, int device);
+void soup_ctx_destroy(soup_ctx* ctx);
+
+/* Message of the last error on this context ("" if none). Valid until the
+ * next call on the context. */
+const char* soup_last_error(const soup_ctx* ctx);
+
+/* Screen tile side in pixels: 8, 16 (default) or 32. */
+soup_status soup_ctx_set_tile(soup_ctx* ctx, int32_t tile);
+int32_t soup_ctx_get_tile(const soup_ctx* ctx);
+
+/* Enable (1) or disable (0, default) counting of decodes in soup_stats. */
+soup_status soup_ctx_set_counting(soup_ctx* ctx, int32_t on);
+soup_status soup_last_stats(const soup_ctx* ctx, soup_stats* out);
+
+/*
+ * Forward pass (Eq. (1), (2), (5); Supplement Algorithm A1, part 1).
+ * For every pixel centre: the fragments are the triangles covering it; each
+ * fragment f draws u_f = Philox(seed; pixel index, triangle, view_id, step)
+ * (24-bit uniform) and passes when u_f < alpha_f (mode 0) or when its opacity
+ * logit is > 0 (mode 1); the winner is the passing fragment with the smallest
+ * key (depth bits << 32 | triangle), found without sorting fragments.
+ * Outputs (device, caller-allocated, overwritten):
+ *   vis   [P] uint64   winner key, 0xFFFFFFFFFFFFFFFF where no fragment passes
+ *   color [P,3] float  sigmoid of the winner's RGB logits, or background
+ *   logp  [P] float    log p(f*) of Eq. (6) (mode 0), or NULL
+ * The call synchronises `stream` once (after binning) to size the tile list
+ * workspace; everything else is asynchronous.
+ */
+soup_status soup_rasterize_fwd(soup_ctx* ctx, const soup_scene* scene, const soup_views* views,
+                               const soup_opts* opts, uint64_t* vis, float* color, float* logp,
+                               void* stream);
+
+/*
+ * Backward pass (Eq. (8), (9); Supplement Algorithm A1, part 2; Section 3.2
+ * edge term), recomputing fragments from the saved visibility buffer.
+ * Inputs: vis and color from soup_rasterize_fwd with the same arguments;
+ * grad_color [P,3] = dL/dcolor; grad_logp [P] = per-pixel weight of the score
+ * term (the sampled pixel loss for Algorithm A1's L * s), or NULL.
+ * Outputs (device, overwritten): grad_verts [T,3,3], grad_feats [T,G,G,C],
+ * grad_mlp [n_params].
+ *   winner f*:        colour path (exact derivative with draws fixed) plus
+ *                     score g_L (1 - alpha*) on its opacity logit;
+ *   f in front of f*: score -g_L alpha_f on its opacity logit (features and
+ *                     MLP only, no vertex motion);
+ *   adjacent pixel pairs (a, b = a + e): w = 1/2 (g_a + g_b).(C_a - C_b)
+ *                     moves the nearer pixel's triangle vertices by
+ *                     w beta_i e in screen space.
+ * Floating-point sums are order-dependent (atomics); results agree with an
+ * exact evaluation to about 1e-6 relative.
+ */
+soup_status soup_rasterize_bwd(soup_ctx* ctx, const soup_scene* scene, const soup_views* views,
+                               const soup_opts* opts, const uint64_t* vis, const float* color,
+                               const float* grad_color, const float* grad_logp,
+                               float* grad_verts, float* grad_feats, float* grad_mlp,
+                               void* stream);
+
+/*
+ * Batched forward-only render of R requests (serving): request r renders
+ * scenes[r] from view r of `views` (views->V == R) into color[r] (device
+ * [H_r, W_r, 3], overwritten). All scenes must share G, C and the MLP shape;
+ * their triangle counts may differ. The mode in opts applies to all
+ * requests (1 = the deterministic threshold render of Eq. (3)).
+ */
+soup_status soup_render(soup_ctx* ctx, const soup_scene* scenes, int32_t R, const soup_views* views,
+                        const soup_opts* opts, float* const* color, void* stream);
+
+/*
+ * Per-pixel L2 photometric loss against `target` (device [P,3]) over P pixels
+ * (the benchmark's loss; any per-pixel loss can feed soup_rasterize_bwd):
+ *   L = mean over P*3 of (color - target)^2,
+ *   grad_color = 2 (color - target) / (3P),
+ *   grad_logp  = sum_c (color - target)^2 / (3P)   (so sum_p grad_logp = L).
+ * loss (device scalar, may be NULL) receives L.
+ */
+soup_status soup_loss_l2(soup_ctx* ctx, const float* color, const float* target, int64_t P,
+                         float* grad_color, float* grad_logp, float* loss, void* stream);
+
+/* Contract self-test: y[i] = the device sigmoid of x[i] (the opacity
+ * sigmoid whose value decides the mask), for checking it bit for bit
+ * against an independent implementation. x, y device [n]. */
+soup_status soup_selftest_sigmoid(soup_ctx* ctx, const float* x, float* y, int64_t n, void* stream);
+
+/* Contract self-test: u[i] = the device 24-bit uniform draw for counter
+ * (pixel[i], tri[i], view_id, step) under `seed`. pixel, tri, u device [n]. */
+soup_status soup_selftest_uniform(soup_ctx* ctx, uint64_t seed, const uint32_t* pixel,
+                                  const uint32_t* tri, uint32_t view_id, uint32_t step,
+                                  float* u, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFSOUP_H */

@@ -1,0 +1,231 @@
+"""ctypes binding of libdiffsoup.so (include/diffsoup.h), argument
+marshalling only: every step of the rasterization runs in the library's HIP
+kernels. Functions carry the C names; tensors are torch tensors on the GPU
+(device memory and streams come from PyTorch).
+
+The library is loaded from this package directory. If it is missing the
+import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdiffsoup.so")
+
+SOUP_OK = 0
+STATUS = {0: "SOUP_OK", 1: "SOUP_ERR_INVALID", 2: "SOUP_ERR_OOM", 3: "SOUP_ERR_CAPACITY",
+          4: "SOUP_ERR_HIP", 5: "SOUP_ERR_UNSUPPORTED"}
+BG_KEY = 0xFFFFFFFFFFFFFFFF
+
+
+class soup_scene(C.Structure):
+    _fields_ = [("T", C.c_int32), ("G", C.c_int32), ("C", C.c_int32), ("n_layers", C.c_int32),
+                ("dims", C.POINTER(C.c_int32)), ("verts", C.c_void_p), ("feats", C.c_void_p),
+                ("mlp", C.c_void_p)]
+
+
+class soup_views(C.Structure):
+    _fields_ = [("V", C.c_int32), ("width", C.POINTER(C.c_int32)), ("height", C.POINTER(C.c_int32)),
+                ("view_id", C.POINTER(C.c_uint32)), ("view_proj", C.POINTER(C.c_float))]
+
+
+class soup_opts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("mode", C.c_int32),
+                ("background", C.c_float * 3), ("edge_pairs", C.c_int32), ("near_w", C.c_float)]
+
+
+class soup_stats(C.Structure):
+    _fields_ = [("pixels", C.c_int64), ("tiles", C.c_int64), ("bin_entries", C.c_int64),
+                ("visible_tris", C.c_int64), ("decodes", C.c_int64)]
+
+
+EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_set_tile",
+           "soup_ctx_get_tile", "soup_ctx_set_counting", "soup_last_stats", "soup_rasterize_fwd",
+           "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
+           "soup_selftest_uniform"]
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(hipcc, gfx950); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.soup_ctx_create.argtypes = [C.POINTER(P), C.c_int]
+    L.soup_ctx_destroy.argtypes = [P]
+    L.soup_ctx_destroy.restype = None
+    L.soup_last_error.argtypes = [P]
+    L.soup_last_error.restype = C.c_char_p
+    L.soup_ctx_set_tile.argtypes = [P, C.c_int32]
+    L.soup_ctx_get_tile.argtypes = [P]
+    L.soup_ctx_set_counting.argtypes = [P, C.c_int32]
+    L.soup_last_stats.argtypes = [P, C.POINTER(soup_stats)]
+    L.soup_rasterize_fwd.argtypes = [P, C.POINTER(soup_scene), C.POINTER(soup_views), C.POINTER(soup_opts),
+                                     P, P, P, P]
+    L.soup_rasterize_bwd.argtypes = [P, C.POINTER(soup_scene), C.POINTER(soup_views), C.POINTER(soup_opts),
+                                     P, P, P, P, P, P, P, P]
+    L.soup_render.argtypes = [P, C.POINTER(soup_scene), C.c_int32, C.POINTER(soup_views),
+                              C.POINTER(soup_opts), C.POINTER(P), P]
+    L.soup_loss_l2.argtypes = [P, P, P, C.c_int64, P, P, P, P]
+    L.soup_selftest_sigmoid.argtypes = [P, P, P, C.c_int64, P]
+    L.soup_selftest_uniform.argtypes = [P, C.c_uint64, P, P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
+    for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
+                 "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
+                 "soup_selftest_sigmoid", "soup_selftest_uniform"]:
+        getattr(L, name).restype = C.c_int
+    L.soup_ctx_get_tile.restype = C.c_int32
+    _lib = L
+    return L
+
+
+class SoupError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class _Holder:
+    """Keeps host arrays alive while a C struct points at them."""
+
+    def __init__(self):
+        self.keep = []
+
+    def arr(self, a, ctype):
+        a = np.ascontiguousarray(a)
+        self.keep.append(a)
+        return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_scene(h: _Holder, verts, feats, mlp, dims: Sequence[int]) -> soup_scene:
+    T = int(verts.shape[0])
+    G = int(feats.shape[1])
+    Cc = int(feats.shape[3])
+    for name, t in (("verts", verts), ("feats", feats), ("mlp", mlp)):
+        if not t.is_cuda or t.dtype.itemsize != 4 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(verts.shape[1:]) != (3, 3) or tuple(feats.shape) != (T, G, G, Cc):
+        raise ValueError("verts must be [T,3,3] and feats [T,G,G,C]")
+    d = np.asarray(dims, np.int32)
+    return soup_scene(T, G, Cc, len(dims) - 1, h.arr(d, C.c_int32), _ptr(verts), _ptr(feats), _ptr(mlp))
+
+
+def make_views(h: _Holder, widths, heights, view_ids, view_proj) -> soup_views:
+    w = np.asarray(widths, np.int32)
+    hh = np.asarray(heights, np.int32)
+    vid = np.asarray(view_ids, np.uint32)
+    M = np.ascontiguousarray(np.asarray(view_proj, np.float32).reshape(-1, 16))
+    if not (len(w) == len(hh) == len(vid) == M.shape[0]):
+        raise ValueError("views: widths, heights, view_ids and view_proj disagree in length")
+    return soup_views(len(w), h.arr(w, C.c_int32), h.arr(hh, C.c_int32), h.arr(vid, C.c_uint32),
+                      h.arr(M, C.c_float))
+
+
+def make_opts(seed=0, step=0, mode=0, background=(0.0, 0.0, 0.0), edge_pairs=0, near_w=0.1) -> soup_opts:
+    return soup_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), int(mode), (C.c_float * 3)(*background),
+                     int(edge_pairs), float(near_w))
+
+
+class Ctx:
+    """Owns one soup_ctx (workspaces on one device)."""
+
+    def __init__(self, device: int = 0):
+        L = lib()
+        p = C.c_void_p()
+        st = L.soup_ctx_create(C.byref(p), int(device))
+        if st != SOUP_OK:
+            raise SoupError(st, f"soup_ctx_create(device={device}) failed")
+        self.p = p
+        self.device = device
+
+    def close(self):
+        if self.p:
+            lib().soup_ctx_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int):
+        if st != SOUP_OK:
+            raise SoupError(st, lib().soup_last_error(self.p).decode())
+
+    def set_tile(self, tile: int):
+        self.check(lib().soup_ctx_set_tile(self.p, int(tile)))
+
+    @property
+    def tile(self) -> int:
+        return int(lib().soup_ctx_get_tile(self.p))
+
+    def set_counting(self, on: bool):
+        self.check(lib().soup_ctx_set_counting(self.p, 1 if on else 0))
+
+    def stats(self) -> dict:
+        s = soup_stats()
+        self.check(lib().soup_last_stats(self.p, C.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in soup_stats._fields_}
+
+
+# ---------------------------------------------------------------------------
+# entry points (C names; torch tensors in, torch tensors out)
+# ---------------------------------------------------------------------------
+
+def soup_rasterize_fwd(ctx: Ctx, scene: soup_scene, views: soup_views, opts: soup_opts, vis, color,
+                       logp=None, stream=None):
+    ctx.check(lib().soup_rasterize_fwd(ctx.p, C.byref(scene), C.byref(views), C.byref(opts), _ptr(vis),
+                                       _ptr(color), _ptr(logp), _stream(stream)))
+
+
+def soup_rasterize_bwd(ctx: Ctx, scene: soup_scene, views: soup_views, opts: soup_opts, vis, color,
+                       grad_color, grad_logp, grad_verts, grad_feats, grad_mlp, stream=None):
+    ctx.check(lib().soup_rasterize_bwd(ctx.p, C.byref(scene), C.byref(views), C.byref(opts), _ptr(vis),
+                                       _ptr(color), _ptr(grad_color), _ptr(grad_logp), _ptr(grad_verts),
+                                       _ptr(grad_feats), _ptr(grad_mlp), _stream(stream)))
+
+
+def soup_render(ctx: Ctx, scenes: Sequence[soup_scene], views: soup_views, opts: soup_opts, colors,
+                stream=None):
+    R = len(scenes)
+    arr = (soup_scene * R)(*scenes)
+    outs = (C.c_void_p * R)(*[_ptr(c) for c in colors])
+    ctx.check(lib().soup_render(ctx.p, arr, R, C.byref(views), C.byref(opts), outs, _stream(stream)))
+
+
+def soup_loss_l2(ctx: Ctx, color, target, grad_color, grad_logp, loss=None, stream=None):
+    P = color.numel() // 3
+    ctx.check(lib().soup_loss_l2(ctx.p, _ptr(color), _ptr(target), P, _ptr(grad_color), _ptr(grad_logp),
+                                 _ptr(loss), _stream(stream)))
+
+
+def soup_selftest_sigmoid(ctx: Ctx, x, y, stream=None):
+    ctx.check(lib().soup_selftest_sigmoid(ctx.p, _ptr(x), _ptr(y), x.numel(), _stream(stream)))
+
+
+def soup_selftest_uniform(ctx: Ctx, seed, pixel, tri, view_id, step, u, stream=None):
+    ctx.check(lib().soup_selftest_uniform(ctx.p, int(seed), _ptr(pixel), _ptr(tri), int(view_id), int(step),
+                                          _ptr(u), u.numel(), _stream(stream)))

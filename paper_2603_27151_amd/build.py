@@ -1,0 +1,60 @@
+"""Build the gfx950 rasterizer library (libdiffsoup.so) in-tree with hipcc.
+
+Flags: -O3 for gfx950 only; -ffp-contract=off so that only the explicit
+fused multiply-adds of the arithmetic contract are fused; packed FP32
+instructions disabled (-packed-fp32-ops target feature off).
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+OUT = os.path.join(HERE, "libdiffsoup.so")
+SOURCES = ["api.hip", "bin.hip", "raster_fwd.hip", "raster_bwd.hip"]
+ARCH = os.environ.get("SOUP_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    return os.path.join(rocm, "bin", "hipcc")
+
+
+def flags():
+    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
+            "-fno-gpu-flush-denormals-to-zero", "-fhip-fp32-correctly-rounded-divide-sqrt",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+            "-I", os.path.join(ROOT, "include")]
+
+
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        cmd = [hipcc(), *flags(), "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
+        objs.append(obj)
+        if len(procs) >= jobs:
+            src0, p0 = procs.pop(0)
+            if p0.wait() != 0:
+                raise RuntimeError(f"hipcc failed on {src0}")
+    for src0, p0 in procs:
+        if p0.wait() != 0:
+            raise RuntimeError(f"hipcc failed on {src0}")
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", OUT + ".tmp", *objs]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
+    os.replace(OUT + ".tmp", OUT)
+    for o in objs:
+        os.remove(o)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

@@ -1,0 +1,518 @@
+// C ABI of the gfx950 soup rasterizer: context, argument validation,
+// workspace management and the launch sequence of each entry point.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/diffsoup.h"
+#include "internal.hpp"
+
+namespace {
+
+using namespace soup;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct soup_ctx {
+    int device = 0;
+    int num_cus = 256;
+    int tile = 16;
+    bool counting = false;
+    std::string err;
+    soup_stats stats{};
+    DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
+    void* host_stage = nullptr;      // pinned: descriptors up, totals down
+    size_t host_stage_bytes = 0;
+};
+
+namespace {
+
+soup_status fail(soup_ctx* c, soup_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(ctx, SOUP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+soup_status ensure(soup_ctx* c, DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return SOUP_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return fail(c, SOUP_ERR_HIP, "hipFree failed: %s", hipGetErrorString(e));
+    }
+    size_t want = bytes + bytes / 4;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(c, SOUP_ERR_OOM, "device allocation of %zu bytes failed", want);
+    }
+    b.bytes = want;
+    return SOUP_OK;
+}
+
+soup_status ensure_host(soup_ctx* c, size_t bytes) {
+    if (c->host_stage_bytes >= bytes) return SOUP_OK;
+    if (c->host_stage) (void)hipHostFree(c->host_stage);
+    c->host_stage = nullptr;
+    c->host_stage_bytes = 0;
+    size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    if (hipHostMalloc(&c->host_stage, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, SOUP_ERR_OOM, "pinned host allocation of %zu bytes failed", want);
+    }
+    c->host_stage_bytes = want;
+    return SOUP_OK;
+}
+
+}  // namespace
+
+namespace soup {
+
+MlpKind mlp_kind(int n_layers, const int32_t* dims) {
+    if (n_layers == 2 && dims[0] == 8 && dims[1] == 16 && dims[2] == 4) return MlpKind::k8_16_1;
+    if (n_layers == 3 && dims[0] == 16 && dims[1] == 32 && dims[2] == 32 && dims[3] == 4) return MlpKind::k16_32_2;
+    if (n_layers == 3 && dims[0] == 32 && dims[1] == 64 && dims[2] == 64 && dims[3] == 4) return MlpKind::k32_64_2;
+    return MlpKind::kNone;
+}
+
+int mlp_params(int n_layers, const int32_t* dims) {
+    int n = 0;
+    for (int l = 0; l < n_layers; ++l) n += dims[l + 1] * dims[l] + dims[l + 1];
+    return n;
+}
+
+}  // namespace soup
+
+namespace {
+
+soup_status check_scene(soup_ctx* c, const soup_scene* s, MlpKind* kind) {
+    if (!s) return fail(c, SOUP_ERR_INVALID, "scene is NULL");
+    if (s->T < 0) return fail(c, SOUP_ERR_INVALID, "scene.T = %d < 0", s->T);
+    if (s->G < 2 || s->G > 256) return fail(c, SOUP_ERR_INVALID, "scene.G = %d outside [2, 256]", s->G);
+    if (s->n_layers < 1 || s->n_layers > 16 || !s->dims)
+        return fail(c, SOUP_ERR_INVALID, "scene.n_layers = %d or dims missing", s->n_layers);
+    if (s->dims[0] != s->C) return fail(c, SOUP_ERR_INVALID, "dims[0] = %d != C = %d", s->dims[0], s->C);
+    if (s->dims[s->n_layers] != 4) return fail(c, SOUP_ERR_INVALID, "dims[last] = %d != 4", s->dims[s->n_layers]);
+    if (s->T > 0 && (!s->verts || !s->feats || !s->mlp))
+        return fail(c, SOUP_ERR_INVALID, "scene device pointers are NULL");
+    *kind = soup::mlp_kind(s->n_layers, s->dims);
+    if (*kind == MlpKind::kNone) {
+        std::string d;
+        for (int i = 0; i <= s->n_layers; ++i) d += (i ? "->" : "") + std::to_string(s->dims[i]);
+        return fail(c, SOUP_ERR_UNSUPPORTED, "MLP shape %s is not compiled in (8->16->4, 16->32->32->4, 32->64->64->4)",
+                    d.c_str());
+    }
+    return SOUP_OK;
+}
+
+soup_status check_views(soup_ctx* c, const soup_views* v) {
+    if (!v) return fail(c, SOUP_ERR_INVALID, "views is NULL");
+    if (v->V < 1 || v->V > soup::kMaxViews) return fail(c, SOUP_ERR_INVALID, "views.V = %d outside [1, 65536]", v->V);
+    if (!v->width || !v->height || !v->view_id || !v->view_proj)
+        return fail(c, SOUP_ERR_INVALID, "views host arrays are NULL");
+    for (int i = 0; i < v->V; ++i)
+        if (v->width[i] < 1 || v->width[i] > 16384 || v->height[i] < 1 || v->height[i] > 16384)
+            return fail(c, SOUP_ERR_INVALID, "view %d size %dx%d outside [1, 16384]", i, v->width[i], v->height[i]);
+    return SOUP_OK;
+}
+
+soup_status check_opts(soup_ctx* c, const soup_opts* o) {
+    if (!o) return fail(c, SOUP_ERR_INVALID, "opts is NULL");
+    if (o->mode != 0 && o->mode != 1) return fail(c, SOUP_ERR_INVALID, "opts.mode = %d (0 or 1)", o->mode);
+    if (o->edge_pairs < 0 || o->edge_pairs > 2)
+        return fail(c, SOUP_ERR_INVALID, "opts.edge_pairs = %d (0, 1 or 2)", o->edge_pairs);
+    if (!(o->near_w > 0.0f)) return fail(c, SOUP_ERR_INVALID, "opts.near_w must be > 0");
+    return SOUP_OK;
+}
+
+Opts to_opts(const soup_opts* o) {
+    Opts r{};
+    r.seed = o->seed;
+    r.step = o->step;
+    r.mode = o->mode;
+    r.bg[0] = o->background[0];
+    r.bg[1] = o->background[1];
+    r.bg[2] = o->background[2];
+    r.edge_pairs = o->edge_pairs;
+    r.near_w = o->near_w;
+    return r;
+}
+
+// Per-call plan: descriptors and sizes.
+struct Plan {
+    std::vector<ViewDesc> views;
+    std::vector<SceneDesc> scenes;
+    int64_t n_tiles = 0, n_pix = 0, n_recs = 0;
+    int maxT = 0;
+    int G = 0;
+    MlpKind kind = MlpKind::kNone;
+    int n_params = 0;
+};
+
+void plan_views(Plan& p, const soup_views* v, int tile, const std::vector<int>& scene_of_view,
+                const std::vector<int64_t>& rec_base) {
+    p.views.resize(v->V);
+    int64_t tb = 0, pb = 0;
+    for (int i = 0; i < v->V; ++i) {
+        ViewDesc& d = p.views[i];
+        memset(&d, 0, sizeof(d));
+        memcpy(d.M, v->view_proj + 16 * i, sizeof(d.M));
+        d.W = v->width[i];
+        d.H = v->height[i];
+        d.view_id = v->view_id[i];
+        d.scene = scene_of_view[i];
+        d.tiles_x = (d.W + tile - 1) / tile;
+        d.tiles_y = (d.H + tile - 1) / tile;
+        d.T = p.scenes[d.scene].T;
+        d.tile_base = tb;
+        d.pix_base = pb;
+        d.rec_base = rec_base[i];
+        tb += static_cast<int64_t>(d.tiles_x) * d.tiles_y;
+        pb += static_cast<int64_t>(d.W) * d.H;
+        p.maxT = std::max(p.maxT, d.T);
+    }
+    p.n_tiles = tb;
+    p.n_pix = pb;
+}
+
+// Upload descriptors, run setup + scan, read the list size, scatter + sort.
+soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
+    const size_t vbytes = p.views.size() * sizeof(ViewDesc), sbytes = p.scenes.size() * sizeof(SceneDesc);
+    soup_status st;
+    if ((st = ensure(c, c->views, vbytes)) || (st = ensure(c, c->scenes, sbytes)) ||
+        (st = ensure(c, c->recs, static_cast<size_t>(p.n_recs) * sizeof(TriRec))) ||
+        (st = ensure(c, c->tile_count, static_cast<size_t>(p.n_tiles) * 4)) ||
+        (st = ensure(c, c->tile_fill, static_cast<size_t>(p.n_tiles) * 4)) ||
+        (st = ensure(c, c->tile_start, static_cast<size_t>(p.n_tiles + 1) * 8)) ||
+        (st = ensure(c, c->bsum, static_cast<size_t>((p.n_tiles + 1023) / 1024 + 1) * 8)) ||
+        (st = ensure(c, c->counters, 64)) || (st = ensure_host(c, vbytes + sbytes + 64)))
+        return st;
+    // the previous call has drained this stream's use of the staging buffer
+    HIP_TRY(c, hipStreamSynchronize(s));
+    char* hs = static_cast<char*>(c->host_stage);
+    memcpy(hs, p.views.data(), vbytes);
+    memcpy(hs + vbytes, p.scenes.data(), sbytes);
+    HIP_TRY(c, hipMemcpyAsync(c->views.p, hs, vbytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->scenes.p, hs + vbytes, sbytes, hipMemcpyHostToDevice, s));
+    unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
+    launch_fill_i32(reinterpret_cast<int32_t*>(cnt), 16, 0, s);
+    launch_fill_i32(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, 0, s);
+    launch_setup(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT,
+                 static_cast<SceneDesc*>(c->scenes.p), o, c->tile, static_cast<TriRec*>(c->recs.p),
+                 static_cast<int32_t*>(c->tile_count.p), c->counting ? cnt + 1 : nullptr, s);
+    launch_scan(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, static_cast<int64_t*>(c->bsum.p),
+                static_cast<int64_t*>(c->tile_start.p), s);
+    int64_t* htotal = reinterpret_cast<int64_t*>(hs + vbytes + sbytes);
+    HIP_TRY(c, hipMemcpyAsync(htotal, static_cast<int64_t*>(c->tile_start.p) + p.n_tiles, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const int64_t total = *htotal;
+    if ((st = ensure(c, c->entries, static_cast<size_t>(total) * 8))) return st;
+    launch_fill_i32(static_cast<int32_t*>(c->tile_fill.p), p.n_tiles, 0, s);
+    launch_scatter(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, c->tile,
+                   static_cast<TriRec*>(c->recs.p), static_cast<int64_t*>(c->tile_start.p),
+                   static_cast<int32_t*>(c->tile_fill.p), static_cast<uint64_t*>(c->entries.p), s);
+    launch_sort(static_cast<int64_t*>(c->tile_start.p), p.n_tiles, static_cast<uint64_t*>(c->entries.p), s);
+    HIP_TRY(c, hipGetLastError());
+    c->stats.pixels = p.n_pix;
+    c->stats.tiles = p.n_tiles;
+    c->stats.bin_entries = total;
+    return SOUP_OK;
+}
+
+RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
+    RasterArgs a{};
+    a.views = static_cast<ViewDesc*>(c->views.p);
+    a.V = static_cast<int>(p.views.size());
+    a.scenes = static_cast<SceneDesc*>(c->scenes.p);
+    a.o = o;
+    a.G = p.G;
+    a.recs = static_cast<TriRec*>(c->recs.p);
+    a.tile_start = static_cast<int64_t*>(c->tile_start.p);
+    a.entries = static_cast<uint64_t*>(c->entries.p);
+    a.n_tiles = p.n_tiles;
+    unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
+    a.counter = c->counting ? cnt : nullptr;
+    a.work = reinterpret_cast<unsigned int*>(cnt + 2);
+    return a;
+}
+
+soup_status finish_stats(soup_ctx* c, hipStream_t s) {
+    if (!c->counting) {
+        c->stats.visible_tris = -1;
+        c->stats.decodes = -1;
+        return SOUP_OK;
+    }
+    unsigned long long h[2];
+    HIP_TRY(c, hipMemcpyAsync(h, c->counters.p, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->stats.decodes = static_cast<int64_t>(h[0]);
+    c->stats.visible_tris = static_cast<int64_t>(h[1]);
+    return SOUP_OK;
+}
+
+int persistent_blocks(soup_ctx* c, const Plan& p) {
+    const int64_t want = static_cast<int64_t>(c->num_cus) * 4;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, p.n_tiles)));
+}
+
+int waves_per_block(int tile) { return tile == 8 ? 1 : 4; }
+
+soup_status plan_single(soup_ctx* c, Plan& p, const soup_scene* scene, const soup_views* views) {
+    soup_status st = check_scene(c, scene, &p.kind);
+    if (st) return st;
+    if ((st = check_views(c, views))) return st;
+    SceneDesc sd{};
+    sd.verts = scene->verts;
+    sd.feats = scene->feats;
+    sd.mlp = scene->mlp;
+    sd.T = scene->T;
+    p.scenes = {sd};
+    p.G = scene->G;
+    p.n_params = mlp_params(scene->n_layers, scene->dims);
+    std::vector<int> sov(views->V, 0);
+    std::vector<int64_t> rb(views->V);
+    for (int i = 0; i < views->V; ++i) rb[i] = static_cast<int64_t>(i) * scene->T;
+    p.n_recs = static_cast<int64_t>(views->V) * scene->T;
+    plan_views(p, views, c->tile, sov, rb);
+    return SOUP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+soup_status soup_ctx_create(soup_ctx** out, int device) {
+    if (!out) return SOUP_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return SOUP_ERR_HIP;
+    }
+    if (hipSetDevice(device) != hipSuccess) return SOUP_ERR_HIP;
+    soup_ctx* c = new soup_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return SOUP_OK;
+}
+
+void soup_ctx_destroy(soup_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&c->views, &c->scenes, &c->recs, &c->tile_count, &c->tile_fill, &c->tile_start,
+                      &c->bsum, &c->entries, &c->vacc, &c->partial, &c->counters};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->host_stage) (void)hipHostFree(c->host_stage);
+    delete c;
+}
+
+const char* soup_last_error(const soup_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+soup_status soup_ctx_set_tile(soup_ctx* c, int32_t tile) {
+    if (!c) return SOUP_ERR_INVALID;
+    if (tile != 8 && tile != 16 && tile != 32) return fail(c, SOUP_ERR_INVALID, "tile = %d (8, 16 or 32)", tile);
+    c->tile = tile;
+    return SOUP_OK;
+}
+
+int32_t soup_ctx_get_tile(const soup_ctx* c) { return c ? c->tile : 0; }
+
+soup_status soup_ctx_set_counting(soup_ctx* c, int32_t on) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->counting = on != 0;
+    return SOUP_OK;
+}
+
+soup_status soup_last_stats(const soup_ctx* c, soup_stats* out) {
+    if (!c || !out) return SOUP_ERR_INVALID;
+    *out = c->stats;
+    return SOUP_OK;
+}
+
+soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_views* views, const soup_opts* opts,
+                               uint64_t* vis, float* color, float* logp, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    soup_status st;
+    Plan p;
+    if ((st = plan_single(c, p, scene, views))) return st;
+    if ((st = check_opts(c, opts))) return st;
+    if (!vis || !color) return fail(c, SOUP_ERR_INVALID, "vis and color outputs are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const Opts o = to_opts(opts);
+    if ((st = bin(c, p, o, s))) return st;
+    RasterArgs a = raster_args(c, p, o);
+    a.vis = vis;
+    a.color = color;
+    launch_raster_fwd(a, c->tile, p.kind, s);
+    HIP_TRY(c, hipGetLastError());
+    if (logp) {
+        if (o.mode != 0) {
+            launch_fill_f32(logp, p.n_pix, 0.0f, s);
+        } else {
+            BwdArgs b{};
+            b.r = a;
+            b.r.counter = nullptr;
+            b.vis = vis;
+            b.logp = logp;
+            b.n_blocks = persistent_blocks(c, p);
+            launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+            launch_raster_bwd(b, c->tile, p.kind, true, s);
+        }
+        HIP_TRY(c, hipGetLastError());
+    }
+    return finish_stats(c, s);
+}
+
+soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_views* views, const soup_opts* opts,
+                               const uint64_t* vis, const float* color, const float* grad_color,
+                               const float* grad_logp, float* grad_verts, float* grad_feats, float* grad_mlp,
+                               void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    soup_status st;
+    Plan p;
+    if ((st = plan_single(c, p, scene, views))) return st;
+    if ((st = check_opts(c, opts))) return st;
+    if (!vis || !color || !grad_color) return fail(c, SOUP_ERR_INVALID, "vis, color and grad_color are required");
+    if (!grad_verts || !grad_feats || !grad_mlp) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const Opts o = to_opts(opts);
+    if ((st = bin(c, p, o, s))) return st;
+    const int nb = persistent_blocks(c, p);
+    const int rows = nb * waves_per_block(c->tile);
+    if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
+        (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)))
+        return st;
+    const int T = scene->T;
+    launch_fill_f32(grad_feats, static_cast<int64_t>(T) * scene->G * scene->G * scene->C, 0.0f, s);
+    launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
+    RasterArgs a = raster_args(c, p, o);
+    launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+    BwdArgs b{};
+    b.r = a;
+    b.vis = vis;
+    b.color = color;
+    b.grad_color = grad_color;
+    b.grad_logp = grad_logp;
+    b.grad_feats = grad_feats;
+    b.vacc = static_cast<float*>(c->vacc.p);
+    b.mlp_partial = static_cast<float*>(c->partial.p);
+    b.n_blocks = nb;
+    launch_raster_bwd(b, c->tile, p.kind, false, s);
+    launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, b.vacc, s);
+    launch_vertex_chain(a.views, a.V, a.scenes, T, a.recs, b.vacc, grad_verts, s);
+    launch_mlp_reduce(b.mlp_partial, rows, p.n_params, grad_mlp, s);
+    HIP_TRY(c, hipGetLastError());
+    return finish_stats(c, s);
+}
+
+soup_status soup_render(soup_ctx* c, const soup_scene* scenes, int32_t R, const soup_views* views,
+                        const soup_opts* opts, float* const* color, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    soup_status st;
+    if (R < 1 || !scenes || !color) return fail(c, SOUP_ERR_INVALID, "render needs R >= 1 scenes and outputs");
+    if ((st = check_views(c, views))) return st;
+    if (views->V != R) return fail(c, SOUP_ERR_INVALID, "views.V = %d != R = %d", views->V, R);
+    if ((st = check_opts(c, opts))) return st;
+    Plan p;
+    std::vector<int> sov(R);
+    std::vector<int64_t> rb(R);
+    int64_t recs = 0;
+    for (int r = 0; r < R; ++r) {
+        MlpKind k;
+        if ((st = check_scene(c, &scenes[r], &k))) return st;
+        if (r == 0) {
+            p.kind = k;
+            p.G = scenes[0].G;
+        } else if (k != p.kind || scenes[r].G != p.G || scenes[r].C != scenes[0].C) {
+            return fail(c, SOUP_ERR_INVALID, "request %d: all scenes of a batch must share G, C and the MLP shape", r);
+        }
+        if (!color[r]) return fail(c, SOUP_ERR_INVALID, "request %d: color output is NULL", r);
+        SceneDesc sd{};
+        sd.verts = scenes[r].verts;
+        sd.feats = scenes[r].feats;
+        sd.mlp = scenes[r].mlp;
+        sd.T = scenes[r].T;
+        p.scenes.push_back(sd);
+        sov[r] = r;
+        rb[r] = recs;
+        recs += scenes[r].T;
+    }
+    p.n_recs = recs;
+    plan_views(p, views, c->tile, sov, rb);
+    for (int r = 0; r < R; ++r) p.views[r].color_out = color[r];
+    HIP_TRY(c, hipSetDevice(c->device));
+    const Opts o = to_opts(opts);
+    if ((st = bin(c, p, o, s))) return st;
+    RasterArgs a = raster_args(c, p, o);
+    a.vis = nullptr;
+    a.color = nullptr;
+    launch_raster_fwd(a, c->tile, p.kind, s);
+    HIP_TRY(c, hipGetLastError());
+    return finish_stats(c, s);
+}
+
+soup_status soup_loss_l2(soup_ctx* c, const float* color, const float* target, int64_t P, float* grad_color,
+                         float* grad_logp, float* loss, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (P < 0 || (P > 0 && (!color || !target || !grad_color || !grad_logp)))
+        return fail(c, SOUP_ERR_INVALID, "loss_l2: bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_loss_l2(color, target, P, grad_color, grad_logp, loss, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_selftest_sigmoid(soup_ctx* c, const float* x, float* y, int64_t n, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(c, SOUP_ERR_INVALID, "selftest_sigmoid: bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_selftest_sigmoid(x, y, n, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_selftest_uniform(soup_ctx* c, uint64_t seed, const uint32_t* pixel, const uint32_t* tri,
+                                  uint32_t view_id, uint32_t step, float* u, int64_t n, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    if (n < 0 || (n > 0 && (!pixel || !tri || !u))) return fail(c, SOUP_ERR_INVALID, "selftest_uniform: bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    launch_selftest_uniform(seed, pixel, tri, view_id, step, u, n, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+}  // extern "C"

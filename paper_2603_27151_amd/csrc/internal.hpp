@@ -1,0 +1,67 @@
+// Host-side declarations of the kernel launchers (internal to the library).
+#pragma once
+
+#include "common.hpp"
+
+namespace soup {
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+void launch_setup(const ViewDesc* views, int V, int maxT, const SceneDesc* scenes, const Opts& o, int tile,
+                  TriRec* recs, int32_t* tile_count, unsigned long long* visible, hipStream_t s);
+void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipStream_t s);
+void launch_scatter(const ViewDesc* views, int V, int maxT, int tile, const TriRec* recs,
+                    const int64_t* tile_start, int32_t* tile_fill, uint64_t* entries, hipStream_t s);
+void launch_sort(const int64_t* tile_start, int64_t n_tiles, uint64_t* entries, hipStream_t s);
+
+// MLP shapes compiled in: (C, H, NH)
+enum class MlpKind { k8_16_1, k16_32_2, k32_64_2, kNone };
+MlpKind mlp_kind(int n_layers, const int32_t* dims);
+int mlp_params(int n_layers, const int32_t* dims);
+
+struct RasterArgs {
+    const ViewDesc* views;
+    int V;
+    const SceneDesc* scenes;
+    Opts o;
+    int G;
+    const TriRec* recs;
+    const int64_t* tile_start;
+    const uint64_t* entries;
+    int64_t n_tiles;
+    uint64_t* vis;                 // concatenated outputs (may be null when views carry their own)
+    float* color;
+    unsigned long long* counter;   // decode counter or null
+    unsigned int* work;            // persistent-kernel tile counter (zeroed by the launcher's caller)
+};
+
+void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
+
+struct BwdArgs {
+    RasterArgs r;
+    const uint64_t* vis;
+    const float* color;
+    const float* grad_color;       // [P,3]
+    const float* grad_logp;        // [P] or null
+    float* grad_feats;             // [T,G,G,C]
+    float* vacc;                   // [records, 16] screen-space accumulators
+    float* mlp_partial;            // [n_waves, n_params]
+    float* logp;                   // logp output (logp pass only)
+    int n_blocks;                  // persistent grid size
+};
+
+void launch_raster_bwd(const BwdArgs& a, int tile, MlpKind k, bool logp_pass, hipStream_t s);
+void launch_edge(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis, const float* color,
+                 const float* grad_color, const TriRec* recs, float* vacc, hipStream_t s);
+void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
+                         const float* vacc, float* grad_verts, hipStream_t s);
+void launch_mlp_reduce(const float* partial, int n_rows, int n_params, float* out, hipStream_t s);
+void launch_loss_l2(const float* color, const float* target, int64_t P, float* gc, float* gl, float* loss,
+                    hipStream_t s);
+void launch_selftest_sigmoid(const float* x, float* y, int64_t n, hipStream_t s);
+void launch_selftest_uniform(uint64_t seed, const uint32_t* pixel, const uint32_t* tri, uint32_t view_id,
+                             uint32_t step, float* u, int64_t n, hipStream_t s);
+
+constexpr int kVacc = 16;          // floats per record in the screen-space accumulator
+
+}  // namespace soup

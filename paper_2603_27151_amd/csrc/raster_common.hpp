@@ -1,0 +1,150 @@
+// Tile-raster building blocks shared by the forward and backward kernels:
+// the LDS chunk of triangle records of one tile and the exact coverage test.
+//
+// Edge functions are evaluated in float64. Every operand is an integer below
+// 2^51 (snapped coordinates are bounded by 2^24, so products of differences
+// are below 2^50), so each value, including the incremental form
+// E(x, y) = E(x0, y0) + dx * a + dy * b, is exact and equals the int64 edge
+// function of the contract; the tie rule and the conversion to float for the
+// barycentrics therefore match it bit for bit.
+#pragma once
+
+#include "internal.hpp"
+
+namespace soup {
+
+template <int TS>
+struct TileCfg {
+    static constexpr int NT = TS * TS >= 256 ? 256 : TS * TS;   // threads per workgroup
+    static constexpr int PPT = TS * TS / NT;                    // pixels per thread
+    static constexpr int NW = NT / 64;                          // waves
+    static_assert(NT % 64 == 0, "tile must hold a multiple of 64 pixels");
+};
+
+template <int NT>
+struct ChunkLds {
+    double e0[3][NT];        // orientation-normalised edge functions at the tile's first pixel centre
+    double ea[3][NT];        // ... step per pixel in x
+    double eb[3][NT];        // ... step per pixel in y
+    float z[3][NT];
+    float iw[3][NT];
+    float ra[NT];            // 1 / |2 x area|
+    uint32_t tri[NT];
+    uint32_t zmin[NT];
+    uint32_t own[NT];        // bit i: edge i owns centres exactly on it
+    uint32_t box[NT];        // tile-local bbox x0 | y0 << 8 | x1 << 16 | y1 << 24
+    int32_t X[3][NT];        // snapped vertices (backward needs them)
+    int32_t Y[3][NT];
+    int32_t rec[NT];         // record index - rec_base (the triangle id)
+};
+
+// Fill slot i of the chunk from a sorted tile entry.
+template <int NT, int TS>
+__device__ __forceinline__ void load_slot(ChunkLds<NT>& ch, int i, uint64_t entry, const TriRec& r, int tx0,
+                                          int ty0) {
+    const uint32_t tri = static_cast<uint32_t>(entry);
+    ch.tri[i] = tri;
+    ch.zmin[i] = static_cast<uint32_t>(entry >> 32);
+    const int bx0 = max(r.x0 - tx0, 0), bx1 = min(r.x1 - tx0, TS - 1);
+    const int by0 = max(r.y0 - ty0, 0), by1 = min(r.y1 - ty0, TS - 1);
+    ch.box[i] = static_cast<uint32_t>(bx0) | (static_cast<uint32_t>(by0) << 8) | (static_cast<uint32_t>(bx1) << 16) |
+                (static_cast<uint32_t>(by1) << 24);
+    const int sgn = r.rA < 0.0f ? -1 : 1;
+    const int64_t PX0 = static_cast<int64_t>(kSnap) * tx0 + kSnap / 2;
+    const int64_t PY0 = static_cast<int64_t>(kSnap) * ty0 + kSnap / 2;
+    uint32_t own = 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int a = e == 2 ? 0 : e + 1;
+        const int b = e == 0 ? 2 : (e == 1 ? 0 : 1);
+        const int32_t dx = r.X[b] - r.X[a], dy = r.Y[b] - r.Y[a];
+        const int64_t E0 = static_cast<int64_t>(dx) * (PY0 - r.Y[a]) - static_cast<int64_t>(dy) * (PX0 - r.X[a]);
+        ch.e0[e][i] = static_cast<double>(sgn * E0);
+        ch.ea[e][i] = static_cast<double>(-static_cast<int64_t>(sgn) * kSnap * dy);
+        ch.eb[e][i] = static_cast<double>(static_cast<int64_t>(sgn) * kSnap * dx);
+        const int32_t ndx = sgn * dx, ndy = sgn * dy;
+        if (ndy < 0 || (ndy == 0 && ndx > 0)) own |= 1u << e;
+        ch.z[e][i] = r.z01[e];
+        ch.iw[e][i] = r.iw[e];
+        ch.X[e][i] = r.X[e];
+        ch.Y[e][i] = r.Y[e];
+    }
+    ch.own[i] = own;
+    ch.ra[i] = __builtin_fabsf(r.rA);
+    ch.rec[i] = static_cast<int32_t>(tri);
+}
+
+struct Frag {
+    uint64_t key;
+    float beta[3];
+};
+
+// Coverage of tile-local pixel (lx, ly) by chunk slot j; on success fills the
+// key and the screen barycentrics of the contract.
+template <int NT>
+__device__ __forceinline__ bool cover(const ChunkLds<NT>& ch, int j, int lx, int ly, Frag& f) {
+    const uint32_t box = ch.box[j];
+    if (lx < static_cast<int>(box & 255u) || ly < static_cast<int>((box >> 8) & 255u) ||
+        lx > static_cast<int>((box >> 16) & 255u) || ly > static_cast<int>(box >> 24))
+        return false;
+    const double dx = static_cast<double>(lx), dy = static_cast<double>(ly);
+    const uint32_t own = ch.own[j];
+    double e[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        e[i] = __builtin_fma(dx, ch.ea[i][j], __builtin_fma(dy, ch.eb[i][j], ch.e0[i][j]));
+        if (e[i] < 0.0 || (e[i] == 0.0 && !((own >> i) & 1u))) return false;
+    }
+    const float ra = ch.ra[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
+    float z = __builtin_fmaf(f.beta[2], ch.z[2][j], __builtin_fmaf(f.beta[1], ch.z[1][j], f.beta[0] * ch.z[0][j]));
+    if (!(z > 0.0f)) z = 0.0f;
+    if (z > 1.0f) z = 1.0f;
+    f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | ch.tri[j];
+    return true;
+}
+
+// Perspective-correct barycentrics of vertices 1 and 2 (contract order).
+template <int NT>
+__device__ __forceinline__ void persp_b(const ChunkLds<NT>& ch, int j, const Frag& f, float& b1, float& b2) {
+    const float t0 = f.beta[0] * ch.iw[0][j], t1 = f.beta[1] * ch.iw[1][j], t2 = f.beta[2] * ch.iw[2][j];
+    const float r = 1.0f / ((t0 + t1) + t2);
+    b1 = t1 * r;
+    b2 = t2 * r;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const uint64_t u = __shfl_xor(v, d, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// Smallest key any not-yet-processed entry of the tile list can produce.
+// Lists are sorted in blocks of kSortBlock, so it is the minimum over the
+// current position and the first entry of every later block.
+__device__ __forceinline__ uint64_t remaining_min(const uint64_t* __restrict__ entries, int64_t beg, int64_t pos,
+                                                  int64_t end) {
+    uint64_t m = entries[pos];
+    for (int64_t b = beg + ((pos - beg) / kSortBlock + 1) * kSortBlock; b < end; b += kSortBlock) {
+        const uint64_t e = entries[b];
+        m = e < m ? e : m;
+    }
+    return m;
+}
+
+// View that owns global tile `tile` (views sorted by tile_base).
+__device__ __forceinline__ int view_of_tile(const ViewDesc* __restrict__ views, int V, int64_t tile) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace soup

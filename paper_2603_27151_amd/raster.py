@@ -1,0 +1,179 @@
+"""Torch-facing API of the rasterizer: device-resident scenes and views, the
+forward / backward calls and a torch.autograd.Function whose backward is the
+library's adjoint kernel (fragments are recomputed from the saved
+visibility buffer, never stored).
+
+All arithmetic runs in libdiffsoup.so; this module only allocates outputs
+with torch and marshals pointers.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+@dataclasses.dataclass
+class DeviceScene:
+    verts: torch.Tensor        # [T,3,3] float32, cuda
+    feats: torch.Tensor        # [T,G,G,C]
+    mlp: torch.Tensor          # [n_params]
+    dims: List[int]
+
+    @staticmethod
+    def from_host(scene, device="cuda") -> "DeviceScene":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        return DeviceScene(t(scene.verts), t(scene.feats), t(scene.mlp), list(scene.dims))
+
+    @property
+    def T(self) -> int:
+        return int(self.verts.shape[0])
+
+    def n_params(self) -> int:
+        d = self.dims
+        return int(sum(o * i + o for i, o in zip(d[:-1], d[1:])))
+
+    def c_struct(self, h: _lib._Holder, verts=None, feats=None, mlp=None) -> _lib.soup_scene:
+        return _lib.make_scene(h, self.verts if verts is None else verts, self.feats if feats is None else feats,
+                               self.mlp if mlp is None else mlp, self.dims)
+
+
+@dataclasses.dataclass
+class Views:
+    widths: np.ndarray
+    heights: np.ndarray
+    view_ids: np.ndarray
+    view_proj: np.ndarray      # [V,4,4] float32 (host)
+
+    @staticmethod
+    def from_list(views) -> "Views":
+        return Views(np.array([v.width for v in views], np.int32), np.array([v.height for v in views], np.int32),
+                     np.array([v.view_id for v in views], np.uint32),
+                     np.stack([np.asarray(v.M, np.float32) for v in views]))
+
+    @property
+    def V(self) -> int:
+        return int(len(self.widths))
+
+    @property
+    def pixels(self) -> int:
+        return int((self.widths.astype(np.int64) * self.heights).sum())
+
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.widths.astype(np.int64) * self.heights)])
+
+    def c_struct(self, h: _lib._Holder) -> _lib.soup_views:
+        return _lib.make_views(h, self.widths, self.heights, self.view_ids, self.view_proj)
+
+
+@dataclasses.dataclass
+class Opts:
+    seed: int = 0
+    step: int = 0
+    mode: int = 0              # 0 stochastic masking, 1 threshold
+    background: tuple = (0.0, 0.0, 0.0)
+    edge_pairs: int = 0        # 0 all pairs, 1 id change, 2 none
+    near_w: float = 0.1
+
+    def c_struct(self) -> _lib.soup_opts:
+        return _lib.make_opts(self.seed, self.step, self.mode, self.background, self.edge_pairs, self.near_w)
+
+
+_ctx_cache = {}
+
+
+def context(device: Optional[int] = None) -> _lib.Ctx:
+    if device is None:
+        device = torch.cuda.current_device()
+    c = _ctx_cache.get(device)
+    if c is None:
+        c = _ctx_cache[device] = _lib.Ctx(device)
+    return c
+
+
+def rasterize_fwd(scene: DeviceScene, views: Views, opts: Opts, want_logp: bool = False,
+                  ctx: Optional[_lib.Ctx] = None, stream=None):
+    """vis [P] int64 (uint64 bits), color [P,3], logp [P] or None."""
+    ctx = ctx or context()
+    dev = scene.verts.device
+    P = views.pixels
+    vis = torch.empty(P, dtype=torch.int64, device=dev)
+    color = torch.empty(P, 3, dtype=torch.float32, device=dev)
+    logp = torch.empty(P, dtype=torch.float32, device=dev) if want_logp else None
+    h = _lib._Holder()
+    _lib.soup_rasterize_fwd(ctx, scene.c_struct(h), views.c_struct(h), opts.c_struct(), vis, color, logp, stream)
+    return vis, color, logp
+
+
+def rasterize_bwd(scene: DeviceScene, views: Views, opts: Opts, vis, color, grad_color, grad_logp=None,
+                  ctx: Optional[_lib.Ctx] = None, stream=None, out=None):
+    ctx = ctx or context()
+    if out is None:
+        gv = torch.empty_like(scene.verts)
+        gf = torch.empty_like(scene.feats)
+        gm = torch.empty_like(scene.mlp)
+    else:
+        gv, gf, gm = out
+    h = _lib._Holder()
+    _lib.soup_rasterize_bwd(ctx, scene.c_struct(h), views.c_struct(h), opts.c_struct(), vis, color,
+                            grad_color.contiguous(), None if grad_logp is None else grad_logp.contiguous(),
+                            gv, gf, gm, stream)
+    return gv, gf, gm
+
+
+def render(scenes: Sequence[DeviceScene], views: Views, opts: Opts, colors=None, ctx=None, stream=None):
+    """Forward-only batched render: request r = scenes[r] seen from view r."""
+    ctx = ctx or context()
+    if colors is None:
+        colors = [torch.empty(int(views.heights[r]), int(views.widths[r]), 3, dtype=torch.float32,
+                              device=scenes[r].verts.device) for r in range(len(scenes))]
+    h = _lib._Holder()
+    _lib.soup_render(ctx, [s.c_struct(h) for s in scenes], views.c_struct(h), opts.c_struct(), colors, stream)
+    return colors
+
+
+def loss_l2(color, target, ctx=None, stream=None):
+    ctx = ctx or context()
+    gc = torch.empty_like(color)
+    gl = torch.empty(color.shape[0], dtype=torch.float32, device=color.device)
+    loss = torch.empty(1, dtype=torch.float32, device=color.device)
+    _lib.soup_loss_l2(ctx, color, target, gc, gl, loss, stream)
+    return loss, gc, gl
+
+
+class SoupRasterize(torch.autograd.Function):
+    """(verts, feats, mlp) -> (color [P,3], logp [P]).
+
+    The gradient of logp is the per-pixel weight of the score term: a loss
+    written as L(color) + (L_pixel(color).detach() * logp).sum() reproduces
+    the estimator of Eq. (8) (Algorithm A1's L * s). The visibility buffer
+    is saved; the backward recomputes fragments from it."""
+
+    @staticmethod
+    def forward(fctx, verts, feats, mlp, dims, views: Views, opts: Opts):
+        scene = DeviceScene(verts.contiguous(), feats.contiguous(), mlp.contiguous(), list(dims))
+        vis, color, logp = rasterize_fwd(scene, views, opts, want_logp=opts.mode == 0)
+        if logp is None:
+            logp = torch.zeros(color.shape[0], dtype=torch.float32, device=color.device)
+        fctx.save_for_backward(scene.verts, scene.feats, scene.mlp, vis, color)
+        fctx.dims, fctx.views, fctx.opts = list(dims), views, opts
+        fctx.mark_non_differentiable(vis)
+        return color, logp, vis
+
+    @staticmethod
+    def backward(fctx, grad_color, grad_logp, _grad_vis):
+        verts, feats, mlp, vis, color = fctx.saved_tensors
+        scene = DeviceScene(verts, feats, mlp, fctx.dims)
+        if grad_color is None:
+            grad_color = torch.zeros_like(color)
+        gv, gf, gm = rasterize_bwd(scene, fctx.views, fctx.opts, vis, color, grad_color, grad_logp)
+        return gv, gf, gm, None, None, None
+
+
+def rasterize(verts, feats, mlp, dims, views: Views, opts: Opts):
+    """Differentiable rasterization: returns (color [P,3], logp [P], vis [P])."""
+    return SoupRasterize.apply(verts, feats, mlp, dims, views, opts)
