@@ -1,0 +1,233 @@
+"""Benchmark of one differentiable rasterization step on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+soup_rasterize_fwd (setup, tile binning, raster with stochastic opacity
+masking, winner shading) -> soup_loss_l2 (L2 against a random target) ->
+soup_rasterize_bwd (setup and bins recomputed, front-set replay with colour
+and score gradients, edge term, vertex chain, MLP-gradient reduction), all on
+one stream with inputs resident in HBM.
+
+Workload (default): the batched configuration -- 50,000 triangles (centres
+uniform in the unit ball, equilateral, side exp(N(-3, 0.5^2))), 8x8x16
+features, MLP 16->32->32->4, 64 views on a Fibonacci sphere of radius 3 with
+resolutions drawn from {256, 512, 800, 1024}^2, all views in one call.
+
+Prints ONE JSON line. Besides the metric it reports the per-view path (a host
+loop over the 64 views on the same GPU), the roofline of the dominant kernel
+(from HIP events recorded around it on its own stream during the timed
+steps) and the CPU oracle timed on a bounded sample on the host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published fp32 vector peak (packed FMA)
+PEAK_HBM_GBS = 8000.0
+
+
+def mlp_macs(dims):
+    return int(sum(i * o for i, o in zip(dims[:-1], dims[1:])))
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched", choices=["batched", "single", "large", "tiny"])
+    ap.add_argument("--tile", type=int, default=0, help="tile side (0: autotuned/default)")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-per-view", action="store_true")
+    ap.add_argument("--cpu-pixels", type=float, default=1.5e6, help="oracle sample size in pixels")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+    import torch
+    from paper_2603_27151_amd import raster as R
+    from paper_2603_27151_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    wl = W.by_name(args.workload)
+    ds = R.DeviceScene.from_host(wl.scene)
+    vs = R.Views.from_list(wl.views)
+    P = vs.pixels
+    target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
+    ctx = R.context()
+    tile = args.tile
+    if tile == 0:
+        try:
+            from paper_2603_27151_amd import autotune
+            tile = autotune.cached_tile(args.workload) or 16
+        except Exception:
+            tile = 16
+    ctx.set_tile(tile)
+    opts = R.Opts(seed=wl.seed, step=wl.step)
+    gv = torch.empty_like(ds.verts)
+    gf = torch.empty_like(ds.feats)
+    gm = torch.empty_like(ds.mlp)
+    log(f"workload {args.workload}: T={ds.T} views={vs.V} pixels={P} tile={tile}")
+
+    def step():
+        vis, color, _ = R.rasterize_fwd(ds, vs, opts, ctx=ctx)
+        loss, gc, gl = R.loss_l2(color, target, ctx=ctx)
+        R.rasterize_bwd(ds, vs, opts, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # work counts of the step (outside the timed region)
+    ctx.set_counting(True)
+    vis, color, _ = R.rasterize_fwd(ds, vs, opts, ctx=ctx)
+    st_fwd = ctx.stats()
+    loss, gc, gl = R.loss_l2(color, target, ctx=ctx)
+    R.rasterize_bwd(ds, vs, opts, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
+    st_bwd = ctx.stats()
+    ctx.set_counting(False)
+    torch.cuda.synchronize()
+    covered = int((vis != -1).sum().item())
+    E = st_bwd["decodes"]          # front set + winner of every pixel: the method's decodes
+    log(f"counts: bins={st_fwd['bin_entries']} fwd decodes={st_fwd['decodes']} E={E} covered={covered}")
+
+    # timed region
+    ctx.read_timings()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    kern = ctx.read_timings()
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    ms = max(wall_ms, ev_ms)
+    mpix = P / (ms * 1e-3) / 1e6
+    log(f"batched step {ms:.3f} ms -> {mpix:.1f} Mpixel/s")
+    per_kernel = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
+    log("per-kernel avg ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_kernel.items() if v > 0))
+
+    # per-view path on the same GPU: a host loop of single-view calls,
+    # gradients summed in place (accumulate)
+    per_view = None
+    if not args.skip_per_view:
+        singles = [R.Views.from_list([v]) for v in wl.views]
+        offs = vs.offsets()
+        opts_acc = R.Opts(seed=wl.seed, step=wl.step, accumulate=1)
+
+        def step_pv():
+            gv.zero_()
+            gf.zero_()
+            gm.zero_()
+            for i, sv in enumerate(singles):
+                vis_i, col_i, _ = R.rasterize_fwd(ds, sv, opts, ctx=ctx)
+                _, gc_i, gl_i = R.loss_l2(col_i, target[offs[i]:offs[i + 1]], ctx=ctx)
+                R.rasterize_bwd(ds, sv, opts_acc, vis_i, col_i, gc_i, gl_i, ctx=ctx, out=(gv, gf, gm))
+
+        step_pv()
+        torch.cuda.synchronize()
+        n_pv = max(2, args.steps // 3)
+        t0 = time.perf_counter()
+        for _ in range(n_pv):
+            step_pv()
+        torch.cuda.synchronize()
+        pv_ms = (time.perf_counter() - t0) * 1e3 / n_pv
+        per_view = {"ms_per_step": round(pv_ms, 3), "mpixel_s": round(P / (pv_ms * 1e-3) / 1e6, 1),
+                    "batched_speedup": round(pv_ms / ms, 3)}
+        log(f"per-view path {pv_ms:.3f} ms -> {per_view['mpixel_s']} Mpixel/s")
+
+    # roofline of the dominant kernel
+    macs = mlp_macs(ds.dims)
+    t_bwd = per_kernel["raster_bwd"]
+    t_fwd = per_kernel["raster_fwd"]
+    flops_bwd = 6.0 * macs * E          # recompute + data backward + weight gradient per decode
+    flops_fwd = 2.0 * macs * E          # one decode per fragment up to the winner
+    if t_bwd >= t_fwd:
+        dom, t_dom, fl = "raster_bwd", t_bwd, flops_bwd
+    else:
+        dom, t_dom, fl = "raster_fwd", t_fwd, flops_fwd
+    achieved = fl / (t_dom * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": fl, "avg_launch_ms": round(t_dom, 4)}
+
+    # CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.skip_cpu:
+        from oracle import oracle as O
+        oo = O.Opts(seed=wl.seed, step=wl.step)
+        sample, npx = [], 0
+        for v in wl.views:
+            if npx >= args.cpu_pixels and sample:
+                break
+            sample.append(v)
+            npx += v.width * v.height
+        t0 = time.perf_counter()
+        Ptot = P
+        for i, v in enumerate(sample):
+            rv, rc, _, _ = O.forward(wl.scene, v, oo, want_logp=False)
+            d = rc - wl.targets[i]
+            g_c = (2 * d / np.float32(3 * Ptot)).astype(np.float32)
+            g_l = ((d * d).sum(-1) / np.float32(3 * Ptot)).astype(np.float32)
+            O.backward(wl.scene, v, oo, rv, rc, g_c, g_l)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(npx / cpu_s / 1e6, 4), "unit": "Mpixel/s", "cores": O.threads(),
+               "kind": "oracle",
+               "sample": f"fwd+bwd of the first {len(sample)} of {vs.V} views ({npx} pixels) in {cpu_s:.1f} s"}
+        log(f"cpu oracle {cpu['value']} Mpixel/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "fwd+bwd Mpixel/s (batched vs per-view) at <=1e-4 grad rel err; render p50/p99 ms",
+        "value": round(mpix, 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {ds.T} triangles, {vs.V} views, {P} pixels, "
+                               f"features {wl.scene.G}x{wl.scene.G}x{wl.scene.C}, MLP "
+                               + "->".join(str(d) for d in ds.dims),
+                   "tile": tile, "triangles_per_s": round(ds.T * vs.V / (ms * 1e-3), 1),
+                   "decodes_E": E, "covered_pixels": covered, "bin_entries": st_fwd["bin_entries"]},
+        "per_view": per_view,
+        "kernels_ms": {k: round(v, 4) for k, v in per_kernel.items() if v > 0},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

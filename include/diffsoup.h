@@ -79,6 +79,7 @@ typedef struct {
     int32_t edge_pairs;        /* 0: every adjacent pixel pair (Section 3.2); 1: only pairs whose
                                   triangle id differs; 2: no edge term */
     float near_w;              /* triangles with any vertex at clip w < near_w are culled (0.1) */
+    int32_t accumulate;        /* backward: 0 overwrite the gradient outputs, 1 add into them */
 } soup_opts;
 
 /* Work counts of the last compute call on a context (filled on request). */
@@ -103,6 +104,30 @@ const char* soup_last_error(const soup_ctx* ctx);
 /* Screen tile side in pixels: 8, 16 (default) or 32. */
 soup_status soup_ctx_set_tile(soup_ctx* ctx, int32_t tile);
 int32_t soup_ctx_get_tile(const soup_ctx* ctx);
+
+/* Per-kernel timing. When enabled, every launch group of a compute call is
+ * bracketed by a pair of HIP events recorded on the call's stream (no
+ * synchronisation is added). soup_read_timings synchronises those events,
+ * adds their elapsed times into ms[k] and the number of launches into
+ * count[k] for k < SOUP_TIMING_KINDS (arrays of that length, host), and
+ * forgets them. Kinds: */
+enum {
+    SOUP_T_SETUP = 0,    /* triangle setup + per-tile counts */
+    SOUP_T_SCAN = 1,     /* tile offsets */
+    SOUP_T_SCATTER = 2,  /* tile lists */
+    SOUP_T_SORT = 3,     /* per-tile depth sort */
+    SOUP_T_FWD = 4,      /* forward raster */
+    SOUP_T_BWD = 5,      /* backward raster (front-set replay) */
+    SOUP_T_EDGE = 6,     /* edge term */
+    SOUP_T_CHAIN = 7,    /* vertex chain */
+    SOUP_T_REDUCE = 8,   /* MLP-gradient reduction */
+    SOUP_T_LOGP = 9,     /* log p(f*) pass */
+    SOUP_T_LOSS = 10,    /* L2 loss */
+    SOUP_T_FILL = 11,    /* zero fills */
+    SOUP_TIMING_KINDS = 12
+};
+soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
+soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);
 
 /* Enable (1) or disable (0, default) counting of decodes in soup_stats. */
 soup_status soup_ctx_set_counting(soup_ctx* ctx, int32_t on);
@@ -132,8 +157,9 @@ soup_status soup_rasterize_fwd(soup_ctx* ctx, const soup_scene* scene, const sou
  * Inputs: vis and color from soup_rasterize_fwd with the same arguments;
  * grad_color [P,3] = dL/dcolor; grad_logp [P] = per-pixel weight of the score
  * term (the sampled pixel loss for Algorithm A1's L * s), or NULL.
- * Outputs (device, overwritten): grad_verts [T,3,3], grad_feats [T,G,G,C],
- * grad_mlp [n_params].
+ * Outputs (device): grad_verts [T,3,3], grad_feats [T,G,G,C], grad_mlp
+ * [n_params]; overwritten, or added into when opts->accumulate is 1 (a loop
+ * over views can then sum its gradients in place).
  *   winner f*:        colour path (exact derivative with draws fixed) plus
  *                     score g_L (1 - alpha*) on its opacity logit;
  *   f in front of f*: score -g_L alpha_f on its opacity logit (features and

@@ -36,7 +36,8 @@ class soup_views(C.Structure):
 
 class soup_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("mode", C.c_int32),
-                ("background", C.c_float * 3), ("edge_pairs", C.c_int32), ("near_w", C.c_float)]
+                ("background", C.c_float * 3), ("edge_pairs", C.c_int32), ("near_w", C.c_float),
+                ("accumulate", C.c_int32)]
 
 
 class soup_stats(C.Structure):
@@ -47,7 +48,9 @@ class soup_stats(C.Structure):
 EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_set_tile",
            "soup_ctx_get_tile", "soup_ctx_set_counting", "soup_last_stats", "soup_rasterize_fwd",
            "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
-           "soup_selftest_uniform"]
+           "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings"]
+TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "raster_bwd", "edge", "vertex_chain",
+                "mlp_reduce", "logp", "loss", "fill"]
 
 _lib = None
 
@@ -79,9 +82,12 @@ def lib() -> C.CDLL:
     L.soup_loss_l2.argtypes = [P, P, P, C.c_int64, P, P, P, P]
     L.soup_selftest_sigmoid.argtypes = [P, P, P, C.c_int64, P]
     L.soup_selftest_uniform.argtypes = [P, C.c_uint64, P, P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
+    L.soup_ctx_set_timing.argtypes = [P, C.c_int32]
+    L.soup_read_timings.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
-                 "soup_selftest_sigmoid", "soup_selftest_uniform"]:
+                 "soup_selftest_sigmoid", "soup_selftest_uniform", "soup_ctx_set_timing",
+                 "soup_read_timings"]:
         getattr(L, name).restype = C.c_int
     L.soup_ctx_get_tile.restype = C.c_int32
     _lib = L
@@ -143,9 +149,10 @@ def make_views(h: _Holder, widths, heights, view_ids, view_proj) -> soup_views:
                       h.arr(M, C.c_float))
 
 
-def make_opts(seed=0, step=0, mode=0, background=(0.0, 0.0, 0.0), edge_pairs=0, near_w=0.1) -> soup_opts:
+def make_opts(seed=0, step=0, mode=0, background=(0.0, 0.0, 0.0), edge_pairs=0, near_w=0.1,
+              accumulate=0) -> soup_opts:
     return soup_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), int(mode), (C.c_float * 3)(*background),
-                     int(edge_pairs), float(near_w))
+                     int(edge_pairs), float(near_w), int(accumulate))
 
 
 class Ctx:
@@ -184,6 +191,17 @@ class Ctx:
 
     def set_counting(self, on: bool):
         self.check(lib().soup_ctx_set_counting(self.p, 1 if on else 0))
+
+    def set_timing(self, on: bool):
+        self.check(lib().soup_ctx_set_timing(self.p, 1 if on else 0))
+
+    def read_timings(self) -> dict:
+        """{kind: (total ms, launches)} of the events recorded since the last read."""
+        n = len(TIMING_KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        self.check(lib().soup_read_timings(self.p, ms, cnt))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
 
     def stats(self) -> dict:
         s = soup_stats()

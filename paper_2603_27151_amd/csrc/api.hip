@@ -31,6 +31,14 @@ struct soup_ctx {
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
     void* host_stage = nullptr;      // pinned: descriptors up, totals down
     size_t host_stage_bytes = 0;
+    // optional per-kernel timing: recorded event pairs and a pool of free events
+    bool timing = false;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -87,6 +95,45 @@ soup_status ensure_host(soup_ctx* c, size_t bytes) {
 
 }  // namespace
 
+namespace {
+
+hipEvent_t take_event(soup_ctx* c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Brackets the launches made during its lifetime with two events (timing on).
+struct Timed {
+    soup_ctx* c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Timed(soup_ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
+        if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, s);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) {
+            c->pool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, s);
+        c->marks.push_back({kind, a, b});
+    }
+};
+
+}  // namespace
+
 namespace soup {
 
 MlpKind mlp_kind(int n_layers, const int32_t* dims) {
@@ -140,6 +187,8 @@ soup_status check_views(soup_ctx* c, const soup_views* v) {
 soup_status check_opts(soup_ctx* c, const soup_opts* o) {
     if (!o) return fail(c, SOUP_ERR_INVALID, "opts is NULL");
     if (o->mode != 0 && o->mode != 1) return fail(c, SOUP_ERR_INVALID, "opts.mode = %d (0 or 1)", o->mode);
+    if (o->accumulate != 0 && o->accumulate != 1)
+        return fail(c, SOUP_ERR_INVALID, "opts.accumulate = %d (0 or 1)", o->accumulate);
     if (o->edge_pairs < 0 || o->edge_pairs > 2)
         return fail(c, SOUP_ERR_INVALID, "opts.edge_pairs = %d (0, 1 or 2)", o->edge_pairs);
     if (!(o->near_w > 0.0f)) return fail(c, SOUP_ERR_INVALID, "opts.near_w must be > 0");
@@ -156,6 +205,7 @@ Opts to_opts(const soup_opts* o) {
     r.bg[2] = o->background[2];
     r.edge_pairs = o->edge_pairs;
     r.near_w = o->near_w;
+    r.accumulate = o->accumulate;
     return r;
 }
 
@@ -216,24 +266,39 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     HIP_TRY(c, hipMemcpyAsync(c->views.p, hs, vbytes, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->scenes.p, hs + vbytes, sbytes, hipMemcpyHostToDevice, s));
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
-    launch_fill_i32(reinterpret_cast<int32_t*>(cnt), 16, 0, s);
-    launch_fill_i32(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, 0, s);
+    {
+        Timed t(c, SOUP_T_FILL, s);
+        launch_fill_i32(reinterpret_cast<int32_t*>(cnt), 16, 0, s);
+        launch_fill_i32(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, 0, s);
+    }
+    {
+    Timed t_setup(c, SOUP_T_SETUP, s);
     launch_setup(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT,
                  static_cast<SceneDesc*>(c->scenes.p), o, c->tile, static_cast<TriRec*>(c->recs.p),
                  static_cast<int32_t*>(c->tile_count.p), c->counting ? cnt + 1 : nullptr, s);
-    launch_scan(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, static_cast<int64_t*>(c->bsum.p),
-                static_cast<int64_t*>(c->tile_start.p), s);
+    }
+    {
+        Timed t(c, SOUP_T_SCAN, s);
+        launch_scan(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, static_cast<int64_t*>(c->bsum.p),
+                    static_cast<int64_t*>(c->tile_start.p), s);
+    }
     int64_t* htotal = reinterpret_cast<int64_t*>(hs + vbytes + sbytes);
     HIP_TRY(c, hipMemcpyAsync(htotal, static_cast<int64_t*>(c->tile_start.p) + p.n_tiles, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(s));
     const int64_t total = *htotal;
     if ((st = ensure(c, c->entries, static_cast<size_t>(total) * 8))) return st;
-    launch_fill_i32(static_cast<int32_t*>(c->tile_fill.p), p.n_tiles, 0, s);
-    launch_scatter(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, c->tile,
-                   static_cast<TriRec*>(c->recs.p), static_cast<int64_t*>(c->tile_start.p),
-                   static_cast<int32_t*>(c->tile_fill.p), static_cast<uint64_t*>(c->entries.p), s);
-    launch_sort(static_cast<int64_t*>(c->tile_start.p), p.n_tiles, static_cast<uint64_t*>(c->entries.p), s);
+    {
+        Timed t(c, SOUP_T_SCATTER, s);
+        launch_fill_i32(static_cast<int32_t*>(c->tile_fill.p), p.n_tiles, 0, s);
+        launch_scatter(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, c->tile,
+                       static_cast<TriRec*>(c->recs.p), static_cast<int64_t*>(c->tile_start.p),
+                       static_cast<int32_t*>(c->tile_fill.p), static_cast<uint64_t*>(c->entries.p), s);
+    }
+    {
+        Timed t(c, SOUP_T_SORT, s);
+        launch_sort(static_cast<int64_t*>(c->tile_start.p), p.n_tiles, static_cast<uint64_t*>(c->entries.p), s);
+    }
     HIP_TRY(c, hipGetLastError());
     c->stats.pixels = p.n_pix;
     c->stats.tiles = p.n_tiles;
@@ -330,6 +395,11 @@ void soup_ctx_destroy(soup_ctx* c) {
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
+    for (auto& m : c->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -343,6 +413,30 @@ soup_status soup_ctx_set_tile(soup_ctx* c, int32_t tile) {
 }
 
 int32_t soup_ctx_get_tile(const soup_ctx* c) { return c ? c->tile : 0; }
+
+soup_status soup_ctx_set_timing(soup_ctx* c, int32_t on) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->timing = on != 0;
+    return SOUP_OK;
+}
+
+soup_status soup_read_timings(soup_ctx* c, double* ms, int64_t* count) {
+    if (!c || !ms || !count) return SOUP_ERR_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (auto& m : c->marks) {
+        HIP_TRY(c, hipEventSynchronize(m.b));
+        float t = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&t, m.a, m.b));
+        if (m.kind >= 0 && m.kind < SOUP_TIMING_KINDS) {
+            ms[m.kind] += t;
+            count[m.kind] += 1;
+        }
+        c->pool.push_back(m.a);
+        c->pool.push_back(m.b);
+    }
+    c->marks.clear();
+    return SOUP_OK;
+}
 
 soup_status soup_ctx_set_counting(soup_ctx* c, int32_t on) {
     if (!c) return SOUP_ERR_INVALID;
@@ -372,9 +466,13 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
     RasterArgs a = raster_args(c, p, o);
     a.vis = vis;
     a.color = color;
-    launch_raster_fwd(a, c->tile, p.kind, s);
+    {
+        Timed t(c, SOUP_T_FWD, s);
+        launch_raster_fwd(a, c->tile, p.kind, s);
+    }
     HIP_TRY(c, hipGetLastError());
     if (logp) {
+        Timed t(c, SOUP_T_LOGP, s);
         if (o.mode != 0) {
             launch_fill_f32(logp, p.n_pix, 0.0f, s);
         } else {
@@ -414,10 +512,14 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)))
         return st;
     const int T = scene->T;
-    launch_fill_f32(grad_feats, static_cast<int64_t>(T) * scene->G * scene->G * scene->C, 0.0f, s);
-    launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
     RasterArgs a = raster_args(c, p, o);
-    launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+    {
+        Timed t(c, SOUP_T_FILL, s);
+        if (!o.accumulate)
+            launch_fill_f32(grad_feats, static_cast<int64_t>(T) * scene->G * scene->G * scene->C, 0.0f, s);
+        launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
+        launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+    }
     BwdArgs b{};
     b.r = a;
     b.vis = vis;
@@ -428,10 +530,22 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     b.vacc = static_cast<float*>(c->vacc.p);
     b.mlp_partial = static_cast<float*>(c->partial.p);
     b.n_blocks = nb;
-    launch_raster_bwd(b, c->tile, p.kind, false, s);
-    launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, b.vacc, s);
-    launch_vertex_chain(a.views, a.V, a.scenes, T, a.recs, b.vacc, grad_verts, s);
-    launch_mlp_reduce(b.mlp_partial, rows, p.n_params, grad_mlp, s);
+    {
+        Timed t(c, SOUP_T_BWD, s);
+        launch_raster_bwd(b, c->tile, p.kind, false, s);
+    }
+    {
+        Timed t(c, SOUP_T_EDGE, s);
+        launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, b.vacc, s);
+    }
+    {
+        Timed t(c, SOUP_T_CHAIN, s);
+        launch_vertex_chain(a.views, a.V, a.scenes, T, a.recs, b.vacc, grad_verts, o.accumulate != 0, s);
+    }
+    {
+        Timed t(c, SOUP_T_REDUCE, s);
+        launch_mlp_reduce(b.mlp_partial, rows, p.n_params, grad_mlp, o.accumulate != 0, s);
+    }
     HIP_TRY(c, hipGetLastError());
     return finish_stats(c, s);
 }
@@ -479,7 +593,10 @@ soup_status soup_render(soup_ctx* c, const soup_scene* scenes, int32_t R, const 
     RasterArgs a = raster_args(c, p, o);
     a.vis = nullptr;
     a.color = nullptr;
-    launch_raster_fwd(a, c->tile, p.kind, s);
+    {
+        Timed t(c, SOUP_T_FWD, s);
+        launch_raster_fwd(a, c->tile, p.kind, s);
+    }
     HIP_TRY(c, hipGetLastError());
     return finish_stats(c, s);
 }
@@ -491,7 +608,10 @@ soup_status soup_loss_l2(soup_ctx* c, const float* color, const float* target, i
     if (P < 0 || (P > 0 && (!color || !target || !grad_color || !grad_logp)))
         return fail(c, SOUP_ERR_INVALID, "loss_l2: bad arguments");
     HIP_TRY(c, hipSetDevice(c->device));
-    launch_loss_l2(color, target, P, grad_color, grad_logp, loss, static_cast<hipStream_t>(stream));
+    {
+        Timed t(c, SOUP_T_LOSS, static_cast<hipStream_t>(stream));
+        launch_loss_l2(color, target, P, grad_color, grad_logp, loss, static_cast<hipStream_t>(stream));
+    }
     HIP_TRY(c, hipGetLastError());
     return SOUP_OK;
 }

@@ -83,7 +83,7 @@ struct Opts {
     float bg[3];
     int32_t edge_pairs;
     float near_w;
-    int32_t pad0;
+    int32_t accumulate;
 };
 
 // --------------------------------------------------------------------------

@@ -245,6 +245,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
             }
             mlp_forward<S>(mlp, x, m);
             const float alpha = sigmoid_c(m.o[3]);
+            if (r.counter && lane == 0) atomicAdd(r.counter, static_cast<unsigned long long>(n));
             if (LOGP) {
                 if (on && r.o.mode == 0) atomicAdd(&s_gl[pl], win ? logf(alpha) : log1pf(-alpha));
                 return;
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(256) void vertex_chain_kernel(const ViewDesc* __res
                                                            const SceneDesc* __restrict__ scenes, int T,
                                                            const TriRec* __restrict__ recs,
                                                            const float* __restrict__ vacc,
-                                                           float* __restrict__ grad_verts) {
+                                                           float* __restrict__ grad_verts, bool accumulate) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
     const float* vt = scenes[0].verts + static_cast<size_t>(t) * 9;
@@ -624,14 +625,17 @@ __global__ __launch_bounds__(256) void vertex_chain_kernel(const ViewDesc* __res
         }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) grad_verts[static_cast<size_t>(t) * 9 + i] = g[i];
+    for (int i = 0; i < 9; ++i) {
+        float* o = grad_verts + static_cast<size_t>(t) * 9 + i;
+        *o = accumulate ? *o + g[i] : g[i];
+    }
 }
 
 void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
-                         const float* vacc, float* grad_verts, hipStream_t s) {
+                         const float* vacc, float* grad_verts, bool accumulate, hipStream_t s) {
     if (T <= 0) return;
     hipLaunchKernelGGL(vertex_chain_kernel, dim3((T + 255) / 256), dim3(256), 0, s, views, V, scenes, T, recs, vacc,
-                       grad_verts);
+                       grad_verts, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -639,17 +643,17 @@ void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, 
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int n_rows, int n_params,
-                                                         float* __restrict__ out) {
+                                                         float* __restrict__ out, bool accumulate) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_params) return;
-    double s = 0.0;
+    double s = accumulate ? static_cast<double>(out[p]) : 0.0;
     for (int r = 0; r < n_rows; ++r) s += partial[static_cast<size_t>(r) * n_params + p];
     out[p] = static_cast<float>(s);
 }
 
-void launch_mlp_reduce(const float* partial, int n_rows, int n_params, float* out, hipStream_t s) {
+void launch_mlp_reduce(const float* partial, int n_rows, int n_params, float* out, bool accumulate, hipStream_t s) {
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((n_params + 255) / 256), dim3(256), 0, s, partial, n_rows, n_params,
-                       out);
+                       out, accumulate);
 }
 
 // ---------------------------------------------------------------------------

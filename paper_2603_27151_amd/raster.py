@@ -78,9 +78,11 @@ class Opts:
     background: tuple = (0.0, 0.0, 0.0)
     edge_pairs: int = 0        # 0 all pairs, 1 id change, 2 none
     near_w: float = 0.1
+    accumulate: int = 0        # backward: 1 = add into the gradient outputs
 
     def c_struct(self) -> _lib.soup_opts:
-        return _lib.make_opts(self.seed, self.step, self.mode, self.background, self.edge_pairs, self.near_w)
+        return _lib.make_opts(self.seed, self.step, self.mode, self.background, self.edge_pairs, self.near_w,
+                              self.accumulate)
 
 
 _ctx_cache = {}
