@@ -29,6 +29,8 @@ struct soup_ctx {
     std::string err;
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
+    DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum;
+    uint64_t rec_cap_hint = 0;       // records of the last backward, to size the next
     void* host_stage = nullptr;      // pinned: descriptors up, totals down
     size_t host_stage_bytes = 0;
     // optional per-kernel timing: recorded event pairs and a pool of free events
@@ -161,6 +163,9 @@ soup_status check_scene(soup_ctx* c, const soup_scene* s, MlpKind* kind) {
         return fail(c, SOUP_ERR_INVALID, "scene.n_layers = %d or dims missing", s->n_layers);
     if (s->dims[0] != s->C) return fail(c, SOUP_ERR_INVALID, "dims[0] = %d != C = %d", s->dims[0], s->C);
     if (s->dims[s->n_layers] != 4) return fail(c, SOUP_ERR_INVALID, "dims[last] = %d != 4", s->dims[s->n_layers]);
+    if (static_cast<int64_t>(s->G) * s->G * s->C > 12288)
+        return fail(c, SOUP_ERR_UNSUPPORTED, "G*G*C = %d exceeds the per-triangle LDS reduction (12288)",
+                    s->G * s->G * s->C);
     if (s->T > 0 && (!s->verts || !s->feats || !s->mlp))
         return fail(c, SOUP_ERR_INVALID, "scene device pointers are NULL");
     *kind = soup::mlp_kind(s->n_layers, s->dims);
@@ -390,8 +395,9 @@ void soup_ctx_destroy(soup_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&c->views, &c->scenes, &c->recs, &c->tile_count, &c->tile_fill, &c->tile_start,
-                      &c->bsum, &c->entries, &c->vacc, &c->partial, &c->counters};
+    DevBuf* bufs[] = {&c->views,    &c->scenes,  &c->recs,      &c->tile_count, &c->tile_fill, &c->tile_start,
+                      &c->bsum,     &c->entries, &c->vacc,      &c->partial,    &c->counters,  &c->records,
+                      &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -508,43 +514,83 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     if ((st = bin(c, p, o, s))) return st;
     const int nb = persistent_blocks(c, p);
     const int rows = nb * waves_per_block(c->tile);
-    if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
-        (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)))
-        return st;
     const int T = scene->T;
+    const int RS = rec_stride(scene->C);
+    if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
+        (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)) ||
+        (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
+        (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 4)) ||
+        (st = ensure(c, c->tri_off, static_cast<size_t>(T + 1) * 8)) ||
+        (st = ensure(c, c->tri_bsum, static_cast<size_t>((T + 1023) / 1024 + 1) * 8)))
+        return st;
     RasterArgs a = raster_args(c, p, o);
-    {
-        Timed t(c, SOUP_T_FILL, s);
-        if (!o.accumulate)
-            launch_fill_f32(grad_feats, static_cast<int64_t>(T) * scene->G * scene->G * scene->C, 0.0f, s);
-        launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
-        launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+    unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
+    // record capacity: last call's count with headroom, else 1.5 records per pixel
+    uint64_t cap = c->rec_cap_hint ? c->rec_cap_hint + c->rec_cap_hint / 4
+                                   : static_cast<uint64_t>(p.n_pix) * 3 / 2 + 1024;
+    int64_t n_rec = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if ((st = ensure(c, c->records, static_cast<size_t>(cap) * RS * 4)) ||
+            (st = ensure(c, c->rec_tri, static_cast<size_t>(cap) * 4)))
+            return st;
+        {
+            Timed t(c, SOUP_T_FILL, s);
+            launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
+            launch_fill_i32(static_cast<int32_t*>(c->tri_count.p), T, 0, s);
+            launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+            launch_fill_i32(reinterpret_cast<int32_t*>(cnt + 3), 2, 0, s);
+        }
+        BwdArgs b{};
+        b.r = a;
+        b.vis = vis;
+        b.color = color;
+        b.grad_color = grad_color;
+        b.grad_logp = grad_logp;
+        b.vacc = static_cast<float*>(c->vacc.p);
+        b.mlp_partial = static_cast<float*>(c->partial.p);
+        b.records = static_cast<float*>(c->records.p);
+        b.rec_tri = static_cast<uint32_t*>(c->rec_tri.p);
+        b.rec_cap = cap;
+        b.rec_count = cnt + 3;
+        b.tri_count = static_cast<int32_t*>(c->tri_count.p);
+        b.n_blocks = nb;
+        {
+            Timed t(c, SOUP_T_BWD, s);
+            launch_raster_bwd(b, c->tile, p.kind, false, s);
+        }
+        HIP_TRY(c, hipGetLastError());
+        int64_t* hcount = reinterpret_cast<int64_t*>(c->host_stage);
+        HIP_TRY(c, hipMemcpyAsync(hcount, cnt + 3, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        n_rec = *hcount;
+        if (static_cast<uint64_t>(n_rec) <= cap) break;
+        cap = static_cast<uint64_t>(n_rec) + static_cast<uint64_t>(n_rec) / 8 + 1024;   // retry once, sized exactly
     }
-    BwdArgs b{};
-    b.r = a;
-    b.vis = vis;
-    b.color = color;
-    b.grad_color = grad_color;
-    b.grad_logp = grad_logp;
-    b.grad_feats = grad_feats;
-    b.vacc = static_cast<float*>(c->vacc.p);
-    b.mlp_partial = static_cast<float*>(c->partial.p);
-    b.n_blocks = nb;
+    if (static_cast<uint64_t>(n_rec) > cap) return fail(c, SOUP_ERR_CAPACITY, "gradient records overflowed twice");
+    c->rec_cap_hint = static_cast<uint64_t>(n_rec);
+    if (n_rec >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "more than 2^32 gradient records");
+    if ((st = ensure(c, c->rec_idx, static_cast<size_t>(n_rec) * 4))) return st;
     {
-        Timed t(c, SOUP_T_BWD, s);
-        launch_raster_bwd(b, c->tile, p.kind, false, s);
+        Timed t(c, SOUP_T_REDUCE, s);
+        launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
+                    static_cast<int64_t*>(c->tri_off.p), s);
+        launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), T, 0, s);
+        launch_bucket(static_cast<uint32_t*>(c->rec_tri.p), n_rec, static_cast<int64_t*>(c->tri_off.p),
+                      static_cast<int32_t*>(c->tri_fill.p), static_cast<uint32_t*>(c->rec_idx.p), s);
+        launch_reduce(static_cast<float*>(c->records.p), scene->C, scene->G, T, static_cast<int64_t*>(c->tri_off.p),
+                      static_cast<uint32_t*>(c->rec_idx.p), grad_feats, grad_verts, o.accumulate != 0, s);
     }
     {
         Timed t(c, SOUP_T_EDGE, s);
-        launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, b.vacc, s);
+        launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, static_cast<float*>(c->vacc.p), s);
     }
     {
         Timed t(c, SOUP_T_CHAIN, s);
-        launch_vertex_chain(a.views, a.V, a.scenes, T, a.recs, b.vacc, grad_verts, o.accumulate != 0, s);
+        launch_vertex_chain(a.views, a.V, a.scenes, T, a.recs, static_cast<float*>(c->vacc.p), grad_verts, s);
     }
     {
         Timed t(c, SOUP_T_REDUCE, s);
-        launch_mlp_reduce(b.mlp_partial, rows, p.n_params, grad_mlp, o.accumulate != 0, s);
+        launch_mlp_reduce(static_cast<float*>(c->partial.p), rows, p.n_params, grad_mlp, o.accumulate != 0, s);
     }
     HIP_TRY(c, hipGetLastError());
     return finish_stats(c, s);

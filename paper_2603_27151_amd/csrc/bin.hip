@@ -267,6 +267,10 @@ void launch_setup(const ViewDesc* views, int V, int maxT, const SceneDesc* scene
 }
 
 void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipStream_t s) {
+    if (n <= 0) {   // empty input: the single offset is 0
+        launch_fill_i32(reinterpret_cast<int32_t*>(out), 2, 0, s);
+        return;
+    }
     const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL(scan_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, bsum);
     hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(256), 0, s, bsum, nb);

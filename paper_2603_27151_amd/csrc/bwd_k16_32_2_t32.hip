@@ -1,0 +1,10 @@
+// Backward raster instantiated for the MLP shape (16, 32, 2) and 32x32 tiles.
+#include "raster_bwd_impl.hpp"
+
+namespace soup {
+
+void launch_raster_bwd_k16_32_2_t32(const BwdArgs& a, bool logp, hipStream_t s) {
+    launch_bwd_t<32, MlpShape<16, 32, 2>>(a, logp, s);
+}
+
+}  // namespace soup

@@ -1,0 +1,8 @@
+// Forward raster instantiated for the MLP shape (32, 64, 2) and 32x32 tiles.
+#include "raster_fwd_impl.hpp"
+
+namespace soup {
+
+void launch_raster_fwd_k32_64_2_t32(const RasterArgs& a, hipStream_t s) { launch_fwd_t<32, MlpShape<32, 64, 2>>(a, s); }
+
+}  // namespace soup

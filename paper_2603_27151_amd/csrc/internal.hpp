@@ -43,8 +43,12 @@ struct BwdArgs {
     const float* color;
     const float* grad_color;       // [P,3]
     const float* grad_logp;        // [P] or null
-    float* grad_feats;             // [T,G,G,C]
-    float* vacc;                   // [records, 16] screen-space accumulators
+    float* vacc;                   // [records, 16] edge-term moments per (view, triangle)
+    float* records;                // [rec_cap, kRecStride<C>] per-fragment gradient records
+    uint32_t* rec_tri;             // [rec_cap] triangle of each record
+    uint64_t rec_cap;
+    unsigned long long* rec_count; // records emitted (may exceed rec_cap: then the call retries)
+    int32_t* tri_count;            // [T] records per triangle
     float* mlp_partial;            // [n_waves, n_params]
     float* logp;                   // logp output (logp pass only)
     int n_blocks;                  // persistent grid size
@@ -54,7 +58,7 @@ void launch_raster_bwd(const BwdArgs& a, int tile, MlpKind k, bool logp_pass, hi
 void launch_edge(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis, const float* color,
                  const float* grad_color, const TriRec* recs, float* vacc, hipStream_t s);
 void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
-                         const float* vacc, float* grad_verts, bool accumulate, hipStream_t s);
+                         const float* vacc, float* grad_verts, hipStream_t s);
 void launch_mlp_reduce(const float* partial, int n_rows, int n_params, float* out, bool accumulate, hipStream_t s);
 void launch_loss_l2(const float* color, const float* target, int64_t P, float* gc, float* gl, float* loss,
                     hipStream_t s);
@@ -62,6 +66,17 @@ void launch_selftest_sigmoid(const float* x, float* y, int64_t n, hipStream_t s)
 void launch_selftest_uniform(uint64_t seed, const uint32_t* pixel, const uint32_t* tri, uint32_t view_id,
                              uint32_t step, float* u, int64_t n, hipStream_t s);
 
-constexpr int kVacc = 16;          // floats per record in the screen-space accumulator
+constexpr int kVacc = 16;          // floats per (view, triangle) in the edge-moment accumulator
+
+// Per-fragment gradient record: tri, cell (ix | iy << 8 | winner << 31), fx, fy,
+// dL/dfeature[C], world-space vertex gradient[9] (winner only); 16-byte rows.
+template <int C>
+constexpr int kRecStride = ((4 + C + 9) + 3) / 4 * 4;
+inline int rec_stride(int C) { return ((4 + C + 9) + 3) / 4 * 4; }
+
+void launch_bucket(const uint32_t* rec_tri, int64_t n, const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx,
+                   hipStream_t s);
+void launch_reduce(const float* records, int C, int G, int T, const int64_t* tri_off, const uint32_t* idx,
+                   float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s);
 
 }  // namespace soup

@@ -1,507 +1,136 @@
-// Backward raster (Supplement Algorithm A1, part 2; Eq. (8), (9)) and the
-// edge term of Section 3.2, recomputing fragments from the saved visibility
-// buffer.
-//
-// raster_bwd: persistent workgroups take screen tiles from a counter. For a
-//   tile, every fragment whose key is <= the pixel's saved winner key is
-//   re-found by the same exact coverage test as the forward (the winner
-//   itself and every fragment in front of it), compacted per wave into an LDS
-//   queue and processed 64 per wave:
-//     - recompute the bilinear feature and the MLP (float32, as the forward);
-//     - logit gradients: winner -> colour path g_C sigma'(o_rgb) and score
-//       g_L (1 - alpha); fragment in front -> score -g_L alpha (Eq. (9)
-//       through the sigmoid);
-//     - back-propagate through the MLP; the weight gradient sum_f delta_f a_f^T
-//       is accumulated in registers: each lane owns 4x4 blocks of every weight
-//       matrix and reads the batch's activations and deltas transposed from
-//       LDS; each wave writes its sums once, at the end, to its own row of a
-//       partial-sum buffer (no atomics; rows are reduced in a fixed order);
-//     - feature gradients scatter to the four texels (float atomics);
-//     - for the winner, the texture-position gradient goes back through the
-//       perspective-correct and screen barycentrics to the screen positions
-//       and 1/w of the triangle's vertices (per-record accumulators).
-//   A logp variant of the same kernel sums log(1 - alpha) over the front set
-//   and log(alpha) of the winner per pixel (log p(f*) of Eq. (6)).
-// edge: one thread per pixel, pairs (x, x+1) and (y, y+1): w = 1/2 (g_a+g_b).
-//   (C_a - C_b) goes to the nearer pixel's triangle as moments sum w,
-//   sum w dx, sum w dy about its vertex 0, per direction (the barycentric
-//   weight is affine in the pixel position, so these moments carry it
-//   exactly).
-// vertex_chain: one thread per triangle, loop over views: moments -> screen
-//   gradients of the vertices, then screen/1-w -> clip -> world through the
-//   view-projection, summed over views in a fixed order.
+// Gradient reduction, edge term, vertex chain, MLP-gradient reduction, loss and
+// contract self-test kernels; dispatch of the backward raster over the
+// compiled MLP shapes (the raster kernel is in raster_bwd_impl.hpp,
+// instantiated once per shape in bwd_*.hip).
 #include "raster_common.hpp"
 
 namespace soup {
 
-constexpr int kStageRows = 16;   // fragments staged per transpose pass
-
-template <class S>
-struct StageCfg {
-    static constexpr int kMax2(int a, int b) { return a > b ? a : b; }
-    static constexpr int kWidth = kMax2(kMax2(S::C + S::H, 2 * S::H), S::H + 4);
-};
-
-// Register accumulators of one layer's weight (4x4 blocks) and bias gradients.
-template <int DIN, int DOUT>
-struct LayerAcc {
-    static constexpr int NBK = DIN / 4;
-    static constexpr int NB = (DOUT / 4) * NBK;
-    static constexpr int PER = (NB + 63) / 64;
-    static constexpr int PB = (DOUT + 63) / 64;
-    float w[PER][16];
-    float b[PB];
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int p = 0; p < PER; ++p)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) w[p][i] = 0.0f;
-#pragma unroll
-        for (int p = 0; p < PB; ++p) b[p] = 0.0f;
-    }
-    // rows [0, nrows) of the stage: in[r][DIN] then d[r][DOUT]
-    __device__ __forceinline__ void accumulate(const float* __restrict__ in, const float* __restrict__ d, int nrows, int lane) {
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int blk = lane + 64 * p;
-            if (blk < NB) {
-                const int bj = blk / NBK, bk = blk % NBK;
-                for (int r = 0; r < nrows; ++r) {
-                    const float4 dv = *reinterpret_cast<const float4*>(d + r * DOUT + 4 * bj);
-                    const float4 iv = *reinterpret_cast<const float4*>(in + r * DIN + 4 * bk);
-                    const float dd[4] = {dv.x, dv.y, dv.z, dv.w};
-                    const float ii[4] = {iv.x, iv.y, iv.z, iv.w};
-#pragma unroll
-                    for (int x = 0; x < 4; ++x)
-#pragma unroll
-                        for (int y = 0; y < 4; ++y) w[p][4 * x + y] = __builtin_fmaf(dd[x], ii[y], w[p][4 * x + y]);
-                }
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < PB; ++p) {
-            const int j = lane + 64 * p;
-            if (j < DOUT)
-                for (int r = 0; r < nrows; ++r) b[p] += d[r * DOUT + j];
-        }
-    }
-    __device__ __forceinline__ void store(float* __restrict__ row, int w_off, int b_off, int lane) const {
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int blk = lane + 64 * p;
-            if (blk < NB) {
-                const int bj = blk / NBK, bk = blk % NBK;
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) row[w_off + (4 * bj + x) * DIN + 4 * bk + y] = w[p][4 * x + y];
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < PB; ++p) {
-            const int j = lane + 64 * p;
-            if (j < DOUT) row[b_off + j] = b[p];
-        }
-    }
-};
-
-// Stage the activations (in) and deltas (dl) of the wave's 64 fragments
-// through LDS, kStageRows at a time, and let every lane accumulate its blocks.
-template <int DIN, int DOUT>
-__device__ __forceinline__ void stage_accumulate(LayerAcc<DIN, DOUT>& la, float* __restrict__ st,
-                                                 const float (&in)[DIN], const float (&dl)[DOUT], int lane) {
-#pragma unroll
-    for (int half = 0; half < 64; half += kStageRows) {
-        if (lane >= half && lane < half + kStageRows) {
-            float* row = st + (lane - half) * DIN;
-#pragma unroll
-            for (int k = 0; k < DIN; k += 4) *reinterpret_cast<float4*>(row + k) = make_float4(in[k], in[k + 1], in[k + 2], in[k + 3]);
-            float* drow = st + kStageRows * DIN + (lane - half) * DOUT;
-#pragma unroll
-            for (int k = 0; k < DOUT; k += 4)
-                *reinterpret_cast<float4*>(drow + k) = make_float4(dl[k], dl[k + 1], dl[k + 2], dl[k + 3]);
-        }
-        __threadfence_block();
-        la.accumulate(st, st + kStageRows * DIN, kStageRows, lane);
-        __threadfence_block();
-    }
-}
-
-template <class S>
-struct MlpGrad {
-    LayerAcc<S::C, S::H> l0;
-    LayerAcc<S::H, S::H> mid[S::NH > 1 ? S::NH - 1 : 1];
-    LayerAcc<S::H, 4> out;
-};
-
-template <int NW>
-struct BwdQueue {
-    uint32_t info[NW][128];   // pixel | slot << 10 | winner << 31
-    float b1[NW][128];
-    float b2[NW][128];
-};
-
-template <int TS, class S, bool LOGP>
-__global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) {
-    using Cfg = TileCfg<TS>;
-    constexpr int NT = Cfg::NT, PPT = Cfg::PPT, NW = Cfg::NW;
-    constexpr int SW = StageCfg<S>::kWidth;
-    __shared__ ChunkLds<NT> ch;
-    __shared__ BwdQueue<NW> q;
-    __shared__ uint64_t s_key[TS * TS];
-    __shared__ float s_gc[TS * TS * 3];
-    __shared__ float s_gl[TS * TS];
-    __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
-    __shared__ uint64_t s_wmax[NW];
-    __shared__ int s_wact[NW];
-    __shared__ int64_t s_tile;
-
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const RasterArgs& r = a.r;
-    const int G = r.G;
-
-    MlpGrad<S> acc;
-    if (!LOGP) {
-        acc.l0.zero();
-        if constexpr (S::NH == 2) acc.mid[0].zero();
-        acc.out.zero();
-    }
-
-    for (;;) {
-        if (tid == 0) s_tile = static_cast<int64_t>(atomicAdd(r.work, 1u));
-        __syncthreads();
-        const int64_t tile = uniform_i64(s_tile);
-        __syncthreads();
-        if (tile >= r.n_tiles) break;
-
-        const int v = view_of_tile(r.views, r.V, tile);
-        const ViewDesc& vd = r.views[v];
-        const int W = vd.W, H = vd.H;
-        const int64_t tl = tile - vd.tile_base;
-        const int tx0 = static_cast<int>(tl % vd.tiles_x) * TS;
-        const int ty0 = static_cast<int>(tl / vd.tiles_x) * TS;
-        const SceneDesc sc = r.scenes[vd.scene];
-        gfloat* __restrict__ feats = as_global(uniform_ptr(sc.feats));
-        cfloat* __restrict__ mlp = as_const(uniform_ptr(sc.mlp));
-        const TriRec* __restrict__ recs = uniform_ptr(r.recs + vd.rec_base);
-
-        // per-pixel state: saved winner key, upstream gradients
-        uint64_t kc[PPT];
-        bool act[PPT], front[PPT];
-        uint64_t wmax = 0;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int pl = tid + k * NT;
-            const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
-            act[k] = false;
-            front[k] = false;
-            kc[k] = 0;
-            float g0 = 0.f, g1 = 0.f, g2 = 0.f, gl = 0.f;
-            if (gx < W && gy < H) {
-                const int64_t p = vd.pix_base + static_cast<int64_t>(gy) * W + gx;
-                kc[k] = a.vis[p];
-                if (LOGP) {
-                    act[k] = true;
-                    front[k] = true;
-                } else {
-                    g0 = a.grad_color[3 * p];
-                    g1 = a.grad_color[3 * p + 1];
-                    g2 = a.grad_color[3 * p + 2];
-                    gl = (a.grad_logp && r.o.mode == 0) ? a.grad_logp[p] : 0.0f;
-                    act[k] = g0 != 0.0f || g1 != 0.0f || g2 != 0.0f || gl != 0.0f;
-                    front[k] = gl != 0.0f;
-                }
-            }
-            s_key[pl] = kc[k];
-            s_gc[3 * pl] = g0;
-            s_gc[3 * pl + 1] = g1;
-            s_gc[3 * pl + 2] = g2;
-            s_gl[pl] = gl;
-            if (act[k]) wmax = kc[k] > wmax ? kc[k] : wmax;
-        }
-        bool any_act = false;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) any_act |= act[k];
-        any_act = __ballot(any_act) != 0;
-        wmax = wave_max_u64(wmax);
-
-        auto run_batch = [&](int n) __attribute__((always_inline)) {
-            __threadfence_block();
-            const bool on = lane < n;
-            uint32_t info = on ? q.info[w][lane] : 0u;
-            const int pl = info & 1023u;
-            const int j = (info >> 10) & 255u;
-            const bool win = (info >> 31) & 1u;
-            const float b1 = on ? q.b1[w][lane] : 0.f, b2 = on ? q.b2[w][lane] : 0.f;
-            const uint32_t tri = on ? ch.tri[j] : 0u;
-            const Cell c = cell_of(b1, b2, G);
-            float x[S::C];
-            MlpAct<S> m;
-            if (on) {
-                fetch_feature<S::C>(feats, tri, G, c, x);
-            } else {
-#pragma unroll
-                for (int k = 0; k < S::C; ++k) x[k] = 0.0f;
-            }
-            mlp_forward<S>(mlp, x, m);
-            const float alpha = sigmoid_c(m.o[3]);
-            if (r.counter && lane == 0) atomicAdd(r.counter, static_cast<unsigned long long>(n));
-            if (LOGP) {
-                if (on && r.o.mode == 0) atomicAdd(&s_gl[pl], win ? logf(alpha) : log1pf(-alpha));
-                return;
-            }
-            float d[4] = {0.f, 0.f, 0.f, 0.f};
-            if (on) {
-                const float gl = s_gl[pl];
-                if (win) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const float s = sigmoid_c(m.o[k]);
-                        d[k] = s_gc[3 * pl + k] * s * (1.0f - s);
-                    }
-                    d[3] = gl * (1.0f - alpha);
-                } else {
-                    d[3] = -gl * alpha;
-                }
-            }
-            // --- MLP backward, output layer first ---
-            float* st = s_stage[w];
-            float dh[S::H];
-#pragma unroll
-            for (int k = 0; k < S::H; ++k) {
-                cfloat* Wk = mlp + S::w_off(S::NH) + k;
-                float s = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) s = __builtin_fmaf(Wk[jj * S::H], d[jj], s);
-                dh[k] = m.h[S::NH - 1][k] > 0.0f ? s : 0.0f;
-            }
-            stage_accumulate<S::H, 4>(acc.out, st, m.h[S::NH - 1], d, lane);
-            // hidden layer 1 -> 0 (the compiled shapes have one or two hidden layers)
-            static_assert(S::NH == 1 || S::NH == 2, "one or two hidden layers");
-            if constexpr (S::NH == 2) {
-                float dprev[S::H];
-#pragma unroll
-                for (int k = 0; k < S::H; ++k) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int jj = 0; jj < S::H; ++jj) s = __builtin_fmaf(mlp[S::w_off(1) + jj * S::H + k], dh[jj], s);
-                    dprev[k] = m.h[0][k] > 0.0f ? s : 0.0f;
-                }
-                stage_accumulate<S::H, S::H>(acc.mid[0], st, m.h[0], dh, lane);
-#pragma unroll
-                for (int k = 0; k < S::H; ++k) dh[k] = dprev[k];
-            }
-            float dx[S::C];
-#pragma unroll
-            for (int k = 0; k < S::C; ++k) {
-                float s = 0.0f;
-#pragma unroll
-                for (int jj = 0; jj < S::H; ++jj) s = __builtin_fmaf(mlp[S::w_off(0) + jj * S::C + k], dh[jj], s);
-                dx[k] = s;
-            }
-            stage_accumulate<S::C, S::H>(acc.l0, st, x, dh, lane);
-            if (!on) return;
-            // --- bilinear scatter to the four texels ---
-            const float w00 = (1.0f - c.fx) * (1.0f - c.fy), w10 = c.fx * (1.0f - c.fy);
-            const float w01 = (1.0f - c.fx) * c.fy, w11 = c.fx * c.fy;
-            const size_t t00 = ((static_cast<size_t>(tri) * G + c.iy) * G + c.ix) * S::C;
-            const size_t t10 = t00 + S::C, t01 = t00 + static_cast<size_t>(G) * S::C, t11 = t01 + S::C;
-            float* gf = a.grad_feats;
-#pragma unroll
-            for (int k = 0; k < S::C; ++k) {
-                if (dx[k] == 0.0f) continue;
-                atomicAdd(gf + t00 + k, w00 * dx[k]);
-                atomicAdd(gf + t10 + k, w10 * dx[k]);
-                atomicAdd(gf + t01 + k, w01 * dx[k]);
-                atomicAdd(gf + t11 + k, w11 * dx[k]);
-            }
-            if (!win) return;
-            // --- winner: texture position -> barycentrics -> vertex screen positions ---
-            float dfx = 0.f, dfy = 0.f;
-#pragma unroll
-            for (int k = 0; k < S::C; ++k) {
-                const float T00 = feats[t00 + k], T10 = feats[t10 + k], T01 = feats[t01 + k], T11 = feats[t11 + k];
-                dfx = __builtin_fmaf(dx[k], (1.0f - c.fy) * (T10 - T00) + c.fy * (T11 - T01), dfx);
-                dfy = __builtin_fmaf(dx[k], (1.0f - c.fx) * (T01 - T00) + c.fx * (T11 - T10), dfy);
-            }
-            const float gm1 = static_cast<float>(G - 1);
-            const int lx = pl % TS, ly = pl / TS;
-            Frag f;
-            cover(ch, j, lx, ly, f);
-            float tt[3], S3 = 0.f;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                tt[i] = f.beta[i] * ch.iw[i][j];
-                S3 += tt[i];
-            }
-            const float bb[3] = {tt[0] / S3, tt[1] / S3, tt[2] / S3};
-            const float db[3] = {0.0f, dfx * gm1, dfy * gm1};
-            const float dot = db[1] * bb[1] + db[2] * bb[2];
-            float dbeta[3], diw[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const float dt = (db[i] - dot) / S3;
-                dbeta[i] = dt * ch.iw[i][j];
-                diw[i] = dt * f.beta[i];
-            }
-            // geometry in pixel units from exact integer differences
-            const int32_t PX = kSnap * (tx0 + lx) + kSnap / 2, PY = kSnap * (ty0 + ly) + kSnap / 2;
-            int32_t Xv[3], Yv[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                Xv[i] = ch.X[i][j];
-                Yv[i] = ch.Y[i][j];
-            }
-            const int64_t Ai = static_cast<int64_t>(Xv[1] - Xv[0]) * (Yv[2] - Yv[0]) -
-                               static_cast<int64_t>(Yv[1] - Yv[0]) * (Xv[2] - Xv[0]);
-            const float area = static_cast<float>(Ai) * (1.0f / 65536.0f);
-            const float inv256 = 1.0f / 256.0f;
-            float gsx[3] = {0.f, 0.f, 0.f}, gsy[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int p = i == 2 ? 0 : i + 1, qq = i == 0 ? 2 : (i == 1 ? 0 : 1);
-                // beta_i = e_i / area, e_i = edge(v_p, v_q, pixel)
-                const float bi = f.beta[i];
-#pragma unroll
-                for (int jv = 0; jv < 3; ++jv) {
-                    const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
-                    float dax = static_cast<float>(Yv[jp] - Yv[jq]) * inv256;
-                    float day = static_cast<float>(Xv[jq] - Xv[jp]) * inv256;
-                    float dex = 0.f, dey = 0.f;
-                    if (jv == p) {
-                        dex = static_cast<float>(Yv[qq] - PY) * inv256;
-                        dey = static_cast<float>(PX - Xv[qq]) * inv256;
-                    } else if (jv == qq) {
-                        dex = static_cast<float>(PY - Yv[p]) * inv256;
-                        dey = static_cast<float>(Xv[p] - PX) * inv256;
-                    }
-                    gsx[jv] += dbeta[i] * (dex - bi * dax) / area;
-                    gsy[jv] += dbeta[i] * (dey - bi * day) / area;
-                }
-            }
-            float* va = a.vacc + static_cast<size_t>(vd.rec_base + tri) * kVacc;
-#pragma unroll
-            for (int jv = 0; jv < 3; ++jv) {
-                atomicAdd(va + 3 * jv + 0, gsx[jv]);
-                atomicAdd(va + 3 * jv + 1, gsy[jv]);
-                atomicAdd(va + 3 * jv + 2, diw[jv]);
-            }
-        };
-
-        const int64_t beg = r.tile_start[tile], end = r.tile_start[tile + 1];
-        int qn = 0;
-        if (LOGP) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) s_gl[tid + k * NT] = 0.0f;
-        }
-        for (int64_t c0 = beg; c0 < end; c0 += NT) {
-            const int n = static_cast<int>(min<int64_t>(NT, end - c0));
-            if (lane == 0) {
-                s_wmax[w] = any_act ? wmax : 0ull;
-                s_wact[w] = any_act ? 1 : 0;
-            }
-            __syncthreads();
-            uint64_t bmax = 0;
-            int bact = 0;
-#pragma unroll
-            for (int i = 0; i < NW; ++i) {
-                bmax = s_wmax[i] > bmax ? s_wmax[i] : bmax;
-                bact |= s_wact[i];
-            }
-            // stop when no pixel needs fragments, or when the rest of the list
-            // lies behind every active pixel's winner
-            if (!bact || remaining_min(r.entries, beg, c0, end) > bmax) break;
-            if (tid < n) {
-                const uint64_t e = r.entries[c0 + tid];
-                load_slot<NT, TS>(ch, tid, e, recs[static_cast<uint32_t>(e)], tx0, ty0);
-            }
-            __syncthreads();
-            if (any_act) {
-                for (int j = 0; j < n; ++j) {
-                    const uint64_t zk = (static_cast<uint64_t>(ch.zmin[j]) << 32) | ch.tri[j];
-                    if (zk > wmax) break;
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const int pl = tid + k * NT;
-                        Frag f;
-                        bool cand = false, win = false;
-                        float b1 = 0.f, b2 = 0.f;
-                        if (act[k] && zk <= kc[k] && cover(ch, j, pl % TS, pl / TS, f) && f.key <= kc[k]) {
-                            win = f.key == kc[k];
-                            cand = win || front[k];
-                            if (cand) persp_b(ch, j, f, b1, b2);
-                        }
-                        const uint64_t mk = __ballot(cand);
-                        if (cand) {
-                            const int pos = qn + __popcll(mk & lanemask_lt());
-                            q.info[w][pos] = static_cast<uint32_t>(pl) | (static_cast<uint32_t>(j) << 10) |
-                                             (win ? 0x80000000u : 0u);
-                            q.b1[w][pos] = b1;
-                            q.b2[w][pos] = b2;
-                        }
-                        qn += __popcll(mk);
-                        if (qn >= 64) {
-                            run_batch(64);
-                            __threadfence_block();
-                            if (lane < qn - 64) {
-                                q.info[w][lane] = q.info[w][64 + lane];
-                                q.b1[w][lane] = q.b1[w][64 + lane];
-                                q.b2[w][lane] = q.b2[w][64 + lane];
-                            }
-                            qn -= 64;
-                            __threadfence_block();
-                        }
-                    }
-                }
-                if (qn > 0) {
-                    run_batch(qn);
-                    qn = 0;
-                    __threadfence_block();
-                }
-            }
-        }
-        __syncthreads();
-        if (LOGP) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int pl = tid + k * NT;
-                const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
-                if (gx < W && gy < H) a.logp[vd.pix_base + static_cast<int64_t>(gy) * W + gx] = s_gl[pl];
-            }
-            __syncthreads();
-        }
-    }
-    if (!LOGP) {
-        float* row = a.mlp_partial + (static_cast<size_t>(blockIdx.x) * NW + w) * S::kParams;
-        acc.l0.store(row, S::w_off(0), S::b_off(0), lane);
-        if constexpr (S::NH == 2) acc.mid[0].store(row, S::w_off(1), S::b_off(1), lane);
-        acc.out.store(row, S::w_off(S::NH), S::b_off(S::NH), lane);
-    }
-}
-
-template <int TS, class S>
-static void launch_bwd_t(const BwdArgs& a, bool logp, hipStream_t s) {
-    if (a.r.n_tiles <= 0) return;
-    if (logp)
-        hipLaunchKernelGGL((raster_bwd_kernel<TS, S, true>), dim3(a.n_blocks), dim3(TileCfg<TS>::NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((raster_bwd_kernel<TS, S, false>), dim3(a.n_blocks), dim3(TileCfg<TS>::NT), 0, s, a);
-}
-
-template <class S>
-static void launch_bwd_s(const BwdArgs& a, int tile, bool logp, hipStream_t s) {
-    switch (tile) {
-        case 8: launch_bwd_t<8, S>(a, logp, s); break;
-        case 32: launch_bwd_t<32, S>(a, logp, s); break;
-        default: launch_bwd_t<16, S>(a, logp, s); break;
-    }
-}
+void launch_raster_bwd_k8_16_1_t8(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k8_16_1_t16(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k8_16_1_t32(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k16_32_2_t8(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k16_32_2_t16(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k16_32_2_t32(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k32_64_2_t8(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k32_64_2_t16(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_raster_bwd_k32_64_2_t32(const BwdArgs& a, bool logp, hipStream_t s);
 
 void launch_raster_bwd(const BwdArgs& a, int tile, MlpKind k, bool logp, hipStream_t s) {
     switch (k) {
-        case MlpKind::k8_16_1: launch_bwd_s<MlpShape<8, 16, 1>>(a, tile, logp, s); break;
-        case MlpKind::k16_32_2: launch_bwd_s<MlpShape<16, 32, 2>>(a, tile, logp, s); break;
-        case MlpKind::k32_64_2: launch_bwd_s<MlpShape<32, 64, 2>>(a, tile, logp, s); break;
+        case MlpKind::k8_16_1:
+            if (tile == 8) launch_raster_bwd_k8_16_1_t8(a, logp, s);
+            else if (tile == 32) launch_raster_bwd_k8_16_1_t32(a, logp, s);
+            else launch_raster_bwd_k8_16_1_t16(a, logp, s);
+            break;
+        case MlpKind::k16_32_2:
+            if (tile == 8) launch_raster_bwd_k16_32_2_t8(a, logp, s);
+            else if (tile == 32) launch_raster_bwd_k16_32_2_t32(a, logp, s);
+            else launch_raster_bwd_k16_32_2_t16(a, logp, s);
+            break;
+        case MlpKind::k32_64_2:
+            if (tile == 8) launch_raster_bwd_k32_64_2_t8(a, logp, s);
+            else if (tile == 32) launch_raster_bwd_k32_64_2_t32(a, logp, s);
+            else launch_raster_bwd_k32_64_2_t16(a, logp, s);
+            break;
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gradient records -> per-triangle lists -> per-triangle reduction
+// ---------------------------------------------------------------------------
+
+// Counting-sort placement of record indices into per-triangle lists; runs of
+// equal triangles in a wave take one atomic.
+__global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict__ rec_tri, int64_t n,
+                                                     const int64_t* __restrict__ tri_off,
+                                                     int32_t* __restrict__ tri_fill, uint32_t* __restrict__ idx) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool on = i < n;
+    const uint32_t tri = on ? rec_tri[i] : 0xFFFFFFFFu;
+    const uint32_t tprev = __shfl_up(tri, 1, 64);
+    const bool head = on && (lane == 0 || tprev != tri);
+    const uint64_t heads = __ballot(head);
+    const uint64_t act = __ballot(on);   // outside the branch: a ballot sees only the lanes that execute it
+    int base = 0;
+    if (head) {
+        const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+        const int last = 63 - __builtin_clzll(act);
+        const int endl = above ? __builtin_ctzll(above) : last + 1;
+        base = atomicAdd(&tri_fill[tri], endl - lane);
+    }
+    const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
+    const int hl = upto ? 63 - __builtin_clzll(upto) : 0;
+    const int hb = __shfl(base, hl, 64);
+    if (on) idx[tri_off[tri] + hb + (lane - hl)] = static_cast<uint32_t>(i);
+}
+
+// One workgroup per triangle: sums its records' feature gradients into the
+// G x G x C grid in LDS (bilinear weights of each record's cell position) and
+// its winners' vertex gradients, then writes both once.
+template <int C>
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ records, int G,
+                                                     const int64_t* __restrict__ tri_off,
+                                                     const uint32_t* __restrict__ idx, float* __restrict__ grad_feats,
+                                                     float* __restrict__ grad_verts, bool accumulate) {
+    extern __shared__ float s_acc[];      // [G*G*C + 16]
+    const int t = blockIdx.x;
+    const int n_feat = G * G * C;
+    float* s_gv = s_acc + n_feat;
+    for (int k = threadIdx.x; k < n_feat + 16; k += blockDim.x) s_acc[k] = 0.0f;
+    __syncthreads();
+    const int64_t beg = tri_off[t], end = tri_off[t + 1];
+    constexpr int RPP = 256 / C;           // records per pass
+    const int c = threadIdx.x % C;
+    for (int64_t i = beg + threadIdx.x / C; i < end; i += RPP) {
+        const float* rec = records + static_cast<size_t>(idx[i]) * kRecStride<C>;
+        const uint32_t cell = __float_as_uint(rec[1]);
+        const int ix = cell & 255u, iy = (cell >> 8) & 255u;
+        const float fx = rec[2], fy = rec[3];
+        const float d = rec[4 + c];
+        const int t00 = (iy * G + ix) * C + c;
+        atomicAdd(&s_acc[t00], (1.0f - fx) * (1.0f - fy) * d);
+        atomicAdd(&s_acc[t00 + C], fx * (1.0f - fy) * d);
+        atomicAdd(&s_acc[t00 + G * C], (1.0f - fx) * fy * d);
+        atomicAdd(&s_acc[t00 + G * C + C], fx * fy * d);
+        if (cell >> 31)
+            for (int k = c; k < 9; k += C) atomicAdd(&s_gv[k], rec[4 + C + k]);
+    }
+    __syncthreads();
+    float* gf = grad_feats + static_cast<size_t>(t) * n_feat;
+    for (int k = threadIdx.x; k < n_feat; k += blockDim.x) gf[k] = accumulate ? gf[k] + s_acc[k] : s_acc[k];
+    if (threadIdx.x < 9) {
+        float* gv = grad_verts + static_cast<size_t>(t) * 9 + threadIdx.x;
+        *gv = accumulate ? *gv + s_gv[threadIdx.x] : s_gv[threadIdx.x];
+    }
+}
+
+void launch_bucket(const uint32_t* rec_tri, int64_t n, const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx,
+                   hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(bucket_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, rec_tri, n,
+                       tri_off, tri_fill, idx);
+}
+
+void launch_reduce(const float* records, int C, int G, int T, const int64_t* tri_off, const uint32_t* idx,
+                   float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
+    if (T <= 0) return;
+    const size_t lds = (static_cast<size_t>(G) * G * C + 16) * sizeof(float);
+    switch (C) {
+        case 8:
+            hipLaunchKernelGGL(reduce_kernel<8>, dim3(T), dim3(256), lds, s, records, G, tri_off, idx, grad_feats,
+                               grad_verts, accumulate);
+            break;
+        case 16:
+            hipLaunchKernelGGL(reduce_kernel<16>, dim3(T), dim3(256), lds, s, records, G, tri_off, idx, grad_feats,
+                               grad_verts, accumulate);
+            break;
+        case 32:
+            hipLaunchKernelGGL(reduce_kernel<32>, dim3(T), dim3(256), lds, s, records, G, tri_off, idx, grad_feats,
+                               grad_verts, accumulate);
+            break;
         default: break;
     }
 }
@@ -572,7 +201,7 @@ __global__ __launch_bounds__(256) void vertex_chain_kernel(const ViewDesc* __res
                                                            const SceneDesc* __restrict__ scenes, int T,
                                                            const TriRec* __restrict__ recs,
                                                            const float* __restrict__ vacc,
-                                                           float* __restrict__ grad_verts, bool accumulate) {
+                                                           float* __restrict__ grad_verts) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
     const float* vt = scenes[0].verts + static_cast<size_t>(t) * 9;
@@ -585,11 +214,7 @@ __global__ __launch_bounds__(256) void vertex_chain_kernel(const ViewDesc* __res
         const TriRec R = recs[rec];
         if (R.x0 > R.x1) continue;
         const float* a = vacc + static_cast<size_t>(rec) * kVacc;
-        float gs[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) gs[i][k] = a[3 * i + k];
+        float gs[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
         // edge moments about vertex 0 -> screen gradients (beta affine in the pixel)
         const float m[2][3] = {{a[9], a[10], a[11]}, {a[12], a[13], a[14]}};
         if (m[0][0] != 0.f || m[0][1] != 0.f || m[0][2] != 0.f || m[1][0] != 0.f || m[1][1] != 0.f ||
@@ -625,17 +250,14 @@ __global__ __launch_bounds__(256) void vertex_chain_kernel(const ViewDesc* __res
         }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        float* o = grad_verts + static_cast<size_t>(t) * 9 + i;
-        *o = accumulate ? *o + g[i] : g[i];
-    }
+    for (int i = 0; i < 9; ++i) grad_verts[static_cast<size_t>(t) * 9 + i] += g[i];
 }
 
 void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
-                         const float* vacc, float* grad_verts, bool accumulate, hipStream_t s) {
+                         const float* vacc, float* grad_verts, hipStream_t s) {
     if (T <= 0) return;
     hipLaunchKernelGGL(vertex_chain_kernel, dim3((T + 255) / 256), dim3(256), 0, s, views, V, scenes, T, recs, vacc,
-                       grad_verts, accumulate);
+                       grad_verts);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,212 +1,37 @@
-// Forward raster: stochastic opacity masking with a 64-bit depth|triangle
-// visibility buffer (Eq. (5); Supplement Algorithm A1, part 1).
-//
-// One workgroup per screen tile. The tile's triangle list (sorted by the
-// lower bound of their depth) is staged through LDS in chunks; every lane
-// tests its pixel(s) against each staged triangle with exact edge functions.
-// A fragment whose key is below the pixel's current best key is a candidate:
-// candidates are compacted per wave (ballot + prefix count) into an LDS queue
-// and decoded 64 at a time, one per lane, so the expensive texture + MLP
-// decode always runs on full waves. A decoded fragment that passes its draw
-// lowers the pixel's key with an LDS 64-bit atomicMin; the lane holding the
-// pixel's minimum then stores its colour. Triangles whose depth bound is
-// already behind every pixel of a wave are skipped, and the tile stops once
-// the remaining list is behind every pixel: front-to-back early-out without
-// sorting fragments.
-#include "raster_common.hpp"
+// Forward raster dispatch over the compiled MLP shapes and tile sizes (the
+// kernel is in raster_fwd_impl.hpp, instantiated once per shape and tile in
+// fwd_*.hip so that the units compile in parallel).
+#include "internal.hpp"
 
 namespace soup {
 
-template <int NW>
-struct FwdQueue {
-    uint64_t key[NW][128];
-    float b1[NW][128];
-    float b2[NW][128];
-    uint16_t pix[NW][128];
-};
-
-template <int TS, class S>
-__global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs a) {
-    using Cfg = TileCfg<TS>;
-    constexpr int NT = Cfg::NT, PPT = Cfg::PPT, NW = Cfg::NW;
-    __shared__ ChunkLds<NT> ch;
-    __shared__ FwdQueue<NW> q;
-    __shared__ uint64_t s_key[TS * TS];
-    __shared__ float s_rgb[TS * TS * 3];
-    __shared__ uint64_t s_wmax[NW];
-
-    const int64_t tile = blockIdx.x;
-    const int v = view_of_tile(a.views, a.V, tile);
-    const ViewDesc& vd = a.views[v];
-    const int W = vd.W, H = vd.H;
-    const int64_t tl = tile - vd.tile_base;
-    const int tx0 = static_cast<int>(tl % vd.tiles_x) * TS;
-    const int ty0 = static_cast<int>(tl / vd.tiles_x) * TS;
-    const SceneDesc sc = a.scenes[vd.scene];
-    gfloat* __restrict__ feats = as_global(uniform_ptr(sc.feats));
-    cfloat* __restrict__ mlp = as_const(uniform_ptr(sc.mlp));
-    const TriRec* __restrict__ recs = uniform_ptr(a.recs + vd.rec_base);
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int G = a.G;
-
-    uint64_t kc[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int pl = tid + k * NT;
-        const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
-        kc[k] = (gx < W && gy < H) ? kBgKey : 0ull;   // pixels outside the view never take fragments
-        s_key[pl] = kc[k];
-    }
-    uint64_t wmax = 0;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) wmax = kc[k] > wmax ? kc[k] : wmax;
-    wmax = wave_max_u64(wmax);
-
-    // decode a batch of n queued candidates of this wave, one per lane
-    auto run_batch = [&](int n) __attribute__((always_inline)) {
-        __threadfence_block();
-        const bool act = lane < n;
-        uint64_t key = 0;
-        int pl = 0;
-        bool pass = false;
-        float o[4] = {0.f, 0.f, 0.f, 0.f};
-        if (act) {
-            key = q.key[w][lane];
-            pl = q.pix[w][lane];
-            const float b1 = q.b1[w][lane], b2 = q.b2[w][lane];
-            const uint32_t tri = static_cast<uint32_t>(key);
-            const Cell c = cell_of(b1, b2, G);
-            float x[S::C];
-            fetch_feature<S::C>(feats, tri, G, c, x);
-            mlp_logits<S>(mlp, x, o);
-            if (a.o.mode == 0) {
-                const float alpha = sigmoid_c(o[3]);
-                const uint32_t pidx = static_cast<uint32_t>((ty0 + pl / TS) * W + tx0 + pl % TS);
-                pass = uniform24(a.o.seed, pidx, tri, vd.view_id, a.o.step) < alpha;
-            } else {
-                pass = o[3] > 0.0f;
-            }
-            if (pass) atomicMin(reinterpret_cast<unsigned long long*>(&s_key[pl]), static_cast<unsigned long long>(key));
-        }
-        __threadfence_block();
-        if (pass && s_key[pl] == key) {
-            s_rgb[3 * pl + 0] = sigmoid_c(o[0]);
-            s_rgb[3 * pl + 1] = sigmoid_c(o[1]);
-            s_rgb[3 * pl + 2] = sigmoid_c(o[2]);
-        }
-        if (a.counter && lane == 0) atomicAdd(a.counter, static_cast<unsigned long long>(n));
-        __threadfence_block();
-    };
-    auto refresh = [&]() __attribute__((always_inline)) {
-        uint64_t m = 0;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            kc[k] = s_key[tid + k * NT];
-            m = kc[k] > m ? kc[k] : m;
-        }
-        wmax = wave_max_u64(m);
-    };
-
-    const int64_t beg = a.tile_start[tile], end = a.tile_start[tile + 1];
-    int qn = 0;
-    for (int64_t c0 = beg; c0 < end; c0 += NT) {
-        const int n = static_cast<int>(min<int64_t>(NT, end - c0));
-        if (lane == 0) s_wmax[w] = wmax;
-        __syncthreads();
-        uint64_t bmax = 0;
-#pragma unroll
-        for (int i = 0; i < NW; ++i) bmax = s_wmax[i] > bmax ? s_wmax[i] : bmax;
-        if (remaining_min(a.entries, beg, c0, end) >= bmax) break;
-        if (tid < n) {
-            const uint64_t e = a.entries[c0 + tid];
-            load_slot<NT, TS>(ch, tid, e, recs[static_cast<uint32_t>(e)], tx0, ty0);
-        }
-        __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            const uint64_t zk = (static_cast<uint64_t>(ch.zmin[j]) << 32) | ch.tri[j];
-            if (zk >= wmax) break;   // sorted: nothing further can beat any pixel of this wave
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int pl = tid + k * NT;
-                Frag f;
-                bool cand = false;
-                float b1 = 0.f, b2 = 0.f;
-                if (zk < kc[k] && cover(ch, j, pl % TS, pl / TS, f) && f.key < kc[k]) {
-                    cand = true;
-                    persp_b(ch, j, f, b1, b2);
-                }
-                const uint64_t m = __ballot(cand);
-                if (cand) {
-                    const int pos = qn + __popcll(m & lanemask_lt());
-                    q.key[w][pos] = f.key;
-                    q.b1[w][pos] = b1;
-                    q.b2[w][pos] = b2;
-                    q.pix[w][pos] = static_cast<uint16_t>(pl);
-                }
-                qn += __popcll(m);
-                if (qn >= 64) {
-                    run_batch(64);
-                    if (lane < qn - 64) {
-                        q.key[w][lane] = q.key[w][64 + lane];
-                        q.b1[w][lane] = q.b1[w][64 + lane];
-                        q.b2[w][lane] = q.b2[w][64 + lane];
-                        q.pix[w][lane] = q.pix[w][64 + lane];
-                    }
-                    qn -= 64;
-                    refresh();
-                }
-            }
-        }
-        if (qn > 0) {
-            run_batch(qn);
-            qn = 0;
-            refresh();
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int pl = tid + k * NT;
-        const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
-        if (gx >= W || gy >= H) continue;
-        const uint64_t key = s_key[pl];
-        const int64_t off = static_cast<int64_t>(gy) * W + gx;
-        float* col = vd.color_out ? vd.color_out + 3 * off : a.color + 3 * (vd.pix_base + off);
-        if (vd.vis_out) vd.vis_out[off] = key;
-        else if (a.vis) a.vis[vd.pix_base + off] = key;
-        if (key == kBgKey) {
-            col[0] = a.o.bg[0];
-            col[1] = a.o.bg[1];
-            col[2] = a.o.bg[2];
-        } else {
-            col[0] = s_rgb[3 * pl + 0];
-            col[1] = s_rgb[3 * pl + 1];
-            col[2] = s_rgb[3 * pl + 2];
-        }
-    }
-}
-
-template <int TS, class S>
-static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
-    if (a.n_tiles <= 0) return;
-    hipLaunchKernelGGL((raster_fwd_kernel<TS, S>), dim3(static_cast<unsigned>(a.n_tiles)), dim3(TileCfg<TS>::NT), 0,
-                       s, a);
-}
-
-template <class S>
-static void launch_fwd_s(const RasterArgs& a, int tile, hipStream_t s) {
-    switch (tile) {
-        case 8: launch_fwd_t<8, S>(a, s); break;
-        case 32: launch_fwd_t<32, S>(a, s); break;
-        default: launch_fwd_t<16, S>(a, s); break;
-    }
-}
+void launch_raster_fwd_k8_16_1_t8(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k8_16_1_t16(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k8_16_1_t32(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k16_32_2_t8(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k16_32_2_t16(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k16_32_2_t32(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k32_64_2_t8(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k32_64_2_t16(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_k32_64_2_t32(const RasterArgs& a, hipStream_t s);
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s) {
     switch (k) {
-        case MlpKind::k8_16_1: launch_fwd_s<MlpShape<8, 16, 1>>(a, tile, s); break;
-        case MlpKind::k16_32_2: launch_fwd_s<MlpShape<16, 32, 2>>(a, tile, s); break;
-        case MlpKind::k32_64_2: launch_fwd_s<MlpShape<32, 64, 2>>(a, tile, s); break;
+        case MlpKind::k8_16_1:
+            if (tile == 8) launch_raster_fwd_k8_16_1_t8(a, s);
+            else if (tile == 32) launch_raster_fwd_k8_16_1_t32(a, s);
+            else launch_raster_fwd_k8_16_1_t16(a, s);
+            break;
+        case MlpKind::k16_32_2:
+            if (tile == 8) launch_raster_fwd_k16_32_2_t8(a, s);
+            else if (tile == 32) launch_raster_fwd_k16_32_2_t32(a, s);
+            else launch_raster_fwd_k16_32_2_t16(a, s);
+            break;
+        case MlpKind::k32_64_2:
+            if (tile == 8) launch_raster_fwd_k32_64_2_t8(a, s);
+            else if (tile == 32) launch_raster_fwd_k32_64_2_t32(a, s);
+            else launch_raster_fwd_k32_64_2_t16(a, s);
+            break;
         default: break;
     }
 }

@@ -60,11 +60,14 @@ def normwise(gpu, ref):
 
 
 def assert_grads(gpu, ref, tol=1e-4, names=("verts", "feats", "mlp")):
+    bad = []
     for n, g, r in zip(names, gpu, ref):
         e = normwise(g, r)
         mx = float(np.max(np.abs(np.asarray(g, np.float64).ravel() - np.asarray(r).ravel()))) if np.size(r) else 0.0
         _say(f"grad {n}: normwise {e:.3e} max-abs {mx:.3e} |ref| {np.linalg.norm(r):.3e}")
-        assert e <= tol, f"grad_{n} normwise error {e:.3e} > {tol} (max-abs {mx:.3e})"
+        if not e <= tol:
+            bad.append(f"grad_{n} normwise error {e:.3e} > {tol} (max-abs {mx:.3e})")
+    assert not bad, "; ".join(bad)
 
 
 def assert_colours(gpu, ref):
