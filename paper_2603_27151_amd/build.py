@@ -29,18 +29,33 @@ def flags():
             "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+OBJDIR = os.path.join(ROOT, "_build", "csrc")
+
+
+def _newest_header() -> float:
+    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    paths.append(os.path.join(ROOT, "include", "diffsoup.h"))
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def build(verbose: bool = False, jobs: int = 0, force: bool = True) -> str:
+    """Compile every source (force) or only those older than their object."""
     if jobs <= 0:
         jobs = max(1, min(len(SOURCES), os.cpu_count() or 4))
+    os.makedirs(OBJDIR, exist_ok=True)
+    hdr = _newest_header()
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *flags(), "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(OBJDIR, src.replace(".hip", ".o"))
+        objs.append(obj)
+        srcp = os.path.join(CSRC, src)
+        if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(srcp), hdr):
+            continue
+        cmd = [hipcc(), *flags(), "-c", "-x", "hip", srcp, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd)))
-        objs.append(obj)
         if len(procs) >= jobs:
             src0, p0 = procs.pop(0)
             if p0.wait() != 0:
@@ -53,10 +68,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
     os.replace(OUT + ".tmp", OUT)
-    for o in objs:
-        os.remove(o)
     return OUT
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, force="--force" in sys.argv)

@@ -29,7 +29,7 @@ struct soup_ctx {
     std::string err;
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
-    DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum;
+    DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum, mlp_mid;
     uint64_t rec_cap_hint = 0;       // records of the last backward, to size the next
     void* host_stage = nullptr;      // pinned: descriptors up, totals down
     size_t host_stage_bytes = 0;
@@ -397,7 +397,8 @@ void soup_ctx_destroy(soup_ctx* c) {
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->views,    &c->scenes,  &c->recs,      &c->tile_count, &c->tile_fill, &c->tile_start,
                       &c->bsum,     &c->entries, &c->vacc,      &c->partial,    &c->counters,  &c->records,
-                      &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum};
+                      &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum,
+                      &c->mlp_mid};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -518,6 +519,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     const int RS = rec_stride(scene->C);
     if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
         (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)) ||
+        (st = ensure(c, c->mlp_mid, static_cast<size_t>(mlp_reduce_mid_rows(rows)) * p.n_params * 8)) ||
         (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
         (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 4)) ||
         (st = ensure(c, c->tri_off, static_cast<size_t>(T + 1) * 8)) ||
@@ -590,7 +592,8 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     }
     {
         Timed t(c, SOUP_T_REDUCE, s);
-        launch_mlp_reduce(static_cast<float*>(c->partial.p), rows, p.n_params, grad_mlp, o.accumulate != 0, s);
+        launch_mlp_reduce(static_cast<float*>(c->partial.p), rows, p.n_params, static_cast<double*>(c->mlp_mid.p),
+                          grad_mlp, o.accumulate != 0, s);
     }
     HIP_TRY(c, hipGetLastError());
     return finish_stats(c, s);

@@ -59,7 +59,9 @@ void launch_edge(const ViewDesc* views, int V, int64_t P, const Opts& o, const u
                  const float* grad_color, const TriRec* recs, float* vacc, hipStream_t s);
 void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
                          const float* vacc, float* grad_verts, hipStream_t s);
-void launch_mlp_reduce(const float* partial, int n_rows, int n_params, float* out, bool accumulate, hipStream_t s);
+void launch_mlp_reduce(const float* partial, int n_rows, int n_params, double* mid, float* out, bool accumulate,
+                       hipStream_t s);
+int mlp_reduce_mid_rows(int n_rows);
 void launch_loss_l2(const float* color, const float* target, int64_t P, float* gc, float* gl, float* loss,
                     hipStream_t s);
 void launch_selftest_sigmoid(const float* x, float* y, int64_t n, hipStream_t s);

@@ -69,7 +69,11 @@ __global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict_
 
 // One workgroup per triangle: sums its records' feature gradients into the
 // G x G x C grid in LDS (bilinear weights of each record's cell position) and
-// its winners' vertex gradients, then writes both once.
+// its winners' vertex gradients, then writes both once. Thread (seg, c) walks
+// a contiguous segment of the triangle's records for channel c; consecutive
+// records mostly share a cell (they come from the same tile), so the four
+// corner sums stay in registers for a run of equal cells and reach LDS once
+// per run.
 template <int C>
 __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ records, int G,
                                                      const int64_t* __restrict__ tri_off,
@@ -82,22 +86,40 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ r
     for (int k = threadIdx.x; k < n_feat + 16; k += blockDim.x) s_acc[k] = 0.0f;
     __syncthreads();
     const int64_t beg = tri_off[t], end = tri_off[t + 1];
-    constexpr int RPP = 256 / C;           // records per pass
-    const int c = threadIdx.x % C;
-    for (int64_t i = beg + threadIdx.x / C; i < end; i += RPP) {
+    constexpr int NSEG = 256 / C;
+    const int c = threadIdx.x % C, seg = threadIdx.x / C;
+    const int64_t per = (end - beg + NSEG - 1) / NSEG;
+    const int64_t i0 = beg + seg * per, i1 = min(end, i0 + per);
+    float a00 = 0.f, a10 = 0.f, a01 = 0.f, a11 = 0.f;
+    int cur = -1;
+    auto flush = [&]() {
+        if (cur < 0) return;
+        const int ix = cur & 255, iy = cur >> 8;
+        const int t00 = (iy * G + ix) * C + c;
+        atomicAdd(&s_acc[t00], a00);
+        atomicAdd(&s_acc[t00 + C], a10);
+        atomicAdd(&s_acc[t00 + G * C], a01);
+        atomicAdd(&s_acc[t00 + G * C + C], a11);
+        a00 = a10 = a01 = a11 = 0.f;
+    };
+    for (int64_t i = i0; i < i1; ++i) {
         const float* rec = records + static_cast<size_t>(idx[i]) * kRecStride<C>;
         const uint32_t cell = __float_as_uint(rec[1]);
-        const int ix = cell & 255u, iy = (cell >> 8) & 255u;
+        const int key = static_cast<int>(cell & 0xFFFFu);
         const float fx = rec[2], fy = rec[3];
         const float d = rec[4 + c];
-        const int t00 = (iy * G + ix) * C + c;
-        atomicAdd(&s_acc[t00], (1.0f - fx) * (1.0f - fy) * d);
-        atomicAdd(&s_acc[t00 + C], fx * (1.0f - fy) * d);
-        atomicAdd(&s_acc[t00 + G * C], (1.0f - fx) * fy * d);
-        atomicAdd(&s_acc[t00 + G * C + C], fx * fy * d);
+        if (key != cur) {
+            flush();
+            cur = key;
+        }
+        a00 = __builtin_fmaf((1.0f - fx) * (1.0f - fy), d, a00);
+        a10 = __builtin_fmaf(fx * (1.0f - fy), d, a10);
+        a01 = __builtin_fmaf((1.0f - fx) * fy, d, a01);
+        a11 = __builtin_fmaf(fx * fy, d, a11);
         if (cell >> 31)
             for (int k = c; k < 9; k += C) atomicAdd(&s_gv[k], rec[4 + C + k]);
     }
+    flush();
     __syncthreads();
     float* gf = grad_feats + static_cast<size_t>(t) * n_feat;
     for (int k = threadIdx.x; k < n_feat; k += blockDim.x) gf[k] = accumulate ? gf[k] + s_acc[k] : s_acc[k];
@@ -139,50 +161,93 @@ void launch_reduce(const float* records, int C, int G, int T, const int64_t* tri
 // edge term
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ float wave_incl_sum(float v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(256) void edge_kernel(const ViewDesc* __restrict__ views, int V, int64_t P, Opts o,
                                                    const uint64_t* __restrict__ vis,
                                                    const float* __restrict__ color,
                                                    const float* __restrict__ gcol,
                                                    const TriRec* __restrict__ recs, float* __restrict__ vacc) {
     const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (p >= P) return;
+    const int lane = threadIdx.x & 63;
+    const bool inb = p < P;
     int lo = 0, hi = V - 1;
+    const int64_t pc = inb ? p : P - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].pix_base <= p) lo = mid;
+        if (views[mid].pix_base <= pc) lo = mid;
         else hi = mid - 1;
     }
     const ViewDesc& vd = views[lo];
-    const int64_t local = p - vd.pix_base;
+    const int64_t local = pc - vd.pix_base;
     const int x = static_cast<int>(local % vd.W), y = static_cast<int>(local / vd.W);
-    const uint64_t ka = vis[p];
-    const float ca[3] = {color[3 * p], color[3 * p + 1], color[3 * p + 2]};
-    const float ga[3] = {gcol[3 * p], gcol[3 * p + 1], gcol[3 * p + 2]};
+    const uint64_t ka = vis[pc];
+    const float ca[3] = {color[3 * pc], color[3 * pc + 1], color[3 * pc + 2]};
+    const float ga[3] = {gcol[3 * pc], gcol[3 * pc + 1], gcol[3 * pc + 2]};
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-        const int xb = x + (dir == 0), yb = y + (dir == 1);
-        if (xb >= vd.W || yb >= vd.H) continue;
-        const int64_t q = p + (dir == 0 ? 1 : vd.W);
-        const uint64_t kb = vis[q];
-        if (ka == kBgKey && kb == kBgKey) continue;
-        if (o.edge_pairs == 1 && ka != kBgKey && kb != kBgKey &&
-            static_cast<uint32_t>(ka) == static_cast<uint32_t>(kb))
-            continue;
+        // this lane's pair (a, b = a + e): weight, occluder record and the occluder pixel
+        int64_t key = -1;
         float wgt = 0.0f;
+        int xo = 0, yo = 0;
+        const int xb = x + (dir == 0), yb = y + (dir == 1);
+        if (inb && xb < vd.W && yb < vd.H) {
+            const int64_t q = pc + (dir == 0 ? 1 : vd.W);
+            const uint64_t kb = vis[q];
+            const bool skip = (ka == kBgKey && kb == kBgKey) ||
+                              (o.edge_pairs == 1 && ka != kBgKey && kb != kBgKey &&
+                               static_cast<uint32_t>(ka) == static_cast<uint32_t>(kb));
+            if (!skip) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) wgt += 0.5f * (ga[c] + gcol[3 * q + c]) * (ca[c] - color[3 * q + c]);
-        if (wgt == 0.0f) continue;
-        const bool oa = ka < kb;
-        const uint32_t tri = static_cast<uint32_t>(oa ? ka : kb);
-        const int xo = oa ? x : xb, yo = oa ? y : yb;
-        const int64_t rec = vd.rec_base + tri;
-        const int32_t X0 = recs[rec].X[0], Y0 = recs[rec].Y[0];
-        const float dx = static_cast<float>(kSnap * xo + kSnap / 2 - X0) * (1.0f / 256.0f);
-        const float dy = static_cast<float>(kSnap * yo + kSnap / 2 - Y0) * (1.0f / 256.0f);
-        float* va = vacc + static_cast<size_t>(rec) * kVacc + 9 + 3 * dir;
-        atomicAdd(va + 0, wgt);
-        atomicAdd(va + 1, wgt * dx);
-        atomicAdd(va + 2, wgt * dy);
+                for (int c = 0; c < 3; ++c) wgt += 0.5f * (ga[c] + gcol[3 * q + c]) * (ca[c] - color[3 * q + c]);
+                if (wgt != 0.0f) {
+                    const bool oa = ka < kb;
+                    key = vd.rec_base + static_cast<uint32_t>(oa ? ka : kb);
+                    xo = oa ? x : xb;
+                    yo = oa ? y : yb;
+                }
+            }
+        }
+        // runs of consecutive lanes with the same occluder record: sums by
+        // prefix sums, one atomic per moment per run (issued by the run head)
+        // every lane takes part in the shuffles (no short-circuit around them)
+        const int64_t kprev = __shfl_up(key, 1, 64);
+        const int64_t knext = __shfl_down(key, 1, 64);
+        const bool head = key >= 0 && (lane == 0 || kprev != key);
+        const bool tail = key >= 0 && (lane == 63 || knext != key);
+        const uint64_t heads = __ballot(head);
+        const uint64_t ends = __ballot(tail);
+        const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
+        const int hl = upto ? 63 - __builtin_clzll(upto) : 0;
+        const int hx = __shfl(xo, hl, 64), hy = __shfl(yo, hl, 64);
+        const float v0 = wgt;
+        const float v1 = key >= 0 ? wgt * static_cast<float>(xo - hx) : 0.0f;
+        const float v2 = key >= 0 ? wgt * static_cast<float>(yo - hy) : 0.0f;
+        const float s0 = wave_incl_sum(v0), s1 = wave_incl_sum(v1), s2 = wave_incl_sum(v2);
+        // run [hl, end]: sum = S(end) - S(hl - 1); the run's end lane issues it
+        const float p0 = __shfl(s0, hl > 0 ? hl - 1 : 0, 64), p1 = __shfl(s1, hl > 0 ? hl - 1 : 0, 64),
+                    p2 = __shfl(s2, hl > 0 ? hl - 1 : 0, 64);
+        if (key >= 0 && ((ends >> lane) & 1ull)) {
+            const float r0 = s0 - (hl > 0 ? p0 : 0.0f);
+            const float r1 = s1 - (hl > 0 ? p1 : 0.0f);
+            const float r2 = s2 - (hl > 0 ? p2 : 0.0f);
+            // moments about vertex 0 of the occluding triangle
+            const int32_t X0 = recs[key].X[0], Y0 = recs[key].Y[0];
+            const float ox = static_cast<float>(kSnap * hx + kSnap / 2 - X0) * (1.0f / 256.0f);
+            const float oy = static_cast<float>(kSnap * hy + kSnap / 2 - Y0) * (1.0f / 256.0f);
+            float* va = vacc + static_cast<size_t>(key) * kVacc + 9 + 3 * dir;
+            atomicAdd(va + 0, r0);
+            atomicAdd(va + 1, r1 + ox * r0);
+            atomicAdd(va + 2, r2 + oy * r0);
+        }
     }
 }
 
@@ -264,18 +329,37 @@ void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, 
 // MLP gradient: fixed-order reduction of the per-wave partial sums
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int n_rows, int n_params,
-                                                         float* __restrict__ out, bool accumulate) {
+constexpr int kMlpRowsPerBlock = 64;
+
+// Level 1: block (param chunk, row chunk) sums kMlpRowsPerBlock rows in order.
+__global__ __launch_bounds__(256) void mlp_reduce1_kernel(const float* __restrict__ partial, int n_rows, int n_params,
+                                                          double* __restrict__ mid) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_params) return;
+    const int r0 = blockIdx.y * kMlpRowsPerBlock, r1 = min(n_rows, r0 + kMlpRowsPerBlock);
+    double s = 0.0;
+    for (int r = r0; r < r1; ++r) s += partial[static_cast<size_t>(r) * n_params + p];
+    mid[static_cast<size_t>(blockIdx.y) * n_params + p] = s;
+}
+
+// Level 2: sum the row chunks in order.
+__global__ __launch_bounds__(256) void mlp_reduce2_kernel(const double* __restrict__ mid, int n_mid, int n_params,
+                                                          float* __restrict__ out, bool accumulate) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_params) return;
     double s = accumulate ? static_cast<double>(out[p]) : 0.0;
-    for (int r = 0; r < n_rows; ++r) s += partial[static_cast<size_t>(r) * n_params + p];
+    for (int r = 0; r < n_mid; ++r) s += mid[static_cast<size_t>(r) * n_params + p];
     out[p] = static_cast<float>(s);
 }
 
-void launch_mlp_reduce(const float* partial, int n_rows, int n_params, float* out, bool accumulate, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((n_params + 255) / 256), dim3(256), 0, s, partial, n_rows, n_params,
-                       out, accumulate);
+int mlp_reduce_mid_rows(int n_rows) { return (n_rows + kMlpRowsPerBlock - 1) / kMlpRowsPerBlock; }
+
+void launch_mlp_reduce(const float* partial, int n_rows, int n_params, double* mid, float* out, bool accumulate,
+                       hipStream_t s) {
+    const int n_mid = mlp_reduce_mid_rows(n_rows);
+    const unsigned gp = static_cast<unsigned>((n_params + 255) / 256);
+    hipLaunchKernelGGL(mlp_reduce1_kernel, dim3(gp, n_mid), dim3(256), 0, s, partial, n_rows, n_params, mid);
+    hipLaunchKernelGGL(mlp_reduce2_kernel, dim3(gp), dim3(256), 0, s, mid, n_mid, n_params, out, accumulate);
 }
 
 // ---------------------------------------------------------------------------
