@@ -102,22 +102,37 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ r
         atomicAdd(&s_acc[t00 + G * C + C], a11);
         a00 = a10 = a01 = a11 = 0.f;
     };
-    for (int64_t i = i0; i < i1; ++i) {
-        const float* rec = records + static_cast<size_t>(idx[i]) * kRecStride<C>;
-        const uint32_t cell = __float_as_uint(rec[1]);
-        const int key = static_cast<int>(cell & 0xFFFFu);
-        const float fx = rec[2], fy = rec[3];
-        const float d = rec[4 + c];
-        if (key != cur) {
-            flush();
-            cur = key;
+    constexpr int U = 4;   // records in flight per thread
+    for (int64_t i = i0; i < i1; i += U) {
+        uint32_t cells[U];
+        float fxs[U], fys[U], ds[U];
+        const float* recs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) recs[u] = i + u < i1 ? records + static_cast<size_t>(idx[i + u]) * kRecStride<C> : nullptr;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!recs[u]) continue;
+            cells[u] = __float_as_uint(recs[u][1]);
+            fxs[u] = recs[u][2];
+            fys[u] = recs[u][3];
+            ds[u] = recs[u][4 + c];
         }
-        a00 = __builtin_fmaf((1.0f - fx) * (1.0f - fy), d, a00);
-        a10 = __builtin_fmaf(fx * (1.0f - fy), d, a10);
-        a01 = __builtin_fmaf((1.0f - fx) * fy, d, a01);
-        a11 = __builtin_fmaf(fx * fy, d, a11);
-        if (cell >> 31)
-            for (int k = c; k < 9; k += C) atomicAdd(&s_gv[k], rec[4 + C + k]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!recs[u]) continue;
+            const int key = static_cast<int>(cells[u] & 0xFFFFu);
+            const float fx = fxs[u], fy = fys[u], d = ds[u];
+            if (key != cur) {
+                flush();
+                cur = key;
+            }
+            a00 = __builtin_fmaf((1.0f - fx) * (1.0f - fy), d, a00);
+            a10 = __builtin_fmaf(fx * (1.0f - fy), d, a10);
+            a01 = __builtin_fmaf((1.0f - fx) * fy, d, a01);
+            a11 = __builtin_fmaf(fx * fy, d, a11);
+            if (cells[u] >> 31)
+                for (int k = c; k < 9; k += C) atomicAdd(&s_gv[k], recs[u][4 + C + k]);
+        }
     }
     flush();
     __syncthreads();

@@ -140,6 +140,7 @@ struct BwdQueue {
     uint32_t info[NW][128];   // pixel | slot << 10 | winner << 31
     float b1[NW][128];
     float b2[NW][128];
+    float beta[3][NW][128];   // screen barycentrics found by the coverage test
 };
 
 template <int TS, class S, bool LOGP>
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int pl = tid + k * NT;
-            const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
+            const int gx = tx0 + px_of<TS>(pl), gy = ty0 + py_of<TS>(pl);
             act[k] = false;
             front[k] = false;
             kc[k] = 0;
@@ -316,13 +317,12 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
                     dfy = __builtin_fmaf(dx[k], (1.0f - c.fx) * (T01 - T00) + c.fx * (T11 - T10), dfy);
                 }
                 const float gm1 = static_cast<float>(G - 1);
-                const int lx = pl % TS, ly = pl / TS;
-                Frag f;
-                cover(ch, j, lx, ly, f);
+                const int lx = px_of<TS>(pl), ly = py_of<TS>(pl);
+                const float fb[3] = {q.beta[0][w][lane], q.beta[1][w][lane], q.beta[2][w][lane]};
                 float tt[3], S3 = 0.f;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    tt[i] = f.beta[i] * ch.iw[i][j];
+                    tt[i] = fb[i] * ch.iw[i][j];
                     S3 += tt[i];
                 }
                 const float inv_s = 1.0f / S3;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
                 for (int i = 0; i < 3; ++i) {
                     const float dt = (db[i] - dot) * inv_s;
                     dbeta[i] = dt * ch.iw[i][j];
-                    diw[i] = dt * f.beta[i];
+                    diw[i] = dt * fb[i];
                 }
                 // geometry in pixel units from exact integer differences
                 const int32_t PX = kSnap * (tx0 + lx) + kSnap / 2, PY = kSnap * (ty0 + ly) + kSnap / 2;
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
                 for (int i = 0; i < 3; ++i) {
                     const int p = i == 2 ? 0 : i + 1, qq = i == 0 ? 2 : (i == 1 ? 0 : 1);
                     // beta_i = e_i / area with e_i = edge(v_p, v_q, pixel centre)
-                    const float bi = f.beta[i];
+                    const float bi = fb[i];
 #pragma unroll
                     for (int jv = 0; jv < 3; ++jv) {
                         const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
@@ -448,13 +448,16 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
                 for (int j = 0; j < n; ++j) {
                     const uint64_t zk = (static_cast<uint64_t>(ch.zmin[j]) << 32) | ch.tri[j];
                     if (zk > wmax) break;
+                    const uint32_t box =
+                        static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(ch.box[j])));
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
+                        if (!box_hits_block<TS>(box, w + k * NW)) continue;   // uniform: the wave's 8x8 block
                         const int pl = tid + k * NT;
                         Frag f;
                         bool cand = false, win = false;
                         float b1 = 0.f, b2 = 0.f;
-                        if (act[k] && zk <= kc[k] && cover(ch, j, pl % TS, pl / TS, f) && f.key <= kc[k]) {
+                        if (act[k] && zk <= kc[k] && cover(ch, j, px_of<TS>(pl), py_of<TS>(pl), f) && f.key <= kc[k]) {
                             win = f.key == kc[k];
                             cand = win || front[k];
                             if (cand) persp_b(ch, j, f, b1, b2);
@@ -466,6 +469,9 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
                                              (win ? 0x80000000u : 0u);
                             q.b1[w][pos] = b1;
                             q.b2[w][pos] = b2;
+                            q.beta[0][w][pos] = f.beta[0];
+                            q.beta[1][w][pos] = f.beta[1];
+                            q.beta[2][w][pos] = f.beta[2];
                         }
                         qn += __popcll(mk);
                         if (qn >= 64) {
@@ -475,6 +481,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
                                 q.info[w][lane] = q.info[w][64 + lane];
                                 q.b1[w][lane] = q.b1[w][64 + lane];
                                 q.b2[w][lane] = q.b2[w][64 + lane];
+#pragma unroll
+                                for (int i = 0; i < 3; ++i) q.beta[i][w][lane] = q.beta[i][w][64 + lane];
                             }
                             qn -= 64;
                             __threadfence_block();
@@ -493,7 +501,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_bwd_kernel(BwdArgs a) 
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int pl = tid + k * NT;
-                const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
+                const int gx = tx0 + px_of<TS>(pl), gy = ty0 + py_of<TS>(pl);
                 if (gx < W && gy < H) a.logp[vd.pix_base + static_cast<int64_t>(gy) * W + gx] = s_gl[pl];
             }
             __syncthreads();

@@ -21,6 +21,26 @@ struct TileCfg {
     static_assert(NT % 64 == 0, "tile must hold a multiple of 64 pixels");
 };
 
+// Tile-local pixel of index pl: 8x8 blocks in row-major block order, row-major
+// inside a block, so each wave (64 consecutive indices) owns one 8x8 block and
+// can skip a triangle whose bounding box misses it with one uniform branch.
+template <int TS>
+__device__ __forceinline__ int px_of(int pl) {
+    return ((pl >> 6) % (TS / 8)) * 8 + (pl & 7);
+}
+template <int TS>
+__device__ __forceinline__ int py_of(int pl) {
+    return ((pl >> 6) / (TS / 8)) * 8 + ((pl & 63) >> 3);
+}
+
+// Does chunk slot j's bounding box touch the 8x8 block b of the tile?
+template <int TS>
+__device__ __forceinline__ bool box_hits_block(uint32_t box, int b) {
+    const int bx0 = (b % (TS / 8)) * 8, by0 = (b / (TS / 8)) * 8;
+    return !(static_cast<int>((box >> 16) & 255u) < bx0 || static_cast<int>(box & 255u) > bx0 + 7 ||
+             static_cast<int>(box >> 24) < by0 || static_cast<int>((box >> 8) & 255u) > by0 + 7);
+}
+
 template <int NT>
 struct ChunkLds {
     double e0[3][NT];        // orientation-normalised edge functions at the tile's first pixel centre

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int pl = tid + k * NT;
-        const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
+        const int gx = tx0 + px_of<TS>(pl), gy = ty0 + py_of<TS>(pl);
         kc[k] = (gx < W && gy < H) ? kBgKey : 0ull;   // pixels outside the view never take fragments
         s_key[pl] = kc[k];
     }
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
             mlp_logits<S>(mlp, x, o);
             if (a.o.mode == 0) {
                 const float alpha = sigmoid_c(o[3]);
-                const uint32_t pidx = static_cast<uint32_t>((ty0 + pl / TS) * W + tx0 + pl % TS);
+                const uint32_t pidx = static_cast<uint32_t>((ty0 + py_of<TS>(pl)) * W + tx0 + px_of<TS>(pl));
                 pass = uniform24(a.o.seed, pidx, tri, vd.view_id, a.o.step) < alpha;
             } else {
                 pass = o[3] > 0.0f;
@@ -126,13 +126,15 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
         for (int j = 0; j < n; ++j) {
             const uint64_t zk = (static_cast<uint64_t>(ch.zmin[j]) << 32) | ch.tri[j];
             if (zk >= wmax) break;   // sorted: nothing further can beat any pixel of this wave
+            const uint32_t box = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(ch.box[j])));
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
+                if (!box_hits_block<TS>(box, w + k * NW)) continue;   // uniform: the wave's 8x8 block
                 const int pl = tid + k * NT;
                 Frag f;
                 bool cand = false;
                 float b1 = 0.f, b2 = 0.f;
-                if (zk < kc[k] && cover(ch, j, pl % TS, pl / TS, f) && f.key < kc[k]) {
+                if (zk < kc[k] && cover(ch, j, px_of<TS>(pl), py_of<TS>(pl), f) && f.key < kc[k]) {
                     cand = true;
                     persp_b(ch, j, f, b1, b2);
                 }
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int pl = tid + k * NT;
-        const int gx = tx0 + pl % TS, gy = ty0 + pl / TS;
+        const int gx = tx0 + px_of<TS>(pl), gy = ty0 + py_of<TS>(pl);
         if (gx >= W || gy >= H) continue;
         const uint64_t key = s_key[pl];
         const int64_t off = static_cast<int64_t>(gy) * W + gx;
