@@ -117,14 +117,16 @@ enum {
     SOUP_T_SCATTER = 2,  /* tile lists */
     SOUP_T_SORT = 3,     /* per-tile depth sort */
     SOUP_T_FWD = 4,      /* forward raster */
-    SOUP_T_BWD = 5,      /* backward raster (front-set replay) */
+    SOUP_T_BWD = 5,      /* backward fragment decode (MLP backward, gradient records) */
     SOUP_T_EDGE = 6,     /* edge term */
     SOUP_T_CHAIN = 7,    /* vertex chain */
     SOUP_T_REDUCE = 8,   /* MLP-gradient reduction */
-    SOUP_T_LOGP = 9,     /* log p(f*) pass */
+    SOUP_T_LOGP = 9,     /* log p(f*) pass (includes its replay and decode) */
     SOUP_T_LOSS = 10,    /* L2 loss */
     SOUP_T_FILL = 11,    /* zero fills */
-    SOUP_TIMING_KINDS = 12
+    SOUP_T_REPLAY = 12,  /* backward front-set replay (coverage, fragment list) */
+    SOUP_T_GRAD = 13,    /* per-triangle feature and vertex gradient reduction */
+    SOUP_TIMING_KINDS = 14
 };
 soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
 soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);

@@ -49,8 +49,8 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_ctx_get_tile", "soup_ctx_set_counting", "soup_last_stats", "soup_rasterize_fwd",
            "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
            "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings"]
-TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "raster_bwd", "edge", "vertex_chain",
-                "mlp_reduce", "logp", "loss", "fill"]
+TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
+                "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce"]
 
 _lib = None
 

@@ -29,8 +29,8 @@ struct soup_ctx {
     std::string err;
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
-    DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum, mlp_mid;
-    uint64_t rec_cap_hint = 0;       // records of the last backward, to size the next
+    DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum, chunk_off, mlp_mid, frags;
+    uint64_t frag_cap_hint = 0;      // fragments of the last replay, to size the next
     void* host_stage = nullptr;      // pinned: descriptors up, totals down
     size_t host_stage_bytes = 0;
     // optional per-kernel timing: recorded event pairs and a pool of free events
@@ -347,7 +347,6 @@ int persistent_blocks(soup_ctx* c, const Plan& p) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, p.n_tiles)));
 }
 
-int waves_per_block(int tile) { return tile == 8 ? 1 : 4; }
 
 soup_status plan_single(soup_ctx* c, Plan& p, const soup_scene* scene, const soup_views* views) {
     soup_status st = check_scene(c, scene, &p.kind);
@@ -398,7 +397,7 @@ void soup_ctx_destroy(soup_ctx* c) {
     DevBuf* bufs[] = {&c->views,    &c->scenes,  &c->recs,      &c->tile_count, &c->tile_fill, &c->tile_start,
                       &c->bsum,     &c->entries, &c->vacc,      &c->partial,    &c->counters,  &c->records,
                       &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum,
-                      &c->mlp_mid};
+                      &c->chunk_off, &c->mlp_mid,  &c->frags};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -457,6 +456,72 @@ soup_status soup_last_stats(const soup_ctx* c, soup_stats* out) {
     return SOUP_OK;
 }
 
+// Backward, part 1: replay the fragments the backward needs into c->frags.
+// The list is sized from the last call's count with headroom (else 1.5 per
+// pixel); an overflow is detected from the count and the replay runs again,
+// sized exactly. Returns the fragment count in *n_frag.
+soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64_t* vis, const float* grad_color,
+                   const float* grad_logp, bool all_front, hipStream_t s, int64_t* n_frag) {
+    if (p.n_pix >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "backward needs fewer than 2^32 pixels per call");
+    unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
+    uint64_t cap = c->frag_cap_hint ? c->frag_cap_hint + c->frag_cap_hint / 4
+                                    : static_cast<uint64_t>(p.n_pix) * 3 / 2 + 1024;
+    soup_status st;
+    int64_t n = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if ((st = ensure(c, c->frags, static_cast<size_t>(cap) * sizeof(FragRec)))) return st;
+        {
+            Timed t(c, SOUP_T_FILL, s);
+            launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+            launch_fill_i32(reinterpret_cast<int32_t*>(cnt + 4), 2, 0, s);
+        }
+        ReplayArgs ra{};
+        ra.r = a;
+        ra.vis = vis;
+        ra.grad_color = grad_color;
+        ra.grad_logp = grad_logp;
+        ra.all_front = all_front ? 1 : 0;
+        ra.frags = static_cast<FragRec*>(c->frags.p);
+        ra.frag_cap = cap;
+        ra.frag_count = cnt + 4;
+        ra.n_blocks = persistent_blocks(c, p);
+        {
+            Timed t(c, SOUP_T_REPLAY, s);
+            launch_replay(ra, c->tile, s);
+        }
+        HIP_TRY(c, hipGetLastError());
+        int64_t* hcount = reinterpret_cast<int64_t*>(c->host_stage);
+        HIP_TRY(c, hipMemcpyAsync(hcount, cnt + 4, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        n = *hcount;
+        if (static_cast<uint64_t>(n) <= cap) break;
+        cap = static_cast<uint64_t>(n) + static_cast<uint64_t>(n) / 8 + 1024;
+    }
+    if (static_cast<uint64_t>(n) > cap) return fail(c, SOUP_ERR_CAPACITY, "fragment list overflowed twice");
+    if (n >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "more than 2^32 backward fragments");
+    c->frag_cap_hint = static_cast<uint64_t>(n);
+    *n_frag = n;
+    return SOUP_OK;
+}
+
+// Persistent grid of the decode kernel: 4 waves per workgroup, 4 workgroups per CU.
+int decode_blocks(soup_ctx* c) { return std::max(1, c->num_cus * 4); }
+
+DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a, uint64_t cap) {
+    DecodeArgs d{};
+    d.views = a.views;
+    d.recs = a.recs;
+    d.feats = p.scenes[0].feats;
+    d.mlp = p.scenes[0].mlp;
+    d.G = p.G;
+    d.frags = static_cast<FragRec*>(c->frags.p);
+    d.frag_cap = cap;
+    d.frag_count = static_cast<unsigned long long*>(c->counters.p) + 4;
+    d.counter = a.counter;
+    d.n_blocks = decode_blocks(c);
+    return d;
+}
+
 soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_views* views, const soup_opts* opts,
                                uint64_t* vis, float* color, float* logp, void* stream) {
     if (!c) return SOUP_ERR_INVALID;
@@ -480,17 +545,15 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
     HIP_TRY(c, hipGetLastError());
     if (logp) {
         Timed t(c, SOUP_T_LOGP, s);
-        if (o.mode != 0) {
-            launch_fill_f32(logp, p.n_pix, 0.0f, s);
-        } else {
-            BwdArgs b{};
-            b.r = a;
-            b.r.counter = nullptr;
-            b.vis = vis;
-            b.logp = logp;
-            b.n_blocks = persistent_blocks(c, p);
-            launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
-            launch_raster_bwd(b, c->tile, p.kind, true, s);
+        launch_fill_f32(logp, p.n_pix, 0.0f, s);
+        if (o.mode == 0) {
+            RasterArgs ra = a;
+            ra.counter = nullptr;
+            int64_t n_frag = 0;
+            if ((st = replay(c, p, ra, vis, nullptr, nullptr, true, s, &n_frag))) return st;
+            DecodeArgs d = decode_args(c, p, ra, static_cast<uint64_t>(n_frag));
+            d.logp = logp;
+            launch_decode_bwd(d, p.kind, true, s);
         }
         HIP_TRY(c, hipGetLastError());
     }
@@ -513,8 +576,8 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     HIP_TRY(c, hipSetDevice(c->device));
     const Opts o = to_opts(opts);
     if ((st = bin(c, p, o, s))) return st;
-    const int nb = persistent_blocks(c, p);
-    const int rows = nb * waves_per_block(c->tile);
+    const int nb = decode_blocks(c);
+    const int rows = nb * 4;
     const int T = scene->T;
     const int RS = rec_stride(scene->C);
     if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
@@ -523,63 +586,45 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
         (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 4)) ||
         (st = ensure(c, c->tri_off, static_cast<size_t>(T + 1) * 8)) ||
+        (st = ensure(c, c->chunk_off, static_cast<size_t>(T + 1) * 8)) ||
         (st = ensure(c, c->tri_bsum, static_cast<size_t>((T + 1023) / 1024 + 1) * 8)))
         return st;
     RasterArgs a = raster_args(c, p, o);
-    unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
-    // record capacity: last call's count with headroom, else 1.5 records per pixel
-    uint64_t cap = c->rec_cap_hint ? c->rec_cap_hint + c->rec_cap_hint / 4
-                                   : static_cast<uint64_t>(p.n_pix) * 3 / 2 + 1024;
+    const float* gl = o.mode == 0 ? grad_logp : nullptr;
     int64_t n_rec = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        if ((st = ensure(c, c->records, static_cast<size_t>(cap) * RS * 4)) ||
-            (st = ensure(c, c->rec_tri, static_cast<size_t>(cap) * 4)))
-            return st;
-        {
-            Timed t(c, SOUP_T_FILL, s);
-            launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
-            launch_fill_i32(static_cast<int32_t*>(c->tri_count.p), T, 0, s);
-            launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
-            launch_fill_i32(reinterpret_cast<int32_t*>(cnt + 3), 2, 0, s);
-        }
-        BwdArgs b{};
-        b.r = a;
-        b.vis = vis;
-        b.color = color;
-        b.grad_color = grad_color;
-        b.grad_logp = grad_logp;
-        b.vacc = static_cast<float*>(c->vacc.p);
-        b.mlp_partial = static_cast<float*>(c->partial.p);
-        b.records = static_cast<float*>(c->records.p);
-        b.rec_tri = static_cast<uint32_t*>(c->rec_tri.p);
-        b.rec_cap = cap;
-        b.rec_count = cnt + 3;
-        b.tri_count = static_cast<int32_t*>(c->tri_count.p);
-        b.n_blocks = nb;
-        {
-            Timed t(c, SOUP_T_BWD, s);
-            launch_raster_bwd(b, c->tile, p.kind, false, s);
-        }
-        HIP_TRY(c, hipGetLastError());
-        int64_t* hcount = reinterpret_cast<int64_t*>(c->host_stage);
-        HIP_TRY(c, hipMemcpyAsync(hcount, cnt + 3, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-        n_rec = *hcount;
-        if (static_cast<uint64_t>(n_rec) <= cap) break;
-        cap = static_cast<uint64_t>(n_rec) + static_cast<uint64_t>(n_rec) / 8 + 1024;   // retry once, sized exactly
+    if ((st = replay(c, p, a, vis, grad_color, gl, false, s, &n_rec))) return st;
+    if ((st = ensure(c, c->records, static_cast<size_t>(n_rec) * RS * 4)) ||
+        (st = ensure(c, c->rec_tri, static_cast<size_t>(n_rec) * 4)))
+        return st;
+    {
+        Timed t(c, SOUP_T_FILL, s);
+        launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
+        launch_fill_i32(static_cast<int32_t*>(c->tri_count.p), T, 0, s);
     }
-    if (static_cast<uint64_t>(n_rec) > cap) return fail(c, SOUP_ERR_CAPACITY, "gradient records overflowed twice");
-    c->rec_cap_hint = static_cast<uint64_t>(n_rec);
-    if (n_rec >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "more than 2^32 gradient records");
+    {
+        DecodeArgs d = decode_args(c, p, a, static_cast<uint64_t>(n_rec));
+        d.grad_color = grad_color;
+        d.grad_logp = gl;
+        d.records = static_cast<float*>(c->records.p);
+        d.rec_tri = static_cast<uint32_t*>(c->rec_tri.p);
+        d.tri_count = static_cast<int32_t*>(c->tri_count.p);
+        d.mlp_partial = static_cast<float*>(c->partial.p);
+        Timed t(c, SOUP_T_BWD, s);
+        launch_decode_bwd(d, p.kind, false, s);
+    }
+    HIP_TRY(c, hipGetLastError());
     if ((st = ensure(c, c->rec_idx, static_cast<size_t>(n_rec) * 4))) return st;
     {
-        Timed t(c, SOUP_T_REDUCE, s);
+        Timed t(c, SOUP_T_GRAD, s);
         launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
                     static_cast<int64_t*>(c->tri_off.p), s);
         launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), T, 0, s);
         launch_bucket(static_cast<uint32_t*>(c->rec_tri.p), n_rec, static_cast<int64_t*>(c->tri_off.p),
                       static_cast<int32_t*>(c->tri_fill.p), static_cast<uint32_t*>(c->rec_idx.p), s);
-        launch_reduce(static_cast<float*>(c->records.p), scene->C, scene->G, T, static_cast<int64_t*>(c->tri_off.p),
+        // tri_fill and tri_bsum are free again once the records are bucketed
+        launch_reduce(static_cast<float*>(c->records.p), scene->C, scene->G, T, n_rec,
+                      static_cast<int64_t*>(c->tri_off.p), static_cast<int32_t*>(c->tri_fill.p),
+                      static_cast<int64_t*>(c->tri_bsum.p), static_cast<int64_t*>(c->chunk_off.p),
                       static_cast<uint32_t*>(c->rec_idx.p), grad_feats, grad_verts, o.accumulate != 0, s);
     }
     {

@@ -278,6 +278,16 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
     return reinterpret_cast<T*>(uniform_i64(reinterpret_cast<int64_t>(p)));
 }
 
+// A wave-uniform pointer whose value the compiler cannot see through: loads
+// from it can neither be hoisted above this point nor merged with loads
+// through another copy.
+template <class T>
+__device__ __forceinline__ T* opaque_ptr(T* p) {
+    uint64_t v = reinterpret_cast<uint64_t>(p);
+    asm volatile("" : "+s"(v));
+    return reinterpret_cast<T*>(v);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int l = __lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));

@@ -1,0 +1,10 @@
+// Backward fragment decode instantiated for the MLP shape (32, 64, 2).
+#include "decode_bwd_impl.hpp"
+
+namespace soup {
+
+void launch_decode_bwd_k32_64_2(const DecodeArgs& a, bool logp, hipStream_t s) {
+    launch_decode_bwd_s<MlpShape<32, 64, 2>>(a, logp, s);
+}
+
+}  // namespace soup

@@ -1,0 +1,10 @@
+// Backward fragment decode instantiated for the MLP shape (8, 16, 1).
+#include "decode_bwd_impl.hpp"
+
+namespace soup {
+
+void launch_decode_bwd_k8_16_1(const DecodeArgs& a, bool logp, hipStream_t s) {
+    launch_decode_bwd_s<MlpShape<8, 16, 1>>(a, logp, s);
+}
+
+}  // namespace soup

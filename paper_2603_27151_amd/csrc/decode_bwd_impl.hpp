@@ -1,0 +1,375 @@
+#pragma once
+// Backward, part 2 (Supplement Algorithm A1, part 2; Eq. (8), (9)): decode of
+// the fragment list written by the replay kernel.
+//
+// Persistent waves take batches of 64 consecutive fragments. For each:
+//   - recompute the bilinear feature and the MLP (float32, as the forward);
+//   - logit gradients: winner -> colour path g_C sigma'(o_rgb) and score
+//     g_L (1 - alpha); fragment in front -> score -g_L alpha (Eq. (9) through
+//     the sigmoid);
+//   - back-propagate through the MLP; the weight gradient sum_f delta_f a_f^T
+//     runs on the matrix cores over the batch (activations and deltas staged
+//     through LDS); each wave writes its sums once, at the end, to its own row
+//     of a partial-sum buffer (rows are reduced later in a fixed order);
+//   - one record per fragment at the fragment's own index: texture cell,
+//     position, feature gradient and, for the winner, the gradient of its
+//     triangle's world-space vertices, through the perspective-correct and
+//     screen barycentrics, the screen positions and 1/w, and the
+//     view-projection.
+// A logp variant sums log(1 - alpha) over the front set and log(alpha) of the
+// winner per pixel (log p(f*) of Eq. (6)).
+#include "raster_common.hpp"
+
+namespace soup {
+
+constexpr int kStageRows = 16;   // fragments staged per transpose pass
+
+template <class S>
+struct StageCfg {
+    static constexpr int kMax2(int a, int b) { return a > b ? a : b; }
+    static constexpr int kWidth = kMax2(kMax2(S::C + S::H, 2 * S::H), S::H + 4);
+};
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Accumulators of one layer's weight gradient dW[DOUT][DIN] += sum_f d_f a_f^T
+// on the matrix cores: the contraction runs over fragments, four per
+// v_mfma_f32_16x16x4f32 (A[m][k] = d[f_k][m], B[k][n] = a[f_k][n]); dW is
+// tiled in 16x16 blocks held in registers (4 per lane per block), padded
+// with zeros where DIN or DOUT is below 16. Lane j < DOUT owns db_j.
+template <int DIN, int DOUT>
+struct LayerAcc {
+    static constexpr int BI = (DIN + 15) / 16;
+    static constexpr int BO = (DOUT + 15) / 16;
+    static constexpr int NB = BI * BO;
+    static_assert(DOUT <= 64, "bias ownership assumes DOUT <= 64");
+    f4v w[NB];
+    float b;
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) w[i] = f4v{0.f, 0.f, 0.f, 0.f};
+        b = 0.0f;
+    }
+    // kStageRows (16) staged fragments: in[r][DIN] and d[r][DOUT] in LDS
+    __device__ __forceinline__ void accumulate(const float* __restrict__ in, const float* __restrict__ d, int lane) {
+        const int col = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int kk = 0; kk < kStageRows / 4; ++kk) {
+            const int r = 4 * kk + kq;
+            float av[BO], bv[BI];
+#pragma unroll
+            for (int bo = 0; bo < BO; ++bo) {
+                const int m = 16 * bo + col;
+                av[bo] = m < DOUT ? d[r * DOUT + m] : 0.0f;
+            }
+#pragma unroll
+            for (int bi = 0; bi < BI; ++bi) {
+                const int n = 16 * bi + col;
+                bv[bi] = n < DIN ? in[r * DIN + n] : 0.0f;
+            }
+#pragma unroll
+            for (int bo = 0; bo < BO; ++bo)
+#pragma unroll
+                for (int bi = 0; bi < BI; ++bi)
+                    w[bo * BI + bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bo], bv[bi], w[bo * BI + bi], 0, 0, 0);
+        }
+        if (lane < DOUT) {
+#pragma unroll
+            for (int r = 0; r < kStageRows; ++r) b += d[r * DOUT + lane];
+        }
+    }
+    // D of a 16x16 block: lane l holds column l % 16, rows 4 (l / 16) + i
+    __device__ __forceinline__ void store(float* __restrict__ row, int w_off, int b_off, int lane) const {
+#pragma unroll
+        for (int bo = 0; bo < BO; ++bo)
+#pragma unroll
+            for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = 16 * bo + 4 * (lane >> 4) + i, n = 16 * bi + (lane & 15);
+                    if (m < DOUT && n < DIN) row[w_off + m * DIN + n] = w[bo * BI + bi][i];
+                }
+        if (lane < DOUT) row[b_off + lane] = b;
+    }
+};
+
+// Stage the activations (in) and deltas (dl) of the wave's 64 fragments
+// through LDS, kStageRows at a time, and accumulate them on the matrix cores.
+template <int DIN, int DOUT>
+__device__ __forceinline__ void stage_accumulate(LayerAcc<DIN, DOUT>& la, float* __restrict__ st,
+                                                 const float (&in)[DIN], const float (&dl)[DOUT], int lane) {
+#pragma unroll
+    for (int half = 0; half < 64; half += kStageRows) {
+        if (lane >= half && lane < half + kStageRows) {
+            float* row = st + (lane - half) * DIN;
+#pragma unroll
+            for (int k = 0; k < DIN; k += 4) *reinterpret_cast<float4*>(row + k) = make_float4(in[k], in[k + 1], in[k + 2], in[k + 3]);
+            float* drow = st + kStageRows * DIN + (lane - half) * DOUT;
+#pragma unroll
+            for (int k = 0; k < DOUT; k += 4)
+                *reinterpret_cast<float4*>(drow + k) = make_float4(dl[k], dl[k + 1], dl[k + 2], dl[k + 3]);
+        }
+        __threadfence_block();
+        la.accumulate(st, st + kStageRows * DIN, lane);
+        __threadfence_block();
+    }
+}
+
+template <class S>
+struct MlpGrad {
+    LayerAcc<S::C, S::H> l0;
+    LayerAcc<S::H, S::H> mid[S::NH > 1 ? S::NH - 1 : 1];
+    LayerAcc<S::H, 4> out;
+};
+
+template <class S, bool LOGP>
+__global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
+    constexpr int NW = 4;
+    constexpr int SW = StageCfg<S>::kWidth;
+    __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int G = a.G;
+    gfloat* __restrict__ feats = as_global(uniform_ptr(a.feats));
+
+    MlpGrad<S> acc;
+    if (!LOGP) {
+        acc.l0.zero();
+        if constexpr (S::NH == 2) acc.mid[0].zero();
+        acc.out.zero();
+    }
+    const uint64_t cnt = *a.frag_count;
+    const uint64_t n = cnt < a.frag_cap ? cnt : a.frag_cap;
+    const uint64_t n_batch = (n + 63) / 64;
+    const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * NW;
+    for (uint64_t bi = static_cast<uint64_t>(blockIdx.x) * NW + w; bi < n_batch; bi += n_waves) {
+        const uint64_t fi = bi * 64 + lane;
+        const bool on = fi < n;
+        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb4 = make_uint4(0u, 0u, 0u, 0u);
+        if (on) {
+            fa = a.frags[fi].a;
+            fb4 = a.frags[fi].b;
+        }
+        const uint32_t pix = fa.x;
+        const uint32_t tri = fa.y & 0x7FFFFFFFu;
+        const bool win = on && (fa.y >> 31);
+        const float b1 = __uint_as_float(fa.z), b2 = __uint_as_float(fa.w);
+        const Cell c = cell_of(b1, b2, G);
+        float x[S::C];
+        MlpAct<S> m;
+        if (on) {
+            fetch_feature<S::C>(feats, tri, G, c, x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < S::C; ++k) x[k] = 0.0f;
+        }
+        // The weights are re-read from the scalar cache in every batch and in
+        // each of the forward and backward halves: an opaque copy of the
+        // pointer per use keeps the compiler from hoisting ~S::kParams scalar
+        // loads out of the loop (or sharing them between the halves), which
+        // would spill them all to VGPR lanes.
+        mlp_forward<S>(as_const(opaque_ptr(a.mlp)), x, m);
+        const float alpha = sigmoid_c(m.o[3]);
+        if (a.counter && lane == 0) {
+            const uint64_t left = n - bi * 64;
+            atomicAdd(a.counter, static_cast<unsigned long long>(left < 64 ? left : 64));
+        }
+        if (LOGP) {
+            if (on) atomicAdd(&a.logp[pix], win ? logf(alpha) : log1pf(-alpha));
+            continue;
+        }
+        float d[4] = {0.f, 0.f, 0.f, 0.f};
+        float gcol[3] = {0.f, 0.f, 0.f};
+        if (on) {
+            const float gl = a.grad_logp ? a.grad_logp[pix] : 0.0f;
+            if (win) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    gcol[k] = a.grad_color[3 * static_cast<size_t>(pix) + k];
+                    const float s = sigmoid_c(m.o[k]);
+                    d[k] = gcol[k] * s * (1.0f - s);
+                }
+                d[3] = gl * (1.0f - alpha);
+            } else {
+                d[3] = -gl * alpha;
+            }
+        }
+        // --- MLP backward, output layer first ---
+        cfloat* __restrict__ mlp = as_const(opaque_ptr(a.mlp));
+        float* st = s_stage[w];
+        // transposed products run row by row (contiguous weight reads), which
+        // keeps each output's summation order: ascending row index
+        float dh[S::H];
+#pragma unroll
+        for (int k = 0; k < S::H; ++k) dh[k] = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            cfloat* Wr = mlp + S::w_off(S::NH) + jj * S::H;
+#pragma unroll
+            for (int k = 0; k < S::H; ++k) dh[k] = __builtin_fmaf(Wr[k], d[jj], dh[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < S::H; ++k) dh[k] = m.h[S::NH - 1][k] > 0.0f ? dh[k] : 0.0f;
+        stage_accumulate<S::H, 4>(acc.out, st, m.h[S::NH - 1], d, lane);
+        // hidden layer 1 -> 0 (the compiled shapes have one or two hidden layers)
+        static_assert(S::NH == 1 || S::NH == 2, "one or two hidden layers");
+        if constexpr (S::NH == 2) {
+            float dprev[S::H];
+#pragma unroll
+            for (int k = 0; k < S::H; ++k) dprev[k] = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < S::H; ++jj) {
+                cfloat* Wr = mlp + S::w_off(1) + jj * S::H;
+#pragma unroll
+                for (int k = 0; k < S::H; ++k) dprev[k] = __builtin_fmaf(Wr[k], dh[jj], dprev[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < S::H; ++k) dprev[k] = m.h[0][k] > 0.0f ? dprev[k] : 0.0f;
+            stage_accumulate<S::H, S::H>(acc.mid[0], st, m.h[0], dh, lane);
+#pragma unroll
+            for (int k = 0; k < S::H; ++k) dh[k] = dprev[k];
+        }
+        float dx[S::C];
+#pragma unroll
+        for (int k = 0; k < S::C; ++k) dx[k] = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < S::H; ++jj) {
+            cfloat* Wr = mlp + S::w_off(0) + jj * S::C;
+#pragma unroll
+            for (int k = 0; k < S::C; ++k) dx[k] = __builtin_fmaf(Wr[k], dh[jj], dx[k]);
+        }
+        stage_accumulate<S::C, S::H>(acc.l0, st, x, dh, lane);
+        // --- the winner's world-space vertex gradient ---
+        float gw[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (win) {
+            const ViewDesc& vd = a.views[fb4.w];
+            const TriRec& tr = a.recs[vd.rec_base + tri];
+            const int W = vd.W, H = vd.H;
+            const int64_t local = static_cast<int64_t>(pix) - vd.pix_base;
+            const int px = static_cast<int>(local % W), py = static_cast<int>(local / W);
+            const size_t t00 = ((static_cast<size_t>(tri) * G + c.iy) * G + c.ix) * S::C;
+            const size_t t10 = t00 + S::C, t01 = t00 + static_cast<size_t>(G) * S::C, t11 = t01 + S::C;
+            // texture position -> barycentrics -> vertex screen positions and 1/w
+            float dfx = 0.f, dfy = 0.f;
+#pragma unroll
+            for (int k = 0; k < S::C; ++k) {
+                const float T00 = feats[t00 + k], T10 = feats[t10 + k], T01 = feats[t01 + k], T11 = feats[t11 + k];
+                dfx = __builtin_fmaf(dx[k], (1.0f - c.fy) * (T10 - T00) + c.fy * (T11 - T01), dfx);
+                dfy = __builtin_fmaf(dx[k], (1.0f - c.fx) * (T01 - T00) + c.fx * (T11 - T10), dfy);
+            }
+            const float gm1 = static_cast<float>(G - 1);
+            const float fb[3] = {__uint_as_float(fb4.x), __uint_as_float(fb4.y), __uint_as_float(fb4.z)};
+            float iwv[3];
+            int32_t Xv[3], Yv[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                iwv[i] = tr.iw[i];
+                Xv[i] = tr.X[i];
+                Yv[i] = tr.Y[i];
+            }
+            float tt[3], S3 = 0.f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                tt[i] = fb[i] * iwv[i];
+                S3 += tt[i];
+            }
+            const float inv_s = 1.0f / S3;
+            const float bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
+            const float db[3] = {0.0f, dfx * gm1, dfy * gm1};
+            const float dot = db[1] * bb[1] + db[2] * bb[2];
+            float dbeta[3], diw[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float dt = (db[i] - dot) * inv_s;
+                dbeta[i] = dt * iwv[i];
+                diw[i] = dt * fb[i];
+            }
+            // geometry in pixel units from exact integer differences
+            const int32_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
+            const int64_t Ai = static_cast<int64_t>(Xv[1] - Xv[0]) * (Yv[2] - Yv[0]) -
+                               static_cast<int64_t>(Yv[1] - Yv[0]) * (Xv[2] - Xv[0]);
+            const float inv_area = 65536.0f / static_cast<float>(Ai);
+            const float inv256 = 1.0f / 256.0f;
+            float gsx[3] = {0.f, 0.f, 0.f}, gsy[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int p = i == 2 ? 0 : i + 1, qq = i == 0 ? 2 : (i == 1 ? 0 : 1);
+                // beta_i = e_i / area with e_i = edge(v_p, v_q, pixel centre)
+                const float bi = fb[i];
+#pragma unroll
+                for (int jv = 0; jv < 3; ++jv) {
+                    const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
+                    const float dax = static_cast<float>(Yv[jp] - Yv[jq]) * inv256;
+                    const float day = static_cast<float>(Xv[jq] - Xv[jp]) * inv256;
+                    float dex = 0.f, dey = 0.f;
+                    if (jv == p) {
+                        dex = static_cast<float>(Yv[qq] - PY) * inv256;
+                        dey = static_cast<float>(PX - Xv[qq]) * inv256;
+                    } else if (jv == qq) {
+                        dex = static_cast<float>(PY - Yv[p]) * inv256;
+                        dey = static_cast<float>(Xv[p] - PX) * inv256;
+                    }
+                    gsx[jv] += dbeta[i] * (dex - bi * dax) * inv_area;
+                    gsy[jv] += dbeta[i] * (dey - bi * day) * inv_area;
+                }
+            }
+            // screen position and 1/w -> clip -> world through the view-projection
+            const float hw = 0.5f * static_cast<float>(W), hh = 0.5f * static_cast<float>(H);
+#pragma unroll
+            for (int jv = 0; jv < 3; ++jv) {
+                const float iw = iwv[jv];
+                const float sx = static_cast<float>(Xv[jv]) * inv256, sy = static_cast<float>(Yv[jv]) * inv256;
+                const float gc0 = gsx[jv] * hw * iw;
+                const float gc1 = -gsy[jv] * hh * iw;
+                const float gc3 = (-gsx[jv] * (sx - hw) + gsy[jv] * (hh - sy)) * iw - diw[jv] * iw * iw;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gw[3 * jv + k] = vd.M[k] * gc0 + vd.M[4 + k] * gc1 + vd.M[12 + k] * gc3;
+            }
+        }
+        // --- the record, at the fragment's own index ---
+        if (on) {
+            float* rec = a.records + fi * kRecStride<S::C>;
+            *reinterpret_cast<float4*>(rec) =
+                make_float4(__uint_as_float(tri),
+                            __uint_as_float(static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 8) |
+                                            (win ? 0x80000000u : 0u)),
+                            c.fx, c.fy);
+#pragma unroll
+            for (int k = 0; k < S::C; k += 4)
+                *reinterpret_cast<float4*>(rec + 4 + k) = make_float4(dx[k], dx[k + 1], dx[k + 2], dx[k + 3]);
+            if (win) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) rec[4 + S::C + k] = gw[k];
+            }
+            a.rec_tri[fi] = tri;
+        }
+        // per-triangle record counts, one atomic per run of equal triangles
+        const uint32_t tkey = on ? tri : 0xFFFFFFFFu;
+        const uint32_t tprev = __shfl_up(tkey, 1, 64);
+        const bool head = on && (lane == 0 || tprev != tkey);
+        const uint64_t heads = __ballot(head);
+        const uint64_t act = __ballot(on);
+        if (head) {
+            const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+            const int last = 63 - __builtin_clzll(act);
+            const int endl = above ? __builtin_ctzll(above) : last + 1;
+            atomicAdd(&a.tri_count[tri], endl - lane);
+        }
+    }
+    if (!LOGP) {
+        float* row = a.mlp_partial + (static_cast<size_t>(blockIdx.x) * NW + w) * S::kParams;
+        acc.l0.store(row, S::w_off(0), S::b_off(0), lane);
+        if constexpr (S::NH == 2) acc.mid[0].store(row, S::w_off(1), S::b_off(1), lane);
+        acc.out.store(row, S::w_off(S::NH), S::b_off(S::NH), lane);
+    }
+}
+
+template <class S>
+static void launch_decode_bwd_s(const DecodeArgs& a, bool logp, hipStream_t s) {
+    if (logp)
+        hipLaunchKernelGGL((decode_bwd_kernel<S, true>), dim3(a.n_blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((decode_bwd_kernel<S, false>), dim3(a.n_blocks), dim3(256), 0, s, a);
+}
+
+}  // namespace soup

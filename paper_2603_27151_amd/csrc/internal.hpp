@@ -37,24 +37,48 @@ struct RasterArgs {
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 
-struct BwdArgs {
+// One fragment the backward needs, 32 bytes: a = (pixel, triangle | winner << 31,
+// perspective-correct b1, b2), b = (screen barycentrics beta0..2, view).
+struct FragRec {
+    uint4 a;
+    uint4 b;
+};
+
+struct ReplayArgs {
     RasterArgs r;
     const uint64_t* vis;
-    const float* color;
-    const float* grad_color;       // [P,3]
+    const float* grad_color;       // [P,3] (null in the logp pass)
     const float* grad_logp;        // [P] or null
-    float* vacc;                   // [records, 16] edge-term moments per (view, triangle)
-    float* records;                // [rec_cap, kRecStride<C>] per-fragment gradient records
-    uint32_t* rec_tri;             // [rec_cap] triangle of each record
-    uint64_t rec_cap;
-    unsigned long long* rec_count; // records emitted (may exceed rec_cap: then the call retries)
-    int32_t* tri_count;            // [T] records per triangle
-    float* mlp_partial;            // [n_waves, n_params]
-    float* logp;                   // logp output (logp pass only)
+    int all_front;                 // logp pass: every pixel needs its whole front set
+    FragRec* frags;                // [frag_cap]
+    uint64_t frag_cap;
+    unsigned long long* frag_count; // fragments found (may exceed frag_cap: then the call retries)
     int n_blocks;                  // persistent grid size
 };
 
-void launch_raster_bwd(const BwdArgs& a, int tile, MlpKind k, bool logp_pass, hipStream_t s);
+void launch_replay(const ReplayArgs& a, int tile, hipStream_t s);
+
+struct DecodeArgs {
+    const ViewDesc* views;
+    const TriRec* recs;
+    const float* feats;
+    const float* mlp;
+    int G;
+    const FragRec* frags;
+    uint64_t frag_cap;
+    const unsigned long long* frag_count;
+    const float* grad_color;       // [P,3]
+    const float* grad_logp;        // [P] or null (also null in threshold mode)
+    float* records;                // [frag_cap, kRecStride<C>] per-fragment gradient records
+    uint32_t* rec_tri;             // [frag_cap] triangle of each record
+    int32_t* tri_count;            // [T] records per triangle
+    float* mlp_partial;            // [n_blocks * 4, n_params]
+    float* logp;                   // logp output (logp pass only; zeroed by the caller)
+    unsigned long long* counter;   // decode counter or null
+    int n_blocks;
+};
+
+void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp_pass, hipStream_t s);
 void launch_edge(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis, const float* color,
                  const float* grad_color, const TriRec* recs, float* vacc, hipStream_t s);
 void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
@@ -78,7 +102,11 @@ inline int rec_stride(int C) { return ((4 + C + 9) + 3) / 4 * 4; }
 
 void launch_bucket(const uint32_t* rec_tri, int64_t n, const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx,
                    hipStream_t s);
-void launch_reduce(const float* records, int C, int G, int T, const int64_t* tri_off, const uint32_t* idx,
+// Per-triangle reduction of the records listed by idx (grouped by triangle,
+// tri_off[T + 1]), in chunks of a bounded number of records. chunk_n [T],
+// chunk_bsum (scan block sums) and chunk_off [T + 1] are scratch.
+void launch_reduce(const float* records, int C, int G, int T, int64_t n_rec, const int64_t* tri_off,
+                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, const uint32_t* idx,
                    float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s);
 
 }  // namespace soup

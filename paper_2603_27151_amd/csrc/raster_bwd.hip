@@ -1,38 +1,21 @@
 // Gradient reduction, edge term, vertex chain, MLP-gradient reduction, loss and
-// contract self-test kernels; dispatch of the backward raster over the
-// compiled MLP shapes (the raster kernel is in raster_bwd_impl.hpp,
-// instantiated once per shape in bwd_*.hip).
+// contract self-test kernels; dispatch of the backward fragment decode over
+// the compiled MLP shapes (the kernel is in decode_bwd_impl.hpp, instantiated
+// once per shape in dbwd_*.hip).
 #include "raster_common.hpp"
 
 namespace soup {
 
-void launch_raster_bwd_k8_16_1_t8(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k8_16_1_t16(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k8_16_1_t32(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k16_32_2_t8(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k16_32_2_t16(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k16_32_2_t32(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k32_64_2_t8(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k32_64_2_t16(const BwdArgs& a, bool logp, hipStream_t s);
-void launch_raster_bwd_k32_64_2_t32(const BwdArgs& a, bool logp, hipStream_t s);
+void launch_decode_bwd_k8_16_1(const DecodeArgs& a, bool logp, hipStream_t s);
+void launch_decode_bwd_k16_32_2(const DecodeArgs& a, bool logp, hipStream_t s);
+void launch_decode_bwd_k32_64_2(const DecodeArgs& a, bool logp, hipStream_t s);
 
-void launch_raster_bwd(const BwdArgs& a, int tile, MlpKind k, bool logp, hipStream_t s) {
+void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
     switch (k) {
-        case MlpKind::k8_16_1:
-            if (tile == 8) launch_raster_bwd_k8_16_1_t8(a, logp, s);
-            else if (tile == 32) launch_raster_bwd_k8_16_1_t32(a, logp, s);
-            else launch_raster_bwd_k8_16_1_t16(a, logp, s);
-            break;
-        case MlpKind::k16_32_2:
-            if (tile == 8) launch_raster_bwd_k16_32_2_t8(a, logp, s);
-            else if (tile == 32) launch_raster_bwd_k16_32_2_t32(a, logp, s);
-            else launch_raster_bwd_k16_32_2_t16(a, logp, s);
-            break;
-        case MlpKind::k32_64_2:
-            if (tile == 8) launch_raster_bwd_k32_64_2_t8(a, logp, s);
-            else if (tile == 32) launch_raster_bwd_k32_64_2_t32(a, logp, s);
-            else launch_raster_bwd_k32_64_2_t16(a, logp, s);
-            break;
+        case MlpKind::k8_16_1: launch_decode_bwd_k8_16_1(a, logp, s); break;
+        case MlpKind::k16_32_2: launch_decode_bwd_k16_32_2(a, logp, s); break;
+        case MlpKind::k32_64_2: launch_decode_bwd_k32_64_2(a, logp, s); break;
         default: break;
     }
 }
@@ -67,25 +50,64 @@ __global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict_
     if (on) idx[tri_off[tri] + hb + (lane - hl)] = static_cast<uint32_t>(i);
 }
 
-// One workgroup per triangle: sums its records' feature gradients into the
-// G x G x C grid in LDS (bilinear weights of each record's cell position) and
-// its winners' vertex gradients, then writes both once. Thread (seg, c) walks
-// a contiguous segment of the triangle's records for channel c; consecutive
-// records mostly share a cell (they come from the same tile), so the four
-// corner sums stay in registers for a run of equal cells and reach LDS once
-// per run.
+// Records per reduction chunk: 64 per thread of a 256-thread workgroup.
 template <int C>
-__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ records, int G,
+constexpr int64_t kChunkRecs = 64 * (256 / C);
+
+// Chunks per triangle (at least one, so that untouched triangles still get
+// their zero gradient written). A triangle split over several chunks is summed
+// with global atomics, so its outputs are cleared here first unless the call
+// accumulates.
+template <int C>
+__global__ __launch_bounds__(256) void reduce_prep_kernel(const int64_t* __restrict__ tri_off, int T, int n_feat,
+                                                          int32_t* __restrict__ chunk_n,
+                                                          float* __restrict__ grad_feats,
+                                                          float* __restrict__ grad_verts, bool accumulate) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int64_t cnt = tri_off[t + 1] - tri_off[t];
+    const int32_t nch = cnt <= kChunkRecs<C> ? 1 : static_cast<int32_t>((cnt + kChunkRecs<C> - 1) / kChunkRecs<C>);
+    chunk_n[t] = nch;
+    if (nch > 1 && !accumulate) {
+        float* gf = grad_feats + static_cast<size_t>(t) * n_feat;
+        for (int k = 0; k < n_feat; ++k) gf[k] = 0.0f;
+        for (int k = 0; k < 9; ++k) grad_verts[static_cast<size_t>(t) * 9 + k] = 0.0f;
+    }
+}
+
+// One workgroup per chunk of at most kChunkRecs records of one triangle: sums
+// the records' feature gradients into the G x G x C grid in LDS (bilinear
+// weights of each record's cell position) and its winners' vertex gradients.
+// Thread (seg, c) walks a contiguous segment of the chunk for channel c;
+// consecutive records mostly share a cell (they come from the same tile), so
+// the four corner sums stay in registers for a run of equal cells and reach
+// LDS once per run. A triangle of one chunk stores its sums; the chunks of a
+// larger triangle add theirs with global atomics, so that no workgroup walks
+// more than a chunk however many pixels one triangle covers.
+template <int C>
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ records, int G, int T,
                                                      const int64_t* __restrict__ tri_off,
+                                                     const int64_t* __restrict__ chunk_off,
                                                      const uint32_t* __restrict__ idx, float* __restrict__ grad_feats,
                                                      float* __restrict__ grad_verts, bool accumulate) {
     extern __shared__ float s_acc[];      // [G*G*C + 16]
-    const int t = blockIdx.x;
+    const int64_t b = blockIdx.x;
+    if (b >= chunk_off[T]) return;        // the grid is sized by an upper bound of the chunk count
+    int lo = 0, hi = T - 1;               // triangle t with chunk_off[t] <= b < chunk_off[t + 1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunk_off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int t = lo;
+    const int64_t ci = b - chunk_off[t];
+    const bool whole = chunk_off[t + 1] - chunk_off[t] == 1;
     const int n_feat = G * G * C;
     float* s_gv = s_acc + n_feat;
     for (int k = threadIdx.x; k < n_feat + 16; k += blockDim.x) s_acc[k] = 0.0f;
     __syncthreads();
-    const int64_t beg = tri_off[t], end = tri_off[t + 1];
+    const int64_t beg = tri_off[t] + ci * kChunkRecs<C>;
+    const int64_t end = min(tri_off[t + 1], beg + kChunkRecs<C>);
     constexpr int NSEG = 256 / C;
     const int c = threadIdx.x % C, seg = threadIdx.x / C;
     const int64_t per = (end - beg + NSEG - 1) / NSEG;
@@ -137,10 +159,14 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ r
     flush();
     __syncthreads();
     float* gf = grad_feats + static_cast<size_t>(t) * n_feat;
-    for (int k = threadIdx.x; k < n_feat; k += blockDim.x) gf[k] = accumulate ? gf[k] + s_acc[k] : s_acc[k];
-    if (threadIdx.x < 9) {
-        float* gv = grad_verts + static_cast<size_t>(t) * 9 + threadIdx.x;
-        *gv = accumulate ? *gv + s_gv[threadIdx.x] : s_gv[threadIdx.x];
+    float* gv = grad_verts + static_cast<size_t>(t) * 9;
+    if (whole) {
+        for (int k = threadIdx.x; k < n_feat; k += blockDim.x) gf[k] = accumulate ? gf[k] + s_acc[k] : s_acc[k];
+        if (threadIdx.x < 9) gv[threadIdx.x] = accumulate ? gv[threadIdx.x] + s_gv[threadIdx.x] : s_gv[threadIdx.x];
+    } else {
+        for (int k = threadIdx.x; k < n_feat; k += blockDim.x)
+            if (s_acc[k] != 0.0f) atomicAdd(&gf[k], s_acc[k]);
+        if (threadIdx.x < 9 && s_gv[threadIdx.x] != 0.0f) atomicAdd(&gv[threadIdx.x], s_gv[threadIdx.x]);
     }
 }
 
@@ -151,22 +177,41 @@ void launch_bucket(const uint32_t* rec_tri, int64_t n, const int64_t* tri_off, i
                        tri_off, tri_fill, idx);
 }
 
-void launch_reduce(const float* records, int C, int G, int T, const int64_t* tri_off, const uint32_t* idx,
+template <int C>
+static void launch_reduce_c(const float* records, int G, int T, int64_t n_rec, const int64_t* tri_off,
+                            int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, const uint32_t* idx,
+                            float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
+    const int n_feat = G * G * C;
+    hipLaunchKernelGGL(reduce_prep_kernel<C>, dim3((T + 255) / 256), dim3(256), 0, s, tri_off, T, n_feat, chunk_n,
+                       grad_feats, grad_verts, accumulate);
+    launch_scan(chunk_n, T, chunk_bsum, chunk_off, s);
+    const int64_t blocks = T + n_rec / kChunkRecs<C> + 1;   // >= sum over t of max(1, ceil(n_t / K))
+    const size_t lds = (static_cast<size_t>(n_feat) + 16) * sizeof(float);
+    hipLaunchKernelGGL(reduce_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, s, records, G, T,
+                       tri_off, chunk_off, idx, grad_feats, grad_verts, accumulate);
+}
+
+int64_t reduce_chunk_bound(int C, int T, int64_t n_rec) {
+    const int64_t K = 64 * (256 / C);
+    return T + n_rec / K + 1;
+}
+
+void launch_reduce(const float* records, int C, int G, int T, int64_t n_rec, const int64_t* tri_off,
+                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, const uint32_t* idx,
                    float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
     if (T <= 0) return;
-    const size_t lds = (static_cast<size_t>(G) * G * C + 16) * sizeof(float);
     switch (C) {
         case 8:
-            hipLaunchKernelGGL(reduce_kernel<8>, dim3(T), dim3(256), lds, s, records, G, tri_off, idx, grad_feats,
-                               grad_verts, accumulate);
+            launch_reduce_c<8>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, idx, grad_feats,
+                               grad_verts, accumulate, s);
             break;
         case 16:
-            hipLaunchKernelGGL(reduce_kernel<16>, dim3(T), dim3(256), lds, s, records, G, tri_off, idx, grad_feats,
-                               grad_verts, accumulate);
+            launch_reduce_c<16>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, idx, grad_feats,
+                                grad_verts, accumulate, s);
             break;
         case 32:
-            hipLaunchKernelGGL(reduce_kernel<32>, dim3(T), dim3(256), lds, s, records, G, tri_off, idx, grad_feats,
-                               grad_verts, accumulate);
+            launch_reduce_c<32>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, idx, grad_feats,
+                                grad_verts, accumulate, s);
             break;
         default: break;
     }

@@ -53,9 +53,6 @@ struct ChunkLds {
     uint32_t zmin[NT];
     uint32_t own[NT];        // bit i: edge i owns centres exactly on it
     uint32_t box[NT];        // tile-local bbox x0 | y0 << 8 | x1 << 16 | y1 << 24
-    int32_t X[3][NT];        // snapped vertices (backward needs them)
-    int32_t Y[3][NT];
-    int32_t rec[NT];         // record index - rec_base (the triangle id)
 };
 
 // Fill slot i of the chunk from a sorted tile entry.
@@ -86,12 +83,9 @@ __device__ __forceinline__ void load_slot(ChunkLds<NT>& ch, int i, uint64_t entr
         if (ndy < 0 || (ndy == 0 && ndx > 0)) own |= 1u << e;
         ch.z[e][i] = r.z01[e];
         ch.iw[e][i] = r.iw[e];
-        ch.X[e][i] = r.X[e];
-        ch.Y[e][i] = r.Y[e];
     }
     ch.own[i] = own;
     ch.ra[i] = __builtin_fabsf(r.rA);
-    ch.rec[i] = static_cast<int32_t>(tri);
 }
 
 struct Frag {
