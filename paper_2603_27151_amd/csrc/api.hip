@@ -30,7 +30,10 @@ struct soup_ctx {
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
     DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum, chunk_off, mlp_mid, frags;
-    uint64_t frag_cap_hint = 0;      // fragments of the last replay, to size the next
+    DevBuf region_counts, region_boff;
+    uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
+    uint64_t frag_region = 0;        // region size and count of the current fragment list
+    int frag_regions = 0;
     void* host_stage = nullptr;      // pinned: descriptors up, totals down
     size_t host_stage_bytes = 0;
     // optional per-kernel timing: recorded event pairs and a pool of free events
@@ -397,7 +400,7 @@ void soup_ctx_destroy(soup_ctx* c) {
     DevBuf* bufs[] = {&c->views,    &c->scenes,  &c->recs,      &c->tile_count, &c->tile_fill, &c->tile_start,
                       &c->bsum,     &c->entries, &c->vacc,      &c->partial,    &c->counters,  &c->records,
                       &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum,
-                      &c->chunk_off, &c->mlp_mid,  &c->frags};
+                      &c->chunk_off, &c->mlp_mid,  &c->frags,    &c->region_counts, &c->region_boff};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -456,24 +459,38 @@ soup_status soup_last_stats(const soup_ctx* c, soup_stats* out) {
     return SOUP_OK;
 }
 
-// Backward, part 1: replay the fragments the backward needs into c->frags.
-// The list is sized from the last call's count with headroom (else 1.5 per
-// pixel); an overflow is detected from the count and the replay runs again,
-// sized exactly. Returns the fragment count in *n_frag.
+// Persistent grid of the replay: 4 workgroups per CU, at most kMaxRegions waves.
+int replay_blocks(soup_ctx* c, const Plan& p) {
+    const int wpb = replay_waves_per_block(c->tile);
+    const int64_t want = std::min<int64_t>(static_cast<int64_t>(c->num_cus) * 4, kMaxRegions / wpb);
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, p.n_tiles)));
+}
+
+// Backward, part 1: replay the fragments the backward needs into c->frags,
+// one region per replay wave, then scan the region counts into batch
+// offsets. Regions are sized from the last call's largest count with
+// headroom (else from 1.5 fragments per pixel); an overflow is detected from
+// the counts and the replay runs again, sized exactly. Returns the number of
+// fragments in *n_frag and of decode batches in *n_batch.
 soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64_t* vis, const float* grad_color,
-                   const float* grad_logp, bool all_front, hipStream_t s, int64_t* n_frag) {
+                   const float* grad_logp, bool all_front, hipStream_t s, int64_t* n_frag, int64_t* n_batch) {
     if (p.n_pix >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "backward needs fewer than 2^32 pixels per call");
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
-    uint64_t cap = c->frag_cap_hint ? c->frag_cap_hint + c->frag_cap_hint / 4
-                                    : static_cast<uint64_t>(p.n_pix) * 3 / 2 + 1024;
+    const int nb = replay_blocks(c, p);
+    const int nr = nb * replay_waves_per_block(c->tile);
+    uint64_t region = c->region_hint ? c->region_hint + c->region_hint / 4 + 64
+                                     : (static_cast<uint64_t>(p.n_pix) * 3 / 2) / nr + 1024;
     soup_status st;
-    int64_t n = 0;
+    if ((st = ensure(c, c->region_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
+        (st = ensure(c, c->region_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
+        return st;
+    uint64_t summary[3] = {0, 0, 0};
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if ((st = ensure(c, c->frags, static_cast<size_t>(cap) * sizeof(FragRec)))) return st;
+        if (region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment region too large");
+        if ((st = ensure(c, c->frags, static_cast<size_t>(region) * nr * sizeof(FragRec)))) return st;
         {
             Timed t(c, SOUP_T_FILL, s);
             launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
-            launch_fill_i32(reinterpret_cast<int32_t*>(cnt + 4), 2, 0, s);
         }
         ReplayArgs ra{};
         ra.r = a;
@@ -482,41 +499,47 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         ra.grad_logp = grad_logp;
         ra.all_front = all_front ? 1 : 0;
         ra.frags = static_cast<FragRec*>(c->frags.p);
-        ra.frag_cap = cap;
-        ra.frag_count = cnt + 4;
-        ra.n_blocks = persistent_blocks(c, p);
+        ra.region = static_cast<uint32_t>(region);
+        ra.counts = static_cast<uint32_t*>(c->region_counts.p);
+        ra.n_blocks = nb;
         {
             Timed t(c, SOUP_T_REPLAY, s);
             launch_replay(ra, c->tile, s);
+            launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4, s);
         }
         HIP_TRY(c, hipGetLastError());
-        int64_t* hcount = reinterpret_cast<int64_t*>(c->host_stage);
-        HIP_TRY(c, hipMemcpyAsync(hcount, cnt + 4, 8, hipMemcpyDeviceToHost, s));
+        uint64_t* h = reinterpret_cast<uint64_t*>(c->host_stage);
+        HIP_TRY(c, hipMemcpyAsync(h, cnt + 4, 24, hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
-        n = *hcount;
-        if (static_cast<uint64_t>(n) <= cap) break;
-        cap = static_cast<uint64_t>(n) + static_cast<uint64_t>(n) / 8 + 1024;
+        memcpy(summary, h, sizeof(summary));
+        if (summary[2] <= region) break;
+        region = summary[2] + summary[2] / 8 + 64;
     }
-    if (static_cast<uint64_t>(n) > cap) return fail(c, SOUP_ERR_CAPACITY, "fragment list overflowed twice");
-    if (n >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "more than 2^32 backward fragments");
-    c->frag_cap_hint = static_cast<uint64_t>(n);
-    *n_frag = n;
+    if (summary[2] > region) return fail(c, SOUP_ERR_CAPACITY, "fragment list overflowed twice");
+    c->region_hint = summary[2];
+    c->frag_region = region;
+    c->frag_regions = nr;
+    *n_frag = static_cast<int64_t>(summary[0]);
+    *n_batch = static_cast<int64_t>(summary[1]);
     return SOUP_OK;
 }
 
 // Persistent grid of the decode kernel: 4 waves per workgroup, 4 workgroups per CU.
 int decode_blocks(soup_ctx* c) { return std::max(1, c->num_cus * 4); }
 
-DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a, uint64_t cap) {
+DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a) {
     DecodeArgs d{};
     d.views = a.views;
+    d.V = a.V;
     d.recs = a.recs;
     d.feats = p.scenes[0].feats;
     d.mlp = p.scenes[0].mlp;
     d.G = p.G;
     d.frags = static_cast<FragRec*>(c->frags.p);
-    d.frag_cap = cap;
-    d.frag_count = static_cast<unsigned long long*>(c->counters.p) + 4;
+    d.region = static_cast<uint32_t>(c->frag_region);
+    d.counts = static_cast<uint32_t*>(c->region_counts.p);
+    d.boff = static_cast<uint32_t*>(c->region_boff.p);
+    d.n_regions = c->frag_regions;
     d.counter = a.counter;
     d.n_blocks = decode_blocks(c);
     return d;
@@ -549,9 +572,9 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
         if (o.mode == 0) {
             RasterArgs ra = a;
             ra.counter = nullptr;
-            int64_t n_frag = 0;
-            if ((st = replay(c, p, ra, vis, nullptr, nullptr, true, s, &n_frag))) return st;
-            DecodeArgs d = decode_args(c, p, ra, static_cast<uint64_t>(n_frag));
+            int64_t n_frag = 0, n_batch = 0;
+            if ((st = replay(c, p, ra, vis, nullptr, nullptr, true, s, &n_frag, &n_batch))) return st;
+            DecodeArgs d = decode_args(c, p, ra);
             d.logp = logp;
             launch_decode_bwd(d, p.kind, true, s);
         }
@@ -591,8 +614,9 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         return st;
     RasterArgs a = raster_args(c, p, o);
     const float* gl = o.mode == 0 ? grad_logp : nullptr;
-    int64_t n_rec = 0;
-    if ((st = replay(c, p, a, vis, grad_color, gl, false, s, &n_rec))) return st;
+    int64_t n_frag = 0, n_batch = 0;
+    if ((st = replay(c, p, a, vis, grad_color, gl, false, s, &n_frag, &n_batch))) return st;
+    const int64_t n_rec = n_batch * 64;   // one record slot per decode lane
     if ((st = ensure(c, c->records, static_cast<size_t>(n_rec) * RS * 4)) ||
         (st = ensure(c, c->rec_tri, static_cast<size_t>(n_rec) * 4)))
         return st;
@@ -602,7 +626,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         launch_fill_i32(static_cast<int32_t*>(c->tri_count.p), T, 0, s);
     }
     {
-        DecodeArgs d = decode_args(c, p, a, static_cast<uint64_t>(n_rec));
+        DecodeArgs d = decode_args(c, p, a);
         d.grad_color = grad_color;
         d.grad_logp = gl;
         d.records = static_cast<float*>(c->records.p);

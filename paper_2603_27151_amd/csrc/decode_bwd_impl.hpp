@@ -2,7 +2,9 @@
 // Backward, part 2 (Supplement Algorithm A1, part 2; Eq. (8), (9)): decode of
 // the fragment list written by the replay kernel.
 //
-// Persistent waves take batches of 64 consecutive fragments. For each:
+// Persistent waves take batches of 64 consecutive fragments of one region of
+// the list (batch b lies in the region w with boff[w] <= b < boff[w + 1],
+// found by a binary search over the offsets staged in LDS). For each:
 //   - recompute the bilinear feature and the MLP (float32, as the forward);
 //   - logit gradients: winner -> colour path g_C sigma'(o_rgb) and score
 //     g_L (1 - alpha); fragment in front -> score -g_L alpha (Eq. (9) through
@@ -127,6 +129,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
     constexpr int NW = 4;
     constexpr int SW = StageCfg<S>::kWidth;
     __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
+    __shared__ uint32_t s_boff[kMaxRegions + 1];
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int G = a.G;
@@ -138,22 +141,34 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         if constexpr (S::NH == 2) acc.mid[0].zero();
         acc.out.zero();
     }
-    const uint64_t cnt = *a.frag_count;
-    const uint64_t n = cnt < a.frag_cap ? cnt : a.frag_cap;
-    const uint64_t n_batch = (n + 63) / 64;
-    const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * NW;
-    for (uint64_t bi = static_cast<uint64_t>(blockIdx.x) * NW + w; bi < n_batch; bi += n_waves) {
-        const uint64_t fi = bi * 64 + lane;
-        const bool on = fi < n;
+    const int NR = a.n_regions;
+    for (int i = tid; i <= NR; i += blockDim.x) s_boff[i] = a.boff[i];
+    __syncthreads();
+    const uint32_t n_batch = s_boff[NR];
+    const uint32_t n_waves = gridDim.x * NW;
+    for (uint32_t bi = blockIdx.x * NW + w; bi < n_batch; bi += n_waves) {
+        int lo = 0, hi = NR - 1;   // region: last w with boff[w] <= bi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_boff[mid] <= bi) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t cr = a.counts[lo];
+        const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
+        const bool on = in_region < (cr < a.region ? cr : a.region);
+        const uint64_t fi = static_cast<uint64_t>(bi) * 64 + lane;   // record index
         uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb4 = make_uint4(0u, 0u, 0u, 0u);
         if (on) {
-            fa = a.frags[fi].a;
-            fb4 = a.frags[fi].b;
+            const FragRec& fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
+            fa = fr.a;
+            fb4 = fr.b;
         }
         const uint32_t pix = fa.x;
         const uint32_t tri = fa.y & 0x7FFFFFFFu;
         const bool win = on && (fa.y >> 31);
-        const float b1 = __uint_as_float(fa.z), b2 = __uint_as_float(fa.w);
+        const float tt[3] = {__uint_as_float(fa.z), __uint_as_float(fa.w), __uint_as_float(fb4.x)};
+        float b1 = 0.f, b2 = 0.f;
+        if (on) persp_from_t(tt[0], tt[1], tt[2], b1, b2);
         const Cell c = cell_of(b1, b2, G);
         float x[S::C];
         MlpAct<S> m;
@@ -170,10 +185,8 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         // would spill them all to VGPR lanes.
         mlp_forward<S>(as_const(opaque_ptr(a.mlp)), x, m);
         const float alpha = sigmoid_c(m.o[3]);
-        if (a.counter && lane == 0) {
-            const uint64_t left = n - bi * 64;
-            atomicAdd(a.counter, static_cast<unsigned long long>(left < 64 ? left : 64));
-        }
+        const uint64_t on_mask = __ballot(on);
+        if (a.counter && lane == 0) atomicAdd(a.counter, static_cast<unsigned long long>(__popcll(on_mask)));
         if (LOGP) {
             if (on) atomicAdd(&a.logp[pix], win ? logf(alpha) : log1pf(-alpha));
             continue;
@@ -242,7 +255,13 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         // --- the winner's world-space vertex gradient ---
         float gw[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (win) {
-            const ViewDesc& vd = a.views[fb4.w];
+            int lo = 0, hi = a.V - 1;   // the view owning the pixel (views sorted by pix_base)
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.views[mid].pix_base <= static_cast<int64_t>(pix)) lo = mid;
+                else hi = mid - 1;
+            }
+            const ViewDesc& vd = a.views[lo];
             const TriRec& tr = a.recs[vd.rec_base + tri];
             const int W = vd.W, H = vd.H;
             const int64_t local = static_cast<int64_t>(pix) - vd.pix_base;
@@ -258,7 +277,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 dfy = __builtin_fmaf(dx[k], (1.0f - c.fx) * (T01 - T00) + c.fx * (T11 - T10), dfy);
             }
             const float gm1 = static_cast<float>(G - 1);
-            const float fb[3] = {__uint_as_float(fb4.x), __uint_as_float(fb4.y), __uint_as_float(fb4.z)};
+            const float fb[3] = {__uint_as_float(fb4.y), __uint_as_float(fb4.z), __uint_as_float(fb4.w)};
             float iwv[3];
             int32_t Xv[3], Yv[3];
 #pragma unroll
@@ -267,13 +286,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 Xv[i] = tr.X[i];
                 Yv[i] = tr.Y[i];
             }
-            float tt[3], S3 = 0.f;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                tt[i] = fb[i] * iwv[i];
-                S3 += tt[i];
-            }
-            const float inv_s = 1.0f / S3;
+            const float inv_s = 1.0f / ((tt[0] + tt[1]) + tt[2]);
             const float bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
             const float db[3] = {0.0f, dfx * gm1, dfy * gm1};
             const float dot = db[1] * bb[1] + db[2] * bb[2];
@@ -341,18 +354,17 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) rec[4 + S::C + k] = gw[k];
             }
-            a.rec_tri[fi] = tri;
         }
-        // per-triangle record counts, one atomic per run of equal triangles
         const uint32_t tkey = on ? tri : 0xFFFFFFFFu;
+        a.rec_tri[fi] = tkey;
+        // per-triangle record counts, one atomic per run of equal triangles
+        // (an empty lane ends a run)
         const uint32_t tprev = __shfl_up(tkey, 1, 64);
-        const bool head = on && (lane == 0 || tprev != tkey);
+        const bool head = lane == 0 || tprev != tkey;
         const uint64_t heads = __ballot(head);
-        const uint64_t act = __ballot(on);
-        if (head) {
+        if (head && on) {
             const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-            const int last = 63 - __builtin_clzll(act);
-            const int endl = above ? __builtin_ctzll(above) : last + 1;
+            const int endl = above ? __builtin_ctzll(above) : 64;
             atomicAdd(&a.tri_count[tri], endl - lane);
         }
     }

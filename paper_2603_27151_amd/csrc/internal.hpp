@@ -38,11 +38,17 @@ struct RasterArgs {
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 
 // One fragment the backward needs, 32 bytes: a = (pixel, triangle | winner << 31,
-// perspective-correct b1, b2), b = (screen barycentrics beta0..2, view).
+// t0, t1), b = (t2, screen barycentrics beta0..2), with t_i = beta_i / w_i.
 struct FragRec {
     uint4 a;
     uint4 b;
 };
+
+// The fragment list is split into one region of `region` entries per replay
+// wave (wave w owns [w * region, (w + 1) * region)), so that no two waves
+// share a counter. counts[w] is the number of fragments wave w found (it may
+// exceed `region`: the call then runs again with larger regions).
+constexpr int kMaxRegions = 4096;
 
 struct ReplayArgs {
     RasterArgs r;
@@ -50,27 +56,37 @@ struct ReplayArgs {
     const float* grad_color;       // [P,3] (null in the logp pass)
     const float* grad_logp;        // [P] or null
     int all_front;                 // logp pass: every pixel needs its whole front set
-    FragRec* frags;                // [frag_cap]
-    uint64_t frag_cap;
-    unsigned long long* frag_count; // fragments found (may exceed frag_cap: then the call retries)
-    int n_blocks;                  // persistent grid size
+    FragRec* frags;                // [n_regions * region]
+    uint32_t region;
+    uint32_t* counts;              // [n_regions]
+    int n_blocks;                  // persistent grid size (n_regions = n_blocks * waves per block)
 };
 
 void launch_replay(const ReplayArgs& a, int tile, hipStream_t s);
+int replay_waves_per_block(int tile);
+
+// Batch offsets of the regions: boff[w] = sum over v < w of ceil(min(counts[v],
+// region) / 64), boff[n] = total batches; summary = (fragments, batches,
+// largest region count).
+void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
+                        unsigned long long* summary, hipStream_t s);
 
 struct DecodeArgs {
     const ViewDesc* views;
+    int V;
     const TriRec* recs;
     const float* feats;
     const float* mlp;
     int G;
     const FragRec* frags;
-    uint64_t frag_cap;
-    const unsigned long long* frag_count;
+    uint32_t region;
+    const uint32_t* counts;        // [n_regions]
+    const uint32_t* boff;          // [n_regions + 1]
+    int n_regions;
     const float* grad_color;       // [P,3]
     const float* grad_logp;        // [P] or null (also null in threshold mode)
-    float* records;                // [frag_cap, kRecStride<C>] per-fragment gradient records
-    uint32_t* rec_tri;             // [frag_cap] triangle of each record
+    float* records;                // [64 * batches, kRecStride<C>] per-fragment gradient records
+    uint32_t* rec_tri;             // [64 * batches] triangle of each record, 0xFFFFFFFF for an empty lane
     int32_t* tri_count;            // [T] records per triangle
     float* mlp_partial;            // [n_blocks * 4, n_params]
     float* logp;                   // logp output (logp pass only; zeroed by the caller)

@@ -31,17 +31,15 @@ __global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict_
                                                      int32_t* __restrict__ tri_fill, uint32_t* __restrict__ idx) {
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const bool on = i < n;
-    const uint32_t tri = on ? rec_tri[i] : 0xFFFFFFFFu;
+    const uint32_t tri = i < n ? rec_tri[i] : 0xFFFFFFFFu;
+    const bool on = tri != 0xFFFFFFFFu;   // empty record lanes carry the sentinel
     const uint32_t tprev = __shfl_up(tri, 1, 64);
-    const bool head = on && (lane == 0 || tprev != tri);
-    const uint64_t heads = __ballot(head);
-    const uint64_t act = __ballot(on);   // outside the branch: a ballot sees only the lanes that execute it
+    const bool head = lane == 0 || tprev != tri;   // a sentinel lane ends a run
+    const uint64_t heads = __ballot(head);   // outside any branch: a ballot sees only the lanes that execute it
     int base = 0;
-    if (head) {
+    if (head && on) {
         const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-        const int last = 63 - __builtin_clzll(act);
-        const int endl = above ? __builtin_ctzll(above) : last + 1;
+        const int endl = above ? __builtin_ctzll(above) : 64;
         base = atomicAdd(&tri_fill[tri], endl - lane);
     }
     const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));

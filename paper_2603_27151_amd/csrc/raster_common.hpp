@@ -88,27 +88,41 @@ __device__ __forceinline__ void load_slot(ChunkLds<NT>& ch, int i, uint64_t entr
     ch.ra[i] = __builtin_fabsf(r.rA);
 }
 
+// Exact inside test of tile-local pixel (lx, ly) against chunk slot j: the
+// orientation-normalised edge values are left in e, and the pixel is inside
+// when every E_i > 0, or E_i == 0 on an edge that owns the centres on it.
+// Every operand is read up front and the test has no branches, so a wave
+// pays one round of LDS latency per triangle.
+template <int NT>
+__device__ __forceinline__ bool edge_inside(const ChunkLds<NT>& ch, int j, int lx, int ly, double (&e)[3]) {
+    const double dx = static_cast<double>(lx), dy = static_cast<double>(ly);
+    const uint32_t own = ch.own[j];
+    double e0[3], ea[3], eb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        e0[i] = ch.e0[i][j];
+        ea[i] = ch.ea[i][j];
+        eb[i] = ch.eb[i][j];
+    }
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        e[i] = __builtin_fma(dx, ea[i], __builtin_fma(dy, eb[i], e0[i]));
+        in = in & ((e[i] > 0.0) | ((e[i] == 0.0) & (((own >> i) & 1u) != 0u)));
+    }
+    return in;
+}
+
 struct Frag {
     uint64_t key;
     float beta[3];
 };
 
-// Coverage of tile-local pixel (lx, ly) by chunk slot j; on success fills the
-// key and the screen barycentrics of the contract.
+// Screen barycentrics and key of a covering fragment from its edge values
+// (contract: beta_i = (float)E_i * (1 / (float)A); depth = sum beta_i z_i in
+// the stated fma order, clamped to [+0, 1]; key = depth bits << 32 | tri).
 template <int NT>
-__device__ __forceinline__ bool cover(const ChunkLds<NT>& ch, int j, int lx, int ly, Frag& f) {
-    const uint32_t box = ch.box[j];
-    if (lx < static_cast<int>(box & 255u) || ly < static_cast<int>((box >> 8) & 255u) ||
-        lx > static_cast<int>((box >> 16) & 255u) || ly > static_cast<int>(box >> 24))
-        return false;
-    const double dx = static_cast<double>(lx), dy = static_cast<double>(ly);
-    const uint32_t own = ch.own[j];
-    double e[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        e[i] = __builtin_fma(dx, ch.ea[i][j], __builtin_fma(dy, ch.eb[i][j], ch.e0[i][j]));
-        if (e[i] < 0.0 || (e[i] == 0.0 && !((own >> i) & 1u))) return false;
-    }
+__device__ __forceinline__ void frag_of(const ChunkLds<NT>& ch, int j, const double (&e)[3], Frag& f) {
     const float ra = ch.ra[j];
 #pragma unroll
     for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
@@ -116,13 +130,11 @@ __device__ __forceinline__ bool cover(const ChunkLds<NT>& ch, int j, int lx, int
     if (!(z > 0.0f)) z = 0.0f;
     if (z > 1.0f) z = 1.0f;
     f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | ch.tri[j];
-    return true;
 }
 
-// Perspective-correct barycentrics of vertices 1 and 2 (contract order).
-template <int NT>
-__device__ __forceinline__ void persp_b(const ChunkLds<NT>& ch, int j, const Frag& f, float& b1, float& b2) {
-    const float t0 = f.beta[0] * ch.iw[0][j], t1 = f.beta[1] * ch.iw[1][j], t2 = f.beta[2] * ch.iw[2][j];
+// Perspective-correct barycentrics of vertices 1 and 2 from t_i = beta_i / w_i
+// (contract order: r = 1 / ((t0 + t1) + t2), b_i = t_i r).
+__device__ __forceinline__ void persp_from_t(float t0, float t1, float t2, float& b1, float& b2) {
     const float r = 1.0f / ((t0 + t1) + t2);
     b1 = t1 * r;
     b2 = t2 * r;

@@ -21,9 +21,8 @@ namespace soup {
 template <int NW>
 struct FwdQueue {
     uint64_t key[NW][128];
-    float b1[NW][128];
-    float b2[NW][128];
-    uint16_t pix[NW][128];
+    float beta[3][NW][128];   // screen barycentrics
+    uint32_t info[NW][128];   // tile pixel | chunk slot << 10
 };
 
 template <int TS, class S>
@@ -73,8 +72,12 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
         float o[4] = {0.f, 0.f, 0.f, 0.f};
         if (act) {
             key = q.key[w][lane];
-            pl = q.pix[w][lane];
-            const float b1 = q.b1[w][lane], b2 = q.b2[w][lane];
+            const uint32_t info = q.info[w][lane];
+            pl = static_cast<int>(info & 1023u);
+            const int j = static_cast<int>(info >> 10);
+            float b1, b2;
+            persp_from_t(q.beta[0][w][lane] * ch.iw[0][j], q.beta[1][w][lane] * ch.iw[1][j],
+                         q.beta[2][w][lane] * ch.iw[2][j], b1, b2);
             const uint32_t tri = static_cast<uint32_t>(key);
             const Cell c = cell_of(b1, b2, G);
             float x[S::C];
@@ -131,29 +134,28 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
             for (int k = 0; k < PPT; ++k) {
                 if (!box_hits_block<TS>(box, w + k * NW)) continue;   // uniform: the wave's 8x8 block
                 const int pl = tid + k * NT;
+                double e[3];
+                const bool in = (zk < kc[k]) & edge_inside(ch, j, px_of<TS>(pl), py_of<TS>(pl), e);
+                if (__ballot(in) == 0) continue;   // uniform: no pixel of the wave is covered
                 Frag f;
-                bool cand = false;
-                float b1 = 0.f, b2 = 0.f;
-                if (zk < kc[k] && cover(ch, j, px_of<TS>(pl), py_of<TS>(pl), f) && f.key < kc[k]) {
-                    cand = true;
-                    persp_b(ch, j, f, b1, b2);
-                }
+                frag_of(ch, j, e, f);
+                const bool cand = in & (f.key < kc[k]);
                 const uint64_t m = __ballot(cand);
                 if (cand) {
                     const int pos = qn + __popcll(m & lanemask_lt());
                     q.key[w][pos] = f.key;
-                    q.b1[w][pos] = b1;
-                    q.b2[w][pos] = b2;
-                    q.pix[w][pos] = static_cast<uint16_t>(pl);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) q.beta[i][w][pos] = f.beta[i];
+                    q.info[w][pos] = static_cast<uint32_t>(pl) | (static_cast<uint32_t>(j) << 10);
                 }
                 qn += __popcll(m);
                 if (qn >= 64) {
                     run_batch(64);
                     if (lane < qn - 64) {
                         q.key[w][lane] = q.key[w][64 + lane];
-                        q.b1[w][lane] = q.b1[w][64 + lane];
-                        q.b2[w][lane] = q.b2[w][64 + lane];
-                        q.pix[w][lane] = q.pix[w][64 + lane];
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) q.beta[i][w][lane] = q.beta[i][w][64 + lane];
+                        q.info[w][lane] = q.info[w][64 + lane];
                     }
                     qn -= 64;
                     refresh();

@@ -7,9 +7,10 @@
 // depth-sorted triangle list with the forward's exact coverage test, in the
 // forward's order, stopping where the rest of the list lies behind every
 // active pixel's winner. Each wave compacts its candidates in LDS and appends
-// them, 64 at a time, to a flat fragment list (one counter bump per batch).
-// No MLP work happens here: the list is decoded by the decode kernel, whose
-// registers then hold only the MLP state, and whose waves are always full.
+// them, 64 at a time, to its own region of the fragment list with a private
+// cursor (no shared counter). No MLP work happens here: the list is decoded
+// by the decode kernel, whose registers then hold only the MLP state, and
+// whose waves are always full.
 #include "raster_common.hpp"
 
 namespace soup {
@@ -18,9 +19,8 @@ template <int NW>
 struct ReplayQueue {
     uint32_t pix[NW][128];
     uint32_t tri[NW][128];     // triangle | winner << 31
-    float b1[NW][128];
-    float b2[NW][128];
-    float beta[3][NW][128];
+    float t[3][NW][128];       // beta_i / w_i
+    float beta[3][NW][128];    // screen barycentrics
 };
 
 template <int TS>
@@ -35,6 +35,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const RasterArgs& r = a.r;
+    const uint64_t region_base = (static_cast<uint64_t>(blockIdx.x) * NW + w) * a.region;
+    uint32_t cursor = 0;   // wave-uniform
 
     for (;;) {
         if (tid == 0) s_tile = static_cast<int64_t>(atomicAdd(r.work, 1u));
@@ -86,20 +88,18 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
         any_act = __ballot(any_act) != 0;
         wmax = wave_max_u64(wmax);
 
-        // append the first n queue entries to the fragment list
+        // append the first n queue entries to this wave's region
         auto flush = [&](int n) __attribute__((always_inline)) {
             __threadfence_block();
-            uint64_t base = 0;
-            if (lane == 0) base = atomicAdd(a.frag_count, static_cast<unsigned long long>(n));
-            base = static_cast<uint64_t>(uniform_i64(static_cast<int64_t>(__shfl(base, 0, 64))));
-            const uint64_t slot = base + lane;
-            if (lane < n && slot < a.frag_cap) {
-                FragRec* f = a.frags + slot;
-                f->a = make_uint4(q.pix[w][lane], q.tri[w][lane], __float_as_uint(q.b1[w][lane]),
-                                  __float_as_uint(q.b2[w][lane]));
-                f->b = make_uint4(__float_as_uint(q.beta[0][w][lane]), __float_as_uint(q.beta[1][w][lane]),
-                                  __float_as_uint(q.beta[2][w][lane]), static_cast<uint32_t>(v));
+            const uint32_t at = cursor + static_cast<uint32_t>(lane);
+            if (lane < n && at < a.region) {
+                FragRec* f = a.frags + region_base + at;
+                f->a = make_uint4(q.pix[w][lane], q.tri[w][lane], __float_as_uint(q.t[0][w][lane]),
+                                  __float_as_uint(q.t[1][w][lane]));
+                f->b = make_uint4(__float_as_uint(q.t[2][w][lane]), __float_as_uint(q.beta[0][w][lane]),
+                                  __float_as_uint(q.beta[1][w][lane]), __float_as_uint(q.beta[2][w][lane]));
             }
+            cursor += static_cast<uint32_t>(n);
         };
 
         const int64_t beg = r.tile_start[tile], end = r.tile_start[tile + 1];
@@ -136,24 +136,25 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                     for (int k = 0; k < PPT; ++k) {
                         if (!box_hits_block<TS>(box, w + k * NW)) continue;   // uniform: the wave's 8x8 block
                         const int pl = tid + k * NT;
+                        double e[3];
+                        const bool in =
+                            act[k] & (zk <= kc[k]) & edge_inside(ch, j, px_of<TS>(pl), py_of<TS>(pl), e);
+                        if (__ballot(in) == 0) continue;   // uniform: no pixel of the wave is covered
                         Frag f;
-                        bool cand = false, win = false;
-                        float b1 = 0.f, b2 = 0.f;
-                        if (act[k] && zk <= kc[k] && cover(ch, j, px_of<TS>(pl), py_of<TS>(pl), f) && f.key <= kc[k]) {
-                            win = f.key == kc[k];
-                            cand = win || front[k];
-                            if (cand) persp_b(ch, j, f, b1, b2);
-                        }
+                        frag_of(ch, j, e, f);
+                        const bool le = in & (f.key <= kc[k]);
+                        const bool win = le & (f.key == kc[k]);
+                        const bool cand = win | (le & front[k]);
                         const uint64_t mk = __ballot(cand);
                         if (cand) {
                             const int pos = qn + __popcll(mk & lanemask_lt());
                             q.pix[w][pos] = pix[k];
                             q.tri[w][pos] = ch.tri[j] | (win ? 0x80000000u : 0u);
-                            q.b1[w][pos] = b1;
-                            q.b2[w][pos] = b2;
-                            q.beta[0][w][pos] = f.beta[0];
-                            q.beta[1][w][pos] = f.beta[1];
-                            q.beta[2][w][pos] = f.beta[2];
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                q.t[i][w][pos] = f.beta[i] * ch.iw[i][j];
+                                q.beta[i][w][pos] = f.beta[i];
+                            }
                         }
                         qn += __popcll(mk);
                         if (qn >= 64) {
@@ -162,10 +163,11 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                             if (lane < qn - 64) {
                                 q.pix[w][lane] = q.pix[w][64 + lane];
                                 q.tri[w][lane] = q.tri[w][64 + lane];
-                                q.b1[w][lane] = q.b1[w][64 + lane];
-                                q.b2[w][lane] = q.b2[w][64 + lane];
 #pragma unroll
-                                for (int i = 0; i < 3; ++i) q.beta[i][w][lane] = q.beta[i][w][64 + lane];
+                                for (int i = 0; i < 3; ++i) {
+                                    q.t[i][w][lane] = q.t[i][w][64 + lane];
+                                    q.beta[i][w][lane] = q.beta[i][w][64 + lane];
+                                }
                             }
                             qn -= 64;
                             __threadfence_block();
@@ -181,7 +183,71 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
         }
         __syncthreads();
     }
+    if (lane == 0) a.counts[blockIdx.x * NW + w] = cursor;
 }
+
+// One workgroup of 1024 threads, n <= kMaxRegions: each thread scans four
+// consecutive regions, then the per-thread sums are scanned in LDS.
+__global__ __launch_bounds__(1024) void region_scan_kernel(const uint32_t* __restrict__ counts, int n,
+                                                           uint32_t region, uint32_t* __restrict__ boff,
+                                                           unsigned long long* __restrict__ summary) {
+    constexpr int kPer = kMaxRegions / 1024;
+    __shared__ uint32_t s_sum[1024];
+    __shared__ unsigned long long s_tot[1024];
+    __shared__ uint32_t s_max[1024];
+    const int t = threadIdx.x;
+    uint32_t nb[kPer];
+    uint32_t local = 0, mx = 0;
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int r = t * kPer + i;
+        const uint32_t c = r < n ? counts[r] : 0u;
+        const uint32_t cl = c < region ? c : region;
+        nb[i] = (cl + 63u) / 64u;
+        local += nb[i];
+        tot += c;
+        mx = c > mx ? c : mx;
+    }
+    s_sum[t] = local;
+    s_tot[t] = tot;
+    s_max[t] = mx;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread batch counts
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = t >= d ? s_sum[t - d] : 0u;
+        __syncthreads();
+        s_sum[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = s_sum[t] - local;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int r = t * kPer + i;
+        if (r < n) boff[r] = run;
+        run += nb[i];
+    }
+    if (t == 1023) boff[n] = s_sum[1023];
+    for (int d = 512; d > 0; d >>= 1) {
+        if (t < d) {
+            s_tot[t] += s_tot[t + d];
+            s_max[t] = s_max[t + d] > s_max[t] ? s_max[t + d] : s_max[t];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        summary[0] = s_tot[0];
+        summary[1] = s_sum[1023];
+        summary[2] = s_max[0];
+    }
+}
+
+void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
+                        unsigned long long* summary, hipStream_t s) {
+    hipLaunchKernelGGL(region_scan_kernel, dim3(1), dim3(1024), 0, s, counts, n, region, boff, summary);
+}
+
+int replay_waves_per_block(int tile) { return TileCfg<8>::NW * (tile == 8) + TileCfg<16>::NW * (tile != 8); }
 
 void launch_replay(const ReplayArgs& a, int tile, hipStream_t s) {
     if (a.r.n_tiles <= 0) return;
