@@ -12,10 +12,15 @@ uniform in the unit ball, equilateral, side exp(N(-3, 0.5^2))), 8x8x16
 features, MLP 16->32->32->4, 64 views on a Fibonacci sphere of radius 3 with
 resolutions drawn from {256, 512, 800, 1024}^2, all views in one call.
 
+The tile size is autotuned (every candidate runs the step), the step is run
+eagerly with per-kernel HIP events recorded on its stream (the per-kernel
+times and the roofline of the dominant kernel come from these steps), then
+captured once into a HIP graph in static-capacity mode and replayed: the
+timed steps of the metric are graph replays (--no-graph times eager calls).
+
 Prints ONE JSON line. Besides the metric it reports the per-view path (a host
 loop over the 64 views on the same GPU), the roofline of the dominant kernel
-(from HIP events recorded around it on its own stream during the timed
-steps) and the CPU oracle timed on a bounded sample on the host's cores.
+and the CPU oracle timed on a bounded sample on the host's cores.
 """
 import argparse
 import json
@@ -42,7 +47,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched", choices=["batched", "single", "large", "tiny"])
-    ap.add_argument("--tile", type=int, default=0, help="tile side (0: autotuned/default)")
+    ap.add_argument("--tile", type=int, default=0, help="tile side (0: autotuned)")
+    ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-per-view", action="store_true")
     ap.add_argument("--cpu-pixels", type=float, default=1.5e6, help="oracle sample size in pixels")
@@ -72,25 +78,32 @@ def main():
     P = vs.pixels
     target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
     ctx = R.context()
-    tile = args.tile
-    if tile == 0:
-        try:
-            from paper_2603_27151_amd import autotune
-            tile = autotune.cached_tile(args.workload) or 16
-        except Exception:
-            tile = 16
-    ctx.set_tile(tile)
     opts = R.Opts(seed=wl.seed, step=wl.step)
+    P3 = (P, 3)
+    vis = torch.empty(P, dtype=torch.int64, device=dev)
+    color = torch.empty(P3, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    gc = torch.empty(P3, dtype=torch.float32, device=dev)
+    gl = torch.empty(P, dtype=torch.float32, device=dev)
     gv = torch.empty_like(ds.verts)
     gf = torch.empty_like(ds.feats)
     gm = torch.empty_like(ds.mlp)
-    log(f"workload {args.workload}: T={ds.T} views={vs.V} pixels={P} tile={tile}")
 
     def step():
-        vis, color, _ = R.rasterize_fwd(ds, vs, opts, ctx=ctx)
-        loss, gc, gl = R.loss_l2(color, target, ctx=ctx)
+        R.rasterize_fwd(ds, vs, opts, ctx=ctx, out=(vis, color, None))
+        R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
         R.rasterize_bwd(ds, vs, opts, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
-        return loss
+
+    # tile size: given, or measured (every candidate runs the step)
+    from paper_2603_27151_amd import autotune
+    tuning = None
+    if args.tile:
+        ctx.set_tile(args.tile)
+    else:
+        tuning = autotune.tune(step, ctx, autotune.signature(ds, vs))
+        log(f"autotune: {tuning}")
+    tile = ctx.tile
+    log(f"workload {args.workload}: T={ds.T} views={vs.V} pixels={P} tile={tile}")
 
     for _ in range(args.warmup):
         step()
@@ -99,9 +112,9 @@ def main():
 
     # work counts of the step (outside the timed region)
     ctx.set_counting(True)
-    vis, color, _ = R.rasterize_fwd(ds, vs, opts, ctx=ctx)
+    R.rasterize_fwd(ds, vs, opts, ctx=ctx, out=(vis, color, None))
     st_fwd = ctx.stats()
-    loss, gc, gl = R.loss_l2(color, target, ctx=ctx)
+    R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
     R.rasterize_bwd(ds, vs, opts, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
     st_bwd = ctx.stats()
     ctx.set_counting(False)
@@ -110,28 +123,58 @@ def main():
     E = st_bwd["decodes"]          # front set + winner of every pixel: the method's decodes
     log(f"counts: bins={st_fwd['bin_entries']} fwd decodes={st_fwd['decodes']} E={E} covered={covered}")
 
-    # timed region
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(k):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return max((t1 - t0) * 1e3 / k, ev0.elapsed_time(ev1) / k)
+
+    # eager steps with per-kernel HIP events (recorded on the launch stream)
     ctx.read_timings()
     ctx.set_timing(True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    eager_ms = timed(step, args.steps)
     ctx.set_timing(False)
     kern = ctx.read_timings()
-    wall_ms = (t1 - t0) * 1e3 / args.steps
-    ev_ms = ev0.elapsed_time(ev1) / args.steps
-    ms = max(wall_ms, ev_ms)
+    per_kernel = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
+    log(f"eager step {eager_ms:.3f} ms")
+    log("per-kernel avg ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_kernel.items() if v > 0))
+
+    # the step captured once into a HIP graph (static-capacity mode) and
+    # replayed: the timed steps
+    ms = eager_ms
+    graph = False
+    if not args.no_graph:
+        ref = (vis.clone(), gv.clone())
+        ctx.set_static(True)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()   # static mode outside capture first
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        ctx.check_overflow()
+        if not torch.equal(vis, ref[0]):
+            raise RuntimeError("graph replay changed the visibility buffer")
+        ms = timed(g.replay, args.steps)
+        torch.cuda.synchronize()
+        ctx.check_overflow()
+        ctx.set_static(False)
+        graph = True
+        log(f"graph step {ms:.3f} ms")
     mpix = P / (ms * 1e-3) / 1e6
     log(f"batched step {ms:.3f} ms -> {mpix:.1f} Mpixel/s")
-    per_kernel = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
-    log("per-kernel avg ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_kernel.items() if v > 0))
 
     # per-view path on the same GPU: a host loop of single-view calls,
     # gradients summed in place (accumulate)
@@ -224,7 +267,9 @@ def main():
         "config": {"workload": f"{args.workload}: {ds.T} triangles, {vs.V} views, {P} pixels, "
                                f"features {wl.scene.G}x{wl.scene.G}x{wl.scene.C}, MLP "
                                + "->".join(str(d) for d in ds.dims),
-                   "tile": tile, "triangles_per_s": round(ds.T * vs.V / (ms * 1e-3), 1),
+                   "tile": tile, "autotune_ms": None if tuning is None else tuning["ms"],
+                   "hip_graph": graph, "eager_ms_per_step": round(eager_ms, 4),
+                   "triangles_per_s": round(ds.T * vs.V / (ms * 1e-3), 1),
                    "decodes_E": E, "covered_pixels": covered, "bin_entries": st_fwd["bin_entries"]},
         "per_view": per_view,
         "kernels_ms": {k: round(v, 4) for k, v in per_kernel.items() if v > 0},

@@ -131,6 +131,24 @@ enum {
 soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
 soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);
 
+/* Static-capacity mode, for callers that capture a sequence of calls into a
+ * HIP graph (hipStreamBeginCapture / torch.cuda.graph) and replay it.
+ * When on, soup_rasterize_fwd / soup_rasterize_bwd / soup_render neither
+ * synchronise nor allocate: every workspace keeps the size an earlier call
+ * outside static mode gave it (run the captured sequence once eagerly first,
+ * with the same scene, views and tile), the views and scenes must equal
+ * those of the previous call (their device copies are reused), and the
+ * lists whose length is only known on the device (tile lists, backward
+ * fragments) are bounded by the capacity in place. A call that would exceed
+ * it produces no fragments for the overflowing part and sets a sticky flag
+ * instead of failing. Counting and timing must be off.
+ * soup_ctx_check synchronises the device, returns SOUP_ERR_CAPACITY (and
+ * clears the flag) if any static-mode call since the last check overflowed,
+ * else SOUP_OK; the caller then reruns outside static mode, which grows the
+ * workspaces, and captures again. */
+soup_status soup_ctx_set_static(soup_ctx* ctx, int32_t on);
+soup_status soup_ctx_check(soup_ctx* ctx);
+
 /* Enable (1) or disable (0, default) counting of decodes in soup_stats. */
 soup_status soup_ctx_set_counting(soup_ctx* ctx, int32_t on);
 soup_status soup_last_stats(const soup_ctx* ctx, soup_stats* out);

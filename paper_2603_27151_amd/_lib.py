@@ -48,7 +48,8 @@ class soup_stats(C.Structure):
 EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_set_tile",
            "soup_ctx_get_tile", "soup_ctx_set_counting", "soup_last_stats", "soup_rasterize_fwd",
            "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
-           "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings"]
+           "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings", "soup_ctx_set_static",
+           "soup_ctx_check"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce"]
 
@@ -82,12 +83,14 @@ def lib() -> C.CDLL:
     L.soup_loss_l2.argtypes = [P, P, P, C.c_int64, P, P, P, P]
     L.soup_selftest_sigmoid.argtypes = [P, P, P, C.c_int64, P]
     L.soup_selftest_uniform.argtypes = [P, C.c_uint64, P, P, C.c_uint32, C.c_uint32, P, C.c_int64, P]
+    L.soup_ctx_set_static.argtypes = [P, C.c_int32]
+    L.soup_ctx_check.argtypes = [P]
     L.soup_ctx_set_timing.argtypes = [P, C.c_int32]
     L.soup_read_timings.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
                  "soup_selftest_sigmoid", "soup_selftest_uniform", "soup_ctx_set_timing",
-                 "soup_read_timings"]:
+                 "soup_read_timings", "soup_ctx_set_static", "soup_ctx_check"]:
         getattr(L, name).restype = C.c_int
     L.soup_ctx_get_tile.restype = C.c_int32
     _lib = L
@@ -188,6 +191,14 @@ class Ctx:
     @property
     def tile(self) -> int:
         return int(lib().soup_ctx_get_tile(self.p))
+
+    def set_static(self, on: bool):
+        """Static-capacity mode (no synchronisation or allocation; HIP-graph capturable)."""
+        self.check(lib().soup_ctx_set_static(self.p, 1 if on else 0))
+
+    def check_overflow(self):
+        """Raises SoupError(SOUP_ERR_CAPACITY) if a static-mode call overflowed since the last check."""
+        self.check(lib().soup_ctx_check(self.p))
 
     def set_counting(self, on: bool):
         self.check(lib().soup_ctx_set_counting(self.p, 1 if on else 0))

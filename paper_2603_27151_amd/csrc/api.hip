@@ -26,11 +26,14 @@ struct soup_ctx {
     int num_cus = 256;
     int tile = 16;
     bool counting = false;
+    bool fixed = false;              // static-capacity mode: no synchronisation, no allocation
+    bool flags_ready = false;        // sticky overflow flags cleared after allocation
+    std::vector<char> desc_cache;    // descriptors of the last upload (static mode reuses them)
     std::string err;
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
     DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum, chunk_off, mlp_mid, frags;
-    DevBuf region_counts, region_boff;
+    DevBuf region_counts, region_boff, chunk_tri, flags;
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
@@ -67,6 +70,9 @@ soup_status fail(soup_ctx* c, soup_status s, const char* fmt, ...) {
 soup_status ensure(soup_ctx* c, DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (b.bytes >= bytes) return SOUP_OK;
+    if (c->fixed)
+        return fail(c, SOUP_ERR_CAPACITY, "static mode: a workspace of %zu bytes is needed (have %zu); run the "
+                    "call once outside static mode to size it", bytes, b.bytes);
     if (b.p) {
         hipError_t e = hipFree(b.p);
         b.p = nullptr;
@@ -123,7 +129,7 @@ struct Timed {
     hipStream_t s;
     hipEvent_t a = nullptr;
     Timed(soup_ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
-        if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, s);
+        if (c->timing && !c->fixed && (a = take_event(c))) (void)hipEventRecord(a, s);
     }
     ~Timed() {
         if (!a) return;
@@ -264,15 +270,30 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
         (st = ensure(c, c->tile_fill, static_cast<size_t>(p.n_tiles) * 4)) ||
         (st = ensure(c, c->tile_start, static_cast<size_t>(p.n_tiles + 1) * 8)) ||
         (st = ensure(c, c->bsum, static_cast<size_t>((p.n_tiles + 1023) / 1024 + 1) * 8)) ||
-        (st = ensure(c, c->counters, 64)) || (st = ensure_host(c, vbytes + sbytes + 64)))
+        (st = ensure(c, c->counters, 64)) || (st = ensure(c, c->flags, 256)) ||
+        (st = ensure_host(c, vbytes + sbytes + 64)))
         return st;
-    // the previous call has drained this stream's use of the staging buffer
-    HIP_TRY(c, hipStreamSynchronize(s));
+    if (!c->flags_ready) {   // first allocation (never in static mode): clear the sticky flags
+        launch_fill_i32(static_cast<int32_t*>(c->flags.p), 64, 0, s);
+        c->flags_ready = true;
+    }
+    const bool same = c->desc_cache.size() == vbytes + sbytes &&
+                      memcmp(c->desc_cache.data(), p.views.data(), vbytes) == 0 &&
+                      memcmp(c->desc_cache.data() + vbytes, p.scenes.data(), sbytes) == 0;
+    if (c->fixed) {
+        // a captured call must not depend on host memory at replay time
+        if (!same) return fail(c, SOUP_ERR_INVALID, "static mode needs the views and scenes of the previous call");
+    } else {
+        // the previous call has drained this stream's use of the staging buffer
+        HIP_TRY(c, hipStreamSynchronize(s));
+        char* hs = static_cast<char*>(c->host_stage);
+        memcpy(hs, p.views.data(), vbytes);
+        memcpy(hs + vbytes, p.scenes.data(), sbytes);
+        HIP_TRY(c, hipMemcpyAsync(c->views.p, hs, vbytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->scenes.p, hs + vbytes, sbytes, hipMemcpyHostToDevice, s));
+        c->desc_cache.assign(hs, hs + vbytes + sbytes);
+    }
     char* hs = static_cast<char*>(c->host_stage);
-    memcpy(hs, p.views.data(), vbytes);
-    memcpy(hs + vbytes, p.scenes.data(), sbytes);
-    HIP_TRY(c, hipMemcpyAsync(c->views.p, hs, vbytes, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(c->scenes.p, hs + vbytes, sbytes, hipMemcpyHostToDevice, s));
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     {
         Timed t(c, SOUP_T_FILL, s);
@@ -290,12 +311,20 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
         launch_scan(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, static_cast<int64_t*>(c->bsum.p),
                     static_cast<int64_t*>(c->tile_start.p), s);
     }
-    int64_t* htotal = reinterpret_cast<int64_t*>(hs + vbytes + sbytes);
-    HIP_TRY(c, hipMemcpyAsync(htotal, static_cast<int64_t*>(c->tile_start.p) + p.n_tiles, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipGetLastError());
-    HIP_TRY(c, hipStreamSynchronize(s));
-    const int64_t total = *htotal;
-    if ((st = ensure(c, c->entries, static_cast<size_t>(total) * 8))) return st;
+    int64_t total = -1;
+    if (c->fixed) {
+        // the capacity in place bounds the lists; an overflow empties them and is flagged
+        launch_clip(static_cast<int64_t*>(c->tile_start.p), p.n_tiles, static_cast<int64_t>(c->entries.bytes / 8),
+                    reinterpret_cast<unsigned int*>(cnt + 7), static_cast<unsigned int*>(c->flags.p), s);
+    } else {
+        int64_t* htotal = reinterpret_cast<int64_t*>(hs + vbytes + sbytes);
+        HIP_TRY(c, hipMemcpyAsync(htotal, static_cast<int64_t*>(c->tile_start.p) + p.n_tiles, 8,
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipStreamSynchronize(s));
+        total = *htotal;
+        if ((st = ensure(c, c->entries, static_cast<size_t>(total) * 8))) return st;
+    }
     {
         Timed t(c, SOUP_T_SCATTER, s);
         launch_fill_i32(static_cast<int32_t*>(c->tile_fill.p), p.n_tiles, 0, s);
@@ -332,7 +361,7 @@ RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
 }
 
 soup_status finish_stats(soup_ctx* c, hipStream_t s) {
-    if (!c->counting) {
+    if (!c->counting || c->fixed) {
         c->stats.visible_tris = -1;
         c->stats.decodes = -1;
         return SOUP_OK;
@@ -400,7 +429,7 @@ void soup_ctx_destroy(soup_ctx* c) {
     DevBuf* bufs[] = {&c->views,    &c->scenes,  &c->recs,      &c->tile_count, &c->tile_fill, &c->tile_start,
                       &c->bsum,     &c->entries, &c->vacc,      &c->partial,    &c->counters,  &c->records,
                       &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum,
-                      &c->chunk_off, &c->mlp_mid,  &c->frags,    &c->region_counts, &c->region_boff};
+                      &c->chunk_off, &c->mlp_mid,  &c->frags,    &c->region_counts, &c->region_boff, &c->chunk_tri, &c->flags};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -447,6 +476,32 @@ soup_status soup_read_timings(soup_ctx* c, double* ms, int64_t* count) {
     return SOUP_OK;
 }
 
+soup_status soup_ctx_set_static(soup_ctx* c, int32_t on) {
+    if (!c) return SOUP_ERR_INVALID;
+    if (on && (c->counting || c->timing))
+        return fail(c, SOUP_ERR_INVALID, "static mode excludes counting and timing (both synchronise)");
+    c->fixed = on != 0;
+    return SOUP_OK;
+}
+
+soup_status soup_ctx_check(soup_ctx* c) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (!c->flags.p) return SOUP_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    unsigned int h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpy(h, c->flags.p, sizeof(h), hipMemcpyDeviceToHost));
+    h[0] &= kOverflowBins | kOverflowFragments;
+    if (!h[0]) return SOUP_OK;
+    const unsigned int zero[2] = {0, 0};
+    HIP_TRY(c, hipMemcpy(c->flags.p, zero, sizeof(zero), hipMemcpyHostToDevice));
+    return fail(c, SOUP_ERR_CAPACITY, "a static-mode call overflowed its %s%s%s; rerun outside static mode to grow "
+                "the workspaces", (h[0] & kOverflowBins) ? "tile lists" : "",
+                (h[0] & kOverflowBins) && (h[0] & kOverflowFragments) ? " and " : "",
+                (h[0] & kOverflowFragments) ? "fragment list" : "");
+}
+
 soup_status soup_ctx_set_counting(soup_ctx* c, int32_t on) {
     if (!c) return SOUP_ERR_INVALID;
     c->counting = on != 0;
@@ -484,6 +539,30 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     if ((st = ensure(c, c->region_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
         (st = ensure(c, c->region_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
         return st;
+    if (c->fixed) {
+        // the fragment list in place bounds the regions; an overflow is flagged
+        if (c->frag_regions != nr || c->frag_region == 0)
+            return fail(c, SOUP_ERR_CAPACITY, "static mode: no fragment list sized for this tile; run the call "
+                        "once outside static mode");
+        ReplayArgs ra{};
+        ra.r = a;
+        ra.vis = vis;
+        ra.grad_color = grad_color;
+        ra.grad_logp = grad_logp;
+        ra.all_front = all_front ? 1 : 0;
+        ra.frags = static_cast<FragRec*>(c->frags.p);
+        ra.region = static_cast<uint32_t>(c->frag_region);
+        ra.counts = static_cast<uint32_t*>(c->region_counts.p);
+        ra.n_blocks = nb;
+        launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+        launch_replay(ra, c->tile, s);
+        launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4,
+                           static_cast<unsigned int*>(c->flags.p), s);
+        HIP_TRY(c, hipGetLastError());
+        *n_frag = -1;
+        *n_batch = static_cast<int64_t>(nr) * static_cast<int64_t>((c->frag_region + 63) / 64);   // upper bound
+        return SOUP_OK;
+    }
     uint64_t summary[3] = {0, 0, 0};
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment region too large");
@@ -505,7 +584,8 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         {
             Timed t(c, SOUP_T_REPLAY, s);
             launch_replay(ra, c->tile, s);
-            launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4, s);
+            launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4,
+                               static_cast<unsigned int*>(c->flags.p), s);
         }
         HIP_TRY(c, hipGetLastError());
         uint64_t* h = reinterpret_cast<uint64_t*>(c->host_stage);
@@ -613,12 +693,16 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         (st = ensure(c, c->tri_bsum, static_cast<size_t>((T + 1023) / 1024 + 1) * 8)))
         return st;
     RasterArgs a = raster_args(c, p, o);
+    unsigned long long* cnt_dev = static_cast<unsigned long long*>(c->counters.p);
     const float* gl = o.mode == 0 ? grad_logp : nullptr;
     int64_t n_frag = 0, n_batch = 0;
     if ((st = replay(c, p, a, vis, grad_color, gl, false, s, &n_frag, &n_batch))) return st;
-    const int64_t n_rec = n_batch * 64;   // one record slot per decode lane
-    if ((st = ensure(c, c->records, static_cast<size_t>(n_rec) * RS * 4)) ||
-        (st = ensure(c, c->rec_tri, static_cast<size_t>(n_rec) * 4)))
+    // one record slot per decode lane; the buffers are sized for the largest
+    // batch count the regions allow, so that static-mode calls fit as well
+    const int64_t n_rec = n_batch * 64;
+    const int64_t rec_cap = static_cast<int64_t>(c->frag_regions) * static_cast<int64_t>((c->frag_region + 63) / 64) * 64;
+    if ((st = ensure(c, c->records, static_cast<size_t>(rec_cap) * RS * 4)) ||
+        (st = ensure(c, c->rec_tri, static_cast<size_t>(rec_cap) * 4)))
         return st;
     {
         Timed t(c, SOUP_T_FILL, s);
@@ -637,19 +721,22 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         launch_decode_bwd(d, p.kind, false, s);
     }
     HIP_TRY(c, hipGetLastError());
-    if ((st = ensure(c, c->rec_idx, static_cast<size_t>(n_rec) * 4))) return st;
+    if ((st = ensure(c, c->rec_idx, static_cast<size_t>(rec_cap) * 4)) ||
+        (st = ensure(c, c->chunk_tri, static_cast<size_t>(reduce_chunk_bound(scene->C, T, rec_cap)) * 4)))
+        return st;
     {
         Timed t(c, SOUP_T_GRAD, s);
         launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
                     static_cast<int64_t*>(c->tri_off.p), s);
         launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), T, 0, s);
-        launch_bucket(static_cast<uint32_t*>(c->rec_tri.p), n_rec, static_cast<int64_t*>(c->tri_off.p),
+        launch_bucket(static_cast<uint32_t*>(c->rec_tri.p), cnt_dev + 5, n_rec, static_cast<int64_t*>(c->tri_off.p),
                       static_cast<int32_t*>(c->tri_fill.p), static_cast<uint32_t*>(c->rec_idx.p), s);
         // tri_fill and tri_bsum are free again once the records are bucketed
         launch_reduce(static_cast<float*>(c->records.p), scene->C, scene->G, T, n_rec,
                       static_cast<int64_t*>(c->tri_off.p), static_cast<int32_t*>(c->tri_fill.p),
                       static_cast<int64_t*>(c->tri_bsum.p), static_cast<int64_t*>(c->chunk_off.p),
-                      static_cast<uint32_t*>(c->rec_idx.p), grad_feats, grad_verts, o.accumulate != 0, s);
+                      static_cast<int32_t*>(c->chunk_tri.p), static_cast<uint32_t*>(c->rec_idx.p), grad_feats,
+                      grad_verts, o.accumulate != 0, s);
     }
     {
         Timed t(c, SOUP_T_EDGE, s);

@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ViewDesc* __restrict
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
             const int64_t g = vd.tile_base + static_cast<int64_t>(ty) * vd.tiles_x + tx;
-            const int32_t k = atomicAdd(&tile_fill[g], 1);
-            entries[tile_start[g] + k] = e;
+            const int64_t at = tile_start[g] + atomicAdd(&tile_fill[g], 1);
+            if (at < tile_start[g + 1]) entries[at] = e;   // always true unless the lists were clipped
         }
 }
 
@@ -282,6 +282,29 @@ void launch_scatter(const ViewDesc* views, int V, int maxT, int tile, const TriR
     if (maxT <= 0) return;
     dim3 grid((maxT + 255) / 256, V);
     hipLaunchKernelGGL(scatter_kernel, grid, dim3(256), 0, s, views, tile, recs, tile_start, tile_fill, entries);
+}
+
+// Static-capacity mode: when the lists need more than `cap` entries, flag the
+// overflow (sticky bit 1) and empty every tile list, so that no kernel of
+// the call touches entries beyond the capacity.
+__global__ void clip_check_kernel(const int64_t* __restrict__ tile_start, int64_t n_tiles, int64_t cap,
+                                  unsigned int* __restrict__ local, unsigned int* __restrict__ sticky) {
+    const bool over = tile_start[n_tiles] > cap;
+    *local = over ? 1u : 0u;
+    if (over) atomicOr(sticky, 1u);
+}
+
+__global__ void clip_apply_kernel(int64_t* __restrict__ tile_start, int64_t n_tiles,
+                                  const unsigned int* __restrict__ local) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i <= n_tiles && *local) tile_start[i] = 0;
+}
+
+void launch_clip(int64_t* tile_start, int64_t n_tiles, int64_t cap, unsigned int* local, unsigned int* sticky,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(clip_check_kernel, dim3(1), dim3(1), 0, s, tile_start, n_tiles, cap, local, sticky);
+    hipLaunchKernelGGL(clip_apply_kernel, dim3(static_cast<unsigned>((n_tiles + 256) / 256)), dim3(256), 0, s,
+                       tile_start, n_tiles, local);
 }
 
 void launch_sort(const int64_t* tile_start, int64_t n_tiles, uint64_t* entries, hipStream_t s) {

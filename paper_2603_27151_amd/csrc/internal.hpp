@@ -13,6 +13,12 @@ void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipS
 void launch_scatter(const ViewDesc* views, int V, int maxT, int tile, const TriRec* recs,
                     const int64_t* tile_start, int32_t* tile_fill, uint64_t* entries, hipStream_t s);
 void launch_sort(const int64_t* tile_start, int64_t n_tiles, uint64_t* entries, hipStream_t s);
+void launch_clip(int64_t* tile_start, int64_t n_tiles, int64_t cap, unsigned int* local, unsigned int* sticky,
+                 hipStream_t s);
+
+// Sticky overflow bits of the static-capacity mode.
+constexpr unsigned kOverflowBins = 1u;
+constexpr unsigned kOverflowFragments = 2u;
 
 // MLP shapes compiled in: (C, H, NH)
 enum class MlpKind { k8_16_1, k16_32_2, k32_64_2, kNone };
@@ -69,7 +75,7 @@ int replay_waves_per_block(int tile);
 // region) / 64), boff[n] = total batches; summary = (fragments, batches,
 // largest region count).
 void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
-                        unsigned long long* summary, hipStream_t s);
+                        unsigned long long* summary, unsigned int* sticky, hipStream_t s);
 
 struct DecodeArgs {
     const ViewDesc* views;
@@ -116,13 +122,16 @@ template <int C>
 constexpr int kRecStride = ((4 + C + 9) + 3) / 4 * 4;
 inline int rec_stride(int C) { return ((4 + C + 9) + 3) / 4 * 4; }
 
-void launch_bucket(const uint32_t* rec_tri, int64_t n, const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx,
-                   hipStream_t s);
+// Records [0, 64 * (*n_batch)) are placed; the grid covers `bound` records.
+void launch_bucket(const uint32_t* rec_tri, const unsigned long long* n_batch, int64_t bound,
+                   const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx, hipStream_t s);
 // Per-triangle reduction of the records listed by idx (grouped by triangle,
 // tri_off[T + 1]), in chunks of a bounded number of records. chunk_n [T],
-// chunk_bsum (scan block sums) and chunk_off [T + 1] are scratch.
+// chunk_bsum (scan block sums), chunk_off [T + 1] and chunk_tri
+// [reduce_chunk_bound] are scratch.
+int64_t reduce_chunk_bound(int C, int T, int64_t n_rec);
 void launch_reduce(const float* records, int C, int G, int T, int64_t n_rec, const int64_t* tri_off,
-                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, const uint32_t* idx,
-                   float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s);
+                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, int32_t* chunk_tri,
+                   const uint32_t* idx, float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s);
 
 }  // namespace soup

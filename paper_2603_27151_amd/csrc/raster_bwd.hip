@@ -26,9 +26,11 @@ void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp, hipStream_t s)
 
 // Counting-sort placement of record indices into per-triangle lists; runs of
 // equal triangles in a wave take one atomic.
-__global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict__ rec_tri, int64_t n,
+__global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict__ rec_tri,
+                                                     const unsigned long long* __restrict__ n_batch,
                                                      const int64_t* __restrict__ tri_off,
                                                      int32_t* __restrict__ tri_fill, uint32_t* __restrict__ idx) {
+    const int64_t n = static_cast<int64_t>(*n_batch) * 64;
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint32_t tri = i < n ? rec_tri[i] : 0xFFFFFFFFu;
@@ -82,22 +84,25 @@ __global__ __launch_bounds__(256) void reduce_prep_kernel(const int64_t* __restr
 // LDS once per run. A triangle of one chunk stores its sums; the chunks of a
 // larger triangle add theirs with global atomics, so that no workgroup walks
 // more than a chunk however many pixels one triangle covers.
+// chunk_tri[c] = the triangle that owns chunk c.
+__global__ __launch_bounds__(256) void chunk_map_kernel(const int64_t* __restrict__ chunk_off, int T,
+                                                        int32_t* __restrict__ chunk_tri) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    for (int64_t c = chunk_off[t]; c < chunk_off[t + 1]; ++c) chunk_tri[c] = t;
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ records, int G, int T,
                                                      const int64_t* __restrict__ tri_off,
                                                      const int64_t* __restrict__ chunk_off,
+                                                     const int32_t* __restrict__ chunk_tri,
                                                      const uint32_t* __restrict__ idx, float* __restrict__ grad_feats,
                                                      float* __restrict__ grad_verts, bool accumulate) {
     extern __shared__ float s_acc[];      // [G*G*C + 16]
     const int64_t b = blockIdx.x;
     if (b >= chunk_off[T]) return;        // the grid is sized by an upper bound of the chunk count
-    int lo = 0, hi = T - 1;               // triangle t with chunk_off[t] <= b < chunk_off[t + 1]
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (chunk_off[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const int t = lo;
+    const int t = chunk_tri[b];
     const int64_t ci = b - chunk_off[t];
     const bool whole = chunk_off[t + 1] - chunk_off[t] == 1;
     const int n_feat = G * G * C;
@@ -168,48 +173,50 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ r
     }
 }
 
-void launch_bucket(const uint32_t* rec_tri, int64_t n, const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx,
-                   hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(bucket_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, rec_tri, n,
-                       tri_off, tri_fill, idx);
+void launch_bucket(const uint32_t* rec_tri, const unsigned long long* n_batch, int64_t bound,
+                   const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx, hipStream_t s) {
+    if (bound <= 0) return;
+    hipLaunchKernelGGL(bucket_kernel, dim3(static_cast<unsigned>((bound + 255) / 256)), dim3(256), 0, s, rec_tri,
+                       n_batch, tri_off, tri_fill, idx);
 }
 
 template <int C>
 static void launch_reduce_c(const float* records, int G, int T, int64_t n_rec, const int64_t* tri_off,
-                            int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, const uint32_t* idx,
-                            float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
+                            int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, int32_t* chunk_tri,
+                            const uint32_t* idx, float* grad_feats, float* grad_verts, bool accumulate,
+                            hipStream_t s) {
     const int n_feat = G * G * C;
     hipLaunchKernelGGL(reduce_prep_kernel<C>, dim3((T + 255) / 256), dim3(256), 0, s, tri_off, T, n_feat, chunk_n,
                        grad_feats, grad_verts, accumulate);
     launch_scan(chunk_n, T, chunk_bsum, chunk_off, s);
-    const int64_t blocks = T + n_rec / kChunkRecs<C> + 1;   // >= sum over t of max(1, ceil(n_t / K))
+    hipLaunchKernelGGL(chunk_map_kernel, dim3((T + 255) / 256), dim3(256), 0, s, chunk_off, T, chunk_tri);
+    const int64_t blocks = reduce_chunk_bound(C, T, n_rec);
     const size_t lds = (static_cast<size_t>(n_feat) + 16) * sizeof(float);
     hipLaunchKernelGGL(reduce_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, s, records, G, T,
-                       tri_off, chunk_off, idx, grad_feats, grad_verts, accumulate);
+                       tri_off, chunk_off, chunk_tri, idx, grad_feats, grad_verts, accumulate);
 }
 
 int64_t reduce_chunk_bound(int C, int T, int64_t n_rec) {
     const int64_t K = 64 * (256 / C);
-    return T + n_rec / K + 1;
+    return T + n_rec / K + 1;   // >= sum over t of max(1, ceil(n_t / K))
 }
 
 void launch_reduce(const float* records, int C, int G, int T, int64_t n_rec, const int64_t* tri_off,
-                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, const uint32_t* idx,
-                   float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
+                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, int32_t* chunk_tri,
+                   const uint32_t* idx, float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
     if (T <= 0) return;
     switch (C) {
         case 8:
-            launch_reduce_c<8>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, idx, grad_feats,
-                               grad_verts, accumulate, s);
+            launch_reduce_c<8>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, chunk_tri, idx,
+                               grad_feats, grad_verts, accumulate, s);
             break;
         case 16:
-            launch_reduce_c<16>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, idx, grad_feats,
-                                grad_verts, accumulate, s);
+            launch_reduce_c<16>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, chunk_tri, idx,
+                                grad_feats, grad_verts, accumulate, s);
             break;
         case 32:
-            launch_reduce_c<32>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, idx, grad_feats,
-                                grad_verts, accumulate, s);
+            launch_reduce_c<32>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, chunk_tri, idx,
+                                grad_feats, grad_verts, accumulate, s);
             break;
         default: break;
     }

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
     const int ty0 = static_cast<int>(tl / vd.tiles_x) * TS;
     const SceneDesc sc = a.scenes[vd.scene];
     gfloat* __restrict__ feats = as_global(uniform_ptr(sc.feats));
-    cfloat* __restrict__ mlp = as_const(uniform_ptr(sc.mlp));
+    const float* mlp_p = uniform_ptr(sc.mlp);
     const TriRec* __restrict__ recs = uniform_ptr(a.recs + vd.rec_base);
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int G = a.G;
@@ -82,7 +82,9 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
             const Cell c = cell_of(b1, b2, G);
             float x[S::C];
             fetch_feature<S::C>(feats, tri, G, c, x);
-            mlp_logits<S>(mlp, x, o);
+            // an opaque copy of the weight pointer per batch: the compiler may
+            // not hoist the weights' scalar loads out of the traversal loops
+            mlp_logits<S>(as_const(opaque_ptr(mlp_p)), x, o);
             if (a.o.mode == 0) {
                 const float alpha = sigmoid_c(o[3]);
                 const uint32_t pidx = static_cast<uint32_t>((ty0 + py_of<TS>(pl)) * W + tx0 + px_of<TS>(pl));

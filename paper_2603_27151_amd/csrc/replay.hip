@@ -190,7 +190,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
 // consecutive regions, then the per-thread sums are scanned in LDS.
 __global__ __launch_bounds__(1024) void region_scan_kernel(const uint32_t* __restrict__ counts, int n,
                                                            uint32_t region, uint32_t* __restrict__ boff,
-                                                           unsigned long long* __restrict__ summary) {
+                                                           unsigned long long* __restrict__ summary,
+                                                           unsigned int* __restrict__ sticky) {
     constexpr int kPer = kMaxRegions / 1024;
     __shared__ uint32_t s_sum[1024];
     __shared__ unsigned long long s_tot[1024];
@@ -239,12 +240,13 @@ __global__ __launch_bounds__(1024) void region_scan_kernel(const uint32_t* __res
         summary[0] = s_tot[0];
         summary[1] = s_sum[1023];
         summary[2] = s_max[0];
+        if (s_max[0] > region) atomicOr(sticky, kOverflowFragments);
     }
 }
 
 void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
-                        unsigned long long* summary, hipStream_t s) {
-    hipLaunchKernelGGL(region_scan_kernel, dim3(1), dim3(1024), 0, s, counts, n, region, boff, summary);
+                        unsigned long long* summary, unsigned int* sticky, hipStream_t s) {
+    hipLaunchKernelGGL(region_scan_kernel, dim3(1), dim3(1024), 0, s, counts, n, region, boff, summary, sticky);
 }
 
 int replay_waves_per_block(int tile) { return TileCfg<8>::NW * (tile == 8) + TileCfg<16>::NW * (tile != 8); }

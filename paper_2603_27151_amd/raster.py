@@ -98,14 +98,18 @@ def context(device: Optional[int] = None) -> _lib.Ctx:
 
 
 def rasterize_fwd(scene: DeviceScene, views: Views, opts: Opts, want_logp: bool = False,
-                  ctx: Optional[_lib.Ctx] = None, stream=None):
-    """vis [P] int64 (uint64 bits), color [P,3], logp [P] or None."""
+                  ctx: Optional[_lib.Ctx] = None, stream=None, out=None):
+    """vis [P] int64 (uint64 bits), color [P,3], logp [P] or None.
+    out: optional preallocated (vis, color, logp-or-None)."""
     ctx = ctx or context()
     dev = scene.verts.device
     P = views.pixels
-    vis = torch.empty(P, dtype=torch.int64, device=dev)
-    color = torch.empty(P, 3, dtype=torch.float32, device=dev)
-    logp = torch.empty(P, dtype=torch.float32, device=dev) if want_logp else None
+    if out is not None:
+        vis, color, logp = out
+    else:
+        vis = torch.empty(P, dtype=torch.int64, device=dev)
+        color = torch.empty(P, 3, dtype=torch.float32, device=dev)
+        logp = torch.empty(P, dtype=torch.float32, device=dev) if want_logp else None
     h = _lib._Holder()
     _lib.soup_rasterize_fwd(ctx, scene.c_struct(h), views.c_struct(h), opts.c_struct(), vis, color, logp, stream)
     return vis, color, logp
@@ -138,11 +142,16 @@ def render(scenes: Sequence[DeviceScene], views: Views, opts: Opts, colors=None,
     return colors
 
 
-def loss_l2(color, target, ctx=None, stream=None):
+def loss_l2(color, target, ctx=None, stream=None, out=None):
+    """L = mean over P*3 of (color - target)^2: (loss [1], dL/dcolor [P,3],
+    per-pixel score weights [P]). out: optional preallocated (loss, gc, gl)."""
     ctx = ctx or context()
-    gc = torch.empty_like(color)
-    gl = torch.empty(color.shape[0], dtype=torch.float32, device=color.device)
-    loss = torch.empty(1, dtype=torch.float32, device=color.device)
+    if out is not None:
+        loss, gc, gl = out
+    else:
+        gc = torch.empty_like(color)
+        gl = torch.empty(color.shape[0], dtype=torch.float32, device=color.device)
+        loss = torch.empty(1, dtype=torch.float32, device=color.device)
     _lib.soup_loss_l2(ctx, color, target, gc, gl, loss, stream)
     return loss, gc, gl
 
