@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--skip-per-view", action="store_true")
     ap.add_argument("--cpu-pixels", type=float, default=1.5e6, help="oracle sample size in pixels")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="open-loop run at 200 req/s")
+    ap.add_argument("--sweep-seconds", type=float, default=2.0, help="duration of each rate of the sweep")
+    ap.add_argument("--serve-budget", type=float, default=0.25, help="admission budget: fraction of free HBM")
     return ap.parse_args()
 
 
@@ -226,6 +230,31 @@ def main():
     step_roofline = {"flops": step_flops, "achieved_tflops": round(step_flops / (ms * 1e-3) / 1e12, 3),
                      "frac": round(step_flops / (ms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4)}
 
+    # serving: forward-only renders of four resident soups, Poisson arrivals,
+    # continuous batching over two streams
+    serving = None
+    if not args.skip_serve:
+        from paper_2603_27151_amd import serve as SV
+        soups = [R.DeviceScene.from_host(sc) for sc in W.serving_soups()]
+        srv = SV.Server(soups, tile=16, n_streams=2, max_batch=16, budget_fraction=args.serve_budget)
+        SV.run(srv, W.serving_requests(200.0, 1.0, seed=99))   # warm-up: workspaces, allocator
+        log(f"serving: {args.serve_seconds:.0f} s at 200 req/s")
+        main_st = SV.run(srv, W.serving_requests(200.0, args.serve_seconds))
+        log(f"serving 200/s: {main_st}")
+        sweep = []
+        for rate in (100, 200, 400, 800, 1600, 3200, 6400, 12800):
+            st = SV.run(srv, W.serving_requests(float(rate), args.sweep_seconds, seed=rate))
+            sweep.append({"rate_hz": rate, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                          "throughput_rps": st["throughput_rps"], "mean_batch": st["mean_batch"]})
+            log(f"serving sweep {rate}/s: {sweep[-1]}")
+            if st["throughput_rps"] is None or st["throughput_rps"] < 0.9 * rate:
+                break   # saturated
+        serving = {"workload": "4 soups (20k/40k/70k/100k triangles), 8x8x16 features, MLP 16->32->32->4, "
+                               "threshold mode, 640x360/1280x720/1920x1080 uniform, Poisson arrivals",
+                   "rate_hz": 200, "duration_s": args.serve_seconds, "streams": 2, "max_batch": 16,
+                   "budget_fraction": args.serve_budget, "budget_bytes": srv.budget,
+                   "slo_p99_ms": 16.7, **main_st, "sweep": sweep}
+
     # CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.skip_cpu:
@@ -276,6 +305,7 @@ def main():
         "roofline": roofline,
         "step_roofline": step_roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
