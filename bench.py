@@ -156,14 +156,27 @@ def main():
     graph = False
     if not args.no_graph:
         ref = (vis.clone(), gv.clone())
-        ctx.set_static(True)
+        from paper_2603_27151_amd import _lib
+        for attempt in range(3):
+            # static mode outside capture first; an overflow means the eager
+            # calls' capacities were short for this run: rerun eagerly (which
+            # grows them) and try again
+            ctx.set_static(True)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                step()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            try:
+                ctx.check_overflow()
+                break
+            except _lib.SoupError as e:
+                log(f"static step overflowed ({e}); growing the workspaces")
+                ctx.set_static(False)
+                step()
+                torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()   # static mode outside capture first
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
         with torch.cuda.graph(g):
             step()
         g.replay()

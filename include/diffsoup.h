@@ -52,7 +52,7 @@ typedef enum {
  * alpha = sigmoid(o3)). */
 typedef struct {
     int32_t T;                 /* triangles, >= 0 */
-    int32_t G;                 /* feature grid side, >= 2 */
+    int32_t G;                 /* feature grid side, >= 2; G * G * C <= 4096 (else SOUP_ERR_UNSUPPORTED) */
     int32_t C;                 /* feature channels = dims[0] */
     int32_t n_layers;          /* MLP layers (linear maps), >= 1 */
     const int32_t* dims;       /* host [n_layers+1]; dims[0] == C, dims[n_layers] == 4 */

@@ -32,8 +32,8 @@ struct soup_ctx {
     std::string err;
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
-    DevBuf records, rec_tri, rec_idx, tri_count, tri_fill, tri_off, tri_bsum, chunk_off, mlp_mid, frags;
-    DevBuf region_counts, region_boff, chunk_tri, flags;
+    DevBuf tri_count, tri_fill, tri_off, tri_bsum, mlp_mid, frags, sorted;
+    DevBuf region_counts, region_boff, flags;
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
@@ -172,8 +172,8 @@ soup_status check_scene(soup_ctx* c, const soup_scene* s, MlpKind* kind) {
         return fail(c, SOUP_ERR_INVALID, "scene.n_layers = %d or dims missing", s->n_layers);
     if (s->dims[0] != s->C) return fail(c, SOUP_ERR_INVALID, "dims[0] = %d != C = %d", s->dims[0], s->C);
     if (s->dims[s->n_layers] != 4) return fail(c, SOUP_ERR_INVALID, "dims[last] = %d != 4", s->dims[s->n_layers]);
-    if (static_cast<int64_t>(s->G) * s->G * s->C > 12288)
-        return fail(c, SOUP_ERR_UNSUPPORTED, "G*G*C = %d exceeds the per-triangle LDS reduction (12288)",
+    if (static_cast<int64_t>(s->G) * s->G * s->C > 4096)
+        return fail(c, SOUP_ERR_UNSUPPORTED, "G*G*C = %d exceeds the per-wave LDS gradient grid (4096 floats)",
                     s->G * s->G * s->C);
     if (s->T > 0 && (!s->verts || !s->feats || !s->mlp))
         return fail(c, SOUP_ERR_INVALID, "scene device pointers are NULL");
@@ -426,10 +426,11 @@ void soup_ctx_destroy(soup_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&c->views,    &c->scenes,  &c->recs,      &c->tile_count, &c->tile_fill, &c->tile_start,
-                      &c->bsum,     &c->entries, &c->vacc,      &c->partial,    &c->counters,  &c->records,
-                      &c->rec_tri,  &c->rec_idx, &c->tri_count, &c->tri_fill,   &c->tri_off,   &c->tri_bsum,
-                      &c->chunk_off, &c->mlp_mid,  &c->frags,    &c->region_counts, &c->region_boff, &c->chunk_tri, &c->flags};
+    DevBuf* bufs[] = {&c->views,     &c->scenes,    &c->recs,          &c->tile_count,  &c->tile_fill,
+                      &c->tile_start, &c->bsum,      &c->entries,       &c->vacc,        &c->partial,
+                      &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
+                      &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
+                      &c->flags};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -523,17 +524,19 @@ int replay_blocks(soup_ctx* c, const Plan& p) {
 
 // Backward, part 1: replay the fragments the backward needs into c->frags,
 // one region per replay wave, then scan the region counts into batch
-// offsets. Regions are sized from the last call's largest count with
+// offsets. Regions are sized from the last call's largest count with 50%
 // headroom (else from 1.5 fragments per pixel); an overflow is detected from
 // the counts and the replay runs again, sized exactly. Returns the number of
 // fragments in *n_frag and of decode batches in *n_batch.
 soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64_t* vis, const float* grad_color,
-                   const float* grad_logp, bool all_front, hipStream_t s, int64_t* n_frag, int64_t* n_batch) {
+                   const float* grad_logp, bool all_front, int32_t* tri_count, int T, hipStream_t s,
+                   int64_t* n_frag, int64_t* n_batch) {
     if (p.n_pix >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "backward needs fewer than 2^32 pixels per call");
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     const int nb = replay_blocks(c, p);
     const int nr = nb * replay_waves_per_block(c->tile);
-    uint64_t region = c->region_hint ? c->region_hint + c->region_hint / 4 + 64
+    // per-wave counts vary between calls (tiles are handed out dynamically): 50% headroom
+    uint64_t region = c->region_hint ? c->region_hint + c->region_hint / 2 + 256
                                      : (static_cast<uint64_t>(p.n_pix) * 3 / 2) / nr + 1024;
     soup_status st;
     if ((st = ensure(c, c->region_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
@@ -553,8 +556,10 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         ra.frags = static_cast<FragRec*>(c->frags.p);
         ra.region = static_cast<uint32_t>(c->frag_region);
         ra.counts = static_cast<uint32_t*>(c->region_counts.p);
+        ra.tri_count = tri_count;
         ra.n_blocks = nb;
         launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+        if (tri_count) launch_fill_i32(tri_count, T, 0, s);
         launch_replay(ra, c->tile, s);
         launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4,
                            static_cast<unsigned int*>(c->flags.p), s);
@@ -570,6 +575,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         {
             Timed t(c, SOUP_T_FILL, s);
             launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
+            if (tri_count) launch_fill_i32(tri_count, T, 0, s);
         }
         ReplayArgs ra{};
         ra.r = a;
@@ -580,6 +586,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         ra.frags = static_cast<FragRec*>(c->frags.p);
         ra.region = static_cast<uint32_t>(region);
         ra.counts = static_cast<uint32_t*>(c->region_counts.p);
+        ra.tri_count = tri_count;
         ra.n_blocks = nb;
         {
             Timed t(c, SOUP_T_REPLAY, s);
@@ -615,6 +622,7 @@ DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a) {
     d.feats = p.scenes[0].feats;
     d.mlp = p.scenes[0].mlp;
     d.G = p.G;
+    d.T = p.scenes[0].T;
     d.frags = static_cast<FragRec*>(c->frags.p);
     d.region = static_cast<uint32_t>(c->frag_region);
     d.counts = static_cast<uint32_t*>(c->region_counts.p);
@@ -653,7 +661,7 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
             RasterArgs ra = a;
             ra.counter = nullptr;
             int64_t n_frag = 0, n_batch = 0;
-            if ((st = replay(c, p, ra, vis, nullptr, nullptr, true, s, &n_frag, &n_batch))) return st;
+            if ((st = replay(c, p, ra, vis, nullptr, nullptr, true, nullptr, 0, s, &n_frag, &n_batch))) return st;
             DecodeArgs d = decode_args(c, p, ra);
             d.logp = logp;
             launch_decode_bwd(d, p.kind, true, s);
@@ -682,62 +690,61 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     const int nb = decode_blocks(c);
     const int rows = nb * 4;
     const int T = scene->T;
-    const int RS = rec_stride(scene->C);
+    const int64_t n_grid = static_cast<int64_t>(scene->G) * scene->G * scene->C;
     if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
         (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)) ||
         (st = ensure(c, c->mlp_mid, static_cast<size_t>(mlp_reduce_mid_rows(rows)) * p.n_params * 8)) ||
         (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
         (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 4)) ||
         (st = ensure(c, c->tri_off, static_cast<size_t>(T + 1) * 8)) ||
-        (st = ensure(c, c->chunk_off, static_cast<size_t>(T + 1) * 8)) ||
         (st = ensure(c, c->tri_bsum, static_cast<size_t>((T + 1023) / 1024 + 1) * 8)))
         return st;
     RasterArgs a = raster_args(c, p, o);
-    unsigned long long* cnt_dev = static_cast<unsigned long long*>(c->counters.p);
     const float* gl = o.mode == 0 ? grad_logp : nullptr;
     int64_t n_frag = 0, n_batch = 0;
-    if ((st = replay(c, p, a, vis, grad_color, gl, false, s, &n_frag, &n_batch))) return st;
-    // one record slot per decode lane; the buffers are sized for the largest
-    // batch count the regions allow, so that static-mode calls fit as well
-    const int64_t n_rec = n_batch * 64;
-    const int64_t rec_cap = static_cast<int64_t>(c->frag_regions) * static_cast<int64_t>((c->frag_region + 63) / 64) * 64;
-    if ((st = ensure(c, c->records, static_cast<size_t>(rec_cap) * RS * 4)) ||
-        (st = ensure(c, c->rec_tri, static_cast<size_t>(rec_cap) * 4)))
+    if ((st = replay(c, p, a, vis, grad_color, gl, false, static_cast<int32_t*>(c->tri_count.p), T, s, &n_frag,
+                     &n_batch)))
         return st;
-    {
-        Timed t(c, SOUP_T_FILL, s);
-        launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
-        launch_fill_i32(static_cast<int32_t*>(c->tri_count.p), T, 0, s);
-    }
-    {
-        DecodeArgs d = decode_args(c, p, a);
-        d.grad_color = grad_color;
-        d.grad_logp = gl;
-        d.records = static_cast<float*>(c->records.p);
-        d.rec_tri = static_cast<uint32_t*>(c->rec_tri.p);
-        d.tri_count = static_cast<int32_t*>(c->tri_count.p);
-        d.mlp_partial = static_cast<float*>(c->partial.p);
-        Timed t(c, SOUP_T_BWD, s);
-        launch_decode_bwd(d, p.kind, false, s);
-    }
-    HIP_TRY(c, hipGetLastError());
-    if ((st = ensure(c, c->rec_idx, static_cast<size_t>(rec_cap) * 4)) ||
-        (st = ensure(c, c->chunk_tri, static_cast<size_t>(reduce_chunk_bound(scene->C, T, rec_cap)) * 4)))
-        return st;
+    // the list sorted by triangle has at most as many entries as the regions hold
+    const int64_t frag_cap = static_cast<int64_t>(c->frag_regions) * static_cast<int64_t>(c->frag_region);
+    if ((st = ensure(c, c->sorted, static_cast<size_t>(frag_cap) * sizeof(FragRec)))) return st;
     {
         Timed t(c, SOUP_T_GRAD, s);
         launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
                     static_cast<int64_t*>(c->tri_off.p), s);
         launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), T, 0, s);
-        launch_bucket(static_cast<uint32_t*>(c->rec_tri.p), cnt_dev + 5, n_rec, static_cast<int64_t*>(c->tri_off.p),
-                      static_cast<int32_t*>(c->tri_fill.p), static_cast<uint32_t*>(c->rec_idx.p), s);
-        // tri_fill and tri_bsum are free again once the records are bucketed
-        launch_reduce(static_cast<float*>(c->records.p), scene->C, scene->G, T, n_rec,
-                      static_cast<int64_t*>(c->tri_off.p), static_cast<int32_t*>(c->tri_fill.p),
-                      static_cast<int64_t*>(c->tri_bsum.p), static_cast<int64_t*>(c->chunk_off.p),
-                      static_cast<int32_t*>(c->chunk_tri.p), static_cast<uint32_t*>(c->rec_idx.p), grad_feats,
-                      grad_verts, o.accumulate != 0, s);
+        PlaceArgs pa{};
+        pa.frags = static_cast<FragRec*>(c->frags.p);
+        pa.region = static_cast<uint32_t>(c->frag_region);
+        pa.counts = static_cast<uint32_t*>(c->region_counts.p);
+        pa.boff = static_cast<uint32_t*>(c->region_boff.p);
+        pa.n_regions = c->frag_regions;
+        pa.tri_off = static_cast<int64_t*>(c->tri_off.p);
+        pa.tri_fill = static_cast<int32_t*>(c->tri_fill.p);
+        pa.sorted = static_cast<FragRec*>(c->sorted.p);
+        pa.n_blocks = decode_blocks(c);
+        launch_place(pa, s);
     }
+    {
+        Timed t(c, SOUP_T_FILL, s);
+        launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
+        if (!o.accumulate) {
+            launch_fill_f32(grad_feats, static_cast<int64_t>(T) * n_grid, 0.0f, s);
+            launch_fill_f32(grad_verts, static_cast<int64_t>(T) * 9, 0.0f, s);
+        }
+    }
+    {
+        DecodeArgs d = decode_args(c, p, a);
+        d.sorted = static_cast<FragRec*>(c->sorted.p);
+        d.tri_off = static_cast<int64_t*>(c->tri_off.p);
+        d.grad_feats = grad_feats;
+        d.grad_verts = grad_verts;
+        d.accumulate = o.accumulate;
+        d.mlp_partial = static_cast<float*>(c->partial.p);
+        Timed t(c, SOUP_T_BWD, s);
+        launch_decode_bwd(d, p.kind, false, s);
+    }
+    HIP_TRY(c, hipGetLastError());
     {
         Timed t(c, SOUP_T_EDGE, s);
         launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, static_cast<float*>(c->vacc.p), s);

@@ -2,9 +2,8 @@
 // Backward, part 2 (Supplement Algorithm A1, part 2; Eq. (8), (9)): decode of
 // the fragment list written by the replay kernel.
 //
-// Persistent waves take batches of 64 consecutive fragments of one region of
-// the list (batch b lies in the region w with boff[w] <= b < boff[w + 1],
-// found by a binary search over the offsets staged in LDS). For each:
+// The backward walks the fragment list sorted by triangle: every wave takes a
+// contiguous range of 64-fragment batches. For each batch:
 //   - recompute the bilinear feature and the MLP (float32, as the forward);
 //   - logit gradients: winner -> colour path g_C sigma'(o_rgb) and score
 //     g_L (1 - alpha); fragment in front -> score -g_L alpha (Eq. (9) through
@@ -13,13 +12,18 @@
 //     runs on the matrix cores over the batch (activations and deltas staged
 //     through LDS); each wave writes its sums once, at the end, to its own row
 //     of a partial-sum buffer (rows are reduced later in a fixed order);
-//   - one record per fragment at the fragment's own index: texture cell,
-//     position, feature gradient and, for the winner, the gradient of its
-//     triangle's world-space vertices, through the perspective-correct and
-//     screen barycentrics, the screen positions and 1/w, and the
-//     view-projection.
-// A logp variant sums log(1 - alpha) over the front set and log(alpha) of the
-// winner per pixel (log p(f*) of Eq. (6)).
+//   - for the winner, the gradient of its triangle's world-space vertices,
+//     through the perspective-correct and screen barycentrics, the screen
+//     positions and 1/w, and the view-projection;
+//   - the feature gradient (bilinear weights of the four texels) and the
+//     vertex gradient are summed into the wave's LDS copy of the current
+//     triangle's G x G x C grid; when the triangle changes, the grid goes to
+//     HBM once (a plain store when the wave holds all of the triangle's
+//     fragments, float atomics for a triangle split between waves).
+// A logp variant walks the unsorted fragment list region by region (batch b
+// lies in the region w with boff[w] <= b < boff[w + 1], found by a binary
+// search over the offsets staged in LDS) and sums log(1 - alpha) over the
+// front set and log(alpha) of the winner per pixel (log p(f*) of Eq. (6)).
 #include "raster_common.hpp"
 
 namespace soup {
@@ -129,10 +133,12 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
     constexpr int NW = 4;
     constexpr int SW = StageCfg<S>::kWidth;
     __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
-    __shared__ uint32_t s_boff[kMaxRegions + 1];
+    __shared__ uint32_t s_boff[LOGP ? kMaxRegions + 1 : 1];
+    extern __shared__ float s_dyn[];   // [NW][G*G*C + 16]: per-wave gradient grid of the current triangle
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int G = a.G;
+    const int n_grid = G * G * S::C;
     gfloat* __restrict__ feats = as_global(uniform_ptr(a.feats));
 
     MlpGrad<S> acc;
@@ -141,34 +147,80 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         if constexpr (S::NH == 2) acc.mid[0].zero();
         acc.out.zero();
     }
-    const int NR = a.n_regions;
-    for (int i = tid; i <= NR; i += blockDim.x) s_boff[i] = a.boff[i];
-    __syncthreads();
-    const uint32_t n_batch = s_boff[NR];
-    const uint32_t n_waves = gridDim.x * NW;
-    for (uint32_t bi = blockIdx.x * NW + w; bi < n_batch; bi += n_waves) {
-        int lo = 0, hi = NR - 1;   // region: last w with boff[w] <= bi
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_boff[mid] <= bi) lo = mid;
-            else hi = mid - 1;
+    const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * NW;
+    const uint64_t wid = static_cast<uint64_t>(blockIdx.x) * NW + w;
+    uint64_t b_begin, b_end, b_step;
+    int64_t E = 0, f0 = 0, f1 = 0;   // sorted list: fragments, this wave's range
+    float* grid = s_dyn + static_cast<size_t>(w) * (n_grid + 16);
+    int cur = -1;                    // triangle held in grid (wave-uniform)
+    if (LOGP) {
+        for (int i = tid; i <= a.n_regions; i += blockDim.x) s_boff[i] = a.boff[i];
+        __syncthreads();
+        b_begin = wid;
+        b_end = s_boff[a.n_regions];
+        b_step = n_waves;
+    } else {
+        E = a.tri_off[a.T];
+        const uint64_t nb = (static_cast<uint64_t>(E) + 63) / 64;
+        const uint64_t per = (nb + n_waves - 1) / n_waves;
+        b_begin = wid * per;
+        b_end = b_begin + per < nb ? b_begin + per : nb;
+        b_step = 1;
+        f0 = static_cast<int64_t>(b_begin) * 64;
+        f1 = static_cast<int64_t>(b_end) * 64 < E ? static_cast<int64_t>(b_end) * 64 : E;
+        for (int k = lane; k < n_grid + 16; k += 64) grid[k] = 0.0f;
+    }
+    // the grid of triangle t goes to HBM and is cleared (whole wave)
+    auto flush = [&](int t) __attribute__((always_inline)) {
+        __threadfence_block();
+        const bool owned = a.tri_off[t] >= f0 && a.tri_off[t + 1] <= f1;
+        float* gf = a.grad_feats + static_cast<size_t>(t) * n_grid;
+        for (int k = lane; k < n_grid; k += 64) {
+            const float v = grid[k];
+            grid[k] = 0.0f;
+            if (owned) gf[k] = a.accumulate ? gf[k] + v : v;
+            else if (v != 0.0f) atomicAdd(&gf[k], v);
         }
-        const uint32_t cr = a.counts[lo];
-        const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
-        const bool on = in_region < (cr < a.region ? cr : a.region);
-        const uint64_t fi = static_cast<uint64_t>(bi) * 64 + lane;   // record index
+        if (lane < 9) {
+            const float v = grid[n_grid + lane];
+            grid[n_grid + lane] = 0.0f;
+            float* gv = a.grad_verts + static_cast<size_t>(t) * 9 + lane;
+            if (owned) *gv = a.accumulate ? *gv + v : v;
+            else if (v != 0.0f) atomicAdd(gv, v);
+        }
+        __threadfence_block();
+    };
+    for (uint64_t bi = b_begin; bi < b_end; bi += b_step) {
+        bool on;
         uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb4 = make_uint4(0u, 0u, 0u, 0u);
-        if (on) {
-            const FragRec& fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
-            fa = fr.a;
-            fb4 = fr.b;
+        if (LOGP) {
+            int lo = 0, hi = a.n_regions - 1;   // region: last w with boff[w] <= bi
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_boff[mid] <= bi) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t cr = a.counts[lo];
+            const uint32_t in_region = (static_cast<uint32_t>(bi) - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
+            on = in_region < (cr < a.region ? cr : a.region);
+            if (on) {
+                const FragRec& fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
+                fa = fr.a;
+                fb4 = fr.b;
+            }
+        } else {
+            const int64_t fi = static_cast<int64_t>(bi) * 64 + lane;
+            on = fi < E;
+            if (on) {
+                const FragRec& fr = a.sorted[fi];
+                fa = fr.a;
+                fb4 = fr.b;
+            }
         }
         const uint32_t pix = fa.x;
         const uint32_t tri = fa.y & 0x7FFFFFFFu;
         const bool win = on && (fa.y >> 31);
-        const float tt[3] = {__uint_as_float(fa.z), __uint_as_float(fa.w), __uint_as_float(fb4.x)};
-        float b1 = 0.f, b2 = 0.f;
-        if (on) persp_from_t(tt[0], tt[1], tt[2], b1, b2);
+        const float b1 = __uint_as_float(fa.z), b2 = __uint_as_float(fa.w);
         const Cell c = cell_of(b1, b2, G);
         float x[S::C];
         MlpAct<S> m;
@@ -192,13 +244,12 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
             continue;
         }
         float d[4] = {0.f, 0.f, 0.f, 0.f};
-        float gcol[3] = {0.f, 0.f, 0.f};
         if (on) {
-            const float gl = a.grad_logp ? a.grad_logp[pix] : 0.0f;
+            const float gl = __uint_as_float(fb4.x);   // the pixel's score weight (0 without one)
             if (win) {
+                const float gcol[3] = {__uint_as_float(fb4.y), __uint_as_float(fb4.z), __uint_as_float(fb4.w)};
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    gcol[k] = a.grad_color[3 * static_cast<size_t>(pix) + k];
                     const float s = sigmoid_c(m.o[k]);
                     d[k] = gcol[k] * s * (1.0f - s);
                 }
@@ -277,7 +328,6 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 dfy = __builtin_fmaf(dx[k], (1.0f - c.fx) * (T01 - T00) + c.fx * (T11 - T10), dfy);
             }
             const float gm1 = static_cast<float>(G - 1);
-            const float fb[3] = {__uint_as_float(fb4.y), __uint_as_float(fb4.z), __uint_as_float(fb4.w)};
             float iwv[3];
             int32_t Xv[3], Yv[3];
 #pragma unroll
@@ -286,6 +336,24 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 Xv[i] = tr.X[i];
                 Yv[i] = tr.Y[i];
             }
+            // geometry in pixel units from exact integer differences
+            const int32_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
+            // the screen barycentrics of the contract, recomputed exactly:
+            // beta_i = (float)E_i * (1 / |2A|) with E_i the orientation-normalised
+            // integer edge function of edge i at the pixel centre
+            float fb[3];
+            {
+                const int64_t sgn = tr.rA < 0.0f ? -1 : 1;
+                const float ra = __builtin_fabsf(tr.rA);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int ea = i == 2 ? 0 : i + 1, eb = i == 0 ? 2 : (i == 1 ? 0 : 1);
+                    const int64_t ex = static_cast<int64_t>(Xv[eb] - Xv[ea]), ey = static_cast<int64_t>(Yv[eb] - Yv[ea]);
+                    const int64_t E = sgn * (ex * (PY - Yv[ea]) - ey * (PX - Xv[ea]));
+                    fb[i] = static_cast<float>(E) * ra;
+                }
+            }
+            const float tt[3] = {fb[0] * iwv[0], fb[1] * iwv[1], fb[2] * iwv[2]};
             const float inv_s = 1.0f / ((tt[0] + tt[1]) + tt[2]);
             const float bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
             const float db[3] = {0.0f, dfx * gm1, dfy * gm1};
@@ -297,8 +365,6 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 dbeta[i] = dt * iwv[i];
                 diw[i] = dt * fb[i];
             }
-            // geometry in pixel units from exact integer differences
-            const int32_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
             const int64_t Ai = static_cast<int64_t>(Xv[1] - Xv[0]) * (Yv[2] - Yv[0]) -
                                static_cast<int64_t>(Yv[1] - Yv[0]) * (Xv[2] - Xv[0]);
             const float inv_area = 65536.0f / static_cast<float>(Ai);
@@ -339,35 +405,96 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 for (int k = 0; k < 3; ++k) gw[3 * jv + k] = vd.M[k] * gc0 + vd.M[4 + k] * gc1 + vd.M[12 + k] * gc3;
             }
         }
-        // --- the record, at the fragment's own index ---
-        if (on) {
-            float* rec = a.records + fi * kRecStride<S::C>;
-            *reinterpret_cast<float4*>(rec) =
-                make_float4(__uint_as_float(tri),
-                            __uint_as_float(static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 8) |
-                                            (win ? 0x80000000u : 0u)),
-                            c.fx, c.fy);
+        // --- sum into the wave's grid, one run of equal triangles at a time ---
+        // The feature gradients are staged (row = fragment) and added one
+        // fragment per step with the wave's lanes spread over (corner,
+        // channel), so that no two lanes of an LDS add share an address;
+        // the winners' vertex gradients are summed over the run by a wave
+        // reduction.
+        static_assert(kStageRows * SW >= 64 * S::C, "the stage holds the batch's feature gradients");
 #pragma unroll
-            for (int k = 0; k < S::C; k += 4)
-                *reinterpret_cast<float4*>(rec + 4 + k) = make_float4(dx[k], dx[k + 1], dx[k + 2], dx[k + 3]);
-            if (win) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) rec[4 + S::C + k] = gw[k];
-            }
-        }
+        for (int k = 0; k < S::C; k += 4)
+            *reinterpret_cast<float4*>(st + lane * S::C + k) = make_float4(dx[k], dx[k + 1], dx[k + 2], dx[k + 3]);
+        const uint32_t cellw = static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 16);
+        __threadfence_block();
         const uint32_t tkey = on ? tri : 0xFFFFFFFFu;
-        a.rec_tri[fi] = tkey;
-        // per-triangle record counts, one atomic per run of equal triangles
-        // (an empty lane ends a run)
         const uint32_t tprev = __shfl_up(tkey, 1, 64);
-        const bool head = lane == 0 || tprev != tkey;
-        const uint64_t heads = __ballot(head);
-        if (head && on) {
-            const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-            const int endl = above ? __builtin_ctzll(above) : 64;
-            atomicAdd(&a.tri_count[tri], endl - lane);
+        uint64_t heads = __ballot(lane == 0 || tprev != tkey);
+        while (heads) {
+            const int h = __builtin_ctzll(heads);
+            heads &= heads - 1;
+            const int t = __builtin_amdgcn_readlane(static_cast<int>(tkey), h);
+            if (t < 0) break;   // the sentinel run: empty lanes at the batch's end
+            if (t != cur) {
+                if (cur >= 0) flush(cur);
+                cur = t;
+            }
+            const int end = heads ? __builtin_ctzll(heads) : 64;
+            const bool in_run = lane >= h && lane < end;
+            if (__ballot(in_run && win)) {   // the run's winners: vertex gradient summed over the wave
+                float v[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) v[k] = in_run ? gw[k] : 0.0f;   // gw is zero for fragments in front
+#pragma unroll
+                for (int d = 32; d > 0; d >>= 1)   // the nine sums advance together
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) v[k] += __shfl_xor(v[k], d, 64);
+                if (lane == 0) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) grid[n_grid + k] += v[k];
+                }
+            }
+            constexpr int LPF = 4 * S::C;                  // (corner, channel) pairs of one fragment
+            constexpr int FPS = LPF >= 64 ? 1 : 64 / LPF;  // fragments per step
+            constexpr int PPF = LPF >= 64 ? LPF / 64 : 1;  // steps per fragment
+            constexpr int UF = 4;                          // steps in flight: their staged reads go first
+            for (int f0 = h; f0 < end; f0 += FPS * UF) {
+                int fs[UF];
+                bool ok[UF];
+                float dv[UF][PPF];
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    const int f = f0 + u * FPS + (FPS > 1 ? lane / LPF : 0);
+                    ok[u] = f < end;
+                    fs[u] = ok[u] ? f : h;                     // lanes past the run repeat h with weight 0
+#pragma unroll
+                    for (int pp = 0; pp < PPF; ++pp) {
+                        const int k = (pp * 64 + (FPS > 1 ? lane % LPF : lane)) % S::C;
+                        dv[u][pp] = st[fs[u] * S::C + k];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    uint32_t cw;
+                    float fx, fy;
+                    if (FPS > 1) {
+                        cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), fs[u], 64));
+                        fx = __shfl(c.fx, fs[u], 64);
+                        fy = __shfl(c.fy, fs[u], 64);
+                    } else {   // one fragment per step: a wave-uniform lane index
+                        const int fu = __builtin_amdgcn_readfirstlane(fs[u]);
+                        cw = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(cellw), fu));
+                        fx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, c.fx), fu));
+                        fy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, c.fy), fu));
+                    }
+                    const int ix = static_cast<int>(cw & 0xFFFFu), iy = static_cast<int>(cw >> 16);
+#pragma unroll
+                    for (int pp = 0; pp < PPF; ++pp) {
+                        const int idx = pp * 64 + (FPS > 1 ? lane % LPF : lane);
+                        const int q = idx / S::C, k = idx % S::C;   // corner, channel
+                        const int dxq = q & 1, dyq = q >> 1;
+                        const float wq = (dxq ? fx : 1.0f - fx) * (dyq ? fy : 1.0f - fy);
+                        float* gp = &grid[((iy + dyq) * G + ix + dxq) * S::C + k];
+                        const float val = ok[u] ? wq * dv[u][pp] : 0.0f;
+                        if (FPS > 1) atomicAdd(gp, val);   // two fragments per step may share a texel
+                        else *gp += val;   // one fragment: 64 distinct addresses; a wave's LDS accesses run in order
+                    }
+                }
+            }
+            __threadfence_block();
         }
     }
+    if (!LOGP && cur >= 0) flush(cur);
     if (!LOGP) {
         float* row = a.mlp_partial + (static_cast<size_t>(blockIdx.x) * NW + w) * S::kParams;
         acc.l0.store(row, S::w_off(0), S::b_off(0), lane);
@@ -378,10 +505,12 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
 
 template <class S>
 static void launch_decode_bwd_s(const DecodeArgs& a, bool logp, hipStream_t s) {
-    if (logp)
+    if (logp) {
         hipLaunchKernelGGL((decode_bwd_kernel<S, true>), dim3(a.n_blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((decode_bwd_kernel<S, false>), dim3(a.n_blocks), dim3(256), 0, s, a);
+    } else {
+        const size_t lds = static_cast<size_t>(4) * (static_cast<size_t>(a.G) * a.G * S::C + 16) * sizeof(float);
+        hipLaunchKernelGGL((decode_bwd_kernel<S, false>), dim3(a.n_blocks), dim3(256), lds, s, a);
+    }
 }
 
 }  // namespace soup

@@ -44,7 +44,8 @@ struct RasterArgs {
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 
 // One fragment the backward needs, 32 bytes: a = (pixel, triangle | winner << 31,
-// t0, t1), b = (t2, screen barycentrics beta0..2), with t_i = beta_i / w_i.
+// perspective-correct b1, b2), b = (the pixel's score weight g_L and colour
+// gradient g_C[3]), so that the decode reads no per-pixel data.
 struct FragRec {
     uint4 a;
     uint4 b;
@@ -65,6 +66,7 @@ struct ReplayArgs {
     FragRec* frags;                // [n_regions * region]
     uint32_t region;
     uint32_t* counts;              // [n_regions]
+    int32_t* tri_count;            // [T] fragments per triangle (added to; null: not counted)
     int n_blocks;                  // persistent grid size (n_regions = n_blocks * waves per block)
 };
 
@@ -77,6 +79,22 @@ int replay_waves_per_block(int tile);
 void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
                         unsigned long long* summary, unsigned int* sticky, hipStream_t s);
 
+// Counting-sort placement of the fragment list by triangle:
+// sorted[tri_off[t] + k] for the k-th fragment of triangle t.
+struct PlaceArgs {
+    const FragRec* frags;
+    uint32_t region;
+    const uint32_t* counts;        // [n_regions]
+    const uint32_t* boff;          // [n_regions + 1]
+    int n_regions;
+    const int64_t* tri_off;        // [T + 1] exclusive scan of the per-triangle counts
+    int32_t* tri_fill;             // [T] zeroed
+    FragRec* sorted;               // [tri_off[T]]
+    int n_blocks;
+};
+
+void launch_place(const PlaceArgs& a, hipStream_t s);
+
 struct DecodeArgs {
     const ViewDesc* views;
     int V;
@@ -84,16 +102,19 @@ struct DecodeArgs {
     const float* feats;
     const float* mlp;
     int G;
+    int T;
+    // logp pass: the region list
     const FragRec* frags;
     uint32_t region;
     const uint32_t* counts;        // [n_regions]
     const uint32_t* boff;          // [n_regions + 1]
     int n_regions;
-    const float* grad_color;       // [P,3]
-    const float* grad_logp;        // [P] or null (also null in threshold mode)
-    float* records;                // [64 * batches, kRecStride<C>] per-fragment gradient records
-    uint32_t* rec_tri;             // [64 * batches] triangle of each record, 0xFFFFFFFF for an empty lane
-    int32_t* tri_count;            // [T] records per triangle
+    // backward: the list sorted by triangle
+    const FragRec* sorted;         // [tri_off[T]]
+    const int64_t* tri_off;        // [T + 1]
+    float* grad_feats;             // [T, G, G, C]: zeroed by the caller unless accumulate
+    float* grad_verts;             // [T, 9]: zeroed by the caller unless accumulate
+    int accumulate;
     float* mlp_partial;            // [n_blocks * 4, n_params]
     float* logp;                   // logp output (logp pass only; zeroed by the caller)
     unsigned long long* counter;   // decode counter or null
@@ -115,23 +136,5 @@ void launch_selftest_uniform(uint64_t seed, const uint32_t* pixel, const uint32_
                              uint32_t step, float* u, int64_t n, hipStream_t s);
 
 constexpr int kVacc = 16;          // floats per (view, triangle) in the edge-moment accumulator
-
-// Per-fragment gradient record: tri, cell (ix | iy << 8 | winner << 31), fx, fy,
-// dL/dfeature[C], world-space vertex gradient[9] (winner only); 16-byte rows.
-template <int C>
-constexpr int kRecStride = ((4 + C + 9) + 3) / 4 * 4;
-inline int rec_stride(int C) { return ((4 + C + 9) + 3) / 4 * 4; }
-
-// Records [0, 64 * (*n_batch)) are placed; the grid covers `bound` records.
-void launch_bucket(const uint32_t* rec_tri, const unsigned long long* n_batch, int64_t bound,
-                   const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx, hipStream_t s);
-// Per-triangle reduction of the records listed by idx (grouped by triangle,
-// tri_off[T + 1]), in chunks of a bounded number of records. chunk_n [T],
-// chunk_bsum (scan block sums), chunk_off [T + 1] and chunk_tri
-// [reduce_chunk_bound] are scratch.
-int64_t reduce_chunk_bound(int C, int T, int64_t n_rec);
-void launch_reduce(const float* records, int C, int G, int T, int64_t n_rec, const int64_t* tri_off,
-                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, int32_t* chunk_tri,
-                   const uint32_t* idx, float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s);
 
 }  // namespace soup

@@ -21,208 +21,6 @@ void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// gradient records -> per-triangle lists -> per-triangle reduction
-// ---------------------------------------------------------------------------
-
-// Counting-sort placement of record indices into per-triangle lists; runs of
-// equal triangles in a wave take one atomic.
-__global__ __launch_bounds__(256) void bucket_kernel(const uint32_t* __restrict__ rec_tri,
-                                                     const unsigned long long* __restrict__ n_batch,
-                                                     const int64_t* __restrict__ tri_off,
-                                                     int32_t* __restrict__ tri_fill, uint32_t* __restrict__ idx) {
-    const int64_t n = static_cast<int64_t>(*n_batch) * 64;
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const uint32_t tri = i < n ? rec_tri[i] : 0xFFFFFFFFu;
-    const bool on = tri != 0xFFFFFFFFu;   // empty record lanes carry the sentinel
-    const uint32_t tprev = __shfl_up(tri, 1, 64);
-    const bool head = lane == 0 || tprev != tri;   // a sentinel lane ends a run
-    const uint64_t heads = __ballot(head);   // outside any branch: a ballot sees only the lanes that execute it
-    int base = 0;
-    if (head && on) {
-        const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-        const int endl = above ? __builtin_ctzll(above) : 64;
-        base = atomicAdd(&tri_fill[tri], endl - lane);
-    }
-    const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
-    const int hl = upto ? 63 - __builtin_clzll(upto) : 0;
-    const int hb = __shfl(base, hl, 64);
-    if (on) idx[tri_off[tri] + hb + (lane - hl)] = static_cast<uint32_t>(i);
-}
-
-// Records per reduction chunk: 64 per thread of a 256-thread workgroup.
-template <int C>
-constexpr int64_t kChunkRecs = 64 * (256 / C);
-
-// Chunks per triangle (at least one, so that untouched triangles still get
-// their zero gradient written). A triangle split over several chunks is summed
-// with global atomics, so its outputs are cleared here first unless the call
-// accumulates.
-template <int C>
-__global__ __launch_bounds__(256) void reduce_prep_kernel(const int64_t* __restrict__ tri_off, int T, int n_feat,
-                                                          int32_t* __restrict__ chunk_n,
-                                                          float* __restrict__ grad_feats,
-                                                          float* __restrict__ grad_verts, bool accumulate) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    const int64_t cnt = tri_off[t + 1] - tri_off[t];
-    const int32_t nch = cnt <= kChunkRecs<C> ? 1 : static_cast<int32_t>((cnt + kChunkRecs<C> - 1) / kChunkRecs<C>);
-    chunk_n[t] = nch;
-    if (nch > 1 && !accumulate) {
-        float* gf = grad_feats + static_cast<size_t>(t) * n_feat;
-        for (int k = 0; k < n_feat; ++k) gf[k] = 0.0f;
-        for (int k = 0; k < 9; ++k) grad_verts[static_cast<size_t>(t) * 9 + k] = 0.0f;
-    }
-}
-
-// One workgroup per chunk of at most kChunkRecs records of one triangle: sums
-// the records' feature gradients into the G x G x C grid in LDS (bilinear
-// weights of each record's cell position) and its winners' vertex gradients.
-// Thread (seg, c) walks a contiguous segment of the chunk for channel c;
-// consecutive records mostly share a cell (they come from the same tile), so
-// the four corner sums stay in registers for a run of equal cells and reach
-// LDS once per run. A triangle of one chunk stores its sums; the chunks of a
-// larger triangle add theirs with global atomics, so that no workgroup walks
-// more than a chunk however many pixels one triangle covers.
-// chunk_tri[c] = the triangle that owns chunk c.
-__global__ __launch_bounds__(256) void chunk_map_kernel(const int64_t* __restrict__ chunk_off, int T,
-                                                        int32_t* __restrict__ chunk_tri) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    for (int64_t c = chunk_off[t]; c < chunk_off[t + 1]; ++c) chunk_tri[c] = t;
-}
-
-template <int C>
-__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ records, int G, int T,
-                                                     const int64_t* __restrict__ tri_off,
-                                                     const int64_t* __restrict__ chunk_off,
-                                                     const int32_t* __restrict__ chunk_tri,
-                                                     const uint32_t* __restrict__ idx, float* __restrict__ grad_feats,
-                                                     float* __restrict__ grad_verts, bool accumulate) {
-    extern __shared__ float s_acc[];      // [G*G*C + 16]
-    const int64_t b = blockIdx.x;
-    if (b >= chunk_off[T]) return;        // the grid is sized by an upper bound of the chunk count
-    const int t = chunk_tri[b];
-    const int64_t ci = b - chunk_off[t];
-    const bool whole = chunk_off[t + 1] - chunk_off[t] == 1;
-    const int n_feat = G * G * C;
-    float* s_gv = s_acc + n_feat;
-    for (int k = threadIdx.x; k < n_feat + 16; k += blockDim.x) s_acc[k] = 0.0f;
-    __syncthreads();
-    const int64_t beg = tri_off[t] + ci * kChunkRecs<C>;
-    const int64_t end = min(tri_off[t + 1], beg + kChunkRecs<C>);
-    constexpr int NSEG = 256 / C;
-    const int c = threadIdx.x % C, seg = threadIdx.x / C;
-    const int64_t per = (end - beg + NSEG - 1) / NSEG;
-    const int64_t i0 = beg + seg * per, i1 = min(end, i0 + per);
-    float a00 = 0.f, a10 = 0.f, a01 = 0.f, a11 = 0.f;
-    int cur = -1;
-    auto flush = [&]() {
-        if (cur < 0) return;
-        const int ix = cur & 255, iy = cur >> 8;
-        const int t00 = (iy * G + ix) * C + c;
-        atomicAdd(&s_acc[t00], a00);
-        atomicAdd(&s_acc[t00 + C], a10);
-        atomicAdd(&s_acc[t00 + G * C], a01);
-        atomicAdd(&s_acc[t00 + G * C + C], a11);
-        a00 = a10 = a01 = a11 = 0.f;
-    };
-    constexpr int U = 4;   // records in flight per thread
-    for (int64_t i = i0; i < i1; i += U) {
-        uint32_t cells[U];
-        float fxs[U], fys[U], ds[U];
-        const float* recs[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) recs[u] = i + u < i1 ? records + static_cast<size_t>(idx[i + u]) * kRecStride<C> : nullptr;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (!recs[u]) continue;
-            cells[u] = __float_as_uint(recs[u][1]);
-            fxs[u] = recs[u][2];
-            fys[u] = recs[u][3];
-            ds[u] = recs[u][4 + c];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (!recs[u]) continue;
-            const int key = static_cast<int>(cells[u] & 0xFFFFu);
-            const float fx = fxs[u], fy = fys[u], d = ds[u];
-            if (key != cur) {
-                flush();
-                cur = key;
-            }
-            a00 = __builtin_fmaf((1.0f - fx) * (1.0f - fy), d, a00);
-            a10 = __builtin_fmaf(fx * (1.0f - fy), d, a10);
-            a01 = __builtin_fmaf((1.0f - fx) * fy, d, a01);
-            a11 = __builtin_fmaf(fx * fy, d, a11);
-            if (cells[u] >> 31)
-                for (int k = c; k < 9; k += C) atomicAdd(&s_gv[k], recs[u][4 + C + k]);
-        }
-    }
-    flush();
-    __syncthreads();
-    float* gf = grad_feats + static_cast<size_t>(t) * n_feat;
-    float* gv = grad_verts + static_cast<size_t>(t) * 9;
-    if (whole) {
-        for (int k = threadIdx.x; k < n_feat; k += blockDim.x) gf[k] = accumulate ? gf[k] + s_acc[k] : s_acc[k];
-        if (threadIdx.x < 9) gv[threadIdx.x] = accumulate ? gv[threadIdx.x] + s_gv[threadIdx.x] : s_gv[threadIdx.x];
-    } else {
-        for (int k = threadIdx.x; k < n_feat; k += blockDim.x)
-            if (s_acc[k] != 0.0f) atomicAdd(&gf[k], s_acc[k]);
-        if (threadIdx.x < 9 && s_gv[threadIdx.x] != 0.0f) atomicAdd(&gv[threadIdx.x], s_gv[threadIdx.x]);
-    }
-}
-
-void launch_bucket(const uint32_t* rec_tri, const unsigned long long* n_batch, int64_t bound,
-                   const int64_t* tri_off, int32_t* tri_fill, uint32_t* idx, hipStream_t s) {
-    if (bound <= 0) return;
-    hipLaunchKernelGGL(bucket_kernel, dim3(static_cast<unsigned>((bound + 255) / 256)), dim3(256), 0, s, rec_tri,
-                       n_batch, tri_off, tri_fill, idx);
-}
-
-template <int C>
-static void launch_reduce_c(const float* records, int G, int T, int64_t n_rec, const int64_t* tri_off,
-                            int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, int32_t* chunk_tri,
-                            const uint32_t* idx, float* grad_feats, float* grad_verts, bool accumulate,
-                            hipStream_t s) {
-    const int n_feat = G * G * C;
-    hipLaunchKernelGGL(reduce_prep_kernel<C>, dim3((T + 255) / 256), dim3(256), 0, s, tri_off, T, n_feat, chunk_n,
-                       grad_feats, grad_verts, accumulate);
-    launch_scan(chunk_n, T, chunk_bsum, chunk_off, s);
-    hipLaunchKernelGGL(chunk_map_kernel, dim3((T + 255) / 256), dim3(256), 0, s, chunk_off, T, chunk_tri);
-    const int64_t blocks = reduce_chunk_bound(C, T, n_rec);
-    const size_t lds = (static_cast<size_t>(n_feat) + 16) * sizeof(float);
-    hipLaunchKernelGGL(reduce_kernel<C>, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, s, records, G, T,
-                       tri_off, chunk_off, chunk_tri, idx, grad_feats, grad_verts, accumulate);
-}
-
-int64_t reduce_chunk_bound(int C, int T, int64_t n_rec) {
-    const int64_t K = 64 * (256 / C);
-    return T + n_rec / K + 1;   // >= sum over t of max(1, ceil(n_t / K))
-}
-
-void launch_reduce(const float* records, int C, int G, int T, int64_t n_rec, const int64_t* tri_off,
-                   int32_t* chunk_n, int64_t* chunk_bsum, int64_t* chunk_off, int32_t* chunk_tri,
-                   const uint32_t* idx, float* grad_feats, float* grad_verts, bool accumulate, hipStream_t s) {
-    if (T <= 0) return;
-    switch (C) {
-        case 8:
-            launch_reduce_c<8>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, chunk_tri, idx,
-                               grad_feats, grad_verts, accumulate, s);
-            break;
-        case 16:
-            launch_reduce_c<16>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, chunk_tri, idx,
-                                grad_feats, grad_verts, accumulate, s);
-            break;
-        case 32:
-            launch_reduce_c<32>(records, G, T, n_rec, tri_off, chunk_n, chunk_bsum, chunk_off, chunk_tri, idx,
-                                grad_feats, grad_verts, accumulate, s);
-            break;
-        default: break;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // edge term
 // ---------------------------------------------------------------------------
 

@@ -20,7 +20,7 @@ struct ReplayQueue {
     uint32_t pix[NW][128];
     uint32_t tri[NW][128];     // triangle | winner << 31
     float t[3][NW][128];       // beta_i / w_i
-    float beta[3][NW][128];    // screen barycentrics
+    float g[4][NW][128];       // the pixel's score weight and colour gradient
 };
 
 template <int TS>
@@ -57,6 +57,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
         uint64_t kc[PPT];
         bool act[PPT], front[PPT];
         uint32_t pix[PPT];
+        float gp[PPT][4];   // g_L, g_C of the pixel
         uint64_t wmax = 0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -66,6 +67,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
             front[k] = false;
             kc[k] = 0;
             pix[k] = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gp[k][i] = 0.0f;
             if (gx < W && gy < H) {
                 const int64_t p = vd.pix_base + static_cast<int64_t>(gy) * W + gx;
                 pix[k] = static_cast<uint32_t>(p);
@@ -74,10 +77,11 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                     act[k] = true;
                     front[k] = true;
                 } else {
-                    const float gl = (a.grad_logp && r.o.mode == 0) ? a.grad_logp[p] : 0.0f;
-                    act[k] = gl != 0.0f || a.grad_color[3 * p] != 0.0f || a.grad_color[3 * p + 1] != 0.0f ||
-                             a.grad_color[3 * p + 2] != 0.0f;
-                    front[k] = gl != 0.0f;
+                    gp[k][0] = (a.grad_logp && r.o.mode == 0) ? a.grad_logp[p] : 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) gp[k][1 + i] = a.grad_color[3 * p + i];
+                    act[k] = gp[k][0] != 0.0f || gp[k][1] != 0.0f || gp[k][2] != 0.0f || gp[k][3] != 0.0f;
+                    front[k] = gp[k][0] != 0.0f;
                 }
             }
             if (act[k]) wmax = kc[k] > wmax ? kc[k] : wmax;
@@ -93,11 +97,26 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
             __threadfence_block();
             const uint32_t at = cursor + static_cast<uint32_t>(lane);
             if (lane < n && at < a.region) {
+                float b1, b2;   // the perspective division, on full batches
+                persp_from_t(q.t[0][w][lane], q.t[1][w][lane], q.t[2][w][lane], b1, b2);
                 FragRec* f = a.frags + region_base + at;
-                f->a = make_uint4(q.pix[w][lane], q.tri[w][lane], __float_as_uint(q.t[0][w][lane]),
-                                  __float_as_uint(q.t[1][w][lane]));
-                f->b = make_uint4(__float_as_uint(q.t[2][w][lane]), __float_as_uint(q.beta[0][w][lane]),
-                                  __float_as_uint(q.beta[1][w][lane]), __float_as_uint(q.beta[2][w][lane]));
+                f->a = make_uint4(q.pix[w][lane], q.tri[w][lane], __float_as_uint(b1), __float_as_uint(b2));
+                f->b = make_uint4(__float_as_uint(q.g[0][w][lane]), __float_as_uint(q.g[1][w][lane]),
+                                  __float_as_uint(q.g[2][w][lane]), __float_as_uint(q.g[3][w][lane]));
+            }
+            // fragments per triangle, counting only those stored (one atomic
+            // per run of equal triangles)
+            if (a.tri_count) {
+                const bool stored = lane < n && at < a.region;
+                const uint32_t tk = stored ? (q.tri[w][lane] & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+                const uint32_t tp = __shfl_up(tk, 1, 64);
+                const bool head = lane == 0 || tp != tk;
+                const uint64_t heads = __ballot(head);
+                if (head && stored) {
+                    const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+                    const int endl = above ? __builtin_ctzll(above) : 64;   // the run ends at the next head
+                    atomicAdd(&a.tri_count[tk], endl - lane);
+                }
             }
             cursor += static_cast<uint32_t>(n);
         };
@@ -151,10 +170,9 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                             q.pix[w][pos] = pix[k];
                             q.tri[w][pos] = ch.tri[j] | (win ? 0x80000000u : 0u);
 #pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                q.t[i][w][pos] = f.beta[i] * ch.iw[i][j];
-                                q.beta[i][w][pos] = f.beta[i];
-                            }
+                            for (int i = 0; i < 3; ++i) q.t[i][w][pos] = f.beta[i] * ch.iw[i][j];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) q.g[i][w][pos] = gp[k][i];
                         }
                         qn += __popcll(mk);
                         if (qn >= 64) {
@@ -164,10 +182,9 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                                 q.pix[w][lane] = q.pix[w][64 + lane];
                                 q.tri[w][lane] = q.tri[w][64 + lane];
 #pragma unroll
-                                for (int i = 0; i < 3; ++i) {
-                                    q.t[i][w][lane] = q.t[i][w][64 + lane];
-                                    q.beta[i][w][lane] = q.beta[i][w][64 + lane];
-                                }
+                                for (int i = 0; i < 3; ++i) q.t[i][w][lane] = q.t[i][w][64 + lane];
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) q.g[i][w][lane] = q.g[i][w][64 + lane];
                             }
                             qn -= 64;
                             __threadfence_block();
@@ -247,6 +264,58 @@ __global__ __launch_bounds__(1024) void region_scan_kernel(const uint32_t* __res
 void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
                         unsigned long long* summary, unsigned int* sticky, hipStream_t s) {
     hipLaunchKernelGGL(region_scan_kernel, dim3(1), dim3(1024), 0, s, counts, n, region, boff, summary, sticky);
+}
+
+// Persistent waves take batches of the region list (as the logp decode
+// does); each fragment goes to sorted[tri_off[t] + k], k from a
+// per-triangle fill counter taken once per run of equal triangles.
+__global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
+    __shared__ uint32_t s_boff[kMaxRegions + 1];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i <= a.n_regions; i += blockDim.x) s_boff[i] = a.boff[i];
+    __syncthreads();
+    const uint32_t n_batch = s_boff[a.n_regions];
+    const uint32_t n_waves = gridDim.x * 4;
+    for (uint32_t bi = blockIdx.x * 4 + w; bi < n_batch; bi += n_waves) {
+        int lo = 0, hi = a.n_regions - 1;   // region: last w with boff[w] <= bi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_boff[mid] <= bi) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t cr = a.counts[lo];
+        const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
+        const bool on = in_region < (cr < a.region ? cr : a.region);
+        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = make_uint4(0u, 0u, 0u, 0u);
+        if (on) {
+            const FragRec& src = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
+            fa = src.a;
+            fb = src.b;
+        }
+        const uint32_t tri = on ? (fa.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+        const uint32_t tprev = __shfl_up(tri, 1, 64);
+        const bool head = lane == 0 || tprev != tri;
+        const uint64_t heads = __ballot(head);
+        int base = 0;
+        if (head && on) {
+            const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+            const int endl = above ? __builtin_ctzll(above) : 64;
+            base = atomicAdd(&a.tri_fill[tri], endl - lane);
+        }
+        const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
+        const int hl = 63 - __builtin_clzll(upto);   // lane 0 is always a head
+        const int hb = __shfl(base, hl, 64);
+        if (on) {
+            FragRec& dst = a.sorted[a.tri_off[tri] + hb + (lane - hl)];
+            dst.a = fa;
+            dst.b = fb;
+        }
+    }
+}
+
+void launch_place(const PlaceArgs& a, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
+    hipLaunchKernelGGL(place_kernel, dim3(a.n_blocks), dim3(256), 0, s, a);
 }
 
 int replay_waves_per_block(int tile) { return TileCfg<8>::NW * (tile == 8) + TileCfg<16>::NW * (tile != 8); }

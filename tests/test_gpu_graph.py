@@ -95,7 +95,7 @@ def test_graph_replay_matches_eager(tile):
         _say(f"replay {rep}: grads rel {_rel(got[3], ref[3]):.2e} {_rel(got[4], ref[4]):.2e} {_rel(got[5], ref[5]):.2e}")
         assert torch.equal(got[0], ref[0]), "visibility differs from the eager step"
         assert torch.equal(got[1], ref[1]), "colours differ from the eager step"
-        assert _rel(got[2], ref[2]) < 1e-6
+        assert _rel(got[2], ref[2]) < 1e-5   # the loss is a float-atomic sum over all pixels
         for k in (3, 4, 5):   # gradient sums: float atomics, order may differ
             assert _rel(got[k], ref[k]) < 1e-5
         # eager work between replays
