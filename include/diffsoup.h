@@ -118,8 +118,8 @@ enum {
     SOUP_T_SORT = 3,     /* per-tile depth sort */
     SOUP_T_FWD = 4,      /* forward raster */
     SOUP_T_BWD = 5,      /* backward fragment decode (MLP backward, gradient records) */
-    SOUP_T_EDGE = 6,     /* edge term */
-    SOUP_T_CHAIN = 7,    /* vertex chain */
+    SOUP_T_EDGE = 6,     /* per-pixel edge weights (the edge term joins the decode's vertex chain) */
+    SOUP_T_CHAIN = 7,    /* reserved (the vertex chain runs inside the backward decode) */
     SOUP_T_REDUCE = 8,   /* MLP-gradient reduction */
     SOUP_T_LOGP = 9,     /* log p(f*) pass (includes its replay and decode) */
     SOUP_T_LOSS = 10,    /* L2 loss */

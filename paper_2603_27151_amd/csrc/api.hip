@@ -31,7 +31,7 @@ struct soup_ctx {
     std::vector<char> desc_cache;    // descriptors of the last upload (static mode reuses them)
     std::string err;
     soup_stats stats{};
-    DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, vacc, partial, counters;
+    DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, edge_w, partial, counters;
     DevBuf tri_count, tri_fill, tri_off, tri_bsum, mlp_mid, frags, sorted;
     DevBuf region_counts, region_boff, flags;
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
@@ -427,7 +427,7 @@ void soup_ctx_destroy(soup_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&c->views,     &c->scenes,    &c->recs,          &c->tile_count,  &c->tile_fill,
-                      &c->tile_start, &c->bsum,      &c->entries,       &c->vacc,        &c->partial,
+                      &c->tile_start, &c->bsum,      &c->entries,       &c->edge_w,      &c->partial,
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
                       &c->flags};
@@ -529,8 +529,8 @@ int replay_blocks(soup_ctx* c, const Plan& p) {
 // the counts and the replay runs again, sized exactly. Returns the number of
 // fragments in *n_frag and of decode batches in *n_batch.
 soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64_t* vis, const float* grad_color,
-                   const float* grad_logp, bool all_front, int32_t* tri_count, int T, hipStream_t s,
-                   int64_t* n_frag, int64_t* n_batch) {
+                   const float* grad_logp, const float2* edge_w, bool all_front, int32_t* tri_count, int T,
+                   hipStream_t s, int64_t* n_frag, int64_t* n_batch) {
     if (p.n_pix >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "backward needs fewer than 2^32 pixels per call");
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     const int nb = replay_blocks(c, p);
@@ -552,6 +552,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         ra.vis = vis;
         ra.grad_color = grad_color;
         ra.grad_logp = grad_logp;
+        ra.edge_w = edge_w;
         ra.all_front = all_front ? 1 : 0;
         ra.frags = static_cast<FragRec*>(c->frags.p);
         ra.region = static_cast<uint32_t>(c->frag_region);
@@ -582,6 +583,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         ra.vis = vis;
         ra.grad_color = grad_color;
         ra.grad_logp = grad_logp;
+        ra.edge_w = edge_w;
         ra.all_front = all_front ? 1 : 0;
         ra.frags = static_cast<FragRec*>(c->frags.p);
         ra.region = static_cast<uint32_t>(region);
@@ -661,7 +663,8 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
             RasterArgs ra = a;
             ra.counter = nullptr;
             int64_t n_frag = 0, n_batch = 0;
-            if ((st = replay(c, p, ra, vis, nullptr, nullptr, true, nullptr, 0, s, &n_frag, &n_batch))) return st;
+            if ((st = replay(c, p, ra, vis, nullptr, nullptr, nullptr, true, nullptr, 0, s, &n_frag, &n_batch)))
+                return st;
             DecodeArgs d = decode_args(c, p, ra);
             d.logp = logp;
             launch_decode_bwd(d, p.kind, true, s);
@@ -691,7 +694,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     const int rows = nb * 4;
     const int T = scene->T;
     const int64_t n_grid = static_cast<int64_t>(scene->G) * scene->G * scene->C;
-    if ((st = ensure(c, c->vacc, static_cast<size_t>(p.n_recs) * kVacc * 4)) ||
+    if ((st = ensure(c, c->edge_w, static_cast<size_t>(p.n_pix) * sizeof(float2))) ||
         (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)) ||
         (st = ensure(c, c->mlp_mid, static_cast<size_t>(mlp_reduce_mid_rows(rows)) * p.n_params * 8)) ||
         (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
@@ -701,8 +704,14 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         return st;
     RasterArgs a = raster_args(c, p, o);
     const float* gl = o.mode == 0 ? grad_logp : nullptr;
+    const float2* ew = nullptr;
+    if (o.edge_pairs != 2) {
+        Timed t(c, SOUP_T_EDGE, s);
+        launch_edge_weights(a.views, a.V, p.n_pix, o, vis, color, grad_color, static_cast<float2*>(c->edge_w.p), s);
+        ew = static_cast<float2*>(c->edge_w.p);
+    }
     int64_t n_frag = 0, n_batch = 0;
-    if ((st = replay(c, p, a, vis, grad_color, gl, false, static_cast<int32_t*>(c->tri_count.p), T, s, &n_frag,
+    if ((st = replay(c, p, a, vis, grad_color, gl, ew, false, static_cast<int32_t*>(c->tri_count.p), T, s, &n_frag,
                      &n_batch)))
         return st;
     // the list sorted by triangle has at most as many entries as the regions hold
@@ -727,7 +736,6 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     }
     {
         Timed t(c, SOUP_T_FILL, s);
-        launch_fill_f32(static_cast<float*>(c->vacc.p), p.n_recs * kVacc, 0.0f, s);
         if (!o.accumulate) {
             launch_fill_f32(grad_feats, static_cast<int64_t>(T) * n_grid, 0.0f, s);
             launch_fill_f32(grad_verts, static_cast<int64_t>(T) * 9, 0.0f, s);
@@ -745,14 +753,6 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         launch_decode_bwd(d, p.kind, false, s);
     }
     HIP_TRY(c, hipGetLastError());
-    {
-        Timed t(c, SOUP_T_EDGE, s);
-        launch_edge(a.views, a.V, p.n_pix, o, vis, color, grad_color, a.recs, static_cast<float*>(c->vacc.p), s);
-    }
-    {
-        Timed t(c, SOUP_T_CHAIN, s);
-        launch_vertex_chain(a.views, a.V, a.scenes, T, a.recs, static_cast<float*>(c->vacc.p), grad_verts, s);
-    }
     {
         Timed t(c, SOUP_T_REDUCE, s);
         launch_mlp_reduce(static_cast<float*>(c->partial.p), rows, p.n_params, static_cast<double*>(c->mlp_mid.p),

@@ -14,7 +14,9 @@
 //     of a partial-sum buffer (rows are reduced later in a fixed order);
 //   - for the winner, the gradient of its triangle's world-space vertices,
 //     through the perspective-correct and screen barycentrics, the screen
-//     positions and 1/w, and the view-projection;
+//     positions and 1/w, and the view-projection; the edge term of Section
+//     3.2 (the pixel's edge weights times its screen barycentrics) joins it
+//     in screen space;
 //   - the feature gradient (bilinear weights of the four texels) and the
 //     vertex gradient are summed into the wave's LDS copy of the current
 //     triangle's G x G x C grid; when the triangle changes, the grid goes to
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
     };
     for (uint64_t bi = b_begin; bi < b_end; bi += b_step) {
         bool on;
-        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb4 = make_uint4(0u, 0u, 0u, 0u);
+        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb4 = make_uint4(0u, 0u, 0u, 0u), fc4 = make_uint4(0u, 0u, 0u, 0u);
         if (LOGP) {
             int lo = 0, hi = a.n_regions - 1;   // region: last w with boff[w] <= bi
             while (lo < hi) {
@@ -207,6 +209,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 const FragRec& fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
                 fa = fr.a;
                 fb4 = fr.b;
+                fc4 = fr.c;
             }
         } else {
             const int64_t fi = static_cast<int64_t>(bi) * 64 + lane;
@@ -215,6 +218,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 const FragRec& fr = a.sorted[fi];
                 fa = fr.a;
                 fb4 = fr.b;
+                fc4 = fr.c;
             }
         }
         const uint32_t pix = fa.x;
@@ -306,13 +310,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         // --- the winner's world-space vertex gradient ---
         float gw[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (win) {
-            int lo = 0, hi = a.V - 1;   // the view owning the pixel (views sorted by pix_base)
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (a.views[mid].pix_base <= static_cast<int64_t>(pix)) lo = mid;
-                else hi = mid - 1;
-            }
-            const ViewDesc& vd = a.views[lo];
+            const ViewDesc& vd = a.views[fc4.z];
             const TriRec& tr = a.recs[vd.rec_base + tri];
             const int W = vd.W, H = vd.H;
             const int64_t local = static_cast<int64_t>(pix) - vd.pix_base;
@@ -391,6 +389,14 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                     gsx[jv] += dbeta[i] * (dex - bi * dax) * inv_area;
                     gsy[jv] += dbeta[i] * (dey - bi * day) * inv_area;
                 }
+            }
+            // edge term (Section 3.2): the boundaries this pixel occludes move
+            // with its surface point, w beta_i e on the screen position of vertex i
+            const float ex = __uint_as_float(fc4.x), ey = __uint_as_float(fc4.y);
+#pragma unroll
+            for (int jv = 0; jv < 3; ++jv) {
+                gsx[jv] = __builtin_fmaf(ex, fb[jv], gsx[jv]);
+                gsy[jv] = __builtin_fmaf(ey, fb[jv], gsy[jv]);
             }
             // screen position and 1/w -> clip -> world through the view-projection
             const float hw = 0.5f * static_cast<float>(W), hh = 0.5f * static_cast<float>(H);

@@ -43,12 +43,14 @@ struct RasterArgs {
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 
-// One fragment the backward needs, 32 bytes: a = (pixel, triangle | winner << 31,
+// One fragment the backward needs, 48 bytes: a = (pixel, triangle | winner << 31,
 // perspective-correct b1, b2), b = (the pixel's score weight g_L and colour
-// gradient g_C[3]), so that the decode reads no per-pixel data.
+// gradient g_C[3]), c = (the pixel's edge weights in x and y, view, 0), so
+// that the decode reads no per-pixel data.
 struct FragRec {
     uint4 a;
     uint4 b;
+    uint4 c;
 };
 
 // The fragment list is split into one region of `region` entries per replay
@@ -62,6 +64,7 @@ struct ReplayArgs {
     const uint64_t* vis;
     const float* grad_color;       // [P,3] (null in the logp pass)
     const float* grad_logp;        // [P] or null
+    const float2* edge_w;          // [P] edge weights or null
     int all_front;                 // logp pass: every pixel needs its whole front set
     FragRec* frags;                // [n_regions * region]
     uint32_t region;
@@ -122,10 +125,9 @@ struct DecodeArgs {
 };
 
 void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp_pass, hipStream_t s);
-void launch_edge(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis, const float* color,
-                 const float* grad_color, const TriRec* recs, float* vacc, hipStream_t s);
-void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
-                         const float* vacc, float* grad_verts, hipStream_t s);
+// ew[p] = (x, y) edge weights of the pairs pixel p occludes (Section 3.2)
+void launch_edge_weights(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis,
+                         const float* color, const float* grad_color, float2* ew, hipStream_t s);
 void launch_mlp_reduce(const float* partial, int n_rows, int n_params, double* mid, float* out, bool accumulate,
                        hipStream_t s);
 int mlp_reduce_mid_rows(int n_rows);
@@ -135,6 +137,5 @@ void launch_selftest_sigmoid(const float* x, float* y, int64_t n, hipStream_t s)
 void launch_selftest_uniform(uint64_t seed, const uint32_t* pixel, const uint32_t* tri, uint32_t view_id,
                              uint32_t step, float* u, int64_t n, hipStream_t s);
 
-constexpr int kVacc = 16;          // floats per (view, triangle) in the edge-moment accumulator
 
 }  // namespace soup

@@ -1,7 +1,7 @@
-// Gradient reduction, edge term, vertex chain, MLP-gradient reduction, loss and
-// contract self-test kernels; dispatch of the backward fragment decode over
-// the compiled MLP shapes (the kernel is in decode_bwd_impl.hpp, instantiated
-// once per shape in dbwd_*.hip).
+// Per-pixel edge weights, MLP-gradient reduction, loss and contract self-test
+// kernels; dispatch of the backward fragment decode over the compiled MLP
+// shapes (the kernel is in decode_bwd_impl.hpp, instantiated once per shape in
+// dbwd_*.hip).
 #include "raster_common.hpp"
 
 namespace soup {
@@ -21,171 +21,67 @@ void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// edge term
+// edge term (Section 3.2), per pixel
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float wave_incl_sum(float v) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const float u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
-__global__ __launch_bounds__(256) void edge_kernel(const ViewDesc* __restrict__ views, int V, int64_t P, Opts o,
-                                                   const uint64_t* __restrict__ vis,
-                                                   const float* __restrict__ color,
-                                                   const float* __restrict__ gcol,
-                                                   const TriRec* __restrict__ recs, float* __restrict__ vacc) {
+// For each pixel p and direction e (x, then y): the sum of the pair weights
+// w = 1/2 (g_a + g_b) . (C_a - C_b) of the two adjacent pairs (p - e, p) and
+// (p, p + e) in which p is the occluder (the smaller key). The backward
+// decode adds w beta_i(p) e to the screen position of vertex i of p's winner
+// triangle, so that the edge term joins the winner's own vertex chain.
+__global__ __launch_bounds__(256) void edge_weight_kernel(const ViewDesc* __restrict__ views, int V, int64_t P,
+                                                          Opts o, const uint64_t* __restrict__ vis,
+                                                          const float* __restrict__ color,
+                                                          const float* __restrict__ gcol, float2* __restrict__ ew) {
     const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const bool inb = p < P;
+    if (p >= P) return;
     int lo = 0, hi = V - 1;
-    const int64_t pc = inb ? p : P - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].pix_base <= pc) lo = mid;
+        if (views[mid].pix_base <= p) lo = mid;
         else hi = mid - 1;
     }
     const ViewDesc& vd = views[lo];
-    const int64_t local = pc - vd.pix_base;
+    const int64_t local = p - vd.pix_base;
     const int x = static_cast<int>(local % vd.W), y = static_cast<int>(local / vd.W);
-    const uint64_t ka = vis[pc];
-    const float ca[3] = {color[3 * pc], color[3 * pc + 1], color[3 * pc + 2]};
-    const float ga[3] = {gcol[3 * pc], gcol[3 * pc + 1], gcol[3 * pc + 2]};
+    const uint64_t kp = vis[p];
+    float e[2] = {0.0f, 0.0f};
+    if (kp != kBgKey) {   // a background pixel never occludes
+        const float cp[3] = {color[3 * p], color[3 * p + 1], color[3 * p + 2]};
+        const float gp[3] = {gcol[3 * p], gcol[3 * p + 1], gcol[3 * p + 2]};
 #pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-        // this lane's pair (a, b = a + e): weight, occluder record and the occluder pixel
-        int64_t key = -1;
-        float wgt = 0.0f;
-        int xo = 0, yo = 0;
-        const int xb = x + (dir == 0), yb = y + (dir == 1);
-        if (inb && xb < vd.W && yb < vd.H) {
-            const int64_t q = pc + (dir == 0 ? 1 : vd.W);
-            const uint64_t kb = vis[q];
-            const bool skip = (ka == kBgKey && kb == kBgKey) ||
-                              (o.edge_pairs == 1 && ka != kBgKey && kb != kBgKey &&
-                               static_cast<uint32_t>(ka) == static_cast<uint32_t>(kb));
-            if (!skip) {
+        for (int dir = 0; dir < 2; ++dir) {
+            const int64_t step = dir == 0 ? 1 : vd.W;
+            const bool has_prev = dir == 0 ? x > 0 : y > 0;
+            const bool has_next = dir == 0 ? x + 1 < vd.W : y + 1 < vd.H;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) wgt += 0.5f * (ga[c] + gcol[3 * q + c]) * (ca[c] - color[3 * q + c]);
-                if (wgt != 0.0f) {
-                    const bool oa = ka < kb;
-                    key = vd.rec_base + static_cast<uint32_t>(oa ? ka : kb);
-                    xo = oa ? x : xb;
-                    yo = oa ? y : yb;
+            for (int side = 0; side < 2; ++side) {   // 0: pair (p - e, p); 1: pair (p, p + e)
+                if (side == 0 ? !has_prev : !has_next) continue;
+                const int64_t q = side == 0 ? p - step : p + step;
+                const uint64_t kq = vis[q];
+                // p must be the occluder: the smaller key, a tie going to the pair's second pixel
+                if (side == 0 ? kq < kp : !(kp < kq)) continue;
+                if (o.edge_pairs == 1 && kq != kBgKey && static_cast<uint32_t>(kq) == static_cast<uint32_t>(kp))
+                    continue;
+                float w = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float ca = side == 0 ? color[3 * q + c] : cp[c];
+                    const float cb = side == 0 ? cp[c] : color[3 * q + c];
+                    w += 0.5f * (gp[c] + gcol[3 * q + c]) * (ca - cb);
                 }
+                e[dir] += w;
             }
         }
-        // runs of consecutive lanes with the same occluder record: sums by
-        // prefix sums, one atomic per moment per run (issued by the run head)
-        // every lane takes part in the shuffles (no short-circuit around them)
-        const int64_t kprev = __shfl_up(key, 1, 64);
-        const int64_t knext = __shfl_down(key, 1, 64);
-        const bool head = key >= 0 && (lane == 0 || kprev != key);
-        const bool tail = key >= 0 && (lane == 63 || knext != key);
-        const uint64_t heads = __ballot(head);
-        const uint64_t ends = __ballot(tail);
-        const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
-        const int hl = upto ? 63 - __builtin_clzll(upto) : 0;
-        const int hx = __shfl(xo, hl, 64), hy = __shfl(yo, hl, 64);
-        const float v0 = wgt;
-        const float v1 = key >= 0 ? wgt * static_cast<float>(xo - hx) : 0.0f;
-        const float v2 = key >= 0 ? wgt * static_cast<float>(yo - hy) : 0.0f;
-        const float s0 = wave_incl_sum(v0), s1 = wave_incl_sum(v1), s2 = wave_incl_sum(v2);
-        // run [hl, end]: sum = S(end) - S(hl - 1); the run's end lane issues it
-        const float p0 = __shfl(s0, hl > 0 ? hl - 1 : 0, 64), p1 = __shfl(s1, hl > 0 ? hl - 1 : 0, 64),
-                    p2 = __shfl(s2, hl > 0 ? hl - 1 : 0, 64);
-        if (key >= 0 && ((ends >> lane) & 1ull)) {
-            const float r0 = s0 - (hl > 0 ? p0 : 0.0f);
-            const float r1 = s1 - (hl > 0 ? p1 : 0.0f);
-            const float r2 = s2 - (hl > 0 ? p2 : 0.0f);
-            // moments about vertex 0 of the occluding triangle
-            const int32_t X0 = recs[key].X[0], Y0 = recs[key].Y[0];
-            const float ox = static_cast<float>(kSnap * hx + kSnap / 2 - X0) * (1.0f / 256.0f);
-            const float oy = static_cast<float>(kSnap * hy + kSnap / 2 - Y0) * (1.0f / 256.0f);
-            float* va = vacc + static_cast<size_t>(key) * kVacc + 9 + 3 * dir;
-            atomicAdd(va + 0, r0);
-            atomicAdd(va + 1, r1 + ox * r0);
-            atomicAdd(va + 2, r2 + oy * r0);
-        }
     }
+    ew[p] = make_float2(e[0], e[1]);
 }
 
-void launch_edge(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis, const float* color,
-                 const float* grad_color, const TriRec* recs, float* vacc, hipStream_t s) {
-    if (P <= 0 || o.edge_pairs == 2) return;
-    hipLaunchKernelGGL(edge_kernel, dim3(static_cast<unsigned>((P + 255) / 256)), dim3(256), 0, s, views, V, P, o, vis,
-                       color, grad_color, recs, vacc);
-}
-
-// ---------------------------------------------------------------------------
-// vertex chain: screen-space accumulators -> world-space vertex gradients
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void vertex_chain_kernel(const ViewDesc* __restrict__ views, int V,
-                                                           const SceneDesc* __restrict__ scenes, int T,
-                                                           const TriRec* __restrict__ recs,
-                                                           const float* __restrict__ vacc,
-                                                           float* __restrict__ grad_verts) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    const float* vt = scenes[0].verts + static_cast<size_t>(t) * 9;
-    float g[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) g[i] = 0.0f;
-    for (int v = 0; v < V; ++v) {
-        const ViewDesc& vd = views[v];
-        const int64_t rec = vd.rec_base + t;
-        const TriRec R = recs[rec];
-        if (R.x0 > R.x1) continue;
-        const float* a = vacc + static_cast<size_t>(rec) * kVacc;
-        float gs[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-        // edge moments about vertex 0 -> screen gradients (beta affine in the pixel)
-        const float m[2][3] = {{a[9], a[10], a[11]}, {a[12], a[13], a[14]}};
-        if (m[0][0] != 0.f || m[0][1] != 0.f || m[0][2] != 0.f || m[1][0] != 0.f || m[1][1] != 0.f ||
-            m[1][2] != 0.f) {
-            const int64_t Ai = static_cast<int64_t>(R.X[1] - R.X[0]) * (R.Y[2] - R.Y[0]) -
-                               static_cast<int64_t>(R.Y[1] - R.Y[0]) * (R.X[2] - R.X[0]);
-            const float area = static_cast<float>(Ai) * (1.0f / 65536.0f);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int p = i == 2 ? 0 : i + 1, q = i == 0 ? 2 : (i == 1 ? 0 : 1);
-                const float dbx = -static_cast<float>(R.Y[q] - R.Y[p]) * (1.0f / 256.0f) / area;
-                const float dby = static_cast<float>(R.X[q] - R.X[p]) * (1.0f / 256.0f) / area;
-                const float b0 = i == 0 ? 1.0f : 0.0f;
-#pragma unroll
-                for (int dir = 0; dir < 2; ++dir) gs[i][dir] += m[dir][0] * b0 + m[dir][1] * dbx + m[dir][2] * dby;
-            }
-        }
-        const float hw = 0.5f * static_cast<float>(vd.W), hh = 0.5f * static_cast<float>(vd.H);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (gs[i][0] == 0.f && gs[i][1] == 0.f && gs[i][2] == 0.f) continue;
-            float c[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                c[j] = vd.M[4 * j + 3] + vd.M[4 * j] * vt[3 * i] + vd.M[4 * j + 1] * vt[3 * i + 1] +
-                       vd.M[4 * j + 2] * vt[3 * i + 2];
-            const float iw = 1.0f / c[3];
-            const float gc0 = gs[i][0] * hw * iw;
-            const float gc1 = -gs[i][1] * hh * iw;
-            const float gc3 = (-gs[i][0] * hw * c[0] + gs[i][1] * hh * c[1]) * iw * iw - gs[i][2] * iw * iw;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) g[3 * i + k] += vd.M[k] * gc0 + vd.M[4 + k] * gc1 + vd.M[12 + k] * gc3;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) grad_verts[static_cast<size_t>(t) * 9 + i] += g[i];
-}
-
-void launch_vertex_chain(const ViewDesc* views, int V, const SceneDesc* scenes, int T, const TriRec* recs,
-                         const float* vacc, float* grad_verts, hipStream_t s) {
-    if (T <= 0) return;
-    hipLaunchKernelGGL(vertex_chain_kernel, dim3((T + 255) / 256), dim3(256), 0, s, views, V, scenes, T, recs, vacc,
-                       grad_verts);
+void launch_edge_weights(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis,
+                         const float* color, const float* grad_color, float2* ew, hipStream_t s) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(edge_weight_kernel, dim3(static_cast<unsigned>((P + 255) / 256)), dim3(256), 0, s, views, V,
+                       P, o, vis, color, grad_color, ew);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,7 +20,7 @@ struct ReplayQueue {
     uint32_t pix[NW][128];
     uint32_t tri[NW][128];     // triangle | winner << 31
     float t[3][NW][128];       // beta_i / w_i
-    float g[4][NW][128];       // the pixel's score weight and colour gradient
+    float g[6][NW][128];       // the pixel's score weight, colour gradient and edge weights
 };
 
 template <int TS>
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
         uint64_t kc[PPT];
         bool act[PPT], front[PPT];
         uint32_t pix[PPT];
-        float gp[PPT][4];   // g_L, g_C of the pixel
+        float gp[PPT][6];   // g_L, g_C, edge weights (x, y) of the pixel
         uint64_t wmax = 0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
             kc[k] = 0;
             pix[k] = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) gp[k][i] = 0.0f;
+            for (int i = 0; i < 6; ++i) gp[k][i] = 0.0f;
             if (gx < W && gy < H) {
                 const int64_t p = vd.pix_base + static_cast<int64_t>(gy) * W + gx;
                 pix[k] = static_cast<uint32_t>(p);
@@ -80,7 +80,13 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                     gp[k][0] = (a.grad_logp && r.o.mode == 0) ? a.grad_logp[p] : 0.0f;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) gp[k][1 + i] = a.grad_color[3 * p + i];
-                    act[k] = gp[k][0] != 0.0f || gp[k][1] != 0.0f || gp[k][2] != 0.0f || gp[k][3] != 0.0f;
+                    if (a.edge_w) {
+                        const float2 e = a.edge_w[p];
+                        gp[k][4] = e.x;
+                        gp[k][5] = e.y;
+                    }
+                    act[k] = gp[k][0] != 0.0f || gp[k][1] != 0.0f || gp[k][2] != 0.0f || gp[k][3] != 0.0f ||
+                             gp[k][4] != 0.0f || gp[k][5] != 0.0f;
                     front[k] = gp[k][0] != 0.0f;
                 }
             }
@@ -103,6 +109,8 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                 f->a = make_uint4(q.pix[w][lane], q.tri[w][lane], __float_as_uint(b1), __float_as_uint(b2));
                 f->b = make_uint4(__float_as_uint(q.g[0][w][lane]), __float_as_uint(q.g[1][w][lane]),
                                   __float_as_uint(q.g[2][w][lane]), __float_as_uint(q.g[3][w][lane]));
+                f->c = make_uint4(__float_as_uint(q.g[4][w][lane]), __float_as_uint(q.g[5][w][lane]),
+                                  static_cast<uint32_t>(v), 0u);
             }
             // fragments per triangle, counting only those stored (one atomic
             // per run of equal triangles)
@@ -172,7 +180,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
 #pragma unroll
                             for (int i = 0; i < 3; ++i) q.t[i][w][pos] = f.beta[i] * ch.iw[i][j];
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) q.g[i][w][pos] = gp[k][i];
+                            for (int i = 0; i < 6; ++i) q.g[i][w][pos] = gp[k][i];
                         }
                         qn += __popcll(mk);
                         if (qn >= 64) {
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
 #pragma unroll
                                 for (int i = 0; i < 3; ++i) q.t[i][w][lane] = q.t[i][w][64 + lane];
 #pragma unroll
-                                for (int i = 0; i < 4; ++i) q.g[i][w][lane] = q.g[i][w][64 + lane];
+                                for (int i = 0; i < 6; ++i) q.g[i][w][lane] = q.g[i][w][64 + lane];
                             }
                             qn -= 64;
                             __threadfence_block();
@@ -286,11 +294,12 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
         const uint32_t cr = a.counts[lo];
         const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
         const bool on = in_region < (cr < a.region ? cr : a.region);
-        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = make_uint4(0u, 0u, 0u, 0u);
+        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = make_uint4(0u, 0u, 0u, 0u), fc = make_uint4(0u, 0u, 0u, 0u);
         if (on) {
             const FragRec& src = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
             fa = src.a;
             fb = src.b;
+            fc = src.c;
         }
         const uint32_t tri = on ? (fa.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
         const uint32_t tprev = __shfl_up(tri, 1, 64);
@@ -309,6 +318,7 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
             FragRec& dst = a.sorted[a.tri_off[tri] + hb + (lane - hl)];
             dst.a = fa;
             dst.b = fb;
+            dst.c = fc;
         }
     }
 }
