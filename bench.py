@@ -83,6 +83,7 @@ def main():
     target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
     ctx = R.context()
     opts = R.Opts(seed=wl.seed, step=wl.step)
+    opts_b = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1)   # the backward reuses the forward's tile lists
     P3 = (P, 3)
     vis = torch.empty(P, dtype=torch.int64, device=dev)
     color = torch.empty(P3, dtype=torch.float32, device=dev)
@@ -96,7 +97,7 @@ def main():
     def step():
         R.rasterize_fwd(ds, vs, opts, ctx=ctx, out=(vis, color, None))
         R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
-        R.rasterize_bwd(ds, vs, opts, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
+        R.rasterize_bwd(ds, vs, opts_b, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
 
     # tile size: given, or measured (every candidate runs the step)
     from paper_2603_27151_amd import autotune
@@ -119,7 +120,7 @@ def main():
     R.rasterize_fwd(ds, vs, opts, ctx=ctx, out=(vis, color, None))
     st_fwd = ctx.stats()
     R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
-    R.rasterize_bwd(ds, vs, opts, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
+    R.rasterize_bwd(ds, vs, opts_b, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
     st_bwd = ctx.stats()
     ctx.set_counting(False)
     torch.cuda.synchronize()

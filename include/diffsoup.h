@@ -80,6 +80,10 @@ typedef struct {
                                   triangle id differs; 2: no edge term */
     float near_w;              /* triangles with any vertex at clip w < near_w are culled (0.1) */
     int32_t accumulate;        /* backward: 0 overwrite the gradient outputs, 1 add into them */
+    int32_t reuse_bins;        /* backward: 1 = reuse the triangle setup and tile lists of the last
+                                  forward on this context when its views, scenes, tile size and near_w
+                                  are the same (else they are rebuilt); the caller guarantees that the
+                                  vertex data did not change in between. 0 = always rebuild. */
 } soup_opts;
 
 /* Work counts of the last compute call on a context (filled on request). */

@@ -37,7 +37,7 @@ class soup_views(C.Structure):
 class soup_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint32), ("mode", C.c_int32),
                 ("background", C.c_float * 3), ("edge_pairs", C.c_int32), ("near_w", C.c_float),
-                ("accumulate", C.c_int32)]
+                ("accumulate", C.c_int32), ("reuse_bins", C.c_int32)]
 
 
 class soup_stats(C.Structure):
@@ -153,9 +153,9 @@ def make_views(h: _Holder, widths, heights, view_ids, view_proj) -> soup_views:
 
 
 def make_opts(seed=0, step=0, mode=0, background=(0.0, 0.0, 0.0), edge_pairs=0, near_w=0.1,
-              accumulate=0) -> soup_opts:
+              accumulate=0, reuse_bins=0) -> soup_opts:
     return soup_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), int(mode), (C.c_float * 3)(*background),
-                     int(edge_pairs), float(near_w), int(accumulate))
+                     int(edge_pairs), float(near_w), int(accumulate), int(reuse_bins))
 
 
 class Ctx:

@@ -84,6 +84,7 @@ struct Opts {
     int32_t edge_pairs;
     float near_w;
     int32_t accumulate;
+    int32_t reuse_bins;
 };
 
 // --------------------------------------------------------------------------

@@ -79,10 +79,11 @@ class Opts:
     edge_pairs: int = 0        # 0 all pairs, 1 id change, 2 none
     near_w: float = 0.1
     accumulate: int = 0        # backward: 1 = add into the gradient outputs
+    reuse_bins: int = 0        # backward: 1 = reuse the last forward's setup and tile lists (same data)
 
     def c_struct(self) -> _lib.soup_opts:
         return _lib.make_opts(self.seed, self.step, self.mode, self.background, self.edge_pairs, self.near_w,
-                              self.accumulate)
+                              self.accumulate, self.reuse_bins)
 
 
 _ctx_cache = {}
@@ -181,7 +182,11 @@ class SoupRasterize(torch.autograd.Function):
         scene = DeviceScene(verts, feats, mlp, fctx.dims)
         if grad_color is None:
             grad_color = torch.zeros_like(color)
-        gv, gf, gm = rasterize_bwd(scene, fctx.views, fctx.opts, vis, color, grad_color, grad_logp)
+        # autograd refuses a backward whose saved tensors were modified in
+        # place, so the forward's setup and tile lists still describe these
+        # vertices (the library rebuilds them if another call intervened)
+        opts = dataclasses.replace(fctx.opts, reuse_bins=1)
+        gv, gf, gm = rasterize_bwd(scene, fctx.views, opts, vis, color, grad_color, grad_logp)
         return gv, gf, gm, None, None, None
 
 

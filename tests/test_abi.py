@@ -55,9 +55,10 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.soup_scene) == 16 + 4 * 8
     # soup_views: int32 (+pad) + 4 pointers
     assert ctypes.sizeof(_lib.soup_views) == 8 + 4 * 8
-    # soup_opts: u64, u32, i32, float[3], i32, float, i32 (+pad to 8)
-    assert ctypes.sizeof(_lib.soup_opts) == 40
+    # soup_opts: u64, u32, i32, float[3], i32, float, i32, i32
+    assert ctypes.sizeof(_lib.soup_opts) == 48
     assert _lib.soup_opts.accumulate.offset == 36
+    assert _lib.soup_opts.reuse_bins.offset == 40
     assert ctypes.sizeof(_lib.soup_stats) == 5 * 8
 
 

@@ -376,3 +376,32 @@ def test_autograd_function_matches_direct_calls():
     for a, b in ((verts.grad, gv), (feats.grad, gf), (mlp.grad, gm)):
         assert normwise(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
     assert abs(float(loss_d) - float(per_pix.sum())) < 1e-6
+
+
+def test_backward_reuses_forward_bins_only_when_valid():
+    """reuse_bins=1 gives the gradients of a rebuilding backward; when another
+    call on the context rebinned other views in between, the library
+    rebuilds instead of reusing."""
+    R = _raster()
+    from paper_2603_27151_amd import _lib
+    wl = W.batched(with_targets=True, n_views=4, T=20000)
+    _say("case: batched 4 views, 20000 triangles, reuse_bins")
+    ds = _dev_scene(wl.scene)
+    vs = _views(wl.views)
+    other = _views(W.batched(with_targets=False, n_views=2, T=20000).views)
+    target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).cuda()
+    ctx = _lib.Ctx(0)
+    o = _opts(wl.seed)
+    o_r = R.Opts(seed=wl.seed, reuse_bins=1)
+    vis, col, _ = R.rasterize_fwd(ds, vs, o, ctx=ctx)
+    _, gc, gl = R.loss_l2(col, target, ctx=ctx)
+    ref = R.rasterize_bwd(ds, vs, o, vis, col, gc, gl, ctx=ctx)
+    R.rasterize_fwd(ds, vs, o, ctx=ctx)
+    got = R.rasterize_bwd(ds, vs, o_r, vis, col, gc, gl, ctx=ctx)
+    R.rasterize_fwd(ds, other, o, ctx=ctx)          # rebins other views
+    got2 = R.rasterize_bwd(ds, vs, o_r, vis, col, gc, gl, ctx=ctx)
+    torch.cuda.synchronize()
+    for a, b, c in zip(ref, got, got2):
+        assert normwise(b.cpu().numpy(), a.cpu().numpy()) < 1e-5
+        assert normwise(c.cpu().numpy(), a.cpu().numpy()) < 1e-5
+    ctx.close()
