@@ -83,7 +83,8 @@ def main():
     target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
     ctx = R.context()
     opts = R.Opts(seed=wl.seed, step=wl.step)
-    opts_b = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1)   # the backward reuses the forward's tile lists
+    # the forward keeps its tile lists and a log of its decoded fragments; the backward reuses both
+    opts_b = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1)
     P3 = (P, 3)
     vis = torch.empty(P, dtype=torch.int64, device=dev)
     color = torch.empty(P3, dtype=torch.float32, device=dev)
@@ -95,7 +96,7 @@ def main():
     gm = torch.empty_like(ds.mlp)
 
     def step():
-        R.rasterize_fwd(ds, vs, opts, ctx=ctx, out=(vis, color, None))
+        R.rasterize_fwd(ds, vs, opts_b, ctx=ctx, out=(vis, color, None))
         R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
         R.rasterize_bwd(ds, vs, opts_b, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
 
@@ -117,7 +118,7 @@ def main():
 
     # work counts of the step (outside the timed region)
     ctx.set_counting(True)
-    R.rasterize_fwd(ds, vs, opts, ctx=ctx, out=(vis, color, None))
+    R.rasterize_fwd(ds, vs, opts_b, ctx=ctx, out=(vis, color, None))
     st_fwd = ctx.stats()
     R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
     R.rasterize_bwd(ds, vs, opts_b, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))

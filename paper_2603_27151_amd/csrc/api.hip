@@ -28,6 +28,14 @@ struct soup_ctx {
     bool counting = false;
     bool fixed = false;              // static-capacity mode: no synchronisation, no allocation
     bool flags_ready = false;        // sticky overflow flags cleared after allocation
+    // the forward's fragment log: region size and count, hint for the next,
+    // and the draws it was made with (valid only with bins_valid)
+    bool log_valid = false;
+    uint64_t log_region = 0, log_hint = 0;
+    int log_regions = 0;
+    uint64_t log_seed = 0;
+    uint32_t log_step = 0;
+    int log_mode = 0;
     // the setup records and tile lists in place: built for desc_cache, this tile size and near_w
     bool bins_valid = false;
     int bins_tile = 0;
@@ -38,6 +46,7 @@ struct soup_ctx {
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, edge_w, partial, counters;
     DevBuf tri_count, tri_fill, tri_off, tri_bsum, mlp_mid, frags, sorted;
     DevBuf region_counts, region_boff, flags;
+    DevBuf log_frag, log_aux, log_counts, log_boff;   // the forward's fragment log
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
@@ -292,6 +301,7 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     }
     const bool same = same_descriptors(c, p);
     c->bins_valid = false;
+    c->log_valid = false;
     if (c->fixed) {
         // a captured call must not depend on host memory at replay time
         if (!same) return fail(c, SOUP_ERR_INVALID, "static mode needs the views and scenes of the previous call");
@@ -372,6 +382,9 @@ RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     a.counter = c->counting ? cnt : nullptr;
     a.work = reinterpret_cast<unsigned int*>(cnt + 2);
+    const int wpb = c->tile == 8 ? 1 : 4;   // waves per forward workgroup
+    a.n_blocks = static_cast<int>(std::max<int64_t>(
+        1, std::min<int64_t>(std::min<int64_t>(static_cast<int64_t>(c->num_cus) * 4, kMaxRegions / wpb), p.n_tiles)));
     return a;
 }
 
@@ -445,7 +458,7 @@ void soup_ctx_destroy(soup_ctx* c) {
                       &c->tile_start, &c->bsum,      &c->entries,       &c->edge_w,      &c->partial,
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
-                      &c->flags};
+                      &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -537,48 +550,79 @@ int replay_blocks(soup_ctx* c, const Plan& p) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, p.n_tiles)));
 }
 
-// Backward, part 1: replay the fragments the backward needs into c->frags,
-// one region per replay wave, then scan the region counts into batch
-// offsets. Regions are sized from the last call's largest count with 50%
-// headroom (else from 1.5 fragments per pixel); an overflow is detected from
-// the counts and the replay runs again, sized exactly. Returns the number of
-// fragments in *n_frag and of decode batches in *n_batch.
+// Persistent grid of the decode kernel: 4 waves per workgroup, 4 workgroups per CU.
+int decode_blocks(soup_ctx* c) { return std::max(1, std::min(c->num_cus * 4, kMaxRegions / 4)); }
+
+// Backward, part 1: gather the fragments the backward needs into c->frags,
+// one region per wave, then scan the region counts into batch offsets. The
+// fragments come from the replay (coverage re-run from the tile lists) or,
+// when from_log, from the filter of the forward's log. Regions are sized
+// from the last call's largest count with 50% headroom (else from 1.5
+// fragments per pixel); an overflow is detected from the counts and the
+// gather runs again, sized exactly. Returns the number of fragments in
+// *n_frag and of decode batches in *n_batch.
 soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64_t* vis, const float* grad_color,
                    const float* grad_logp, const float2* edge_w, bool all_front, int32_t* tri_count, int T,
-                   hipStream_t s, int64_t* n_frag, int64_t* n_batch) {
+                   hipStream_t s, int64_t* n_frag, int64_t* n_batch, bool from_log = false) {
     if (p.n_pix >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "backward needs fewer than 2^32 pixels per call");
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
-    const int nb = replay_blocks(c, p);
-    const int nr = nb * replay_waves_per_block(c->tile);
+    const int nb = from_log ? decode_blocks(c) : replay_blocks(c, p);
+    const int nr = nb * (from_log ? 4 : replay_waves_per_block(c->tile));
     // per-wave counts vary between calls (tiles are handed out dynamically): 50% headroom
-    uint64_t region = c->region_hint ? c->region_hint + c->region_hint / 2 + 256
-                                     : (static_cast<uint64_t>(p.n_pix) * 3 / 2) / nr + 1024;
+    uint64_t hint = c->region_hint;
+    if (hint && c->frag_regions && c->frag_regions != nr) hint = hint * c->frag_regions / nr + 64;
+    uint64_t region = hint ? hint + hint / 2 + 256 : (static_cast<uint64_t>(p.n_pix) * 3 / 2) / nr + 1024;
     soup_status st;
     if ((st = ensure(c, c->region_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
         (st = ensure(c, c->region_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
         return st;
+    auto launch = [&](uint64_t reg) {
+        if (from_log) {
+            CollectArgs ca{};
+            ca.log_frag = static_cast<uint4*>(c->log_frag.p);
+            ca.log_aux = static_cast<uint2*>(c->log_aux.p);
+            ca.log_region = static_cast<uint32_t>(c->log_region);
+            ca.log_counts = static_cast<uint32_t*>(c->log_counts.p);
+            ca.log_boff = static_cast<uint32_t*>(c->log_boff.p);
+            ca.log_regions = c->log_regions;
+            ca.vis = vis;
+            ca.grad_color = grad_color;
+            ca.grad_logp = grad_logp;
+            ca.edge_w = edge_w;
+            ca.all_front = all_front ? 1 : 0;
+            ca.frags = static_cast<FragRec*>(c->frags.p);
+            ca.region = static_cast<uint32_t>(reg);
+            ca.counts = static_cast<uint32_t*>(c->region_counts.p);
+            ca.tri_count = tri_count;
+            ca.n_blocks = nb;
+            launch_collect(ca, s);
+        } else {
+            ReplayArgs ra{};
+            ra.r = a;
+            ra.vis = vis;
+            ra.grad_color = grad_color;
+            ra.grad_logp = grad_logp;
+            ra.edge_w = edge_w;
+            ra.all_front = all_front ? 1 : 0;
+            ra.frags = static_cast<FragRec*>(c->frags.p);
+            ra.region = static_cast<uint32_t>(reg);
+            ra.counts = static_cast<uint32_t*>(c->region_counts.p);
+            ra.tri_count = tri_count;
+            ra.n_blocks = nb;
+            launch_replay(ra, c->tile, s);
+        }
+        launch_region_scan(static_cast<uint32_t*>(c->region_counts.p), nr, static_cast<uint32_t>(reg),
+                           static_cast<uint32_t*>(c->region_boff.p), cnt + 4, static_cast<unsigned int*>(c->flags.p),
+                           s);
+    };
     if (c->fixed) {
         // the fragment list in place bounds the regions; an overflow is flagged
         if (c->frag_regions != nr || c->frag_region == 0)
-            return fail(c, SOUP_ERR_CAPACITY, "static mode: no fragment list sized for this tile; run the call "
-                        "once outside static mode");
-        ReplayArgs ra{};
-        ra.r = a;
-        ra.vis = vis;
-        ra.grad_color = grad_color;
-        ra.grad_logp = grad_logp;
-        ra.edge_w = edge_w;
-        ra.all_front = all_front ? 1 : 0;
-        ra.frags = static_cast<FragRec*>(c->frags.p);
-        ra.region = static_cast<uint32_t>(c->frag_region);
-        ra.counts = static_cast<uint32_t*>(c->region_counts.p);
-        ra.tri_count = tri_count;
-        ra.n_blocks = nb;
+            return fail(c, SOUP_ERR_CAPACITY, "static mode: no fragment list sized for this call; run it once "
+                        "outside static mode");
         launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
         if (tri_count) launch_fill_i32(tri_count, T, 0, s);
-        launch_replay(ra, c->tile, s);
-        launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4,
-                           static_cast<unsigned int*>(c->flags.p), s);
+        launch(c->frag_region);
         HIP_TRY(c, hipGetLastError());
         *n_frag = -1;
         *n_batch = static_cast<int64_t>(nr) * static_cast<int64_t>((c->frag_region + 63) / 64);   // upper bound
@@ -593,23 +637,9 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
             launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
             if (tri_count) launch_fill_i32(tri_count, T, 0, s);
         }
-        ReplayArgs ra{};
-        ra.r = a;
-        ra.vis = vis;
-        ra.grad_color = grad_color;
-        ra.grad_logp = grad_logp;
-        ra.edge_w = edge_w;
-        ra.all_front = all_front ? 1 : 0;
-        ra.frags = static_cast<FragRec*>(c->frags.p);
-        ra.region = static_cast<uint32_t>(region);
-        ra.counts = static_cast<uint32_t*>(c->region_counts.p);
-        ra.tri_count = tri_count;
-        ra.n_blocks = nb;
         {
             Timed t(c, SOUP_T_REPLAY, s);
-            launch_replay(ra, c->tile, s);
-            launch_region_scan(ra.counts, nr, ra.region, static_cast<uint32_t*>(c->region_boff.p), cnt + 4,
-                               static_cast<unsigned int*>(c->flags.p), s);
+            launch(region);
         }
         HIP_TRY(c, hipGetLastError());
         uint64_t* h = reinterpret_cast<uint64_t*>(c->host_stage);
@@ -627,9 +657,6 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     *n_batch = static_cast<int64_t>(summary[1]);
     return SOUP_OK;
 }
-
-// Persistent grid of the decode kernel: 4 waves per workgroup, 4 workgroups per CU.
-int decode_blocks(soup_ctx* c) { return std::max(1, c->num_cus * 4); }
 
 DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a) {
     DecodeArgs d{};
@@ -666,11 +693,59 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
     RasterArgs a = raster_args(c, p, o);
     a.vis = vis;
     a.color = color;
+    // reuse_bins: keep a log of the decoded fragments for the backward
+    const bool keep = o.reuse_bins != 0;
+    const int log_nr = a.n_blocks * (c->tile == 8 ? 1 : 4);
+    uint64_t log_region = 0;
+    if (keep) {
+        if (c->fixed) {
+            if (c->log_regions != log_nr || c->log_region == 0)
+                return fail(c, SOUP_ERR_CAPACITY, "static mode: no fragment log sized for this call; run it once "
+                            "outside static mode");
+            log_region = c->log_region;
+        } else {
+            log_region = c->log_hint ? c->log_hint + c->log_hint / 2 + 256
+                                     : (static_cast<uint64_t>(p.n_pix) * 2) / log_nr + 1024;
+            if (log_region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment log region too large");
+            if ((st = ensure(c, c->log_frag, static_cast<size_t>(log_region) * log_nr * sizeof(uint4))) ||
+                (st = ensure(c, c->log_aux, static_cast<size_t>(log_region) * log_nr * sizeof(uint2))) ||
+                (st = ensure(c, c->log_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
+                (st = ensure(c, c->log_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
+                return st;
+        }
+        a.log_frag = static_cast<uint4*>(c->log_frag.p);
+        a.log_aux = static_cast<uint2*>(c->log_aux.p);
+        a.log_region = static_cast<uint32_t>(log_region);
+        a.log_counts = static_cast<uint32_t*>(c->log_counts.p);
+    }
+    launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
     {
         Timed t(c, SOUP_T_FWD, s);
         launch_raster_fwd(a, c->tile, p.kind, s);
     }
     HIP_TRY(c, hipGetLastError());
+    if (keep) {
+        unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
+        // an eager call reads the largest count: an overflowing log is simply not
+        // used (the backward replays); in static mode the overflow is flagged
+        launch_region_scan(a.log_counts, log_nr, a.log_region, static_cast<uint32_t*>(c->log_boff.p), cnt + 4,
+                           c->fixed ? static_cast<unsigned int*>(c->flags.p) : nullptr, s);
+        HIP_TRY(c, hipGetLastError());
+        bool ok = true;
+        if (!c->fixed) {
+            uint64_t* h = reinterpret_cast<uint64_t*>(c->host_stage);
+            HIP_TRY(c, hipMemcpyAsync(h, cnt + 4, 24, hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            ok = h[2] <= log_region;
+            c->log_hint = h[2];
+        }
+        c->log_valid = ok;
+        c->log_region = log_region;
+        c->log_regions = log_nr;
+        c->log_seed = o.seed;
+        c->log_step = o.step;
+        c->log_mode = o.mode;
+    }
     if (logp) {
         Timed t(c, SOUP_T_LOGP, s);
         launch_fill_f32(logp, p.n_pix, 0.0f, s);
@@ -678,7 +753,8 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
             RasterArgs ra = a;
             ra.counter = nullptr;
             int64_t n_frag = 0, n_batch = 0;
-            if ((st = replay(c, p, ra, vis, nullptr, nullptr, nullptr, true, nullptr, 0, s, &n_frag, &n_batch)))
+            if ((st = replay(c, p, ra, vis, nullptr, nullptr, nullptr, true, nullptr, 0, s, &n_frag, &n_batch,
+                             keep && c->log_valid)))
                 return st;
             DecodeArgs d = decode_args(c, p, ra);
             d.logp = logp;
@@ -704,13 +780,18 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     if (!grad_verts || !grad_feats || !grad_mlp) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
     HIP_TRY(c, hipSetDevice(c->device));
     const Opts o = to_opts(opts);
+    bool reused = false;
     if (o.reuse_bins && c->bins_valid && c->bins_tile == c->tile && c->bins_near_w == o.near_w &&
         same_descriptors(c, p)) {
         // the last forward's setup records and tile lists are those of these inputs
         launch_fill_i32(static_cast<int32_t*>(c->counters.p), 16, 0, s);
+        reused = true;
     } else if ((st = bin(c, p, o, s))) {
         return st;
     }
+    // ... and its fragment log, if it was made with these draws
+    const bool from_log = reused && c->log_valid && c->log_seed == o.seed && c->log_step == o.step &&
+                          c->log_mode == o.mode;
     const int nb = decode_blocks(c);
     const int rows = nb * 4;
     const int T = scene->T;
@@ -733,7 +814,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     }
     int64_t n_frag = 0, n_batch = 0;
     if ((st = replay(c, p, a, vis, grad_color, gl, ew, false, static_cast<int32_t*>(c->tri_count.p), T, s, &n_frag,
-                     &n_batch)))
+                     &n_batch, from_log)))
         return st;
     // the list sorted by triangle has at most as many entries as the regions hold
     const int64_t frag_cap = static_cast<int64_t>(c->frag_regions) * static_cast<int64_t>(c->frag_region);
@@ -826,6 +907,7 @@ soup_status soup_render(soup_ctx* c, const soup_scene* scenes, int32_t R, const 
     RasterArgs a = raster_args(c, p, o);
     a.vis = nullptr;
     a.color = nullptr;
+    launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
     {
         Timed t(c, SOUP_T_FWD, s);
         launch_raster_fwd(a, c->tile, p.kind, s);

@@ -39,6 +39,13 @@ struct RasterArgs {
     float* color;
     unsigned long long* counter;   // decode counter or null
     unsigned int* work;            // persistent-kernel tile counter (zeroed by the launcher's caller)
+    int n_blocks;                  // persistent grid of the forward
+    // optional log of the forward's decoded fragments, one region per wave:
+    // log_frag = (pixel, triangle, b1, b2), log_aux = (depth bits, view)
+    uint4* log_frag;
+    uint2* log_aux;
+    uint32_t log_region;
+    uint32_t* log_counts;
 };
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
@@ -74,11 +81,36 @@ struct ReplayArgs {
 };
 
 void launch_replay(const ReplayArgs& a, int tile, hipStream_t s);
+
+// The same fragment list as the replay, filtered from the forward's log:
+// every fragment with key <= the pixel's winner key was decoded (and logged)
+// by the forward, since the forward's best key never drops below the winner's.
+struct CollectArgs {
+    const uint4* log_frag;
+    const uint2* log_aux;
+    uint32_t log_region;
+    const uint32_t* log_counts;    // [log_regions]
+    const uint32_t* log_boff;      // [log_regions + 1] batch offsets of the log
+    int log_regions;
+    const uint64_t* vis;
+    const float* grad_color;       // [P,3] (null in the logp pass)
+    const float* grad_logp;        // [P] or null
+    const float2* edge_w;          // [P] or null
+    int all_front;                 // logp pass
+    FragRec* frags;
+    uint32_t region;
+    uint32_t* counts;              // [n_blocks * 4]
+    int32_t* tri_count;            // [T] or null
+    int n_blocks;
+};
+
+void launch_collect(const CollectArgs& a, hipStream_t s);
 int replay_waves_per_block(int tile);
 
 // Batch offsets of the regions: boff[w] = sum over v < w of ceil(min(counts[v],
 // region) / 64), boff[n] = total batches; summary = (fragments, batches,
-// largest region count).
+// largest region count); an overflow sets kOverflowFragments in *sticky
+// (when not null).
 void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
                         unsigned long long* summary, unsigned int* sticky, hipStream_t s);
 

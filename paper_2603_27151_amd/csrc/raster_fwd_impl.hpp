@@ -2,7 +2,7 @@
 // Forward raster: stochastic opacity masking with a 64-bit depth|triangle
 // visibility buffer (Eq. (5); Supplement Algorithm A1, part 1).
 //
-// One workgroup per screen tile. The tile's triangle list (sorted by the
+// Persistent workgroups take screen tiles from a counter. A tile's triangle list (sorted by the
 // lower bound of their depth) is staged through LDS in chunks; every lane
 // tests its pixel(s) against each staged triangle with exact edge functions.
 // A fragment whose key is below the pixel's current best key is a candidate:
@@ -34,8 +34,20 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
     __shared__ uint64_t s_key[TS * TS];
     __shared__ float s_rgb[TS * TS * 3];
     __shared__ uint64_t s_wmax[NW];
+    __shared__ int64_t s_tile;
 
-    const int64_t tile = blockIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int G = a.G;
+    // optional log of every decoded fragment: this wave's region, private cursor
+    const uint64_t log_base = (static_cast<uint64_t>(blockIdx.x) * NW + w) * a.log_region;
+    uint32_t log_cursor = 0;   // wave-uniform
+
+    for (;;) {   // persistent: tiles from a counter
+    if (tid == 0) s_tile = static_cast<int64_t>(atomicAdd(a.work, 1u));
+    __syncthreads();
+    const int64_t tile = uniform_i64(s_tile);
+    __syncthreads();
+    if (tile >= a.n_tiles) break;
     const int v = view_of_tile(a.views, a.V, tile);
     const ViewDesc& vd = a.views[v];
     const int W = vd.W, H = vd.H;
@@ -46,8 +58,6 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
     gfloat* __restrict__ feats = as_global(uniform_ptr(sc.feats));
     const float* mlp_p = uniform_ptr(sc.mlp);
     const TriRec* __restrict__ recs = uniform_ptr(a.recs + vd.rec_base);
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int G = a.G;
 
     uint64_t kc[PPT];
 #pragma unroll
@@ -93,7 +103,17 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
                 pass = o[3] > 0.0f;
             }
             if (pass) atomicMin(reinterpret_cast<unsigned long long*>(&s_key[pl]), static_cast<unsigned long long>(key));
+            if (a.log_frag) {
+                const uint32_t at = log_cursor + static_cast<uint32_t>(lane);
+                if (at < a.log_region) {
+                    const int64_t pg = vd.pix_base + static_cast<int64_t>(ty0 + py_of<TS>(pl)) * W + tx0 + px_of<TS>(pl);
+                    a.log_frag[log_base + at] =
+                        make_uint4(static_cast<uint32_t>(pg), tri, __float_as_uint(b1), __float_as_uint(b2));
+                    a.log_aux[log_base + at] = make_uint2(static_cast<uint32_t>(key >> 32), static_cast<uint32_t>(v));
+                }
+            }
         }
+        if (a.log_frag) log_cursor += static_cast<uint32_t>(n);
         __threadfence_block();
         if (pass && s_key[pl] == key) {
             s_rgb[3 * pl + 0] = sigmoid_c(o[0]);
@@ -191,12 +211,14 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void raster_fwd_kernel(RasterArgs 
             col[2] = s_rgb[3 * pl + 2];
         }
     }
+    }   // tiles
+    if (a.log_counts && lane == 0) a.log_counts[blockIdx.x * NW + w] = log_cursor;
 }
 
 template <int TS, class S>
 static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
-    if (a.n_tiles <= 0) return;
-    hipLaunchKernelGGL((raster_fwd_kernel<TS, S>), dim3(static_cast<unsigned>(a.n_tiles)), dim3(TileCfg<TS>::NT), 0,
+    if (a.n_tiles <= 0 || a.n_blocks <= 0) return;
+    hipLaunchKernelGGL((raster_fwd_kernel<TS, S>), dim3(static_cast<unsigned>(a.n_blocks)), dim3(TileCfg<TS>::NT), 0,
                        s, a);
 }
 

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(1024) void region_scan_kernel(const uint32_t* __res
         summary[0] = s_tot[0];
         summary[1] = s_sum[1023];
         summary[2] = s_max[0];
-        if (s_max[0] > region) atomicOr(sticky, kOverflowFragments);
+        if (sticky && s_max[0] > region) atomicOr(sticky, kOverflowFragments);
     }
 }
 
@@ -326,6 +326,93 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
 void launch_place(const PlaceArgs& a, hipStream_t s) {
     if (a.n_blocks <= 0) return;
     hipLaunchKernelGGL(place_kernel, dim3(a.n_blocks), dim3(256), 0, s, a);
+}
+
+// Persistent waves take batches of the forward's log (region by region, as
+// the place kernel does) and keep the fragments the backward needs: the
+// pixel's winner (key == the saved key) when the pixel carries any upstream
+// gradient, and every fragment in front of it (key < the saved key) when it
+// carries a score weight. Kept fragments are compacted per batch and appended
+// to the wave's output region; per-triangle counts as in the replay.
+__global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
+    __shared__ uint32_t s_boff[kMaxRegions + 1];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i <= a.log_regions; i += blockDim.x) s_boff[i] = a.log_boff[i];
+    __syncthreads();
+    const uint32_t n_batch = s_boff[a.log_regions];
+    const uint32_t n_waves = gridDim.x * 4;
+    const uint32_t wid = blockIdx.x * 4 + w;
+    const uint64_t out_base = static_cast<uint64_t>(wid) * a.region;
+    uint32_t cursor = 0;   // wave-uniform
+    for (uint32_t bi = wid; bi < n_batch; bi += n_waves) {
+        int lo = 0, hi = a.log_regions - 1;   // region: last w with boff[w] <= bi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_boff[mid] <= bi) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t cr = a.log_counts[lo];
+        const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
+        const bool on = in_region < (cr < a.log_region ? cr : a.log_region);
+        bool keep = false, win = false;
+        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = make_uint4(0u, 0u, 0u, 0u), fc = make_uint4(0u, 0u, 0u, 0u);
+        if (on) {
+            const uint64_t at = static_cast<uint64_t>(lo) * a.log_region + in_region;
+            const uint4 e = a.log_frag[at];
+            const uint2 x = a.log_aux[at];
+            const uint64_t key = (static_cast<uint64_t>(x.x) << 32) | e.y;
+            const uint64_t kstar = a.vis[e.x];
+            win = key == kstar;
+            const bool front = key < kstar;
+            float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (a.all_front) {
+                keep = win || front;
+            } else {
+                if (a.grad_logp) g[0] = a.grad_logp[e.x];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) g[1 + i] = a.grad_color[3 * static_cast<size_t>(e.x) + i];
+                if (a.edge_w) {
+                    const float2 ew = a.edge_w[e.x];
+                    g[4] = ew.x;
+                    g[5] = ew.y;
+                }
+                const bool any = g[0] != 0.f || g[1] != 0.f || g[2] != 0.f || g[3] != 0.f || g[4] != 0.f || g[5] != 0.f;
+                keep = (win && any) || (front && g[0] != 0.0f);
+            }
+            fa = make_uint4(e.x, e.y | (win ? 0x80000000u : 0u), e.z, e.w);
+            fb = make_uint4(__float_as_uint(g[0]), __float_as_uint(g[1]), __float_as_uint(g[2]), __float_as_uint(g[3]));
+            fc = make_uint4(__float_as_uint(g[4]), __float_as_uint(g[5]), x.y, 0u);
+        }
+        const uint64_t km = __ballot(keep);
+        const uint32_t pos = cursor + static_cast<uint32_t>(__popcll(km & lanemask_lt()));
+        if (keep && pos < a.region) {
+            FragRec& d = a.frags[out_base + pos];
+            d.a = fa;
+            d.b = fb;
+            d.c = fc;
+        }
+        // fragments per triangle, counting only those stored (one atomic per
+        // run of equal triangles among consecutive lanes)
+        if (a.tri_count) {
+            const bool stored = keep && pos < a.region;
+            const uint32_t tk = stored ? (fa.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+            const uint32_t tp = __shfl_up(tk, 1, 64);
+            const bool head = lane == 0 || tp != tk;
+            const uint64_t heads = __ballot(head);
+            if (head && stored) {
+                const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+                const int endl = above ? __builtin_ctzll(above) : 64;
+                atomicAdd(&a.tri_count[tk], endl - lane);
+            }
+        }
+        cursor += static_cast<uint32_t>(__popcll(km));
+    }
+    if (lane == 0) a.counts[wid] = cursor;
+}
+
+void launch_collect(const CollectArgs& a, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
+    hipLaunchKernelGGL(collect_kernel, dim3(a.n_blocks), dim3(256), 0, s, a);
 }
 
 int replay_waves_per_block(int tile) { return TileCfg<8>::NW * (tile == 8) + TileCfg<16>::NW * (tile != 8); }

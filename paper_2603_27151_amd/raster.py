@@ -168,7 +168,9 @@ class SoupRasterize(torch.autograd.Function):
     @staticmethod
     def forward(fctx, verts, feats, mlp, dims, views: Views, opts: Opts):
         scene = DeviceScene(verts.contiguous(), feats.contiguous(), mlp.contiguous(), list(dims))
-        vis, color, logp = rasterize_fwd(scene, views, opts, want_logp=opts.mode == 0)
+        # keep the tile lists and the log of decoded fragments for the backward
+        vis, color, logp = rasterize_fwd(scene, views, dataclasses.replace(opts, reuse_bins=1),
+                                         want_logp=opts.mode == 0)
         if logp is None:
             logp = torch.zeros(color.shape[0], dtype=torch.float32, device=color.device)
         fctx.save_for_backward(scene.verts, scene.feats, scene.mlp, vis, color)

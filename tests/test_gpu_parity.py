@@ -405,3 +405,29 @@ def test_backward_reuses_forward_bins_only_when_valid():
         assert normwise(b.cpu().numpy(), a.cpu().numpy()) < 1e-5
         assert normwise(c.cpu().numpy(), a.cpu().numpy()) < 1e-5
     ctx.close()
+
+
+def test_backward_from_forward_log_matches_replay():
+    """A forward that keeps its fragment log (reuse_bins=1) lets the backward
+    filter the log instead of replaying coverage: same gradients, same log p."""
+    R = _raster()
+    from paper_2603_27151_amd import _lib
+    wl = W.batched(with_targets=True, n_views=4, T=20000)
+    _say("case: batched 4 views, 20000 triangles, backward from the forward's log")
+    ds = _dev_scene(wl.scene)
+    vs = _views(wl.views)
+    target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).cuda()
+    ctx = _lib.Ctx(0)
+    o = _opts(wl.seed)
+    o_k = R.Opts(seed=wl.seed, reuse_bins=1)
+    vis, col, lp = R.rasterize_fwd(ds, vs, o, want_logp=True, ctx=ctx)
+    _, gc, gl = R.loss_l2(col, target, ctx=ctx)
+    ref = R.rasterize_bwd(ds, vs, o, vis, col, gc, gl, ctx=ctx)
+    vis2, col2, lp2 = R.rasterize_fwd(ds, vs, o_k, want_logp=True, ctx=ctx)
+    got = R.rasterize_bwd(ds, vs, o_k, vis2, col2, gc, gl, ctx=ctx)
+    torch.cuda.synchronize()
+    assert torch.equal(vis, vis2) and torch.equal(col, col2)
+    assert normwise(lp2.cpu().numpy(), lp.cpu().numpy()) < 1e-6
+    for a, b in zip(ref, got):
+        assert normwise(b.cpu().numpy(), a.cpu().numpy()) < 1e-5
+    ctx.close()
