@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-per-view", action="store_true")
-    ap.add_argument("--cpu-pixels", type=float, default=1.5e6, help="oracle sample size in pixels")
+    ap.add_argument("--cpu-pixels", type=float, default=8e6, help="oracle sample size in pixels (about 10 s of host work)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="open-loop run at 200 req/s")
