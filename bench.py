@@ -41,6 +41,37 @@ def mlp_macs(dims):
     return int(sum(i * o for i, o in zip(dims[:-1], dims[1:])))
 
 
+def csrc_sha1() -> str:
+    """Hash of the kernel sources (matches profiles/traffic_batched.txt when unchanged)."""
+    import hashlib
+    root = os.path.join(ROOT, "paper_2603_27151_amd", "csrc")
+    h = hashlib.sha1()
+    for f in sorted(f for f in os.listdir(root) if f.endswith((".hip", ".hpp"))):
+        h.update(f.encode())
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, scaled by its copy-kernel calibration; None when the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_batched.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("csrc_sha1") != csrc_sha1() or f"{kernel}.fetch_kb" not in kv:
+        return None
+    return int(float(kv[f"{kernel}.fetch_kb"]) * 1024 * float(kv["fetch_scale"]) +
+               float(kv[f"{kernel}.write_kb"]) * 1024 * float(kv["write_scale"]))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +85,9 @@ def parse():
     ap.add_argument("--cpu-pixels", type=float, default=8e6, help="oracle sample size in pixels (about 10 s of host work)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first copy this many MiB device to device three times (a known-size kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="open-loop run at 200 req/s")
     ap.add_argument("--sweep-seconds", type=float, default=2.0, help="duration of each rate of the sweep")
     ap.add_argument("--serve-budget", type=float, default=0.25, help="admission budget: fraction of free HBM")
@@ -76,6 +110,14 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = W.by_name(args.workload)
     ds = R.DeviceScene.from_host(wl.scene)
     vs = R.Views.from_list(wl.views)
@@ -239,7 +281,7 @@ def main():
     achieved = fl / (t_dom * 1e-3) / 1e12
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(dom),
                 "flops_per_launch": fl, "avg_launch_ms": round(t_dom, 4)}
     step_flops = work["decode_bwd"] + work["raster_fwd"]
     step_roofline = {"flops": step_flops, "achieved_tflops": round(step_flops / (ms * 1e-3) / 1e12, 3),
