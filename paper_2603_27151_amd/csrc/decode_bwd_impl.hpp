@@ -26,7 +26,7 @@
 // lies in the region w with boff[w] <= b < boff[w + 1], found by a binary
 // search over the offsets staged in LDS) and sums log(1 - alpha) over the
 // front set and log(alpha) of the winner per pixel (log p(f*) of Eq. (6)).
-#include "raster_common.hpp"
+#include "decode_mfma.hpp"
 
 namespace soup {
 
@@ -37,8 +37,6 @@ struct StageCfg {
     static constexpr int kMax2(int a, int b) { return a > b ? a : b; }
     static constexpr int kWidth = kMax2(kMax2(S::C + S::H, 2 * S::H), S::H + 4);
 };
-
-typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Accumulators of one layer's weight gradient dW[DOUT][DIN] += sum_f d_f a_f^T
 // on the matrix cores: the contraction runs over fragments, four per
@@ -136,6 +134,8 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
     constexpr int SW = StageCfg<S>::kWidth;
     __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
     __shared__ uint32_t s_boff[LOGP ? kMaxRegions + 1 : 1];
+    __shared__ MfmaWeights<S> s_w;     // the MLP in the matrix cores' operand order (backward only)
+    __shared__ __align__(16) float s_dx[LOGP ? 1 : NW][LOGP ? 4 : 64 * S::C];   // the batch's feature gradients
     extern __shared__ float s_dyn[];   // [NW][G*G*C + 16]: per-wave gradient grid of the current triangle
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -148,6 +148,10 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         acc.l0.zero();
         if constexpr (S::NH == 2) acc.mid[0].zero();
         acc.out.zero();
+    }
+    if (!LOGP) {
+        s_w.load(a.mlp, tid, blockDim.x);
+        __syncthreads();
     }
     const uint64_t n_waves = static_cast<uint64_t>(gridDim.x) * NW;
     const uint64_t wid = static_cast<uint64_t>(blockIdx.x) * NW + w;
@@ -226,87 +230,142 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         const bool win = on && (fa.y >> 31);
         const float b1 = __uint_as_float(fa.z), b2 = __uint_as_float(fa.w);
         const Cell c = cell_of(b1, b2, G);
-        float x[S::C];
-        MlpAct<S> m;
-        if (on) {
-            fetch_feature<S::C>(feats, tri, G, c, x);
-        } else {
-#pragma unroll
-            for (int k = 0; k < S::C; ++k) x[k] = 0.0f;
-        }
-        // The weights are re-read from the scalar cache in every batch and in
-        // each of the forward and backward halves: an opaque copy of the
-        // pointer per use keeps the compiler from hoisting ~S::kParams scalar
-        // loads out of the loop (or sharing them between the halves), which
-        // would spill them all to VGPR lanes.
-        mlp_forward<S>(as_const(opaque_ptr(a.mlp)), x, m);
-        const float alpha = sigmoid_c(m.o[3]);
         const uint64_t on_mask = __ballot(on);
         if (a.counter && lane == 0) atomicAdd(a.counter, static_cast<unsigned long long>(__popcll(on_mask)));
         if (LOGP) {
+            float x[S::C];
+            MlpAct<S> m;
+            if (on) {
+                fetch_feature<S::C>(feats, tri, G, c, x);
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::C; ++k) x[k] = 0.0f;
+            }
+            // an opaque copy of the weight pointer per batch: the compiler may
+            // not hoist the weights' scalar loads out of the batch loop
+            mlp_forward<S>(as_const(opaque_ptr(a.mlp)), x, m);
+            const float alpha = sigmoid_c(m.o[3]);
             if (on) atomicAdd(&a.logp[pix], win ? logf(alpha) : log1pf(-alpha));
             continue;
         }
-        float d[4] = {0.f, 0.f, 0.f, 0.f};
-        if (on) {
-            const float gl = __uint_as_float(fb4.x);   // the pixel's score weight (0 without one)
-            if (win) {
-                const float gcol[3] = {__uint_as_float(fb4.y), __uint_as_float(fb4.z), __uint_as_float(fb4.w)};
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const float s = sigmoid_c(m.o[k]);
-                    d[k] = gcol[k] * s * (1.0f - s);
-                }
-                d[3] = gl * (1.0f - alpha);
-            } else {
-                d[3] = -gl * alpha;
-            }
-        }
-        // --- MLP backward, output layer first ---
-        cfloat* __restrict__ mlp = as_const(opaque_ptr(a.mlp));
         float* st = s_stage[w];
-        // transposed products run row by row (contiguous weight reads), which
-        // keeps each output's summation order: ascending row index
-        float dh[S::H];
+        const uint32_t cellw = static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 16);
+        {   // ---- the batch's MLP on the matrix cores, one 16-fragment block at a time ----
+            constexpr int CB = MfmaWeights<S>::CB, HB = MfmaWeights<S>::HB;
+            const int col = lane & 15, grp = lane >> 4;
+            const MfmaWeights<S>& Wt = s_w;
+            for (int nb = 0; nb < 4; ++nb) {   // fragment 16 nb + col
+                const int src = 16 * nb + col;
+                const bool on_n = __shfl(static_cast<int>(on), src, 64) != 0;
+                // inputs, unit-major: channels 16 cb + 4 grp .. + 3
+                f4v xin[CB];
+                {
+                    const uint32_t tri_n = static_cast<uint32_t>(__shfl(static_cast<int>(tri), src, 64));
+                    const uint32_t cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), src, 64));
+                    const float fx = __shfl(c.fx, src, 64), fy = __shfl(c.fy, src, 64);
+                    const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy), w01 = (1.0f - fx) * fy,
+                                w11 = fx * fy;
+                    const size_t t00 = ((static_cast<size_t>(tri_n) * G + (cw >> 16)) * G + (cw & 0xFFFFu)) * S::C;
 #pragma unroll
-        for (int k = 0; k < S::H; ++k) dh[k] = 0.0f;
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const int ch = 16 * cb + 4 * grp;
+                        f4v v = {0.f, 0.f, 0.f, 0.f};
+                        if (on_n && ch < S::C) {
+                            const float4 q00 = *reinterpret_cast<gfloat4*>(feats + t00 + ch);
+                            const float4 q10 = *reinterpret_cast<gfloat4*>(feats + t00 + S::C + ch);
+                            const float4 q01 = *reinterpret_cast<gfloat4*>(feats + t00 + static_cast<size_t>(G) * S::C + ch);
+                            const float4 q11 =
+                                *reinterpret_cast<gfloat4*>(feats + t00 + static_cast<size_t>(G + 1) * S::C + ch);
+                            v[0] = w00 * q00.x + w10 * q10.x + w01 * q01.x + w11 * q11.x;
+                            v[1] = w00 * q00.y + w10 * q10.y + w01 * q01.y + w11 * q11.y;
+                            v[2] = w00 * q00.z + w10 * q10.z + w01 * q01.z + w11 * q11.z;
+                            v[3] = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
+                        }
+                        xin[cb] = v;
+                    }
+                }
+                // forward
+                f4v h0[HB];
+                mfma_layer<HB, CB, true>(Wt.l0, Wt.b0, xin, h0, lane);
+                f4v h1[S::NH == 2 ? HB : 1];
+                if constexpr (S::NH == 2) mfma_layer<HB, HB, true>(Wt.l1, Wt.b1, h0, h1, lane);
+                const f4v (&hl)[HB] = *reinterpret_cast<const f4v (*)[HB]>(S::NH == 2 ? &h1[0] : &h0[0]);
+                // output layer and the logit gradients (Eq. (9) through the sigmoid for the score term)
+                float dO;   // lane group j: output j of the fragment
+                {
+                    f4v o = {Wt.bo[lane], 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            cfloat* Wr = mlp + S::w_off(S::NH) + jj * S::H;
+                    for (int ib = 0; ib < HB; ++ib) {
+                        const f4v wv = Wt.lo[ib][lane];
 #pragma unroll
-            for (int k = 0; k < S::H; ++k) dh[k] = __builtin_fmaf(Wr[k], d[jj], dh[k]);
-        }
+                        for (int s4 = 0; s4 < 4; ++s4) o = mfma4(wv[s4], hl[ib][s4], o);
+                    }
+                    const bool win_n = __shfl(static_cast<int>(win), src, 64) != 0;
+                    const float gl_n = __shfl(__uint_as_float(fb4.x), src, 64);
+                    const float g0 = __shfl(__uint_as_float(fb4.y), src, 64), g1 = __shfl(__uint_as_float(fb4.z), src, 64),
+                                g2 = __shfl(__uint_as_float(fb4.w), src, 64);
+                    const float sg = sigmoid_c(o[0]);
+                    float d;
+                    if (grp == 3) d = win_n ? gl_n * (1.0f - sg) : -gl_n * sg;
+                    else d = win_n ? (grp == 0 ? g0 : (grp == 1 ? g1 : g2)) * sg * (1.0f - sg) : 0.0f;
+                    dO = on_n ? d : 0.0f;
+                }
+                // output-layer weight gradient (rows = this block's fragments)
+                stage_rows<HB>(st, S::H, hl, lane);
+                st[kStageRows * S::H + col * 4 + grp] = dO;
+                __threadfence_block();
+                acc.out.accumulate(st, st + kStageRows * S::H, lane);
+                __threadfence_block();
+                // back through the output layer: K = the four outputs, one step
+                f4v dl[HB];
 #pragma unroll
-        for (int k = 0; k < S::H; ++k) dh[k] = m.h[S::NH - 1][k] > 0.0f ? dh[k] : 0.0f;
-        stage_accumulate<S::H, 4>(acc.out, st, m.h[S::NH - 1], d, lane);
-        // hidden layer 1 -> 0 (the compiled shapes have one or two hidden layers)
-        static_assert(S::NH == 1 || S::NH == 2, "one or two hidden layers");
-        if constexpr (S::NH == 2) {
-            float dprev[S::H];
+                for (int ob = 0; ob < HB; ++ob) {
+                    f4v v = mfma4(Wt.loT[ob][lane], dO, f4v{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-            for (int k = 0; k < S::H; ++k) dprev[k] = 0.0f;
+                    for (int i = 0; i < 4; ++i) v[i] = hl[ob][i] > 0.0f ? v[i] : 0.0f;
+                    dl[ob] = v;
+                }
+                f4v dh0[HB];
+                if constexpr (S::NH == 2) {
+                    // hidden layer 1 weight gradient, then back to layer 0
+                    stage_rows<HB>(st, S::H, h0, lane);
+                    stage_rows<HB>(st + kStageRows * S::H, S::H, dl, lane);
+                    __threadfence_block();
+                    acc.mid[0].accumulate(st, st + kStageRows * S::H, lane);
+                    __threadfence_block();
+                    mfma_back<HB, HB, true>(Wt.l1T, dl, h0, dh0, lane);
+                } else {
 #pragma unroll
-            for (int jj = 0; jj < S::H; ++jj) {
-                cfloat* Wr = mlp + S::w_off(1) + jj * S::H;
+                    for (int ob = 0; ob < HB; ++ob) dh0[ob] = dl[ob];
+                }
+                // first-layer weight gradient
+                stage_rows<CB>(st, S::C, xin, lane);
+                stage_rows<HB>(st + kStageRows * S::C, S::H, dh0, lane);
+                __threadfence_block();
+                acc.l0.accumulate(st, st + kStageRows * S::C, lane);
+                __threadfence_block();
+                // feature gradients into the rows [fragment][C] kept past the stage's working rows
+                f4v dxv[CB];
+                mfma_back<CB, HB, false>(Wt.l0T, dh0, nullptr, dxv, lane);
 #pragma unroll
-                for (int k = 0; k < S::H; ++k) dprev[k] = __builtin_fmaf(Wr[k], dh[jj], dprev[k]);
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int ch = 16 * cb + 4 * grp;
+                    if (ch < S::C)
+                        *reinterpret_cast<float4*>(s_dx[w] + (16 * nb + col) * S::C + ch) =
+                            make_float4(dxv[cb][0], dxv[cb][1], dxv[cb][2], dxv[cb][3]);
+                }
             }
-#pragma unroll
-            for (int k = 0; k < S::H; ++k) dprev[k] = m.h[0][k] > 0.0f ? dprev[k] : 0.0f;
-            stage_accumulate<S::H, S::H>(acc.mid[0], st, m.h[0], dh, lane);
-#pragma unroll
-            for (int k = 0; k < S::H; ++k) dh[k] = dprev[k];
+            __threadfence_block();
         }
-        float dx[S::C];
+        float dx[S::C];   // this lane's fragment
 #pragma unroll
-        for (int k = 0; k < S::C; ++k) dx[k] = 0.0f;
-#pragma unroll
-        for (int jj = 0; jj < S::H; ++jj) {
-            cfloat* Wr = mlp + S::w_off(0) + jj * S::C;
-#pragma unroll
-            for (int k = 0; k < S::C; ++k) dx[k] = __builtin_fmaf(Wr[k], dh[jj], dx[k]);
+        for (int k = 0; k < S::C; k += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(s_dx[w] + lane * S::C + k);
+            dx[k] = v.x;
+            dx[k + 1] = v.y;
+            dx[k + 2] = v.z;
+            dx[k + 3] = v.w;
         }
-        stage_accumulate<S::C, S::H>(acc.l0, st, x, dh, lane);
         // --- the winner's world-space vertex gradient ---
         float gw[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (win) {
@@ -417,11 +476,6 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         // channel), so that no two lanes of an LDS add share an address;
         // the winners' vertex gradients are summed over the run by a wave
         // reduction.
-        static_assert(kStageRows * SW >= 64 * S::C, "the stage holds the batch's feature gradients");
-#pragma unroll
-        for (int k = 0; k < S::C; k += 4)
-            *reinterpret_cast<float4*>(st + lane * S::C + k) = make_float4(dx[k], dx[k + 1], dx[k + 2], dx[k + 3]);
-        const uint32_t cellw = static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 16);
         __threadfence_block();
         const uint32_t tkey = on ? tri : 0xFFFFFFFFu;
         const uint32_t tprev = __shfl_up(tkey, 1, 64);
@@ -466,7 +520,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
 #pragma unroll
                     for (int pp = 0; pp < PPF; ++pp) {
                         const int k = (pp * 64 + (FPS > 1 ? lane % LPF : lane)) % S::C;
-                        dv[u][pp] = st[fs[u] * S::C + k];
+                        dv[u][pp] = s_dx[w][fs[u] * S::C + k];
                     }
                 }
 #pragma unroll

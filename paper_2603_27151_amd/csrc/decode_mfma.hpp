@@ -1,0 +1,168 @@
+#pragma once
+// The backward's MLP over a 64-fragment batch on the matrix cores
+// (v_mfma_f32_16x16x4f32): recompute, data backward and weight gradient.
+//
+// Operand layout of the instruction (lane l, col = l & 15, grp = l >> 4): the
+// lane supplies A[col][grp] and B[grp][col] (K = 4 runs over the four lane
+// groups) and holds D[4 grp + i][col], i = 0..3.
+//
+// Activations are kept unit-major: an f4v act[ub][nb] holds units
+// 16 ub + 4 grp + i of fragment 16 nb + col. A layer out = W in runs as
+// D = W act with the contraction over input units split in steps of four,
+// step s of input block ib taking unit 16 ib + 4 grp + s in lane group grp;
+// the B operand of step s is then register s of the previous layer's D, so
+// layers chain without moving data between lanes, and the A operand is the
+// weight W[16 ob + col][16 ib + 4 grp + s] (pre-arranged in LDS, four steps
+// per 16-byte read). The output layer puts output j on row 4 j of a padded
+// 16-row block, so that lane group j holds output j of every fragment, which
+// is exactly the B operand of the first backward product (K = the 4 outputs).
+// Weight gradients contract over fragments, the other index; activations and
+// deltas are staged through LDS as rows, 16 fragments at a time.
+//
+// The backward needs no bit-exact forward (only the forward's mask decision
+// is fixed by the contract), so the recompute may sum in the matrix cores'
+// order.
+#include "raster_common.hpp"
+
+namespace soup {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Weights and biases of one MLP in the A-operand arrangement, per lane.
+template <class S>
+struct MfmaWeights {
+    static constexpr int CB = (S::C + 15) / 16;   // channel blocks
+    static constexpr int HB = S::H / 16;          // hidden-unit blocks
+    static constexpr int MB = S::NH == 2 ? HB : 1;
+    f4v l0[HB][CB][64];      // W0[16 ob + col][16 ib + 4 grp + s]
+    f4v l1[MB][MB][64];      // W1[16 ob + col][16 ib + 4 grp + s]
+    f4v lo[HB][64];          // padded output block: row 4 j = W_out[j][16 ib + 4 grp + s]
+    float loT[HB][64];       // W_out[grp][16 ob + col]
+    f4v l1T[MB][MB][64];     // W1[16 ib + 4 grp + s][16 ob + col]
+    f4v l0T[CB][HB][64];     // W0[16 ib + 4 grp + s][16 cb + col]
+    f4v b0[HB][64];          // b0[16 ob + 4 grp + i]
+    f4v b1[MB][64];          // b1[16 ob + 4 grp + i]
+    float bo[64];            // b_out[grp]
+
+    // Cooperative fill by the whole workgroup from the flat parameter array.
+    __device__ void load(const float* __restrict__ p, int tid, int nt) {
+        const float* W0 = p + S::w_off(0);
+        const float* B0 = p + S::b_off(0);
+        const float* WO = p + S::w_off(S::NH);
+        const float* BO = p + S::b_off(S::NH);
+        for (int e = tid; e < HB * CB * 64; e += nt) {
+            const int l = e & 63, ib = (e >> 6) % CB, ob = (e >> 6) / CB, col = l & 15, grp = l >> 4;
+            f4v v, t;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * ib + 4 * grp + s;
+                v[s] = k < S::C ? W0[(16 * ob + col) * S::C + k] : 0.0f;
+            }
+            l0[ob][ib][l] = v;
+            // transposed: output block = channel block ib (as cb), input block = ob (as unit block)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int u = 16 * ob + 4 * grp + s, ch = 16 * ib + col;
+                t[s] = ch < S::C ? W0[u * S::C + ch] : 0.0f;
+            }
+            l0T[ib][ob][l] = t;
+        }
+        for (int e = tid; e < HB * 64; e += nt) {
+            const int l = e & 63, b = e >> 6, col = l & 15, grp = l >> 4;
+            f4v v, bb;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * b + 4 * grp + s;
+                v[s] = (col & 3) == 0 ? WO[(col >> 2) * S::H + k] : 0.0f;
+                bb[s] = B0[16 * b + 4 * grp + s];
+            }
+            lo[b][l] = v;
+            b0[b][l] = bb;
+            loT[b][l] = WO[grp * S::H + 16 * b + col];
+        }
+        if constexpr (S::NH == 2) {
+            const float* W1 = p + S::w_off(1);
+            const float* B1 = p + S::b_off(1);
+            for (int e = tid; e < HB * HB * 64; e += nt) {
+                const int l = e & 63, ib = (e >> 6) % HB, ob = (e >> 6) / HB, col = l & 15, grp = l >> 4;
+                f4v v, t;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    v[s] = W1[(16 * ob + col) * S::H + 16 * ib + 4 * grp + s];
+                    t[s] = W1[(16 * ib + 4 * grp + s) * S::H + 16 * ob + col];
+                }
+                l1[ob][ib][l] = v;
+                l1T[ob][ib][l] = t;
+            }
+            for (int e = tid; e < HB * 64; e += nt) {
+                const int l = e & 63, b = e >> 6, grp = l >> 4;
+                f4v bb;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) bb[s] = B1[16 * b + 4 * grp + s];
+                b1[b][l] = bb;
+            }
+        }
+        for (int e = tid; e < 64; e += nt) bo[e] = BO[e >> 4];
+    }
+};
+
+// One 16-fragment block: out[ob] = act(bias + W in), IB input blocks, OB
+// output blocks.
+template <int OB, int IB, bool RELU>
+__device__ __forceinline__ void mfma_layer(const f4v (*w)[IB][64], const f4v (*bias)[64], const f4v (&in)[IB],
+                                           f4v (&out)[OB], int lane) {
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+        f4v acc = bias[ob][lane];
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) {
+            const f4v wv = w[ob][ib][lane];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = mfma4(wv[s], in[ib][s], acc);
+        }
+        if (RELU) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = acc[i] > 0.0f ? acc[i] : 0.0f;
+        }
+        out[ob] = acc;
+    }
+}
+
+// One 16-fragment block: d_in[ob] = (W^T d_out), masked by act > 0 when MASK.
+template <int OB, int IB, bool MASK>
+__device__ __forceinline__ void mfma_back(const f4v (*wT)[IB][64], const f4v (&d_out)[IB], const f4v* mask,
+                                          f4v (&d_in)[OB], int lane) {
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+        f4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) {
+            const f4v wv = wT[ob][ib][lane];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = mfma4(wv[s], d_out[ib][s], acc);
+        }
+        if (MASK) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = mask[ob][i] > 0.0f ? acc[i] : 0.0f;
+        }
+        d_in[ob] = acc;
+    }
+}
+
+// The 16 rows of one fragment block into an LDS stage laid out [row][D]
+// (D = n_units): lane (grp, col) writes its four units of row col.
+template <int NBLK>
+__device__ __forceinline__ void stage_rows(float* __restrict__ st, int D, const f4v (&v)[NBLK], int lane) {
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        const int u = 16 * b + 4 * grp;
+        if (u < D) *reinterpret_cast<float4*>(st + col * D + u) = make_float4(v[b][0], v[b][1], v[b][2], v[b][3]);
+    }
+}
+
+}  // namespace soup
