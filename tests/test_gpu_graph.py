@@ -54,12 +54,12 @@ class _Step:
         return [t.clone() for t in (self.vis, self.col, self.loss, self.gv, self.gf, self.gm)]
 
 
-@pytest.mark.parametrize("tile", [8, 16])
-def test_graph_replay_matches_eager(tile):
+@pytest.mark.parametrize("tile,reuse", [(8, 0), (16, 0), (16, 1)])
+def test_graph_replay_matches_eager(tile, reuse):
     from paper_2603_27151_amd import _lib
     from paper_2603_27151_amd import raster as R
     wl = W.batched(with_targets=True, n_views=6, T=20000)
-    _say(f"case: batched 6 views, 20000 triangles, tile {tile}")
+    _say(f"case: batched 6 views, 20000 triangles, tile {tile}, reuse_bins {reuse}")
     ds = R.DeviceScene.from_host(wl.scene)
     vs = R.Views.from_list(wl.views)
     target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).cuda()
@@ -68,7 +68,8 @@ def test_graph_replay_matches_eager(tile):
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        step = _Step(R, ctx, ds, vs, R.Opts(seed=wl.seed, step=wl.step), target)
+        # reuse = 1: the forward keeps its tile lists and fragment log for the backward
+        step = _Step(R, ctx, ds, vs, R.Opts(seed=wl.seed, step=wl.step, reuse_bins=reuse), target)
         step()   # eager: sizes every workspace
         step()
         torch.cuda.synchronize()
