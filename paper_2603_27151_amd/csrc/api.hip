@@ -44,6 +44,7 @@ struct soup_ctx {
     std::string err;
     soup_stats stats{};
     DevBuf views, scenes, recs, tile_count, tile_fill, tile_start, bsum, entries, edge_w, partial, counters;
+    DevBuf chunk_base;   // [binning chunks][tiles] first slot of a chunk in each tile list
     DevBuf tri_count, tri_fill, tri_off, tri_bsum, mlp_mid, frags, sorted;
     DevBuf region_counts, region_boff, flags;
     DevBuf log_frag, log_aux, log_counts, log_boff;   // the forward's fragment log
@@ -286,10 +287,14 @@ bool same_descriptors(const soup_ctx* c, const Plan& p) {
 soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     const size_t vbytes = p.views.size() * sizeof(ViewDesc), sbytes = p.scenes.size() * sizeof(SceneDesc);
     soup_status st;
+    // the forward counts its 8x8 blocks in 32 bits
+    if (p.n_tiles * (c->tile / 8) * (c->tile / 8) >= (int64_t(1) << 32))
+        return fail(c, SOUP_ERR_CAPACITY, "too many pixels in one call (2^32 8x8 blocks)");
     if ((st = ensure(c, c->views, vbytes)) || (st = ensure(c, c->scenes, sbytes)) ||
         (st = ensure(c, c->recs, static_cast<size_t>(p.n_recs) * sizeof(TriRec))) ||
         (st = ensure(c, c->tile_count, static_cast<size_t>(p.n_tiles) * 4)) ||
         (st = ensure(c, c->tile_fill, static_cast<size_t>(p.n_tiles) * 4)) ||
+        (st = ensure(c, c->chunk_base, static_cast<size_t>(bin_chunks(p.maxT)) * p.n_tiles * 4)) ||
         (st = ensure(c, c->tile_start, static_cast<size_t>(p.n_tiles + 1) * 8)) ||
         (st = ensure(c, c->bsum, static_cast<size_t>((p.n_tiles + 1023) / 1024 + 1) * 8)) ||
         (st = ensure(c, c->counters, 64)) || (st = ensure(c, c->flags, 256)) ||
@@ -326,7 +331,8 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     Timed t_setup(c, SOUP_T_SETUP, s);
     launch_setup(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT,
                  static_cast<SceneDesc*>(c->scenes.p), o, c->tile, static_cast<TriRec*>(c->recs.p),
-                 static_cast<int32_t*>(c->tile_count.p), c->counting ? cnt + 1 : nullptr, s);
+                 static_cast<int32_t*>(c->tile_count.p), static_cast<int32_t*>(c->chunk_base.p), p.n_tiles,
+                 c->counting ? cnt + 1 : nullptr, s);
     }
     {
         Timed t(c, SOUP_T_SCAN, s);
@@ -351,8 +357,9 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
         Timed t(c, SOUP_T_SCATTER, s);
         launch_fill_i32(static_cast<int32_t*>(c->tile_fill.p), p.n_tiles, 0, s);
         launch_scatter(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, c->tile,
-                       static_cast<TriRec*>(c->recs.p), static_cast<int64_t*>(c->tile_start.p),
-                       static_cast<int32_t*>(c->tile_fill.p), static_cast<uint64_t*>(c->entries.p), s);
+                       static_cast<TriRec*>(c->recs.p), static_cast<int64_t*>(c->tile_start.p), p.n_tiles,
+                       static_cast<int32_t*>(c->chunk_base.p), static_cast<int32_t*>(c->tile_fill.p),
+                       static_cast<uint64_t*>(c->entries.p), s);
     }
     {
         Timed t(c, SOUP_T_SORT, s);
@@ -382,9 +389,10 @@ RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     a.counter = c->counting ? cnt : nullptr;
     a.work = reinterpret_cast<unsigned int*>(cnt + 2);
-    const int wpb = c->tile == 8 ? 1 : 4;   // waves per forward workgroup
-    a.n_blocks = static_cast<int>(std::max<int64_t>(
-        1, std::min<int64_t>(std::min<int64_t>(static_cast<int64_t>(c->num_cus) * 4, kMaxRegions / wpb), p.n_tiles)));
+    // the forward's workgroups are single waves, one 8x8 block of a tile at a time: as many as are resident
+    const int64_t items = p.n_tiles * (c->tile / 8) * (c->tile / 8);
+    const int64_t resident = static_cast<int64_t>(c->num_cus) * raster_fwd_blocks_per_cu(c->tile, p.kind);
+    a.n_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(resident, kMaxRegions), items)));
     return a;
 }
 
@@ -458,7 +466,8 @@ void soup_ctx_destroy(soup_ctx* c) {
                       &c->tile_start, &c->bsum,      &c->entries,       &c->edge_w,      &c->partial,
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
-                      &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff};
+                      &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff,
+                      &c->chunk_base};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -695,7 +704,7 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
     a.color = color;
     // reuse_bins: keep a log of the decoded fragments for the backward
     const bool keep = o.reuse_bins != 0;
-    const int log_nr = a.n_blocks * (c->tile == 8 ? 1 : 4);
+    const int log_nr = a.n_blocks;   // one log region per forward wave
     uint64_t log_region = 0;
     if (keep) {
         if (c->fixed) {

@@ -28,10 +28,12 @@ constexpr int kMaxViews = 1 << 16;
 using cfloat = const float __attribute__((address_space(4)));
 using gfloat = const float __attribute__((address_space(1)));
 using gfloat4 = const float4 __attribute__((address_space(1)));
+using guint4 = const uint4 __attribute__((address_space(1)));
 #else
 using cfloat = const float;
 using gfloat = const float;
 using gfloat4 = const float4;
+using guint4 = const uint4;
 #endif
 
 __device__ __forceinline__ cfloat* as_const(const float* p) {
@@ -39,6 +41,9 @@ __device__ __forceinline__ cfloat* as_const(const float* p) {
 }
 __device__ __forceinline__ gfloat* as_global(const float* p) {
     return reinterpret_cast<gfloat*>(reinterpret_cast<uintptr_t>(p));
+}
+__device__ __forceinline__ guint4* as_global(const uint4* p) {
+    return reinterpret_cast<guint4*>(reinterpret_cast<uintptr_t>(p));
 }
 
 // Per-view descriptor (device copy built by the host for every call).

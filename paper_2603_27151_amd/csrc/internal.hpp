@@ -7,11 +7,19 @@ namespace soup {
 
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// Binning works on chunks of kBinChunk triangles per view; a view with at most
+// kHistBins tiles is counted in LDS, and chunk_base ([chunks][tiles] int32)
+// receives each chunk's first slot in every tile list it touches.
+constexpr int kBinChunk = 4096;
+constexpr int kHistBins = 8192;
+int bin_chunks(int maxT);
 void launch_setup(const ViewDesc* views, int V, int maxT, const SceneDesc* scenes, const Opts& o, int tile,
-                  TriRec* recs, int32_t* tile_count, unsigned long long* visible, hipStream_t s);
+                  TriRec* recs, int32_t* tile_count, int32_t* chunk_base, int64_t n_tiles,
+                  unsigned long long* visible, hipStream_t s);
 void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipStream_t s);
 void launch_scatter(const ViewDesc* views, int V, int maxT, int tile, const TriRec* recs,
-                    const int64_t* tile_start, int32_t* tile_fill, uint64_t* entries, hipStream_t s);
+                    const int64_t* tile_start, int64_t n_tiles, const int32_t* chunk_base, int32_t* tile_fill,
+                    uint64_t* entries, hipStream_t s);
 void launch_sort(const int64_t* tile_start, int64_t n_tiles, uint64_t* entries, hipStream_t s);
 void launch_clip(int64_t* tile_start, int64_t n_tiles, int64_t cap, unsigned int* local, unsigned int* sticky,
                  hipStream_t s);
@@ -39,8 +47,8 @@ struct RasterArgs {
     float* color;
     unsigned long long* counter;   // decode counter or null
     unsigned int* work;            // persistent-kernel tile counter (zeroed by the launcher's caller)
-    int n_blocks;                  // persistent grid of the forward
-    // optional log of the forward's decoded fragments, one region per wave:
+    int n_blocks;                  // persistent grid of the forward (single-wave workgroups)
+    // optional log of the forward's decoded fragments, one region per wave (= workgroup):
     // log_frag = (pixel, triangle, b1, b2), log_aux = (depth bits, view)
     uint4* log_frag;
     uint2* log_aux;
@@ -49,6 +57,8 @@ struct RasterArgs {
 };
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
+// Resident single-wave workgroups per CU of the forward kernel for a tile side and MLP shape.
+int raster_fwd_blocks_per_cu(int tile, MlpKind k);
 
 // One fragment the backward needs, 48 bytes: a = (pixel, triangle | winner << 31,
 // perspective-correct b1, b2), b = (the pixel's score weight g_L and colour

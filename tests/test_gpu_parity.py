@@ -223,6 +223,25 @@ def test_ragged_views_and_multiview():
         _fwd_bwd_case(wl, tile=tile, check_bwd=(tile == 16))
 
 
+def test_tile_list_longer_than_sort_block():
+    """3000 large triangles cover every pixel of a 32x32 view, so every tile
+    list is longer than one sort block (lists are sorted block by block) and,
+    with a low opacity, every pixel walks deep into its list."""
+    wl = W.tiny()
+    rng = np.random.default_rng(2048)
+    T = 3000
+    centres = W.uniform_ball(rng, T, 0.5)
+    ang = rng.uniform(0.0, 2.0 * np.pi, T)[:, None] + np.array([0.0, 2.0 * np.pi / 3.0, 4.0 * np.pi / 3.0])
+    verts = np.stack([4.0 * np.cos(ang), 4.0 * np.sin(ang), rng.uniform(-0.2, 0.2, (T, 3))], axis=2)
+    verts = (verts + centres[:, None, :]).astype(np.float32)
+    wl.scene = W.random_scene(rng, verts, 4, 8, [8, 16, 4])
+    wl.scene.mlp[-1] = -3.0          # opacity bias: about one fragment in twenty passes
+    wl.views = [W.View(32, 32, 3, W.view_proj((0.0, 0.0, 3.0), 32, 32))]
+    wl.targets = None
+    for tile in (8, 16, 32):
+        _fwd_bwd_case(wl, tile=tile, check_bwd=(tile == 16))
+
+
 def test_empty_and_culled_scenes():
     R = _raster()
     wl = W.tiny()
