@@ -287,9 +287,9 @@ bool same_descriptors(const soup_ctx* c, const Plan& p) {
 soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     const size_t vbytes = p.views.size() * sizeof(ViewDesc), sbytes = p.scenes.size() * sizeof(SceneDesc);
     soup_status st;
-    // the forward counts its 8x8 blocks in 32 bits
-    if (p.n_tiles * (c->tile / 8) * (c->tile / 8) >= (int64_t(1) << 32))
-        return fail(c, SOUP_ERR_CAPACITY, "too many pixels in one call (2^32 8x8 blocks)");
+    // the forward counts its regions in 32 bits
+    if (p.n_tiles * fwd_regions_per_tile(c->tile) >= (int64_t(1) << 32))
+        return fail(c, SOUP_ERR_CAPACITY, "too many pixels in one call (2^32 forward regions)");
     if ((st = ensure(c, c->views, vbytes)) || (st = ensure(c, c->scenes, sbytes)) ||
         (st = ensure(c, c->recs, static_cast<size_t>(p.n_recs) * sizeof(TriRec))) ||
         (st = ensure(c, c->tile_count, static_cast<size_t>(p.n_tiles) * 4)) ||
@@ -389,8 +389,9 @@ RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     a.counter = c->counting ? cnt : nullptr;
     a.work = reinterpret_cast<unsigned int*>(cnt + 2);
-    // the forward's workgroups are single waves, one 8x8 block of a tile at a time: as many as are resident
-    const int64_t items = p.n_tiles * (c->tile / 8) * (c->tile / 8);
+    // the forward's workgroups are single waves, one region of a tile at a time (16x16 pixels, 8x8 for
+    // 8-pixel tiles): as many as are resident
+    const int64_t items = p.n_tiles * fwd_regions_per_tile(c->tile);
     const int64_t resident = static_cast<int64_t>(c->num_cus) * raster_fwd_blocks_per_cu(c->tile, p.kind);
     a.n_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(resident, kMaxRegions), items)));
     return a;

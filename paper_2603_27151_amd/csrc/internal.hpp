@@ -59,6 +59,8 @@ struct RasterArgs {
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 // Resident single-wave workgroups per CU of the forward kernel for a tile side and MLP shape.
 int raster_fwd_blocks_per_cu(int tile, MlpKind k);
+// The forward's unit of work: a 16x16 region of a tile (8x8 for 8-pixel tiles).
+inline int fwd_regions_per_tile(int tile) { return tile >= 16 ? (tile / 16) * (tile / 16) : 1; }
 
 // One fragment the backward needs, 48 bytes: a = (pixel, triangle | winner << 31,
 // perspective-correct b1, b2), b = (the pixel's score weight g_L and colour

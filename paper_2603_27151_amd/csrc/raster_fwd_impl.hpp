@@ -2,26 +2,31 @@
 // Forward raster: stochastic opacity masking with a 64-bit depth|triangle
 // visibility buffer (Eq. (5); Supplement Algorithm A1, part 1).
 //
-// One wave is one workgroup and owns one 8x8 pixel block of a screen tile at a
-// time, taken from a counter (persistent), so no barrier ever waits for
-// another wave. It walks the tile's triangle list (sorted by a lower bound of
-// their depth) in three steps:
-//  - scan, lanes over list entries: an entry whose bounding box touches the
-//    block and whose depth bound can beat a pixel is appended (in list order)
-//    to a queue of waiting entries;
-//  - coverage, lanes over 64 waiting triangles: each computes its triangle's
-//    exact 64-pixel coverage mask of the block from its float64 edge
-//    functions (every value an exact integer); covering triangles leave their
+// One wave is one workgroup and owns one region of a screen tile at a time
+// (16x16 pixels, four 8x8 blocks; 8x8 for 8-pixel tiles), taken from a
+// counter (persistent, the next region fetched while the current one runs),
+// so no barrier ever waits for another wave. It walks the tile's triangle
+// list (sorted by a lower bound of their depth) in three steps, all in one
+// loop with uniform control flow:
+//  - scan, lanes over list entries: each entry whose bounding box touches a
+//    block of the region, and whose depth bound can still beat a pixel of
+//    that block, appends one (triangle, block) pair per such block to a queue
+//    of waiting pairs, in list order;
+//  - coverage, lanes over 64 waiting pairs: each computes the exact 64-pixel
+//    coverage mask of its triangle over its block from float64 edge
+//    functions (every value an exact integer); covering pairs leave their
 //    edge and vertex data in the wave's LDS;
-//  - fragments, lanes over pixels: the covering triangles are visited in list
-//    order; each covered pixel computes its fragment's key, and a fragment
-//    whose key is below the pixel's current best is a candidate, compacted
-//    (ballot + prefix count) into an LDS queue.
+//  - fragments, lanes over the pixels of a block: the covering pairs are
+//    visited in list order; each covered pixel computes its fragment's key,
+//    and a fragment whose key is below the pixel's current best is a
+//    candidate, compacted (ballot + prefix count) into an LDS queue together
+//    with its perspective-correct barycentrics.
 // The queue is decoded 64 candidates at a time, one per lane, so the
 // expensive texture + MLP decode always runs on full waves. A decoded
 // fragment that passes its draw lowers the pixel's key with an LDS 64-bit
-// atomicMin; the lane holding the pixel's minimum then stores its colour.
-// Entries whose depth bound is already behind every pixel of the block are
+// atomicMin; the lane holding the pixel's minimum then writes its colour to
+// the output (a later, nearer passing fragment overwrites it).
+// Entries whose depth bound is already behind every pixel of a block are
 // skipped, and the walk stops once the rest of the list is behind every
 // pixel: front-to-back early-out without sorting fragments. The result does
 // not depend on the visiting order (the draws are fixed by Philox), only the
@@ -30,24 +35,27 @@
 
 namespace soup {
 
-// LDS of one wave.
+// LDS of one wave owning NB 8x8 blocks.
+template <int NB>
 struct FwdWaveLds {
-    // triangles of the current 64-entry slice that cover a pixel of the block
+    // the current slice: (triangle, block) pairs that cover a pixel of their block
     double e0[3][64];    // orientation-normalised edge functions at the block's first pixel centre
-    double ea[3][64];    // ... step per pixel in x
-    double eb[3][64];    // ... step per pixel in y
+    int32_t ndx[3][64];  // ... whose steps per pixel are -256 ndy in x and 256 ndx in y
+    int32_t ndy[3][64];
     float z[3][64];      // vertex depths
     float iw[3][64];     // 1 / w at the vertices
     float ra[64];        // 1 / |2 x area|
-    // list entries waiting for the coverage phase (in list order)
-    uint64_t pend[128];
+    // (triangle, block) pairs waiting for the coverage step, in list order: a ring of
+    // kRing slots (at most 63 wait when a scan of 64 entries appends up to 64 NB more)
+    static constexpr int kRing = 64 * (NB + 1);
+    uint32_t ptri[kRing];
+    uint8_t pblk[kRing];
     // candidate queue
     uint64_t qkey[128];
-    float qt[3][128];    // beta_i / w_i
-    uint32_t qpl[128];   // pixel of the block
-    // the block's pixels
-    uint64_t key[64];
-    float rgb[3][64];
+    float qb[2][128];    // perspective-correct barycentrics b1, b2
+    uint16_t qpl[128];   // pixel of the region: block * 64 + pixel of the block
+    // the region's pixels: current best key (their colours go straight to the output)
+    uint64_t key[64 * NB];
 };
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
@@ -56,41 +64,80 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+__device__ __forceinline__ int wave_incl_scan_i32(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Element b of a small register array, as masks: a chain of selects of
+// array elements would be folded back into an indexed load, which puts the
+// array in scratch memory.
+template <int N>
+__device__ __forceinline__ uint64_t pick(const uint64_t (&arr)[N], int b) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r |= arr[i] & (0ull - static_cast<uint64_t>(b == i));
+    return r;
+}
+
 template <int TS, class S>
-__global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
-    constexpr int BX = TS / 8, BPT = BX * BX;   // 8x8 blocks per tile
-    __shared__ FwdWaveLds L;
+__global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
+    constexpr int RS = TS >= 16 ? 16 : 8;          // side of the region a wave owns
+    constexpr int BR = RS / 8, NB = BR * BR;       // 8x8 blocks per region
+    constexpr int RT = TS / RS, RPT = RT * RT;     // regions per tile
+    __shared__ FwdWaveLds<NB> L;
     const int lane = threadIdx.x;
-    const int pu = lane & 7, pv = lane >> 3;    // the lane's pixel in the block
+    const int pu = lane & 7, pv = lane >> 3;       // the lane's pixel in a block
+    const double fx = static_cast<double>(pu), fy = static_cast<double>(pv);
     const int G = a.G;
-    const uint64_t n_items = static_cast<uint64_t>(a.n_tiles) * BPT;
+    const uint64_t n_items = static_cast<uint64_t>(a.n_tiles) * RPT;
     // optional log of every decoded fragment: this wave's region, private cursor
     const uint64_t log_base = static_cast<uint64_t>(blockIdx.x) * a.log_region;
     uint32_t log_cursor = 0;   // wave-uniform
+    int vcur = 0;              // view of the previous region, and its tiles [vlo, vhi)
+    int64_t vlo = 0, vhi = 0;
+    uint32_t next = 0;
+    if (lane == 0) next = atomicAdd(a.work, 1u);
 
-    for (;;) {   // persistent: blocks from a counter
-    uint32_t taken = 0;
-    if (lane == 0) taken = atomicAdd(a.work, 1u);
-    const uint64_t item = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(taken)));
+    for (;;) {   // persistent: regions from a counter
+    const uint64_t item = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(next)));
     if (item >= n_items) break;
-    const int64_t tile = static_cast<int64_t>(item / BPT);
-    const int blk = static_cast<int>(item % BPT);
-    const int v = view_of_tile(a.views, a.V, tile);
+    if (lane == 0) next = atomicAdd(a.work, 1u);   // the following region, fetched while this one runs
+    const int64_t tile = static_cast<int64_t>(item / RPT);
+    const int rq = static_cast<int>(item % RPT);
+    if (tile < vlo || tile >= vhi) {
+        vcur = view_of_tile(a.views, a.V, tile);
+        vlo = a.views[vcur].tile_base;
+        vhi = vcur + 1 < a.V ? a.views[vcur + 1].tile_base : a.n_tiles;
+    }
+    const int v = vcur;
     const ViewDesc& vd = a.views[v];
     const int W = vd.W, H = vd.H;
     const int64_t tl = tile - vd.tile_base;
-    const int bx = static_cast<int>(tl % vd.tiles_x) * TS + (blk % BX) * 8;
-    const int by = static_cast<int>(tl / vd.tiles_x) * TS + (blk / BX) * 8;
-    if (bx >= W || by >= H) continue;   // a block of a ragged tile that lies outside the view
+    const int rx = static_cast<int>(tl % vd.tiles_x) * TS + (rq % RT) * RS;
+    const int ry = static_cast<int>(tl / vd.tiles_x) * TS + (rq / RT) * RS;
+    if (rx >= W || ry >= H) continue;   // a region of a ragged tile that lies outside the view
     const SceneDesc sc = a.scenes[vd.scene];
     gfloat* __restrict__ feats = as_global(uniform_ptr(sc.feats));
     const float* mlp_p = uniform_ptr(sc.mlp);
     const TriRec* __restrict__ recs = uniform_ptr(a.recs + vd.rec_base);
 
-    const bool inview = bx + pu < W && by + pv < H;
-    uint64_t kc = inview ? kBgKey : 0ull;   // pixels outside the view never take fragments
-    L.key[lane] = kc;
-    uint64_t wmax = wave_max_u64(kc);
+    uint64_t kc[NB];     // this lane's pixel of every block: current best key
+    uint64_t wmaxb[NB];  // per block: the largest best key of its pixels (wave-uniform)
+    uint64_t wmax = 0;   // ... over the region
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const bool inview = rx + (b % BR) * 8 + pu < W && ry + (b / BR) * 8 + pv < H;
+        kc[b] = inview ? kBgKey : 0ull;   // pixels outside the view never take fragments
+        L.key[b * 64 + lane] = kc[b];
+        wmaxb[b] = wave_max_u64(kc[b]);
+        wmax = wmaxb[b] > wmax ? wmaxb[b] : wmax;
+    }
 
     // decode a batch of n queued candidates, one per lane
     auto run_batch = [&](int n) __attribute__((always_inline)) {
@@ -103,8 +150,7 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
         if (act) {
             key = L.qkey[lane];
             pl = static_cast<int>(L.qpl[lane]);
-            float b1, b2;
-            persp_from_t(L.qt[0][lane], L.qt[1][lane], L.qt[2][lane], b1, b2);
+            const float b1 = L.qb[0][lane], b2 = L.qb[1][lane];
             const uint32_t tri = static_cast<uint32_t>(key);
             const Cell c = cell_of(b1, b2, G);
             float x[S::C];
@@ -112,7 +158,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
             // an opaque copy of the weight pointer per batch: the compiler may
             // not hoist the weights' scalar loads out of the traversal loops
             mlp_logits<S>(as_const(opaque_ptr(mlp_p)), x, o);
-            const int gy = by + (pl >> 3), gx = bx + (pl & 7);
+            const int blk = pl >> 6, p = pl & 63;
+            const int gx = rx + (blk % BR) * 8 + (p & 7), gy = ry + (blk / BR) * 8 + (p >> 3);
             if (a.o.mode == 0) {
                 const float alpha = sigmoid_c(o[3]);
                 const uint32_t pidx = static_cast<uint32_t>(gy * W + gx);
@@ -134,31 +181,40 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
         if (a.log_frag) log_cursor += static_cast<uint32_t>(n);
         __syncthreads();
         if (pass && L.key[pl] == key) {
-            L.rgb[0][pl] = sigmoid_c(o[0]);
-            L.rgb[1][pl] = sigmoid_c(o[1]);
-            L.rgb[2][pl] = sigmoid_c(o[2]);
+            // the pixel's new best: its colour goes to the output now (a later batch that lowers
+            // the key again writes after this one, behind the workgroup barriers between them)
+            const int blk = pl >> 6, p = pl & 63;
+            const int64_t off = static_cast<int64_t>(ry + (blk / BR) * 8 + (p >> 3)) * W + rx + (blk % BR) * 8 + (p & 7);
+            float* col = vd.color_out ? vd.color_out + 3 * off : a.color + 3 * (vd.pix_base + off);
+            col[0] = sigmoid_c(o[0]);
+            col[1] = sigmoid_c(o[1]);
+            col[2] = sigmoid_c(o[2]);
         }
         if (a.counter && lane == 0) atomicAdd(a.counter, static_cast<unsigned long long>(n));
         __syncthreads();
-        kc = L.key[lane];
-        wmax = wave_max_u64(kc);
+        wmax = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            kc[b] = L.key[b * 64 + lane];
+            wmaxb[b] = wave_max_u64(kc[b]);
+            wmax = wmaxb[b] > wmax ? wmaxb[b] : wmax;
+        }
     };
 
-    // snapped position of the block's first pixel centre
-    const int64_t PX0 = static_cast<int64_t>(kSnap) * bx + kSnap / 2;
-    const int64_t PY0 = static_cast<int64_t>(kSnap) * by + kSnap / 2;
     const int64_t beg = a.tile_start[tile], end = a.tile_start[tile + 1];
-    const double fx = static_cast<double>(pu), fy = static_cast<double>(pv);
     int64_t c0 = beg;         // next list entry to scan
     bool listed = false;      // the scan has reached the end of the list or its early-out
-    int pn = 0;               // entries waiting for the coverage phase (L.pend)
+    constexpr int kRing = FwdWaveLds<NB>::kRing;
+    int ph = 0;               // first waiting pair in the ring (L.ptri, L.pblk)
+    int pn = 0;               // pairs waiting for the coverage step
     int qn = 0;               // queued candidates
     uint64_t hit = 0;         // slice slots that cover a pixel and are not visited yet
-    uint64_t ent = kBgKey;    // this lane's slice entry
-    uint32_t mlo = 0, mhi = 0;   // ... and its coverage of block pixels 0..31, 32..63
-    // One loop, uniform control flow: decode when 64 candidates wait (or at the
-    // end), else visit the next covering slot, else run coverage on the next 64
-    // waiting entries, else scan the next 64 list entries.
+    uint64_t cent = kBgKey;   // this lane's slice pair: list entry,
+    int cblk = 0;             // ... block,
+    uint32_t mlo = 0, mhi = 0;   // ... and coverage of the block's pixels 0..31, 32..63
+    // Decode when 64 candidates wait (or at the end), else visit the next
+    // covering pair, else run coverage on the next 64 waiting pairs, else scan
+    // the next 64 list entries.
     for (;;) {
         if (qn >= 64 || (hit == 0 && pn == 0 && listed)) {
             if (qn == 0) break;
@@ -166,8 +222,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
             run_batch(n);
             if (lane < qn - n) {
                 L.qkey[lane] = L.qkey[n + lane];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) L.qt[i][lane] = L.qt[i][n + lane];
+                L.qb[0][lane] = L.qb[0][n + lane];
+                L.qb[1][lane] = L.qb[1][n + lane];
                 L.qpl[lane] = L.qpl[n + lane];
             }
             qn -= n;
@@ -175,23 +231,28 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
             continue;
         }
         if (hit) {
-            // ---- fragments of one covering triangle: lane = pixel ----
+            // ---- fragments of one covering pair: lane = pixel of the pair's block ----
             const int j = __builtin_ctzll(hit);
             hit &= hit - 1;
-            const uint64_t zk = readlane_u64(ent, j);
+            const uint64_t zk = readlane_u64(cent, j);
+            const int bj = __builtin_amdgcn_readlane(cblk, j);
             // the depth bound no longer beats any pixel of the block (a list longer than a sort
-            // block is sorted only block by block, so later slots are tested one by one)
-            if (zk >= wmax) continue;
+            // block is sorted only block by block, so later pairs are tested one by one)
+            if (zk >= pick<NB>(wmaxb, bj)) continue;
+            const uint64_t kp = pick<NB>(kc, bj);
             // lanes 0..31 test their bit in mlo of slot j, lanes 32..63 in mhi
             const uint32_t mj_lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mlo), j));
             const uint32_t mj_hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mhi), j));
-            const bool cov = (((lane < 32 ? mj_lo >> lane : mj_hi >> (lane - 32)) & 1u) != 0u) & (zk < kc);
+            const bool cov = (((lane < 32 ? mj_lo >> lane : mj_hi >> (lane - 32)) & 1u) != 0u) & (zk < kp);
             bool cand = false;
             Frag f;
             if (cov) {
                 double e[3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) e[i] = __builtin_fma(fx, L.ea[i][j], __builtin_fma(fy, L.eb[i][j], L.e0[i][j]));
+                for (int i = 0; i < 3; ++i) {   // exact: every term is an integer below 2^51
+                    const double t = __builtin_fma(fy, static_cast<double>(L.ndx[i][j]), -(fx * static_cast<double>(L.ndy[i][j])));
+                    e[i] = __builtin_fma(static_cast<double>(kSnap), t, L.e0[i][j]);
+                }
                 const float ra = L.ra[j];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
@@ -199,33 +260,50 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
                 if (!(z > 0.0f)) z = 0.0f;
                 if (z > 1.0f) z = 1.0f;
                 f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | static_cast<uint32_t>(zk);
-                cand = f.key < kc;
+                cand = f.key < kp;
             }
             const uint64_t m = __ballot(cand);
             if (cand) {
                 const int pos = qn + __popcll(m & lanemask_lt());
+                float b1, b2;
+                persp_from_t(f.beta[0] * L.iw[0][j], f.beta[1] * L.iw[1][j], f.beta[2] * L.iw[2][j], b1, b2);
                 L.qkey[pos] = f.key;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) L.qt[i][pos] = f.beta[i] * L.iw[i][j];
-                L.qpl[pos] = static_cast<uint32_t>(lane);
+                L.qb[0][pos] = b1;
+                L.qb[1][pos] = b2;
+                L.qpl[pos] = static_cast<uint16_t>(bj * 64 + lane);
             }
             qn += __popcll(m);
             continue;
         }
         if (pn >= 64 || (listed && pn > 0)) {
-            // ---- coverage of up to 64 waiting entries: lane = triangle ----
+            // ---- coverage of up to 64 waiting pairs: lane = (triangle, block) ----
             const int n = pn < 64 ? pn : 64;
-            ent = lane < n ? L.pend[lane] : kBgKey;
+            cent = kBgKey;
+            int slot = ph + lane;
+            if (slot >= kRing) slot -= kRing;
+            cblk = lane < n ? static_cast<int>(L.pblk[slot]) : 0;
             mlo = 0;
             mhi = 0;
-            if (ent < wmax) {   // still able to beat a pixel of the block (pads are kBgKey)
-                guint4* rp = as_global(reinterpret_cast<const uint4*>(recs + static_cast<uint32_t>(ent)));
-                const uint4 q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
+            uint4 q0, q1, q2, q3;
+            if (lane < n) {
+                const uint32_t tri = L.ptri[slot];
+                guint4* rp = as_global(reinterpret_cast<const uint4*>(recs + tri));
+                q0 = rp[0];
+                q1 = rp[1];
+                q2 = rp[2];
+                q3 = rp[3];
+                cent = (static_cast<uint64_t>(q3.y) << 32) | tri;   // the list entry: depth bound | triangle
+            }
+            if (cent < pick<NB>(wmaxb, cblk)) {   // still able to beat a pixel of the block (pads are kBgKey)
                 const int32_t X[3] = {static_cast<int32_t>(q0.x), static_cast<int32_t>(q0.y), static_cast<int32_t>(q0.z)};
                 const int32_t Y[3] = {static_cast<int32_t>(q0.w), static_cast<int32_t>(q1.x), static_cast<int32_t>(q1.y)};
                 const float rA = __uint_as_float(q3.x);
                 const int sgn = rA < 0.0f ? -1 : 1;
+                // snapped position of the block's first pixel centre
+                const int64_t PX0 = static_cast<int64_t>(kSnap) * (rx + (cblk % BR) * 8) + kSnap / 2;
+                const int64_t PY0 = static_cast<int64_t>(kSnap) * (ry + (cblk / BR) * 8) + kSnap / 2;
                 double e0[3], ea[3], eb[3], thr[3];
+                int32_t nx[3], ny[3];
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {   // edge e joins vertices e+1 and e+2
                     const int va = e == 2 ? 0 : e + 1;
@@ -234,12 +312,13 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
                     const int64_t E0 =
                         static_cast<int64_t>(dx) * (PY0 - Y[va]) - static_cast<int64_t>(dy) * (PX0 - X[va]);
                     e0[e] = static_cast<double>(sgn * E0);
-                    ea[e] = static_cast<double>(-static_cast<int64_t>(sgn) * kSnap * dy);
-                    eb[e] = static_cast<double>(static_cast<int64_t>(sgn) * kSnap * dx);
+                    nx[e] = sgn * dx;
+                    ny[e] = sgn * dy;
+                    ea[e] = -static_cast<double>(kSnap) * static_cast<double>(ny[e]);
+                    eb[e] = static_cast<double>(kSnap) * static_cast<double>(nx[e]);
                     // an edge owns the centres exactly on it when it is a top or left edge:
                     // E > 0, or E == 0 on an owning edge, is E > -1/2 for integer E
-                    const int32_t ndx = sgn * dx, ndy = sgn * dy;
-                    thr[e] = (ndy < 0 || (ndy == 0 && ndx > 0)) ? -0.5 : 0.0;
+                    thr[e] = (ny[e] < 0 || (ny[e] == 0 && nx[e] > 0)) ? -0.5 : 0.0;
                 }
 #pragma unroll
                 for (int pv2 = 0; pv2 < 8; ++pv2) {
@@ -262,8 +341,8 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
                         L.e0[e][lane] = e0[e];
-                        L.ea[e][lane] = ea[e];
-                        L.eb[e][lane] = eb[e];
+                        L.ndx[e][lane] = nx[e];
+                        L.ndy[e][lane] = ny[e];
                     }
                     L.z[0][lane] = __uint_as_float(q1.z);
                     L.z[1][lane] = __uint_as_float(q1.w);
@@ -275,50 +354,63 @@ __global__ __launch_bounds__(64) void raster_fwd_kernel(RasterArgs a) {
                 }
             }
             hit = __ballot((mlo | mhi) != 0);
-            __syncthreads();
-            if (lane < pn - n) L.pend[lane] = L.pend[n + lane];
+            ph += n;
+            if (ph >= kRing) ph -= kRing;
             pn -= n;
             __syncthreads();
             continue;
         }
-        // ---- scan the next 64 list entries: keep those that can cover the block ----
+        // ---- scan the next 64 list entries: lane = entry ----
         if (c0 >= end || remaining_min(a.entries, beg, c0, end) >= wmax) {
             listed = true;
             continue;
         }
         const uint64_t e = c0 + lane < end ? a.entries[c0 + lane] : kBgKey;
-        bool keep = false;
-        if (e < wmax) {   // its depth bound can beat some pixel of the block
+        uint32_t touch = 0;   // blocks the entry's bounding box touches and whose pixels it can beat
+        if (e < wmax) {
             const uint4 q3 = as_global(reinterpret_cast<const uint4*>(recs + static_cast<uint32_t>(e)))[3];
             const int x0 = static_cast<int16_t>(q3.z & 0xFFFFu), y0 = static_cast<int16_t>(q3.z >> 16);
             const int x1 = static_cast<int16_t>(q3.w & 0xFFFFu), y1 = static_cast<int16_t>(q3.w >> 16);
-            keep = !(x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int bx = rx + (b % BR) * 8, by = ry + (b / BR) * 8;
+                if (!(x1 < bx || x0 > bx + 7 || y1 < by || y0 > by + 7) && e < wmaxb[b]) touch |= 1u << b;
+            }
         }
-        const uint64_t km = __ballot(keep);
-        if (keep) L.pend[pn + __popcll(km & lanemask_lt())] = e;
-        pn += __popcll(km);
+        const int cnt = __popc(touch);
+        const int incl = wave_incl_scan_i32(cnt);
+        int at = ph + pn + incl - cnt;   // below 2 kRing: pn < 64 and pn + 64 NB <= kRing
+        if (at >= kRing) at -= kRing;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if ((touch >> b) & 1u) {
+                L.ptri[at] = static_cast<uint32_t>(e);
+                L.pblk[at] = static_cast<uint8_t>(b);
+                if (++at == kRing) at = 0;
+            }
+        }
+        pn += __builtin_amdgcn_readlane(incl, 63);
         c0 += 64;
         __syncthreads();
     }
-    if (inview) {
-        const int gx = bx + pu, gy = by + pv;
-        const uint64_t key = L.key[lane];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int gx = rx + (b % BR) * 8 + pu, gy = ry + (b / BR) * 8 + pv;
+        if (gx >= W || gy >= H) continue;
+        const int pl = b * 64 + lane;
+        const uint64_t key = L.key[pl];
         const int64_t off = static_cast<int64_t>(gy) * W + gx;
-        float* col = vd.color_out ? vd.color_out + 3 * off : a.color + 3 * (vd.pix_base + off);
         if (vd.vis_out) vd.vis_out[off] = key;
         else if (a.vis) a.vis[vd.pix_base + off] = key;
-        if (key == kBgKey) {
+        if (key == kBgKey) {   // covered pixels got their colour when their best key was set
+            float* col = vd.color_out ? vd.color_out + 3 * off : a.color + 3 * (vd.pix_base + off);
             col[0] = a.o.bg[0];
             col[1] = a.o.bg[1];
             col[2] = a.o.bg[2];
-        } else {
-            col[0] = L.rgb[0][lane];
-            col[1] = L.rgb[1][lane];
-            col[2] = L.rgb[2][lane];
         }
     }
     __syncthreads();
-    }   // blocks
+    }   // regions
     if (a.log_counts && lane == 0) a.log_counts[blockIdx.x] = log_cursor;
 }
 
