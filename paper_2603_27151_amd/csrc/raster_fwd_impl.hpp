@@ -50,10 +50,10 @@ struct FwdWaveLds {
     static constexpr int kRing = 64 * (NB + 1);
     uint32_t ptri[kRing];
     uint8_t pblk[kRing];
-    // candidate queue
-    uint64_t qkey[128];
-    float qb[2][128];    // perspective-correct barycentrics b1, b2
-    uint16_t qpl[128];   // pixel of the region: block * 64 + pixel of the block
+    // candidate queue (below 64 waiting, plus up to 64 from each of two pairs)
+    uint64_t qkey[192];
+    float qb[2][192];    // perspective-correct barycentrics b1, b2
+    uint16_t qpl[192];   // pixel of the region: block * 64 + pixel of the block
     // the region's pixels: current best key (their colours go straight to the output)
     uint64_t key[64 * NB];
 };
@@ -212,6 +212,46 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     uint64_t cent = kBgKey;   // this lane's slice pair: list entry,
     int cblk = 0;             // ... block,
     uint32_t mlo = 0, mhi = 0;   // ... and coverage of the block's pixels 0..31, 32..63
+    // The fragment of this lane's pixel of the block of slice pair j: true when
+    // the pair covers the pixel and the fragment's key is below the pixel's best.
+    auto frag_of_pair = [&](int j, Frag& f) __attribute__((always_inline)) -> bool {
+        const uint64_t zk = readlane_u64(cent, j);
+        const int bj = __builtin_amdgcn_readlane(cblk, j);
+        const uint64_t kp = pick<NB>(kc, bj);
+        // lanes 0..31 test their bit in mlo of slot j, lanes 32..63 in mhi
+        const uint32_t mj_lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mlo), j));
+        const uint32_t mj_hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mhi), j));
+        const bool cov = (((lane < 32 ? mj_lo >> lane : mj_hi >> (lane - 32)) & 1u) != 0u) & (zk < kp);
+        // every lane evaluates (the values of uncovered lanes are not used)
+        double e[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {   // exact: every term is an integer below 2^51
+            const double t = __builtin_fma(fy, static_cast<double>(L.ndx[i][j]), -(fx * static_cast<double>(L.ndy[i][j])));
+            e[i] = __builtin_fma(static_cast<double>(kSnap), t, L.e0[i][j]);
+        }
+        const float ra = L.ra[j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
+        float z = __builtin_fmaf(f.beta[2], L.z[2][j], __builtin_fmaf(f.beta[1], L.z[1][j], f.beta[0] * L.z[0][j]));
+        if (!(z > 0.0f)) z = 0.0f;
+        if (z > 1.0f) z = 1.0f;
+        f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | static_cast<uint32_t>(zk);
+        return cov & (f.key < kp);
+    };
+    // Append the candidates of slice pair j to the queue (ballot + prefix count).
+    auto enqueue = [&](int j, bool cand, const Frag& f) __attribute__((always_inline)) {
+        const uint64_t m = __ballot(cand);
+        if (cand) {
+            const int pos = qn + __popcll(m & lanemask_lt());
+            float b1, b2;
+            persp_from_t(f.beta[0] * L.iw[0][j], f.beta[1] * L.iw[1][j], f.beta[2] * L.iw[2][j], b1, b2);
+            L.qkey[pos] = f.key;
+            L.qb[0][pos] = b1;
+            L.qb[1][pos] = b2;
+            L.qpl[pos] = static_cast<uint16_t>(__builtin_amdgcn_readlane(cblk, j) * 64 + lane);
+        }
+        qn += __popcll(m);
+    };
     // Decode when 64 candidates wait (or at the end), else visit the next
     // covering pair, else run coverage on the next 64 waiting pairs, else scan
     // the next 64 list entries.
@@ -220,59 +260,35 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             if (qn == 0) break;
             const int n = qn < 64 ? qn : 64;
             run_batch(n);
-            if (lane < qn - n) {
-                L.qkey[lane] = L.qkey[n + lane];
-                L.qb[0][lane] = L.qb[0][n + lane];
-                L.qb[1][lane] = L.qb[1][n + lane];
-                L.qpl[lane] = L.qpl[n + lane];
+            // the rest moves to the front; the reads of each chunk precede its writes,
+            // and a chunk writes only where the previous chunk has read
+            for (int i = lane; i < qn - n; i += 64) {
+                L.qkey[i] = L.qkey[n + i];
+                L.qb[0][i] = L.qb[0][n + i];
+                L.qb[1][i] = L.qb[1][n + i];
+                L.qpl[i] = L.qpl[n + i];
             }
             qn -= n;
+            // slice pairs whose depth bound no longer beats any pixel of their block are dropped
+            // (a list longer than a sort block is sorted only block by block, so pairs are
+            // tested one by one)
+            hit &= __ballot(cent < pick<NB>(wmaxb, cblk));
             __syncthreads();
             continue;
         }
         if (hit) {
-            // ---- fragments of one covering pair: lane = pixel of the pair's block ----
-            const int j = __builtin_ctzll(hit);
+            // ---- fragments of the next two covering pairs (their loads and arithmetic
+            // overlap): lane = pixel of the pair's block ----
+            const int j1 = __builtin_ctzll(hit);
             hit &= hit - 1;
-            const uint64_t zk = readlane_u64(cent, j);
-            const int bj = __builtin_amdgcn_readlane(cblk, j);
-            // the depth bound no longer beats any pixel of the block (a list longer than a sort
-            // block is sorted only block by block, so later pairs are tested one by one)
-            if (zk >= pick<NB>(wmaxb, bj)) continue;
-            const uint64_t kp = pick<NB>(kc, bj);
-            // lanes 0..31 test their bit in mlo of slot j, lanes 32..63 in mhi
-            const uint32_t mj_lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mlo), j));
-            const uint32_t mj_hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mhi), j));
-            const bool cov = (((lane < 32 ? mj_lo >> lane : mj_hi >> (lane - 32)) & 1u) != 0u) & (zk < kp);
-            bool cand = false;
-            Frag f;
-            if (cov) {
-                double e[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {   // exact: every term is an integer below 2^51
-                    const double t = __builtin_fma(fy, static_cast<double>(L.ndx[i][j]), -(fx * static_cast<double>(L.ndy[i][j])));
-                    e[i] = __builtin_fma(static_cast<double>(kSnap), t, L.e0[i][j]);
-                }
-                const float ra = L.ra[j];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
-                float z = __builtin_fmaf(f.beta[2], L.z[2][j], __builtin_fmaf(f.beta[1], L.z[1][j], f.beta[0] * L.z[0][j]));
-                if (!(z > 0.0f)) z = 0.0f;
-                if (z > 1.0f) z = 1.0f;
-                f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | static_cast<uint32_t>(zk);
-                cand = f.key < kp;
-            }
-            const uint64_t m = __ballot(cand);
-            if (cand) {
-                const int pos = qn + __popcll(m & lanemask_lt());
-                float b1, b2;
-                persp_from_t(f.beta[0] * L.iw[0][j], f.beta[1] * L.iw[1][j], f.beta[2] * L.iw[2][j], b1, b2);
-                L.qkey[pos] = f.key;
-                L.qb[0][pos] = b1;
-                L.qb[1][pos] = b2;
-                L.qpl[pos] = static_cast<uint16_t>(bj * 64 + lane);
-            }
-            qn += __popcll(m);
+            const bool two = hit != 0;
+            const int j2 = two ? __builtin_ctzll(hit) : j1;
+            if (two) hit &= hit - 1;
+            Frag f1, f2;
+            const bool c1 = frag_of_pair(j1, f1);
+            const bool c2 = frag_of_pair(j2, f2) & two;
+            enqueue(j1, c1, f1);
+            enqueue(j2, c2, f2);
             continue;
         }
         if (pn >= 64 || (listed && pn > 0)) {
