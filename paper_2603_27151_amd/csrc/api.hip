@@ -24,6 +24,7 @@ struct DevBuf {
 struct soup_ctx {
     int device = 0;
     int num_cus = 256;
+    size_t lds_limit = 163840;   // LDS bytes one workgroup may use (the CU's whole LDS on this GPU)
     int tile = 16;
     bool counting = false;
     bool fixed = false;              // static-capacity mode: no synchronisation, no allocation
@@ -198,6 +199,16 @@ soup_status check_scene(soup_ctx* c, const soup_scene* s, MlpKind* kind) {
         return fail(c, SOUP_ERR_UNSUPPORTED, "MLP shape %s is not compiled in (8->16->4, 16->32->32->4, 32->64->64->4)",
                     d.c_str());
     }
+    return SOUP_OK;
+}
+
+// The backward decode keeps one triangle's gradient grid per wave in LDS: refuse a
+// grid that would not fit one workgroup's LDS rather than launch it.
+soup_status check_decode_lds(soup_ctx* c, MlpKind kind, int G, bool logp) {
+    const size_t need = decode_bwd_lds(kind, G, logp);
+    if (need > c->lds_limit)
+        return fail(c, SOUP_ERR_UNSUPPORTED, "the backward decode needs %zu bytes of LDS per workgroup for G = %d "
+                    "(the device has %zu): use a smaller texture grid", need, G, c->lds_limit);
     return SOUP_OK;
 }
 
@@ -455,6 +466,11 @@ soup_status soup_ctx_create(soup_ctx** out, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cus = prop.multiProcessorCount;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess && lds > 0)
+        c->lds_limit = static_cast<size_t>(lds);
+    else
+        (void)hipGetLastError();
     *out = c;
     return SOUP_OK;
 }
@@ -697,6 +713,7 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
     if ((st = plan_single(c, p, scene, views))) return st;
     if ((st = check_opts(c, opts))) return st;
     if (!vis || !color) return fail(c, SOUP_ERR_INVALID, "vis and color outputs are required");
+    if (logp && (st = check_decode_lds(c, p.kind, p.G, true))) return st;
     HIP_TRY(c, hipSetDevice(c->device));
     const Opts o = to_opts(opts);
     if ((st = bin(c, p, o, s))) return st;
@@ -788,6 +805,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     if ((st = check_opts(c, opts))) return st;
     if (!vis || !color || !grad_color) return fail(c, SOUP_ERR_INVALID, "vis, color and grad_color are required");
     if (!grad_verts || !grad_feats || !grad_mlp) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
+    if ((st = check_decode_lds(c, p.kind, p.G, false))) return st;
     HIP_TRY(c, hipSetDevice(c->device));
     const Opts o = to_opts(opts);
     bool reused = false;

@@ -7,4 +7,6 @@ void launch_decode_bwd_k16_32_2(const DecodeArgs& a, bool logp, hipStream_t s) {
     launch_decode_bwd_s<MlpShape<16, 32, 2>>(a, logp, s);
 }
 
+size_t decode_bwd_lds_k16_32_2(int G, bool logp) { return decode_bwd_lds_s<MlpShape<16, 32, 2>>(G, logp); }
+
 }  // namespace soup

@@ -7,4 +7,6 @@ void launch_decode_bwd_k8_16_1(const DecodeArgs& a, bool logp, hipStream_t s) {
     launch_decode_bwd_s<MlpShape<8, 16, 1>>(a, logp, s);
 }
 
+size_t decode_bwd_lds_k8_16_1(int G, bool logp) { return decode_bwd_lds_s<MlpShape<8, 16, 1>>(G, logp); }
+
 }  // namespace soup

@@ -563,6 +563,21 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
     }
 }
 
+// Bytes of LDS one workgroup of the decode needs (static + dynamic), or 0 when
+// the runtime cannot say.
+template <class S>
+static size_t decode_bwd_lds_s(int G, bool logp) {
+    hipFuncAttributes fa;
+    const hipError_t e = logp ? hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(decode_bwd_kernel<S, true>))
+                              : hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(decode_bwd_kernel<S, false>));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const size_t dyn = logp ? 0 : static_cast<size_t>(4) * (static_cast<size_t>(G) * G * S::C + 16) * sizeof(float);
+    return fa.sharedSizeBytes + dyn;
+}
+
 template <class S>
 static void launch_decode_bwd_s(const DecodeArgs& a, bool logp, hipStream_t s) {
     if (logp) {

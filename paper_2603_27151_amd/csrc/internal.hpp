@@ -169,6 +169,8 @@ struct DecodeArgs {
 };
 
 void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp_pass, hipStream_t s);
+// LDS bytes one workgroup of the decode needs for a grid side G (0: unknown).
+size_t decode_bwd_lds(MlpKind k, int G, bool logp_pass);
 // ew[p] = (x, y) edge weights of the pairs pixel p occludes (Section 3.2)
 void launch_edge_weights(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis,
                          const float* color, const float* grad_color, float2* ew, hipStream_t s);

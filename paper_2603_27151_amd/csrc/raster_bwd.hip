@@ -10,6 +10,19 @@ void launch_decode_bwd_k8_16_1(const DecodeArgs& a, bool logp, hipStream_t s);
 void launch_decode_bwd_k16_32_2(const DecodeArgs& a, bool logp, hipStream_t s);
 void launch_decode_bwd_k32_64_2(const DecodeArgs& a, bool logp, hipStream_t s);
 
+size_t decode_bwd_lds_k8_16_1(int G, bool logp);
+size_t decode_bwd_lds_k16_32_2(int G, bool logp);
+size_t decode_bwd_lds_k32_64_2(int G, bool logp);
+
+size_t decode_bwd_lds(MlpKind k, int G, bool logp) {
+    switch (k) {
+        case MlpKind::k8_16_1: return decode_bwd_lds_k8_16_1(G, logp);
+        case MlpKind::k16_32_2: return decode_bwd_lds_k16_32_2(G, logp);
+        case MlpKind::k32_64_2: return decode_bwd_lds_k32_64_2(G, logp);
+        default: return 0;
+    }
+}
+
 void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp, hipStream_t s) {
     if (a.n_blocks <= 0) return;
     switch (k) {

@@ -272,6 +272,15 @@ def test_invalid_arguments_are_rejected():
         R.rasterize_fwd(ds, vs, _opts(mode=3))
     with pytest.raises(_lib.SoupError, match="INVALID"):
         R.context().set_tile(12)
+    # a texture grid whose backward gradient grid would not fit one workgroup's LDS
+    # (11 x 11 x 32 floats per wave with the 32->64->64->4 MLP) is refused, not launched
+    rng = np.random.default_rng(3)
+    big = W.random_scene(rng, wl.scene.verts, 11, 32, [32, 64, 64, 4])
+    dsb = _dev_scene(big)
+    vis, col, _ = R.rasterize_fwd(dsb, vs, _opts())
+    gc = torch.zeros_like(col)
+    with pytest.raises(_lib.SoupError, match="UNSUPPORTED"):
+        R.rasterize_bwd(dsb, vs, _opts(), vis, col, gc, None)
 
 
 def test_batching_invariance():
