@@ -46,14 +46,18 @@ __global__ __launch_bounds__(256) void edge_weight_kernel(const ViewDesc* __rest
                                                           Opts o, const uint64_t* __restrict__ vis,
                                                           const float* __restrict__ color,
                                                           const float* __restrict__ gcol, float2* __restrict__ ew) {
-    const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (p >= P) return;
+    // the view of the workgroup's first pixel (a wave-uniform search), then per lane
+    // the few steps past it when the workgroup straddles views
+    const int64_t p0 = blockIdx.x * static_cast<int64_t>(blockDim.x);
     int lo = 0, hi = V - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].pix_base <= p) lo = mid;
+        if (views[mid].pix_base <= p0) lo = mid;
         else hi = mid - 1;
     }
+    const int64_t p = p0 + threadIdx.x;
+    if (p >= P) return;
+    while (lo + 1 < V && views[lo + 1].pix_base <= p) ++lo;
     const ViewDesc& vd = views[lo];
     const int64_t local = p - vd.pix_base;
     const int x = static_cast<int>(local % vd.W), y = static_cast<int>(local / vd.W);
