@@ -293,7 +293,9 @@ def main():
     if not args.skip_serve:
         from paper_2603_27151_amd import serve as SV
         soups = [R.DeviceScene.from_host(sc) for sc in W.serving_soups()]
-        srv = SV.Server(soups, tile=16, n_streams=2, max_batch=16, budget_fraction=args.serve_budget)
+        srv = SV.Server(soups, tile=None, n_streams=2, max_batch=16, budget_fraction=args.serve_budget)
+        tuned = srv.tune_tiles([W.View(w, h, 0, W.view_proj((0.0, 0.3, 3.0), w, h)) for w, h in W.SERVING_RES])
+        log(f"serving tiles: {srv.tile_by_res}")
         SV.run(srv, W.serving_requests(200.0, 1.0, seed=99))   # warm-up: workspaces, allocator
         log(f"serving: {args.serve_seconds:.0f} s at 200 req/s")
         main_st = SV.run(srv, W.serving_requests(200.0, args.serve_seconds))
@@ -310,6 +312,7 @@ def main():
                                "threshold mode, 640x360/1280x720/1920x1080 uniform, Poisson arrivals",
                    "rate_hz": 200, "duration_s": args.serve_seconds, "streams": 2, "max_batch": 16,
                    "budget_fraction": args.serve_budget, "budget_bytes": srv.budget,
+                   "tiles": {f"{w}x{h}": t for (w, h), t in srv.tile_by_res.items()},
                    "slo_p99_ms": 16.7, **main_st, "sweep": sweep}
 
     # CPU oracle on a bounded sample of the same workload

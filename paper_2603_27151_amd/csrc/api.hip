@@ -297,15 +297,16 @@ bool same_descriptors(const soup_ctx* c, const Plan& p) {
 // Upload descriptors, run setup + scan, read the list size, scatter + sort.
 soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     const size_t vbytes = p.views.size() * sizeof(ViewDesc), sbytes = p.scenes.size() * sizeof(SceneDesc);
+    const int chunk = bin_chunk_size(static_cast<int>(p.views.size()), p.maxT, c->num_cus);
     soup_status st;
     // the forward counts its regions in 32 bits
-    if (p.n_tiles * fwd_regions_per_tile(c->tile) >= (int64_t(1) << 32))
+    if (p.n_tiles * fwd_regions_per_tile(c->tile, 8) >= (int64_t(1) << 32))
         return fail(c, SOUP_ERR_CAPACITY, "too many pixels in one call (2^32 forward regions)");
     if ((st = ensure(c, c->views, vbytes)) || (st = ensure(c, c->scenes, sbytes)) ||
         (st = ensure(c, c->recs, static_cast<size_t>(p.n_recs) * sizeof(TriRec))) ||
         (st = ensure(c, c->tile_count, static_cast<size_t>(p.n_tiles) * 4)) ||
         (st = ensure(c, c->tile_fill, static_cast<size_t>(p.n_tiles) * 4)) ||
-        (st = ensure(c, c->chunk_base, static_cast<size_t>(bin_chunks(p.maxT)) * p.n_tiles * 4)) ||
+        (st = ensure(c, c->chunk_base, static_cast<size_t>(bin_chunks(p.maxT, chunk)) * p.n_tiles * 4)) ||
         (st = ensure(c, c->tile_start, static_cast<size_t>(p.n_tiles + 1) * 8)) ||
         (st = ensure(c, c->bsum, static_cast<size_t>((p.n_tiles + 1023) / 1024 + 1) * 8)) ||
         (st = ensure(c, c->counters, 64)) || (st = ensure(c, c->flags, 256)) ||
@@ -340,7 +341,7 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     }
     {
     Timed t_setup(c, SOUP_T_SETUP, s);
-    launch_setup(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT,
+    launch_setup(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, chunk,
                  static_cast<SceneDesc*>(c->scenes.p), o, c->tile, static_cast<TriRec*>(c->recs.p),
                  static_cast<int32_t*>(c->tile_count.p), static_cast<int32_t*>(c->chunk_base.p), p.n_tiles,
                  c->counting ? cnt + 1 : nullptr, s);
@@ -367,7 +368,7 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     {
         Timed t(c, SOUP_T_SCATTER, s);
         launch_fill_i32(static_cast<int32_t*>(c->tile_fill.p), p.n_tiles, 0, s);
-        launch_scatter(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, c->tile,
+        launch_scatter(static_cast<ViewDesc*>(c->views.p), static_cast<int>(p.views.size()), p.maxT, chunk, c->tile,
                        static_cast<TriRec*>(c->recs.p), static_cast<int64_t*>(c->tile_start.p), p.n_tiles,
                        static_cast<int32_t*>(c->chunk_base.p), static_cast<int32_t*>(c->tile_fill.p),
                        static_cast<uint64_t*>(c->entries.p), s);
@@ -400,10 +401,18 @@ RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     a.counter = c->counting ? cnt : nullptr;
     a.work = reinterpret_cast<unsigned int*>(cnt + 2);
-    // the forward's workgroups are single waves, one region of a tile at a time (16x16 pixels, 8x8 for
-    // 8-pixel tiles): as many as are resident
-    const int64_t items = p.n_tiles * fwd_regions_per_tile(c->tile);
-    const int64_t resident = static_cast<int64_t>(c->num_cus) * raster_fwd_blocks_per_cu(c->tile, p.kind);
+    // the forward's workgroups are single waves, one region of a tile at a time: 16x16 pixels, or a
+    // single 8x8 block for 8-pixel tiles and for calls with fewer 16x16 regions than two per resident
+    // wave (a small render); as many waves as are resident
+    int region = 8;
+    if (c->tile >= 16) {
+        const int64_t r16 = p.n_tiles * fwd_regions_per_tile(c->tile, 16);
+        const int64_t res16 = static_cast<int64_t>(c->num_cus) * raster_fwd_blocks_per_cu(c->tile, p.kind, 16);
+        region = r16 >= 2 * res16 ? 16 : 8;
+    }
+    a.region = region;
+    const int64_t items = p.n_tiles * fwd_regions_per_tile(c->tile, region);
+    const int64_t resident = static_cast<int64_t>(c->num_cus) * raster_fwd_blocks_per_cu(c->tile, p.kind, region);
     a.n_blocks = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(resident, kMaxRegions), items)));
     return a;
 }

@@ -15,23 +15,23 @@
 
 namespace soup {
 
-// One workgroup bins kBinChunk triangles of one view. When the view has at
-// most kHistBins tiles, its (tile, triangle) pairs are counted in an LDS
-// histogram, and only the chunk's non-zero tile counts go to the global
+// One workgroup bins a chunk of `chunk` triangles of one view. When the chunk
+// is large (kBinChunk) and the view has at most kHistBins tiles, its (tile,
+// triangle) pairs are counted in an LDS histogram, and only the chunk's non-zero tile counts go to the global
 // counters (one returning atomic per tile touched: the chunk's first slot in
 // that tile's list); otherwise every pair is counted with a global atomic.
 __global__ __launch_bounds__(256) void setup_kernel(const ViewDesc* __restrict__ views,
-                                                    const SceneDesc* __restrict__ scenes, Opts o, int tile,
+                                                    const SceneDesc* __restrict__ scenes, Opts o, int tile, int chunk,
                                                     TriRec* __restrict__ recs, int32_t* __restrict__ tile_count,
                                                     int32_t* __restrict__ chunk_base, int64_t n_tiles,
                                                     unsigned long long* __restrict__ visible) {
     __shared__ int32_t hist[kHistBins];
     const ViewDesc& vd = views[blockIdx.y];
-    const int t_beg = blockIdx.x * kBinChunk;
+    const int t_beg = blockIdx.x * chunk;
     if (t_beg >= vd.T) return;
-    const int t_end = min(t_beg + kBinChunk, vd.T);
+    const int t_end = min(t_beg + chunk, vd.T);
     const int nb = vd.tiles_x * vd.tiles_y;
-    const bool local = nb <= kHistBins;
+    const bool local = chunk >= kBinChunk && nb <= kHistBins;
     if (local) {
         for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
         __syncthreads();
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void setup_kernel(const ViewDesc* __restrict__
 // box touches, over the same chunks as the setup. A view binned in LDS takes
 // its positions from an LDS cursor per tile, started at the tile's list offset
 // plus the chunk's first slot; other views take them from a global atomic.
-__global__ __launch_bounds__(256) void scatter_kernel(const ViewDesc* __restrict__ views, int tile,
+__global__ __launch_bounds__(256) void scatter_kernel(const ViewDesc* __restrict__ views, int tile, int chunk,
                                                       const TriRec* __restrict__ recs,
                                                       const int64_t* __restrict__ tile_start, int64_t n_tiles,
                                                       const int32_t* __restrict__ chunk_base,
@@ -134,13 +134,13 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ViewDesc* __restrict
                                                       uint64_t* __restrict__ entries) {
     __shared__ unsigned long long cur[kHistBins];
     const ViewDesc& vd = views[blockIdx.y];
-    const int t_beg = blockIdx.x * kBinChunk;
+    const int t_beg = blockIdx.x * chunk;
     if (t_beg >= vd.T) return;
     const int64_t total = tile_start[n_tiles];
     if (total == 0) return;   // no entries, or lists emptied by the static capacity check
-    const int t_end = min(t_beg + kBinChunk, vd.T);
+    const int t_end = min(t_beg + chunk, vd.T);
     const int nb = vd.tiles_x * vd.tiles_y;
-    const bool local = nb <= kHistBins;
+    const bool local = chunk >= kBinChunk && nb <= kHistBins;
     if (local) {
         // bins this chunk does not touch hold stale offsets and are never used
         const int32_t* base = chunk_base + static_cast<int64_t>(blockIdx.x) * n_tiles + vd.tile_base;
@@ -366,15 +366,19 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
 }
 
-int bin_chunks(int maxT) { return maxT <= 0 ? 0 : (maxT + kBinChunk - 1) / kBinChunk; }
+// Large chunks when they still give every CU two workgroups, else one triangle per thread.
+int bin_chunk_size(int V, int maxT, int num_cus) {
+    const int64_t wgs = static_cast<int64_t>(V) * bin_chunks(maxT, kBinChunk);
+    return wgs >= 2 * static_cast<int64_t>(num_cus) ? kBinChunk : 256;
+}
 
-void launch_setup(const ViewDesc* views, int V, int maxT, const SceneDesc* scenes, const Opts& o, int tile,
-                  TriRec* recs, int32_t* tile_count, int32_t* chunk_base, int64_t n_tiles,
+void launch_setup(const ViewDesc* views, int V, int maxT, int chunk, const SceneDesc* scenes, const Opts& o,
+                  int tile, TriRec* recs, int32_t* tile_count, int32_t* chunk_base, int64_t n_tiles,
                   unsigned long long* visible, hipStream_t s) {
     if (maxT <= 0) return;
-    dim3 grid(bin_chunks(maxT), V);
-    hipLaunchKernelGGL(setup_kernel, grid, dim3(256), 0, s, views, scenes, o, tile, recs, tile_count, chunk_base,
-                       n_tiles, visible);
+    dim3 grid(bin_chunks(maxT, chunk), V);
+    hipLaunchKernelGGL(setup_kernel, grid, dim3(256), 0, s, views, scenes, o, tile, chunk, recs, tile_count,
+                       chunk_base, n_tiles, visible);
 }
 
 void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipStream_t s) {
@@ -388,13 +392,13 @@ void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipS
     hipLaunchKernelGGL(scan_apply_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, in, n, bsum, out);
 }
 
-void launch_scatter(const ViewDesc* views, int V, int maxT, int tile, const TriRec* recs,
+void launch_scatter(const ViewDesc* views, int V, int maxT, int chunk, int tile, const TriRec* recs,
                     const int64_t* tile_start, int64_t n_tiles, const int32_t* chunk_base, int32_t* tile_fill,
                     uint64_t* entries, hipStream_t s) {
     if (maxT <= 0) return;
-    dim3 grid(bin_chunks(maxT), V);
-    hipLaunchKernelGGL(scatter_kernel, grid, dim3(256), 0, s, views, tile, recs, tile_start, n_tiles, chunk_base,
-                       tile_fill, entries);
+    dim3 grid(bin_chunks(maxT, chunk), V);
+    hipLaunchKernelGGL(scatter_kernel, grid, dim3(256), 0, s, views, tile, chunk, recs, tile_start, n_tiles,
+                       chunk_base, tile_fill, entries);
 }
 
 // Static-capacity mode: when the lists need more than `cap` entries, flag the

@@ -4,6 +4,6 @@
 namespace soup {
 
 void launch_raster_fwd_k16_32_2_t8(const RasterArgs& a, hipStream_t s) { launch_fwd_t<8, MlpShape<16, 32, 2>>(a, s); }
-int raster_fwd_per_cu_k16_32_2_t8() { return fwd_blocks_per_cu<8, MlpShape<16, 32, 2>>(); }
+int raster_fwd_per_cu_k16_32_2_t8(int region) { return fwd_blocks_per_cu<8, MlpShape<16, 32, 2>>(region); }
 
 }  // namespace soup

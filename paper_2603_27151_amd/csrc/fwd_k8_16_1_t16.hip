@@ -4,6 +4,6 @@
 namespace soup {
 
 void launch_raster_fwd_k8_16_1_t16(const RasterArgs& a, hipStream_t s) { launch_fwd_t<16, MlpShape<8, 16, 1>>(a, s); }
-int raster_fwd_per_cu_k8_16_1_t16() { return fwd_blocks_per_cu<16, MlpShape<8, 16, 1>>(); }
+int raster_fwd_per_cu_k8_16_1_t16(int region) { return fwd_blocks_per_cu<16, MlpShape<8, 16, 1>>(region); }
 
 }  // namespace soup

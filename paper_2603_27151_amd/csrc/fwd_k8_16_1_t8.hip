@@ -4,6 +4,6 @@
 namespace soup {
 
 void launch_raster_fwd_k8_16_1_t8(const RasterArgs& a, hipStream_t s) { launch_fwd_t<8, MlpShape<8, 16, 1>>(a, s); }
-int raster_fwd_per_cu_k8_16_1_t8() { return fwd_blocks_per_cu<8, MlpShape<8, 16, 1>>(); }
+int raster_fwd_per_cu_k8_16_1_t8(int region) { return fwd_blocks_per_cu<8, MlpShape<8, 16, 1>>(region); }
 
 }  // namespace soup

@@ -7,17 +7,21 @@ namespace soup {
 
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
-// Binning works on chunks of kBinChunk triangles per view; a view with at most
-// kHistBins tiles is counted in LDS, and chunk_base ([chunks][tiles] int32)
-// receives each chunk's first slot in every tile list it touches.
+// Binning works on chunks of triangles per view. Large chunks (kBinChunk) of
+// a view with at most kHistBins tiles are counted in an LDS histogram, and
+// chunk_base ([chunks][tiles] int32) receives each chunk's first slot in every
+// tile list it touches; when large chunks would leave the GPU idle (few views,
+// few triangles) the chunks are one triangle per thread, counted with global
+// atomics.
 constexpr int kBinChunk = 4096;
 constexpr int kHistBins = 8192;
-int bin_chunks(int maxT);
-void launch_setup(const ViewDesc* views, int V, int maxT, const SceneDesc* scenes, const Opts& o, int tile,
-                  TriRec* recs, int32_t* tile_count, int32_t* chunk_base, int64_t n_tiles,
+int bin_chunk_size(int V, int maxT, int num_cus);
+inline int bin_chunks(int maxT, int chunk) { return maxT <= 0 ? 0 : (maxT + chunk - 1) / chunk; }
+void launch_setup(const ViewDesc* views, int V, int maxT, int chunk, const SceneDesc* scenes, const Opts& o,
+                  int tile, TriRec* recs, int32_t* tile_count, int32_t* chunk_base, int64_t n_tiles,
                   unsigned long long* visible, hipStream_t s);
 void launch_scan(const int32_t* in, int64_t n, int64_t* bsum, int64_t* out, hipStream_t s);
-void launch_scatter(const ViewDesc* views, int V, int maxT, int tile, const TriRec* recs,
+void launch_scatter(const ViewDesc* views, int V, int maxT, int chunk, int tile, const TriRec* recs,
                     const int64_t* tile_start, int64_t n_tiles, const int32_t* chunk_base, int32_t* tile_fill,
                     uint64_t* entries, hipStream_t s);
 void launch_sort(const int64_t* tile_start, int64_t n_tiles, uint64_t* entries, hipStream_t s);
@@ -48,6 +52,7 @@ struct RasterArgs {
     unsigned long long* counter;   // decode counter or null
     unsigned int* work;            // persistent-kernel tile counter (zeroed by the launcher's caller)
     int n_blocks;                  // persistent grid of the forward (single-wave workgroups)
+    int region;                    // side of a forward wave's region: 16 (tiles of 16, 32) or 8
     // optional log of the forward's decoded fragments, one region per wave (= workgroup):
     // log_frag = (pixel, triangle, b1, b2), log_aux = (depth bits, view)
     uint4* log_frag;
@@ -57,10 +62,11 @@ struct RasterArgs {
 };
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
-// Resident single-wave workgroups per CU of the forward kernel for a tile side and MLP shape.
-int raster_fwd_blocks_per_cu(int tile, MlpKind k);
-// The forward's unit of work: a 16x16 region of a tile (8x8 for 8-pixel tiles).
-inline int fwd_regions_per_tile(int tile) { return tile >= 16 ? (tile / 16) * (tile / 16) : 1; }
+// Resident single-wave workgroups per CU of the forward kernel for a tile side, MLP shape and
+// region side (16: 16x16 pixels of a tile of 16 or 32; 8: one 8x8 block).
+int raster_fwd_blocks_per_cu(int tile, MlpKind k, int region);
+// The forward's unit of work: a region of `region` x `region` pixels of a tile.
+inline int fwd_regions_per_tile(int tile, int region) { return (tile / region) * (tile / region); }
 
 // One fragment the backward needs, 48 bytes: a = (pixel, triangle | winner << 31,
 // perspective-correct b1, b2), b = (the pixel's score weight g_L and colour

@@ -3,8 +3,9 @@
 // visibility buffer (Eq. (5); Supplement Algorithm A1, part 1).
 //
 // One wave is one workgroup and owns one region of a screen tile at a time
-// (16x16 pixels, four 8x8 blocks; 8x8 for 8-pixel tiles), taken from a
-// counter (persistent, the next region fetched while the current one runs),
+// (16x16 pixels, four 8x8 blocks, or a single 8x8 block when a call has too
+// few 16x16 regions to fill the GPU), taken from a counter (persistent, the
+// next region fetched while the current one runs),
 // so no barrier ever waits for another wave. It walks the tile's triangle
 // list (sorted by a lower bound of their depth) in three steps, all in one
 // loop with uniform control flow:
@@ -85,9 +86,9 @@ __device__ __forceinline__ uint64_t pick(const uint64_t (&arr)[N], int b) {
     return r;
 }
 
-template <int TS, class S>
+template <int TS, int RS, class S>
 __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
-    constexpr int RS = TS >= 16 ? 16 : 8;          // side of the region a wave owns
+    static_assert(RS == 8 || (RS == 16 && TS >= 16), "a region is one 8x8 block, or 16x16 pixels of a larger tile");
     constexpr int BR = RS / 8, NB = BR * BR;       // 8x8 blocks per region
     constexpr int RT = TS / RS, RPT = RT * RT;     // regions per tile
     __shared__ FwdWaveLds<NB> L;
@@ -431,12 +432,12 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
 }
 
 // Resident waves per CU of the forward (its workgroups are single waves).
-template <int TS, class S>
-static int fwd_blocks_per_cu() {
+template <int TS, int RS, class S>
+static int fwd_blocks_per_cu_r() {
     static int n = 0;
     if (n == 0) {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, raster_fwd_kernel<TS, S>, 64, 0) != hipSuccess || b < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, raster_fwd_kernel<TS, RS, S>, 64, 0) != hipSuccess || b < 1)
             b = 8;
         n = b;
     }
@@ -444,9 +445,24 @@ static int fwd_blocks_per_cu() {
 }
 
 template <int TS, class S>
+static int fwd_blocks_per_cu(int region) {
+    if constexpr (TS >= 16) {
+        if (region == 16) return fwd_blocks_per_cu_r<TS, 16, S>();
+    }
+    return fwd_blocks_per_cu_r<TS, 8, S>();
+}
+
+template <int TS, class S>
 static void launch_fwd_t(const RasterArgs& a, hipStream_t s) {
     if (a.n_tiles <= 0 || a.n_blocks <= 0) return;
-    hipLaunchKernelGGL((raster_fwd_kernel<TS, S>), dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), 0, s, a);
+    if constexpr (TS >= 16) {
+        if (a.region == 16) {
+            hipLaunchKernelGGL((raster_fwd_kernel<TS, 16, S>), dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), 0,
+                               s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((raster_fwd_kernel<TS, 8, S>), dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), 0, s, a);
 }
 
 

@@ -115,9 +115,14 @@ class Scheduler:
 
 
 class Server:
-    """Device backend: one context and one stream per slot; soups resident."""
+    """Device backend: one context and one stream per slot; soups resident.
 
-    def __init__(self, soups, tile: int = 16, n_streams: int = 2, max_batch: int = 16,
+    The screen-tile side is fixed (``tile``) or, with ``tile=None``, tuned per
+    request resolution by ``tune_tiles`` (the forward's work unit is a tile
+    region, so a small render wants small tiles to fill the GPU); a batch
+    takes the tile of its largest request."""
+
+    def __init__(self, soups, tile: Optional[int] = 16, n_streams: int = 2, max_batch: int = 16,
                  budget_fraction: float = 0.25, opts=None, keep_colors: bool = False):
         import torch
         from . import _lib
@@ -127,11 +132,14 @@ class Server:
         self.opts = opts if opts is not None else R.Opts(mode=1)
         self.keep_colors = keep_colors
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.tile = tile
+        self.tile_by_res: Dict[tuple, int] = {}   # (width, height) -> tuned tile side
         self.ctxs = []
         for _ in range(n_streams):
             c = _lib.Ctx(torch.cuda.current_device())
-            c.set_tile(tile)
+            c.set_tile(tile if tile is not None else 16)
             self.ctxs.append(c)
+        self.ctx_tile = [tile if tile is not None else 16] * n_streams
         free, _total = torch.cuda.mem_get_info()
         self.budget = int(budget_fraction * free)
         self.t0 = time.perf_counter()
@@ -147,11 +155,50 @@ class Server:
     def need(self, soup: int, view) -> int:
         return request_bytes(view.width, view.height, self.soups[soup].T)
 
+    def tune_tiles(self, views: Sequence, reps: int = 5) -> Dict[tuple, dict]:
+        """For each distinct resolution among ``views``, time one render of
+        every soup at that view with every tile side (autotune.tune) and keep
+        the fastest."""
+        from . import autotune
+        torch, R = self.torch, self.R
+        out = {}
+        for v in views:
+            res = (int(v.width), int(v.height))
+            if res in out:
+                continue
+            vs = R.Views.from_list([v])
+            colors = [torch.empty(v.height, v.width, 3, dtype=torch.float32, device="cuda")]
+
+            def step(vs=vs, colors=colors):   # on the current stream, which the tuner times
+                for sc in self.soups:
+                    R.render([sc], vs, self.opts, colors, ctx=self.ctxs[0])
+
+            key = "serve-%dx%d-%s" % (res[0], res[1], ",".join(str(sc.T) for sc in self.soups))
+            out[res] = autotune.tune(step, self.ctxs[0], key, reps=reps)
+            self.tile_by_res[res] = int(out[res]["tile"])
+        self.ctxs[0].set_tile(self.ctx_tile[0])
+        return out
+
+    def tile_for(self, tickets: List[Ticket]) -> int:
+        if self.tile is not None or not self.tile_by_res:
+            return self.tile if self.tile is not None else 16
+        big = max(tickets, key=lambda t: t.view.width * t.view.height).view
+        res = (int(big.width), int(big.height))
+        if res in self.tile_by_res:
+            return self.tile_by_res[res]
+        px = big.width * big.height   # nearest tuned resolution by pixel count
+        near = min(self.tile_by_res, key=lambda r: abs(r[0] * r[1] - px))
+        return self.tile_by_res[near]
+
     def _launch(self, slot: int, batch: List[Ticket]):
         torch, R = self.torch, self.R
         s = self.streams[slot]
         views = R.Views.from_list([t.view for t in batch])
         scenes = [self.soups[t.soup] for t in batch]
+        tile = self.tile_for(batch)
+        if tile != self.ctx_tile[slot]:
+            self.ctxs[slot].set_tile(tile)
+            self.ctx_tile[slot] = tile
         with torch.cuda.stream(s):
             colors = [torch.empty(t.view.height, t.view.width, 3, dtype=torch.float32, device="cuda")
                       for t in batch]

@@ -52,3 +52,36 @@ def test_open_loop_run_completes(server):
     assert st["requests"] == len(reqs)
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     assert st["p99_ms"] < 1000.0
+
+
+def test_tuned_tiles_keep_results():
+    """With tiles tuned per resolution, a batch renders with the tile of its
+    largest request; colours do not depend on the tile side, so every request
+    still equals its lone render at the default tile."""
+    from paper_2603_27151_amd import raster as R
+    from paper_2603_27151_amd import serve as SV
+    soups = [R.DeviceScene.from_host(s) for s in W.serving_soups()[:2]]
+    srv = SV.Server(soups, tile=None, n_streams=2, max_batch=4, keep_colors=True)
+    sizes = [(160, 90), (320, 180)]
+    tuned = srv.tune_tiles([W.View(w, h, 0, W.view_proj((0.0, 0.3, 3.0), w, h)) for w, h in sizes], reps=1)
+    _say(f"case: tuned tiles {srv.tile_by_res}")
+    assert set(srv.tile_by_res) == set(sizes)
+    assert all(t in (8, 16, 32) for t in srv.tile_by_res.values())
+    assert all(set(e["ms"]) == {"8", "16", "32"} for e in tuned.values())
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(6):
+        w, h = sizes[i % 2]
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        reqs.append(SV.Ticket(i, i % 2, W.View(w, h, 100 + i, W.view_proj(3.0 * d, w, h)), 0.0, 0))
+    for t in reqs:
+        t.need = srv.need(t.soup, t.view)
+        srv.sched.submit(t)
+    done = []
+    while srv.sched.busy:
+        done += srv.sched.poll()
+    assert len(done) == len(reqs)
+    ref = SV.Server(soups, tile=16, n_streams=1, max_batch=1)
+    for t in done:
+        assert torch.equal(t.color, ref.render_alone(t.soup, t.view)), f"request {t.rid} differs"
