@@ -53,7 +53,7 @@ struct FwdWaveLds {
     uint8_t pblk[kRing];
     // candidate queue (below 64 waiting, plus up to 64 from each of two pairs)
     uint64_t qkey[192];
-    float qb[2][192];    // perspective-correct barycentrics b1, b2
+    float qt[3][192];    // beta_i / w_i (the decode forms the perspective-correct barycentrics)
     uint16_t qpl[192];   // pixel of the region: block * 64 + pixel of the block
     // the region's pixels: current best key (their colours go straight to the output)
     uint64_t key[64 * NB];
@@ -128,15 +128,15 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     const float* mlp_p = uniform_ptr(sc.mlp);
     const TriRec* __restrict__ recs = uniform_ptr(a.recs + vd.rec_base);
 
-    uint64_t kc[NB];     // this lane's pixel of every block: current best key
-    uint64_t wmaxb[NB];  // per block: the largest best key of its pixels (wave-uniform)
+    // the pixels' best keys live in L.key; per block, the largest of them (wave-uniform)
+    uint64_t wmaxb[NB];
     uint64_t wmax = 0;   // ... over the region
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const bool inview = rx + (b % BR) * 8 + pu < W && ry + (b / BR) * 8 + pv < H;
-        kc[b] = inview ? kBgKey : 0ull;   // pixels outside the view never take fragments
-        L.key[b * 64 + lane] = kc[b];
-        wmaxb[b] = wave_max_u64(kc[b]);
+        const uint64_t k0 = inview ? kBgKey : 0ull;   // pixels outside the view never take fragments
+        L.key[b * 64 + lane] = k0;
+        wmaxb[b] = wave_max_u64(k0);
         wmax = wmaxb[b] > wmax ? wmaxb[b] : wmax;
     }
 
@@ -151,7 +151,8 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         if (act) {
             key = L.qkey[lane];
             pl = static_cast<int>(L.qpl[lane]);
-            const float b1 = L.qb[0][lane], b2 = L.qb[1][lane];
+            float b1, b2;
+            persp_from_t(L.qt[0][lane], L.qt[1][lane], L.qt[2][lane], b1, b2);
             const uint32_t tri = static_cast<uint32_t>(key);
             const Cell c = cell_of(b1, b2, G);
             float x[S::C];
@@ -196,8 +197,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         wmax = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            kc[b] = L.key[b * 64 + lane];
-            wmaxb[b] = wave_max_u64(kc[b]);
+            wmaxb[b] = wave_max_u64(L.key[b * 64 + lane]);
             wmax = wmaxb[b] > wmax ? wmaxb[b] : wmax;
         }
     };
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     auto frag_of_pair = [&](int j, Frag& f) __attribute__((always_inline)) -> bool {
         const uint64_t zk = readlane_u64(cent, j);
         const int bj = __builtin_amdgcn_readlane(cblk, j);
-        const uint64_t kp = pick<NB>(kc, bj);
+        const uint64_t kp = L.key[bj * 64 + lane];   // the pixel's best key as of the last decode batch
         // lanes 0..31 test their bit in mlo of slot j, lanes 32..63 in mhi
         const uint32_t mj_lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mlo), j));
         const uint32_t mj_hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mhi), j));
@@ -244,11 +244,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         const uint64_t m = __ballot(cand);
         if (cand) {
             const int pos = qn + __popcll(m & lanemask_lt());
-            float b1, b2;
-            persp_from_t(f.beta[0] * L.iw[0][j], f.beta[1] * L.iw[1][j], f.beta[2] * L.iw[2][j], b1, b2);
             L.qkey[pos] = f.key;
-            L.qb[0][pos] = b1;
-            L.qb[1][pos] = b2;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) L.qt[i][pos] = f.beta[i] * L.iw[i][j];
             L.qpl[pos] = static_cast<uint16_t>(__builtin_amdgcn_readlane(cblk, j) * 64 + lane);
         }
         qn += __popcll(m);
@@ -265,8 +263,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             // and a chunk writes only where the previous chunk has read
             for (int i = lane; i < qn - n; i += 64) {
                 L.qkey[i] = L.qkey[n + i];
-                L.qb[0][i] = L.qb[0][n + i];
-                L.qb[1][i] = L.qb[1][n + i];
+                L.qt[0][i] = L.qt[0][n + i];
+                L.qt[1][i] = L.qt[1][n + i];
+                L.qt[2][i] = L.qt[2][n + i];
                 L.qpl[i] = L.qpl[n + i];
             }
             qn -= n;
