@@ -17,11 +17,12 @@
 //    coverage mask of its triangle over its block from float64 edge
 //    functions (every value an exact integer); covering pairs leave their
 //    edge and vertex data in the wave's LDS;
-//  - fragments, lanes over the pixels of a block: the covering pairs are
-//    visited in list order; each covered pixel computes its fragment's key,
-//    and a fragment whose key is below the pixel's current best is a
-//    candidate, compacted (ballot + prefix count) into an LDS queue together
-//    with its perspective-correct barycentrics.
+//  - fragments, lanes over covered (pair, pixel) combinations: the slice's
+//    combinations are taken 64 at a time in slice order (a lane finds its pair
+//    by a max-scan over the starts of the pairs' runs and its pixel as the
+//    k-th set bit of the pair's mask); each computes its fragment's key, and a
+//    fragment whose key is below the pixel's current best is a candidate,
+//    compacted (ballot + prefix count) into an LDS queue with beta_i / w_i.
 // The queue is decoded 64 candidates at a time, one per lane, so the
 // expensive texture + MLP decode always runs on full waves. A decoded
 // fragment that passes its draw lowers the pixel's key with an LDS 64-bit
@@ -57,6 +58,8 @@ struct FwdWaveLds {
     uint16_t qpl[192];   // pixel of the region: block * 64 + pixel of the block
     // the region's pixels: current best key (their colours go straight to the output)
     uint64_t key[64 * NB];
+    // per round of the fragment step: the slice pair whose run of combinations starts here
+    int32_t head[64];
 };
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
@@ -73,6 +76,24 @@ __device__ __forceinline__ int wave_incl_scan_i32(int v) {
         if (lane >= d) v += u;
     }
     return v;
+}
+
+// Position of the k-th set bit (k from 0) of the 64-bit mask hi:lo.
+__device__ __forceinline__ int select_bit(uint32_t lo, uint32_t hi, int k) {
+    const int cl = __popc(lo);
+    uint32_t x = k < cl ? lo : hi;
+    int pos = k < cl ? 0 : 32;
+    k = k < cl ? k : k - cl;
+    int c = __popc(x & 0xFFFFu);
+    if (k >= c) { k -= c; x >>= 16; pos += 16; }
+    c = __popc(x & 0xFFu);
+    if (k >= c) { k -= c; x >>= 8; pos += 8; }
+    c = __popc(x & 0xFu);
+    if (k >= c) { k -= c; x >>= 4; pos += 4; }
+    c = __popc(x & 0x3u);
+    if (k >= c) { k -= c; x >>= 2; pos += 2; }
+    if (k >= static_cast<int>(x & 1u)) pos += 1;
+    return pos;
 }
 
 // Element b of a small register array, as masks: a chain of selects of
@@ -209,53 +230,17 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     int ph = 0;               // first waiting pair in the ring (L.ptri, L.pblk)
     int pn = 0;               // pairs waiting for the coverage step
     int qn = 0;               // queued candidates
-    uint64_t hit = 0;         // slice slots that cover a pixel and are not visited yet
     uint64_t cent = kBgKey;   // this lane's slice pair: list entry,
     int cblk = 0;             // ... block,
-    uint32_t mlo = 0, mhi = 0;   // ... and coverage of the block's pixels 0..31, 32..63
-    // The fragment of this lane's pixel of the block of slice pair j: true when
-    // the pair covers the pixel and the fragment's key is below the pixel's best.
-    auto frag_of_pair = [&](int j, Frag& f) __attribute__((always_inline)) -> bool {
-        const uint64_t zk = readlane_u64(cent, j);
-        const int bj = __builtin_amdgcn_readlane(cblk, j);
-        const uint64_t kp = L.key[bj * 64 + lane];   // the pixel's best key as of the last decode batch
-        // lanes 0..31 test their bit in mlo of slot j, lanes 32..63 in mhi
-        const uint32_t mj_lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mlo), j));
-        const uint32_t mj_hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(mhi), j));
-        const bool cov = (((lane < 32 ? mj_lo >> lane : mj_hi >> (lane - 32)) & 1u) != 0u) & (zk < kp);
-        // every lane evaluates (the values of uncovered lanes are not used)
-        double e[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {   // exact: every term is an integer below 2^51
-            const double t = __builtin_fma(fy, static_cast<double>(L.ndx[i][j]), -(fx * static_cast<double>(L.ndy[i][j])));
-            e[i] = __builtin_fma(static_cast<double>(kSnap), t, L.e0[i][j]);
-        }
-        const float ra = L.ra[j];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
-        float z = __builtin_fmaf(f.beta[2], L.z[2][j], __builtin_fmaf(f.beta[1], L.z[1][j], f.beta[0] * L.z[0][j]));
-        if (!(z > 0.0f)) z = 0.0f;
-        if (z > 1.0f) z = 1.0f;
-        f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | static_cast<uint32_t>(zk);
-        return cov & (f.key < kp);
-    };
-    // Append the candidates of slice pair j to the queue (ballot + prefix count).
-    auto enqueue = [&](int j, bool cand, const Frag& f) __attribute__((always_inline)) {
-        const uint64_t m = __ballot(cand);
-        if (cand) {
-            const int pos = qn + __popcll(m & lanemask_lt());
-            L.qkey[pos] = f.key;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) L.qt[i][pos] = f.beta[i] * L.iw[i][j];
-            L.qpl[pos] = static_cast<uint16_t>(__builtin_amdgcn_readlane(cblk, j) * 64 + lane);
-        }
-        qn += __popcll(m);
-    };
-    // Decode when 64 candidates wait (or at the end), else visit the next
-    // covering pair, else run coverage on the next 64 waiting pairs, else scan
-    // the next 64 list entries.
+    uint32_t mlo = 0, mhi = 0;   // ... coverage of the block's pixels 0..31, 32..63,
+    int cnt = 0, off = 0;     // ... number of covered pixels and the first of its combinations
+    int n_comb = 0;           // covered (pair, pixel) combinations of the slice
+    int rnd = 0, n_rnd = 0;   // rounds of 64 combinations: next, total
+    // Decode when 64 candidates wait (or at the end), else take the next 64
+    // covered (pair, pixel) combinations of the slice, else run coverage on the
+    // next 64 waiting pairs, else scan the next 64 list entries.
     for (;;) {
-        if (qn >= 64 || (hit == 0 && pn == 0 && listed)) {
+        if (qn >= 64 || (rnd >= n_rnd && pn == 0 && listed)) {
             if (qn == 0) break;
             const int n = qn < 64 ? qn : 64;
             run_batch(n);
@@ -269,26 +254,66 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                 L.qpl[i] = L.qpl[n + i];
             }
             qn -= n;
-            // slice pairs whose depth bound no longer beats any pixel of their block are dropped
-            // (a list longer than a sort block is sorted only block by block, so pairs are
-            // tested one by one)
-            hit &= __ballot(cent < pick<NB>(wmaxb, cblk));
             __syncthreads();
             continue;
         }
-        if (hit) {
-            // ---- fragments of the next two covering pairs (their loads and arithmetic
-            // overlap): lane = pixel of the pair's block ----
-            const int j1 = __builtin_ctzll(hit);
-            hit &= hit - 1;
-            const bool two = hit != 0;
-            const int j2 = two ? __builtin_ctzll(hit) : j1;
-            if (two) hit &= hit - 1;
-            Frag f1, f2;
-            const bool c1 = frag_of_pair(j1, f1);
-            const bool c2 = frag_of_pair(j2, f2) & two;
-            enqueue(j1, c1, f1);
-            enqueue(j2, c2, f2);
+        if (rnd < n_rnd) {
+            // ---- fragments of 64 covered (pair, pixel) combinations, in slice order:
+            // lane = combination ----
+            const int base = 64 * rnd;
+            ++rnd;
+            // the pair of a combination: the last pair whose run starts at or before it
+            L.head[lane] = -1;
+            __syncthreads();
+            if (cnt > 0 && off >= base && off < base + 64) L.head[off - base] = lane;
+            __syncthreads();
+            int h = L.head[lane];
+            const uint64_t before = __ballot(cnt > 0 && off < base);
+            const int carry = before ? 63 - __builtin_clzll(before) : -1;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int o = __shfl_up(h, d, 64);
+                if (lane >= d) h = o > h ? o : h;
+            }
+            const int c = base + lane;
+            const bool valid = c < n_comb;
+            const int j = valid ? (h > carry ? h : carry) : 0;
+            // its pixel: the k-th covered pixel of the pair, k its rank in the pair's run (every
+            // lane takes part in the shuffles: a lane reading an inactive lane gets no value)
+            const int offj = __shfl(off, j, 64);
+            const uint32_t mjl = static_cast<uint32_t>(__shfl(static_cast<int>(mlo), j, 64));
+            const uint32_t mjh = static_cast<uint32_t>(__shfl(static_cast<int>(mhi), j, 64));
+            const int p = select_bit(mjl, mjh, valid ? c - offj : 0);
+            const int bj = __shfl(cblk, j, 64);
+            const uint64_t zk =
+                (static_cast<uint64_t>(static_cast<uint32_t>(__shfl(static_cast<int>(cent >> 32), j, 64))) << 32) |
+                static_cast<uint32_t>(__shfl(static_cast<int>(cent), j, 64));
+            const uint64_t kp = L.key[bj * 64 + p];   // the pixel's best key as of the last decode batch
+            const double px = static_cast<double>(p & 7), py = static_cast<double>(p >> 3);
+            Frag f;
+            double e[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {   // exact: every term is an integer below 2^51
+                const double t = __builtin_fma(py, static_cast<double>(L.ndx[i][j]), -(px * static_cast<double>(L.ndy[i][j])));
+                e[i] = __builtin_fma(static_cast<double>(kSnap), t, L.e0[i][j]);
+            }
+            const float ra = L.ra[j];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
+            float z = __builtin_fmaf(f.beta[2], L.z[2][j], __builtin_fmaf(f.beta[1], L.z[1][j], f.beta[0] * L.z[0][j]));
+            if (!(z > 0.0f)) z = 0.0f;
+            if (z > 1.0f) z = 1.0f;
+            f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | static_cast<uint32_t>(zk);
+            const bool cand = valid & (zk < kp) & (f.key < kp);
+            const uint64_t m = __ballot(cand);
+            if (cand) {
+                const int pos = qn + __popcll(m & lanemask_lt());
+                L.qkey[pos] = f.key;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) L.qt[i][pos] = f.beta[i] * L.iw[i][j];
+                L.qpl[pos] = static_cast<uint16_t>(bj * 64 + p);
+            }
+            qn += __popcll(m);
             continue;
         }
         if (pn >= 64 || (listed && pn > 0)) {
@@ -369,7 +394,12 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     L.ra[lane] = __builtin_fabsf(rA);
                 }
             }
-            hit = __ballot((mlo | mhi) != 0);
+            cnt = __popc(mlo) + __popc(mhi);
+            const int incl = wave_incl_scan_i32(cnt);
+            off = incl - cnt;
+            n_comb = __builtin_amdgcn_readlane(incl, 63);
+            rnd = 0;
+            n_rnd = (n_comb + 63) >> 6;
             ph += n;
             if (ph >= kRing) ph -= kRing;
             pn -= n;
