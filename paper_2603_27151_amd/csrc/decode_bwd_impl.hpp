@@ -35,7 +35,8 @@ constexpr int kStageRows = 16;   // fragments staged per transpose pass
 template <class S>
 struct StageCfg {
     static constexpr int kMax2(int a, int b) { return a > b ? a : b; }
-    static constexpr int kWidth = kMax2(kMax2(S::C + S::H, 2 * S::H), S::H + 4);
+    // the widest pair of staged rows (in, d), each row padded by kRowPad floats
+    static constexpr int kWidth = kMax2(kMax2(S::C + S::H, 2 * S::H), S::H + 4) + 2 * kRowPad;
 };
 
 // Accumulators of one layer's weight gradient dW[DOUT][DIN] += sum_f d_f a_f^T
@@ -56,7 +57,7 @@ struct LayerAcc {
         for (int i = 0; i < NB; ++i) w[i] = f4v{0.f, 0.f, 0.f, 0.f};
         b = 0.0f;
     }
-    // kStageRows (16) staged fragments: in[r][DIN] and d[r][DOUT] in LDS
+    // kStageRows (16) staged fragments: in[r][DIN] and d[r][DOUT] in LDS, rows padded by kRowPad
     __device__ __forceinline__ void accumulate(const float* __restrict__ in, const float* __restrict__ d, int lane) {
         const int col = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -66,12 +67,12 @@ struct LayerAcc {
 #pragma unroll
             for (int bo = 0; bo < BO; ++bo) {
                 const int m = 16 * bo + col;
-                av[bo] = m < DOUT ? d[r * DOUT + m] : 0.0f;
+                av[bo] = m < DOUT ? d[r * (DOUT + kRowPad) + m] : 0.0f;
             }
 #pragma unroll
             for (int bi = 0; bi < BI; ++bi) {
                 const int n = 16 * bi + col;
-                bv[bi] = n < DIN ? in[r * DIN + n] : 0.0f;
+                bv[bi] = n < DIN ? in[r * (DIN + kRowPad) + n] : 0.0f;
             }
 #pragma unroll
             for (int bo = 0; bo < BO; ++bo)
@@ -81,7 +82,7 @@ struct LayerAcc {
         }
         if (lane < DOUT) {
 #pragma unroll
-            for (int r = 0; r < kStageRows; ++r) b += d[r * DOUT + lane];
+            for (int r = 0; r < kStageRows; ++r) b += d[r * (DOUT + kRowPad) + lane];
         }
     }
     // D of a 16x16 block: lane l holds column l % 16, rows 4 (l / 16) + i
@@ -99,28 +100,6 @@ struct LayerAcc {
     }
 };
 
-// Stage the activations (in) and deltas (dl) of the wave's 64 fragments
-// through LDS, kStageRows at a time, and accumulate them on the matrix cores.
-template <int DIN, int DOUT>
-__device__ __forceinline__ void stage_accumulate(LayerAcc<DIN, DOUT>& la, float* __restrict__ st,
-                                                 const float (&in)[DIN], const float (&dl)[DOUT], int lane) {
-#pragma unroll
-    for (int half = 0; half < 64; half += kStageRows) {
-        if (lane >= half && lane < half + kStageRows) {
-            float* row = st + (lane - half) * DIN;
-#pragma unroll
-            for (int k = 0; k < DIN; k += 4) *reinterpret_cast<float4*>(row + k) = make_float4(in[k], in[k + 1], in[k + 2], in[k + 3]);
-            float* drow = st + kStageRows * DIN + (lane - half) * DOUT;
-#pragma unroll
-            for (int k = 0; k < DOUT; k += 4)
-                *reinterpret_cast<float4*>(drow + k) = make_float4(dl[k], dl[k + 1], dl[k + 2], dl[k + 3]);
-        }
-        __threadfence_block();
-        la.accumulate(st, st + kStageRows * DIN, lane);
-        __threadfence_block();
-    }
-}
-
 template <class S>
 struct MlpGrad {
     LayerAcc<S::C, S::H> l0;
@@ -135,7 +114,10 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
     __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
     __shared__ uint32_t s_boff[LOGP ? kMaxRegions + 1 : 1];
     __shared__ MfmaWeights<S> s_w;     // the MLP in the matrix cores' operand order (backward only)
-    __shared__ __align__(16) float s_dx[LOGP ? 1 : NW][LOGP ? 4 : 64 * S::C];   // the batch's feature gradients
+    // the batch's feature gradients, rows of C padded by kRowPad (not for C = 32: that
+    // shape's LDS is full)
+    constexpr int DXS = S::C + (S::C >= 32 ? 0 : kRowPad);
+    __shared__ __align__(16) float s_dx[LOGP ? 1 : NW][LOGP ? 4 : 64 * DXS];
     extern __shared__ float s_dyn[];   // [NW][G*G*C + 16]: per-wave gradient grid of the current triangle
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -312,9 +294,9 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 }
                 // output-layer weight gradient (rows = this block's fragments)
                 stage_rows<HB>(st, S::H, hl, lane);
-                st[kStageRows * S::H + col * 4 + grp] = dO;
+                st[kStageRows * (S::H + kRowPad) + col * (4 + kRowPad) + grp] = dO;
                 __threadfence_block();
-                acc.out.accumulate(st, st + kStageRows * S::H, lane);
+                acc.out.accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
                 __threadfence_block();
                 // back through the output layer: K = the four outputs, one step
                 f4v dl[HB];
@@ -329,9 +311,9 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 if constexpr (S::NH == 2) {
                     // hidden layer 1 weight gradient, then back to layer 0
                     stage_rows<HB>(st, S::H, h0, lane);
-                    stage_rows<HB>(st + kStageRows * S::H, S::H, dl, lane);
+                    stage_rows<HB>(st + kStageRows * (S::H + kRowPad), S::H, dl, lane);
                     __threadfence_block();
-                    acc.mid[0].accumulate(st, st + kStageRows * S::H, lane);
+                    acc.mid[0].accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
                     __threadfence_block();
                     mfma_back<HB, HB, true>(Wt.l1T, dl, h0, dh0, lane);
                 } else {
@@ -340,9 +322,9 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 }
                 // first-layer weight gradient
                 stage_rows<CB>(st, S::C, xin, lane);
-                stage_rows<HB>(st + kStageRows * S::C, S::H, dh0, lane);
+                stage_rows<HB>(st + kStageRows * (S::C + kRowPad), S::H, dh0, lane);
                 __threadfence_block();
-                acc.l0.accumulate(st, st + kStageRows * S::C, lane);
+                acc.l0.accumulate(st, st + kStageRows * (S::C + kRowPad), lane);
                 __threadfence_block();
                 // feature gradients into the rows [fragment][C] kept past the stage's working rows
                 f4v dxv[CB];
@@ -351,7 +333,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 for (int cb = 0; cb < CB; ++cb) {
                     const int ch = 16 * cb + 4 * grp;
                     if (ch < S::C)
-                        *reinterpret_cast<float4*>(s_dx[w] + (16 * nb + col) * S::C + ch) =
+                        *reinterpret_cast<float4*>(s_dx[w] + (16 * nb + col) * DXS + ch) =
                             make_float4(dxv[cb][0], dxv[cb][1], dxv[cb][2], dxv[cb][3]);
                 }
             }
@@ -360,7 +342,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         float dx[S::C];   // this lane's fragment
 #pragma unroll
         for (int k = 0; k < S::C; k += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(s_dx[w] + lane * S::C + k);
+            const float4 v = *reinterpret_cast<const float4*>(s_dx[w] + lane * DXS + k);
             dx[k] = v.x;
             dx[k + 1] = v.y;
             dx[k + 2] = v.z;
@@ -520,7 +502,7 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
 #pragma unroll
                     for (int pp = 0; pp < PPF; ++pp) {
                         const int k = (pp * 64 + (FPS > 1 ? lane % LPF : lane)) % S::C;
-                        dv[u][pp] = s_dx[w][fs[u] * S::C + k];
+                        dv[u][pp] = s_dx[w][fs[u] * DXS + k];
                     }
                 }
 #pragma unroll

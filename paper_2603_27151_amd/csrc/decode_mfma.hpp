@@ -28,6 +28,11 @@ namespace soup {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Staged rows in LDS are padded by this many floats: the 16 rows a wave writes
+// at once then start on different banks (unpadded rows of 16 or 32 floats all
+// began on the same four).
+constexpr int kRowPad = 4;
+
 __device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -153,7 +158,7 @@ __device__ __forceinline__ void mfma_back(const f4v (*wT)[IB][64], const f4v (&d
     }
 }
 
-// The 16 rows of one fragment block into an LDS stage laid out [row][D]
+// The 16 rows of one fragment block into an LDS stage laid out [row][D + kRowPad]
 // (D = n_units): lane (grp, col) writes its four units of row col.
 template <int NBLK>
 __device__ __forceinline__ void stage_rows(float* __restrict__ st, int D, const f4v (&v)[NBLK], int lane) {
@@ -161,7 +166,7 @@ __device__ __forceinline__ void stage_rows(float* __restrict__ st, int D, const 
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
         const int u = 16 * b + 4 * grp;
-        if (u < D) *reinterpret_cast<float4*>(st + col * D + u) = make_float4(v[b][0], v[b][1], v[b][2], v[b][3]);
+        if (u < D) *reinterpret_cast<float4*>(st + col * (D + kRowPad) + u) = make_float4(v[b][0], v[b][1], v[b][2], v[b][3]);
     }
 }
 
