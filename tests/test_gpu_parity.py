@@ -459,3 +459,24 @@ def test_backward_from_forward_log_matches_replay():
     for a, b in zip(ref, got):
         assert normwise(b.cpu().numpy(), a.cpu().numpy()) < 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("P,offset", [(1001, 0), (4096, 1), (7, 0)])
+def test_loss_l2_vector_and_tail_paths(P, offset):
+    """The L2 loss kernel (16-byte path plus scalar tail; scalar throughout for
+    unaligned buffers) against the float64 definition."""
+    R = _raster()
+    g = torch.Generator().manual_seed(P)
+    base_c = torch.rand(P + offset, 3, generator=g).cuda()
+    base_t = torch.rand(P + offset, 3, generator=g).cuda()
+    col, tgt = base_c[offset:], base_t[offset:]
+    _say(f"case: loss P={P} offset={offset}")
+    loss, gc, gl = R.loss_l2(col, tgt)
+    torch.cuda.synchronize()
+    c64, t64 = col.double().cpu(), tgt.double().cpu()
+    d = c64 - t64
+    ref_gc = 2.0 * d / (3.0 * P)
+    ref_gl = (d * d).sum(-1) / (3.0 * P)
+    assert torch.allclose(gc.double().cpu(), ref_gc, rtol=1e-6, atol=1e-12)
+    assert torch.allclose(gl.double().cpu(), ref_gl, rtol=1e-6, atol=1e-12)
+    assert abs(float(loss) - float(ref_gl.sum())) <= 1e-6 * float(ref_gl.sum())
