@@ -458,6 +458,19 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         // channel), so that no two lanes of an LDS add share an address;
         // the winners' vertex gradients are summed over the run by a wave
         // reduction.
+        constexpr int LPF = 4 * S::C;                  // (corner, channel) pairs of one fragment
+        constexpr int FPS = LPF >= 64 ? 1 : 64 / LPF;  // fragments per step
+        constexpr int PPF = LPF >= 64 ? LPF / 64 : 1;  // steps per fragment
+        // One fragment per step: each lane's fragment leaves its four corner
+        // weights (corner q = 2 dy + dx) in the stage, free once the MLP is
+        // done, and keeps its cell's first texel; the steps then need no
+        // per-fragment weight or address arithmetic beyond one add.
+        int cbase = 0;
+        if constexpr (FPS == 1) {
+            const float x1 = c.fx, y1 = c.fy, x0 = 1.0f - c.fx, y0 = 1.0f - c.fy;
+            *reinterpret_cast<float4*>(st + 4 * lane) = make_float4(x0 * y0, x1 * y0, x0 * y1, x1 * y1);
+            cbase = (c.iy * G + c.ix) * S::C;
+        }
         __threadfence_block();
         const uint32_t tkey = on ? tri : 0xFFFFFFFFu;
         const uint32_t tprev = __shfl_up(tkey, 1, 64);
@@ -486,50 +499,74 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                     for (int k = 0; k < 9; ++k) grid[n_grid + k] += v[k];
                 }
             }
-            constexpr int LPF = 4 * S::C;                  // (corner, channel) pairs of one fragment
-            constexpr int FPS = LPF >= 64 ? 1 : 64 / LPF;  // fragments per step
-            constexpr int PPF = LPF >= 64 ? LPF / 64 : 1;  // steps per fragment
             constexpr int UF = 4;                          // steps in flight: their staged reads go first
-            for (int f0 = h; f0 < end; f0 += FPS * UF) {
-                int fs[UF];
-                bool ok[UF];
-                float dv[UF][PPF];
+            if constexpr (FPS == 1) {
+                // lane (corner q, channel k) of step pp: weight st[4 f + q],
+                // gradient s_dx[f][k], texel q of the fragment's cell
+                float* gl[PPF];
+                const float* wl[PPF];
+                const float* dl[PPF];
 #pragma unroll
-                for (int u = 0; u < UF; ++u) {
-                    const int f = f0 + u * FPS + (FPS > 1 ? lane / LPF : 0);
-                    ok[u] = f < end;
-                    fs[u] = ok[u] ? f : h;                     // lanes past the run repeat h with weight 0
-#pragma unroll
-                    for (int pp = 0; pp < PPF; ++pp) {
-                        const int k = (pp * 64 + (FPS > 1 ? lane % LPF : lane)) % S::C;
-                        dv[u][pp] = s_dx[w][fs[u] * DXS + k];
-                    }
+                for (int pp = 0; pp < PPF; ++pp) {
+                    const int idx = pp * 64 + lane;
+                    const int q = idx / S::C, k = idx % S::C;
+                    gl[pp] = grid + ((q >> 1) * G + (q & 1)) * S::C + k;
+                    wl[pp] = st + q;
+                    dl[pp] = s_dx[w] + k;
                 }
-#pragma unroll
-                for (int u = 0; u < UF; ++u) {
-                    uint32_t cw;
-                    float fx, fy;
-                    if (FPS > 1) {
-                        cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), fs[u], 64));
-                        fx = __shfl(c.fx, fs[u], 64);
-                        fy = __shfl(c.fy, fs[u], 64);
-                    } else {   // one fragment per step: a wave-uniform lane index
-                        const int fu = __builtin_amdgcn_readfirstlane(fs[u]);
-                        cw = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(cellw), fu));
-                        fx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, c.fx), fu));
-                        fy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, c.fy), fu));
-                    }
-                    const int ix = static_cast<int>(cw & 0xFFFFu), iy = static_cast<int>(cw >> 16);
+                auto add = [&](int f, const float (&wv)[PPF], const float (&dv)[PPF]) __attribute__((always_inline)) {
+                    const int cb = __builtin_amdgcn_readlane(cbase, f);
 #pragma unroll
                     for (int pp = 0; pp < PPF; ++pp) {
-                        const int idx = pp * 64 + (FPS > 1 ? lane % LPF : lane);
-                        const int q = idx / S::C, k = idx % S::C;   // corner, channel
+                        float* gp = gl[pp] + cb;   // one fragment: 64 distinct addresses
+                        *gp = __builtin_fmaf(wv[pp], dv[pp], *gp);
+                    }
+                };
+                int f = h;
+                for (; f + UF <= end; f += UF) {
+                    float wv[UF][PPF], dv[UF][PPF];
+#pragma unroll
+                    for (int u = 0; u < UF; ++u)
+#pragma unroll
+                        for (int pp = 0; pp < PPF; ++pp) {
+                            wv[u][pp] = wl[pp][4 * (f + u)];
+                            dv[u][pp] = dl[pp][(f + u) * DXS];
+                        }
+#pragma unroll
+                    for (int u = 0; u < UF; ++u) add(f + u, wv[u], dv[u]);
+                }
+                for (; f < end; ++f) {
+                    float wv[PPF], dv[PPF];
+#pragma unroll
+                    for (int pp = 0; pp < PPF; ++pp) {
+                        wv[pp] = wl[pp][4 * f];
+                        dv[pp] = dl[pp][f * DXS];
+                    }
+                    add(f, wv, dv);
+                }
+            } else {
+                for (int f0 = h; f0 < end; f0 += FPS * UF) {
+                    int fs[UF];
+                    bool ok[UF];
+                    float dv[UF];
+#pragma unroll
+                    for (int u = 0; u < UF; ++u) {
+                        const int f = f0 + u * FPS + lane / LPF;
+                        ok[u] = f < end;
+                        fs[u] = ok[u] ? f : h;                     // lanes past the run repeat h with weight 0
+                        dv[u] = s_dx[w][fs[u] * DXS + lane % LPF % S::C];
+                    }
+#pragma unroll
+                    for (int u = 0; u < UF; ++u) {
+                        const uint32_t cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), fs[u], 64));
+                        const float fx = __shfl(c.fx, fs[u], 64);
+                        const float fy = __shfl(c.fy, fs[u], 64);
+                        const int ix = static_cast<int>(cw & 0xFFFFu), iy = static_cast<int>(cw >> 16);
+                        const int q = lane % LPF / S::C, k = lane % LPF % S::C;   // corner, channel
                         const int dxq = q & 1, dyq = q >> 1;
                         const float wq = (dxq ? fx : 1.0f - fx) * (dyq ? fy : 1.0f - fy);
-                        float* gp = &grid[((iy + dyq) * G + ix + dxq) * S::C + k];
-                        const float val = ok[u] ? wq * dv[u][pp] : 0.0f;
-                        if (FPS > 1) atomicAdd(gp, val);   // two fragments per step may share a texel
-                        else *gp += val;   // one fragment: 64 distinct addresses; a wave's LDS accesses run in order
+                        // two fragments per step may share a texel
+                        atomicAdd(&grid[((iy + dyq) * G + ix + dxq) * S::C + k], ok[u] ? wq * dv[u] : 0.0f);
                     }
                 }
             }
