@@ -108,7 +108,7 @@ struct MlpGrad {
 };
 
 template <class S, bool LOGP>
-__global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void decode_bwd_kernel(DecodeArgs a) {
     constexpr int NW = 4;
     constexpr int SW = StageCfg<S>::kWidth;
     __shared__ __align__(16) float s_stage[LOGP ? 1 : NW][LOGP ? 4 : kStageRows * SW];
@@ -158,6 +158,18 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
         f1 = static_cast<int64_t>(b_end) * 64 < E ? static_cast<int64_t>(b_end) * 64 : E;
         for (int k = lane; k < n_grid + 16; k += 64) grid[k] = 0.0f;
     }
+    // sorted list: the next batch's records, loaded one batch ahead
+    uint4 na = make_uint4(0u, 0u, 0u, 0u), nb4 = na, nc4 = na;
+    auto prefetch = [&](uint64_t bi) __attribute__((always_inline)) {
+        const int64_t fi = static_cast<int64_t>(bi) * 64 + lane;
+        if (bi < b_end && fi < E) {
+            const FragRec& fr = a.sorted[fi];
+            na = fr.a;
+            nb4 = fr.b;
+            nc4 = fr.c;
+        }
+    };
+    if (!LOGP) prefetch(b_begin);
     // the grid of triangle t goes to HBM and is cleared (whole wave)
     auto flush = [&](int t) __attribute__((always_inline)) {
         __threadfence_block();
@@ -198,14 +210,13 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
                 fc4 = fr.c;
             }
         } else {
-            const int64_t fi = static_cast<int64_t>(bi) * 64 + lane;
-            on = fi < E;
+            on = static_cast<int64_t>(bi) * 64 + lane < E;
             if (on) {
-                const FragRec& fr = a.sorted[fi];
-                fa = fr.a;
-                fb4 = fr.b;
-                fc4 = fr.c;
+                fa = na;
+                fb4 = nb4;
+                fc4 = nc4;
             }
+            prefetch(bi + 1);
         }
         const uint32_t pix = fa.x;
         const uint32_t tri = fa.y & 0x7FFFFFFFu;
@@ -236,36 +247,51 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
             constexpr int CB = MfmaWeights<S>::CB, HB = MfmaWeights<S>::HB;
             const int col = lane & 15, grp = lane >> 4;
             const MfmaWeights<S>& Wt = s_w;
+            // The four corners of block nb's texels are loaded one block ahead:
+            // they are in flight while the previous block runs on the matrix
+            // cores. Lane (col, grp) takes channels 16 cb + 4 grp .. + 3 of
+            // fragment 16 nb + col.
+            float4 qv[CB][4];
+            float qw[4];
+            auto gather = [&](int nb) __attribute__((always_inline)) {
+                const int src = 16 * nb + col;
+                const bool on_n = __shfl(static_cast<int>(on), src, 64) != 0;
+                const uint32_t tri_n = static_cast<uint32_t>(__shfl(static_cast<int>(tri), src, 64));
+                const uint32_t cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), src, 64));
+                const float fx = __shfl(c.fx, src, 64), fy = __shfl(c.fy, src, 64);
+                qw[0] = (1.0f - fx) * (1.0f - fy);
+                qw[1] = fx * (1.0f - fy);
+                qw[2] = (1.0f - fx) * fy;
+                qw[3] = fx * fy;
+                // unconditional loads (an empty lane reads texel 0 of triangle
+                // 0 and its input is zeroed), so that the wait before their use
+                // can leave the next block's loads in flight
+                const size_t t00 =
+                    on_n ? ((static_cast<size_t>(tri_n) * G + (cw >> 16)) * G + (cw & 0xFFFFu)) * S::C : 0;
+                const size_t toff[4] = {0, S::C, static_cast<size_t>(G) * S::C, static_cast<size_t>(G + 1) * S::C};
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int ch = 16 * cb + 4 * grp < S::C ? 16 * cb + 4 * grp : 0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) qv[cb][q] = *reinterpret_cast<gfloat4*>(feats + t00 + toff[q] + ch);
+                }
+            };
+            gather(0);
             for (int nb = 0; nb < 4; ++nb) {   // fragment 16 nb + col
                 const int src = 16 * nb + col;
                 const bool on_n = __shfl(static_cast<int>(on), src, 64) != 0;
                 // inputs, unit-major: channels 16 cb + 4 grp .. + 3
                 f4v xin[CB];
-                {
-                    const uint32_t tri_n = static_cast<uint32_t>(__shfl(static_cast<int>(tri), src, 64));
-                    const uint32_t cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), src, 64));
-                    const float fx = __shfl(c.fx, src, 64), fy = __shfl(c.fy, src, 64);
-                    const float w00 = (1.0f - fx) * (1.0f - fy), w10 = fx * (1.0f - fy), w01 = (1.0f - fx) * fy,
-                                w11 = fx * fy;
-                    const size_t t00 = ((static_cast<size_t>(tri_n) * G + (cw >> 16)) * G + (cw & 0xFFFFu)) * S::C;
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-                        const int ch = 16 * cb + 4 * grp;
-                        f4v v = {0.f, 0.f, 0.f, 0.f};
-                        if (on_n && ch < S::C) {
-                            const float4 q00 = *reinterpret_cast<gfloat4*>(feats + t00 + ch);
-                            const float4 q10 = *reinterpret_cast<gfloat4*>(feats + t00 + S::C + ch);
-                            const float4 q01 = *reinterpret_cast<gfloat4*>(feats + t00 + static_cast<size_t>(G) * S::C + ch);
-                            const float4 q11 =
-                                *reinterpret_cast<gfloat4*>(feats + t00 + static_cast<size_t>(G + 1) * S::C + ch);
-                            v[0] = w00 * q00.x + w10 * q10.x + w01 * q01.x + w11 * q11.x;
-                            v[1] = w00 * q00.y + w10 * q10.y + w01 * q01.y + w11 * q11.y;
-                            v[2] = w00 * q00.z + w10 * q10.z + w01 * q01.z + w11 * q11.z;
-                            v[3] = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
-                        }
-                        xin[cb] = v;
-                    }
+                for (int cb = 0; cb < CB; ++cb) {
+                    const bool use = on_n && 16 * cb + 4 * grp < S::C;
+                    const float4 q00 = qv[cb][0], q10 = qv[cb][1], q01 = qv[cb][2], q11 = qv[cb][3];
+                    xin[cb][0] = use ? qw[0] * q00.x + qw[1] * q10.x + qw[2] * q01.x + qw[3] * q11.x : 0.0f;
+                    xin[cb][1] = use ? qw[0] * q00.y + qw[1] * q10.y + qw[2] * q01.y + qw[3] * q11.y : 0.0f;
+                    xin[cb][2] = use ? qw[0] * q00.z + qw[1] * q10.z + qw[2] * q01.z + qw[3] * q11.z : 0.0f;
+                    xin[cb][3] = use ? qw[0] * q00.w + qw[1] * q10.w + qw[2] * q01.w + qw[3] * q11.w : 0.0f;
                 }
+                if (nb < 3) gather(nb + 1);
                 // forward
                 f4v h0[HB];
                 mfma_layer<HB, CB, true>(Wt.l0, Wt.b0, xin, h0, lane);
@@ -359,13 +385,17 @@ __global__ __launch_bounds__(256) void decode_bwd_kernel(DecodeArgs a) {
             const size_t t00 = ((static_cast<size_t>(tri) * G + c.iy) * G + c.ix) * S::C;
             const size_t t10 = t00 + S::C, t01 = t00 + static_cast<size_t>(G) * S::C, t11 = t01 + S::C;
             // texture position -> barycentrics -> vertex screen positions and 1/w
-            float dfx = 0.f, dfy = 0.f;
+            // d f / d(gx, gy) from the four corners' dot products with the feature gradient
+            float s00 = 0.f, s10 = 0.f, s01 = 0.f, s11 = 0.f;
 #pragma unroll
             for (int k = 0; k < S::C; ++k) {
-                const float T00 = feats[t00 + k], T10 = feats[t10 + k], T01 = feats[t01 + k], T11 = feats[t11 + k];
-                dfx = __builtin_fmaf(dx[k], (1.0f - c.fy) * (T10 - T00) + c.fy * (T11 - T01), dfx);
-                dfy = __builtin_fmaf(dx[k], (1.0f - c.fx) * (T01 - T00) + c.fx * (T11 - T10), dfy);
+                s00 = __builtin_fmaf(dx[k], feats[t00 + k], s00);
+                s10 = __builtin_fmaf(dx[k], feats[t10 + k], s10);
+                s01 = __builtin_fmaf(dx[k], feats[t01 + k], s01);
+                s11 = __builtin_fmaf(dx[k], feats[t11 + k], s11);
             }
+            const float dfx = (1.0f - c.fy) * (s10 - s00) + c.fy * (s11 - s01);
+            const float dfy = (1.0f - c.fx) * (s01 - s00) + c.fx * (s11 - s10);
             const float gm1 = static_cast<float>(G - 1);
             float iwv[3];
             int32_t Xv[3], Yv[3];

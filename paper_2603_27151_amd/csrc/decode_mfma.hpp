@@ -131,7 +131,8 @@ __device__ __forceinline__ void mfma_layer(const f4v (*w)[IB][64], const f4v (*b
         }
         if (RELU) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] = acc[i] > 0.0f ? acc[i] : 0.0f;
+            for (int i = 0; i < 4; ++i)   // max(x, 0) on the bit pattern: one integer max, no canonicalisation
+                acc[i] = __int_as_float(max(__float_as_int(acc[i]), 0));
         }
         out[ob] = acc;
     }
