@@ -43,47 +43,60 @@ struct StageCfg {
 // on the matrix cores: the contraction runs over fragments, four per
 // v_mfma_f32_16x16x4f32 (A[m][k] = d[f_k][m], B[k][n] = a[f_k][n]); dW is
 // tiled in 16x16 blocks held in registers (4 per lane per block), padded
-// with zeros where DIN or DOUT is below 16. Lane j < DOUT owns db_j.
-template <int DIN, int DOUT>
+// with zeros where DIN or DOUT is below 16. The bias gradient sum_f d_f is
+// kept per lane in the unit-major layout of d (units 16 bo + 4 grp + i of the
+// lane's fragments; for the output layer, OUTL, output grp in element 0) and
+// summed over the lanes of a lane group at the end.
+template <int DIN, int DOUT, bool OUTL = false>
 struct LayerAcc {
     static constexpr int BI = (DIN + 15) / 16;
     static constexpr int BO = (DOUT + 15) / 16;
     static constexpr int NB = BI * BO;
-    static_assert(DOUT <= 64, "bias ownership assumes DOUT <= 64");
+    static_assert(!OUTL || DOUT == 4, "the output layer has four outputs, one per lane group");
     f4v w[NB];
-    float b;
+    f4v bs[BO];
     __device__ __forceinline__ void zero() {
 #pragma unroll
         for (int i = 0; i < NB; ++i) w[i] = f4v{0.f, 0.f, 0.f, 0.f};
-        b = 0.0f;
-    }
-    // kStageRows (16) staged fragments: in[r][DIN] and d[r][DOUT] in LDS, rows padded by kRowPad
-    __device__ __forceinline__ void accumulate(const float* __restrict__ in, const float* __restrict__ d, int lane) {
-        const int col = lane & 15, kq = lane >> 4;
 #pragma unroll
-        for (int kk = 0; kk < kStageRows / 4; ++kk) {
+        for (int i = 0; i < BO; ++i) bs[i] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    __device__ __forceinline__ void add_bias(const f4v (&d)[BO]) {
+        if (OUTL) {
+            bs[0][0] += d[0][0];
+        } else {
+#pragma unroll
+            for (int i = 0; i < BO; ++i) bs[i] += d[i];
+        }
+    }
+    // kStageRows (16) staged fragments: in[r][DIN] and d[r][DOUT] in LDS, rows
+    // padded by kRowPad; every step's operands are read before the first product
+    __device__ __forceinline__ void accumulate(const float* __restrict__ in, const float* __restrict__ d, int lane) {
+        constexpr int KS = kStageRows / 4;
+        const int col = lane & 15, kq = lane >> 4;
+        float av[KS][BO], bv[KS][BI];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
             const int r = 4 * kk + kq;
-            float av[BO], bv[BI];
 #pragma unroll
             for (int bo = 0; bo < BO; ++bo) {
                 const int m = 16 * bo + col;
-                av[bo] = m < DOUT ? d[r * (DOUT + kRowPad) + m] : 0.0f;
+                av[kk][bo] = m < DOUT ? d[r * (DOUT + kRowPad) + m] : 0.0f;
             }
 #pragma unroll
             for (int bi = 0; bi < BI; ++bi) {
                 const int n = 16 * bi + col;
-                bv[bi] = n < DIN ? in[r * (DIN + kRowPad) + n] : 0.0f;
+                bv[kk][bi] = n < DIN ? in[r * (DIN + kRowPad) + n] : 0.0f;
             }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
             for (int bo = 0; bo < BO; ++bo)
 #pragma unroll
                 for (int bi = 0; bi < BI; ++bi)
-                    w[bo * BI + bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bo], bv[bi], w[bo * BI + bi], 0, 0, 0);
-        }
-        if (lane < DOUT) {
-#pragma unroll
-            for (int r = 0; r < kStageRows; ++r) b += d[r * (DOUT + kRowPad) + lane];
-        }
+                    w[bo * BI + bi] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk][bo], bv[kk][bi], w[bo * BI + bi], 0, 0, 0);
     }
     // D of a 16x16 block: lane l holds column l % 16, rows 4 (l / 16) + i
     __device__ __forceinline__ void store(float* __restrict__ row, int w_off, int b_off, int lane) const {
@@ -96,7 +109,26 @@ struct LayerAcc {
                     const int m = 16 * bo + 4 * (lane >> 4) + i, n = 16 * bi + (lane & 15);
                     if (m < DOUT && n < DIN) row[w_off + m * DIN + n] = w[bo * BI + bi][i];
                 }
-        if (lane < DOUT) row[b_off + lane] = b;
+        // bias: sum over the 16 lanes (fragments) of each lane group
+#pragma unroll
+        for (int bo = 0; bo < BO; ++bo) {
+            f4v v = bs[bo];
+#pragma unroll
+            for (int sh = 1; sh < 16; sh <<= 1)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], sh, 64);
+            if ((lane & 15) == 0) {
+                if (OUTL) {
+                    row[b_off + (lane >> 4)] = v[0];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int m = 16 * bo + 4 * (lane >> 4) + i;
+                        if (m < DOUT) row[b_off + m] = v[i];
+                    }
+                }
+            }
+        }
     }
 };
 
@@ -104,7 +136,7 @@ template <class S>
 struct MlpGrad {
     LayerAcc<S::C, S::H> l0;
     LayerAcc<S::H, S::H> mid[S::NH > 1 ? S::NH - 1 : 1];
-    LayerAcc<S::H, 4> out;
+    LayerAcc<S::H, 4, true> out;
 };
 
 template <class S, bool LOGP>
@@ -323,6 +355,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 st[kStageRows * (S::H + kRowPad) + col * (4 + kRowPad) + grp] = dO;
                 __threadfence_block();
                 acc.out.accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
+                {
+                    const f4v db[1] = {f4v{dO, 0.f, 0.f, 0.f}};
+                    acc.out.add_bias(db);
+                }
                 __threadfence_block();
                 // back through the output layer: K = the four outputs, one step
                 f4v dl[HB];
@@ -340,6 +376,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     stage_rows<HB>(st + kStageRows * (S::H + kRowPad), S::H, dl, lane);
                     __threadfence_block();
                     acc.mid[0].accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
+                    acc.mid[0].add_bias(dl);
                     __threadfence_block();
                     mfma_back<HB, HB, true>(Wt.l1T, dl, h0, dh0, lane);
                 } else {
@@ -351,6 +388,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 stage_rows<HB>(st + kStageRows * (S::C + kRowPad), S::H, dh0, lane);
                 __threadfence_block();
                 acc.l0.accumulate(st, st + kStageRows * (S::C + kRowPad), lane);
+                acc.l0.add_bias(dh0);
                 __threadfence_block();
                 // feature gradients into the rows [fragment][C] kept past the stage's working rows
                 f4v dxv[CB];
