@@ -173,6 +173,11 @@ struct MlpShape {
 
 // Texture position of perspective-correct barycentrics (b1, b2) on a G x G
 // grid: vertex 0 -> (0,0), vertex 1 -> (G-1,0), vertex 2 -> (0,G-1).
+// Orders one wave's LDS accesses for the compiler only: a wave's LDS
+// operations execute in issue order, so a lane's read sees another lane's
+// earlier write of the same wave without a wait.
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 struct Cell {
     int ix, iy;
     float fx, fy;

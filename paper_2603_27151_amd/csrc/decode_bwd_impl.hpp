@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     if (!LOGP) prefetch(b_begin);
     // the grid of triangle t goes to HBM and is cleared (whole wave)
     auto flush = [&](int t) __attribute__((always_inline)) {
-        __threadfence_block();
+        wave_fence();
         const bool owned = a.tri_off[t] >= f0 && a.tri_off[t + 1] <= f1;
         float* gf = a.grad_feats + static_cast<size_t>(t) * n_grid;
         for (int k = lane; k < n_grid; k += 64) {
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             if (owned) *gv = a.accumulate ? *gv + v : v;
             else if (v != 0.0f) atomicAdd(gv, v);
         }
-        __threadfence_block();
+        wave_fence();
     };
     for (uint64_t bi = b_begin; bi < b_end; bi += b_step) {
         bool on;
@@ -353,13 +353,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 // output-layer weight gradient (rows = this block's fragments)
                 stage_rows<HB>(st, S::H, hl, lane);
                 st[kStageRows * (S::H + kRowPad) + col * (4 + kRowPad) + grp] = dO;
-                __threadfence_block();
+                wave_fence();
                 acc.out.accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
                 {
                     const f4v db[1] = {f4v{dO, 0.f, 0.f, 0.f}};
                     acc.out.add_bias(db);
                 }
-                __threadfence_block();
+                wave_fence();
                 // back through the output layer: K = the four outputs, one step
                 f4v dl[HB];
 #pragma unroll
@@ -374,10 +374,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     // hidden layer 1 weight gradient, then back to layer 0
                     stage_rows<HB>(st, S::H, h0, lane);
                     stage_rows<HB>(st + kStageRows * (S::H + kRowPad), S::H, dl, lane);
-                    __threadfence_block();
+                    wave_fence();
                     acc.mid[0].accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
                     acc.mid[0].add_bias(dl);
-                    __threadfence_block();
+                    wave_fence();
                     mfma_back<HB, HB, true>(Wt.l1T, dl, h0, dh0, lane);
                 } else {
 #pragma unroll
@@ -386,10 +386,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 // first-layer weight gradient
                 stage_rows<CB>(st, S::C, xin, lane);
                 stage_rows<HB>(st + kStageRows * (S::C + kRowPad), S::H, dh0, lane);
-                __threadfence_block();
+                wave_fence();
                 acc.l0.accumulate(st, st + kStageRows * (S::C + kRowPad), lane);
                 acc.l0.add_bias(dh0);
-                __threadfence_block();
+                wave_fence();
                 // feature gradients into the rows [fragment][C] kept past the stage's working rows
                 f4v dxv[CB];
                 mfma_back<CB, HB, false>(Wt.l0T, dh0, nullptr, dxv, lane);
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                             make_float4(dxv[cb][0], dxv[cb][1], dxv[cb][2], dxv[cb][3]);
                 }
             }
-            __threadfence_block();
+            wave_fence();
         }
         float dx[S::C];   // this lane's fragment
 #pragma unroll
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             *reinterpret_cast<float4*>(st + 4 * lane) = make_float4(x0 * y0, x1 * y0, x0 * y1, x1 * y1);
             cbase = (c.iy * G + c.ix) * S::C;
         }
-        __threadfence_block();
+        wave_fence();
         const uint32_t tkey = on ? tri : 0xFFFFFFFFu;
         const uint32_t tprev = __shfl_up(tkey, 1, 64);
         uint64_t heads = __ballot(lane == 0 || tprev != tkey);
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     }
                 }
             }
-            __threadfence_block();
+            wave_fence();
         }
     }
     if (!LOGP && cur >= 0) flush(cur);
