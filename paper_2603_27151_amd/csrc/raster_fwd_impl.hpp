@@ -361,6 +361,11 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     // E > 0, or E == 0 on an owning edge, is E > -1/2 for integer E
                     thr[e] = (ny[e] < 0 || (ny[e] == 0 && nx[e] > 0)) ? -0.5 : 0.0;
                 }
+                // a covered pixel whose best key is already at or below the
+                // triangle's depth bound can take no fragment of it (keys only
+                // fall), so it is left out of the mask here rather than
+                // rejected one combination at a time later
+                const uint64_t* __restrict__ kb = &L.key[cblk * 64];
 #pragma unroll
                 for (int pv2 = 0; pv2 < 8; ++pv2) {
                     double c[3];
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     uint32_t row = 0;
 #pragma unroll
                     for (int pu2 = 0; pu2 < 8; ++pu2) {
-                        bool in = true;
+                        bool in = cent < kb[pv2 * 8 + pu2];
 #pragma unroll
                         for (int e = 0; e < 3; ++e)
                             in = in & (__builtin_fma(static_cast<double>(pu2), ea[e], c[e]) > thr[e]);
