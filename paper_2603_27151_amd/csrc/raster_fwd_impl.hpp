@@ -244,16 +244,37 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             if (qn == 0) break;
             const int n = qn < 64 ? qn : 64;
             run_batch(n);
-            // the rest moves to the front; the reads of each chunk precede its writes,
-            // and a chunk writes only where the previous chunk has read
-            for (int i = lane; i < qn - n; i += 64) {
-                L.qkey[i] = L.qkey[n + i];
-                L.qt[0][i] = L.qt[0][n + i];
-                L.qt[1][i] = L.qt[1][n + i];
-                L.qt[2][i] = L.qt[2][n + i];
-                L.qpl[i] = L.qpl[n + i];
+            // the rest moves to the front, less the candidates that a key this
+            // batch set already beats (they were queued against the older keys
+            // and would decode to nothing); the reads of each chunk precede its
+            // writes, and a chunk writes only where it or the previous chunk has read
+            int kept = 0;
+            for (int i0 = n; i0 < qn; i0 += 64) {
+                const int i = i0 + lane;
+                uint64_t k = 0;
+                float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+                uint16_t qp = 0;
+                bool keep = false;
+                if (i < qn) {
+                    k = L.qkey[i];
+                    t0 = L.qt[0][i];
+                    t1 = L.qt[1][i];
+                    t2 = L.qt[2][i];
+                    qp = L.qpl[i];
+                    keep = k < L.key[qp];
+                }
+                const uint64_t m = __ballot(keep);
+                if (keep) {
+                    const int pos = kept + __popcll(m & lanemask_lt());
+                    L.qkey[pos] = k;
+                    L.qt[0][pos] = t0;
+                    L.qt[1][pos] = t1;
+                    L.qt[2][pos] = t2;
+                    L.qpl[pos] = qp;
+                }
+                kept += __popcll(m);
             }
-            qn -= n;
+            qn = kept;
             __syncthreads();
             continue;
         }
