@@ -148,6 +148,12 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     gfloat* __restrict__ feats = as_global(uniform_ptr(sc.feats));
     const float* mlp_p = uniform_ptr(sc.mlp);
     const TriRec* __restrict__ recs = uniform_ptr(a.recs + vd.rec_base);
+    // the view's fields that the batches and the epilogue use, read once: read
+    // through vd after a store, they would be loaded again (the store may alias)
+    const uint32_t view_id = vd.view_id;
+    const int64_t pix_base = vd.pix_base;
+    float* const color_base = uniform_ptr(vd.color_out ? vd.color_out : a.color + 3 * vd.pix_base);
+    uint64_t* const vis_base = uniform_ptr(vd.vis_out ? vd.vis_out : (a.vis ? a.vis + vd.pix_base : nullptr));
 
     // the pixels' best keys live in L.key; per block, the largest of them (wave-uniform)
     uint64_t wmaxb[NB];
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             if (a.o.mode == 0) {
                 const float alpha = sigmoid_c(o[3]);
                 const uint32_t pidx = static_cast<uint32_t>(gy * W + gx);
-                pass = uniform24(a.o.seed, pidx, tri, vd.view_id, a.o.step) < alpha;
+                pass = uniform24(a.o.seed, pidx, tri, view_id, a.o.step) < alpha;
             } else {
                 pass = o[3] > 0.0f;
             }
@@ -194,7 +200,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             if (a.log_frag) {
                 const uint32_t at = log_cursor + static_cast<uint32_t>(lane);
                 if (at < a.log_region) {
-                    const int64_t pg = vd.pix_base + static_cast<int64_t>(gy) * W + gx;
+                    const int64_t pg = pix_base + static_cast<int64_t>(gy) * W + gx;
                     a.log_frag[log_base + at] =
                         make_uint4(static_cast<uint32_t>(pg), tri, __float_as_uint(b1), __float_as_uint(b2));
                     a.log_aux[log_base + at] = make_uint2(static_cast<uint32_t>(key >> 32), static_cast<uint32_t>(v));
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             // the key again writes after this one, behind the workgroup barriers between them)
             const int blk = pl >> 6, p = pl & 63;
             const int64_t off = static_cast<int64_t>(ry + (blk / BR) * 8 + (p >> 3)) * W + rx + (blk % BR) * 8 + (p & 7);
-            float* col = vd.color_out ? vd.color_out + 3 * off : a.color + 3 * (vd.pix_base + off);
+            float* col = color_base + 3 * off;
             col[0] = sigmoid_c(o[0]);
             col[1] = sigmoid_c(o[1]);
             col[2] = sigmoid_c(o[2]);
@@ -472,10 +478,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         const int pl = b * 64 + lane;
         const uint64_t key = L.key[pl];
         const int64_t off = static_cast<int64_t>(gy) * W + gx;
-        if (vd.vis_out) vd.vis_out[off] = key;
-        else if (a.vis) a.vis[vd.pix_base + off] = key;
+        if (vis_base) vis_base[off] = key;
         if (key == kBgKey) {   // covered pixels got their colour when their best key was set
-            float* col = vd.color_out ? vd.color_out + 3 * off : a.color + 3 * (vd.pix_base + off);
+            float* col = color_base + 3 * off;
             col[0] = a.o.bg[0];
             col[1] = a.o.bg[1];
             col[2] = a.o.bg[2];
