@@ -47,6 +47,10 @@ __device__ __forceinline__ guint4* as_global(const uint4* p) {
 }
 
 // Per-view descriptor (device copy built by the host for every call).
+// MI355X has eight XCDs, each with its own L2; consecutive workgroups of a
+// launch go to them in turn.
+constexpr int kXcds = 8;
+
 struct ViewDesc {
     float M[16];             // view-projection, row-major
     int32_t W, H;

@@ -46,9 +46,14 @@ __global__ __launch_bounds__(256) void edge_weight_kernel(const ViewDesc* __rest
                                                           Opts o, const uint64_t* __restrict__ vis,
                                                           const float* __restrict__ color,
                                                           const float* __restrict__ gcol, float2* __restrict__ ew) {
+    // Workgroups are dealt to the eight XCDs in turn; block b takes pixel block
+    // (b % 8) * per + b / 8, so that each XCD walks one contiguous eighth of the
+    // pixels and the rows above and below a block are read through its own L2.
+    const uint32_t per = gridDim.x / kXcds;
+    const uint32_t pb = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
     // the view of the workgroup's first pixel (a wave-uniform search), then per lane
     // the few steps past it when the workgroup straddles views
-    const int64_t p0 = blockIdx.x * static_cast<int64_t>(blockDim.x);
+    const int64_t p0 = pb * static_cast<int64_t>(blockDim.x);
     int lo = 0, hi = V - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -59,8 +64,9 @@ __global__ __launch_bounds__(256) void edge_weight_kernel(const ViewDesc* __rest
     if (p >= P) return;
     while (lo + 1 < V && views[lo + 1].pix_base <= p) ++lo;
     const ViewDesc& vd = views[lo];
-    const int64_t local = p - vd.pix_base;
-    const int x = static_cast<int>(local % vd.W), y = static_cast<int>(local / vd.W);
+    const uint32_t Wv = static_cast<uint32_t>(vd.W);
+    const uint32_t local = static_cast<uint32_t>(p - vd.pix_base);   // below W * H <= 2^28
+    const int y = static_cast<int>(local / Wv), x = static_cast<int>(local - static_cast<uint32_t>(y) * Wv);
     const uint64_t kp = vis[p];
     float e[2] = {0.0f, 0.0f};
     if (kp != kBgKey) {   // a background pixel never occludes
@@ -97,8 +103,11 @@ __global__ __launch_bounds__(256) void edge_weight_kernel(const ViewDesc* __rest
 void launch_edge_weights(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis,
                          const float* color, const float* grad_color, float2* ew, hipStream_t s) {
     if (P <= 0) return;
-    hipLaunchKernelGGL(edge_weight_kernel, dim3(static_cast<unsigned>((P + 255) / 256)), dim3(256), 0, s, views, V,
-                       P, o, vis, color, grad_color, ew);
+    // a multiple of the XCD count, so that the block remapping is a bijection
+    // (blocks past the last pixel return at once)
+    const int64_t nb = ((P + 255) / 256 + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(edge_weight_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, views, V, P, o, vis,
+                       color, grad_color, ew);
 }
 
 // ---------------------------------------------------------------------------
