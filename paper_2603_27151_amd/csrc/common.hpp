@@ -29,11 +29,15 @@ using cfloat = const float __attribute__((address_space(4)));
 using gfloat = const float __attribute__((address_space(1)));
 using gfloat4 = const float4 __attribute__((address_space(1)));
 using guint4 = const uint4 __attribute__((address_space(1)));
+using gfloat_w = float __attribute__((address_space(1)));
+using guint64_w = uint64_t __attribute__((address_space(1)));
 #else
 using cfloat = const float;
 using gfloat = const float;
 using gfloat4 = const float4;
 using guint4 = const uint4;
+using gfloat_w = float;
+using guint64_w = uint64_t;
 #endif
 
 __device__ __forceinline__ cfloat* as_const(const float* p) {
@@ -44,6 +48,14 @@ __device__ __forceinline__ gfloat* as_global(const float* p) {
 }
 __device__ __forceinline__ guint4* as_global(const uint4* p) {
     return reinterpret_cast<guint4*>(reinterpret_cast<uintptr_t>(p));
+}
+// writable global pointers: stores through them are global stores, not flat
+// ones (which also count as LDS operations in the wait counters)
+__device__ __forceinline__ gfloat_w* as_global_w(float* p) {
+    return reinterpret_cast<gfloat_w*>(reinterpret_cast<uintptr_t>(p));
+}
+__device__ __forceinline__ guint64_w* as_global_w(uint64_t* p) {
+    return reinterpret_cast<guint64_w*>(reinterpret_cast<uintptr_t>(p));
 }
 
 // Per-view descriptor (device copy built by the host for every call).

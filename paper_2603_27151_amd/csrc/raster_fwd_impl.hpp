@@ -152,8 +152,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     // through vd after a store, they would be loaded again (the store may alias)
     const uint32_t view_id = vd.view_id;
     const int64_t pix_base = vd.pix_base;
-    float* const color_base = uniform_ptr(vd.color_out ? vd.color_out : a.color + 3 * vd.pix_base);
-    uint64_t* const vis_base = uniform_ptr(vd.vis_out ? vd.vis_out : (a.vis ? a.vis + vd.pix_base : nullptr));
+    gfloat_w* const color_base = as_global_w(uniform_ptr(vd.color_out ? vd.color_out : a.color + 3 * vd.pix_base));
+    guint64_w* const vis_base =
+        as_global_w(uniform_ptr(vd.vis_out ? vd.vis_out : (a.vis ? a.vis + vd.pix_base : nullptr)));
 
     // the pixels' best keys live in L.key; per block, the largest of them (wave-uniform)
     uint64_t wmaxb[NB];
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             // the key again writes after this one, behind the workgroup barriers between them)
             const int blk = pl >> 6, p = pl & 63;
             const int64_t off = static_cast<int64_t>(ry + (blk / BR) * 8 + (p >> 3)) * W + rx + (blk % BR) * 8 + (p & 7);
-            float* col = color_base + 3 * off;
+            gfloat_w* col = color_base + 3 * off;
             col[0] = sigmoid_c(o[0]);
             col[1] = sigmoid_c(o[1]);
             col[2] = sigmoid_c(o[2]);
@@ -471,16 +472,24 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         c0 += 64;
         __syncthreads();
     }
+    // every read first, then the stores (a wait for a read issued between
+    // stores would also wait for the stores)
+    uint64_t okey[NB];
+    int64_t ooff[NB];
+    bool oin[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int gx = rx + (b % BR) * 8 + pu, gy = ry + (b / BR) * 8 + pv;
-        if (gx >= W || gy >= H) continue;
-        const int pl = b * 64 + lane;
-        const uint64_t key = L.key[pl];
-        const int64_t off = static_cast<int64_t>(gy) * W + gx;
-        if (vis_base) vis_base[off] = key;
-        if (key == kBgKey) {   // covered pixels got their colour when their best key was set
-            float* col = color_base + 3 * off;
+        oin[b] = gx < W && gy < H;
+        ooff[b] = static_cast<int64_t>(gy) * W + gx;
+        okey[b] = L.key[b * 64 + lane];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (!oin[b]) continue;
+        if (vis_base) vis_base[ooff[b]] = okey[b];
+        if (okey[b] == kBgKey) {   // covered pixels got their colour when their best key was set
+            gfloat_w* col = color_base + 3 * ooff[b];
             col[0] = a.o.bg[0];
             col[1] = a.o.bg[1];
             col[2] = a.o.bg[2];
