@@ -884,6 +884,8 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         DecodeArgs d = decode_args(c, p, a);
         d.sorted = static_cast<FragRec*>(c->sorted.p);
         d.tri_off = static_cast<int64_t*>(c->tri_off.p);
+        d.grad_color = grad_color;
+        d.edge_w = ew;
         d.grad_feats = grad_feats;
         d.grad_verts = grad_verts;
         d.accumulate = o.accumulate;

@@ -190,18 +190,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
         f1 = static_cast<int64_t>(b_end) * 64 < E ? static_cast<int64_t>(b_end) * 64 : E;
         for (int k = lane; k < n_grid + 16; k += 64) grid[k] = 0.0f;
     }
-    // sorted list: the next batch's records, loaded one batch ahead
-    uint4 na = make_uint4(0u, 0u, 0u, 0u), nb4 = na, nc4 = na;
+    // sorted list: the next batch's records, loaded one batch ahead, and the
+    // per-pixel data of its winners (colour gradient, edge weights), loaded
+    // once those records are in (after the current batch's MLP)
+    uint4 na = make_uint4(0u, 0u, 0u, 0u);   // (pixel, triangle | winner, b1, b2)
+    uint2 nx = make_uint2(0u, 0u);           // (score weight, view)
+    float ng0 = 0.f, ng1 = 0.f, ng2 = 0.f, nex = 0.f, ney = 0.f;
+    bool nvalid = false;
     auto prefetch = [&](uint64_t bi) __attribute__((always_inline)) {
         const int64_t fi = static_cast<int64_t>(bi) * 64 + lane;
-        if (bi < b_end && fi < E) {
-            const FragRec& fr = a.sorted[fi];
-            na = fr.a;
-            nb4 = fr.b;
-            nc4 = fr.c;
+        nvalid = bi < b_end && fi < E;
+        if (nvalid) {
+            const FragRec fr = a.sorted[fi];
+            na = make_uint4(fr.p0.x, fr.p0.y, fr.p1.x, fr.p1.y);
+            nx = fr.x;
         }
     };
-    if (!LOGP) prefetch(b_begin);
+    auto pixfetch = [&]() __attribute__((always_inline)) {
+        ng0 = ng1 = ng2 = nex = ney = 0.0f;
+        if (nvalid && (na.y >> 31)) {
+            const size_t p = na.x;
+            ng0 = a.grad_color[3 * p];
+            ng1 = a.grad_color[3 * p + 1];
+            ng2 = a.grad_color[3 * p + 2];
+            if (a.edge_w) {
+                const float2 e = a.edge_w[p];
+                nex = e.x;
+                ney = e.y;
+            }
+        }
+    };
+    if (!LOGP) {
+        prefetch(b_begin);
+        pixfetch();
+    }
     // the grid of triangle t goes to HBM and is cleared (whole wave)
     auto flush = [&](int t) __attribute__((always_inline)) {
         wave_fence();
@@ -236,17 +258,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             const uint32_t in_region = (static_cast<uint32_t>(bi) - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
             on = in_region < (cr < a.region ? cr : a.region);
             if (on) {
-                const FragRec& fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
-                fa = fr.a;
-                fb4 = fr.b;
-                fc4 = fr.c;
+                const FragRec fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
+                fa = make_uint4(fr.p0.x, fr.p0.y, fr.p1.x, fr.p1.y);
             }
         } else {
             on = static_cast<int64_t>(bi) * 64 + lane < E;
             if (on) {
                 fa = na;
-                fb4 = nb4;
-                fc4 = nc4;
+                fb4 = make_uint4(nx.x, __float_as_uint(ng0), __float_as_uint(ng1), __float_as_uint(ng2));
+                fc4 = make_uint4(__float_as_uint(nex), __float_as_uint(ney), nx.y, 0u);
             }
             prefetch(bi + 1);
         }
@@ -412,6 +432,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             dx[k + 2] = v.z;
             dx[k + 3] = v.w;
         }
+        pixfetch();   // the next batch's winners
         // --- the winner's world-space vertex gradient ---
         float gw[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (win) {

@@ -20,7 +20,7 @@ struct ReplayQueue {
     uint32_t pix[NW][128];
     uint32_t tri[NW][128];     // triangle | winner << 31
     float t[3][NW][128];       // beta_i / w_i
-    float g[6][NW][128];       // the pixel's score weight, colour gradient and edge weights
+    float gl[NW][128];         // the pixel's score weight
 };
 
 template <int TS>
@@ -106,11 +106,9 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                 float b1, b2;   // the perspective division, on full batches
                 persp_from_t(q.t[0][w][lane], q.t[1][w][lane], q.t[2][w][lane], b1, b2);
                 FragRec* f = a.frags + region_base + at;
-                f->a = make_uint4(q.pix[w][lane], q.tri[w][lane], __float_as_uint(b1), __float_as_uint(b2));
-                f->b = make_uint4(__float_as_uint(q.g[0][w][lane]), __float_as_uint(q.g[1][w][lane]),
-                                  __float_as_uint(q.g[2][w][lane]), __float_as_uint(q.g[3][w][lane]));
-                f->c = make_uint4(__float_as_uint(q.g[4][w][lane]), __float_as_uint(q.g[5][w][lane]),
-                                  static_cast<uint32_t>(v), 0u);
+                f->p0 = make_uint2(q.pix[w][lane], q.tri[w][lane]);
+                f->p1 = make_uint2(__float_as_uint(b1), __float_as_uint(b2));
+                f->x = make_uint2(__float_as_uint(q.gl[w][lane]), static_cast<uint32_t>(v));
             }
             // fragments per triangle, counting only those stored (one atomic
             // per run of equal triangles)
@@ -179,8 +177,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                             q.tri[w][pos] = ch.tri[j] | (win ? 0x80000000u : 0u);
 #pragma unroll
                             for (int i = 0; i < 3; ++i) q.t[i][w][pos] = f.beta[i] * ch.iw[i][j];
-#pragma unroll
-                            for (int i = 0; i < 6; ++i) q.g[i][w][pos] = gp[k][i];
+                            q.gl[w][pos] = gp[k][0];
                         }
                         qn += __popcll(mk);
                         if (qn >= 64) {
@@ -191,8 +188,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                                 q.tri[w][lane] = q.tri[w][64 + lane];
 #pragma unroll
                                 for (int i = 0; i < 3; ++i) q.t[i][w][lane] = q.t[i][w][64 + lane];
-#pragma unroll
-                                for (int i = 0; i < 6; ++i) q.g[i][w][lane] = q.g[i][w][64 + lane];
+                                q.gl[w][lane] = q.gl[w][64 + lane];
                             }
                             qn -= 64;
                             __threadfence_block();
@@ -294,14 +290,9 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
         const uint32_t cr = a.counts[lo];
         const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
         const bool on = in_region < (cr < a.region ? cr : a.region);
-        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = make_uint4(0u, 0u, 0u, 0u), fc = make_uint4(0u, 0u, 0u, 0u);
-        if (on) {
-            const FragRec& src = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
-            fa = src.a;
-            fb = src.b;
-            fc = src.c;
-        }
-        const uint32_t tri = on ? (fa.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+        FragRec fr = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
+        if (on) fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
+        const uint32_t tri = on ? (fr.p0.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
         const uint32_t tprev = __shfl_up(tri, 1, 64);
         const bool head = lane == 0 || tprev != tri;
         const uint64_t heads = __ballot(head);
@@ -315,10 +306,7 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
         const int hl = 63 - __builtin_clzll(upto);   // lane 0 is always a head
         const int hb = __shfl(base, hl, 64);
         if (on) {
-            FragRec& dst = a.sorted[a.tri_off[tri] + hb + (lane - hl)];
-            dst.a = fa;
-            dst.b = fb;
-            dst.c = fc;
+            a.sorted[a.tri_off[tri] + hb + (lane - hl)] = fr;
         }
     }
 }
@@ -355,7 +343,7 @@ __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
         const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
         const bool on = in_region < (cr < a.log_region ? cr : a.log_region);
         bool keep = false, win = false;
-        uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = make_uint4(0u, 0u, 0u, 0u), fc = make_uint4(0u, 0u, 0u, 0u);
+        FragRec fr = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
         if (on) {
             const uint64_t at = static_cast<uint64_t>(lo) * a.log_region + in_region;
             const uint4 e = a.log_frag[at];
@@ -379,23 +367,18 @@ __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
                 const bool any = g[0] != 0.f || g[1] != 0.f || g[2] != 0.f || g[3] != 0.f || g[4] != 0.f || g[5] != 0.f;
                 keep = (win && any) || (front && g[0] != 0.0f);
             }
-            fa = make_uint4(e.x, e.y | (win ? 0x80000000u : 0u), e.z, e.w);
-            fb = make_uint4(__float_as_uint(g[0]), __float_as_uint(g[1]), __float_as_uint(g[2]), __float_as_uint(g[3]));
-            fc = make_uint4(__float_as_uint(g[4]), __float_as_uint(g[5]), x.y, 0u);
+            fr.p0 = make_uint2(e.x, e.y | (win ? 0x80000000u : 0u));
+            fr.p1 = make_uint2(e.z, e.w);
+            fr.x = make_uint2(__float_as_uint(g[0]), x.y);
         }
         const uint64_t km = __ballot(keep);
         const uint32_t pos = cursor + static_cast<uint32_t>(__popcll(km & lanemask_lt()));
-        if (keep && pos < a.region) {
-            FragRec& d = a.frags[out_base + pos];
-            d.a = fa;
-            d.b = fb;
-            d.c = fc;
-        }
+        if (keep && pos < a.region) a.frags[out_base + pos] = fr;
         // fragments per triangle, counting only those stored (one atomic per
         // run of equal triangles among consecutive lanes)
         if (a.tri_count) {
             const bool stored = keep && pos < a.region;
-            const uint32_t tk = stored ? (fa.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+            const uint32_t tk = stored ? (fr.p0.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
             const uint32_t tp = __shfl_up(tk, 1, 64);
             const bool head = lane == 0 || tp != tk;
             const uint64_t heads = __ballot(head);
