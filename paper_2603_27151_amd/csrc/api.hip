@@ -592,7 +592,7 @@ int decode_blocks(soup_ctx* c) { return std::max(1, std::min(c->num_cus * 4, kMa
 // one region per wave, then scan the region counts into batch offsets. The
 // fragments come from the replay (coverage re-run from the tile lists) or,
 // when from_log, from the filter of the forward's log. Regions are sized
-// from the last call's largest count with 50% headroom (else from 1.5
+// from the last call's largest count, doubled (else from 1.5
 // fragments per pixel); an overflow is detected from the counts and the
 // gather runs again, sized exactly. Returns the number of fragments in
 // *n_frag and of decode batches in *n_batch.
@@ -603,10 +603,11 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     const int nb = from_log ? decode_blocks(c) : replay_blocks(c, p);
     const int nr = nb * (from_log ? 4 : replay_waves_per_block(c->tile));
-    // per-wave counts vary between calls (tiles are handed out dynamically): 50% headroom
+    // per-wave counts vary between calls (tiles are handed out dynamically):
+    // twice the last call's largest, so that a static-mode call fits
     uint64_t hint = c->region_hint;
     if (hint && c->frag_regions && c->frag_regions != nr) hint = hint * c->frag_regions / nr + 64;
-    uint64_t region = hint ? hint + hint / 2 + 256 : (static_cast<uint64_t>(p.n_pix) * 3 / 2) / nr + 1024;
+    uint64_t region = hint ? 2 * hint + 1024 : (static_cast<uint64_t>(p.n_pix) * 3 / 2) / nr + 1024;
     soup_status st;
     if ((st = ensure(c, c->region_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
         (st = ensure(c, c->region_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
@@ -740,7 +741,10 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
                             "outside static mode");
             log_region = c->log_region;
         } else {
-            log_region = c->log_hint ? c->log_hint + c->log_hint / 2 + 256
+            // twice the last call's largest count: per-wave counts vary from call to
+            // call (regions are handed out dynamically), and a static-mode call
+            // (which cannot grow the log) must fit
+            log_region = c->log_hint ? 2 * c->log_hint + 1024
                                      : (static_cast<uint64_t>(p.n_pix) * 2) / log_nr + 1024;
             if (log_region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment log region too large");
             if ((st = ensure(c, c->log_frag, static_cast<size_t>(log_region) * log_nr * sizeof(uint4))) ||
