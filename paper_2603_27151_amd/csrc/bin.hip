@@ -234,15 +234,15 @@ __global__ __launch_bounds__(256) void sort_kernel(const int64_t* __restrict__ t
             __syncthreads();
             for (int k = 2; k <= N; k <<= 1) {
                 for (int j = k >> 1; j > 0; j >>= 1) {
-                    for (int x = threadIdx.x; x < N; x += blockDim.x) {
-                        const int xj = x ^ j;
-                        if (xj > x) {
-                            const uint64_t a = s[x], c = s[xj];
-                            const bool up = (x & k) == 0;
-                            if ((a > c) == up) {
-                                s[x] = c;
-                                s[xj] = a;
-                            }
+                    // one compare-exchange per thread and step: pair t has its lower
+                    // element at t with a zero bit inserted at j's position
+                    for (int t = threadIdx.x; t < (N >> 1); t += blockDim.x) {
+                        const int x = 2 * t - (t & (j - 1)), xj = x + j;
+                        const uint64_t a = s[x], c = s[xj];
+                        const bool up = (x & k) == 0;
+                        if ((a > c) == up) {
+                            s[x] = c;
+                            s[xj] = a;
                         }
                     }
                     __syncthreads();
