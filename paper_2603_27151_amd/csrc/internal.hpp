@@ -13,7 +13,7 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 // tile list it touches; when large chunks would leave the GPU idle (few views,
 // few triangles) the chunks are one triangle per thread, counted with global
 // atomics.
-constexpr int kBinChunk = 4096;
+constexpr int kBinChunk = 2048;
 constexpr int kHistBins = 8192;
 int bin_chunk_size(int V, int maxT, int num_cus);
 inline int bin_chunks(int maxT, int chunk) { return maxT <= 0 ? 0 : (maxT + chunk - 1) / chunk; }
