@@ -53,10 +53,11 @@ def csrc_sha1() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str, tile: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, scaled by its copy-kernel calibration; None when the
-    kernel sources changed since the counters were taken."""
+    kernel sources changed since the counters were taken, or when the summary
+    covers another workload or tile side."""
     path = os.path.join(ROOT, "profiles", "traffic_batched.txt")
     if not os.path.exists(path):
         return None
@@ -67,6 +68,8 @@ def measured_traffic(kernel: str):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("csrc_sha1") != csrc_sha1() or f"{kernel}.fetch_kb" not in kv:
+        return None
+    if kv.get("workload") != workload or kv.get("tile") != str(tile):
         return None
     return int(float(kv[f"{kernel}.fetch_kb"]) * 1024 * float(kv["fetch_scale"]) +
                float(kv[f"{kernel}.write_kb"]) * 1024 * float(kv["write_scale"]))
@@ -281,7 +284,7 @@ def main():
     achieved = fl / (t_dom * 1e-3) / 1e12
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(dom),
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(dom, args.workload, tile),
                 "flops_per_launch": fl, "avg_launch_ms": round(t_dom, 4)}
     step_flops = work["decode_bwd"] + work["raster_fwd"]
     step_roofline = {"flops": step_flops, "achieved_tflops": round(step_flops / (ms * 1e-3) / 1e12, 3),
