@@ -622,9 +622,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
             ca.log_boff = static_cast<uint32_t*>(c->log_boff.p);
             ca.log_regions = c->log_regions;
             ca.vis = vis;
-            ca.grad_color = grad_color;
             ca.grad_logp = grad_logp;
-            ca.edge_w = edge_w;
             ca.all_front = all_front ? 1 : 0;
             ca.frags = static_cast<FragRec*>(c->frags.p);
             ca.region = static_cast<uint32_t>(reg);

@@ -113,9 +113,7 @@ struct CollectArgs {
     const uint32_t* log_boff;      // [log_regions + 1] batch offsets of the log
     int log_regions;
     const uint64_t* vis;
-    const float* grad_color;       // [P,3] (null in the logp pass)
     const float* grad_logp;        // [P] or null
-    const float2* edge_w;          // [P] or null
     int all_front;                 // logp pass
     FragRec* frags;
     uint32_t region;
@@ -181,7 +179,8 @@ struct DecodeArgs {
 void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp_pass, hipStream_t s);
 // LDS bytes one workgroup of the decode needs for a grid side G (0: unknown).
 size_t decode_bwd_lds(MlpKind k, int G, bool logp_pass);
-// ew[p] = (x, y) edge weights of the pairs pixel p occludes (Section 3.2)
+// ew[p] = (x, y) edge weights of the pairs pixel p occludes (Section 3.2),
+// written for covered pixels only (a background pixel occludes nothing)
 void launch_edge_weights(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis,
                          const float* color, const float* grad_color, float2* ew, hipStream_t s);
 void launch_mlp_reduce(const float* partial, int n_rows, int n_params, double* mid, float* out, bool accumulate,

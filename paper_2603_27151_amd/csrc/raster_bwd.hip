@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void edge_weight_kernel(const ViewDesc* __rest
             }
         }
     }
-    ew[p] = make_float2(e[0], e[1]);
+    if (kp != kBgKey) ew[p] = make_float2(e[0], e[1]);   // read for covered pixels only
 }
 
 void launch_edge_weights(const ViewDesc* views, int V, int64_t P, const Opts& o, const uint64_t* vis,

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(TileCfg<TS>::NT) void replay_kernel(ReplayArgs a) {
                     gp[k][0] = (a.grad_logp && r.o.mode == 0) ? a.grad_logp[p] : 0.0f;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) gp[k][1 + i] = a.grad_color[3 * p + i];
-                    if (a.edge_w) {
+                    if (a.edge_w && kc[k] != kBgKey) {   // written for covered pixels only
                         const float2 e = a.edge_w[p];
                         gp[k][4] = e.x;
                         gp[k][5] = e.y;
@@ -318,10 +318,10 @@ void launch_place(const PlaceArgs& a, hipStream_t s) {
 
 // Persistent waves take batches of the forward's log (region by region, as
 // the place kernel does) and keep the fragments the backward needs: the
-// pixel's winner (key == the saved key) when the pixel carries any upstream
-// gradient, and every fragment in front of it (key < the saved key) when it
-// carries a score weight. Kept fragments are compacted per batch and appended
-// to the wave's output region; per-triangle counts as in the replay.
+// pixel's winner (key == the saved key), and every fragment in front of it
+// (key < the saved key) when the pixel carries a score weight. Kept
+// fragments are compacted per batch and appended to the wave's output
+// region; per-triangle counts as in the replay.
 __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
     __shared__ uint32_t s_boff[kMaxRegions + 1];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -352,24 +352,14 @@ __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
             const uint64_t kstar = a.vis[e.x];
             win = key == kstar;
             const bool front = key < kstar;
-            float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (a.all_front) {
-                keep = win || front;
-            } else {
-                if (a.grad_logp) g[0] = a.grad_logp[e.x];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) g[1 + i] = a.grad_color[3 * static_cast<size_t>(e.x) + i];
-                if (a.edge_w) {
-                    const float2 ew = a.edge_w[e.x];
-                    g[4] = ew.x;
-                    g[5] = ew.y;
-                }
-                const bool any = g[0] != 0.f || g[1] != 0.f || g[2] != 0.f || g[3] != 0.f || g[4] != 0.f || g[5] != 0.f;
-                keep = (win && any) || (front && g[0] != 0.0f);
-            }
+            // every winner (its colour gradient and edge weights are read by the
+            // decode; a winner without any adds zeros), and the fragments in front
+            // of it where the pixel carries a score weight
+            const float gl = (!a.all_front && a.grad_logp) ? a.grad_logp[e.x] : 0.0f;
+            keep = win || (front && (a.all_front || gl != 0.0f));
             fr.p0 = make_uint2(e.x, e.y | (win ? 0x80000000u : 0u));
             fr.p1 = make_uint2(e.z, e.w);
-            fr.x = make_uint2(__float_as_uint(g[0]), x.y);
+            fr.x = make_uint2(__float_as_uint(gl), x.y);
         }
         const uint64_t km = __ballot(keep);
         const uint32_t pos = cursor + static_cast<uint32_t>(__popcll(km & lanemask_lt()));
