@@ -461,6 +461,40 @@ def test_backward_from_forward_log_matches_replay():
     ctx.close()
 
 
+@pytest.mark.parametrize("from_log", [False, True])
+def test_partial_upstream_gradients(from_log):
+    """Upstream gradients that vanish on parts of the image: no colour gradient
+    on the left half, no score weight on a checkerboard. Winners are then kept
+    with or without any gradient (from the forward's log) or only with one
+    (replay); either way the gradients match the oracle's."""
+    R = _raster()
+    from paper_2603_27151_amd import _lib
+    wl = W.single(T=3000, res=400)
+    _say(f"case: single view 400x400, 3000 triangles, partial upstream gradients, from_log={from_log}")
+    ds = _dev_scene(wl.scene)
+    vs = _views(wl.views)
+    oo = _oopts(wl.seed, wl.step)
+    o = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1 if from_log else 0)
+    ctx = _lib.Ctx(0)
+    vis, col, _ = R.rasterize_fwd(ds, vs, o, ctx=ctx)
+    torch.cuda.synchronize()
+    v = wl.views[0]
+    ref = O.forward(wl.scene, v, oo)
+    assert np.array_equal(_u64(vis).reshape(v.height, v.width), ref[0])
+    gcs, gls = l2_grads([ref[1]], wl.targets, vs.pixels)
+    gc, gl = gcs[0].copy(), gls[0].copy()
+    gc[:, : v.width // 2] = 0.0
+    yy, xx = np.mgrid[0 : v.height, 0 : v.width]
+    gl[((yy // 8) + (xx // 8)) % 2 == 0] = 0.0
+    gpu = R.rasterize_bwd(ds, vs, o, vis, col, torch.from_numpy(gc.reshape(-1, 3)).cuda(),
+                          torch.from_numpy(gl.ravel()).cuda(), ctx=ctx)
+    torch.cuda.synchronize()
+    gpu = [g.cpu().numpy() for g in gpu]
+    rv, rf, rm = O.backward(wl.scene, v, oo, ref[0], ref[1], gc, gl)
+    assert_grads(gpu, (rv, rf, rm))
+    ctx.close()
+
+
 @pytest.mark.parametrize("P,offset", [(1001, 0), (4096, 1), (7, 0)])
 def test_loss_l2_vector_and_tail_paths(P, offset):
     """The L2 loss kernel (16-byte path plus scalar tail; scalar throughout for
