@@ -140,13 +140,45 @@ __device__ __forceinline__ void persp_from_t(float t0, float t1, float t2, float
     b2 = t2 * r;
 }
 
+// Inclusive scans over the wave on the data-parallel primitives (DPP), with no
+// LDS round trip: shifted moves by 1, 2, 4 and 8 lanes within each row of 16
+// (a lane with no source in its row keeps its value), then the broadcasts of
+// lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3 (the GFX9
+// wave64 controls: row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143).
+template <int CTRL, int ROWS, class Op>
+__device__ __forceinline__ int dpp_step(int v, int identity, Op op) {
+    return op(v, __builtin_amdgcn_update_dpp(identity, v, CTRL, ROWS, 0xF, false));
+}
+template <class Op>
+__device__ __forceinline__ int wave_scan_dpp(int v, int identity, Op op) {
+    v = dpp_step<0x111, 0xF>(v, identity, op);
+    v = dpp_step<0x112, 0xF>(v, identity, op);
+    v = dpp_step<0x114, 0xF>(v, identity, op);
+    v = dpp_step<0x118, 0xF>(v, identity, op);
+    v = dpp_step<0x142, 0xA>(v, identity, op);
+    return dpp_step<0x143, 0xC>(v, identity, op);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_max_step_u64(uint64_t v) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROWS, 0xF, false));
+    const uint32_t hi =
+        static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v >> 32), CTRL, ROWS, 0xF, false));
+    const uint64_t u = (static_cast<uint64_t>(hi) << 32) | lo;
+    return u > v ? u : v;
+}
+
+// The largest value over the wave (wave-uniform).
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        const uint64_t u = __shfl_xor(v, d, 64);
-        v = u > v ? u : v;
-    }
-    return v;
+    v = dpp_max_step_u64<0x111, 0xF>(v);
+    v = dpp_max_step_u64<0x112, 0xF>(v);
+    v = dpp_max_step_u64<0x114, 0xF>(v);
+    v = dpp_max_step_u64<0x118, 0xF>(v);
+    v = dpp_max_step_u64<0x142, 0xA>(v);
+    v = dpp_max_step_u64<0x143, 0xC>(v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v >> 32), 63));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
 // Smallest key any not-yet-processed entry of the tile list can produce.

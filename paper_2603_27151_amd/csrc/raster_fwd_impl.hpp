@@ -69,13 +69,7 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
 }
 
 __device__ __forceinline__ int wave_incl_scan_i32(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
+    return wave_scan_dpp(v, 0, [](int x, int y) { return x + y; });
 }
 
 // Position of the k-th set bit (k from 0) of the 64-bit mask hi:lo.
@@ -295,14 +289,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             __syncthreads();
             if (cnt > 0 && off >= base && off < base + 64) L.head[off - base] = lane;
             __syncthreads();
-            int h = L.head[lane];
             const uint64_t before = __ballot(cnt > 0 && off < base);
             const int carry = before ? 63 - __builtin_clzll(before) : -1;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int o = __shfl_up(h, d, 64);
-                if (lane >= d) h = o > h ? o : h;
-            }
+            const int h = wave_scan_dpp(L.head[lane], -1, [](int x, int y) { return x > y ? x : y; });
             const int c = base + lane;
             const bool valid = c < n_comb;
             const int j = valid ? (h > carry ? h : carry) : 0;
