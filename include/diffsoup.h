@@ -130,7 +130,10 @@ enum {
     SOUP_T_FILL = 11,    /* zero fills */
     SOUP_T_REPLAY = 12,  /* backward front-set replay (coverage, fragment list) */
     SOUP_T_GRAD = 13,    /* per-triangle feature and vertex gradient reduction */
-    SOUP_TIMING_KINDS = 14
+    SOUP_T_COVER = 14,   /* adaptive control: coverage counts */
+    SOUP_T_EDGELEN = 15, /* adaptive control: screen-space edge lengths */
+    SOUP_T_APPLY = 16,   /* adaptive control: applying a plan */
+    SOUP_TIMING_KINDS = 17
 };
 soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
 soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);
@@ -220,6 +223,67 @@ soup_status soup_render(soup_ctx* ctx, const soup_scene* scenes, int32_t R, cons
  */
 soup_status soup_loss_l2(soup_ctx* ctx, const float* color, const float* target, int64_t P,
                          float* grad_color, float* grad_logp, float* loss, void* stream);
+
+/*
+ * Adaptive control of primitives (Section 3.4, "Adaptive control of
+ * primitives"; Supplement B, resampling of a random initialisation): split
+ * edges that look long on a sample of views, prune the triangles that cover
+ * the fewest pixels, keep the triangle budget. Measure (soup_coverage_count,
+ * soup_edge_lengths, device), decide (soup_adaptive_plan, host), rebuild
+ * (soup_adaptive_apply, device).
+ */
+
+/* Pixel coverage: counts[t] += the number of keys of vis [n] (device uint64,
+ * from soup_rasterize_fwd over any views of one scene) whose low 32 bits,
+ * the winner's triangle index, equal t. Background keys and indices >= T
+ * are skipped. counts: device [T] uint32, added into (zero it for a fresh
+ * count); the order of the additions does not matter (integers). */
+soup_status soup_coverage_count(soup_ctx* ctx, const uint64_t* vis, int64_t n, int32_t T, uint32_t* counts,
+                                void* stream);
+
+/* Screen-space edge lengths: rel_len (device [T,3] float, overwritten)
+ * receives for edge k of triangle t (vertex k to vertex (k+1) mod 3) its
+ * largest length in pixels divided by the view's height, over the views in
+ * which every vertex is at clip w >= near_w and the screen bounding box meets
+ * [0,W] x [0,H]; 0 where no view qualifies. The projection is the one of
+ * soup_views, evaluated in float64 (products, then sums left to right), the
+ * result rounded to float32 once. verts: device [T,3,3]; views->view_id is
+ * not read. Any number of views (launched 32 at a time). */
+soup_status soup_edge_lengths(soup_ctx* ctx, const float* verts, int32_t T, const soup_views* views, float near_w,
+                              float* rel_len, void* stream);
+
+enum { SOUP_ACT_REMOVE = 0, SOUP_ACT_KEEP = 1, SOUP_ACT_SPLIT0 = 2 }; /* SPLIT0 + k: split edge k */
+enum { SOUP_PLAN_PRUNE_ZERO = 1, SOUP_PLAN_FILL = 2 };
+
+/* Plan (host code on host arrays; synchronous; ctx may be NULL).
+ *  1. a triangle whose longest edge (lowest k among equals) has
+ *     rel_len > split_frac (float32 comparison) splits on that edge;
+ *  2. SOUP_PLAN_PRUNE_ZERO: triangles with counts == 0 are removed;
+ *  3. while the triangle count after the splits exceeds target, triangles
+ *     are removed in order of (counts, index) ascending, each with its split;
+ *  4. SOUP_PLAN_FILL: while the count is below target, kept unsplit
+ *     triangles split on their longest edge, longest first (index order
+ *     among equals).
+ * Outputs: actions [T] (SOUP_ACT_*), offsets [T] (each triangle's first
+ * output slot: the exclusive prefix sum of 0 / 1 / 2 outputs), *n_new.
+ * 0 <= T <= 2^30, target >= 0. */
+soup_status soup_adaptive_plan(soup_ctx* ctx, const uint32_t* counts, const float* rel_len, int32_t T,
+                               float split_frac, int32_t target, int32_t flags, int32_t* actions, int32_t* offsets,
+                               int32_t* n_new);
+
+/* Apply a plan (device): verts_out [n_new,3,3] and feats_out [n_new,G,G,C]
+ * (device, overwritten) receive the kept triangles in order and, for a
+ * split of edge k, two halves at offsets[t] and offsets[t]+1: half 0 takes
+ * the midpoint in place of vertex k+1, half 1 in place of vertex k (the
+ * vertex order, hence the orientation, is kept). A half's texel (ix, iy),
+ * at (ix, iy)/(G-1) in its barycentrics, samples the parent's grid
+ * bilinearly at the same surface point (grid coordinates clamped to
+ * [0, G-1]). Uses scene->T, G, C, verts, feats; the MLP is unchanged.
+ * actions, offsets: device [T], a plan from soup_adaptive_plan; entries whose
+ * outputs would fall outside [0, n_new) are not written. */
+soup_status soup_adaptive_apply(soup_ctx* ctx, const soup_scene* scene, const int32_t* actions,
+                                const int32_t* offsets, int32_t n_new, float* verts_out, float* feats_out,
+                                void* stream);
 
 /* Contract self-test: y[i] = the device sigmoid of x[i] (the opacity
  * sigmoid whose value decides the mask), for checking it bit for bit

@@ -49,9 +49,13 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_ctx_get_tile", "soup_ctx_set_counting", "soup_last_stats", "soup_rasterize_fwd",
            "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
            "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings", "soup_ctx_set_static",
-           "soup_ctx_check"]
+           "soup_ctx_check", "soup_coverage_count", "soup_edge_lengths", "soup_adaptive_plan",
+           "soup_adaptive_apply"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
-                "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce"]
+                "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
+                "adaptive_apply"]
+ACT_REMOVE, ACT_KEEP, ACT_SPLIT0 = 0, 1, 2
+PLAN_PRUNE_ZERO, PLAN_FILL = 1, 2
 
 _lib = None
 
@@ -87,10 +91,16 @@ def lib() -> C.CDLL:
     L.soup_ctx_check.argtypes = [P]
     L.soup_ctx_set_timing.argtypes = [P, C.c_int32]
     L.soup_read_timings.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.soup_coverage_count.argtypes = [P, P, C.c_int64, C.c_int32, P, P]
+    L.soup_edge_lengths.argtypes = [P, P, C.c_int32, C.POINTER(soup_views), C.c_float, P, P]
+    L.soup_adaptive_plan.argtypes = [P, P, P, C.c_int32, C.c_float, C.c_int32, C.c_int32, P, P,
+                                     C.POINTER(C.c_int32)]
+    L.soup_adaptive_apply.argtypes = [P, C.POINTER(soup_scene), P, P, C.c_int32, P, P, P]
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
                  "soup_selftest_sigmoid", "soup_selftest_uniform", "soup_ctx_set_timing",
-                 "soup_read_timings", "soup_ctx_set_static", "soup_ctx_check"]:
+                 "soup_read_timings", "soup_ctx_set_static", "soup_ctx_check", "soup_coverage_count",
+                 "soup_edge_lengths", "soup_adaptive_plan", "soup_adaptive_apply"]:
         getattr(L, name).restype = C.c_int
     L.soup_ctx_get_tile.restype = C.c_int32
     _lib = L
@@ -258,3 +268,36 @@ def soup_selftest_sigmoid(ctx: Ctx, x, y, stream=None):
 def soup_selftest_uniform(ctx: Ctx, seed, pixel, tri, view_id, step, u, stream=None):
     ctx.check(lib().soup_selftest_uniform(ctx.p, int(seed), _ptr(pixel), _ptr(tri), int(view_id), int(step),
                                           _ptr(u), u.numel(), _stream(stream)))
+
+
+def soup_coverage_count(ctx: Ctx, vis, T: int, counts, stream=None):
+    ctx.check(lib().soup_coverage_count(ctx.p, _ptr(vis), vis.numel(), int(T), _ptr(counts), _stream(stream)))
+
+
+def soup_edge_lengths(ctx: Ctx, verts, views: soup_views, near_w: float, rel_len, stream=None):
+    ctx.check(lib().soup_edge_lengths(ctx.p, _ptr(verts), int(verts.shape[0]), C.byref(views), float(near_w),
+                                      _ptr(rel_len), _stream(stream)))
+
+
+def soup_adaptive_plan(counts: np.ndarray, rel_len: np.ndarray, split_frac: float, target: int, flags: int = 0):
+    """Host arrays in, (actions int32 [T], offsets int32 [T], n_new) out; needs no GPU."""
+    cnt = np.ascontiguousarray(counts, dtype=np.uint32)
+    rel = np.ascontiguousarray(rel_len, dtype=np.float32).reshape(-1)
+    T = cnt.shape[0]
+    if rel.shape[0] != 3 * T:
+        raise ValueError("rel_len must hold 3 lengths per triangle")
+    act = np.zeros(T, np.int32)
+    off = np.zeros(T, np.int32)
+    n = C.c_int32(0)
+    st = lib().soup_adaptive_plan(None, cnt.ctypes.data_as(C.c_void_p), rel.ctypes.data_as(C.c_void_p), T,
+                                  float(split_frac), int(target), int(flags), act.ctypes.data_as(C.c_void_p),
+                                  off.ctypes.data_as(C.c_void_p), C.byref(n))
+    if st != 0:
+        raise SoupError(st, "soup_adaptive_plan: bad arguments")
+    return act, off, int(n.value)
+
+
+def soup_adaptive_apply(ctx: Ctx, scene: soup_scene, actions, offsets, n_new: int, verts_out, feats_out,
+                        stream=None):
+    ctx.check(lib().soup_adaptive_apply(ctx.p, C.byref(scene), _ptr(actions), _ptr(offsets), int(n_new),
+                                        _ptr(verts_out), _ptr(feats_out), _stream(stream)))

@@ -972,6 +972,84 @@ soup_status soup_loss_l2(soup_ctx* c, const float* color, const float* target, i
     return SOUP_OK;
 }
 
+soup_status soup_coverage_count(soup_ctx* c, const uint64_t* vis, int64_t n, int32_t T, uint32_t* counts,
+                                void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (n < 0 || T < 0 || (n > 0 && !vis) || (T > 0 && !counts))
+        return fail(c, SOUP_ERR_INVALID, "coverage_count: bad arguments (n = %lld, T = %d)", (long long)n, T);
+    HIP_TRY(c, hipSetDevice(c->device));
+    {
+        Timed t(c, SOUP_T_COVER, static_cast<hipStream_t>(stream));
+        launch_coverage(vis, n, T, counts, c->num_cus, static_cast<hipStream_t>(stream));
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_edge_lengths(soup_ctx* c, const float* verts, int32_t T, const soup_views* v, float near_w,
+                              float* rel_len, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (T < 0 || (T > 0 && (!verts || !rel_len))) return fail(c, SOUP_ERR_INVALID, "edge_lengths: bad arguments");
+    if (!v || v->V < 1 || !v->width || !v->height || !v->view_proj)
+        return fail(c, SOUP_ERR_INVALID, "edge_lengths: views missing");
+    for (int i = 0; i < v->V; ++i)
+        if (v->width[i] < 1 || v->width[i] > 16384 || v->height[i] < 1 || v->height[i] > 16384)
+            return fail(c, SOUP_ERR_INVALID, "view %d size %dx%d outside [1, 16384]", i, v->width[i], v->height[i]);
+    if (!(near_w > 0.0f)) return fail(c, SOUP_ERR_INVALID, "edge_lengths: near_w must be > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        Timed t(c, SOUP_T_EDGELEN, s);
+        for (int v0 = 0; v0 < v->V; v0 += soup::kEdgeViews) {
+            soup::EdgeViews ev{};
+            ev.n = std::min(soup::kEdgeViews, v->V - v0);
+            for (int i = 0; i < ev.n; ++i) {
+                std::memcpy(ev.m[i], v->view_proj + static_cast<size_t>(v0 + i) * 16, 16 * sizeof(float));
+                ev.w[i] = static_cast<float>(v->width[v0 + i]);
+                ev.h[i] = static_cast<float>(v->height[v0 + i]);
+            }
+            launch_edge_lengths(verts, T, ev, near_w, v0 == 0, rel_len, s);
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_adaptive_plan(soup_ctx* c, const uint32_t* counts, const float* rel_len, int32_t T, float split_frac,
+                               int32_t target, int32_t flags, int32_t* actions, int32_t* offsets, int32_t* n_new) {
+    if (c) c->err.clear();
+    if (!n_new || T < 0 || T > (1 << 30) || target < 0 || (flags & ~3) != 0 ||
+        (T > 0 && (!counts || !rel_len || !actions || !offsets)))
+        return fail(c, SOUP_ERR_INVALID, "adaptive_plan: bad arguments (T = %d, target = %d, flags = %d)", T, target,
+                    flags);
+    if (!(split_frac == split_frac)) return fail(c, SOUP_ERR_INVALID, "adaptive_plan: split_frac is NaN");
+    *n_new = soup::plan_host(counts, rel_len, T, split_frac, target, (flags & SOUP_PLAN_PRUNE_ZERO) != 0,
+                             (flags & SOUP_PLAN_FILL) != 0, actions, offsets);
+    return SOUP_OK;
+}
+
+soup_status soup_adaptive_apply(soup_ctx* c, const soup_scene* sc, const int32_t* actions, const int32_t* offsets,
+                                int32_t n_new, float* verts_out, float* feats_out, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (!sc || sc->T < 0 || sc->G < 2 || sc->G > 256 || sc->C < 1 || n_new < 0)
+        return fail(c, SOUP_ERR_INVALID, "adaptive_apply: bad scene or n_new");
+    if (sc->T > 0 && (!sc->verts || !sc->feats || !actions || !offsets))
+        return fail(c, SOUP_ERR_INVALID, "adaptive_apply: device pointers are NULL");
+    if (n_new > 0 && (!verts_out || !feats_out))
+        return fail(c, SOUP_ERR_INVALID, "adaptive_apply: output pointers are NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    {
+        Timed t(c, SOUP_T_APPLY, static_cast<hipStream_t>(stream));
+        launch_apply(sc->verts, sc->feats, actions, offsets, sc->T, sc->G, sc->C, n_new, verts_out, feats_out,
+                     static_cast<hipStream_t>(stream));
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
 soup_status soup_selftest_sigmoid(soup_ctx* c, const float* x, float* y, int64_t n, void* stream) {
     if (!c) return SOUP_ERR_INVALID;
     if (n < 0 || (n > 0 && (!x || !y))) return fail(c, SOUP_ERR_INVALID, "selftest_sigmoid: bad arguments");

@@ -193,4 +193,20 @@ void launch_selftest_uniform(uint64_t seed, const uint32_t* pixel, const uint32_
                              uint32_t step, float* u, int64_t n, hipStream_t s);
 
 
+// Adaptive control of primitives.
+constexpr int kEdgeViews = 32;  // views per edge-length launch (kernel argument)
+struct EdgeViews {
+    float m[kEdgeViews][16];    // row-major view-projection matrices
+    float w[kEdgeViews], h[kEdgeViews];
+    int n;
+};
+constexpr int kActRemove = 0, kActKeep = 1, kActSplit0 = 2;
+void launch_coverage(const uint64_t* vis, int64_t n, int32_t T, uint32_t* counts, int num_cus, hipStream_t s);
+void launch_edge_lengths(const float* verts, int32_t T, const EdgeViews& ev, float near_w, bool first, float* rel,
+                         hipStream_t s);
+void launch_apply(const float* verts, const float* feats, const int32_t* actions, const int32_t* offsets, int32_t T,
+                  int32_t G, int32_t C, int32_t n_new, float* vout, float* fout, hipStream_t s);
+int32_t plan_host(const uint32_t* counts, const float* rel, int32_t T, float split_frac, int32_t target,
+                  bool prune_zero, bool fill, int32_t* actions, int32_t* offsets);
+
 }  // namespace soup

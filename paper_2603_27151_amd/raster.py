@@ -195,3 +195,53 @@ class SoupRasterize(torch.autograd.Function):
 def rasterize(verts, feats, mlp, dims, views: Views, opts: Opts):
     """Differentiable rasterization: returns (color [P,3], logp [P], vis [P])."""
     return SoupRasterize.apply(verts, feats, mlp, dims, views, opts)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive control of primitives (Section 3.4; Supplement B)
+
+def coverage_count(vis, T: int, counts=None, ctx=None, stream=None):
+    """Pixels won per triangle from visibility keys (any views of one scene),
+    added into `counts` (uint32 [T] on the device; a fresh zeroed one by
+    default)."""
+    ctx = ctx or context()
+    if counts is None:
+        counts = torch.zeros(int(T), dtype=torch.int32, device=vis.device)
+    _lib.soup_coverage_count(ctx, vis, T, counts, stream)
+    return counts
+
+
+def edge_lengths(verts, views: Views, near_w: float = 0.1, ctx=None, stream=None):
+    """[T,3] float32: each edge's longest screen-space length over the views,
+    in units of the view's height (0 where no view sees the triangle)."""
+    ctx = ctx or context()
+    rel = torch.empty(int(verts.shape[0]), 3, dtype=torch.float32, device=verts.device)
+    h = _lib._Holder()
+    _lib.soup_edge_lengths(ctx, verts, views.c_struct(h), near_w, rel, stream)
+    return rel
+
+
+def adaptive_plan(counts, rel_len, split_frac: float = 0.2, target: int = 0, prune_zero: bool = False,
+                  fill: bool = False):
+    """Host plan: (actions [T], offsets [T], n_new) as numpy int32 arrays."""
+    flags = (_lib.PLAN_PRUNE_ZERO if prune_zero else 0) | (_lib.PLAN_FILL if fill else 0)
+    if isinstance(counts, torch.Tensor):
+        counts = counts.cpu().numpy().view(np.uint32)
+    if isinstance(rel_len, torch.Tensor):
+        rel_len = rel_len.cpu().numpy()
+    return _lib.soup_adaptive_plan(counts, rel_len, split_frac, target, flags)
+
+
+def adaptive_apply(scene: DeviceScene, actions, offsets, n_new: int, ctx=None, stream=None) -> DeviceScene:
+    """The soup after a plan: kept triangles, halves of split ones (vertices
+    and resampled textures); the MLP is shared with `scene`."""
+    ctx = ctx or context()
+    dev = scene.verts.device
+    act = torch.as_tensor(np.ascontiguousarray(actions, np.int32)).to(dev)
+    off = torch.as_tensor(np.ascontiguousarray(offsets, np.int32)).to(dev)
+    G, Cc = int(scene.feats.shape[1]), int(scene.feats.shape[3])
+    v = torch.empty(int(n_new), 3, 3, dtype=torch.float32, device=dev)
+    f = torch.empty(int(n_new), G, G, Cc, dtype=torch.float32, device=dev)
+    h = _lib._Holder()
+    _lib.soup_adaptive_apply(ctx, scene.c_struct(h), act, off, n_new, v, f, stream)
+    return DeviceScene(v, f, scene.mlp, list(scene.dims))
