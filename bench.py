@@ -88,6 +88,7 @@ def parse():
     ap.add_argument("--cpu-pixels", type=float, default=8e6, help="oracle sample size in pixels (about 10 s of host work)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--skip-adaptive", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first copy this many MiB device to device three times (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -269,6 +270,65 @@ def main():
                     "batched_speedup": round(pv_ms / ms, 3)}
         log(f"per-view path {pv_ms:.3f} ms -> {per_view['mpixel_s']} Mpixel/s")
 
+    # adaptive control of primitives on the same soup and visibility buffer
+    # (not part of the step): coverage counts over every pixel, edge lengths
+    # over a 20-view sample, the host plan of a random initialisation
+    # (prune zero coverage, then split longest edges back to the triangle
+    # count), and its application
+    adaptive = None
+    if not args.skip_adaptive:
+        k_ad = max(3, args.steps)
+        counts = torch.zeros(ds.T, dtype=torch.int32, device=dev)
+        pick = np.sort(np.random.default_rng(20).choice(vs.V, size=min(20, vs.V), replace=False))
+        sample = R.Views.from_list([wl.views[i] for i in pick])
+        R.coverage_count(vis, ds.T, counts=counts, ctx=ctx)
+        rel = R.edge_lengths(ds.verts, sample, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.read_timings()
+        ctx.set_timing(True)
+        for _ in range(k_ad):
+            counts.zero_()
+            R.coverage_count(vis, ds.T, counts=counts, ctx=ctx)
+            rel = R.edge_lengths(ds.verts, sample, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        act, off, n_new = R.adaptive_plan(counts, rel, 0.2, target=ds.T, prune_zero=True, fill=True)
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(k_ad):
+            new = R.adaptive_apply(ds, act, off, n_new, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        kt = ctx.read_timings()
+        avg = {k: kt[k][0] / kt[k][1] for k in ("coverage", "edge_lengths", "adaptive_apply") if kt[k][1]}
+        n_split = int((act >= 2).sum())
+        n_keep = int((act == 1).sum())
+        per_tri = 4 * wl.scene.G * wl.scene.G * wl.scene.C + 36
+        cov_bytes = 8 * P
+        apply_bytes = (n_keep + n_split) * per_tri + n_new * per_tri + 8 * ds.T
+        adaptive = {
+            "coverage": {"ms": round(avg["coverage"], 4), "bytes": cov_bytes,
+                         "gb_s": round(cov_bytes / (avg["coverage"] * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(cov_bytes / (avg["coverage"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+            "edge_lengths": {"ms": round(avg["edge_lengths"], 4), "views": int(sample.V),
+                             "triangle_views_per_s": round(ds.T * sample.V / (avg["edge_lengths"] * 1e-3), 1)},
+            "plan_host_ms": round(plan_ms, 3),
+            "apply": {"ms": round(avg["adaptive_apply"], 4), "bytes": apply_bytes,
+                      "gb_s": round(apply_bytes / (avg["adaptive_apply"] * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(apply_bytes / (avg["adaptive_apply"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                      "removed": int((act == 0).sum()), "split": n_split, "n_new": int(n_new)},
+        }
+        # the coverage kernel issues one device-scope atomic per distinct
+        # triangle among each wave's 256 consecutive keys: count them
+        keys = vis.cpu().numpy().view(np.uint64)
+        tri = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        valid = (keys != np.uint64(0xFFFFFFFFFFFFFFFF)) & (tri < ds.T)
+        chunk = np.nonzero(valid)[0] // 256
+        runs = int(np.unique(chunk * ds.T + tri[valid]).size)
+        adaptive["coverage"]["atomics"] = runs
+        adaptive["coverage"]["atomics_per_s"] = round(runs / (avg["coverage"] * 1e-3), 1)
+        del new, keys, tri, valid, chunk
+        log("adaptive: " + json.dumps(adaptive))
+
     # roofline of the dominant kernel: the MLP kernels are bound by float32
     # ALU work; their algorithmic FLOPs count the decodes the method needs
     # (E = front set + winner per pixel, counted exactly by the backward
@@ -369,6 +429,7 @@ def main():
         "step_roofline": step_roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "adaptive": adaptive,
     }
     print(json.dumps(out), flush=True)
 

@@ -280,7 +280,8 @@ soup_status soup_adaptive_plan(soup_ctx* ctx, const uint32_t* counts, const floa
  * bilinearly at the same surface point (grid coordinates clamped to
  * [0, G-1]). Uses scene->T, G, C, verts, feats; the MLP is unchanged.
  * actions, offsets: device [T], a plan from soup_adaptive_plan; entries whose
- * outputs would fall outside [0, n_new) are not written. */
+ * outputs would fall outside [0, n_new) are not written. feats and
+ * feats_out must be 16-byte aligned (as any device allocation is). */
 soup_status soup_adaptive_apply(soup_ctx* ctx, const soup_scene* scene, const int32_t* actions,
                                 const int32_t* offsets, int32_t n_new, float* verts_out, float* feats_out,
                                 void* stream);

@@ -1,11 +1,12 @@
 // Adaptive control of primitives (Section 3.4, "Adaptive control of
 // primitives"; Supplement B, resampling of a random initialisation).
 //
-//  * coverage_kernel: pixels won per triangle, from the visibility keys.
-//    HBM-bound (8 bytes read per pixel). Neighbouring pixels of a row mostly
-//    share their winner, so each wave merges runs of equal triangle indices
-//    over its 64 consecutive keys (a head bit per run from a ballot, the run
-//    length from the next head) and issues one atomic per run, not per pixel.
+//  * coverage_kernel: pixels won per triangle, from the visibility keys
+//    (8 bytes read per pixel). Device-scope atomics set its pace, and
+//    stochastic masking interleaves the winners of neighbouring pixels (runs
+//    of equal winners average under two pixels), so each wave loads 256
+//    consecutive keys and issues one atomic per distinct triangle among
+//    them, with the count of its pixels.
 //  * edge_length_kernel: per triangle, the longest screen-space length of
 //    each edge over up to kEdgeViews views, in units of the view's height.
 //    One thread per triangle; the views travel as a kernel argument. Float64
@@ -29,25 +30,43 @@ namespace soup {
 
 namespace {
 
+constexpr int kCoverUnroll = 4;  // 64-key chunks per wave and iteration, loaded together
+
 __global__ void __launch_bounds__(256) coverage_kernel(const uint64_t* __restrict__ vis, int64_t n, uint32_t T,
                                                        uint32_t* __restrict__ counts) {
     const int lane = threadIdx.x & 63;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    // i0 is the wave's first key: every lane of a wave runs the same iterations
-    for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); i0 < n; i0 += stride) {
-        const int64_t i = i0 + lane;
-        uint32_t id = 0xFFFFFFFFu;
-        if (i < n) {
-            const uint64_t k = vis[i];
-            const uint32_t t = static_cast<uint32_t>(k);
-            if (k != kBgKey && t < T) id = t;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x * kCoverUnroll;
+    // w0 is the wave's first key: every lane of a wave runs the same iterations
+    for (int64_t w0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)) * kCoverUnroll; w0 < n;
+         w0 += stride) {
+        uint64_t k[kCoverUnroll];
+        for (int u = 0; u < kCoverUnroll; ++u) {
+            const int64_t i = w0 + u * 64 + lane;
+            k[u] = i < n ? vis[i] : kBgKey;
         }
-        const uint32_t prev = __shfl_up(id, 1, 64);
-        const bool head = lane == 0 || prev != id;
-        const uint64_t heads = __ballot(head);
-        const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-        const int next = above ? __builtin_ctzll(above) : 64;
-        if (head && id != 0xFFFFFFFFu) atomicAdd(&counts[id], static_cast<uint32_t>(next - lane));
+        uint32_t id[kCoverUnroll];
+        uint64_t pending[kCoverUnroll];
+        for (int u = 0; u < kCoverUnroll; ++u) {
+            const uint32_t t = static_cast<uint32_t>(k[u]);
+            id[u] = (k[u] != kBgKey && t < T) ? t : 0xFFFFFFFFu;
+            pending[u] = __ballot(id[u] != 0xFFFFFFFFu);
+        }
+        // one atomic per distinct triangle among the wave's keys: the first
+        // pending lane names a triangle, every lane holding it is counted
+        // and retired (each pass retires at least that lane)
+        for (int u0 = 0; u0 < kCoverUnroll; ++u0) {
+            while (pending[u0]) {
+                const int leader = __builtin_ctzll(pending[u0]);
+                const uint32_t lid = __builtin_amdgcn_readlane(id[u0], leader);
+                uint32_t total = 0;
+                for (int u = u0; u < kCoverUnroll; ++u) {
+                    const uint64_t same = __ballot(id[u] == lid);
+                    total += static_cast<uint32_t>(__builtin_popcountll(same));
+                    pending[u] &= ~same;
+                }
+                if (lane == leader) atomicAdd(&counts[lid], total);
+            }
+        }
     }
 }
 
@@ -116,7 +135,13 @@ __global__ void __launch_bounds__(256) apply_kernel(const float* __restrict__ ve
         if (kids == 1) {
             if (threadIdx.x < 9) vout[static_cast<int64_t>(o) * 9 + threadIdx.x] = vp[threadIdx.x];
             float* fo = fout + static_cast<int64_t>(o) * per;
-            for (int64_t i = threadIdx.x; i < per; i += blockDim.x) fo[i] = fp[i];
+            if ((per & 3) == 0) {  // 16-byte rows: the caller's buffers are at least 16-byte aligned
+                const float4* s4 = reinterpret_cast<const float4*>(fp);
+                float4* d4 = reinterpret_cast<float4*>(fo);
+                for (int64_t i = threadIdx.x; i < per / 4; i += blockDim.x) d4[i] = s4[i];
+            } else {
+                for (int64_t i = threadIdx.x; i < per; i += blockDim.x) fo[i] = fp[i];
+            }
             continue;
         }
         const int k = a - kActSplit0;
@@ -160,8 +185,8 @@ __global__ void __launch_bounds__(256) apply_kernel(const float* __restrict__ ve
 
 void launch_coverage(const uint64_t* vis, int64_t n, int32_t T, uint32_t* counts, int num_cus, hipStream_t s) {
     if (n <= 0 || T <= 0) return;
-    int64_t g = (n + 255) / 256;
-    const int64_t cap = static_cast<int64_t>(num_cus) * 8;
+    int64_t g = (n + 256 * kCoverUnroll - 1) / (256 * kCoverUnroll);
+    const int64_t cap = static_cast<int64_t>(num_cus) * 16;
     if (g > cap) g = cap;
     hipLaunchKernelGGL(coverage_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, vis, n,
                        static_cast<uint32_t>(T), counts);

@@ -1040,6 +1040,8 @@ soup_status soup_adaptive_apply(soup_ctx* c, const soup_scene* sc, const int32_t
         return fail(c, SOUP_ERR_INVALID, "adaptive_apply: device pointers are NULL");
     if (n_new > 0 && (!verts_out || !feats_out))
         return fail(c, SOUP_ERR_INVALID, "adaptive_apply: output pointers are NULL");
+    if ((reinterpret_cast<uintptr_t>(sc->feats) | reinterpret_cast<uintptr_t>(feats_out)) & 15)
+        return fail(c, SOUP_ERR_INVALID, "adaptive_apply: feats and feats_out must be 16-byte aligned");
     HIP_TRY(c, hipSetDevice(c->device));
     {
         Timed t(c, SOUP_T_APPLY, static_cast<hipStream_t>(stream));
