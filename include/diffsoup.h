@@ -133,7 +133,9 @@ enum {
     SOUP_T_COVER = 14,   /* adaptive control: coverage counts */
     SOUP_T_EDGELEN = 15, /* adaptive control: screen-space edge lengths */
     SOUP_T_APPLY = 16,   /* adaptive control: applying a plan */
-    SOUP_TIMING_KINDS = 17
+    SOUP_T_TLOSS = 17,   /* L1 + SSIM loss */
+    SOUP_T_ADAM = 18,    /* optimiser steps */
+    SOUP_TIMING_KINDS = 19
 };
 soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
 soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);
@@ -285,6 +287,38 @@ soup_status soup_adaptive_plan(soup_ctx* ctx, const uint32_t* counts, const floa
 soup_status soup_adaptive_apply(soup_ctx* ctx, const soup_scene* scene, const int32_t* actions,
                                 const int32_t* offsets, int32_t n_new, float* verts_out, float* feats_out,
                                 void* stream);
+
+/*
+ * Photometric loss of training (Section 3.4, "Loss function"):
+ *   L = lambda L1 + (1 - lambda) (1 - SSIM), lambda = 0.8 in the paper,
+ * L1 = mean over the P pixels of all views and 3 channels of |color - target|;
+ * SSIM = mean over pixels and channels of the SSIM map (Wang et al. 2004):
+ * 11 x 11 Gaussian window (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, local
+ * statistics per view and channel with zero padding outside the image.
+ * color, target: device [P,3] (views concatenated, as in soup_rasterize_fwd);
+ * views: only width and height are read. Outputs (device, overwritten):
+ *   grad_color [P,3] = dL/dcolor (the L1 part uses sign, 0 at equality);
+ *   grad_logp  [P]   = pixel p's share of L, [lambda sum_c |d| +
+ *                      (1 - lambda) sum_c (1 - S_c(p))] / (3P), so the shares
+ *                      sum to L (the score term's per-pixel loss);
+ *   loss (device scalar, may be NULL) = L (summed with atomics).
+ * Uses a context workspace of 48 bytes per pixel of the largest view. */
+soup_status soup_loss_l1_ssim(soup_ctx* ctx, const float* color, const float* target, const soup_views* views,
+                              float lambda, float* grad_color, float* grad_logp, float* loss, void* stream);
+
+/*
+ * One optimiser step (Section 3.4; Supplement, hyperparameters): Adam for
+ * vec = 1, VectorAdam for vec = 3 (vertex positions: one second moment per
+ * 3-vector, from its squared norm). For each vector i of n / vec:
+ *   m = b1 m + (1 - b1) g;   v_i = b2 v_i + (1 - b2) |g_i|^2;
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v_i / (1 - b2^t)) + eps).
+ * p, m: device [n] float, updated; g: device [n]; v: device [n / vec],
+ * updated; t >= 1 is the step count; n must be a multiple of vec. The
+ * betas are double so that 1 - beta and the bias corrections are formed from
+ * the exact hyperparameters (in float, 1 - 0.999 is off by 1.3e-5).
+ */
+soup_status soup_adam_step(soup_ctx* ctx, float* p, const float* g, float* m, float* v, int64_t n, int32_t vec,
+                           float lr, double beta1, double beta2, float eps, int32_t t, void* stream);
 
 /* Contract self-test: y[i] = the device sigmoid of x[i] (the opacity
  * sigmoid whose value decides the mask), for checking it bit for bit

@@ -1,6 +1,7 @@
 // C ABI of the gfx950 soup rasterizer: context, argument validation,
 // workspace management and the launch sequence of each entry point.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -49,6 +50,7 @@ struct soup_ctx {
     DevBuf tri_count, tri_fill, tri_off, tri_bsum, mlp_mid, frags, sorted;
     DevBuf region_counts, region_boff, flags;
     DevBuf log_frag, log_aux, log_counts, log_boff;   // the forward's fragment log
+    DevBuf ssim;                                      // SSIM statistics of the training loss
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
@@ -492,7 +494,7 @@ void soup_ctx_destroy(soup_ctx* c) {
                       &c->tile_start, &c->bsum,      &c->entries,       &c->edge_w,      &c->partial,
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
-                      &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff,
+                      &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff, &c->ssim,
                       &c->chunk_base};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1047,6 +1049,72 @@ soup_status soup_adaptive_apply(soup_ctx* c, const soup_scene* sc, const int32_t
         Timed t(c, SOUP_T_APPLY, static_cast<hipStream_t>(stream));
         launch_apply(sc->verts, sc->feats, actions, offsets, sc->T, sc->G, sc->C, n_new, verts_out, feats_out,
                      static_cast<hipStream_t>(stream));
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_loss_l1_ssim(soup_ctx* c, const float* color, const float* target, const soup_views* v,
+                              float lambda, float* grad_color, float* grad_logp, float* loss, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (!v || v->V < 1 || !v->width || !v->height) return fail(c, SOUP_ERR_INVALID, "loss_l1_ssim: views missing");
+    if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(c, SOUP_ERR_INVALID, "loss_l1_ssim: lambda outside [0, 1]");
+    int64_t P = 0, maxp = 0;
+    for (int i = 0; i < v->V; ++i) {
+        if (v->width[i] < 1 || v->width[i] > 16384 || v->height[i] < 1 || v->height[i] > 16384)
+            return fail(c, SOUP_ERR_INVALID, "view %d size %dx%d outside [1, 16384]", i, v->width[i], v->height[i]);
+        const int64_t np = static_cast<int64_t>(v->width[i]) * v->height[i];
+        P += np;
+        maxp = std::max(maxp, np);
+    }
+    if (!color || !target || !grad_color || !grad_logp)
+        return fail(c, SOUP_ERR_INVALID, "loss_l1_ssim: device pointers are NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    soup_status st = ensure(c, c->ssim, static_cast<size_t>(maxp) * 12 * sizeof(float));
+    if (st != SOUP_OK) return st;
+    // the window: normalised 1-D Gaussian, sigma 1.5, summed in double
+    soup::SsimWindow win{};
+    double g[2 * soup::kSsimR + 1], sum = 0.0;
+    for (int i = 0; i <= 2 * soup::kSsimR; ++i) {
+        const double x = i - soup::kSsimR;
+        g[i] = std::exp(-x * x / (2.0 * 1.5 * 1.5));
+        sum += g[i];
+    }
+    for (int i = 0; i <= 2 * soup::kSsimR; ++i) win.g[i] = static_cast<float>(g[i] / sum);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const float inv_n = static_cast<float>(1.0 / (3.0 * static_cast<double>(P)));
+    {
+        Timed t(c, SOUP_T_TLOSS, s);
+        if (loss) launch_fill_f32(loss, 1, 0.0f, s);
+        int64_t off = 0;
+        for (int i = 0; i < v->V; ++i) {
+            const int64_t np = static_cast<int64_t>(v->width[i]) * v->height[i];
+            launch_loss_l1_ssim(color + off * 3, target + off * 3, v->width[i], v->height[i], lambda, inv_n, win,
+                                static_cast<float*>(c->ssim.p), grad_color + off * 3, grad_logp + off, loss, s);
+            off += np;
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_adam_step(soup_ctx* c, float* p, const float* g, float* m, float* v, int64_t n, int32_t vec, float lr,
+                           double beta1, double beta2, float eps, int32_t t, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (n < 0 || vec < 1 || vec > 4 || n % vec != 0 || t < 1 || (n > 0 && (!p || !g || !m || !v)))
+        return fail(c, SOUP_ERR_INVALID, "adam_step: bad arguments (n = %lld, vec = %d, t = %d)", (long long)n, vec, t);
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0f))
+        return fail(c, SOUP_ERR_INVALID, "adam_step: betas must lie in [0, 1) and eps >= 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const float bc1 = static_cast<float>(1.0 - std::pow(beta1, t));
+    const float bc2 = static_cast<float>(1.0 - std::pow(beta2, t));
+    {
+        Timed tm(c, SOUP_T_ADAM, static_cast<hipStream_t>(stream));
+        launch_adam(p, g, m, v, n / vec, vec, lr, static_cast<float>(beta1), static_cast<float>(1.0 - beta1),
+                    static_cast<float>(beta2), static_cast<float>(1.0 - beta2), eps, bc1, bc2,
+                    static_cast<hipStream_t>(stream));
     }
     HIP_TRY(c, hipGetLastError());
     return SOUP_OK;

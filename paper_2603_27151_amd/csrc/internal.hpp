@@ -209,4 +209,15 @@ void launch_apply(const float* verts, const float* feats, const int32_t* actions
 int32_t plan_host(const uint32_t* counts, const float* rel, int32_t T, float split_frac, int32_t target,
                   bool prune_zero, bool fill, int32_t* actions, int32_t* offsets);
 
+// Training step: L1 + SSIM loss, Adam / VectorAdam.
+constexpr int kSsimR = 5;  // 11 x 11 window
+struct SsimWindow {
+    float g[2 * kSsimR + 1];   // normalised 1-D Gaussian, sigma 1.5; the window is its outer product
+};
+void launch_loss_l1_ssim(const float* color, const float* target, int W, int H, float lam, float inv_n,
+                         const SsimWindow& win, float* stats, float* grad_color, float* grad_logp, float* loss,
+                         hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t nvec, int vec, float lr, float b1, float omb1,
+                 float b2, float omb2, float eps, float bc1, float bc2, hipStream_t s);
+
 }  // namespace soup

@@ -245,3 +245,29 @@ def adaptive_apply(scene: DeviceScene, actions, offsets, n_new: int, ctx=None, s
     h = _lib._Holder()
     _lib.soup_adaptive_apply(ctx, scene.c_struct(h), act, off, n_new, v, f, stream)
     return DeviceScene(v, f, scene.mlp, list(scene.dims))
+
+
+# ---------------------------------------------------------------------------
+# Training step (Section 3.4 "Loss function"; Supplement, hyperparameters)
+
+def loss_l1_ssim(color, target, views: Views, lam: float = 0.8, ctx=None, stream=None, out=None):
+    """lam L1 + (1 - lam) D-SSIM over the views' images: (loss [1], dL/dcolor
+    [P,3], per-pixel score weights [P] summing to the loss)."""
+    ctx = ctx or context()
+    if out is not None:
+        loss, gc, gl = out
+    else:
+        gc = torch.empty_like(color)
+        gl = torch.empty(color.shape[0], dtype=torch.float32, device=color.device)
+        loss = torch.empty(1, dtype=torch.float32, device=color.device)
+    h = _lib._Holder()
+    _lib.soup_loss_l1_ssim(ctx, color, target, views.c_struct(h), lam, gc, gl, loss, stream)
+    return loss, gc, gl
+
+
+def adam_step(p, g, m, v, lr: float, t: int, vec: int = 1, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8, ctx=None, stream=None):
+    """In-place Adam (vec = 1) or VectorAdam (vec = 3) step t >= 1 on p, m, v
+    (v holds one entry per vec-vector)."""
+    ctx = ctx or context()
+    _lib.soup_adam_step(ctx, p, g, m, v, vec, lr, beta1, beta2, eps, t, stream)

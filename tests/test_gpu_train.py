@@ -1,0 +1,138 @@
+"""GPU parity of the training step (Section 3.4 "Loss function";
+Supplement, hyperparameters) against the oracle: the L1 + D-SSIM loss, its
+colour gradient and per-pixel score weights (ragged views, 1 x 1 images,
+pixels equal to the target), Adam and VectorAdam over several steps, and a
+short training run whose loss falls."""
+import numpy as np
+import pytest
+
+from oracle import train as TR
+from paper_2603_27151_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu-train]", *a, flush=True)
+
+
+def _R():
+    from paper_2603_27151_amd import raster as R
+    return R
+
+
+def normwise(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _smooth(rng, h, w):
+    yy, xx = np.mgrid[0:h, 0:w] / max(h, w)
+    base = np.stack([np.sin(3 * xx + c) * np.cos(2 * yy - c) for c in range(3)], -1) * 0.4 + 0.5
+    return (base + 0.05 * rng.standard_normal((h, w, 3))).clip(0, 1)
+
+
+@pytest.mark.parametrize("sizes,lam", [([(37, 23)], 0.8), ([(64, 64), (13, 200), (1, 1)], 0.8),
+                                       ([(40, 30)], 0.0), ([(40, 30)], 1.0)])
+def test_l1_ssim_matches_the_oracle(sizes, lam):
+    _say("loss", sizes, lam)
+    rng = np.random.default_rng(len(sizes) * 10 + int(lam * 10))
+    cols = [_smooth(rng, h, w) for (w, h) in sizes]
+    tgts = [_smooth(rng, h, w) * 0.9 + 0.05 for (w, h) in sizes]
+    cols[0][0, :3] = tgts[0][0, :3]                       # exact matches: sign 0
+    cols = [c.astype(np.float32) for c in cols]
+    tgts = [t.astype(np.float32) for t in tgts]
+    R = _R()
+    views = R.Views(np.array([w for w, h in sizes], np.int32), np.array([h for w, h in sizes], np.int32),
+                    np.zeros(len(sizes), np.uint32), np.tile(np.eye(4, dtype=np.float32), (len(sizes), 1, 1)))
+    c = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in cols])).cuda()
+    t = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in tgts])).cuda()
+    loss, gc, gl = R.loss_l1_ssim(c, t, views, lam)
+    torch.cuda.synchronize()
+    rl, rgc, rgl = TR.loss_l1_ssim([x.astype(np.float64) for x in cols], [x.astype(np.float64) for x in tgts], lam)
+    assert float(loss.item()) == pytest.approx(rl, rel=1e-5)
+    e1, e2 = normwise(gc.cpu().numpy(), rgc), normwise(gl.cpu().numpy(), rgl)
+    _say("grad_color", e1, "grad_logp", e2)
+    # float32 statistics: sigma^2 = E[x^2] - mu^2 cancels about two digits on
+    # smooth images, so S and 1 - S carry relative errors near 1e-5
+    assert e1 < 1e-4 and e2 < 1e-4
+
+
+def test_l1_ssim_at_full_size():
+    """Four 800 x 800 views, the paper's batch, on images of the batched
+    workload's targets: the loss and the sum of the score weights agree,
+    and sampled rows of the colour gradient match the oracle on crops that
+    contain their whole 11 x 11 x 11 x 11 dependence."""
+    R = _R()
+    rng = np.random.default_rng(77)
+    sizes = [(800, 800)] * 4
+    cols = [_smooth(rng, 800, 800).astype(np.float32) for _ in sizes]
+    tgts = [rng.random((800, 800, 3)).astype(np.float32) for _ in sizes]
+    views = R.Views(np.array([800] * 4, np.int32), np.array([800] * 4, np.int32), np.zeros(4, np.uint32),
+                    np.tile(np.eye(4, dtype=np.float32), (4, 1, 1)))
+    c = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in cols])).cuda()
+    t = torch.from_numpy(np.concatenate([x.reshape(-1, 3) for x in tgts])).cuda()
+    loss, gc, gl = R.loss_l1_ssim(c, t, views, 0.8)
+    torch.cuda.synchronize()
+    assert float(gl.sum().item()) == pytest.approx(float(loss.item()), rel=1e-4)
+    gc = gc.cpu().numpy().reshape(4, 800, 800, 3)
+    P = 4 * 800 * 800
+    for v, y, x in [(0, 0, 0), (1, 400, 400), (2, 799, 5), (3, 123, 777)]:
+        # crop of radius 10 around (y, x): the gradient at (y, x) depends on pixels within 10
+        y0, y1, x0, x1 = max(0, y - 10), min(800, y + 11), max(0, x - 10), min(800, x + 11)
+        # the crop's own border would differ from the image's, so compare only where the crop
+        # reaches the image border or extends 10 pixels past the sample
+        _, rgc, _ = TR.loss_l1_ssim([cols[v][y0:y1, x0:x1].astype(np.float64)],
+                                    [tgts[v][y0:y1, x0:x1].astype(np.float64)], 0.8)
+        n_crop = (y1 - y0) * (x1 - x0)
+        ref = rgc.reshape(y1 - y0, x1 - x0, 3)[y - y0, x - x0] * n_crop / P   # rescale 1/(3P)
+        np.testing.assert_allclose(gc[v, y, x], ref, rtol=2e-4, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,vec", [(1000, 1), (999, 3), (1, 1), (3, 3)])
+def test_adam_matches_the_oracle(n, vec):
+    _say("adam", n, vec)
+    rng = np.random.default_rng(n + vec)
+    p = rng.standard_normal(n).astype(np.float32)
+    R = _R()
+    pt = torch.from_numpy(p.copy()).cuda()
+    mt = torch.zeros(n, device="cuda")
+    vt = torch.zeros(n // vec, device="cuda")
+    rp, rm, rv = p.astype(np.float64), np.zeros(n), np.zeros(n // vec)
+    for t in range(1, 6):
+        g = (rng.standard_normal(n) * 10.0 ** rng.integers(-3, 2, size=n)).astype(np.float32)
+        lr = TR.lr_at(0.05, t - 1, 5)
+        R.adam_step(pt, torch.from_numpy(g).cuda(), mt, vt, lr, t, vec=vec)
+        rp, rm, rv = TR.adam(rp, g, rm, rv, lr, t, vec=vec)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(pt.cpu().numpy(), rp, rtol=1e-5, atol=1e-6)
+    # the moments mix gradients of both signs and magnitudes 1e-3 .. 10 in float32:
+    # absolute error of a few float32 ulps of the largest term
+    np.testing.assert_allclose(mt.cpu().numpy(), rm, rtol=1e-5, atol=1e-6 * np.abs(rm).max())
+    np.testing.assert_allclose(vt.cpu().numpy(), rv, rtol=1e-5, atol=1e-6 * np.abs(rv).max())
+
+
+def test_training_reduces_the_loss():
+    """Fit a perturbed copy of a soup to the teacher's threshold renders."""
+    from paper_2603_27151_amd import train as T
+    R = _R()
+    wl = W.single(with_targets=False, T=3000, res=128)
+    eyes = W.fibonacci_sphere(8, 3.0)
+    views = [W.View(128, 128, i, W.view_proj(eyes[i], 128, 128)) for i in range(8)]
+    teacher = R.DeviceScene.from_host(wl.scene)
+    targets = []
+    for v in views:
+        col = R.render([teacher], R.Views.from_list([v]), R.Opts(mode=1))[0]
+        targets.append(col.cpu().numpy())
+    rng = np.random.default_rng(9)
+    sc = wl.scene
+    student = R.DeviceScene.from_host(W.Scene(sc.verts, (sc.feats + rng.normal(0, 0.3, sc.feats.shape)).astype(np.float32),
+                                              sc.mlp, sc.dims))
+    tr = T.Trainer(student, views, targets, T.TrainConfig(iters=60, adapt_every=30, target_tris=3000))
+    losses = [tr.step() for _ in range(60)]
+    _say("loss", losses[0], losses[-1], "triangles", tr.scene.T)
+    assert np.isfinite(losses).all()
+    assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:10])
+    assert tr.scene.T <= 3000
