@@ -89,6 +89,7 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-adaptive", action="store_true")
+    ap.add_argument("--skip-train", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first copy this many MiB device to device three times (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -329,6 +330,44 @@ def main():
         del new, keys, tri, valid, chunk
         log("adaptive: " + json.dumps(adaptive))
 
+    # the training step's own kernels (not part of the step timed above): the
+    # L1 + D-SSIM loss on a batch of four views (the paper's batch) and one
+    # optimiser step over every parameter (VectorAdam on vertices, Adam on
+    # features and MLP), on copies of the parameters
+    train = None
+    if not args.skip_train:
+        k_tr = max(3, args.steps)
+        four = R.Views.from_list(wl.views[:4])
+        P4 = four.pixels
+        c4, t4 = color[:P4].contiguous(), target[:P4].contiguous()
+        out4 = (torch.empty(1, device=dev), torch.empty_like(c4), torch.empty(P4, device=dev))
+        R.loss_l1_ssim(c4, t4, four, 0.8, ctx=ctx, out=out4)
+        pv, pf, pm = ds.verts.clone().view(-1), ds.feats.clone().view(-1), ds.mlp.clone()
+        mv, mf, mm = torch.zeros_like(pv), torch.zeros_like(pf), torch.zeros_like(pm)
+        vv, vf, vm = torch.zeros(pv.numel() // 3, device=dev), torch.zeros_like(pf), torch.zeros_like(pm)
+        torch.cuda.synchronize()
+        ctx.read_timings()
+        ctx.set_timing(True)
+        for it in range(1, k_tr + 1):
+            R.loss_l1_ssim(c4, t4, four, 0.8, ctx=ctx, out=out4)
+            R.adam_step(pv, gv.view(-1), mv, vv, 1e-3, it, vec=3, ctx=ctx)
+            R.adam_step(pf, gf.view(-1), mf, vf, 5e-2, it, ctx=ctx)
+            R.adam_step(pm, gm, mm, vm, 1e-2, it, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        kt = ctx.read_timings()
+        loss_ms = kt["train_loss"][0] / kt["train_loss"][1]
+        adam_ms = kt["adam"][0] / k_tr                        # the three launches of one step
+        n_par = pv.numel() + pf.numel() + pm.numel()
+        adam_bytes = 28 * (pf.numel() + pm.numel()) + 24 * pv.numel() + 8 * vv.numel()
+        train = {"loss_l1_ssim": {"ms": round(loss_ms, 4), "views": 4, "pixels": int(P4),
+                                  "mpixel_s": round(P4 / (loss_ms * 1e-3) / 1e6, 1)},
+                 "adam_step": {"ms": round(adam_ms, 4), "params": int(n_par), "bytes": int(adam_bytes),
+                               "gb_s": round(adam_bytes / (adam_ms * 1e-3) / 1e9, 1),
+                               "frac_hbm": round(adam_bytes / (adam_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
+        del pv, pf, pm, mv, mf, mm, vv, vf, vm
+        log("train: " + json.dumps(train))
+
     # roofline of the dominant kernel: the MLP kernels are bound by float32
     # ALU work; their algorithmic FLOPs count the decodes the method needs
     # (E = front set + winner per pixel, counted exactly by the backward
@@ -430,6 +469,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "adaptive": adaptive,
+        "train": train,
     }
     print(json.dumps(out), flush=True)
 

@@ -3,7 +3,7 @@
 //
 //  * ssim_stats_kernel: per pixel and channel, the local statistics of the
 //    SSIM map under an 11 x 11 Gaussian window (zero outside the image):
-//    S and the three factors through which S depends on the window sums,
+//    the three factors through which S depends on the window sums,
 //        G1 = dS/dmu_x - 2 mu_x dS/dsigma_x^2 - mu_y dS/dsigma_xy,
 //        G2 = dS/dsigma_x^2,   G3 = dS/dsigma_xy,
 //    so that dS(q)/dx_p = w(p - q) (G1(q) + 2 x_p G2(q) + y_p G3(q)). It also
@@ -65,10 +65,9 @@ __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict
             const float dS_dmx = 2.0f * my * A2 / (B1 * B2) - S * 2.0f * mx / B1;
             const float dS_dvx = -S / B2;
             const float dS_dcxy = 2.0f * A1 / (B1 * B2);
-            st[c] = S;
-            st[3 + c] = dS_dmx - 2.0f * mx * dS_dvx - my * dS_dcxy;
-            st[6 + c] = dS_dvx;
-            st[9 + c] = dS_dcxy;
+            st[c] = dS_dmx - 2.0f * mx * dS_dvx - my * dS_dcxy;
+            st[3 + c] = dS_dvx;
+            st[6 + c] = dS_dcxy;
             const float d = color[p * 3 + c] - target[p * 3 + c];
             share += lam * fabsf(d) + (1.0f - lam) * (1.0f - S);
         }
@@ -98,12 +97,18 @@ __global__ void __launch_bounds__(256) ssim_grad_kernel(const float* __restrict_
             const int xx = x + dx;
             if (xx < 0 || xx >= W) continue;
             const float w = win.g[dy + kSsimR] * win.g[dx + kSsimR];
-            const float* st = stats + (static_cast<int64_t>(yy) * W + xx) * 12;
-            for (int c = 0; c < 3; ++c) {
-                s1[c] += w * st[3 + c];
-                s2[c] += w * st[6 + c];
-                s3[c] += w * st[9 + c];
-            }
+            // a pixel's record is G1[3] G2[3] G3[3] and three unused floats: three 16-byte loads
+            const float4* st = reinterpret_cast<const float4*>(stats + (static_cast<int64_t>(yy) * W + xx) * 12);
+            const float4 r0 = st[0], r1 = st[1], r2 = st[2];
+            s1[0] += w * r0.x;
+            s1[1] += w * r0.y;
+            s1[2] += w * r0.z;
+            s2[0] += w * r0.w;
+            s2[1] += w * r1.x;
+            s2[2] += w * r1.y;
+            s3[0] += w * r1.z;
+            s3[1] += w * r1.w;
+            s3[2] += w * r2.x;
         }
     }
     for (int c = 0; c < 3; ++c) {
