@@ -11,8 +11,8 @@
 //    the loss into a scalar.
 //  * ssim_grad_kernel: dL/dC = lambda sign(C - T) / (3P) minus
 //    (1 - lambda) / (3P) times the window sums of G1, G2, G3 around p.
-//    One thread per pixel; the 11 x 11 taps come through the L1 and L2
-//    caches (a view's image is read 121 times per pass, from cache).
+//    One thread per pixel of a 32 x 8 tile; the window is applied as two
+//    11-tap passes over an LDS copy of the tile and its halo.
 //  * adam_kernel: Adam (vec = 1) or VectorAdam (vec = 3: one second moment
 //    per 3-vector from its squared norm), one thread per vector.
 #include <hip/hip_runtime.h>
@@ -26,39 +26,65 @@ namespace {
 constexpr float kC1 = 0.0001f;  // 0.01^2
 constexpr float kC2 = 0.0009f;  // 0.03^2
 
+// Both SSIM passes work on 32 x 8 pixel tiles, one thread per pixel. The
+// tile plus its 5-pixel halo is staged in LDS (zeros outside the image: the
+// zero padding of the definition), filtered along rows for the tile's
+// columns, then along columns: 22 taps per map instead of 121.
+constexpr int kTW = 32, kTH = 8;
+constexpr int kHW = kTW + 2 * kSsimR, kHH = kTH + 2 * kSsimR;
+
 __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict__ color,
                                                          const float* __restrict__ target, int W, int H, float lam,
                                                          float inv_n, SsimWindow win, float* __restrict__ stats,
                                                          float* __restrict__ grad_logp, float* __restrict__ loss) {
+    __shared__ float in[kHH][kHW][6];   // colour rgb, target rgb
+    __shared__ float hs[kHH][kTW][15];  // row sums: x, y, x^2, y^2, xy per channel
     __shared__ float part[4];
-    const int64_t np = static_cast<int64_t>(W) * H;
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    float share = 0.0f;
-    if (p < np) {
-        const int x = static_cast<int>(p % W), y = static_cast<int>(p / W);
-        float sx[3] = {0, 0, 0}, sy[3] = {0, 0, 0}, sxx[3] = {0, 0, 0}, syy[3] = {0, 0, 0}, sxy[3] = {0, 0, 0};
-        for (int dy = -kSsimR; dy <= kSsimR; ++dy) {
-            const int yy = y + dy;
-            if (yy < 0 || yy >= H) continue;
-            for (int dx = -kSsimR; dx <= kSsimR; ++dx) {
-                const int xx = x + dx;
-                if (xx < 0 || xx >= W) continue;
-                const float w = win.g[dy + kSsimR] * win.g[dx + kSsimR];
-                const int64_t q = static_cast<int64_t>(yy) * W + xx;
-                for (int c = 0; c < 3; ++c) {
-                    const float a = color[q * 3 + c], b = target[q * 3 + c];
-                    sx[c] += w * a;
-                    sy[c] += w * b;
-                    sxx[c] += w * (a * a);
-                    syy[c] += w * (b * b);
-                    sxy[c] += w * (a * b);
-                }
+    const int tx0 = blockIdx.x * kTW, ty0 = blockIdx.y * kTH;
+    for (int i = threadIdx.x; i < kHH * kHW; i += blockDim.x) {
+        const int r = i / kHW, cc = i % kHW;
+        const int gx = tx0 + cc - kSsimR, gy = ty0 + r - kSsimR;
+        const bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
+        const int64_t q = ok ? static_cast<int64_t>(gy) * W + gx : 0;
+        for (int c = 0; c < 3; ++c) {
+            in[r][cc][c] = ok ? color[q * 3 + c] : 0.0f;
+            in[r][cc][3 + c] = ok ? target[q * 3 + c] : 0.0f;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHH * kTW; i += blockDim.x) {
+        const int r = i / kTW, col = i % kTW;
+        float acc[15];
+        for (int j = 0; j < 15; ++j) acc[j] = 0.0f;
+        for (int k = 0; k <= 2 * kSsimR; ++k) {
+            const float w = win.g[k];
+            for (int c = 0; c < 3; ++c) {
+                const float a = in[r][col + k][c], b = in[r][col + k][3 + c];
+                acc[c] += w * a;
+                acc[3 + c] += w * b;
+                acc[6 + c] += w * (a * a);
+                acc[9 + c] += w * (b * b);
+                acc[12 + c] += w * (a * b);
             }
         }
+        for (int j = 0; j < 15; ++j) hs[r][col][j] = acc[j];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % kTW, ly = threadIdx.x / kTW;
+    const int x = tx0 + lx, y = ty0 + ly;
+    float share = 0.0f;
+    if (x < W && y < H) {
+        float sm[15];
+        for (int j = 0; j < 15; ++j) sm[j] = 0.0f;
+        for (int k = 0; k <= 2 * kSsimR; ++k) {
+            const float w = win.g[k];
+            for (int j = 0; j < 15; ++j) sm[j] += w * hs[ly + k][lx][j];
+        }
+        const int64_t p = static_cast<int64_t>(y) * W + x;
         float* st = stats + p * 12;
         for (int c = 0; c < 3; ++c) {
-            const float mx = sx[c], my = sy[c];
-            const float vx = sxx[c] - mx * mx, vy = syy[c] - my * my, cxy = sxy[c] - mx * my;
+            const float mx = sm[c], my = sm[3 + c];
+            const float vx = sm[6 + c] - mx * mx, vy = sm[9 + c] - my * my, cxy = sm[12 + c] - mx * my;
             const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
             const float B1 = mx * mx + my * my + kC1, B2 = vx + vy + kC2;
             const float S = (A1 * A2) / (B1 * B2);
@@ -68,7 +94,7 @@ __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict
             st[c] = dS_dmx - 2.0f * mx * dS_dvx - my * dS_dcxy;
             st[3 + c] = dS_dvx;
             st[6 + c] = dS_dcxy;
-            const float d = color[p * 3 + c] - target[p * 3 + c];
+            const float d = in[ly + kSsimR][lx + kSsimR][c] - in[ly + kSsimR][lx + kSsimR][3 + c];
             share += lam * fabsf(d) + (1.0f - lam) * (1.0f - S);
         }
         share *= inv_n;
@@ -85,37 +111,56 @@ __global__ void __launch_bounds__(256) ssim_grad_kernel(const float* __restrict_
                                                         const float* __restrict__ target, int W, int H, float lam,
                                                         float inv_n, SsimWindow win, const float* __restrict__ stats,
                                                         float* __restrict__ grad_color) {
-    const int64_t np = static_cast<int64_t>(W) * H;
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int x = static_cast<int>(p % W), y = static_cast<int>(p / W);
-    float s1[3] = {0, 0, 0}, s2[3] = {0, 0, 0}, s3[3] = {0, 0, 0};
-    for (int dy = -kSsimR; dy <= kSsimR; ++dy) {
-        const int yy = y + dy;
-        if (yy < 0 || yy >= H) continue;
-        for (int dx = -kSsimR; dx <= kSsimR; ++dx) {
-            const int xx = x + dx;
-            if (xx < 0 || xx >= W) continue;
-            const float w = win.g[dy + kSsimR] * win.g[dx + kSsimR];
-            // a pixel's record is G1[3] G2[3] G3[3] and three unused floats: three 16-byte loads
-            const float4* st = reinterpret_cast<const float4*>(stats + (static_cast<int64_t>(yy) * W + xx) * 12);
+    __shared__ float in[kHH][kHW][9];   // G1, G2, G3 per channel (zero outside the image)
+    __shared__ float hs[kHH][kTW][9];
+    const int tx0 = blockIdx.x * kTW, ty0 = blockIdx.y * kTH;
+    for (int i = threadIdx.x; i < kHH * kHW; i += blockDim.x) {
+        const int r = i / kHW, cc = i % kHW;
+        const int gx = tx0 + cc - kSsimR, gy = ty0 + r - kSsimR;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+            // a record is G1[3] G2[3] G3[3] and three unused floats: three 16-byte loads
+            const float4* st = reinterpret_cast<const float4*>(stats + (static_cast<int64_t>(gy) * W + gx) * 12);
             const float4 r0 = st[0], r1 = st[1], r2 = st[2];
-            s1[0] += w * r0.x;
-            s1[1] += w * r0.y;
-            s1[2] += w * r0.z;
-            s2[0] += w * r0.w;
-            s2[1] += w * r1.x;
-            s2[2] += w * r1.y;
-            s3[0] += w * r1.z;
-            s3[1] += w * r1.w;
-            s3[2] += w * r2.x;
+            in[r][cc][0] = r0.x;
+            in[r][cc][1] = r0.y;
+            in[r][cc][2] = r0.z;
+            in[r][cc][3] = r0.w;
+            in[r][cc][4] = r1.x;
+            in[r][cc][5] = r1.y;
+            in[r][cc][6] = r1.z;
+            in[r][cc][7] = r1.w;
+            in[r][cc][8] = r2.x;
+        } else {
+            for (int j = 0; j < 9; ++j) in[r][cc][j] = 0.0f;
         }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHH * kTW; i += blockDim.x) {
+        const int r = i / kTW, col = i % kTW;
+        float acc[9];
+        for (int j = 0; j < 9; ++j) acc[j] = 0.0f;
+        for (int k = 0; k <= 2 * kSsimR; ++k) {
+            const float w = win.g[k];
+            for (int j = 0; j < 9; ++j) acc[j] += w * in[r][col + k][j];
+        }
+        for (int j = 0; j < 9; ++j) hs[r][col][j] = acc[j];
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % kTW, ly = threadIdx.x / kTW;
+    const int x = tx0 + lx, y = ty0 + ly;
+    if (x >= W || y >= H) return;
+    float sm[9];
+    for (int j = 0; j < 9; ++j) sm[j] = 0.0f;
+    for (int k = 0; k <= 2 * kSsimR; ++k) {
+        const float w = win.g[k];
+        for (int j = 0; j < 9; ++j) sm[j] += w * hs[ly + k][lx][j];
+    }
+    const int64_t p = static_cast<int64_t>(y) * W + x;
     for (int c = 0; c < 3; ++c) {
         const float a = color[p * 3 + c], b = target[p * 3 + c];
         const float d = a - b;
         const float sgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-        const float dssim = s1[c] + 2.0f * a * s2[c] + b * s3[c];
+        const float dssim = sm[c] + 2.0f * a * sm[3 + c] + b * sm[6 + c];
         grad_color[p * 3 + c] = inv_n * (lam * sgn - (1.0f - lam) * dssim);
     }
 }
@@ -150,10 +195,10 @@ void launch_loss_l1_ssim(const float* color, const float* target, int W, int H, 
                          hipStream_t s) {
     const int64_t np = static_cast<int64_t>(W) * H;
     if (np <= 0) return;
-    const unsigned g = static_cast<unsigned>((np + 255) / 256);
-    hipLaunchKernelGGL(ssim_stats_kernel, dim3(g), dim3(256), 0, s, color, target, W, H, lam, inv_n, win, stats,
+    const dim3 g(static_cast<unsigned>((W + kTW - 1) / kTW), static_cast<unsigned>((H + kTH - 1) / kTH));
+    hipLaunchKernelGGL(ssim_stats_kernel, g, dim3(kTW * kTH), 0, s, color, target, W, H, lam, inv_n, win, stats,
                        grad_logp, loss);
-    hipLaunchKernelGGL(ssim_grad_kernel, dim3(g), dim3(256), 0, s, color, target, W, H, lam, inv_n, win, stats,
+    hipLaunchKernelGGL(ssim_grad_kernel, g, dim3(kTW * kTH), 0, s, color, target, W, H, lam, inv_n, win, stats,
                        grad_color);
 }
 
