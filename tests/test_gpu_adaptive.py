@@ -148,3 +148,39 @@ def test_adaptive_round_trip_renders():
     assert torch.isfinite(color2).all()
     # the split halves cover what their parents covered: coverage is not lost wholesale
     assert int((vis2 != -1).sum()) > 0.9 * int((vis != -1).sum())
+
+
+def test_adaptive_at_full_size_on_sampled_triangles():
+    """The batched workload's soup (50,000 triangles, 8 x 8 x 16 textures):
+    coverage over its 64 views, edge lengths over 20 of them, the plan of a
+    random initialisation, and the applied soup, checked against the oracle
+    on sampled triangles (edge lengths; each sampled source's outputs)."""
+    R = _R()
+    wl = W.batched(with_targets=False)
+    sc = R.DeviceScene.from_host(wl.scene)
+    views = R.Views.from_list(wl.views)
+    vis, _, _ = R.rasterize_fwd(sc, views, R.Opts(seed=wl.seed), want_logp=False)
+    counts = R.coverage_count(vis, sc.T)
+    pick = np.sort(np.random.default_rng(20).choice(len(wl.views), size=20, replace=False))
+    sample = [wl.views[i] for i in pick]
+    rel = R.edge_lengths(sc.verts, R.Views.from_list(sample)).cpu().numpy()
+    act, off, n = R.adaptive_plan(counts, rel, 0.2, target=sc.T, prune_zero=True, fill=True)
+    assert n == sc.T
+    new = R.adaptive_apply(sc, act, off, n)
+    torch.cuda.synchronize()
+    nv, nf = new.verts.cpu().numpy(), new.feats.cpu().numpy()
+    rng = np.random.default_rng(21)
+    split_ids = np.nonzero(act >= A.SPLIT0)[0]
+    keep_ids = np.nonzero(act == A.KEEP)[0]
+    ids = np.concatenate([rng.choice(split_ids, size=min(20, split_ids.size), replace=False),
+                          rng.choice(keep_ids, size=20, replace=False)])
+    _say("full size: splits", split_ids.size, "sampled", ids.size)
+    ref_rel = A.edge_lengths(wl.scene.verts[ids], np.stack([v.M for v in sample]),
+                             [v.width for v in sample], [v.height for v in sample], 0.1)
+    np.testing.assert_allclose(rel[ids], ref_rel, rtol=1e-6, atol=0)
+    for t in ids:
+        kids = 2 if act[t] >= A.SPLIT0 else 1
+        ov, of = A.apply(wl.scene.verts[t:t + 1], wl.scene.feats[t:t + 1], act[t:t + 1], np.zeros(1, np.int32), kids)
+        o = int(off[t])
+        assert np.array_equal(nv[o:o + kids], ov)
+        np.testing.assert_allclose(nf[o:o + kids], of, rtol=1e-6, atol=1e-6)
