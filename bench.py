@@ -366,6 +366,24 @@ def main():
                                "gb_s": round(adam_bytes / (adam_ms * 1e-3) / 1e9, 1),
                                "frac_hbm": round(adam_bytes / (adam_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
         del pv, pf, pm, mv, mf, mm, vv, vf, vm
+        # whole training iterations as the paper runs them: four random views
+        # of the 64, stochastic forward, loss, backward, three optimiser
+        # launches (one host synchronisation per iteration, for the loss value)
+        from paper_2603_27151_amd import train as TRN
+        student = R.DeviceScene(ds.verts.clone(), ds.feats.clone(), ds.mlp.clone(), list(ds.dims))
+        trainer = TRN.Trainer(student, wl.views, wl.targets, TRN.TrainConfig(iters=1000), ctx=ctx)
+        for _ in range(2):
+            trainer.step()
+        torch.cuda.synchronize()
+        n_it = max(5, args.steps)
+        t0 = time.perf_counter()
+        for _ in range(n_it):
+            trainer.step()
+        torch.cuda.synchronize()
+        it_ms = (time.perf_counter() - t0) * 1e3 / n_it
+        train["iteration"] = {"ms": round(it_ms, 3), "iters_per_s": round(1e3 / it_ms, 1), "views": 4,
+                              "mean_pixels": int(np.mean([v.width * v.height for v in wl.views]) * 4)}
+        del student, trainer
         log("train: " + json.dumps(train))
 
     # roofline of the dominant kernel: the MLP kernels are bound by float32
