@@ -91,7 +91,7 @@ def test_l1_ssim_at_full_size():
         np.testing.assert_allclose(gc[v, y, x], ref, rtol=2e-4, atol=1e-12)
 
 
-@pytest.mark.parametrize("n,vec", [(1000, 1), (999, 3), (1, 1), (3, 3)])
+@pytest.mark.parametrize("n,vec", [(1000, 1), (1002, 1), (999, 3), (1, 1), (3, 3)])
 def test_adam_matches_the_oracle(n, vec):
     _say("adam", n, vec)
     rng = np.random.default_rng(n + vec)
