@@ -43,7 +43,8 @@ class TrainConfig:
 
 class Trainer:
     def __init__(self, scene: R.DeviceScene, views: Sequence, targets: Sequence[np.ndarray],
-                 cfg: TrainConfig = TrainConfig(), ctx=None):
+                 cfg: Optional[TrainConfig] = None, ctx=None):
+        cfg = cfg or TrainConfig()
         self.cfg = cfg
         self.ctx = ctx or R.context()
         self.scene = scene
