@@ -189,8 +189,11 @@ soup_status soup_rasterize_fwd(soup_ctx* ctx, const soup_scene* scene, const sou
  * Outputs (device): grad_verts [T,3,3], grad_feats [T,G,G,C], grad_mlp
  * [n_params]; overwritten, or added into when opts->accumulate is 1 (a loop
  * over views can then sum its gradients in place).
- *   winner f*:        colour path (exact derivative with draws fixed) plus
- *                     score g_L (1 - alpha*) on its opacity logit;
+ *   winner f*:        colour path (exact derivative with draws fixed),
+ *                     through the texture position to the vertices, plus
+ *                     score g_L (1 - alpha*) on its opacity logit (features
+ *                     and MLP only: the score term moves no vertex, Section
+ *                     3.2);
  *   f in front of f*: score -g_L alpha_f on its opacity logit (features and
  *                     MLP only, no vertex motion);
  *   adjacent pixel pairs (a, b = a + e): w = 1/2 (g_a + g_b).(C_a - C_b)

@@ -764,6 +764,11 @@ static void backprop_at(const view_ctx* c, const frag_t* f, int x, int y, const 
  * fragment in front of it, pushed through the sigmoid:
  *   winner:  g_L * (1/alpha) * alpha(1-alpha) = g_L (1 - alpha)
  *   in front: g_L * (-1/(1-alpha)) * alpha(1-alpha) = -g_L alpha
+ * The score term is an opacity gradient only (Eq. (8), second term; Section
+ * 3.2 opens its discussion of visibility discontinuities by noting that the
+ * masking gives no motion gradient): for every fragment, the winner
+ * included, it reaches the texture and the MLP but not the vertices. Only
+ * the winner's colour logits are chained to its vertex positions.
  * Reading for the background (no fragment passes): it is an always-opaque
  * layer behind everything with no parameters, so every fragment is in front. */
 static void pixel_backward(const view_ctx* c, int x, int y, const frag_buf* b, uint64_t key_star,
@@ -798,7 +803,12 @@ static void pixel_backward(const view_ctx* c, int x, int y, const frag_buf* b, u
                 }
                 if (c->o->mode == 0) d[3] = gL * (1.0 - sigmoid_d(a64[L][3]));
             }
-            backprop_at(c, f, x, y, d, 1, go);
+            /* colour logits: through the texture position to the vertices;
+             * the score logit: texture and MLP only */
+            const double d_col[4] = {d[0], d[1], d[2], 0.0};
+            const double d_score[4] = {0.0, 0.0, 0.0, d[3]};
+            backprop_at(c, f, x, y, d_col, 1, go);
+            if (d[3] != 0.0) backprop_at(c, f, x, y, d_score, 0, go);
             break;
         }
         if (c->o->mode != 0 || gL == 0.0) continue;

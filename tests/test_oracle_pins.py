@@ -479,6 +479,114 @@ def test_estimator_is_unbiased_for_expected_loss():
     assert np.all(np.abs(sc.mean(0) - drgb) < 5 * se_c + 1e-9), (sc.mean(0), drgb, se_c)
 
 
+def test_score_term_moves_no_vertex():
+    """Section 3.2: the masking yields opacity gradients but no motion
+    gradient; the score term of Eq. (8) reaches features and MLP only. On the
+    tiny workload (textured, random MLP) with the edge term off, a score-only
+    upstream gradient must leave every vertex gradient exactly zero, for the
+    winners as for the fragments in front of them."""
+    wl = W.tiny()
+    view = wl.views[0]
+    for analysis in (0, 1):
+        o = O.Opts(seed=wl.seed, edge_pairs=2, analysis=analysis)
+        vis, color, _, st = O.forward(wl.scene, view, o)
+        assert st["winners"] > 100 and st["front_fragments"] > 100
+        rng = np.random.default_rng(9)
+        gl = rng.uniform(0.1, 1.0, (view.height, view.width)).astype(np.float32)
+        zero_c = np.zeros((view.height, view.width, 3), np.float32)
+        gv, gf, gm = O.backward(wl.scene, view, o, vis, color, zero_c, gl)
+        assert np.all(gv == 0.0)
+        assert np.abs(gf).max() > 1e-3 and np.abs(gm).max() > 1e-3
+        # the vertex gradient of a mixed upstream gradient is the colour path's alone
+        gc = rng.normal(0, 1, (view.height, view.width, 3)).astype(np.float32)
+        gv_c, _, _ = O.backward(wl.scene, view, o, vis, color, gc, None)
+        gv_m, gf_m, _ = O.backward(wl.scene, view, o, vis, color, gc, gl)
+        assert np.abs(gv_c).max() > 1e-3
+        assert np.allclose(gv_m, gv_c, rtol=1e-12, atol=1e-14 * np.abs(gv_c).max())
+
+
+def _bary_screen(tri_xy, px, py):
+    """float64 barycentrics of the pixel centre in a screen triangle."""
+    (x0, y0), (x1, y1), (x2, y2) = tri_xy
+    a = (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0)
+    b1 = ((px - x0) * (y2 - y0) - (py - y0) * (x2 - x0)) / a
+    b2 = ((x1 - x0) * (py - y0) - (y1 - y0) * (px - x0)) / a
+    return 1.0 - b1 - b2, b1, b2
+
+
+def test_estimator_is_unbiased_on_textured_layers():
+    """Eq. (8) on layers whose opacity and colour vary over the triangle: the
+    mean of the estimator's per-texel gradients over independent draws equals
+    the exact derivative of E_p[L] = sum_p sum_f p(f) L(C_f(p)) (Eq. (6), (7)),
+    computed here from float64 barycentrics of an orthographic view. The
+    texture position of a fragment depends on the vertices, so E_p[L] has a
+    vertex derivative through alpha too; the estimator leaves that out
+    (Section 3.2), which a score-only upstream gradient shows as an exactly
+    zero vertex gradient."""
+    Wd, Hd, G = 16, 12, 2            # W != H: no pixel centre on a square's diagonal
+    zs = [-0.4, 0.3]
+    rng = np.random.default_rng(77)
+    n = len(zs)
+    tris, feats = [], []
+    quad = [(-1, -1), (1, -1), (1, 1), (-1, 1)]
+    for k in range(n):
+        for (a, b, c) in [(0, 1, 2), (0, 2, 3)]:
+            tris.append(np.array([[*quad[a], zs[k]], [*quad[b], zs[k]], [*quad[c], zs[k]]], np.float32))
+            f = np.zeros((G, G, 8), np.float32)
+            f[..., 0] = rng.uniform(-1.2, 1.2, (G, G))     # opacity logit per texel
+            f[..., 1:4] = rng.uniform(-1.5, 1.5, (G, G, 3))
+            feats.append(f)
+    scene = W.Scene(np.array(tris), np.array(feats), W.passthrough_mlp(8, 16), [8, 16, 4])
+    view = S.ortho_view(Wd, Hd)
+    target = np.array([0.2, 0.7, 0.4])
+
+    def sig(x):
+        return 1.0 / (1.0 + np.exp(-x))
+
+    # exact derivative of the expected loss with respect to every texel feature
+    T = len(tris)
+    exact = np.zeros((T, G, G, 8))
+    for py in range(Hd):
+        for px in range(Wd):
+            cx, cy = px + 0.5, py + 0.5
+            layer = []
+            for k in range(n):
+                for t in (2 * k, 2 * k + 1):
+                    xy = [((v[0] + 1) * Wd / 2, (1 - v[1]) * Hd / 2) for v in scene.verts[t]]
+                    b = _bary_screen(xy, cx, cy)
+                    if min(b) > 0:
+                        w = np.array([[(1 - b[1]) * (1 - b[2]), b[1] * (1 - b[2])],
+                                      [(1 - b[1]) * b[2], b[1] * b[2]]])      # [iy][ix]
+                        lg = (w[..., None] * scene.feats[t].astype(np.float64)).sum((0, 1))
+                        layer.append((t, w, sig(lg[0]), sig(lg[1:4])))
+            assert len(layer) == n
+            al = [l[2] for l in layer]
+            cols = [l[3] for l in layer]
+            p = [np.prod([1 - al[j] for j in range(k)]) * al[k] for k in range(n)] + [np.prod([1 - a for a in al])]
+            Lf = [float(((c - target) ** 2).sum()) for c in cols] + [float((target ** 2).sum())]
+            for k, (t, w, a, c) in enumerate(layer):
+                dE = Lf[k] * p[k] / a - sum(Lf[f] * p[f] / (1 - a) for f in range(k + 1, n + 1))
+                exact[t, :, :, 0] += dE * a * (1 - a) * w
+                exact[t, :, :, 1:4] += (p[k] * 2 * (c - target) * c * (1 - c))[None, None, :] * w[..., None]
+
+    samples = []
+    for step in range(40):
+        o = O.Opts(seed=515, step=step, edge_pairs=2)
+        vis, color, _, _ = O.forward(scene, view, o)
+        c = color.astype(np.float64)
+        gC = (2 * (c - target)).astype(np.float32)
+        gL = ((c - target) ** 2).sum(-1).astype(np.float32)
+        gv, gf, _ = O.backward(scene, view, o, vis, color, gC, gL)
+        samples.append(gf[..., :4].ravel())
+        gv_s, _, _ = O.backward(scene, view, o, vis, color, np.zeros_like(gC), gL)
+        assert np.all(gv_s == 0.0)
+    sm = np.array(samples)
+    se = sm.std(0, ddof=1) / math.sqrt(len(sm))
+    want = exact[..., :4].ravel()
+    assert np.abs(want).max() > 1e-2
+    assert np.all(np.abs(sm.mean(0) - want) < 5 * se + 1e-9), np.abs(sm.mean(0) - want) / (se + 1e-12)
+
+
 # --------------------------------------------------------------------------
 # Colour-path gradients (Algorithm A1, 2(a)) by finite differences
 # --------------------------------------------------------------------------
