@@ -75,6 +75,64 @@ def measured_traffic(kernel: str, workload: str, tile: int):
                float(kv[f"{kernel}.write_kb"]) * 1024 * float(kv["write_scale"]))
 
 
+class Step:
+    """One step of the hot path on one stream, into preallocated buffers:
+    soup_rasterize_fwd (keeping its tile lists and fragment log) ->
+    soup_loss_l2 -> soup_rasterize_bwd (reusing both). The same object is
+    run eagerly, in static-capacity mode and under HIP-graph capture."""
+
+    def __init__(self, R, ctx, ds, vs, target, seed, step=0):
+        import torch
+        self.R, self.ctx, self.ds, self.vs, self.target = R, ctx, ds, vs, target
+        dev = ds.verts.device
+        P = vs.pixels
+        self.opts = R.Opts(seed=seed, step=step, reuse_bins=1)
+        self.vis = torch.empty(P, dtype=torch.int64, device=dev)
+        self.color = torch.empty(P, 3, dtype=torch.float32, device=dev)
+        self.loss = torch.empty(1, dtype=torch.float32, device=dev)
+        self.gc = torch.empty(P, 3, dtype=torch.float32, device=dev)
+        self.gl = torch.empty(P, dtype=torch.float32, device=dev)
+        self.gv = torch.empty_like(ds.verts)
+        self.gf = torch.empty_like(ds.feats)
+        self.gm = torch.empty_like(ds.mlp)
+
+    def __call__(self):
+        R, ctx = self.R, self.ctx
+        R.rasterize_fwd(self.ds, self.vs, self.opts, ctx=ctx, out=(self.vis, self.color, None))
+        R.loss_l2(self.color, self.target, ctx=ctx, out=(self.loss, self.gc, self.gl))
+        R.rasterize_bwd(self.ds, self.vs, self.opts, self.vis, self.color, self.gc, self.gl, ctx=ctx,
+                        out=(self.gv, self.gf, self.gm))
+
+    def capture(self, log=None):
+        """Static-capacity mode, then one HIP-graph capture of the step; returns
+        the graph (static mode stays on until the caller turns it off). A
+        static step that overflows the workspaces sized by the eager calls is
+        rerun eagerly (which grows them) and tried again."""
+        import torch
+        from paper_2603_27151_amd import _lib
+        for attempt in range(3):
+            self.ctx.set_static(True)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                self()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            try:
+                self.ctx.check_overflow()
+                break
+            except _lib.SoupError as e:
+                if log:
+                    log(f"static step overflowed ({e}); growing the workspaces")
+                self.ctx.set_static(False)
+                self()
+                torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self()
+        return g
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,23 +187,11 @@ def main():
     P = vs.pixels
     target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
     ctx = R.context()
-    opts = R.Opts(seed=wl.seed, step=wl.step)
     # the forward keeps its tile lists and a log of its decoded fragments; the backward reuses both
-    opts_b = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1)
-    P3 = (P, 3)
-    vis = torch.empty(P, dtype=torch.int64, device=dev)
-    color = torch.empty(P3, dtype=torch.float32, device=dev)
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
-    gc = torch.empty(P3, dtype=torch.float32, device=dev)
-    gl = torch.empty(P, dtype=torch.float32, device=dev)
-    gv = torch.empty_like(ds.verts)
-    gf = torch.empty_like(ds.feats)
-    gm = torch.empty_like(ds.mlp)
-
-    def step():
-        R.rasterize_fwd(ds, vs, opts_b, ctx=ctx, out=(vis, color, None))
-        R.loss_l2(color, target, ctx=ctx, out=(loss, gc, gl))
-        R.rasterize_bwd(ds, vs, opts_b, vis, color, gc, gl, ctx=ctx, out=(gv, gf, gm))
+    step = Step(R, ctx, ds, vs, target, wl.seed, wl.step)
+    opts_b = step.opts
+    vis, color, loss, gc, gl = step.vis, step.color, step.loss, step.gc, step.gl
+    gv, gf, gm = step.gv, step.gf, step.gm
 
     # tile size: given, or measured (every candidate runs the step)
     from paper_2603_27151_amd import autotune
@@ -172,9 +218,13 @@ def main():
     st_bwd = ctx.stats()
     ctx.set_counting(False)
     torch.cuda.synchronize()
-    covered = int((vis != -1).sum().item())
+    winners = int((vis != -1).sum().item())           # pixels where some fragment passes
+    P_cov = st_fwd["covered_pixels"]                   # pixels that at least one fragment covers
+    # winners that also carry a score weight: their colour logits get a data backward of their own
+    W_s = int(((vis != -1) & (gl != 0)).sum().item())
     E = st_bwd["decodes"]          # front set + winner of every pixel: the method's decodes
-    log(f"counts: bins={st_fwd['bin_entries']} fwd decodes={st_fwd['decodes']} E={E} covered={covered}")
+    log(f"counts: bins={st_fwd['bin_entries']} fwd decodes={st_fwd['decodes']} E={E} winners={winners} "
+        f"P_cov={P_cov} W_s={W_s}")
 
     def timed(fn, k):
         torch.cuda.synchronize()
@@ -205,29 +255,7 @@ def main():
     graph = False
     if not args.no_graph:
         ref = (vis.clone(), gv.clone())
-        from paper_2603_27151_amd import _lib
-        for attempt in range(3):
-            # static mode outside capture first; an overflow means the eager
-            # calls' capacities were short for this run: rerun eagerly (which
-            # grows them) and try again
-            ctx.set_static(True)
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                step()
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            try:
-                ctx.check_overflow()
-                break
-            except _lib.SoupError as e:
-                log(f"static step overflowed ({e}); growing the workspaces")
-                ctx.set_static(False)
-                step()
-                torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            step()
+        g = step.capture(log)
         g.replay()
         torch.cuda.synchronize()
         ctx.check_overflow()
@@ -242,21 +270,27 @@ def main():
     mpix = P / (ms * 1e-3) / 1e6
     log(f"batched step {ms:.3f} ms -> {mpix:.1f} Mpixel/s")
 
-    # per-view path on the same GPU: a host loop of single-view calls,
-    # gradients summed in place (accumulate)
+    # per-view path on the same GPU: a host loop of single-view calls with the
+    # batched step's options (the forward keeps its tile lists and fragment
+    # log, the backward reuses both), gradients summed in place (accumulate),
+    # outputs written into slices of the batched step's buffers
     per_view = None
     if not args.skip_per_view:
         singles = [R.Views.from_list([v]) for v in wl.views]
         offs = vs.offsets()
-        opts_acc = R.Opts(seed=wl.seed, step=wl.step, accumulate=1)
+        opts_f = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1)
+        opts_acc = R.Opts(seed=wl.seed, step=wl.step, accumulate=1, reuse_bins=1)
+        loss_i = torch.empty(1, dtype=torch.float32, device=dev)
 
         def step_pv():
             gv.zero_()
             gf.zero_()
             gm.zero_()
             for i, sv in enumerate(singles):
-                vis_i, col_i, _ = R.rasterize_fwd(ds, sv, opts, ctx=ctx)
-                _, gc_i, gl_i = R.loss_l2(col_i, target[offs[i]:offs[i + 1]], ctx=ctx)
+                a, b = int(offs[i]), int(offs[i + 1])
+                vis_i, col_i, gc_i, gl_i = vis[a:b], color[a:b], gc[a:b], gl[a:b]
+                R.rasterize_fwd(ds, sv, opts_f, ctx=ctx, out=(vis_i, col_i, None))
+                R.loss_l2(col_i, target[a:b], ctx=ctx, out=(loss_i, gc_i, gl_i))
                 R.rasterize_bwd(ds, sv, opts_acc, vis_i, col_i, gc_i, gl_i, ctx=ctx, out=(gv, gf, gm))
 
         step_pv()
@@ -268,7 +302,9 @@ def main():
         torch.cuda.synchronize()
         pv_ms = (time.perf_counter() - t0) * 1e3 / n_pv
         per_view = {"ms_per_step": round(pv_ms, 3), "mpixel_s": round(P / (pv_ms * 1e-3) / 1e6, 1),
-                    "batched_speedup": round(pv_ms / ms, 3)}
+                    "options": "reuse_bins=1 on forward and backward, as the batched step",
+                    "batched_speedup": round(pv_ms / ms, 3),
+                    "batched_eager_speedup": round(pv_ms / eager_ms, 3)}
         log(f"per-view path {pv_ms:.3f} ms -> {per_view['mpixel_s']} Mpixel/s")
 
     # adaptive control of primitives on the same soup and visibility buffer
@@ -388,12 +424,16 @@ def main():
 
     # roofline of the dominant kernel: the MLP kernels are bound by float32
     # ALU work; their algorithmic FLOPs count the decodes the method needs
-    # (E = front set + winner per pixel, counted exactly by the backward
-    # replay; P_cov covered pixels re-shade their winner in the forward)
+    # (E = front set + winner per pixel, counted exactly by the backward's
+    # decode). The forward shades a winner from the decode that tests it, so
+    # it needs E decodes and no re-shade; the backward recomputes, back-
+    # propagates and forms the weight gradient of every one of the E, plus a
+    # second data backward for the colour logits of each winner that also
+    # carries a score weight (its vertices move with those alone)
     macs = mlp_macs(ds.dims)
     work = {
-        "decode_bwd": 6.0 * macs * E,               # recompute + data backward + weight gradient
-        "raster_fwd": 2.0 * macs * (E + covered),   # decodes up to the winner + winner shading
+        "decode_bwd": 6.0 * macs * E + 2.0 * macs * W_s,
+        "raster_fwd": 2.0 * macs * E,
     }
     dom = max(work, key=lambda k: per_kernel.get(k, 0.0))
     t_dom = per_kernel[dom]
@@ -479,7 +519,9 @@ def main():
                    "tile": tile, "autotune_ms": None if tuning is None else tuning["ms"],
                    "hip_graph": graph, "eager_ms_per_step": round(eager_ms, 4),
                    "triangles_per_s": round(ds.T * vs.V / (ms * 1e-3), 1),
-                   "decodes_E": E, "covered_pixels": covered, "bin_entries": st_fwd["bin_entries"]},
+                   "decodes_E": E, "winners": winners, "covered_pixels_P_cov": P_cov,
+                   "winners_with_score_weight": W_s, "forward_decodes": st_fwd["decodes"],
+                   "bin_entries": st_fwd["bin_entries"]},
         "per_view": per_view,
         "kernels_ms": {k: round(v, 4) for k, v in per_kernel.items() if v > 0},
         "roofline": roofline,

@@ -92,7 +92,10 @@ typedef struct {
     int64_t tiles;             /* screen tiles of all views */
     int64_t bin_entries;       /* (tile, triangle) pairs after binning */
     int64_t visible_tris;      /* (view, triangle) records that survived culling */
-    int64_t decodes;           /* texture + MLP decodes performed by the raster kernel */
+    int64_t decodes;           /* texture + MLP decodes performed by the raster kernel (forward,
+                                  render) or by the backward's decode (the fragments it needs) */
+    int64_t covered_pixels;    /* forward and render: pixels that at least one fragment covers
+                                  (Eq. (1)); -1 for the backward */
 } soup_stats;
 
 /* Create a context on HIP device `device`. Owns the workspaces (triangle

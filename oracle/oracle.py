@@ -124,12 +124,19 @@ def forward(scene, view, opts: Opts, want_logp: bool = True):
             logp.reshape(H, W) if want_logp else None, stats)
 
 
-def backward(scene, view, opts: Opts, vis, color, grad_color, grad_logp=None):
+def backward(scene, view, opts: Opts, vis, color, grad_color, grad_logp=None, out=None):
+    """Gradients of one view; with out = (gv, gf, gm) (contiguous float64
+    arrays of the gradient shapes) they are added into those arrays."""
     k = _Keep(scene, view, opts)
     T, G, Cc = scene.verts.shape[0], scene.feats.shape[1], scene.feats.shape[3]
-    gv = np.zeros(T * 9, np.float64)
-    gf = np.zeros(T * G * G * Cc, np.float64)
-    gm = np.zeros(n_params(scene.dims), np.float64)
+    if out is not None:
+        gv, gf, gm = (o.reshape(-1) for o in out)
+        assert gv.size == T * 9 and gf.size == T * G * G * Cc and gm.size == n_params(scene.dims)
+        assert all(o.dtype == np.float64 and o.flags.c_contiguous for o in out)
+    else:
+        gv = np.zeros(T * 9, np.float64)
+        gf = np.zeros(T * G * G * Cc, np.float64)
+        gm = np.zeros(n_params(scene.dims), np.float64)
     vis = np.ascontiguousarray(vis, dtype=np.uint64).ravel()
     color = np.ascontiguousarray(color, dtype=np.float32).ravel()
     gc = np.ascontiguousarray(grad_color, dtype=np.float32).ravel()

@@ -42,7 +42,7 @@ class soup_opts(C.Structure):
 
 class soup_stats(C.Structure):
     _fields_ = [("pixels", C.c_int64), ("tiles", C.c_int64), ("bin_entries", C.c_int64),
-                ("visible_tris", C.c_int64), ("decodes", C.c_int64)]
+                ("visible_tris", C.c_int64), ("decodes", C.c_int64), ("covered_pixels", C.c_int64)]
 
 
 EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_set_tile",

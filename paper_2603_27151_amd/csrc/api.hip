@@ -50,6 +50,8 @@ struct soup_ctx {
     DevBuf tri_count, tri_fill, tri_off, tri_bsum, mlp_mid, frags, sorted;
     DevBuf region_counts, region_boff, flags;
     DevBuf log_frag, log_aux, log_counts, log_boff;   // the forward's fragment log
+    DevBuf frag_gates, sorted_gates;                  // ReLU gates of the kept and sorted fragments
+    bool frags_gated = false;        // the current fragment list carries the forward's gates
     DevBuf ssim;                                      // SSIM statistics of the training loss
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
@@ -163,6 +165,15 @@ struct Timed {
 }  // namespace
 
 namespace soup {
+
+int gate_words(MlpKind k) {
+    switch (k) {
+        case MlpKind::k8_16_1: return 1;
+        case MlpKind::k16_32_2: return 2;
+        case MlpKind::k32_64_2: return 4;
+        default: return 0;
+    }
+}
 
 MlpKind mlp_kind(int n_layers, const int32_t* dims) {
     if (n_layers == 2 && dims[0] == 8 && dims[1] == 16 && dims[2] == 4) return MlpKind::k8_16_1;
@@ -311,7 +322,7 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
         (st = ensure(c, c->chunk_base, static_cast<size_t>(bin_chunks(p.maxT, chunk)) * p.n_tiles * 4)) ||
         (st = ensure(c, c->tile_start, static_cast<size_t>(p.n_tiles + 1) * 8)) ||
         (st = ensure(c, c->bsum, static_cast<size_t>((p.n_tiles + 1023) / 1024 + 1) * 8)) ||
-        (st = ensure(c, c->counters, 64)) || (st = ensure(c, c->flags, 256)) ||
+        (st = ensure(c, c->counters, 128)) || (st = ensure(c, c->flags, 256)) ||
         (st = ensure_host(c, vbytes + sbytes + 64)))
         return st;
     if (!c->flags_ready) {   // first allocation (never in static mode): clear the sticky flags
@@ -338,7 +349,7 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     {
         Timed t(c, SOUP_T_FILL, s);
-        launch_fill_i32(reinterpret_cast<int32_t*>(cnt), 16, 0, s);
+        launch_fill_i32(reinterpret_cast<int32_t*>(cnt), 32, 0, s);
         launch_fill_i32(static_cast<int32_t*>(c->tile_count.p), p.n_tiles, 0, s);
     }
     {
@@ -419,17 +430,19 @@ RasterArgs raster_args(soup_ctx* c, const Plan& p, const Opts& o) {
     return a;
 }
 
-soup_status finish_stats(soup_ctx* c, hipStream_t s) {
+soup_status finish_stats(soup_ctx* c, hipStream_t s, bool raster = true) {
     if (!c->counting || c->fixed) {
         c->stats.visible_tris = -1;
         c->stats.decodes = -1;
+        c->stats.covered_pixels = -1;
         return SOUP_OK;
     }
-    unsigned long long h[2];
-    HIP_TRY(c, hipMemcpyAsync(h, c->counters.p, 16, hipMemcpyDeviceToHost, s));
+    unsigned long long h[9];
+    HIP_TRY(c, hipMemcpyAsync(h, c->counters.p, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     c->stats.decodes = static_cast<int64_t>(h[0]);
     c->stats.visible_tris = static_cast<int64_t>(h[1]);
+    c->stats.covered_pixels = raster ? static_cast<int64_t>(h[8]) : -1;
     return SOUP_OK;
 }
 
@@ -495,7 +508,7 @@ void soup_ctx_destroy(soup_ctx* c) {
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
                       &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff, &c->ssim,
-                      &c->chunk_base};
+                      &c->chunk_base, &c->frag_gates, &c->sorted_gates};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -600,7 +613,10 @@ int decode_blocks(soup_ctx* c) { return std::max(1, std::min(c->num_cus * 4, kMa
 // *n_frag and of decode batches in *n_batch.
 soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64_t* vis, const float* grad_color,
                    const float* grad_logp, const float2* edge_w, bool all_front, int32_t* tri_count, int T,
-                   hipStream_t s, int64_t* n_frag, int64_t* n_batch, bool from_log = false) {
+                   hipStream_t s, int64_t* n_frag, int64_t* n_batch, bool from_log = false, bool want_gates = false) {
+    // the forward's ReLU gates travel with the fragments when they come from its log
+    want_gates = want_gates && from_log;
+    c->frags_gated = want_gates;
     if (p.n_pix >= (int64_t(1) << 32)) return fail(c, SOUP_ERR_CAPACITY, "backward needs fewer than 2^32 pixels per call");
     unsigned long long* cnt = static_cast<unsigned long long*>(c->counters.p);
     const int nb = from_log ? decode_blocks(c) : replay_blocks(c, p);
@@ -614,11 +630,14 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     if ((st = ensure(c, c->region_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
         (st = ensure(c, c->region_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
         return st;
+    const int gw = gate_words(p.kind);
     auto launch = [&](uint64_t reg) {
         if (from_log) {
             CollectArgs ca{};
             ca.log_frag = static_cast<uint4*>(c->log_frag.p);
             ca.log_aux = static_cast<uint2*>(c->log_aux.p);
+            ca.gate_words = gw;   // the log's record layout
+            if (want_gates) ca.frag_gates = static_cast<uint32_t*>(c->frag_gates.p);
             ca.log_region = static_cast<uint32_t>(c->log_region);
             ca.log_counts = static_cast<uint32_t*>(c->log_counts.p);
             ca.log_boff = static_cast<uint32_t*>(c->log_boff.p);
@@ -656,6 +675,9 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         if (c->frag_regions != nr || c->frag_region == 0)
             return fail(c, SOUP_ERR_CAPACITY, "static mode: no fragment list sized for this call; run it once "
                         "outside static mode");
+        if (want_gates && c->frag_gates.bytes < static_cast<size_t>(c->frag_region) * nr * gw * 4)
+            return fail(c, SOUP_ERR_CAPACITY, "static mode: no gate list sized for this call; run it once "
+                        "outside static mode");
         launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
         if (tri_count) launch_fill_i32(tri_count, T, 0, s);
         launch(c->frag_region);
@@ -668,6 +690,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment region too large");
         if ((st = ensure(c, c->frags, static_cast<size_t>(region) * nr * sizeof(FragRec)))) return st;
+        if (want_gates && (st = ensure(c, c->frag_gates, static_cast<size_t>(region) * nr * gw * 4))) return st;
         {
             Timed t(c, SOUP_T_FILL, s);
             launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
@@ -703,6 +726,7 @@ DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a) {
     d.mlp = p.scenes[0].mlp;
     d.G = p.G;
     d.T = p.scenes[0].T;
+    d.verts = p.scenes[0].verts;
     d.frags = static_cast<FragRec*>(c->frags.p);
     d.region = static_cast<uint32_t>(c->frag_region);
     d.counts = static_cast<uint32_t*>(c->region_counts.p);
@@ -748,7 +772,7 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
                                      : (static_cast<uint64_t>(p.n_pix) * 2) / log_nr + 1024;
             if (log_region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment log region too large");
             if ((st = ensure(c, c->log_frag, static_cast<size_t>(log_region) * log_nr * sizeof(uint4))) ||
-                (st = ensure(c, c->log_aux, static_cast<size_t>(log_region) * log_nr * sizeof(uint2))) ||
+                (st = ensure(c, c->log_aux, static_cast<size_t>(log_region) * log_nr * aux_words(gate_words(p.kind)) * 4)) ||
                 (st = ensure(c, c->log_counts, static_cast<size_t>(kMaxRegions) * 4)) ||
                 (st = ensure(c, c->log_boff, static_cast<size_t>(kMaxRegions + 1) * 4)))
                 return st;
@@ -825,7 +849,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     if (o.reuse_bins && c->bins_valid && c->bins_tile == c->tile && c->bins_near_w == o.near_w &&
         same_descriptors(c, p)) {
         // the last forward's setup records and tile lists are those of these inputs
-        launch_fill_i32(static_cast<int32_t*>(c->counters.p), 16, 0, s);
+        launch_fill_i32(static_cast<int32_t*>(c->counters.p), 32, 0, s);
         reused = true;
     } else if ((st = bin(c, p, o, s))) {
         return st;
@@ -841,7 +865,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         (st = ensure(c, c->partial, static_cast<size_t>(rows) * p.n_params * 4)) ||
         (st = ensure(c, c->mlp_mid, static_cast<size_t>(mlp_reduce_mid_rows(rows)) * p.n_params * 8)) ||
         (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
-        (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 4)) ||
+        (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 8)) ||
         (st = ensure(c, c->tri_off, static_cast<size_t>(T + 1) * 8)) ||
         (st = ensure(c, c->tri_bsum, static_cast<size_t>((T + 1023) / 1024 + 1) * 8)))
         return st;
@@ -855,16 +879,25 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     }
     int64_t n_frag = 0, n_batch = 0;
     if ((st = replay(c, p, a, vis, grad_color, gl, ew, false, static_cast<int32_t*>(c->tri_count.p), T, s, &n_frag,
-                     &n_batch, from_log)))
+                     &n_batch, from_log, true)))
         return st;
     // the list sorted by triangle has at most as many entries as the regions hold
     const int64_t frag_cap = static_cast<int64_t>(c->frag_regions) * static_cast<int64_t>(c->frag_region);
+    const int gw = gate_words(p.kind);
+    if (!c->frags_gated) {
+        // replayed fragments: their ReLU gates from a decode in the forward's arithmetic
+        if ((st = ensure(c, c->frag_gates, static_cast<size_t>(frag_cap) * gw * 4))) return st;
+        Timed t(c, SOUP_T_REPLAY, s);
+        launch_fragment_gates(decode_args(c, p, a), p.kind, static_cast<uint32_t*>(c->frag_gates.p), s);
+        c->frags_gated = true;
+    }
     if ((st = ensure(c, c->sorted, static_cast<size_t>(frag_cap) * sizeof(FragRec)))) return st;
+    if (c->frags_gated && (st = ensure(c, c->sorted_gates, static_cast<size_t>(frag_cap) * gw * 4))) return st;
     {
         Timed t(c, SOUP_T_GRAD, s);
         launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
                     static_cast<int64_t*>(c->tri_off.p), s);
-        launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), T, 0, s);
+        launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), 2 * T, 0, s);
         PlaceArgs pa{};
         pa.frags = static_cast<FragRec*>(c->frags.p);
         pa.region = static_cast<uint32_t>(c->frag_region);
@@ -872,8 +905,13 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
         pa.boff = static_cast<uint32_t*>(c->region_boff.p);
         pa.n_regions = c->frag_regions;
         pa.tri_off = static_cast<int64_t*>(c->tri_off.p);
-        pa.tri_fill = static_cast<int32_t*>(c->tri_fill.p);
+        pa.tri_fill = static_cast<unsigned long long*>(c->tri_fill.p);
         pa.sorted = static_cast<FragRec*>(c->sorted.p);
+        if (c->frags_gated) {
+            pa.frag_gates = static_cast<uint32_t*>(c->frag_gates.p);
+            pa.sorted_gates = static_cast<uint32_t*>(c->sorted_gates.p);
+            pa.gate_words = gw;
+        }
         pa.n_blocks = decode_blocks(c);
         launch_place(pa, s);
     }
@@ -887,6 +925,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     {
         DecodeArgs d = decode_args(c, p, a);
         d.sorted = static_cast<FragRec*>(c->sorted.p);
+        d.sorted_gates = c->frags_gated ? static_cast<uint32_t*>(c->sorted_gates.p) : nullptr;
         d.tri_off = static_cast<int64_t*>(c->tri_off.p);
         d.grad_color = grad_color;
         d.edge_w = ew;
@@ -904,7 +943,7 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
                           grad_mlp, o.accumulate != 0, s);
     }
     HIP_TRY(c, hipGetLastError());
-    return finish_stats(c, s);
+    return finish_stats(c, s, false);
 }
 
 soup_status soup_render(soup_ctx* c, const soup_scene* scenes, int32_t R, const soup_views* views,

@@ -270,6 +270,45 @@ __device__ __forceinline__ void mlp_forward(cfloat* __restrict__ p, const float 
     dense<S::H, 4, false>(p + S::w_off(S::NH), p + S::b_off(S::NH), a.h[S::NH - 1], a.o);
 }
 
+// Words of ReLU gate bits per decoded fragment: bit l * H + k is set when
+// hidden unit k of layer l is positive (the ReLU passes it).
+template <class S>
+struct GateWords {
+    static constexpr int kWords = (S::NH * S::H + 31) / 32;
+};
+
+// One dense hidden layer as `dense`, then gate bit (base + j) of `gates` set
+// for every positive unit j (read off the layer's output, which is positive
+// exactly where the ReLU passes).
+template <int DIN, int DOUT, int NW>
+__device__ __forceinline__ void dense_relu_gates(cfloat* __restrict__ W, cfloat* __restrict__ b,
+                                                 const float (&in)[DIN], float (&out)[DOUT], int base,
+                                                 uint32_t (&gates)[NW]) {
+    dense<DIN, DOUT, true>(W, b, in, out);
+    // out[j] is +0 or positive: its bit pattern is nonzero exactly when the gate is open
+#pragma unroll
+    for (int j = 0; j < DOUT; ++j)
+        gates[(base + j) >> 5] |= min(__float_as_uint(out[j]), 1u) << ((base + j) & 31);
+}
+
+// mlp_logits that also returns the hidden units' ReLU gates (same arithmetic).
+template <class S>
+__device__ __forceinline__ void mlp_logits_gates(cfloat* __restrict__ p, const float (&x)[S::C], float (&o)[4],
+                                                 uint32_t (&gates)[GateWords<S>::kWords]) {
+#pragma unroll
+    for (int w = 0; w < GateWords<S>::kWords; ++w) gates[w] = 0u;
+    float h[S::H];
+    dense_relu_gates<S::C, S::H>(p + S::w_off(0), p + S::b_off(0), x, h, 0, gates);
+#pragma unroll
+    for (int l = 1; l < S::NH; ++l) {
+        float h2[S::H];
+        dense_relu_gates<S::H, S::H>(p + S::w_off(l), p + S::b_off(l), h, h2, l * S::H, gates);
+#pragma unroll
+        for (int k = 0; k < S::H; ++k) h[k] = h2[k];
+    }
+    dense<S::H, 4, false>(p + S::w_off(S::NH), p + S::b_off(S::NH), h, o);
+}
+
 // Lightweight forward (no stored activations beyond one hidden layer).
 template <class S>
 __device__ __forceinline__ void mlp_logits(cfloat* __restrict__ p, const float (&x)[S::C],

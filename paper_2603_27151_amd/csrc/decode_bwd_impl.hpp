@@ -12,11 +12,14 @@
 //     runs on the matrix cores over the batch (activations and deltas staged
 //     through LDS); each wave writes its sums once, at the end, to its own row
 //     of a partial-sum buffer (rows are reduced later in a fixed order);
-//   - for the winner, the gradient of its triangle's world-space vertices,
-//     through the perspective-correct and screen barycentrics, the screen
-//     positions and 1/w, and the view-projection; the edge term of Section
-//     3.2 (the pixel's edge weights times its screen barycentrics) joins it
-//     in screen space;
+//   - for the winner, the gradient of its triangle's world-space vertices
+//     from its colour logits only (the score term moves no vertex, Section
+//     3.2): the feature gradient of the colour logits (a second data backward
+//     where the winner also carries a score weight) dotted with the texture's
+//     derivative along the cell position, then through the perspective-
+//     correct and screen barycentrics, the screen positions and 1/w, and the
+//     view-projection; the edge term of Section 3.2 (the pixel's edge weights
+//     times its screen barycentrics) joins it in screen space;
 //   - the feature gradient (bilinear weights of the four texels) and the
 //     vertex gradient are summed into the wave's LDS copy of the current
 //     triangle's G x G x C grid; when the triangle changes, the grid goes to
@@ -31,6 +34,9 @@
 namespace soup {
 
 constexpr int kStageRows = 16;   // fragments staged per transpose pass
+// floats after a wave's gradient grid: the current triangle's nine vertex
+// gradient sums, as doubles
+constexpr int kGridTail = 32;
 
 template <class S>
 struct StageCfg {
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     // shape's LDS is full)
     constexpr int DXS = S::C + (S::C >= 32 ? 0 : kRowPad);
     __shared__ __align__(16) float s_dx[LOGP ? 1 : NW][LOGP ? 4 : 64 * DXS];
-    extern __shared__ float s_dyn[];   // [NW][G*G*C + 16]: per-wave gradient grid of the current triangle
+    extern __shared__ __align__(16) float s_dyn[];   // [NW][G*G*C + kGridTail]: per-wave gradient grid of the current triangle
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int G = a.G;
@@ -171,7 +177,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     const uint64_t wid = static_cast<uint64_t>(blockIdx.x) * NW + w;
     uint64_t b_begin, b_end, b_step;
     int64_t E = 0, f0 = 0, f1 = 0;   // sorted list: fragments, this wave's range
-    float* grid = s_dyn + static_cast<size_t>(w) * (n_grid + 16);
+    float* grid = s_dyn + static_cast<size_t>(w) * (n_grid + kGridTail);
+    double* vgrid = reinterpret_cast<double*>(grid + n_grid);   // the nine vertex sums (n_grid is even)
     int cur = -1;                    // triangle held in grid (wave-uniform)
     if (LOGP) {
         for (int i = tid; i <= a.n_regions; i += blockDim.x) s_boff[i] = a.boff[i];
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
         b_step = 1;
         f0 = static_cast<int64_t>(b_begin) * 64;
         f1 = static_cast<int64_t>(b_end) * 64 < E ? static_cast<int64_t>(b_end) * 64 : E;
-        for (int k = lane; k < n_grid + 16; k += 64) grid[k] = 0.0f;
+        for (int k = lane; k < n_grid + kGridTail; k += 64) grid[k] = 0.0f;
     }
     // sorted list: the next batch's records, loaded one batch ahead, and the
     // per-pixel data of its winners (colour gradient, edge weights), loaded
@@ -197,6 +204,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     uint2 nx = make_uint2(0u, 0u);           // (score weight, view)
     float ng0 = 0.f, ng1 = 0.f, ng2 = 0.f, nex = 0.f, ney = 0.f;
     bool nvalid = false;
+    constexpr int GW = GateWords<S>::kWords;
+    const bool use_gates = !LOGP && a.sorted_gates != nullptr;   // the forward's ReLU gates, when logged
+    uint32_t ngate[GW];
+#pragma unroll
+    for (int k = 0; k < GW; ++k) ngate[k] = 0u;
     auto prefetch = [&](uint64_t bi) __attribute__((always_inline)) {
         const int64_t fi = static_cast<int64_t>(bi) * 64 + lane;
         nvalid = bi < b_end && fi < E;
@@ -204,6 +216,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             const FragRec fr = a.sorted[fi];
             na = make_uint4(fr.p0.x, fr.p0.y, fr.p1.x, fr.p1.y);
             nx = fr.x;
+            if (use_gates) {
+#pragma unroll
+                for (int k = 0; k < GW; ++k) ngate[k] = a.sorted_gates[fi * GW + k];
+            }
         }
     };
     auto pixfetch = [&]() __attribute__((always_inline)) {
@@ -236,8 +252,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             else if (v != 0.0f) atomicAdd(&gf[k], v);
         }
         if (lane < 9) {
-            const float v = grid[n_grid + lane];
-            grid[n_grid + lane] = 0.0f;
+            const float v = static_cast<float>(vgrid[lane]);
+            vgrid[lane] = 0.0;
             float* gv = a.grad_verts + static_cast<size_t>(t) * 9 + lane;
             if (owned) *gv = a.accumulate ? *gv + v : v;
             else if (v != 0.0f) atomicAdd(gv, v);
@@ -247,6 +263,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     for (uint64_t bi = b_begin; bi < b_end; bi += b_step) {
         bool on;
         uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb4 = make_uint4(0u, 0u, 0u, 0u), fc4 = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t gt[GW];   // this lane's fragment: the forward's ReLU gates
+#pragma unroll
+        for (int k = 0; k < GW; ++k) gt[k] = ngate[k];
         if (LOGP) {
             int lo = 0, hi = a.n_regions - 1;   // region: last w with boff[w] <= bi
             while (lo < hi) {
@@ -295,6 +314,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
         }
         float* st = s_stage[w];
         const uint32_t cellw = static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 16);
+        float my_dfx = 0.0f, my_dfy = 0.0f;   // this lane's fragment: d loss / d (fx, fy), colour logits
         {   // ---- the batch's MLP on the matrix cores, one 16-fragment block at a time ----
             constexpr int CB = MfmaWeights<S>::CB, HB = MfmaWeights<S>::HB;
             const int col = lane & 15, grp = lane >> 4;
@@ -305,12 +325,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             // fragment 16 nb + col.
             float4 qv[CB][4];
             float qw[4];
+            float qfx = 0.0f, qfy = 0.0f;   // the block fragment's position in its texture cell
             auto gather = [&](int nb) __attribute__((always_inline)) {
                 const int src = 16 * nb + col;
                 const bool on_n = __shfl(static_cast<int>(on), src, 64) != 0;
                 const uint32_t tri_n = static_cast<uint32_t>(__shfl(static_cast<int>(tri), src, 64));
                 const uint32_t cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), src, 64));
                 const float fx = __shfl(c.fx, src, 64), fy = __shfl(c.fy, src, 64);
+                qfx = fx;
+                qfy = fy;
                 qw[0] = (1.0f - fx) * (1.0f - fy);
                 qw[1] = fx * (1.0f - fy);
                 qw[2] = (1.0f - fx) * fy;
@@ -343,15 +366,55 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     xin[cb][2] = use ? qw[0] * q00.z + qw[1] * q10.z + qw[2] * q01.z + qw[3] * q11.z : 0.0f;
                     xin[cb][3] = use ? qw[0] * q00.w + qw[1] * q10.w + qw[2] * q01.w + qw[3] * q11.w : 0.0f;
                 }
+                // d feature / d fx and d feature / d fy at the fragment's texture
+                // position (bilinear), the directions in which a winner's vertices
+                // move its texture sample
+                f4v tgx[CB], tgy[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const bool use = on_n && 16 * cb + 4 * grp < S::C;
+                    const float4 q00 = qv[cb][0], q10 = qv[cb][1], q01 = qv[cb][2], q11 = qv[cb][3];
+                    const float ax = 1.0f - qfy, ay = 1.0f - qfx;
+                    tgx[cb][0] = use ? ax * (q10.x - q00.x) + qfy * (q11.x - q01.x) : 0.0f;
+                    tgx[cb][1] = use ? ax * (q10.y - q00.y) + qfy * (q11.y - q01.y) : 0.0f;
+                    tgx[cb][2] = use ? ax * (q10.z - q00.z) + qfy * (q11.z - q01.z) : 0.0f;
+                    tgx[cb][3] = use ? ax * (q10.w - q00.w) + qfy * (q11.w - q01.w) : 0.0f;
+                    tgy[cb][0] = use ? ay * (q01.x - q00.x) + qfx * (q11.x - q10.x) : 0.0f;
+                    tgy[cb][1] = use ? ay * (q01.y - q00.y) + qfx * (q11.y - q10.y) : 0.0f;
+                    tgy[cb][2] = use ? ay * (q01.z - q00.z) + qfx * (q11.z - q10.z) : 0.0f;
+                    tgy[cb][3] = use ? ay * (q01.w - q00.w) + qfx * (q11.w - q10.w) : 0.0f;
+                }
                 if (nb < 3) gather(nb + 1);
+                // the block fragment's gates of this lane's units 16 ob + 4 grp + i
+                uint32_t gate0[HB], gate1[HB];
+#pragma unroll
+                for (int ob = 0; ob < HB; ++ob) {
+                    gate0[ob] = 0u;
+                    gate1[ob] = 0u;
+                }
+                if (use_gates) {
+#pragma unroll
+                    for (int ob = 0; ob < HB; ++ob) {
+                        constexpr int kH = S::H;
+                        const int b0 = 16 * ob, b1 = kH + 16 * ob;   // first unit of the block, layers 0 and 1
+                        const uint32_t w0 = static_cast<uint32_t>(__shfl(static_cast<int>(gt[b0 >> 5]), src, 64));
+                        gate0[ob] = (w0 >> ((b0 & 31) + 4 * grp)) & 0xFu;
+                        if constexpr (S::NH == 2) {
+                            const uint32_t w1 = static_cast<uint32_t>(__shfl(static_cast<int>(gt[b1 >> 5]), src, 64));
+                            gate1[ob] = (w1 >> ((b1 & 31) + 4 * grp)) & 0xFu;
+                        }
+                    }
+                }
                 // forward
                 f4v h0[HB];
-                mfma_layer<HB, CB, true>(Wt.l0, Wt.b0, xin, h0, lane);
+                mfma_layer_gated<HB, CB>(Wt.l0, Wt.b0, xin, h0, lane, use_gates, gate0);
                 f4v h1[S::NH == 2 ? HB : 1];
-                if constexpr (S::NH == 2) mfma_layer<HB, HB, true>(Wt.l1, Wt.b1, h0, h1, lane);
+                if constexpr (S::NH == 2) mfma_layer_gated<HB, HB>(Wt.l1, Wt.b1, h0, h1, lane, use_gates, gate1);
                 const f4v (&hl)[HB] = *reinterpret_cast<const f4v (*)[HB]>(S::NH == 2 ? &h1[0] : &h0[0]);
                 // output layer and the logit gradients (Eq. (9) through the sigmoid for the score term)
                 float dO;   // lane group j: output j of the fragment
+                const bool win_n = on_n && __shfl(static_cast<int>(win), src, 64) != 0;
+                const float gl_n = __shfl(__uint_as_float(fb4.x), src, 64);
                 {
                     f4v o = {Wt.bo[lane], 0.f, 0.f, 0.f};
 #pragma unroll
@@ -360,8 +423,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
 #pragma unroll
                         for (int s4 = 0; s4 < 4; ++s4) o = mfma4(wv[s4], hl[ib][s4], o);
                     }
-                    const bool win_n = __shfl(static_cast<int>(win), src, 64) != 0;
-                    const float gl_n = __shfl(__uint_as_float(fb4.x), src, 64);
                     const float g0 = __shfl(__uint_as_float(fb4.y), src, 64), g1 = __shfl(__uint_as_float(fb4.z), src, 64),
                                 g2 = __shfl(__uint_as_float(fb4.w), src, 64);
                     const float sg = sigmoid_c(o[0]);
@@ -369,6 +430,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     if (grp == 3) d = win_n ? gl_n * (1.0f - sg) : -gl_n * sg;
                     else d = win_n ? (grp == 0 ? g0 : (grp == 1 ? g1 : g2)) * sg * (1.0f - sg) : 0.0f;
                     dO = on_n ? d : 0.0f;
+                }
+                // A winner's vertices move with the feature gradient of its colour
+                // logits only: the score logit reaches texture and MLP but no vertex
+                // (Section 3.2). Where a winner of the block carries a score weight,
+                // the colour logits get a data backward of their own; otherwise the
+                // full one below is the same thing.
+                const bool split = __ballot(win_n && gl_n != 0.0f) != 0;
+                const float dOc = grp == 3 ? 0.0f : dO;
+                float pfx = 0.0f, pfy = 0.0f;   // this lane's channels of d logits / d (fx, fy)
+                if (split) {
+                    f4v dlc[HB];
+#pragma unroll
+                    for (int ob = 0; ob < HB; ++ob) {
+                        f4v v = mfma4(Wt.loT[ob][lane], dOc, f4v{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) v[i] = hl[ob][i] > 0.0f ? v[i] : 0.0f;
+                        dlc[ob] = v;
+                    }
+                    f4v dh0c[HB];
+                    if constexpr (S::NH == 2) {
+                        mfma_back<HB, HB, true>(Wt.l1T, dlc, h0, dh0c, lane);
+                    } else {
+#pragma unroll
+                        for (int ob = 0; ob < HB; ++ob) dh0c[ob] = dlc[ob];
+                    }
+                    f4v dxc[CB];
+                    mfma_back<CB, HB, false>(Wt.l0T, dh0c, nullptr, dxc, lane);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            pfx = __builtin_fmaf(dxc[cb][i], tgx[cb][i], pfx);
+                            pfy = __builtin_fmaf(dxc[cb][i], tgy[cb][i], pfy);
+                        }
                 }
                 // output-layer weight gradient (rows = this block's fragments)
                 stage_rows<HB>(st, S::H, hl, lane);
@@ -420,43 +515,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                         *reinterpret_cast<float4*>(s_dx[w] + (16 * nb + col) * DXS + ch) =
                             make_float4(dxv[cb][0], dxv[cb][1], dxv[cb][2], dxv[cb][3]);
                 }
+                if (!split) {
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            pfx = __builtin_fmaf(dxv[cb][i], tgx[cb][i], pfx);
+                            pfy = __builtin_fmaf(dxv[cb][i], tgy[cb][i], pfy);
+                        }
+                }
+                // sum over the four lane groups' channels; lane 16 nb + col keeps
+                // the values of its own fragment
+                pfx += __shfl_xor(pfx, 16, 64);
+                pfy += __shfl_xor(pfy, 16, 64);
+                pfx += __shfl_xor(pfx, 32, 64);
+                pfy += __shfl_xor(pfy, 32, 64);
+                if (grp == nb) {
+                    my_dfx = pfx;
+                    my_dfy = pfy;
+                }
             }
             wave_fence();
         }
-        float dx[S::C];   // this lane's fragment
-#pragma unroll
-        for (int k = 0; k < S::C; k += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(s_dx[w] + lane * DXS + k);
-            dx[k] = v.x;
-            dx[k + 1] = v.y;
-            dx[k + 2] = v.z;
-            dx[k + 3] = v.w;
-        }
         pixfetch();   // the next batch's winners
-        // --- the winner's world-space vertex gradient ---
-        float gw[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // --- the winner's world-space vertex gradient, in double precision ---
+        // The chain is evaluated at the snapped vertex positions and the pixel
+        // centre from exact integers, with the clip coordinates recomputed in
+        // the setup's float32 order; its sums cancel, and float32 left errors
+        // of about 1e-4 of a vertex's total.
+        double gw[9] = {0., 0., 0., 0., 0., 0., 0., 0., 0.};
         if (win) {
             const ViewDesc& vd = a.views[fc4.z];
             const TriRec& tr = a.recs[vd.rec_base + tri];
             const int W = vd.W, H = vd.H;
             const int64_t local = static_cast<int64_t>(pix) - vd.pix_base;
             const int px = static_cast<int>(local % W), py = static_cast<int>(local / W);
-            const size_t t00 = ((static_cast<size_t>(tri) * G + c.iy) * G + c.ix) * S::C;
-            const size_t t10 = t00 + S::C, t01 = t00 + static_cast<size_t>(G) * S::C, t11 = t01 + S::C;
             // texture position -> barycentrics -> vertex screen positions and 1/w
-            // d f / d(gx, gy) from the four corners' dot products with the feature gradient
-            float s00 = 0.f, s10 = 0.f, s01 = 0.f, s11 = 0.f;
-#pragma unroll
-            for (int k = 0; k < S::C; ++k) {
-                s00 = __builtin_fmaf(dx[k], feats[t00 + k], s00);
-                s10 = __builtin_fmaf(dx[k], feats[t10 + k], s10);
-                s01 = __builtin_fmaf(dx[k], feats[t01 + k], s01);
-                s11 = __builtin_fmaf(dx[k], feats[t11 + k], s11);
-            }
-            const float dfx = (1.0f - c.fy) * (s10 - s00) + c.fy * (s11 - s01);
-            const float dfy = (1.0f - c.fx) * (s01 - s00) + c.fx * (s11 - s10);
-            const float gm1 = static_cast<float>(G - 1);
-            float iwv[3];
+            const double gm1 = static_cast<double>(G - 1);
+            double iwv[3];
             int32_t Xv[3], Yv[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -464,57 +560,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 Xv[i] = tr.X[i];
                 Yv[i] = tr.Y[i];
             }
-            // geometry in pixel units from exact integer differences
-            const int32_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
-            // the screen barycentrics of the contract, recomputed exactly:
-            // beta_i = (float)E_i * (1 / |2A|) with E_i the orientation-normalised
-            // integer edge function of edge i at the pixel centre
-            float fb[3];
+            const int64_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
+            // screen barycentrics beta_i = E_i / A: E_i the orientation-normalised
+            // integer edge function of edge i at the pixel centre, A their sum
+            double fb[3];
             {
                 const int64_t sgn = tr.rA < 0.0f ? -1 : 1;
-                const float ra = __builtin_fabsf(tr.rA);
+                int64_t Ei[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const int ea = i == 2 ? 0 : i + 1, eb = i == 0 ? 2 : (i == 1 ? 0 : 1);
                     const int64_t ex = static_cast<int64_t>(Xv[eb] - Xv[ea]), ey = static_cast<int64_t>(Yv[eb] - Yv[ea]);
-                    const int64_t E = sgn * (ex * (PY - Yv[ea]) - ey * (PX - Xv[ea]));
-                    fb[i] = static_cast<float>(E) * ra;
+                    Ei[i] = sgn * (ex * (PY - Yv[ea]) - ey * (PX - Xv[ea]));
                 }
+                const double inv_a = 1.0 / static_cast<double>(Ei[0] + Ei[1] + Ei[2]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) fb[i] = static_cast<double>(Ei[i]) * inv_a;
             }
-            const float tt[3] = {fb[0] * iwv[0], fb[1] * iwv[1], fb[2] * iwv[2]};
-            const float inv_s = 1.0f / ((tt[0] + tt[1]) + tt[2]);
-            const float bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
-            const float db[3] = {0.0f, dfx * gm1, dfy * gm1};
-            const float dot = db[1] * bb[1] + db[2] * bb[2];
-            float dbeta[3], diw[3];
+            const double tt[3] = {fb[0] * iwv[0], fb[1] * iwv[1], fb[2] * iwv[2]};
+            const double inv_s = 1.0 / ((tt[0] + tt[1]) + tt[2]);
+            const double bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
+            const double db[3] = {0.0, static_cast<double>(my_dfx) * gm1, static_cast<double>(my_dfy) * gm1};
+            const double dot = db[1] * bb[1] + db[2] * bb[2];
+            double dbeta[3], diw[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const float dt = (db[i] - dot) * inv_s;
+                const double dt = (db[i] - dot) * inv_s;
                 dbeta[i] = dt * iwv[i];
                 diw[i] = dt * fb[i];
             }
             const int64_t Ai = static_cast<int64_t>(Xv[1] - Xv[0]) * (Yv[2] - Yv[0]) -
                                static_cast<int64_t>(Yv[1] - Yv[0]) * (Xv[2] - Xv[0]);
-            const float inv_area = 65536.0f / static_cast<float>(Ai);
-            const float inv256 = 1.0f / 256.0f;
-            float gsx[3] = {0.f, 0.f, 0.f}, gsy[3] = {0.f, 0.f, 0.f};
+            const double inv_area = 65536.0 / static_cast<double>(Ai);   // 1 / (signed 2 x area in px^2)
+            const double inv256 = 1.0 / 256.0;
+            double gsx[3] = {0., 0., 0.}, gsy[3] = {0., 0., 0.};
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int p = i == 2 ? 0 : i + 1, qq = i == 0 ? 2 : (i == 1 ? 0 : 1);
                 // beta_i = e_i / area with e_i = edge(v_p, v_q, pixel centre)
-                const float bi = fb[i];
+                const double bi = fb[i];
 #pragma unroll
                 for (int jv = 0; jv < 3; ++jv) {
                     const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
-                    const float dax = static_cast<float>(Yv[jp] - Yv[jq]) * inv256;
-                    const float day = static_cast<float>(Xv[jq] - Xv[jp]) * inv256;
-                    float dex = 0.f, dey = 0.f;
+                    const double dax = static_cast<double>(Yv[jp] - Yv[jq]) * inv256;
+                    const double day = static_cast<double>(Xv[jq] - Xv[jp]) * inv256;
+                    double dex = 0., dey = 0.;
                     if (jv == p) {
-                        dex = static_cast<float>(Yv[qq] - PY) * inv256;
-                        dey = static_cast<float>(PX - Xv[qq]) * inv256;
+                        dex = static_cast<double>(Yv[qq] - PY) * inv256;
+                        dey = static_cast<double>(PX - Xv[qq]) * inv256;
                     } else if (jv == qq) {
-                        dex = static_cast<float>(PY - Yv[p]) * inv256;
-                        dey = static_cast<float>(Xv[p] - PX) * inv256;
+                        dex = static_cast<double>(PY - Yv[p]) * inv256;
+                        dey = static_cast<double>(Xv[p] - PX) * inv256;
                     }
                     gsx[jv] += dbeta[i] * (dex - bi * dax) * inv_area;
                     gsy[jv] += dbeta[i] * (dey - bi * day) * inv_area;
@@ -522,23 +618,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             }
             // edge term (Section 3.2): the boundaries this pixel occludes move
             // with its surface point, w beta_i e on the screen position of vertex i
-            const float ex = __uint_as_float(fc4.x), ey = __uint_as_float(fc4.y);
+            const double ex = __uint_as_float(fc4.x), ey = __uint_as_float(fc4.y);
 #pragma unroll
             for (int jv = 0; jv < 3; ++jv) {
-                gsx[jv] = __builtin_fmaf(ex, fb[jv], gsx[jv]);
-                gsy[jv] = __builtin_fmaf(ey, fb[jv], gsy[jv]);
+                gsx[jv] += ex * fb[jv];
+                gsy[jv] += ey * fb[jv];
             }
-            // screen position and 1/w -> clip -> world through the view-projection
-            const float hw = 0.5f * static_cast<float>(W), hh = 0.5f * static_cast<float>(H);
+            // screen position (s = W/2 (c_x / c_w) + W/2, H/2 - H/2 (c_y / c_w)) and 1/w
+            // -> clip -> world through the view-projection
+            const double hw = 0.5 * W, hh = 0.5 * H;
+            const float* vp = a.verts + static_cast<size_t>(tri) * 9;
 #pragma unroll
             for (int jv = 0; jv < 3; ++jv) {
-                const float iw = iwv[jv];
-                const float sx = static_cast<float>(Xv[jv]) * inv256, sy = static_cast<float>(Yv[jv]) * inv256;
-                const float gc0 = gsx[jv] * hw * iw;
-                const float gc1 = -gsy[jv] * hh * iw;
-                const float gc3 = (-gsx[jv] * (sx - hw) + gsy[jv] * (hh - sy)) * iw - diw[jv] * iw * iw;
+                const float x = vp[3 * jv], y = vp[3 * jv + 1], z = vp[3 * jv + 2];
+                float cc[4];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) gw[3 * jv + k] = vd.M[k] * gc0 + vd.M[4 + k] * gc1 + vd.M[12 + k] * gc3;
+                for (int j = 0; j < 4; ++j) {   // the setup's transform (row z unused)
+                    float acc = vd.M[j * 4 + 3];
+                    acc = __builtin_fmaf(vd.M[j * 4 + 0], x, acc);
+                    acc = __builtin_fmaf(vd.M[j * 4 + 1], y, acc);
+                    acc = __builtin_fmaf(vd.M[j * 4 + 2], z, acc);
+                    cc[j] = acc;
+                }
+                const double cx = cc[0], cy = cc[1], iw = 1.0 / static_cast<double>(cc[3]);
+                const double gc0 = gsx[jv] * hw * iw;
+                const double gc1 = -gsy[jv] * hh * iw;
+                const double gc3 = (-gsx[jv] * hw * cx + gsy[jv] * hh * cy - diw[jv]) * (iw * iw);
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    gw[3 * jv + k] = static_cast<double>(vd.M[k]) * gc0 + static_cast<double>(vd.M[4 + k]) * gc1 +
+                                     static_cast<double>(vd.M[12 + k]) * gc3;
             }
         }
         // --- sum into the wave's grid, one run of equal triangles at a time ---
@@ -576,16 +685,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             const int end = heads ? __builtin_ctzll(heads) : 64;
             const bool in_run = lane >= h && lane < end;
             if (__ballot(in_run && win)) {   // the run's winners: vertex gradient summed over the wave
-                float v[9];
+                double v[9];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) v[k] = in_run ? gw[k] : 0.0f;   // gw is zero for fragments in front
+                for (int k = 0; k < 9; ++k) v[k] = in_run ? gw[k] : 0.0;   // gw is zero for fragments in front
 #pragma unroll
                 for (int d = 32; d > 0; d >>= 1)   // the nine sums advance together
 #pragma unroll
                     for (int k = 0; k < 9; ++k) v[k] += __shfl_xor(v[k], d, 64);
                 if (lane == 0) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) grid[n_grid + k] += v[k];
+                    for (int k = 0; k < 9; ++k) vgrid[k] += v[k];
                 }
             }
             constexpr int UF = 4;                          // steps in flight: their staged reads go first
@@ -671,6 +780,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     }
 }
 
+// The forward's ReLU gates of every fragment of a replayed list (a backward
+// without the forward's log): each lane decodes its fragment with the
+// forward's float32 arithmetic (the contract's texture fetch and MLP, from the
+// same barycentrics) and keeps the gates in gates_out, at the fragment's slot
+// of the region list. Waves take batches as the logp decode does.
+template <class S>
+__global__ __launch_bounds__(256) void fragment_gates_kernel(DecodeArgs a, uint32_t* __restrict__ gates_out) {
+    constexpr int NW = 4, GW = GateWords<S>::kWords;
+    __shared__ uint32_t s_boff[kMaxRegions + 1];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i <= a.n_regions; i += blockDim.x) s_boff[i] = a.boff[i];
+    __syncthreads();
+    gfloat* __restrict__ feats = as_global(uniform_ptr(a.feats));
+    const uint32_t n_batch = s_boff[a.n_regions];
+    const uint32_t n_waves = gridDim.x * NW;
+    for (uint32_t bi = blockIdx.x * NW + w; bi < n_batch; bi += n_waves) {
+        int lo = 0, hi = a.n_regions - 1;   // region: last w with boff[w] <= bi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_boff[mid] <= bi) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t cr = a.counts[lo];
+        const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
+        if (in_region >= (cr < a.region ? cr : a.region)) continue;
+        const uint64_t at = static_cast<uint64_t>(lo) * a.region + in_region;
+        const FragRec fr = a.frags[at];
+        const Cell c = cell_of(__uint_as_float(fr.p1.x), __uint_as_float(fr.p1.y), a.G);
+        float x[S::C];
+        fetch_feature<S::C>(feats, fr.p0.y & 0x7FFFFFFFu, a.G, c, x);
+        float o[4];
+        uint32_t g[GW];
+        mlp_logits_gates<S>(as_const(opaque_ptr(a.mlp)), x, o, g);
+#pragma unroll
+        for (int k = 0; k < GW; ++k) gates_out[at * GW + k] = g[k];
+    }
+}
+
+template <class S>
+static void launch_fragment_gates_s(const DecodeArgs& a, uint32_t* gates_out, hipStream_t s) {
+    hipLaunchKernelGGL(fragment_gates_kernel<S>, dim3(a.n_blocks), dim3(256), 0, s, a, gates_out);
+}
+
 // Bytes of LDS one workgroup of the decode needs (static + dynamic), or 0 when
 // the runtime cannot say.
 template <class S>
@@ -682,7 +834,7 @@ static size_t decode_bwd_lds_s(int G, bool logp) {
         (void)hipGetLastError();
         return 0;
     }
-    const size_t dyn = logp ? 0 : static_cast<size_t>(4) * (static_cast<size_t>(G) * G * S::C + 16) * sizeof(float);
+    const size_t dyn = logp ? 0 : static_cast<size_t>(4) * (static_cast<size_t>(G) * G * S::C + kGridTail) * sizeof(float);
     return fa.sharedSizeBytes + dyn;
 }
 
@@ -691,7 +843,7 @@ static void launch_decode_bwd_s(const DecodeArgs& a, bool logp, hipStream_t s) {
     if (logp) {
         hipLaunchKernelGGL((decode_bwd_kernel<S, true>), dim3(a.n_blocks), dim3(256), 0, s, a);
     } else {
-        const size_t lds = static_cast<size_t>(4) * (static_cast<size_t>(a.G) * a.G * S::C + 16) * sizeof(float);
+        const size_t lds = static_cast<size_t>(4) * (static_cast<size_t>(a.G) * a.G * S::C + kGridTail) * sizeof(float);
         hipLaunchKernelGGL((decode_bwd_kernel<S, false>), dim3(a.n_blocks), dim3(256), lds, s, a);
     }
 }

@@ -138,6 +138,34 @@ __device__ __forceinline__ void mfma_layer(const f4v (*w)[IB][64], const f4v (*b
     }
 }
 
+// mfma_layer with the ReLU gate of unit 16 ob + 4 grp + i taken from bit i of
+// gate[ob] when use_gates (the forward's decision, logged by its bit-exact
+// decode), else from the sign of the recomputed value. The recompute sums in
+// the matrix cores' order, so a pre-activation within rounding of zero may
+// land on the other side of the kink than in the forward; the logged gate
+// keeps the forward's side. An open gate keeps at least FLT_MIN, so that the
+// "> 0" tests of the backward see it.
+template <int OB, int IB>
+__device__ __forceinline__ void mfma_layer_gated(const f4v (*w)[IB][64], const f4v (*bias)[64], const f4v (&in)[IB],
+                                                 f4v (&out)[OB], int lane, bool use_gates, const uint32_t (&gate)[OB]) {
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+        f4v acc = bias[ob][lane];
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) {
+            const f4v wv = w[ob][ib][lane];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = mfma4(wv[s], in[ib][s], acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool open = use_gates ? ((gate[ob] >> i) & 1u) != 0u : acc[i] > 0.0f;
+            acc[i] = open ? __builtin_fmaxf(acc[i], 0x1p-126f) : 0.0f;
+        }
+        out[ob] = acc;
+    }
+}
+
 // One 16-fragment block: d_in[ob] = (W^T d_out), masked by act > 0 when MASK.
 template <int OB, int IB, bool MASK>
 __device__ __forceinline__ void mfma_back(const f4v (*wT)[IB][64], const f4v (&d_out)[IB], const f4v* mask,

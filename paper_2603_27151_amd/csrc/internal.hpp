@@ -49,17 +49,23 @@ struct RasterArgs {
     int64_t n_tiles;
     uint64_t* vis;                 // concatenated outputs (may be null when views carry their own)
     float* color;
-    unsigned long long* counter;   // decode counter or null
+    unsigned long long* counter;   // counters or null: [0] decodes, [8] pixels that some fragment covers
     unsigned int* work;            // persistent-kernel tile counter (zeroed by the launcher's caller)
     int n_blocks;                  // persistent grid of the forward (single-wave workgroups)
     int region;                    // side of a forward wave's region: 16 (tiles of 16, 32) or 8
     // optional log of the forward's decoded fragments, one region per wave (= workgroup):
-    // log_frag = (pixel, triangle, b1, b2), log_aux = (depth bits, view)
+    // log_frag = (pixel, triangle, b1, b2); log_aux = aux_words(gate_words) words per
+    // fragment: depth bits, view, then the decode's ReLU gates (zero-padded to an even count)
     uint4* log_frag;
     uint2* log_aux;
     uint32_t log_region;
     uint32_t* log_counts;
 };
+
+// Words of ReLU gate bits a decode of this MLP shape logs (one bit per hidden unit).
+int gate_words(MlpKind k);
+// Words of one log_aux record: depth bits, view and the gates, rounded up to an even count.
+__host__ __device__ constexpr int aux_words(int gate_words) { return (2 + gate_words + 1) & ~1; }
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 // Resident single-wave workgroups per CU of the forward kernel for a tile side, MLP shape and
@@ -107,7 +113,9 @@ void launch_replay(const ReplayArgs& a, int tile, hipStream_t s);
 // by the forward, since the forward's best key never drops below the winner's.
 struct CollectArgs {
     const uint4* log_frag;
-    const uint2* log_aux;
+    const uint2* log_aux;          // aux_words(gate_words) words per logged fragment
+    uint32_t* frag_gates;          // the log's ReLU gates of every kept fragment (same slots as frags), or null
+    int gate_words;
     uint32_t log_region;
     const uint32_t* log_counts;    // [log_regions]
     const uint32_t* log_boff;      // [log_regions + 1] batch offsets of the log
@@ -132,8 +140,11 @@ int replay_waves_per_block(int tile);
 void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t* boff,
                         unsigned long long* summary, unsigned int* sticky, hipStream_t s);
 
-// Counting-sort placement of the fragment list by triangle:
-// sorted[tri_off[t] + k] for the k-th fragment of triangle t.
+// Counting-sort placement of the fragment list by triangle. Within triangle
+// t's range [tri_off[t], tri_off[t + 1]) its winners come first (filled
+// upwards from the start) and the fragments in front of winners last (filled
+// downwards from the end), so that most 64-fragment batches of the decode
+// hold winners only or none.
 struct PlaceArgs {
     const FragRec* frags;
     uint32_t region;
@@ -141,8 +152,11 @@ struct PlaceArgs {
     const uint32_t* boff;          // [n_regions + 1]
     int n_regions;
     const int64_t* tri_off;        // [T + 1] exclusive scan of the per-triangle counts
-    int32_t* tri_fill;             // [T] zeroed
+    unsigned long long* tri_fill;  // [T] zeroed: winners placed (low 32 bits), others (high 32 bits)
     FragRec* sorted;               // [tri_off[T]]
+    const uint32_t* frag_gates;    // ReLU gates of frags (gate_words each), or null
+    uint32_t* sorted_gates;        // ... placed as sorted
+    int gate_words;
     int n_blocks;
 };
 
@@ -164,7 +178,9 @@ struct DecodeArgs {
     int n_regions;
     // backward: the list sorted by triangle
     const FragRec* sorted;         // [tri_off[T]]
+    const uint32_t* sorted_gates;  // the forward's ReLU gates of each sorted fragment, or null (recomputed)
     const int64_t* tri_off;        // [T + 1]
+    const float* verts;            // [T, 3, 3]: the winners' clip coordinates are recomputed
     const float* grad_color;       // [P, 3]: the winners' colour gradients
     const float2* edge_w;          // [P] the winners' edge weights, or null (none)
     float* grad_feats;             // [T, G, G, C]: zeroed by the caller unless accumulate
@@ -177,6 +193,9 @@ struct DecodeArgs {
 };
 
 void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp_pass, hipStream_t s);
+// The forward's ReLU gates of a replayed fragment list (a.frags, a.region, a.counts,
+// a.boff, a.n_regions), gate_words(k) words per slot into gates_out.
+void launch_fragment_gates(const DecodeArgs& a, MlpKind k, uint32_t* gates_out, hipStream_t s);
 // LDS bytes one workgroup of the decode needs for a grid side G (0: unknown).
 size_t decode_bwd_lds(MlpKind k, int G, bool logp_pass);
 // ew[p] = (x, y) edge weights of the pairs pixel p occludes (Section 3.2),

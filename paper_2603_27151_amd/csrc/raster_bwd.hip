@@ -23,6 +23,20 @@ size_t decode_bwd_lds(MlpKind k, int G, bool logp) {
     }
 }
 
+void launch_fragment_gates_k8_16_1(const DecodeArgs& a, uint32_t* gates_out, hipStream_t s);
+void launch_fragment_gates_k16_32_2(const DecodeArgs& a, uint32_t* gates_out, hipStream_t s);
+void launch_fragment_gates_k32_64_2(const DecodeArgs& a, uint32_t* gates_out, hipStream_t s);
+
+void launch_fragment_gates(const DecodeArgs& a, MlpKind k, uint32_t* gates_out, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
+    switch (k) {
+        case MlpKind::k8_16_1: launch_fragment_gates_k8_16_1(a, gates_out, s); break;
+        case MlpKind::k16_32_2: launch_fragment_gates_k16_32_2(a, gates_out, s); break;
+        case MlpKind::k32_64_2: launch_fragment_gates_k32_64_2(a, gates_out, s); break;
+        default: break;
+    }
+}
+
 void launch_decode_bwd(const DecodeArgs& a, MlpKind k, bool logp, hipStream_t s) {
     if (a.n_blocks <= 0) return;
     switch (k) {

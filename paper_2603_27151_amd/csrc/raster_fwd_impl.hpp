@@ -60,6 +60,8 @@ struct FwdWaveLds {
     uint64_t key[64 * NB];
     // per round of the fragment step: the slice pair whose run of combinations starts here
     int32_t head[64];
+    // counting only: the region's pixels that some fragment covers, per block (bits 0..31, 32..63)
+    uint32_t cov[2 * NB];
 };
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
@@ -161,6 +163,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         wmaxb[b] = wave_max_u64(k0);
         wmax = wmaxb[b] > wmax ? wmaxb[b] : wmax;
     }
+    if (a.counter && lane < 2 * NB) L.cov[lane] = 0u;
 
     // decode a batch of n queued candidates, one per lane
     auto run_batch = [&](int n) __attribute__((always_inline)) {
@@ -170,6 +173,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         int pl = 0;
         bool pass = false;
         float o[4] = {0.f, 0.f, 0.f, 0.f};
+        uint32_t gates[GateWords<S>::kWords];
+#pragma unroll
+        for (int w = 0; w < GateWords<S>::kWords; ++w) gates[w] = 0u;
         if (act) {
             key = L.qkey[lane];
             pl = static_cast<int>(L.qpl[lane]);
@@ -181,7 +187,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             fetch_feature<S::C>(feats, tri, G, c, x);
             // an opaque copy of the weight pointer per batch: the compiler may
             // not hoist the weights' scalar loads out of the traversal loops
-            mlp_logits<S>(as_const(opaque_ptr(mlp_p)), x, o);
+            // (the ReLU gates are kept for the log; forming them costs two
+            // instructions per hidden unit)
+            mlp_logits_gates<S>(as_const(opaque_ptr(mlp_p)), x, o, gates);
             const int blk = pl >> 6, p = pl & 63;
             const int gx = rx + (blk % BR) * 8 + (p & 7), gy = ry + (blk / BR) * 8 + (p >> 3);
             if (a.o.mode == 0) {
@@ -198,7 +206,11 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     const int64_t pg = pix_base + static_cast<int64_t>(gy) * W + gx;
                     a.log_frag[log_base + at] =
                         make_uint4(static_cast<uint32_t>(pg), tri, __float_as_uint(b1), __float_as_uint(b2));
-                    a.log_aux[log_base + at] = make_uint2(static_cast<uint32_t>(key >> 32), static_cast<uint32_t>(v));
+                    constexpr int GW = GateWords<S>::kWords, AW2 = aux_words(GW) / 2;
+                    uint2* ax = a.log_aux + (log_base + at) * AW2;
+                    ax[0] = make_uint2(static_cast<uint32_t>(key >> 32), static_cast<uint32_t>(v));
+#pragma unroll
+                    for (int w = 0; w < GW; w += 2) ax[1 + w / 2] = make_uint2(gates[w], w + 1 < GW ? gates[w + 1] : 0u);
                 }
             }
         }
@@ -400,6 +412,13 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     if (pv2 < 4) mlo |= row << (8 * pv2);
                     else mhi |= row << (8 * (pv2 - 4));
                 }
+                // A pixel left out of the mask already has a passing fragment; every
+                // fragment of a pixel without one is in some mask, since the walk
+                // then reaches the end of the list.
+                if (a.counter && (mlo | mhi) != 0) {
+                    atomicOr(&L.cov[2 * cblk], mlo);
+                    atomicOr(&L.cov[2 * cblk + 1], mhi);
+                }
                 if ((mlo | mhi) != 0) {
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
@@ -472,6 +491,15 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         oin[b] = gx < W && gy < H;
         ooff[b] = static_cast<int64_t>(gy) * W + gx;
         okey[b] = L.key[b * 64 + lane];
+    }
+    if (a.counter) {   // covered = a passing fragment, or a fragment in some coverage mask
+        int n_cov = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint64_t won = __ballot(oin[b] && okey[b] != kBgKey);
+            n_cov += __popcll(won | (static_cast<uint64_t>(L.cov[2 * b + 1]) << 32) | L.cov[2 * b]);
+        }
+        if (lane == 0 && n_cov) atomicAdd(a.counter + 8, static_cast<unsigned long long>(n_cov));
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {

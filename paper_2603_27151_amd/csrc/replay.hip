@@ -271,8 +271,10 @@ void launch_region_scan(const uint32_t* counts, int n, uint32_t region, uint32_t
 }
 
 // Persistent waves take batches of the region list (as the logp decode
-// does); each fragment goes to sorted[tri_off[t] + k], k from a
-// per-triangle fill counter taken once per run of equal triangles.
+// does). Triangle t's winners go to sorted[tri_off[t] + k] and its other
+// fragments to sorted[tri_off[t + 1] - 1 - k], k from a per-triangle pair of
+// fill counters (one 64-bit atomic per run of equal triangles among
+// consecutive lanes).
 __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
     __shared__ uint32_t s_boff[kMaxRegions + 1];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -293,20 +295,36 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
         FragRec fr = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
         if (on) fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
         const uint32_t tri = on ? (fr.p0.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+        const bool win = on && (fr.p0.y >> 31);
         const uint32_t tprev = __shfl_up(tri, 1, 64);
         const bool head = lane == 0 || tprev != tri;
         const uint64_t heads = __ballot(head);
-        int base = 0;
-        if (head && on) {
-            const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-            const int endl = above ? __builtin_ctzll(above) : 64;
-            base = atomicAdd(&a.tri_fill[tri], endl - lane);
-        }
+        const uint64_t wins = __ballot(win);
         const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
-        const int hl = 63 - __builtin_clzll(upto);   // lane 0 is always a head
-        const int hb = __shfl(base, hl, 64);
+        const int hl = 63 - __builtin_clzll(upto);   // lane 0 is always a head: this lane's run starts at hl
+        const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+        const int endl = above ? __builtin_ctzll(above) : 64;
+        // the run [hl, end): winners before this lane, winners in the whole run
+        const uint64_t run_lo = (hl == 0 ? ~0ull : (~0ull << hl));
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const int w_before = __popcll(wins & run_lo & below);
+        unsigned long long base = 0;
+        if (head && on) {
+            const uint64_t run = run_lo & (endl == 64 ? ~0ull : ((1ull << endl) - 1));
+            const unsigned long long nw = static_cast<unsigned long long>(__popcll(wins & run));
+            const unsigned long long nf = static_cast<unsigned long long>(endl - lane) - nw;
+            base = atomicAdd(&a.tri_fill[tri], nw | (nf << 32));
+        }
+        const unsigned long long hb = __shfl(base, hl, 64);
         if (on) {
-            a.sorted[a.tri_off[tri] + hb + (lane - hl)] = fr;
+            const int64_t dst = win ? a.tri_off[tri] + static_cast<int64_t>(hb & 0xFFFFFFFFull) + w_before
+                                    : a.tri_off[tri + 1] - 1 - static_cast<int64_t>(hb >> 32) - ((lane - hl) - w_before);
+            a.sorted[dst] = fr;
+            if (a.frag_gates) {
+                const uint64_t src = static_cast<uint64_t>(lo) * a.region + in_region;
+                for (int w = 0; w < a.gate_words; ++w)
+                    a.sorted_gates[static_cast<uint64_t>(dst) * a.gate_words + w] = a.frag_gates[src * a.gate_words + w];
+            }
         }
     }
 }
@@ -347,7 +365,8 @@ __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
         if (on) {
             const uint64_t at = static_cast<uint64_t>(lo) * a.log_region + in_region;
             const uint4 e = a.log_frag[at];
-            const uint2 x = a.log_aux[at];
+            const int aw2 = aux_words(a.gate_words) / 2;
+            const uint2 x = a.log_aux[at * aw2];
             const uint64_t key = (static_cast<uint64_t>(x.x) << 32) | e.y;
             const uint64_t kstar = a.vis[e.x];
             win = key == kstar;
@@ -363,7 +382,14 @@ __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
         }
         const uint64_t km = __ballot(keep);
         const uint32_t pos = cursor + static_cast<uint32_t>(__popcll(km & lanemask_lt()));
-        if (keep && pos < a.region) a.frags[out_base + pos] = fr;
+        if (keep && pos < a.region) {
+            a.frags[out_base + pos] = fr;
+            if (a.frag_gates) {
+                const uint64_t at = static_cast<uint64_t>(lo) * a.log_region + in_region;
+                const uint32_t* g = reinterpret_cast<const uint32_t*>(a.log_aux + at * (aux_words(a.gate_words) / 2)) + 2;
+                for (int w = 0; w < a.gate_words; ++w) a.frag_gates[(out_base + pos) * a.gate_words + w] = g[w];
+            }
+        }
         // fragments per triangle, counting only those stored (one atomic per
         // run of equal triangles among consecutive lanes)
         if (a.tri_count) {

@@ -59,7 +59,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(_lib.soup_opts) == 48
     assert _lib.soup_opts.accumulate.offset == 36
     assert _lib.soup_opts.reuse_bins.offset == 40
-    assert ctypes.sizeof(_lib.soup_stats) == 5 * 8
+    assert ctypes.sizeof(_lib.soup_stats) == 6 * 8
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
