@@ -313,6 +313,24 @@ soup_status soup_loss_l1_ssim(soup_ctx* ctx, const float* color, const float* ta
                               float lambda, float* grad_color, float* grad_logp, float* loss, void* stream);
 
 /*
+ * soup_loss_l1_ssim for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc): the same arguments, kernels and results, with the
+ * statistics record in a static device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends, instead of a
+ * context workspace. The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine; no timing events). A view of more than
+ * 1,398,101 pixels (64 MiB / 48 B) is rejected with SOUP_ERR_CAPACITY.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other contexts, other threads) race and must be
+ * ordered by the caller. Nothing in the array needs to start at zero: each
+ * pixel's record is written before it is read within the same call.
+ */
+soup_status soup_loss_l1_ssim_noalloc(soup_ctx* ctx, const float* color, const float* target,
+                                      const soup_views* views, float lambda, float* grad_color, float* grad_logp,
+                                      float* loss, void* stream);
+
+/*
  * One optimiser step (Section 3.4; Supplement, hyperparameters): Adam for
  * vec = 1, VectorAdam for vec = 3 (vertex positions: one second moment per
  * 3-vector, from its squared norm). For each vector i of n / vec:

@@ -50,7 +50,7 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
            "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings", "soup_ctx_set_static",
            "soup_ctx_check", "soup_coverage_count", "soup_edge_lengths", "soup_adaptive_plan",
-           "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step"]
+           "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step", "soup_loss_l1_ssim_noalloc"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
                 "adaptive_apply", "train_loss", "adam"]
@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(C.c_int32)]
     L.soup_adaptive_apply.argtypes = [P, C.POINTER(soup_scene), P, P, C.c_int32, P, P, P]
     L.soup_loss_l1_ssim.argtypes = [P, P, P, C.POINTER(soup_views), C.c_float, P, P, P, P]
+    L.soup_loss_l1_ssim_noalloc.argtypes = [P, P, P, C.POINTER(soup_views), C.c_float, P, P, P, P]
     L.soup_adam_step.argtypes = [P, P, P, P, P, C.c_int64, C.c_int32, C.c_float, C.c_double, C.c_double, C.c_float,
                                  C.c_int32, P]
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
@@ -104,7 +105,7 @@ def lib() -> C.CDLL:
                  "soup_selftest_sigmoid", "soup_selftest_uniform", "soup_ctx_set_timing",
                  "soup_read_timings", "soup_ctx_set_static", "soup_ctx_check", "soup_coverage_count",
                  "soup_edge_lengths", "soup_adaptive_plan", "soup_adaptive_apply", "soup_loss_l1_ssim",
-                 "soup_adam_step"]:
+                 "soup_adam_step", "soup_loss_l1_ssim_noalloc"]:
         getattr(L, name).restype = C.c_int
     L.soup_ctx_get_tile.restype = C.c_int32
     _lib = L
@@ -311,6 +312,12 @@ def soup_loss_l1_ssim(ctx: Ctx, color, target, views: soup_views, lam: float, gr
                       stream=None):
     ctx.check(lib().soup_loss_l1_ssim(ctx.p, _ptr(color), _ptr(target), C.byref(views), float(lam),
                                       _ptr(grad_color), _ptr(grad_logp), _ptr(loss), _stream(stream)))
+
+
+def soup_loss_l1_ssim_noalloc(ctx: Ctx, color, target, views: soup_views, lam: float, grad_color, grad_logp,
+                              loss=None, stream=None):
+    ctx.check(lib().soup_loss_l1_ssim_noalloc(ctx.p, _ptr(color), _ptr(target), C.byref(views), float(lam),
+                                              _ptr(grad_color), _ptr(grad_logp), _ptr(loss), _stream(stream)))
 
 
 def soup_adam_step(ctx: Ctx, p, g, m, v, vec: int, lr: float, beta1: float, beta2: float, eps: float, t: int,

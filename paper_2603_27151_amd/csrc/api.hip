@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,7 @@ struct soup_ctx {
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
     void* host_stage = nullptr;      // pinned: descriptors up, totals down
+    float* scratch = nullptr;        // this device's address of the allocation-free loss's static scratch
     size_t host_stage_bytes = 0;
     // optional per-kernel timing: recorded event pairs and a pool of free events
     bool timing = false;
@@ -474,6 +476,42 @@ soup_status plan_single(soup_ctx* c, Plan& p, const soup_scene* scene, const sou
 
 }  // namespace
 
+namespace {
+
+// Scratch of soup_loss_l1_ssim_noalloc: the SSIM statistics record (12
+// floats per pixel) of one view at a time. Every GPU the library runs on
+// holds its own copy of this array until the process ends. Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): it uses the address hipGetSymbolAddress gives on each
+// device, kept in noalloc_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+std::mutex noalloc_scratch_mu;
+float* noalloc_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Once per device, with that device current: the device address of scratch.
+soup_status noalloc_scratch_setup(soup_ctx* c) {
+    std::lock_guard<std::mutex> lock(noalloc_scratch_mu);
+    if (c->device >= kNoAllocMaxDevices)
+        return fail(c, SOUP_ERR_UNSUPPORTED, "device %d: the allocation-free entry point supports devices 0..%d",
+                    c->device, kNoAllocMaxDevices - 1);
+    if (!noalloc_scratch_ptr[c->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(c, SOUP_ERR_HIP, "hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+        }
+        noalloc_scratch_ptr[c->device] = static_cast<float*>(p);
+    }
+    c->scratch = noalloc_scratch_ptr[c->device];
+    return SOUP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 soup_status soup_ctx_create(soup_ctx** out, int device) {
@@ -495,6 +533,13 @@ soup_status soup_ctx_create(soup_ctx** out, int device) {
         c->lds_limit = static_cast<size_t>(lds);
     else
         (void)hipGetLastError();
+    // error messages are formatted into a 512-byte buffer: with this capacity in
+    // place, reporting one allocates no memory
+    c->err.reserve(512);
+    if (noalloc_scratch_setup(c) != SOUP_OK) {
+        delete c;
+        return SOUP_ERR_HIP;
+    }
     *out = c;
     return SOUP_OK;
 }
@@ -1093,10 +1138,12 @@ soup_status soup_adaptive_apply(soup_ctx* c, const soup_scene* sc, const int32_t
     return SOUP_OK;
 }
 
-soup_status soup_loss_l1_ssim(soup_ctx* c, const float* color, const float* target, const soup_views* v,
-                              float lambda, float* grad_color, float* grad_logp, float* loss, void* stream) {
-    if (!c) return SOUP_ERR_INVALID;
-    c->err.clear();
+namespace {
+
+// Arguments of the L1 + D-SSIM loss: the total and the largest view's pixels.
+soup_status check_loss_l1_ssim(soup_ctx* c, const float* color, const float* target, const soup_views* v,
+                               float lambda, const float* grad_color, const float* grad_logp, int64_t* P_out,
+                               int64_t* maxp_out) {
     if (!v || v->V < 1 || !v->width || !v->height) return fail(c, SOUP_ERR_INVALID, "loss_l1_ssim: views missing");
     if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(c, SOUP_ERR_INVALID, "loss_l1_ssim: lambda outside [0, 1]");
     int64_t P = 0, maxp = 0;
@@ -1109,9 +1156,17 @@ soup_status soup_loss_l1_ssim(soup_ctx* c, const float* color, const float* targ
     }
     if (!color || !target || !grad_color || !grad_logp)
         return fail(c, SOUP_ERR_INVALID, "loss_l1_ssim: device pointers are NULL");
-    HIP_TRY(c, hipSetDevice(c->device));
-    soup_status st = ensure(c, c->ssim, static_cast<size_t>(maxp) * 12 * sizeof(float));
-    if (st != SOUP_OK) return st;
+    *P_out = P;
+    *maxp_out = maxp;
+    return SOUP_OK;
+}
+
+// The loss's launches, view by view, with the statistics record in `stats`
+// (12 floats per pixel of the largest view). Allocates nothing when `timed`
+// is false (the timing events come from a pool that may grow).
+void loss_l1_ssim_launch(soup_ctx* c, const float* color, const float* target, const soup_views* v, float lambda,
+                         float* grad_color, float* grad_logp, float* loss, int64_t P, float* stats, bool timed,
+                         hipStream_t s) {
     // the window: normalised 1-D Gaussian, sigma 1.5, summed in double
     soup::SsimWindow win{};
     double g[2 * soup::kSsimR + 1], sum = 0.0;
@@ -1121,19 +1176,58 @@ soup_status soup_loss_l1_ssim(soup_ctx* c, const float* color, const float* targ
         sum += g[i];
     }
     for (int i = 0; i <= 2 * soup::kSsimR; ++i) win.g[i] = static_cast<float>(g[i] / sum);
-    const hipStream_t s = static_cast<hipStream_t>(stream);
     const float inv_n = static_cast<float>(1.0 / (3.0 * static_cast<double>(P)));
-    {
-        Timed t(c, SOUP_T_TLOSS, s);
+    auto run = [&]() {
         if (loss) launch_fill_f32(loss, 1, 0.0f, s);
         int64_t off = 0;
         for (int i = 0; i < v->V; ++i) {
             const int64_t np = static_cast<int64_t>(v->width[i]) * v->height[i];
             launch_loss_l1_ssim(color + off * 3, target + off * 3, v->width[i], v->height[i], lambda, inv_n, win,
-                                static_cast<float*>(c->ssim.p), grad_color + off * 3, grad_logp + off, loss, s);
+                                stats, grad_color + off * 3, grad_logp + off, loss, s);
             off += np;
         }
+    };
+    if (timed) {
+        Timed t(c, SOUP_T_TLOSS, s);
+        run();
+    } else {
+        run();
     }
+}
+
+}  // namespace
+
+soup_status soup_loss_l1_ssim(soup_ctx* c, const float* color, const float* target, const soup_views* v,
+                              float lambda, float* grad_color, float* grad_logp, float* loss, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    int64_t P = 0, maxp = 0;
+    soup_status st = check_loss_l1_ssim(c, color, target, v, lambda, grad_color, grad_logp, &P, &maxp);
+    if (st != SOUP_OK) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((st = ensure(c, c->ssim, static_cast<size_t>(maxp) * 12 * sizeof(float)))) return st;
+    loss_l1_ssim_launch(c, color, target, v, lambda, grad_color, grad_logp, loss, P, static_cast<float*>(c->ssim.p),
+                        true, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_loss_l1_ssim_noalloc(soup_ctx* c, const float* color, const float* target, const soup_views* v,
+                                      float lambda, float* grad_color, float* grad_logp, float* loss, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    int64_t P = 0, maxp = 0;
+    soup_status st = check_loss_l1_ssim(c, color, target, v, lambda, grad_color, grad_logp, &P, &maxp);
+    if (st != SOUP_OK) return st;
+    const int64_t max_pixels = static_cast<int64_t>(kNoAllocScratchBytes / (12 * sizeof(float)));
+    if (maxp > max_pixels)
+        return fail(c, SOUP_ERR_CAPACITY, "loss_l1_ssim_noalloc: a view of %lld pixels exceeds the static scratch "
+                    "(%zu MiB: views of at most %lld pixels); use soup_loss_l1_ssim", static_cast<long long>(maxp),
+                    kNoAllocScratchBytes >> 20, static_cast<long long>(max_pixels));
+    if (!c->scratch) return fail(c, SOUP_ERR_HIP, "loss_l1_ssim_noalloc: the static scratch has no device address");
+    HIP_TRY(c, hipSetDevice(c->device));
+    loss_l1_ssim_launch(c, color, target, v, lambda, grad_color, grad_logp, loss, P, c->scratch, false,
+                        static_cast<hipStream_t>(stream));
     HIP_TRY(c, hipGetLastError());
     return SOUP_OK;
 }
