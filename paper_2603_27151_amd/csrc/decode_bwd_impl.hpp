@@ -38,6 +38,20 @@ constexpr int kStageRows = 16;   // fragments staged per transpose pass
 // gradient sums, as doubles
 constexpr int kGridTail = 32;
 
+// 1/x in double: the hardware estimate refined by two Newton steps (about one
+// ulp; the backward needs no correctly rounded quotient)
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// The sigmoid of the backward's recompute, from the hardware exp2 and
+// reciprocal (a few ulp; only the forward's mask decision is bit-exact)
+__device__ __forceinline__ float sigmoid_fast(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+
 template <class S>
 struct StageCfg {
     static constexpr int kMax2(int a, int b) { return a > b ? a : b; }
@@ -205,7 +219,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
     float ng0 = 0.f, ng1 = 0.f, ng2 = 0.f, nex = 0.f, ney = 0.f;
     bool nvalid = false;
     constexpr int GW = GateWords<S>::kWords;
-    const bool use_gates = !LOGP && a.sorted_gates != nullptr;   // the forward's ReLU gates, when logged
+    // the forward's ReLU gates of every sorted fragment (from its log, or from
+    // fragment_gates_kernel for a replayed list): the host always provides them
+    const bool use_gates = !LOGP;
     uint32_t ngate[GW];
 #pragma unroll
     for (int k = 0; k < GW; ++k) ngate[k] = 0u;
@@ -334,10 +350,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 const float fx = __shfl(c.fx, src, 64), fy = __shfl(c.fy, src, 64);
                 qfx = fx;
                 qfy = fy;
-                qw[0] = (1.0f - fx) * (1.0f - fy);
-                qw[1] = fx * (1.0f - fy);
-                qw[2] = (1.0f - fx) * fy;
-                qw[3] = fx * fy;
+                // an empty lane's weights are zero, so that its input is zero
+                const float ox = on_n ? 1.0f - fx : 0.0f, oy = 1.0f - fy;
+                qw[0] = ox * oy;
+                qw[1] = on_n ? fx * oy : 0.0f;
+                qw[2] = ox * fy;
+                qw[3] = on_n ? fx * fy : 0.0f;
                 // unconditional loads (an empty lane reads texel 0 of triangle
                 // 0 and its input is zeroed), so that the wait before their use
                 // can leave the next block's loads in flight
@@ -354,35 +372,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             gather(0);
             for (int nb = 0; nb < 4; ++nb) {   // fragment 16 nb + col
                 const int src = 16 * nb + col;
-                const bool on_n = __shfl(static_cast<int>(on), src, 64) != 0;
-                // inputs, unit-major: channels 16 cb + 4 grp .. + 3
+                // inputs, unit-major: channels 16 cb + 4 grp .. + 3 (an empty lane's
+                // weights are zero; channels past C meet zero weights in layer 0)
                 f4v xin[CB];
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    const bool use = on_n && 16 * cb + 4 * grp < S::C;
-                    const float4 q00 = qv[cb][0], q10 = qv[cb][1], q01 = qv[cb][2], q11 = qv[cb][3];
-                    xin[cb][0] = use ? qw[0] * q00.x + qw[1] * q10.x + qw[2] * q01.x + qw[3] * q11.x : 0.0f;
-                    xin[cb][1] = use ? qw[0] * q00.y + qw[1] * q10.y + qw[2] * q01.y + qw[3] * q11.y : 0.0f;
-                    xin[cb][2] = use ? qw[0] * q00.z + qw[1] * q10.z + qw[2] * q01.z + qw[3] * q11.z : 0.0f;
-                    xin[cb][3] = use ? qw[0] * q00.w + qw[1] * q10.w + qw[2] * q01.w + qw[3] * q11.w : 0.0f;
-                }
                 // d feature / d fx and d feature / d fy at the fragment's texture
                 // position (bilinear), the directions in which a winner's vertices
-                // move its texture sample
+                // move its texture sample (an empty lane's are multiplied by a
+                // zero feature gradient)
                 f4v tgx[CB], tgy[CB];
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
-                    const bool use = on_n && 16 * cb + 4 * grp < S::C;
                     const float4 q00 = qv[cb][0], q10 = qv[cb][1], q01 = qv[cb][2], q11 = qv[cb][3];
                     const float ax = 1.0f - qfy, ay = 1.0f - qfx;
-                    tgx[cb][0] = use ? ax * (q10.x - q00.x) + qfy * (q11.x - q01.x) : 0.0f;
-                    tgx[cb][1] = use ? ax * (q10.y - q00.y) + qfy * (q11.y - q01.y) : 0.0f;
-                    tgx[cb][2] = use ? ax * (q10.z - q00.z) + qfy * (q11.z - q01.z) : 0.0f;
-                    tgx[cb][3] = use ? ax * (q10.w - q00.w) + qfy * (q11.w - q01.w) : 0.0f;
-                    tgy[cb][0] = use ? ay * (q01.x - q00.x) + qfx * (q11.x - q10.x) : 0.0f;
-                    tgy[cb][1] = use ? ay * (q01.y - q00.y) + qfx * (q11.y - q10.y) : 0.0f;
-                    tgy[cb][2] = use ? ay * (q01.z - q00.z) + qfx * (q11.z - q10.z) : 0.0f;
-                    tgy[cb][3] = use ? ay * (q01.w - q00.w) + qfx * (q11.w - q10.w) : 0.0f;
+                    const float a00[4] = {q00.x, q00.y, q00.z, q00.w}, a10[4] = {q10.x, q10.y, q10.z, q10.w};
+                    const float a01[4] = {q01.x, q01.y, q01.z, q01.w}, a11[4] = {q11.x, q11.y, q11.z, q11.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        xin[cb][i] = __builtin_fmaf(qw[3], a11[i], __builtin_fmaf(qw[2], a01[i],
+                                                    __builtin_fmaf(qw[1], a10[i], qw[0] * a00[i])));
+                        tgx[cb][i] = __builtin_fmaf(ax, a10[i] - a00[i], qfy * (a11[i] - a01[i]));
+                        tgy[cb][i] = __builtin_fmaf(ay, a01[i] - a00[i], qfx * (a11[i] - a10[i]));
+                    }
                 }
                 if (nb < 3) gather(nb + 1);
                 // the block fragment's gates of this lane's units 16 ob + 4 grp + i
@@ -413,7 +423,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 const f4v (&hl)[HB] = *reinterpret_cast<const f4v (*)[HB]>(S::NH == 2 ? &h1[0] : &h0[0]);
                 // output layer and the logit gradients (Eq. (9) through the sigmoid for the score term)
                 float dO;   // lane group j: output j of the fragment
-                const bool win_n = on_n && __shfl(static_cast<int>(win), src, 64) != 0;
+                // an empty fragment has zero colour gradient and score weight, so its dO is zero
+                const bool win_n = __shfl(static_cast<int>(win), src, 64) != 0;
                 const float gl_n = __shfl(__uint_as_float(fb4.x), src, 64);
                 {
                     f4v o = {Wt.bo[lane], 0.f, 0.f, 0.f};
@@ -425,11 +436,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     }
                     const float g0 = __shfl(__uint_as_float(fb4.y), src, 64), g1 = __shfl(__uint_as_float(fb4.z), src, 64),
                                 g2 = __shfl(__uint_as_float(fb4.w), src, 64);
-                    const float sg = sigmoid_c(o[0]);
+                    const float sg = sigmoid_fast(o[0]);
                     float d;
                     if (grp == 3) d = win_n ? gl_n * (1.0f - sg) : -gl_n * sg;
                     else d = win_n ? (grp == 0 ? g0 : (grp == 1 ? g1 : g2)) * sg * (1.0f - sg) : 0.0f;
-                    dO = on_n ? d : 0.0f;
+                    dO = d;
                 }
                 // A winner's vertices move with the feature gradient of its colour
                 // logits only: the score logit reaches texture and MLP but no vertex
@@ -548,8 +559,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             const ViewDesc& vd = a.views[fc4.z];
             const TriRec& tr = a.recs[vd.rec_base + tri];
             const int W = vd.W, H = vd.H;
-            const int64_t local = static_cast<int64_t>(pix) - vd.pix_base;
-            const int px = static_cast<int>(local % W), py = static_cast<int>(local / W);
+            // the pixel within its view (below 2^32: a view has at most 16384^2 pixels)
+            const uint32_t local = pix - static_cast<uint32_t>(vd.pix_base);
+            const int py = static_cast<int>(local / static_cast<uint32_t>(W));
+            const int px = static_cast<int>(local - static_cast<uint32_t>(py) * static_cast<uint32_t>(W));
             // texture position -> barycentrics -> vertex screen positions and 1/w
             const double gm1 = static_cast<double>(G - 1);
             double iwv[3];
@@ -560,25 +573,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 Xv[i] = tr.X[i];
                 Yv[i] = tr.Y[i];
             }
-            const int64_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
+            const int32_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
             // screen barycentrics beta_i = E_i / A: E_i the orientation-normalised
-            // integer edge function of edge i at the pixel centre, A their sum
+            // integer edge function of edge i at the pixel centre, A their sum.
+            // Every factor is an integer below 2^26 and every E_i below 2^52, so
+            // the products and the fused sums are exact in double.
             double fb[3];
             {
-                const int64_t sgn = tr.rA < 0.0f ? -1 : 1;
-                int64_t Ei[3];
+                const double sgn = tr.rA < 0.0f ? -1.0 : 1.0;
+                double Ei[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const int ea = i == 2 ? 0 : i + 1, eb = i == 0 ? 2 : (i == 1 ? 0 : 1);
-                    const int64_t ex = static_cast<int64_t>(Xv[eb] - Xv[ea]), ey = static_cast<int64_t>(Yv[eb] - Yv[ea]);
-                    Ei[i] = sgn * (ex * (PY - Yv[ea]) - ey * (PX - Xv[ea]));
+                    const double ex = static_cast<double>(Xv[eb] - Xv[ea]), ey = static_cast<double>(Yv[eb] - Yv[ea]);
+                    Ei[i] = sgn * __builtin_fma(ex, static_cast<double>(PY - Yv[ea]),
+                                                -(ey * static_cast<double>(PX - Xv[ea])));
                 }
-                const double inv_a = 1.0 / static_cast<double>(Ei[0] + Ei[1] + Ei[2]);
+                const double inv_a = rcp64((Ei[0] + Ei[1]) + Ei[2]);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) fb[i] = static_cast<double>(Ei[i]) * inv_a;
+                for (int i = 0; i < 3; ++i) fb[i] = Ei[i] * inv_a;
             }
             const double tt[3] = {fb[0] * iwv[0], fb[1] * iwv[1], fb[2] * iwv[2]};
-            const double inv_s = 1.0 / ((tt[0] + tt[1]) + tt[2]);
+            const double inv_s = rcp64((tt[0] + tt[1]) + tt[2]);
             const double bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
             const double db[3] = {0.0, static_cast<double>(my_dfx) * gm1, static_cast<double>(my_dfy) * gm1};
             const double dot = db[1] * bb[1] + db[2] * bb[2];
@@ -589,9 +605,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 dbeta[i] = dt * iwv[i];
                 diw[i] = dt * fb[i];
             }
-            const int64_t Ai = static_cast<int64_t>(Xv[1] - Xv[0]) * (Yv[2] - Yv[0]) -
-                               static_cast<int64_t>(Yv[1] - Yv[0]) * (Xv[2] - Xv[0]);
-            const double inv_area = 65536.0 / static_cast<double>(Ai);   // 1 / (signed 2 x area in px^2)
+            const double Ai = __builtin_fma(static_cast<double>(Xv[1] - Xv[0]), static_cast<double>(Yv[2] - Yv[0]),
+                                            -(static_cast<double>(Yv[1] - Yv[0]) * static_cast<double>(Xv[2] - Xv[0])));
+            const double inv_area = 65536.0 * rcp64(Ai);   // 1 / (signed 2 x area in px^2)
             const double inv256 = 1.0 / 256.0;
             double gsx[3] = {0., 0., 0.}, gsy[3] = {0., 0., 0.};
 #pragma unroll
@@ -640,7 +656,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     acc = __builtin_fmaf(vd.M[j * 4 + 2], z, acc);
                     cc[j] = acc;
                 }
-                const double cx = cc[0], cy = cc[1], iw = 1.0 / static_cast<double>(cc[3]);
+                const double cx = cc[0], cy = cc[1], iw = rcp64(static_cast<double>(cc[3]));
                 const double gc0 = gsx[jv] * hw * iw;
                 const double gc1 = -gsy[jv] * hh * iw;
                 const double gc3 = (-gsx[jv] * hw * cx + gsy[jv] * hh * cy - diw[jv]) * (iw * iw);

@@ -159,8 +159,12 @@ __device__ __forceinline__ void mfma_layer_gated(const f4v (*w)[IB][64], const f
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const bool open = use_gates ? ((gate[ob] >> i) & 1u) != 0u : acc[i] > 0.0f;
-            acc[i] = open ? __builtin_fmaxf(acc[i], 0x1p-126f) : 0.0f;
+            if (use_gates) {   // bit i of the gate as an all-ones or all-zeros mask
+                const int m = static_cast<int>(gate[ob] << (31 - i)) >> 31;
+                acc[i] = __int_as_float(__float_as_int(__builtin_fmaxf(acc[i], 0x1p-126f)) & m);
+            } else {
+                acc[i] = acc[i] > 0.0f ? acc[i] : 0.0f;
+            }
         }
         out[ob] = acc;
     }
