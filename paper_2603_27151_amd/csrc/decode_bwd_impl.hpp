@@ -450,32 +450,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 const bool split = __ballot(win_n && gl_n != 0.0f) != 0;
                 const float dOc = grp == 3 ? 0.0f : dO;
                 float pfx = 0.0f, pfy = 0.0f;   // this lane's channels of d logits / d (fx, fy)
-                if (split) {
-                    f4v dlc[HB];
-#pragma unroll
-                    for (int ob = 0; ob < HB; ++ob) {
-                        f4v v = mfma4(Wt.loT[ob][lane], dOc, f4v{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) v[i] = hl[ob][i] > 0.0f ? v[i] : 0.0f;
-                        dlc[ob] = v;
-                    }
-                    f4v dh0c[HB];
-                    if constexpr (S::NH == 2) {
-                        mfma_back<HB, HB, true>(Wt.l1T, dlc, h0, dh0c, lane);
-                    } else {
-#pragma unroll
-                        for (int ob = 0; ob < HB; ++ob) dh0c[ob] = dlc[ob];
-                    }
-                    f4v dxc[CB];
-                    mfma_back<CB, HB, false>(Wt.l0T, dh0c, nullptr, dxc, lane);
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            pfx = __builtin_fmaf(dxc[cb][i], tgx[cb][i], pfx);
-                            pfy = __builtin_fmaf(dxc[cb][i], tgy[cb][i], pfy);
-                        }
-                }
                 // output-layer weight gradient (rows = this block's fragments)
                 stage_rows<HB>(st, S::H, hl, lane);
                 st[kStageRows * (S::H + kRowPad) + col * (4 + kRowPad) + grp] = dO;
@@ -487,15 +461,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 }
                 wave_fence();
                 // back through the output layer: K = the four outputs, one step
-                f4v dl[HB];
+                // (with split, the colour logits' backward runs beside it)
+                f4v dl[HB], dlc[HB];
 #pragma unroll
                 for (int ob = 0; ob < HB; ++ob) {
-                    f4v v = mfma4(Wt.loT[ob][lane], dO, f4v{0.f, 0.f, 0.f, 0.f});
+                    const float wl = Wt.loT[ob][lane];
+                    f4v v = mfma4(wl, dO, f4v{0.f, 0.f, 0.f, 0.f});
+                    f4v vc = split ? mfma4(wl, dOc, f4v{0.f, 0.f, 0.f, 0.f}) : f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = hl[ob][i] > 0.0f ? v[i] : 0.0f;
+                    for (int i = 0; i < 4; ++i) {
+                        v[i] = hl[ob][i] > 0.0f ? v[i] : 0.0f;
+                        vc[i] = hl[ob][i] > 0.0f ? vc[i] : 0.0f;
+                    }
                     dl[ob] = v;
+                    dlc[ob] = vc;
                 }
-                f4v dh0[HB];
+                f4v dh0[HB], dh0c[HB];
                 if constexpr (S::NH == 2) {
                     // hidden layer 1 weight gradient, then back to layer 0
                     stage_rows<HB>(st, S::H, h0, lane);
@@ -504,10 +485,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     acc.mid[0].accumulate(st, st + kStageRows * (S::H + kRowPad), lane);
                     acc.mid[0].add_bias(dl);
                     wave_fence();
-                    mfma_back<HB, HB, true>(Wt.l1T, dl, h0, dh0, lane);
+                    if (split) mfma_back2<HB, HB, true>(Wt.l1T, dl, dlc, h0, dh0, dh0c, lane);
+                    else mfma_back<HB, HB, true>(Wt.l1T, dl, h0, dh0, lane);
                 } else {
 #pragma unroll
-                    for (int ob = 0; ob < HB; ++ob) dh0[ob] = dl[ob];
+                    for (int ob = 0; ob < HB; ++ob) {
+                        dh0[ob] = dl[ob];
+                        dh0c[ob] = dlc[ob];
+                    }
                 }
                 // first-layer weight gradient
                 stage_rows<CB>(st, S::C, xin, lane);
@@ -516,24 +501,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 acc.l0.accumulate(st, st + kStageRows * (S::C + kRowPad), lane);
                 acc.l0.add_bias(dh0);
                 wave_fence();
-                // feature gradients into the rows [fragment][C] kept past the stage's working rows
-                f4v dxv[CB];
-                mfma_back<CB, HB, false>(Wt.l0T, dh0, nullptr, dxv, lane);
+                // feature gradients into the rows [fragment][C] kept past the stage's working rows;
+                // the winners' vertices move with those of the colour logits alone
+                f4v dxv[CB], dxc[CB];
+                if (split) {
+                    mfma_back2<CB, HB, false>(Wt.l0T, dh0, dh0c, nullptr, dxv, dxc, lane);
+                } else {
+                    mfma_back<CB, HB, false>(Wt.l0T, dh0, nullptr, dxv, lane);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) dxc[cb] = dxv[cb];
+                }
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
                     const int ch = 16 * cb + 4 * grp;
                     if (ch < S::C)
                         *reinterpret_cast<float4*>(s_dx[w] + (16 * nb + col) * DXS + ch) =
                             make_float4(dxv[cb][0], dxv[cb][1], dxv[cb][2], dxv[cb][3]);
-                }
-                if (!split) {
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            pfx = __builtin_fmaf(dxv[cb][i], tgx[cb][i], pfx);
-                            pfy = __builtin_fmaf(dxv[cb][i], tgy[cb][i], pfy);
-                        }
+                    for (int i = 0; i < 4; ++i) {
+                        pfx = __builtin_fmaf(dxc[cb][i], tgx[cb][i], pfx);
+                        pfy = __builtin_fmaf(dxc[cb][i], tgy[cb][i], pfy);
+                    }
                 }
                 // sum over the four lane groups' channels; lane 16 nb + col keeps
                 // the values of its own fragment

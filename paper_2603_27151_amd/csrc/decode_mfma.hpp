@@ -191,6 +191,36 @@ __device__ __forceinline__ void mfma_back(const f4v (*wT)[IB][64], const f4v (&d
     }
 }
 
+// Two data backwards through the same layer at once (each weight operand read
+// once, two independent product chains): d_in1 = W^T d_out1, d_in2 = W^T d_out2,
+// both masked by act > 0 when MASK.
+template <int OB, int IB, bool MASK>
+__device__ __forceinline__ void mfma_back2(const f4v (*wT)[IB][64], const f4v (&d_out1)[IB], const f4v (&d_out2)[IB],
+                                           const f4v* mask, f4v (&d_in1)[OB], f4v (&d_in2)[OB], int lane) {
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+        f4v acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) {
+            const f4v wv = wT[ob][ib][lane];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                acc1 = mfma4(wv[s], d_out1[ib][s], acc1);
+                acc2 = mfma4(wv[s], d_out2[ib][s], acc2);
+            }
+        }
+        if (MASK) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                acc1[i] = mask[ob][i] > 0.0f ? acc1[i] : 0.0f;
+                acc2[i] = mask[ob][i] > 0.0f ? acc2[i] : 0.0f;
+            }
+        }
+        d_in1[ob] = acc1;
+        d_in2[ob] = acc2;
+    }
+}
+
 // The 16 rows of one fragment block into an LDS stage laid out [row][D + kRowPad]
 // (D = n_units): lane (grp, col) writes its four units of row col.
 template <int NBLK>
