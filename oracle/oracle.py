@@ -41,6 +41,11 @@ class _Stats(C.Structure):
                 ("decodes", C.c_int64), ("winners", C.c_int64), ("front_fragments", C.c_int64)]
 
 
+class _PScene(C.Structure):
+    _fields_ = [("T", C.c_int32), ("R", C.c_int32), ("verts", C.c_void_p), ("tex", C.c_void_p),
+                ("mlp", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -68,6 +73,16 @@ def lib():
         L.orc_count_valid.argtypes = [P, P, P]
         L.orc_count_valid.restype = C.c_int64
         L.orc_threads.restype = C.c_int
+        L.orc_mc_count.argtypes = [C.c_int]
+        L.orc_mc_lookup.argtypes = [C.c_int, C.c_float, C.c_float, P, P]
+        L.orc_mc_assemble.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P]
+        L.orc_mc_assemble_bwd.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P]
+        L.orc_sh2.argtypes = [P, P]
+        L.orc_sh2.restype = None
+        L.orc_view_dir.argtypes = [P, P, C.c_int32, C.c_int32, P]
+        L.orc_pforward.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_pbackward.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_pcolor_f64.argtypes = [P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P]
         _lib = L
     return _lib
 
@@ -233,3 +248,141 @@ def count_valid(scene, view, opts: Opts) -> int:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+# ---------------------------------------------------------------------------
+# Paper form (Section 3.3; Supplement B.3, B.6): mesh-colour texture, opacity
+# outside the MLP, deferred shading with spherical harmonics. A paper-form
+# scene has verts [T,3,3], tex [T,V(R),8] (activated), mlp (the 16-16-16-3
+# MLP's flat parameters) and R.
+# ---------------------------------------------------------------------------
+
+N_PCH = 8
+
+
+def mc_count(R: int) -> int:
+    return int(lib().orc_mc_count(R))
+
+
+def pmlp_params() -> int:
+    return int(lib().orc_pmlp_params())
+
+
+def mc_lookup(R: int, b1: float, b2: float):
+    idx = np.zeros(3, np.int32)
+    w = np.zeros(3, np.float32)
+    lib().orc_mc_lookup(R, b1, b2, _ptr(idx), _ptr(w))
+    return idx, w
+
+
+def mc_assemble(raw: Sequence[np.ndarray], Rmin: int, Rmax: Optional[int] = None):
+    """tex [T, V(Rmax), 8] = sigmoid(sum of the learnable levels sampled at the
+    level-Rmax grid's vertices); raw[l] is [T, V(Rmin + l), 8]; Rmax defaults
+    to the top learnable level."""
+    raw = [np.ascontiguousarray(r, dtype=np.float32) for r in raw]
+    Rtop = Rmin + len(raw) - 1
+    Rmax = Rtop if Rmax is None else Rmax
+    T = raw[0].shape[0]
+    for l, r in enumerate(raw):
+        assert r.shape == (T, mc_count(Rmin + l), N_PCH)
+    tex = np.empty((T, mc_count(Rmax), N_PCH), np.float32)
+    ptrs = (C.c_void_p * len(raw))(*[r.ctypes.data for r in raw])
+    if lib().orc_mc_assemble(T, Rmin, Rtop, Rmax, ptrs, _ptr(tex)) != 0:
+        raise ValueError("oracle mc_assemble rejected its arguments")
+    return tex
+
+
+def mc_assemble_bwd(tex, grad_tex, Rmin: int, n_levels: int, Rmax: Optional[int] = None):
+    tex = np.ascontiguousarray(tex, dtype=np.float32)
+    gt = np.ascontiguousarray(grad_tex, dtype=np.float32)
+    T = tex.shape[0]
+    Rtop = Rmin + n_levels - 1
+    Rmax = Rtop if Rmax is None else Rmax
+    outs = [np.zeros((T, mc_count(Rmin + l), N_PCH), np.float64) for l in range(n_levels)]
+    ptrs = (C.c_void_p * n_levels)(*[o.ctypes.data for o in outs])
+    if lib().orc_mc_assemble_bwd(T, Rmin, Rtop, Rmax, _ptr(tex), _ptr(gt), ptrs) != 0:
+        raise ValueError("oracle mc_assemble_bwd rejected its arguments")
+    return outs
+
+
+def sh2(d) -> np.ndarray:
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    out = np.zeros(9, np.float32)
+    lib().orc_sh2(_ptr(d), _ptr(out))
+    return out
+
+
+def view_dir(view, minv, x: int, y: int) -> np.ndarray:
+    M = np.ascontiguousarray(view.M, dtype=np.float32)
+    Mi = np.ascontiguousarray(minv, dtype=np.float32).reshape(16)
+    v = _View(view.width, view.height, view.view_id, M.ctypes.data)
+    d = np.zeros(3, np.float32)
+    if lib().orc_view_dir(C.byref(v), _ptr(Mi), x, y, _ptr(d)) != 0:
+        raise ValueError("bad pixel")
+    return d
+
+
+class _PKeep:
+    def __init__(self, ps, view, minv, opts):
+        self.verts = np.ascontiguousarray(ps.verts, dtype=np.float32)
+        self.tex = np.ascontiguousarray(ps.tex, dtype=np.float32)
+        self.mlp = np.ascontiguousarray(ps.mlp, dtype=np.float32)
+        T = self.verts.shape[0]
+        assert self.tex.shape == (T, mc_count(ps.R), N_PCH) and self.mlp.size == pmlp_params()
+        self.M = np.ascontiguousarray(view.M, dtype=np.float32)
+        self.Minv = np.ascontiguousarray(minv, dtype=np.float32).reshape(16)
+        self.s = _PScene(T, ps.R, self.verts.ctypes.data, self.tex.ctypes.data, self.mlp.ctypes.data)
+        self.v = _View(view.width, view.height, view.view_id, self.M.ctypes.data)
+        self.o = _Opts(opts.seed, opts.step, opts.mode, (C.c_float * 3)(*opts.background),
+                       opts.edge_pairs, opts.near_w, opts.analysis)
+
+    def args(self):
+        return C.byref(self.s), C.byref(self.v), _ptr(self.Minv), C.byref(self.o)
+
+
+def pforward(ps, view, minv, opts: Opts, want_logp: bool = True):
+    k = _PKeep(ps, view, minv, opts)
+    H, W = view.height, view.width
+    vis = np.empty(H * W, np.uint64)
+    color = np.empty(H * W * 3, np.float32)
+    logp = np.empty(H * W, np.float64) if want_logp else None
+    st = _Stats()
+    rc = lib().orc_pforward(*k.args(), _ptr(vis), _ptr(color), _ptr(logp) if want_logp else None, C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle pforward rejected its arguments")
+    stats = {f: int(getattr(st, f)) for f, _ in _Stats._fields_}
+    return vis.reshape(H, W), color.reshape(H, W, 3), (logp.reshape(H, W) if want_logp else None), stats
+
+
+def pbackward(ps, view, minv, opts: Opts, vis, color, grad_color, grad_logp=None, out=None):
+    """Gradients of one paper-form view (float64): d verts [T,3,3], d tex
+    [T,V,8], d mlp; with out = (gv, gt, gm) they are added into those arrays."""
+    k = _PKeep(ps, view, minv, opts)
+    T, V = k.tex.shape[0], k.tex.shape[1]
+    if out is not None:
+        gv, gt, gm = (o.reshape(-1) for o in out)
+        assert gv.size == T * 9 and gt.size == T * V * N_PCH and gm.size == pmlp_params()
+        assert all(o.dtype == np.float64 and o.flags.c_contiguous for o in out)
+    else:
+        gv = np.zeros(T * 9, np.float64)
+        gt = np.zeros(T * V * N_PCH, np.float64)
+        gm = np.zeros(pmlp_params(), np.float64)
+    vis = np.ascontiguousarray(vis, dtype=np.uint64).ravel()
+    color = np.ascontiguousarray(color, dtype=np.float32).ravel()
+    gc = np.ascontiguousarray(grad_color, dtype=np.float32).ravel()
+    gl = None if grad_logp is None else np.ascontiguousarray(grad_logp, dtype=np.float32).ravel()
+    rc = lib().orc_pbackward(*k.args(), _ptr(vis), _ptr(color), _ptr(gc), _ptr(gl) if gl is not None else None,
+                             _ptr(gv), _ptr(gt), _ptr(gm))
+    if rc != 0:
+        raise ValueError("oracle pbackward rejected its arguments")
+    return gv.reshape(T, 3, 3), gt.reshape(T, V, N_PCH), gm
+
+
+def pcolor_f64(ps, view, minv, opts: Opts, tri: int, x: int, y: int):
+    k = _PKeep(ps, view, minv, opts)
+    rgb = np.zeros(3, np.float64)
+    a = C.c_double(0)
+    rc = lib().orc_pcolor_f64(*k.args(), tri, x, y, _ptr(rgb), C.byref(a))
+    if rc < 0:
+        raise ValueError("bad arguments")
+    return (rgb, a.value) if rc == 1 else (None, None)

@@ -1130,3 +1130,680 @@ int64_t orc_count_valid(const orc_scene* s, const orc_view* v, const orc_opts* o
     ctx_free(&c);
     return n;
 }
+
+/* ========================================================================= */
+/* Paper form of the step (Section 3.3, "Learnable multi-resolution triangle   */
+/* texture" and "Neural deferred shading"; Supplement B.3, MLP architecture;   */
+/* Supplement B.6, 561 grid points at R = 5).                                  */
+/*                                                                             */
+/* Texture: per triangle, the finest mesh-colour grid of level R: the          */
+/* triangle subdivided into n = 2^R segments per edge, grid vertex (i, j)      */
+/* (i, j >= 0, i + j <= n) at barycentrics (b1, b2) = (i/n, j/n); 8 channels    */
+/* per vertex, activated (in [0,1]): 7 colour features, then the opacity.      */
+/* Opacity stays outside the MLP: a fragment's alpha is the opacity channel     */
+/* interpolated in the micro-triangle that contains it. The MLP runs once per   */
+/* pixel, on the winner (deferred): input = the 7 interpolated features and     */
+/* the 9 real spherical harmonics of degree <= 2 of the view direction; two     */
+/* hidden layers of 16 (ReLU); 3 outputs through the sigmoid. Reading of the    */
+/* skip blend: features 0..3 are RGBA, and the colour is                        */
+/* A * RGB + (1 - A) * MLP.                                                     */
+/* Everything up to the mask decision and the deferred colour follows one      */
+/* float32 operation sequence, so both are reproducible bit for bit.           */
+/* ========================================================================= */
+
+#define PCH 8            /* channels per grid vertex */
+#define PFEAT 7          /* colour features */
+#define PIN 16           /* MLP input: 7 features + 9 harmonics */
+#define PHID 16
+
+int orc_mc_count(int R)
+{
+    const int n = 1 << R;
+    return (n + 1) * (n + 2) / 2;
+}
+
+/* Row-major layout: row j holds n + 1 - j vertices, i ascending. */
+static int mc_index(int n, int i, int j)
+{
+    return j * (n + 1) - j * (j - 1) / 2 + i;
+}
+
+/* The micro-triangle of the level with n segments per edge that contains the
+ * point (b1, b2), and the point's barycentric weights in it (float32): u = b1 n
+ * and v = b2 n (exact: n is a power of two), i = floor(u) clamped to
+ * [0, n - 1], j = floor(v) clamped to [0, n - 1 - i], fu = u - i, fv = v - j.
+ * If fu + fv > 1 and the inverted micro-triangle exists (i + j <= n - 2) the
+ * point lies in it: vertices (i+1, j+1), (i+1, j), (i, j+1), weights
+ * (fu + fv - 1, 1 - fv, 1 - fu); otherwise in the upright one: (i, j),
+ * (i+1, j), (i, j+1), weights ((1 - fu) - fv, fu, fv). */
+static void mc_lookup(int n, float b1, float b2, int idx[3], float w[3], float* fu_out, float* fv_out, int* inv_out)
+{
+    const float u = b1 * (float)n, v = b2 * (float)n;
+    int i = (int)floorf(u);
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    int j = (int)floorf(v);
+    if (j < 0) j = 0;
+    if (j > n - 1 - i) j = n - 1 - i;
+    const float fu = u - (float)i, fv = v - (float)j;
+    const float s = fu + fv;
+    int inv = s > 1.0f && i + j <= n - 2;
+    if (inv) {
+        idx[0] = mc_index(n, i + 1, j + 1); idx[1] = mc_index(n, i + 1, j); idx[2] = mc_index(n, i, j + 1);
+        w[0] = s - 1.0f; w[1] = 1.0f - fv; w[2] = 1.0f - fu;
+    } else {
+        idx[0] = mc_index(n, i, j); idx[1] = mc_index(n, i + 1, j); idx[2] = mc_index(n, i, j + 1);
+        w[0] = (1.0f - fu) - fv; w[1] = fu; w[2] = fv;
+    }
+    if (fu_out) *fu_out = fu;
+    if (fv_out) *fv_out = fv;
+    if (inv_out) *inv_out = inv;
+}
+
+static float mc_interp(const float* tex, int ch, const int idx[3], const float w[3])
+{
+    return fmaf(w[2], tex[(size_t)idx[2] * PCH + ch], fmaf(w[1], tex[(size_t)idx[1] * PCH + ch],
+                                                          w[0] * tex[(size_t)idx[0] * PCH + ch]));
+}
+
+int orc_mc_lookup(int R, float b1, float b2, int32_t idx[3], float w[3])
+{
+    int ii[3];
+    mc_lookup(1 << R, b1, b2, ii, w, NULL, NULL, NULL);
+    for (int k = 0; k < 3; ++k) idx[k] = ii[k];
+    return 0;
+}
+
+/* Multi-resolution texture (Section 3.3): learnable grids of levels Rmin ..
+ * Rtop (Rtop <= Rmax), raw[l] of level Rmin + l, [T][V(level)][8], each
+ * sampled at the vertices of the level-Rmax grid by the micro-triangle lookup
+ * and summed (Rmin first) before the sigmoid: tex [T][V(Rmax)][8] =
+ * sigmoid(sum). The paper keeps grids up to Rmax - 1 and accumulates them on
+ * the finest grid (Rtop = Rmax - 1); Rtop = Rmax makes the finest grid
+ * learnable as well. */
+static int levels_ok(int T, int Rmin, int Rtop, int Rmax)
+{
+    return T >= 0 && Rmin >= 0 && Rtop >= Rmin && Rmax >= Rtop && Rmax <= 10;
+}
+
+int orc_mc_assemble(int T, int Rmin, int Rtop, int Rmax, const float* const* raw, float* tex)
+{
+    if (!levels_ok(T, Rmin, Rtop, Rmax)) return -1;
+    const int n = 1 << Rmax, V = orc_mc_count(Rmax);
+    #pragma omp parallel for schedule(static)
+    for (int t = 0; t < T; ++t) {
+        for (int j = 0; j <= n; ++j)
+            for (int i = 0; i + j <= n; ++i) {
+                const float b1 = (float)i / (float)n, b2 = (float)j / (float)n;
+                float z[PCH] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int R = Rmin; R <= Rtop; ++R) {
+                    const float* g = raw[R - Rmin] + (size_t)t * orc_mc_count(R) * PCH;
+                    int idx[3];
+                    float w[3];
+                    mc_lookup(1 << R, b1, b2, idx, w, NULL, NULL, NULL);
+                    for (int c = 0; c < PCH; ++c) z[c] = z[c] + mc_interp(g, c, idx, w);
+                }
+                float* out = tex + ((size_t)t * V + mc_index(n, i, j)) * PCH;
+                for (int c = 0; c < PCH; ++c) out[c] = orc_sigmoid(z[c]);
+            }
+    }
+    return 0;
+}
+
+/* Gradient of orc_mc_assemble: d raw[l] += sum over finest vertices of
+ * sigmoid' * d tex * (the vertex's weight in the level's lookup). The
+ * sigmoid derivative is taken from the assembled value: tex (1 - tex). */
+int orc_mc_assemble_bwd(int T, int Rmin, int Rtop, int Rmax, const float* tex, const float* grad_tex,
+                        double* const* grad_raw)
+{
+    if (!levels_ok(T, Rmin, Rtop, Rmax)) return -1;
+    const int n = 1 << Rmax, V = orc_mc_count(Rmax);
+    #pragma omp parallel for schedule(static)
+    for (int t = 0; t < T; ++t) {
+        for (int j = 0; j <= n; ++j)
+            for (int i = 0; i + j <= n; ++i) {
+                const size_t at = ((size_t)t * V + mc_index(n, i, j)) * PCH;
+                const float b1 = (float)i / (float)n, b2 = (float)j / (float)n;
+                for (int R = Rmin; R <= Rtop; ++R) {
+                    double* g = grad_raw[R - Rmin] + (size_t)t * orc_mc_count(R) * PCH;
+                    int idx[3];
+                    float w[3];
+                    mc_lookup(1 << R, b1, b2, idx, w, NULL, NULL, NULL);
+                    for (int c = 0; c < PCH; ++c) {
+                        const double s = tex[at + c];
+                        const double dz = (double)grad_tex[at + c] * s * (1.0 - s);
+                        for (int k = 0; k < 3; ++k) g[(size_t)idx[k] * PCH + c] += (double)w[k] * dz;
+                    }
+                }
+            }
+    }
+    return 0;
+}
+
+/* The view direction through the centre of pixel (x, y), float32: the pixel's
+ * normalised device coordinates at the near (-1) and far (+1) depth mapped
+ * back through Minv (the inverse view-projection, given with the view), each
+ * row as the vertex transform (bias first, then x, y, z by FMA), divided by
+ * w; the difference normalised. */
+static void view_dir(const orc_view* v, const float* Minv, int x, int y, float d[3])
+{
+    const float nx = (2.0f * (float)x + 1.0f) / (float)v->W - 1.0f;
+    const float ny = 1.0f - (2.0f * (float)y + 1.0f) / (float)v->H;
+    float p[2][4];
+    for (int e = 0; e < 2; ++e) {
+        const float nz = e == 0 ? -1.0f : 1.0f;
+        for (int r = 0; r < 4; ++r) {
+            float a = Minv[r * 4 + 3];
+            a = fmaf(Minv[r * 4 + 0], nx, a);
+            a = fmaf(Minv[r * 4 + 1], ny, a);
+            a = fmaf(Minv[r * 4 + 2], nz, a);
+            p[e][r] = a;
+        }
+    }
+    for (int k = 0; k < 3; ++k) d[k] = p[1][k] / p[1][3] - p[0][k] / p[0][3];
+    const float len = sqrtf(fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0])));
+    for (int k = 0; k < 3; ++k) d[k] = d[k] / len;
+}
+
+int orc_view_dir(const orc_view* v, const float* Minv, int32_t x, int32_t y, float d[3])
+{
+    if (!v || !Minv || x < 0 || y < 0 || x >= v->W || y >= v->H) return -1;
+    view_dir(v, Minv, x, y, d);
+    return 0;
+}
+
+/* The 9 real spherical harmonics of degree <= 2 (orthonormal on the sphere,
+ * no Condon-Shortley sign) of a unit vector, float32:
+ *   1/(2 sqrt(pi));  sqrt(3/(4 pi)) (y, z, x);
+ *   sqrt(15/(4 pi)) (xy, yz), sqrt(5/(16 pi)) (2z^2 - x^2 - y^2),
+ *   sqrt(15/(4 pi)) xz, sqrt(15/(16 pi)) (x^2 - y^2). */
+void orc_sh2(const float d[3], float out[9])
+{
+    const float x = d[0], y = d[1], z = d[2];
+    const float c0 = 0.28209479177387814f, c1 = 0.48860251190291992f;
+    const float c2 = 1.0925484305920792f, c3 = 0.31539156525252005f, c4 = 0.54627421529603959f;
+    out[0] = c0;
+    out[1] = c1 * y;
+    out[2] = c1 * z;
+    out[3] = c1 * x;
+    out[4] = c2 * (x * y);
+    out[5] = c2 * (y * z);
+    out[6] = c3 * fmaf(2.0f * z, z, -fmaf(x, x, y * y));
+    out[7] = c2 * (x * z);
+    out[8] = c4 * fmaf(x, x, -(y * y));
+}
+
+/* orc_sh2 in double, constants from their closed forms. */
+static void sh2_d(const double d[3], double out[9])
+{
+    const double PI = 3.14159265358979323846;
+    const double x = d[0], y = d[1], z = d[2];
+    const double c0 = 0.5 / sqrt(PI), c1 = sqrt(3.0 / (4 * PI)), c2 = sqrt(15.0 / (4 * PI)),
+                 c3 = sqrt(5.0 / (16 * PI)), c4 = sqrt(15.0 / (16 * PI));
+    out[0] = c0;
+    out[1] = c1 * y; out[2] = c1 * z; out[3] = c1 * x;
+    out[4] = c2 * x * y; out[5] = c2 * y * z; out[6] = c3 * (2 * z * z - x * x - y * y);
+    out[7] = c2 * x * z; out[8] = c4 * (x * x - y * y);
+}
+
+/* Deferred MLP, float32 contract (as decode_f32): act[0] = input, act[1],
+ * act[2] = hidden layers, act[3][0..2] = output logits. Parameters: W0[16][16],
+ * b0[16], W1[16][16], b1[16], W2[3][16], b2[3]. */
+static void pmlp_f32(const float* p, const float in[PIN], float act[4][PHID])
+{
+    for (int k = 0; k < PIN; ++k) act[0][k] = in[k];
+    const int din[3] = {PIN, PHID, PHID}, dout[3] = {PHID, PHID, 3};
+    for (int l = 0; l < 3; ++l) {
+        const float* W = p;
+        const float* b = p + dout[l] * din[l];
+        for (int j = 0; j < dout[l]; ++j) {
+            float h = b[j];
+            for (int k = 0; k < din[l]; ++k) h = fmaf(W[j * din[l] + k], act[l][k], h);
+            if (l < 2) h = h > 0.0f ? h : 0.0f;
+            act[l + 1][j] = h;
+        }
+        p += dout[l] * din[l] + dout[l];
+    }
+}
+
+int orc_pmlp_params(void) { return PIN * PHID + PHID + PHID * PHID + PHID + 3 * PHID + 3; }
+
+typedef struct {
+    const float* tex;        /* [T][V][8] */
+    const float* mlp;
+    const float* Minv;       /* this view's inverse view-projection */
+    int R, n, V;
+} pctx;
+
+/* Colour of the winner fragment f at pixel (x, y) (float32 contract): the
+ * features and A at its barycentrics, the MLP on features + harmonics, the
+ * blend. act/feat/mlp_rgb are returned for the backward. */
+static void pshade(const pctx* P, const orc_view* v, const frag_t* f, int x, int y, float rgb[3],
+                   float feat[PFEAT], float act[4][PHID], int idx[3], float w[3])
+{
+    const float* tt = P->tex + (size_t)f->tri * P->V * PCH;
+    mc_lookup(P->n, f->b1, f->b2, idx, w, NULL, NULL, NULL);
+    for (int c = 0; c < PFEAT; ++c) feat[c] = mc_interp(tt, c, idx, w);
+    float d[3], in[PIN];
+    view_dir(v, P->Minv, x, y, d);
+    for (int c = 0; c < PFEAT; ++c) in[c] = feat[c];
+    orc_sh2(d, in + PFEAT);
+    pmlp_f32(P->mlp, in, act);
+    const float A = feat[3];
+    for (int c = 0; c < 3; ++c) {
+        const float m = orc_sigmoid(act[3][c]);
+        rgb[c] = fmaf(A, feat[c] - m, m);     /* A RGB + (1 - A) MLP */
+    }
+}
+
+static float palpha(const pctx* P, const frag_t* f)
+{
+    int idx[3];
+    float w[3];
+    mc_lookup(P->n, f->b1, f->b2, idx, w, NULL, NULL, NULL);
+    return mc_interp(P->tex + (size_t)f->tri * P->V * PCH, PFEAT, idx, w);
+}
+
+/* Mask test with the opacity texture: Eq. (5) (u < alpha) or Eq. (3) read as
+ * alpha > 0.5. */
+static int ppasses(const orc_view* v, const orc_opts* o, int x, int y, uint32_t tri, float a)
+{
+    if (o->mode == 1) return a > 0.5f;
+    return orc_uniform(o->seed, (uint32_t)(y * v->W + x), tri, v->view_id, o->step) < a;
+}
+
+static void ppixel_forward(const view_ctx* c, const pctx* P, int x, int y, const frag_buf* b, pixel_result* r)
+{
+    r->winner = -1;
+    r->key = BG_KEY;
+    for (int k = 0; k < 3; ++k) r->rgb[k] = c->o->background[k];
+    r->logp = 0.0;
+    r->decodes = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const float a = palpha(P, &b->f[i]);
+        r->decodes++;
+        if (ppasses(c->v, c->o, x, y, b->f[i].tri, a)) {
+            r->winner = i;
+            r->key = b->f[i].key;
+            float feat[PFEAT], act[4][PHID], w[3];
+            int idx[3];
+            pshade(P, c->v, &b->f[i], x, y, r->rgb, feat, act, idx, w);
+            if (c->o->mode == 0) r->logp += log((double)a);
+            return;
+        }
+        if (c->o->mode == 0) r->logp += log1p(-(double)a);
+    }
+}
+
+/* geometry-only scene for the shared setup and coverage code */
+static orc_scene pgeom(const orc_pscene* s, int32_t* dims)
+{
+    orc_scene g;
+    dims[0] = 1; dims[1] = 4;
+    g.T = s->T; g.G = 2; g.C = 1; g.n_layers = 1; g.dims = dims;
+    g.verts = s->verts; g.feats = NULL; g.mlp = NULL;
+    return g;
+}
+
+static int pscene_ok(const orc_pscene* s)
+{
+    return s && s->T >= 0 && s->R >= 0 && s->R <= 10 && (s->T == 0 || (s->verts && s->tex && s->mlp));
+}
+
+int orc_pforward(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
+                 uint64_t* vis, float* color, double* logp, orc_stats* st)
+{
+    if (!pscene_ok(s) || !Minv) return -1;
+    int32_t dims[2];
+    orc_scene g = pgeom(s, dims);
+    view_ctx c;
+    if (ctx_init(&c, &g, v, o, 1) != 0) return -1;
+    pctx P = {s->tex, s->mlp, Minv, s->R, 1 << s->R, orc_mc_count(s->R)};
+    int64_t cov = 0, frags = 0, dec = 0, win = 0, front = 0;
+    #pragma omp parallel reduction(+ : cov, frags, dec, win, front)
+    {
+        frag_buf b = {0};
+        #pragma omp for schedule(dynamic, 4)
+        for (int y = 0; y < v->H; ++y)
+            for (int x = 0; x < v->W; ++x) {
+                size_t p = (size_t)y * v->W + x;
+                pixel_fragments(&c, x, y, &b);
+                pixel_result r;
+                ppixel_forward(&c, &P, x, y, &b, &r);
+                vis[p] = r.key;
+                for (int k = 0; k < 3; ++k) color[3 * p + k] = r.rgb[k];
+                if (logp) logp[p] = r.logp;
+                cov += b.n > 0;
+                frags += b.n;
+                dec += r.decodes;
+                win += r.winner >= 0;
+                front += r.winner >= 0 ? r.winner : b.n;
+            }
+        free(b.f);
+    }
+    if (st) {
+        st->covered_pixels = cov;
+        st->covering_fragments = frags;
+        st->decodes = dec;
+        st->winners = win;
+        st->front_fragments = front;
+    }
+    ctx_free(&c);
+    return 0;
+}
+
+/* d loss / d (perspective-correct b1, b2) of fragment f -> the screen
+ * positions and 1/w of its triangle's vertices (as the colour path of the
+ * workloads' form: perspective division, screen barycentrics). */
+static void push_bary(const view_ctx* c, const frag_t* f, int x, int y, double db1, double db2, grad_out* go)
+{
+    const tri_setup* t = &c->ts[f->tri];
+    frag_geom g;
+    geom_of(c, t, x, y, &g);
+    double tt[3], S = 0;
+    for (int i = 0; i < 3; ++i) { tt[i] = g.beta[i] * g.iw[i]; S += tt[i]; }
+    const double b[3] = {tt[0] / S, tt[1] / S, tt[2] / S};
+    const double db[3] = {0.0, db1, db2};
+    const double dot = db[0] * b[0] + db[1] * b[1] + db[2] * b[2];
+    double dbeta_v[3], diw[3];
+    for (int i = 0; i < 3; ++i) {
+        const double dtt = (db[i] - dot) / S;
+        dbeta_v[i] = dtt * g.iw[i];
+        diw[i] = dtt * g.beta[i];
+    }
+    double D[3][3][2];
+    dbeta(&g, D);
+    double* gv = go->g_verts_screen + (size_t)f->tri * 9;
+    for (int j = 0; j < 3; ++j) {
+        double sx = 0, sy = 0;
+        for (int i = 0; i < 3; ++i) { sx += dbeta_v[i] * D[i][j][0]; sy += dbeta_v[i] * D[i][j][1]; }
+        atomic_add(&gv[3 * j + 0], sx);
+        atomic_add(&gv[3 * j + 1], sy);
+        atomic_add(&gv[3 * j + 2], diw[j]);
+    }
+}
+
+/* The winner's shading inputs at which the backward differentiates: the
+ * float32 contract values, or in analysis mode float64 values at the exact
+ * perspective-correct barycentrics (the micro-triangle kept from the float32
+ * lookup) with the view direction, harmonics and MLP in double. feat[0..7],
+ * act[0] = MLP input, act[1..2] hidden, act[3][0..2] logits. */
+static void pshade_d(const view_ctx* c, const pctx* P, const frag_t* f, int x, int y, const int idx[3], int inv,
+                     float fu32, float fv32, double feat[PCH], double act[4][PHID], double w[3])
+{
+    const float* tt = P->tex + (size_t)f->tri * P->V * PCH;
+    if (!c->o->analysis) {
+        float rgb[3], ft[PFEAT], a32[4][PHID], w32[3];
+        int id[3];
+        pshade(P, c->v, f, x, y, rgb, ft, a32, id, w32);
+        for (int k = 0; k < 3; ++k) w[k] = w32[k];
+        for (int k = 0; k < PFEAT; ++k) feat[k] = ft[k];
+        feat[PFEAT] = palpha(P, f);
+        for (int l = 0; l < 4; ++l)
+            for (int k = 0; k < PHID; ++k) act[l][k] = a32[l][k];
+        return;
+    }
+    const tri_setup* t = &c->ts[f->tri];
+    frag_geom g;
+    geom_of(c, t, x, y, &g);
+    double q[3], S = 0;
+    for (int i = 0; i < 3; ++i) { q[i] = g.beta[i] * g.iw[i]; S += q[i]; }
+    const int n = P->n;
+    /* cell origin from the float32 lookup: u = i + fu */
+    const double i0 = (double)(f->b1 * (float)n) - fu32, j0 = (double)(f->b2 * (float)n) - fv32;
+    const double fu = q[1] / S * n - i0, fv = q[2] / S * n - j0;
+    w[0] = inv ? fu + fv - 1.0 : 1.0 - fu - fv;
+    w[1] = inv ? 1.0 - fv : fu;
+    w[2] = inv ? 1.0 - fu : fv;
+    for (int ch = 0; ch < PCH; ++ch)
+        feat[ch] = w[0] * tt[(size_t)idx[0] * PCH + ch] + w[1] * tt[(size_t)idx[1] * PCH + ch] +
+                   w[2] * tt[(size_t)idx[2] * PCH + ch];
+    const float* Mi = P->Minv;
+    const double nx = (2.0 * x + 1.0) / c->v->W - 1.0, ny = 1.0 - (2.0 * y + 1.0) / c->v->H;
+    double pr[2][4], d[3], len = 0;
+    for (int e = 0; e < 2; ++e)
+        for (int r = 0; r < 4; ++r)
+            pr[e][r] = Mi[r * 4 + 3] + Mi[r * 4] * nx + Mi[r * 4 + 1] * ny + Mi[r * 4 + 2] * (e ? 1.0 : -1.0);
+    for (int k = 0; k < 3; ++k) { d[k] = pr[1][k] / pr[1][3] - pr[0][k] / pr[0][3]; len += d[k] * d[k]; }
+    len = sqrt(len);
+    for (int k = 0; k < 3; ++k) d[k] /= len;
+    double* in = act[0];
+    for (int k = 0; k < PFEAT; ++k) in[k] = feat[k];
+    sh2_d(d, in + PFEAT);
+    const int din[3] = {PIN, PHID, PHID}, dout[3] = {PHID, PHID, 3};
+    const float* p = P->mlp;
+    for (int l = 0; l < 3; ++l) {
+        for (int j = 0; j < dout[l]; ++j) {
+            double h = p[dout[l] * din[l] + j];
+            for (int k = 0; k < din[l]; ++k) h += (double)p[j * din[l] + k] * act[l][k];
+            act[l + 1][j] = l < 2 ? (h > 0 ? h : 0) : h;
+        }
+        p += dout[l] * din[l] + dout[l];
+    }
+}
+
+/* Algorithm A1, part 2, for one pixel of the paper form.
+ * (a) colour of the winner: out = A RGB + (1 - A) m, m = sigmoid(MLP logits):
+ *     d RGB = A gC, d A = gC . (RGB - m), d m = (1 - A) gC, back through the
+ *     sigmoid and the MLP (its ReLU gates those of the float32 forward) to the
+ *     7 features; the features' gradient goes to the 3 grid vertices of the
+ *     micro-triangle (weights w) and, through the interpolation's derivative
+ *     along (b1, b2), to the vertices of the triangle.
+ * (b) score term (Eq. (9)): the winner's opacity d alpha = g_L / alpha, each
+ *     fragment in front d alpha = -g_L / (1 - alpha) (alpha is the texture
+ *     value itself, no sigmoid here); to the opacity channel of the 3 grid
+ *     vertices, no vertex motion (Section 3.2). */
+static void ppixel_backward(const view_ctx* c, const pctx* P, int x, int y, const frag_buf* b, uint64_t key_star,
+                            const double gC[3], double gL, double* g_tex, double* g_mlp, grad_out* go)
+{
+    for (int i = 0; i < b->n; ++i) {
+        const frag_t* f = &b->f[i];
+        if (f->key > key_star) break;
+        const float a = palpha(P, f);
+        int idx[3], inv;
+        float w[3], fu, fv;
+        mc_lookup(P->n, f->b1, f->b2, idx, w, &fu, &fv, &inv);
+        double* gt = g_tex + (size_t)f->tri * P->V * PCH;
+        if (f->key == key_star) {
+            if (c->o->mode == 0 && gL != 0.0)
+                for (int k = 0; k < 3; ++k) atomic_add(&gt[(size_t)idx[k] * PCH + PFEAT], (double)w[k] * gL / (double)a);
+            if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0) break;
+            double feat[PCH], act[4][PHID], wd[3];
+            pshade_d(c, P, f, x, y, idx, inv, fu, fv, feat, act, wd);
+            const double A = feat[3];
+            double dfeat[PFEAT] = {0, 0, 0, 0, 0, 0, 0};
+            double delta[PHID], prev[PHID];
+            double dA = 0;
+            for (int k = 0; k < 3; ++k) {
+                const double m = 1.0 / (1.0 + exp(-act[3][k]));
+                dfeat[k] += A * gC[k];
+                dA += gC[k] * (feat[k] - m);
+                delta[k] = (1.0 - A) * gC[k] * m * (1.0 - m);
+            }
+            dfeat[3] += dA;
+            /* MLP backward (parameter offsets per layer) */
+            const int din[3] = {PIN, PHID, PHID}, dout[3] = {PHID, PHID, 3};
+            int off[3] = {0, 0, 0};
+            for (int l = 1; l < 3; ++l) off[l] = off[l - 1] + dout[l - 1] * din[l - 1] + dout[l - 1];
+            for (int l = 2; l >= 0; --l) {
+                const float* Wl = P->mlp + off[l];
+                double* gW = g_mlp + off[l];
+                double* gb = gW + dout[l] * din[l];
+                for (int j = 0; j < dout[l]; ++j) {
+                    if (delta[j] == 0.0) continue;
+                    atomic_add(&gb[j], delta[j]);
+                    for (int k = 0; k < din[l]; ++k)
+                        if (act[l][k] != 0.0) atomic_add(&gW[j * din[l] + k], delta[j] * act[l][k]);
+                }
+                for (int k = 0; k < din[l]; ++k) {
+                    double acc = 0;
+                    for (int j = 0; j < dout[l]; ++j) acc += (double)Wl[j * din[l] + k] * delta[j];
+                    if (l > 0 && !(act[l][k] > 0.0)) acc = 0;
+                    prev[k] = acc;
+                }
+                memcpy(delta, prev, sizeof(double) * (size_t)din[l]);
+            }
+            for (int k = 0; k < PFEAT; ++k) dfeat[k] += delta[k];   /* the harmonics have no parameters */
+            /* features -> grid vertices, and along (b1, b2) -> triangle vertices */
+            const float* tt = P->tex + (size_t)f->tri * P->V * PCH;
+            double dfu = 0, dfv = 0;
+            for (int k = 0; k < PFEAT; ++k) {
+                for (int q = 0; q < 3; ++q) atomic_add(&gt[(size_t)idx[q] * PCH + k], wd[q] * dfeat[k]);
+                const double t0 = tt[(size_t)idx[0] * PCH + k], t1 = tt[(size_t)idx[1] * PCH + k],
+                             t2 = tt[(size_t)idx[2] * PCH + k];
+                /* upright: w = (1 - fu - fv, fu, fv); inverted: w = (fu + fv - 1, 1 - fv, 1 - fu) */
+                dfu += dfeat[k] * (inv ? t0 - t2 : t1 - t0);
+                dfv += dfeat[k] * (inv ? t0 - t1 : t2 - t0);
+            }
+            push_bary(c, f, x, y, dfu * P->n, dfv * P->n, go);
+            break;
+        }
+        if (c->o->mode != 0 || gL == 0.0) continue;
+        for (int k = 0; k < 3; ++k)
+            atomic_add(&gt[(size_t)idx[k] * PCH + PFEAT], -(double)w[k] * gL / (1.0 - (double)a));
+    }
+}
+
+int orc_pbackward(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
+                  const uint64_t* vis, const float* color, const float* grad_color, const float* grad_logp,
+                  double* g_verts, double* g_tex, double* g_mlp)
+{
+    if (!pscene_ok(s) || !Minv) return -1;
+    int32_t dims[2];
+    orc_scene g = pgeom(s, dims);
+    view_ctx c;
+    if (ctx_init(&c, &g, v, o, 1) != 0) return -1;
+    pctx P = {s->tex, s->mlp, Minv, s->R, 1 << s->R, orc_mc_count(s->R)};
+    grad_out go;
+    go.g_verts_screen = (double*)calloc((size_t)(s->T > 0 ? s->T : 1) * 9, sizeof(double));
+    go.g_feats = NULL;
+    go.g_mlp = NULL;
+    const int W = v->W, H = v->H;
+    #pragma omp parallel
+    {
+        frag_buf b = {0};
+        #pragma omp for schedule(dynamic, 4)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t p = (size_t)y * W + x;
+                double gC[3] = {grad_color[3 * p], grad_color[3 * p + 1], grad_color[3 * p + 2]};
+                double gL = grad_logp ? grad_logp[p] : 0.0;
+                if (gC[0] == 0 && gC[1] == 0 && gC[2] == 0 && gL == 0) continue;
+                pixel_fragments(&c, x, y, &b);
+                ppixel_backward(&c, &P, x, y, &b, vis[p], gC, gL, g_tex, g_mlp, &go);
+            }
+        free(b.f);
+        #pragma omp for schedule(dynamic, 4)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t a = (size_t)y * W + x;
+                double ga[3] = {grad_color[3 * a], grad_color[3 * a + 1], grad_color[3 * a + 2]};
+                if (x + 1 < W) {
+                    size_t q = a + 1;
+                    double gb[3] = {grad_color[3 * q], grad_color[3 * q + 1], grad_color[3 * q + 2]};
+                    pair_edge(&c, x, y, x + 1, y, vis[a], vis[q], color + 3 * a, color + 3 * q, ga, gb, &go);
+                }
+                if (y + 1 < H) {
+                    size_t q = a + (size_t)W;
+                    double gb[3] = {grad_color[3 * q], grad_color[3 * q + 1], grad_color[3 * q + 2]};
+                    pair_edge(&c, x, y, x, y + 1, vis[a], vis[q], color + 3 * a, color + 3 * q, ga, gb, &go);
+                }
+            }
+    }
+    vertex_chain(&c, go.g_verts_screen, g_verts);
+    free(go.g_verts_screen);
+    ctx_free(&c);
+    return 0;
+}
+
+/* float64, unsnapped colour and opacity of triangle tri at the centre of
+ * pixel (x, y), ignoring visibility (the paper form's counterpart of
+ * orc_color_f64, for finite differences): geometry from the exact clip
+ * coordinates, the micro-triangle chosen at that point, harmonics and MLP in
+ * double. Returns 0 if the triangle's setup culls it. */
+int orc_pcolor_f64(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
+                   int32_t tri, int32_t x, int32_t y, double* rgb, double* alpha)
+{
+    if (!pscene_ok(s) || !Minv || tri < 0 || tri >= s->T) return -1;
+    int32_t dims[2];
+    orc_scene g = pgeom(s, dims);
+    tri_setup t;
+    setup_triangle(&g, v, o, tri, &t);
+    if (!t.sgn) return 0;
+    const float* M = v->M;
+    double vx[3], vy[3], iw[3];
+    for (int i = 0; i < 3; ++i) {
+        const float* p = s->verts + ((size_t)tri * 3 + i) * 3;
+        double cc[4];
+        for (int j = 0; j < 4; ++j)
+            cc[j] = (double)M[j * 4 + 3] + (double)M[j * 4] * p[0] + (double)M[j * 4 + 1] * p[1] +
+                    (double)M[j * 4 + 2] * p[2];
+        iw[i] = 1.0 / cc[3];
+        vx[i] = 0.5 * v->W * (cc[0] * iw[i]) + 0.5 * v->W;
+        vy[i] = 0.5 * v->H - 0.5 * v->H * (cc[1] * iw[i]);
+    }
+    const double px = x + 0.5, py = y + 0.5;
+    const double a = edge_d(vx[0], vy[0], vx[1], vy[1], vx[2], vy[2]);
+    double tt[3], S = 0;
+    for (int i = 0; i < 3; ++i) {
+        const int p = (i + 1) % 3, q = (i + 2) % 3;
+        tt[i] = edge_d(vx[p], vy[p], vx[q], vy[q], px, py) / a * iw[i];
+        S += tt[i];
+    }
+    const int n = 1 << s->R, V = orc_mc_count(s->R);
+    const double u = tt[1] / S * n, vv = tt[2] / S * n;
+    int i = (int)floor(u);
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    int j = (int)floor(vv);
+    if (j < 0) j = 0;
+    if (j > n - 1 - i) j = n - 1 - i;
+    const double fu = u - i, fv = vv - j;
+    int idx[3];
+    double w[3];
+    if (fu + fv > 1.0 && i + j <= n - 2) {
+        idx[0] = mc_index(n, i + 1, j + 1); idx[1] = mc_index(n, i + 1, j); idx[2] = mc_index(n, i, j + 1);
+        w[0] = fu + fv - 1.0; w[1] = 1.0 - fv; w[2] = 1.0 - fu;
+    } else {
+        idx[0] = mc_index(n, i, j); idx[1] = mc_index(n, i + 1, j); idx[2] = mc_index(n, i, j + 1);
+        w[0] = 1.0 - fu - fv; w[1] = fu; w[2] = fv;
+    }
+    const float* tx = s->tex + (size_t)tri * V * PCH;
+    double feat[PCH];
+    for (int ch = 0; ch < PCH; ++ch)
+        feat[ch] = w[0] * tx[(size_t)idx[0] * PCH + ch] + w[1] * tx[(size_t)idx[1] * PCH + ch] +
+                   w[2] * tx[(size_t)idx[2] * PCH + ch];
+    /* view direction and harmonics in double */
+    double pr[2][4];
+    const double nx = (2.0 * x + 1.0) / v->W - 1.0, ny = 1.0 - (2.0 * y + 1.0) / v->H;
+    for (int e = 0; e < 2; ++e)
+        for (int r = 0; r < 4; ++r)
+            pr[e][r] = Minv[r * 4 + 3] + Minv[r * 4] * nx + Minv[r * 4 + 1] * ny + Minv[r * 4 + 2] * (e ? 1.0 : -1.0);
+    double d[3], len = 0;
+    for (int k = 0; k < 3; ++k) { d[k] = pr[1][k] / pr[1][3] - pr[0][k] / pr[0][3]; len += d[k] * d[k]; }
+    len = sqrt(len);
+    for (int k = 0; k < 3; ++k) d[k] /= len;
+    double in[PIN];
+    for (int k = 0; k < PFEAT; ++k) in[k] = feat[k];
+    sh2_d(d, in + PFEAT);
+    double h[3][PHID];
+    const float* p = s->mlp;
+    const int din[3] = {PIN, PHID, PHID}, dout[3] = {PHID, PHID, 3};
+    const double* src = in;
+    for (int l = 0; l < 3; ++l) {
+        for (int jj = 0; jj < dout[l]; ++jj) {
+            double acc = p[dout[l] * din[l] + jj];
+            for (int k = 0; k < din[l]; ++k) acc += (double)p[jj * din[l] + k] * src[k];
+            h[l][jj] = l < 2 ? (acc > 0 ? acc : 0) : acc;
+        }
+        src = h[l];
+        p += dout[l] * din[l] + dout[l];
+    }
+    const double A = feat[3];
+    for (int k = 0; k < 3; ++k) {
+        const double m = 1.0 / (1.0 + exp(-h[2][k]));
+        rgb[k] = A * feat[k] + (1.0 - A) * m;
+    }
+    *alpha = feat[PFEAT];
+    return 1;
+}

@@ -105,6 +105,46 @@ int orc_pixel_fragments(const orc_scene* s, const orc_view* v, const orc_opts* o
 int orc_color_f64(const orc_scene* s, const orc_view* v, const orc_opts* o,
                   int32_t tri, int32_t x, int32_t y, double* rgb, double* alpha);
 
+/* ------------------------------------------------------------------------- */
+/* Paper form (Section 3.3; Supplement B.3, B.6): multi-resolution mesh-colour */
+/* texture, opacity outside the MLP, deferred MLP with spherical harmonics.   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t T;
+    int32_t R;                /* finest texture level: n = 2^R segments per edge */
+    const float* verts;       /* [T,3,3] */
+    const float* tex;         /* [T, V(R), 8]: 7 colour features, then the opacity, in [0,1] */
+    const float* mlp;         /* W0[16][16], b0[16], W1[16][16], b1[16], W2[3][16], b2[3] */
+} orc_pscene;
+
+/* Grid vertices of level R: (2^(R-1) + 1)(2^R + 1) = (n + 1)(n + 2) / 2. */
+int orc_mc_count(int R);
+/* The contract lookup: grid vertices (row-major indices) and weights of the
+ * micro-triangle of level R containing perspective-correct barycentrics (b1, b2). */
+int orc_mc_lookup(int R, float b1, float b2, int32_t idx[3], float w[3]);
+/* tex [T, V(Rmax), 8] = sigmoid(sum of the learnable levels Rmin..Rtop
+ * (Rtop <= Rmax) sampled at the level-Rmax grid's vertices);
+ * raw[l] = [T, V(Rmin + l), 8]. */
+int orc_mc_assemble(int T, int Rmin, int Rtop, int Rmax, const float* const* raw, float* tex);
+/* Adds d loss / d raw[l] (float64) given tex and d loss / d tex. */
+int orc_mc_assemble_bwd(int T, int Rmin, int Rtop, int Rmax, const float* tex, const float* grad_tex,
+                        double* const* grad_raw);
+/* The 9 real spherical harmonics of degree <= 2 of a unit vector (float32). */
+void orc_sh2(const float d[3], float out[9]);
+int orc_pmlp_params(void);
+/* Unit view direction through the centre of pixel (x, y) (float32). */
+int orc_view_dir(const orc_view* v, const float* Minv, int32_t x, int32_t y, float d[3]);
+/* Forward / backward of the paper form; Minv = this view's inverse
+ * view-projection [4,4] (row-major). Gradients are ADDED (g_tex [T,V,8]). */
+int orc_pforward(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
+                 uint64_t* vis, float* color, double* logp, orc_stats* st);
+int orc_pbackward(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
+                  const uint64_t* vis, const float* color, const float* grad_color, const float* grad_logp,
+                  double* g_verts, double* g_tex, double* g_mlp);
+int orc_pcolor_f64(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
+                   int32_t tri, int32_t x, int32_t y, double* rgb, double* alpha);
+
 /* Contract pieces, exposed for their own tests. */
 float orc_exp(float x);
 float orc_sigmoid(float x);

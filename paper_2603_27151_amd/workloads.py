@@ -302,6 +302,78 @@ def serving_requests(rate_hz: float, duration_s: float, seed: int = 1004_1) -> L
     return out
 
 
+# ---------------------------------------------------------------------------
+# paper form: mesh-colour texture levels and the deferred-shading MLP
+# ---------------------------------------------------------------------------
+
+PF_MLP_DIMS = [16, 16, 16, 3]       # 7 features + 9 harmonics -> 16 -> 16 -> RGB
+PF_CHANNELS = 8                     # 7 colour features, then the opacity
+
+
+def mc_vertices(R: int) -> int:
+    """Grid vertices of a level-R mesh-colour grid (n = 2^R segments per edge)."""
+    n = 1 << R
+    return (n + 1) * (n + 2) // 2
+
+
+def inv_view_proj(M: np.ndarray) -> np.ndarray:
+    """The inverse of a float32 view-projection matrix, taken in float64 and
+    rounded once to float32 (an input of the deferred shading)."""
+    return np.linalg.inv(np.asarray(M, np.float64)).astype(np.float32)
+
+
+@dataclasses.dataclass
+class PScene:
+    """A paper-form scene: per-triangle activated texture tex [T, V(R), 8] in
+    [0, 1] (grid vertex (i, j) of the level-R grid at row-major index
+    j (n + 1) - j (j - 1) / 2 + i) and the shading MLP's flat parameters."""
+    verts: np.ndarray          # float32 [T,3,3]
+    tex: np.ndarray            # float32 [T,V(R),8]
+    mlp: np.ndarray            # float32 [P]
+    R: int
+
+    @property
+    def T(self) -> int:
+        return int(self.verts.shape[0])
+
+
+@dataclasses.dataclass
+class PLevels:
+    """The learnable texture levels Rmin..Rtop ([T, V(level), 8] each, before
+    the sigmoid) accumulated on the level-Rmax grid."""
+    raw: List[np.ndarray]
+    Rmin: int
+    Rmax: int
+
+    @property
+    def Rtop(self) -> int:
+        return self.Rmin + len(self.raw) - 1
+
+
+def random_pscene(rng, verts, R: int = 5, lo: float = 0.05, hi: float = 0.95) -> PScene:
+    """Activated texture values U[lo, hi] per grid vertex and channel, Glorot
+    MLP with small random biases."""
+    T = verts.shape[0]
+    tex = rng.uniform(lo, hi, (T, mc_vertices(R), PF_CHANNELS)).astype(np.float32)
+    mlp = glorot_mlp(rng, PF_MLP_DIMS)
+    nW = [o * i for i, o in zip(PF_MLP_DIMS[:-1], PF_MLP_DIMS[1:])]
+    at = 0
+    for l, w in enumerate(nW):
+        at += w
+        o = PF_MLP_DIMS[l + 1]
+        mlp[at:at + o] = rng.normal(0.0, 0.1, o)
+        at += o
+    return PScene(np.ascontiguousarray(verts, np.float32), tex, mlp, R)
+
+
+def random_levels(rng, T: int, Rmin: int, Rtop: int, Rmax: int, sd: float = 0.5) -> PLevels:
+    """Raw texture levels N(0, sd^2) (the paper starts them at zero; random
+    values make every level's contribution visible)."""
+    raw = [rng.normal(0.0, sd, (T, mc_vertices(R), PF_CHANNELS)).astype(np.float32)
+           for R in range(Rmin, Rtop + 1)]
+    return PLevels(raw, Rmin, Rmax)
+
+
 def by_name(name: str, **kw) -> Workload:
     return {"tiny": tiny, "single": single, "batched": batched, "large": large}[name](**kw)
 
