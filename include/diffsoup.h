@@ -138,7 +138,9 @@ enum {
     SOUP_T_APPLY = 16,   /* adaptive control: applying a plan */
     SOUP_T_TLOSS = 17,   /* L1 + SSIM loss */
     SOUP_T_ADAM = 18,    /* optimiser steps */
-    SOUP_TIMING_KINDS = 19
+    SOUP_T_SHADE = 19,   /* paper form: deferred shading of the winners */
+    SOUP_T_ASSEMBLE = 20, /* paper form: texture assembly and its gradient */
+    SOUP_TIMING_KINDS = 21
 };
 soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
 soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);
@@ -293,6 +295,93 @@ soup_status soup_adaptive_plan(soup_ctx* ctx, const uint32_t* counts, const floa
 soup_status soup_adaptive_apply(soup_ctx* ctx, const soup_scene* scene, const int32_t* actions,
                                 const int32_t* offsets, int32_t n_new, float* verts_out, float* feats_out,
                                 void* stream);
+
+/*
+ * Paper form of the step (Section 3.3, "Learnable multi-resolution triangle
+ * texture" and "Neural deferred shading"; Supplement B.3 and B.6).
+ *
+ * Texture: per triangle the level-R mesh-colour grid: n = 2^R segments per
+ * edge, grid vertex (i, j), i + j <= n, at perspective-correct barycentrics
+ * (b1, b2) = (i/n, j/n), V(R) = (n + 1)(n + 2)/2 vertices (561 at R = 5)
+ * stored row-major: vertex (i, j) at index j (n + 1) - j (j - 1)/2 + i. Each
+ * vertex holds 8 floats (32 bytes): 7 colour features, then the opacity, all
+ * in [0, 1] (after the sigmoid). A fragment's values are interpolated
+ * linearly in the micro-triangle that contains it: u = b1 n, v = b2 n,
+ * i = floor(u) in [0, n-1], j = floor(v) in [0, n-1-i], fu = u - i,
+ * fv = v - j; if fu + fv > 1 and i + j <= n - 2, the vertices (i+1, j+1),
+ * (i+1, j), (i, j+1) with weights (fu + fv - 1, 1 - fv, 1 - fu), else
+ * (i, j), (i+1, j), (i, j+1) with ((1 - fu) - fv, fu, fv).
+ * Mask: the opacity alpha of a fragment is channel 7 (no MLP); the draws and
+ * the winner are those of soup_rasterize_fwd (mode 1: alpha > 1/2).
+ * Colour (deferred, winners only): input = the 7 features and the 9 real
+ * spherical harmonics of degree <= 2 of the pixel's view direction (order
+ * Y00; Y1: y, z, x; Y2: xy, yz, 2z^2 - x^2 - y^2, xz, x^2 - y^2, orthonormal,
+ * no Condon-Shortley sign); MLP 16 -> 16 -> 16 -> 3, ReLU hidden layers,
+ * sigmoid outputs m; features 0..3 read as RGBA: colour = A RGB + (1 - A) m.
+ * The view direction of pixel (x, y) is normalize(P(+1) - P(-1)) with P(z)
+ * the point of normalised device coordinates ((2x + 1)/W - 1, 1 - (2y + 1)/H,
+ * z) through the view's inverse view-projection (divided by w).
+ */
+typedef struct {
+    int32_t T;                 /* triangles, >= 0 */
+    int32_t R;                 /* texture level, 0..7 */
+    const float* verts;        /* device [T,3,3] world positions */
+    const float* tex;          /* device [T,V(R),8], 16-byte aligned */
+    const float* mlp;          /* device [595]: W0[16][16], b0[16], W1[16][16], b1[16], W2[3][16], b2[3]
+                                  (W[out][in] row-major) */
+} soup_pscene;
+
+/*
+ * Paper-form forward (Eq. (1), (2), (5) with the texture's opacity; the
+ * deferred colour). inv_view_proj: host [V,4,4] row-major, the inverse of
+ * each view's view_proj (the caller's, used as given). Outputs as in
+ * soup_rasterize_fwd: vis [P] (bit-identical to an evaluation of the same
+ * float32 operations), color [P,3], logp [P] or NULL. With opts->reuse_bins
+ * (or logp in mode 0) the call keeps a log of its opacity decodes for
+ * soup_pbackward / the logp pass. Synchronises the stream as
+ * soup_rasterize_fwd does.
+ */
+soup_status soup_pforward(soup_ctx* ctx, const soup_pscene* scene, const soup_views* views,
+                          const float* inv_view_proj, const soup_opts* opts, uint64_t* vis, float* color,
+                          float* logp, void* stream);
+
+/*
+ * Paper-form backward (Algorithm A1, part 2; Eq. (8), (9); the edge term of
+ * Section 3.2). Inputs as in soup_rasterize_bwd. Outputs (device):
+ * grad_verts [T,3,3], grad_tex [T,V(R),8], grad_mlp [595]; overwritten, or
+ * added into when opts->accumulate is 1.
+ *   winner f*:   colour path (d colour / d RGB = A, d / d A = RGB - m, the
+ *                MLP backward to the 7 features), onto the micro-triangle's
+ *                3 grid vertices with its weights, and through (b1, b2) to
+ *                the vertices; score g_L / alpha* on its opacity channel;
+ *   f in front:  score -g_L / (1 - alpha_f) on its opacity channel;
+ *   the score term moves no vertex; the edge term as in soup_rasterize_bwd.
+ * Floating-point sums use atomics (order-dependent, about 1e-6 relative).
+ */
+soup_status soup_pbackward(soup_ctx* ctx, const soup_pscene* scene, const soup_views* views,
+                           const float* inv_view_proj, const soup_opts* opts, const uint64_t* vis,
+                           const float* color, const float* grad_color, const float* grad_logp,
+                           float* grad_verts, float* grad_tex, float* grad_mlp, void* stream);
+
+/*
+ * Multi-resolution texture assembly (Section 3.3): the learnable grids of
+ * levels Rmin..Rtop (raw: host array of Rtop - Rmin + 1 device pointers,
+ * level Rmin + l at raw[l], [T,V(Rmin + l),8], before the sigmoid) are each
+ * sampled at the vertices of the level-Rmax grid by the micro-triangle
+ * lookup, summed (Rmin first) and passed through the sigmoid:
+ * tex [T,V(Rmax),8] (device, overwritten). 0 <= Rmin <= Rtop <= Rmax <= 7.
+ * The paper keeps grids up to Rmax - 1 (Rtop = Rmax - 1); Rtop = Rmax makes
+ * the finest grid learnable as well. Buffers 16-byte aligned.
+ */
+soup_status soup_mc_assemble(soup_ctx* ctx, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax,
+                             const float* const* raw, float* tex, void* stream);
+
+/* Gradient of soup_mc_assemble: grad_raw[l] (device, [T,V(Rmin + l),8])
+ * receives the sum over the level-Rmax vertices of the lookup weight times
+ * tex (1 - tex) grad_tex; overwritten, or added into when accumulate is 1. */
+soup_status soup_mc_assemble_bwd(soup_ctx* ctx, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax,
+                                 const float* tex, const float* grad_tex, float* const* grad_raw,
+                                 int32_t accumulate, void* stream);
 
 /*
  * Photometric loss of training (Section 3.4, "Loss function"):

@@ -82,6 +82,8 @@ def lib():
         L.orc_view_dir.argtypes = [P, P, C.c_int32, C.c_int32, P]
         L.orc_pforward.argtypes = [P, P, P, P, P, P, P, P]
         L.orc_pbackward.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_pforward_pixels.argtypes = [P, P, P, P, C.c_int64, P, P, P, P]
+        L.orc_pbackward_pixels.argtypes = [P, P, P, P, C.c_int64, P, P, P, P, P, P]
         L.orc_pcolor_f64.argtypes = [P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P]
         _lib = L
     return _lib
@@ -375,6 +377,34 @@ def pbackward(ps, view, minv, opts: Opts, vis, color, grad_color, grad_logp=None
                              _ptr(gv), _ptr(gt), _ptr(gm))
     if rc != 0:
         raise ValueError("oracle pbackward rejected its arguments")
+    return gv.reshape(T, 3, 3), gt.reshape(T, V, N_PCH), gm
+
+
+def pforward_pixels(ps, view, minv, opts: Opts, xy):
+    k = _PKeep(ps, view, minv, opts)
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    vis = np.empty(n, np.uint64)
+    color = np.empty(n * 3, np.float32)
+    logp = np.empty(n, np.float64)
+    if lib().orc_pforward_pixels(*k.args(), n, _ptr(xy), _ptr(vis), _ptr(color), _ptr(logp)) != 0:
+        raise ValueError("oracle pforward_pixels rejected its arguments")
+    return vis, color.reshape(n, 3), logp
+
+
+def pbackward_pixels(ps, view, minv, opts: Opts, xy, grad_color, grad_logp=None):
+    k = _PKeep(ps, view, minv, opts)
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    T, V = k.tex.shape[0], k.tex.shape[1]
+    gv = np.zeros(T * 9, np.float64)
+    gt = np.zeros(T * V * N_PCH, np.float64)
+    gm = np.zeros(pmlp_params(), np.float64)
+    gc = np.ascontiguousarray(grad_color, dtype=np.float32).reshape(-1)
+    gl = None if grad_logp is None else np.ascontiguousarray(grad_logp, dtype=np.float32).reshape(-1)
+    if lib().orc_pbackward_pixels(*k.args(), n, _ptr(xy), _ptr(gc), _ptr(gl) if gl is not None else None,
+                                  _ptr(gv), _ptr(gt), _ptr(gm)) != 0:
+        raise ValueError("oracle pbackward_pixels rejected its arguments")
     return gv.reshape(T, 3, 3), gt.reshape(T, V, N_PCH), gm
 
 

@@ -1807,3 +1807,144 @@ int orc_pcolor_f64(const orc_pscene* s, const orc_view* v, const float* Minv, co
     *alpha = feat[PFEAT];
     return 1;
 }
+
+/* The paper form's forward at a list of pixels (x, y) of one view: vis,
+ * colour and log p of each (as orc_pforward computes them). */
+int orc_pforward_pixels(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o, int64_t n,
+                        const int32_t* xy, uint64_t* vis, float* color, double* logp)
+{
+    if (!pscene_ok(s) || !Minv) return -1;
+    int32_t dims[2];
+    orc_scene g = pgeom(s, dims);
+    view_ctx c;
+    if (ctx_init(&c, &g, v, o, 0) != 0) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (xy[2 * i] < 0 || xy[2 * i] >= v->W || xy[2 * i + 1] < 0 || xy[2 * i + 1] >= v->H) {
+            ctx_free(&c);
+            return -1;
+        }
+    pctx P = {s->tex, s->mlp, Minv, s->R, 1 << s->R, orc_mc_count(s->R)};
+    #pragma omp parallel
+    {
+        frag_buf b = {0};
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < n; ++i) {
+            const int x = xy[2 * i], y = xy[2 * i + 1];
+            pixel_fragments(&c, x, y, &b);
+            pixel_result r;
+            ppixel_forward(&c, &P, x, y, &b, &r);
+            vis[i] = r.key;
+            for (int k = 0; k < 3; ++k) color[3 * i + k] = r.rgb[k];
+            if (logp) logp[i] = r.logp;
+        }
+        free(b.f);
+    }
+    ctx_free(&c);
+    return 0;
+}
+
+/* The paper form's backward of the loss terms of a list of distinct pixels
+ * (grad_color [n,3], grad_logp [n] or NULL, in list order; every other
+ * pixel's gradients are zero): their colour and score paths, and the edge
+ * pairs that touch a listed pixel. Gradients are ADDED. */
+int orc_pbackward_pixels(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o, int64_t n,
+                         const int32_t* xy, const float* grad_color, const float* grad_logp, double* g_verts,
+                         double* g_tex, double* g_mlp)
+{
+    if (!pscene_ok(s) || !Minv) return -1;
+    int32_t dims[2];
+    orc_scene g = pgeom(s, dims);
+    view_ctx c;
+    if (ctx_init(&c, &g, v, o, 0) != 0) return -1;
+    const int W = v->W, H = v->H;
+    pctx P = {s->tex, s->mlp, Minv, s->R, 1 << s->R, orc_mc_count(s->R)};
+    /* the listed pixels' linear indices, sorted, with their list positions */
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * (n > 0 ? n : 1)));
+    for (int64_t i = 0; i < n; ++i) {
+        const int x = xy[2 * i], y = xy[2 * i + 1];
+        if (x < 0 || x >= W || y < 0 || y >= H) { free(idx); ctx_free(&c); return -1; }
+        idx[2 * i] = (int64_t)y * W + x;
+        idx[2 * i + 1] = i;
+    }
+    qsort(idx, (size_t)n, 2 * sizeof(int64_t), cmp_i64);
+    for (int64_t i = 1; i < n; ++i)
+        if (idx[2 * i] == idx[2 * i - 2]) { free(idx); ctx_free(&c); return -1; }
+    /* every pixel that takes part: the listed ones and their 4 neighbours */
+    int64_t m = 0;
+    int64_t* all = (int64_t*)malloc(sizeof(int64_t) * (size_t)(5 * (n > 0 ? n : 1)));
+    static const int nb[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 5; ++k) {
+            const int x = xy[2 * i] + nb[k][0], y = xy[2 * i + 1] + nb[k][1];
+            if (x >= 0 && x < W && y >= 0 && y < H) all[m++] = (int64_t)y * W + x;
+        }
+    qsort(all, (size_t)m, sizeof(int64_t), cmp_i64);
+    int64_t u = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (u == 0 || all[i] != all[u - 1]) all[u++] = all[i];
+    m = u;
+    uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+    float* col = (float*)malloc(sizeof(float) * 3 * (size_t)(m > 0 ? m : 1));
+    int64_t* pos_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t lo = 0, hi = n - 1;
+        pos_of[i] = -1;
+        while (lo <= hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (idx[2 * mid] == all[i]) { pos_of[i] = idx[2 * mid + 1]; break; }
+            if (idx[2 * mid] < all[i]) lo = mid + 1; else hi = mid - 1;
+        }
+    }
+    grad_out go;
+    go.g_verts_screen = (double*)calloc((size_t)(s->T > 0 ? s->T : 1) * 9, sizeof(double));
+    go.g_feats = NULL;
+    go.g_mlp = NULL;
+    #pragma omp parallel
+    {
+        frag_buf b = {0};
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < m; ++i) {
+            const int x = (int)(all[i] % W), y = (int)(all[i] / W);
+            pixel_fragments(&c, x, y, &b);
+            pixel_result r;
+            ppixel_forward(&c, &P, x, y, &b, &r);
+            key[i] = r.key;
+            for (int k = 0; k < 3; ++k) col[3 * i + k] = r.rgb[k];
+            const int64_t pos = pos_of[i];
+            if (pos >= 0) {
+                const double gC[3] = {grad_color[3 * pos], grad_color[3 * pos + 1], grad_color[3 * pos + 2]};
+                const double gL = grad_logp ? grad_logp[pos] : 0.0;
+                if (gC[0] != 0 || gC[1] != 0 || gC[2] != 0 || gL != 0)
+                    ppixel_backward(&c, &P, x, y, &b, r.key, gC, gL, g_tex, g_mlp, &go);
+            }
+        }
+        free(b.f);
+    }
+    /* edge pairs (a, b = a + e) with a listed pixel among them, each once */
+    for (int64_t i = 0; i < m; ++i) {
+        const int x = (int)(all[i] % W), y = (int)(all[i] / W);
+        for (int dir = 0; dir < 2; ++dir) {
+            const int xb = x + (dir == 0), yb = y + (dir == 1);
+            if (xb >= W || yb >= H) continue;
+            const int64_t lb = (int64_t)yb * W + xb;
+            int64_t lo = 0, hi = m - 1, jb = -1;
+            while (lo <= hi) {
+                const int64_t mid = (lo + hi) / 2;
+                if (all[mid] == lb) { jb = mid; break; }
+                if (all[mid] < lb) lo = mid + 1; else hi = mid - 1;
+            }
+            if (jb < 0 || (pos_of[i] < 0 && pos_of[jb] < 0)) continue;
+            double ga[3] = {0, 0, 0}, gb[3] = {0, 0, 0};
+            for (int k = 0; k < 3; ++k) {
+                if (pos_of[i] >= 0) ga[k] = grad_color[3 * pos_of[i] + k];
+                if (pos_of[jb] >= 0) gb[k] = grad_color[3 * pos_of[jb] + k];
+            }
+            pair_edge(&c, x, y, xb, yb, key[i], key[jb], col + 3 * i, col + 3 * jb, ga, gb, &go);
+        }
+    }
+    vertex_chain(&c, go.g_verts_screen, g_verts);
+    free(go.g_verts_screen);
+    free(idx); free(all); free(key); free(col); free(pos_of);
+    ctx_free(&c);
+    return 0;
+}

@@ -142,6 +142,13 @@ int orc_pforward(const orc_pscene* s, const orc_view* v, const float* Minv, cons
 int orc_pbackward(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
                   const uint64_t* vis, const float* color, const float* grad_color, const float* grad_logp,
                   double* g_verts, double* g_tex, double* g_mlp);
+/* The same at a list of pixels xy [n,2] of one view (distinct for the
+ * backward, whose grad_color [n,3] and grad_logp [n] belong to them). */
+int orc_pforward_pixels(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o, int64_t n,
+                        const int32_t* xy, uint64_t* vis, float* color, double* logp);
+int orc_pbackward_pixels(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o, int64_t n,
+                         const int32_t* xy, const float* grad_color, const float* grad_logp, double* g_verts,
+                         double* g_tex, double* g_mlp);
 int orc_pcolor_f64(const orc_pscene* s, const orc_view* v, const float* Minv, const orc_opts* o,
                    int32_t tri, int32_t x, int32_t y, double* rgb, double* alpha);
 

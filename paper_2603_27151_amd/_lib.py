@@ -40,6 +40,11 @@ class soup_opts(C.Structure):
                 ("accumulate", C.c_int32), ("reuse_bins", C.c_int32)]
 
 
+class soup_pscene(C.Structure):
+    _fields_ = [("T", C.c_int32), ("R", C.c_int32), ("verts", C.c_void_p), ("tex", C.c_void_p),
+                ("mlp", C.c_void_p)]
+
+
 class soup_stats(C.Structure):
     _fields_ = [("pixels", C.c_int64), ("tiles", C.c_int64), ("bin_entries", C.c_int64),
                 ("visible_tris", C.c_int64), ("decodes", C.c_int64), ("covered_pixels", C.c_int64)]
@@ -50,10 +55,12 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_rasterize_bwd", "soup_render", "soup_loss_l2", "soup_selftest_sigmoid",
            "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings", "soup_ctx_set_static",
            "soup_ctx_check", "soup_coverage_count", "soup_edge_lengths", "soup_adaptive_plan",
-           "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step", "soup_loss_l1_ssim_noalloc"]
+           "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step", "soup_loss_l1_ssim_noalloc",
+           "soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
-                "adaptive_apply", "train_loss", "adam"]
+                "adaptive_apply", "train_loss", "adam", "shade", "assemble"]
+PMLP_PARAMS = 595
 ACT_REMOVE, ACT_KEEP, ACT_SPLIT0 = 0, 1, 2
 PLAN_PRUNE_ZERO, PLAN_FILL = 1, 2
 
@@ -100,6 +107,14 @@ def lib() -> C.CDLL:
     L.soup_loss_l1_ssim_noalloc.argtypes = [P, P, P, C.POINTER(soup_views), C.c_float, P, P, P, P]
     L.soup_adam_step.argtypes = [P, P, P, P, P, C.c_int64, C.c_int32, C.c_float, C.c_double, C.c_double, C.c_float,
                                  C.c_int32, P]
+    L.soup_pforward.argtypes = [P, C.POINTER(soup_pscene), C.POINTER(soup_views), P, C.POINTER(soup_opts),
+                                P, P, P, P]
+    L.soup_pbackward.argtypes = [P, C.POINTER(soup_pscene), C.POINTER(soup_views), P, C.POINTER(soup_opts),
+                                 P, P, P, P, P, P, P, P]
+    L.soup_mc_assemble.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
+    L.soup_mc_assemble_bwd.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_int32, P]
+    for name in ["soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd"]:
+        getattr(L, name).restype = C.c_int
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
                  "soup_selftest_sigmoid", "soup_selftest_uniform", "soup_ctx_set_timing",
@@ -154,6 +169,17 @@ def make_scene(h: _Holder, verts, feats, mlp, dims: Sequence[int]) -> soup_scene
         raise ValueError("verts must be [T,3,3] and feats [T,G,G,C]")
     d = np.asarray(dims, np.int32)
     return soup_scene(T, G, Cc, len(dims) - 1, h.arr(d, C.c_int32), _ptr(verts), _ptr(feats), _ptr(mlp))
+
+
+def make_pscene(verts, tex, mlp, R: int) -> soup_pscene:
+    T = int(verts.shape[0])
+    V = ((1 << R) + 1) * ((1 << R) + 2) // 2
+    for name, t in (("verts", verts), ("tex", tex), ("mlp", mlp)):
+        if not t.is_cuda or t.dtype.itemsize != 4 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(verts.shape[1:]) != (3, 3) or tuple(tex.shape) != (T, V, 8) or mlp.numel() != PMLP_PARAMS:
+        raise ValueError(f"verts must be [T,3,3], tex [T,{V},8] and mlp [{PMLP_PARAMS}]")
+    return soup_pscene(T, int(R), _ptr(verts), _ptr(tex), _ptr(mlp))
 
 
 def make_views(h: _Holder, widths, heights, view_ids, view_proj) -> soup_views:
@@ -324,3 +350,38 @@ def soup_adam_step(ctx: Ctx, p, g, m, v, vec: int, lr: float, beta1: float, beta
                    stream=None):
     ctx.check(lib().soup_adam_step(ctx.p, _ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), int(vec), float(lr),
                                    float(beta1), float(beta2), float(eps), int(t), _stream(stream)))
+
+
+def soup_pforward(ctx: Ctx, scene: soup_pscene, views: soup_views, inv_view_proj, opts: soup_opts, vis, color,
+                  logp=None, stream=None):
+    mi = np.ascontiguousarray(np.asarray(inv_view_proj, np.float32).reshape(-1, 16))
+    if mi.shape[0] != views.V:
+        raise ValueError("inv_view_proj needs one 4x4 matrix per view")
+    ctx.check(lib().soup_pforward(ctx.p, C.byref(scene), C.byref(views), mi.ctypes.data_as(C.c_void_p),
+                                  C.byref(opts), _ptr(vis), _ptr(color), _ptr(logp), _stream(stream)))
+
+
+def soup_pbackward(ctx: Ctx, scene: soup_pscene, views: soup_views, inv_view_proj, opts: soup_opts, vis, color,
+                   grad_color, grad_logp, grad_verts, grad_tex, grad_mlp, stream=None):
+    mi = np.ascontiguousarray(np.asarray(inv_view_proj, np.float32).reshape(-1, 16))
+    if mi.shape[0] != views.V:
+        raise ValueError("inv_view_proj needs one 4x4 matrix per view")
+    ctx.check(lib().soup_pbackward(ctx.p, C.byref(scene), C.byref(views), mi.ctypes.data_as(C.c_void_p),
+                                   C.byref(opts), _ptr(vis), _ptr(color), _ptr(grad_color), _ptr(grad_logp),
+                                   _ptr(grad_verts), _ptr(grad_tex), _ptr(grad_mlp), _stream(stream)))
+
+
+def soup_mc_assemble(ctx: Ctx, raw: Sequence, Rmin: int, Rmax: int, tex, stream=None):
+    """raw: device tensors of the learnable levels Rmin, Rmin + 1, ...; tex [T, V(Rmax), 8]."""
+    ptrs = (C.c_void_p * len(raw))(*[_ptr(r) for r in raw])
+    Rtop = Rmin + len(raw) - 1
+    ctx.check(lib().soup_mc_assemble(ctx.p, int(tex.shape[0]), int(Rmin), Rtop, int(Rmax), ptrs, _ptr(tex),
+                                     _stream(stream)))
+
+
+def soup_mc_assemble_bwd(ctx: Ctx, tex, grad_tex, Rmin: int, Rmax: int, grad_raw: Sequence, accumulate: int = 0,
+                         stream=None):
+    ptrs = (C.c_void_p * len(grad_raw))(*[_ptr(r) for r in grad_raw])
+    Rtop = Rmin + len(grad_raw) - 1
+    ctx.check(lib().soup_mc_assemble_bwd(ctx.p, int(tex.shape[0]), int(Rmin), Rtop, int(Rmax), _ptr(tex),
+                                         _ptr(grad_tex), ptrs, int(accumulate), _stream(stream)))

@@ -11,6 +11,7 @@
 
 #include "../../include/diffsoup.h"
 #include "internal.hpp"
+#include "pform.hpp"
 
 namespace {
 
@@ -54,6 +55,7 @@ struct soup_ctx {
     DevBuf frag_gates, sorted_gates;                  // ReLU gates of the kept and sorted fragments
     bool frags_gated = false;        // the current fragment list carries the forward's gates
     DevBuf ssim;                                      // SSIM statistics of the training loss
+    DevBuf gvert;                                     // the paper form's float64 vertex gradient sums
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
@@ -474,6 +476,37 @@ soup_status plan_single(soup_ctx* c, Plan& p, const soup_scene* scene, const sou
     return SOUP_OK;
 }
 
+soup_status check_pscene(soup_ctx* c, const soup_pscene* s) {
+    if (!s) return fail(c, SOUP_ERR_INVALID, "scene is NULL");
+    if (s->T < 0) return fail(c, SOUP_ERR_INVALID, "scene.T = %d < 0", s->T);
+    if (s->R < 0 || s->R > kPMaxR) return fail(c, SOUP_ERR_INVALID, "scene.R = %d outside [0, %d]", s->R, kPMaxR);
+    if (s->T > 0 && (!s->verts || !s->tex || !s->mlp)) return fail(c, SOUP_ERR_INVALID, "scene device pointers are NULL");
+    return SOUP_OK;
+}
+
+soup_status plan_paper(soup_ctx* c, Plan& p, const soup_pscene* scene, const soup_views* views,
+                       const float* inv_view_proj) {
+    soup_status st;
+    if ((st = check_pscene(c, scene)) || (st = check_views(c, views))) return st;
+    if (!inv_view_proj) return fail(c, SOUP_ERR_INVALID, "inv_view_proj is NULL");
+    SceneDesc sd{};
+    sd.verts = scene->verts;
+    sd.feats = scene->tex;   // the raster reads the opacity channel through the feature pointer
+    sd.mlp = scene->mlp;
+    sd.T = scene->T;
+    p.scenes = {sd};
+    p.G = scene->R;          // ... and the texture level through the grid side
+    p.kind = MlpKind::kPaper;
+    p.n_params = kPParams;
+    std::vector<int> sov(views->V, 0);
+    std::vector<int64_t> rb(views->V);
+    for (int i = 0; i < views->V; ++i) rb[i] = static_cast<int64_t>(i) * scene->T;
+    p.n_recs = static_cast<int64_t>(views->V) * scene->T;
+    plan_views(p, views, c->tile, sov, rb);
+    for (int i = 0; i < views->V; ++i) memcpy(p.views[i].Mi, inv_view_proj + 16 * i, sizeof(p.views[i].Mi));
+    return SOUP_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -553,7 +586,7 @@ void soup_ctx_destroy(soup_ctx* c) {
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
                       &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff, &c->ssim,
-                      &c->chunk_base, &c->frag_gates, &c->sorted_gates};
+                      &c->chunk_base, &c->frag_gates, &c->sorted_gates, &c->gvert};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -762,45 +795,14 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     return SOUP_OK;
 }
 
-DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a) {
-    DecodeArgs d{};
-    d.views = a.views;
-    d.V = a.V;
-    d.recs = a.recs;
-    d.feats = p.scenes[0].feats;
-    d.mlp = p.scenes[0].mlp;
-    d.G = p.G;
-    d.T = p.scenes[0].T;
-    d.verts = p.scenes[0].verts;
-    d.frags = static_cast<FragRec*>(c->frags.p);
-    d.region = static_cast<uint32_t>(c->frag_region);
-    d.counts = static_cast<uint32_t*>(c->region_counts.p);
-    d.boff = static_cast<uint32_t*>(c->region_boff.p);
-    d.n_regions = c->frag_regions;
-    d.counter = a.counter;
-    d.n_blocks = decode_blocks(c);
-    return d;
-}
-
-soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_views* views, const soup_opts* opts,
-                               uint64_t* vis, float* color, float* logp, void* stream) {
-    if (!c) return SOUP_ERR_INVALID;
-    c->err.clear();
-    hipStream_t s = static_cast<hipStream_t>(stream);
+// The forward raster, with the log of its decoded fragments when `keep`: the
+// log is sized from the last call's largest region count (twice, so that a
+// static-mode call fits), its counts are scanned, and an eager call reads
+// whether it overflowed (an overflowing log is simply not used: the backward
+// replays).
+static soup_status raster_forward(soup_ctx* c, const Plan& p, const Opts& o, RasterArgs& a, bool keep,
+                                  hipStream_t s) {
     soup_status st;
-    Plan p;
-    if ((st = plan_single(c, p, scene, views))) return st;
-    if ((st = check_opts(c, opts))) return st;
-    if (!vis || !color) return fail(c, SOUP_ERR_INVALID, "vis and color outputs are required");
-    if (logp && (st = check_decode_lds(c, p.kind, p.G, true))) return st;
-    HIP_TRY(c, hipSetDevice(c->device));
-    const Opts o = to_opts(opts);
-    if ((st = bin(c, p, o, s))) return st;
-    RasterArgs a = raster_args(c, p, o);
-    a.vis = vis;
-    a.color = color;
-    // reuse_bins: keep a log of the decoded fragments for the backward
-    const bool keep = o.reuse_bins != 0;
     const int log_nr = a.n_blocks;   // one log region per forward wave
     uint64_t log_region = 0;
     if (keep) {
@@ -855,6 +857,49 @@ soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_
         c->log_step = o.step;
         c->log_mode = o.mode;
     }
+    return SOUP_OK;
+}
+
+DecodeArgs decode_args(soup_ctx* c, const Plan& p, const RasterArgs& a) {
+    DecodeArgs d{};
+    d.views = a.views;
+    d.V = a.V;
+    d.recs = a.recs;
+    d.feats = p.scenes[0].feats;
+    d.mlp = p.scenes[0].mlp;
+    d.G = p.G;
+    d.T = p.scenes[0].T;
+    d.verts = p.scenes[0].verts;
+    d.frags = static_cast<FragRec*>(c->frags.p);
+    d.region = static_cast<uint32_t>(c->frag_region);
+    d.counts = static_cast<uint32_t*>(c->region_counts.p);
+    d.boff = static_cast<uint32_t*>(c->region_boff.p);
+    d.n_regions = c->frag_regions;
+    d.counter = a.counter;
+    d.n_blocks = decode_blocks(c);
+    return d;
+}
+
+soup_status soup_rasterize_fwd(soup_ctx* c, const soup_scene* scene, const soup_views* views, const soup_opts* opts,
+                               uint64_t* vis, float* color, float* logp, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    soup_status st;
+    Plan p;
+    if ((st = plan_single(c, p, scene, views))) return st;
+    if ((st = check_opts(c, opts))) return st;
+    if (!vis || !color) return fail(c, SOUP_ERR_INVALID, "vis and color outputs are required");
+    if (logp && (st = check_decode_lds(c, p.kind, p.G, true))) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const Opts o = to_opts(opts);
+    if ((st = bin(c, p, o, s))) return st;
+    RasterArgs a = raster_args(c, p, o);
+    a.vis = vis;
+    a.color = color;
+    // reuse_bins: keep a log of the decoded fragments for the backward
+    const bool keep = o.reuse_bins != 0;
+    if ((st = raster_forward(c, p, o, a, keep, s))) return st;
     if (logp) {
         Timed t(c, SOUP_T_LOGP, s);
         launch_fill_f32(logp, p.n_pix, 0.0f, s);
@@ -1041,6 +1086,232 @@ soup_status soup_render(soup_ctx* c, const soup_scene* scenes, int32_t R, const 
     }
     HIP_TRY(c, hipGetLastError());
     return finish_stats(c, s);
+}
+
+soup_status soup_pforward(soup_ctx* c, const soup_pscene* scene, const soup_views* views, const float* inv_view_proj,
+                          const soup_opts* opts, uint64_t* vis, float* color, float* logp, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    soup_status st;
+    Plan p;
+    if ((st = plan_paper(c, p, scene, views, inv_view_proj))) return st;
+    if ((st = check_opts(c, opts))) return st;
+    if (!vis || !color) return fail(c, SOUP_ERR_INVALID, "vis and color outputs are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const Opts o = to_opts(opts);
+    if ((st = bin(c, p, o, s))) return st;
+    RasterArgs a = raster_args(c, p, o);
+    a.vis = vis;
+    a.color = color;
+    const bool keep = o.reuse_bins != 0 || (logp && o.mode == 0);
+    if ((st = raster_forward(c, p, o, a, keep, s))) return st;
+    {
+        Timed t(c, SOUP_T_SHADE, s);
+        PShadeArgs sa{};
+        sa.views = a.views;
+        sa.V = a.V;
+        sa.P = p.n_pix;
+        sa.recs = a.recs;
+        sa.tex = scene->tex;
+        sa.mlp = scene->mlp;
+        sa.R = scene->R;
+        sa.vis = vis;
+        sa.color = color;
+        sa.o = o;
+        launch_pshade(sa, s);
+    }
+    HIP_TRY(c, hipGetLastError());
+    if (logp) {
+        Timed t(c, SOUP_T_LOGP, s);
+        launch_fill_f32(logp, p.n_pix, 0.0f, s);
+        if (o.mode == 0) {
+            RasterArgs ra = a;
+            ra.counter = nullptr;
+            int64_t n_frag = 0, n_batch = 0;
+            if ((st = replay(c, p, ra, vis, nullptr, nullptr, nullptr, true, nullptr, 0, s, &n_frag, &n_batch,
+                             c->log_valid)))
+                return st;
+            PFragArgs fa{};
+            fa.frags = static_cast<FragRec*>(c->frags.p);
+            fa.region = static_cast<uint32_t>(c->frag_region);
+            fa.counts = static_cast<uint32_t*>(c->region_counts.p);
+            fa.boff = static_cast<uint32_t*>(c->region_boff.p);
+            fa.n_regions = c->frag_regions;
+            fa.tex = scene->tex;
+            fa.R = scene->R;
+            fa.logp = logp;
+            fa.n_blocks = decode_blocks(c);
+            launch_pfrag(fa, true, s);
+        }
+        HIP_TRY(c, hipGetLastError());
+    }
+    return finish_stats(c, s);
+}
+
+soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_views* views, const float* inv_view_proj,
+                           const soup_opts* opts, const uint64_t* vis, const float* color, const float* grad_color,
+                           const float* grad_logp, float* grad_verts, float* grad_tex, float* grad_mlp,
+                           void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    soup_status st;
+    Plan p;
+    if ((st = plan_paper(c, p, scene, views, inv_view_proj))) return st;
+    if ((st = check_opts(c, opts))) return st;
+    if (!vis || !color || !grad_color) return fail(c, SOUP_ERR_INVALID, "vis, color and grad_color are required");
+    if (!grad_verts || !grad_tex || !grad_mlp) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const Opts o = to_opts(opts);
+    bool reused = false;
+    if (o.reuse_bins && c->bins_valid && c->bins_tile == c->tile && c->bins_near_w == o.near_w &&
+        same_descriptors(c, p)) {
+        launch_fill_i32(static_cast<int32_t*>(c->counters.p), 32, 0, s);
+        reused = true;
+    } else if ((st = bin(c, p, o, s))) {
+        return st;
+    }
+    const bool from_log = reused && c->log_valid && c->log_seed == o.seed && c->log_step == o.step &&
+                          c->log_mode == o.mode;
+    const int T = scene->T;
+    const int64_t n_tex = static_cast<int64_t>(T) * mc_count(scene->R) * kPCh;
+    const int nb = pwinner_blocks(c->num_cus);
+    const int rows = nb * 4;
+    if ((st = ensure(c, c->edge_w, static_cast<size_t>(p.n_pix) * sizeof(float2))) ||
+        (st = ensure(c, c->partial, static_cast<size_t>(rows) * kPParams * 4)) ||
+        (st = ensure(c, c->mlp_mid, static_cast<size_t>(mlp_reduce_mid_rows(rows)) * kPParams * 8)) ||
+        (st = ensure(c, c->gvert, static_cast<size_t>(T) * 9 * sizeof(double))))
+        return st;
+    RasterArgs a = raster_args(c, p, o);
+    const float2* ew = nullptr;
+    if (o.edge_pairs != 2) {
+        Timed t(c, SOUP_T_EDGE, s);
+        launch_edge_weights(a.views, a.V, p.n_pix, o, vis, color, grad_color, static_cast<float2*>(c->edge_w.p), s);
+        ew = static_cast<float2*>(c->edge_w.p);
+    }
+    {
+        Timed t(c, SOUP_T_FILL, s);
+        if (!o.accumulate) launch_fill_f32(grad_tex, n_tex, 0.0f, s);
+        launch_fill_i32(static_cast<int32_t*>(c->gvert.p), static_cast<int64_t>(T) * 18, 0, s);
+    }
+    if (o.mode == 0 && grad_logp) {
+        // the score term (Eq. (9)): every fragment in front of a winner, and the winner
+        int64_t n_frag = 0, n_batch = 0;
+        if ((st = replay(c, p, a, vis, grad_color, grad_logp, nullptr, false, nullptr, 0, s, &n_frag, &n_batch,
+                         from_log)))
+            return st;
+        Timed t(c, SOUP_T_GRAD, s);
+        PFragArgs fa{};
+        fa.frags = static_cast<FragRec*>(c->frags.p);
+        fa.region = static_cast<uint32_t>(c->frag_region);
+        fa.counts = static_cast<uint32_t*>(c->region_counts.p);
+        fa.boff = static_cast<uint32_t*>(c->region_boff.p);
+        fa.n_regions = c->frag_regions;
+        fa.tex = scene->tex;
+        fa.R = scene->R;
+        fa.grad_tex = grad_tex;
+        fa.n_blocks = decode_blocks(c);
+        launch_pfrag(fa, false, s);
+    }
+    {
+        Timed t(c, SOUP_T_BWD, s);
+        PWinArgs wa{};
+        wa.views = a.views;
+        wa.V = a.V;
+        wa.P = p.n_pix;
+        wa.recs = a.recs;
+        wa.verts = scene->verts;
+        wa.tex = scene->tex;
+        wa.mlp = scene->mlp;
+        wa.R = scene->R;
+        wa.vis = vis;
+        wa.grad_color = grad_color;
+        wa.edge_w = ew;
+        wa.grad_tex = grad_tex;
+        wa.gvert = static_cast<double*>(c->gvert.p);
+        wa.mlp_partial = static_cast<float*>(c->partial.p);
+        wa.n_blocks = nb;
+        launch_pwinner_bwd(wa, s);
+    }
+    HIP_TRY(c, hipGetLastError());
+    {
+        Timed t(c, SOUP_T_REDUCE, s);
+        launch_pvert_finish(static_cast<double*>(c->gvert.p), grad_verts, static_cast<int64_t>(T) * 9,
+                            o.accumulate != 0, s);
+        launch_mlp_reduce(static_cast<float*>(c->partial.p), rows, kPParams, static_cast<double*>(c->mlp_mid.p),
+                          grad_mlp, o.accumulate != 0, s);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return finish_stats(c, s, false);
+}
+
+static soup_status check_levels(soup_ctx* c, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax) {
+    if (T < 0) return fail(c, SOUP_ERR_INVALID, "T = %d < 0", T);
+    if (Rmin < 0 || Rtop < Rmin || Rmax < Rtop || Rmax > kPMaxR || Rtop - Rmin + 1 > kPMaxLevels)
+        return fail(c, SOUP_ERR_INVALID, "levels Rmin = %d, Rtop = %d, Rmax = %d: need 0 <= Rmin <= Rtop <= Rmax <= %d",
+                    Rmin, Rtop, Rmax, kPMaxR);
+    return SOUP_OK;
+}
+
+soup_status soup_mc_assemble(soup_ctx* c, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax, const float* const* raw,
+                             float* tex, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    soup_status st;
+    if ((st = check_levels(c, T, Rmin, Rtop, Rmax))) return st;
+    if (T > 0 && (!raw || !tex)) return fail(c, SOUP_ERR_INVALID, "mc_assemble: NULL buffers");
+    AssembleArgs aa{};
+    for (int l = 0; l <= Rtop - Rmin; ++l) {
+        if (T > 0 && !raw[l]) return fail(c, SOUP_ERR_INVALID, "mc_assemble: level %d is NULL", Rmin + l);
+        aa.raw[l] = raw[l];
+    }
+    aa.Rmin = Rmin;
+    aa.Rtop = Rtop;
+    aa.Rmax = Rmax;
+    aa.T = T;
+    aa.tex_out = tex;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        Timed t(c, SOUP_T_ASSEMBLE, s);
+        launch_mc_assemble(aa, s);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_mc_assemble_bwd(soup_ctx* c, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax, const float* tex,
+                                 const float* grad_tex, float* const* grad_raw, int32_t accumulate, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    soup_status st;
+    if ((st = check_levels(c, T, Rmin, Rtop, Rmax))) return st;
+    if (accumulate != 0 && accumulate != 1) return fail(c, SOUP_ERR_INVALID, "accumulate = %d (0 or 1)", accumulate);
+    if (T > 0 && (!tex || !grad_tex || !grad_raw)) return fail(c, SOUP_ERR_INVALID, "mc_assemble_bwd: NULL buffers");
+    AssembleArgs aa{};
+    for (int l = 0; l <= Rtop - Rmin; ++l) {
+        if (T > 0 && !grad_raw[l]) return fail(c, SOUP_ERR_INVALID, "mc_assemble_bwd: level %d is NULL", Rmin + l);
+        aa.graw[l] = grad_raw[l];
+    }
+    aa.Rmin = Rmin;
+    aa.Rtop = Rtop;
+    aa.Rmax = Rmax;
+    aa.T = T;
+    aa.tex = tex;
+    aa.grad_tex = grad_tex;
+    aa.accumulate = accumulate;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        Timed t(c, SOUP_T_ASSEMBLE, s);
+        if (mc_assemble_bwd_lds(Rmin, Rtop) > mc_assemble_bwd_lds_cap(c->lds_limit) && !accumulate && T > 0)
+            for (int l = 0; l <= Rtop - Rmin; ++l)
+                launch_fill_f32(grad_raw[l], static_cast<int64_t>(T) * mc_count(Rmin + l) * kPCh, 0.0f, s);
+        launch_mc_assemble_bwd(aa, c->lds_limit, s);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
 }
 
 soup_status soup_loss_l2(soup_ctx* c, const float* color, const float* target, int64_t P, float* grad_color,

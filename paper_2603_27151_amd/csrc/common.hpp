@@ -76,6 +76,7 @@ struct ViewDesc {
     int64_t rec_base;        // record index of (this view, triangle 0)
     float* color_out;        // per-request colour buffer (render) or nullptr
     uint64_t* vis_out;       // per-request visibility buffer or nullptr
+    float Mi[16];            // inverse view-projection (the paper form's view directions), else zero
 };
 
 struct SceneDesc {
@@ -174,6 +175,7 @@ __device__ __forceinline__ float uniform24(uint64_t seed, uint32_t pixel, uint32
 // Shape of the shared MLP: C inputs, NH hidden layers of width H, 4 outputs.
 template <int C_, int H_, int NH_>
 struct MlpShape {
+    static constexpr bool kPaper = false;   // the paper form's raster policy sets it
     static constexpr int C = C_;
     static constexpr int H = H_;
     static constexpr int NH = NH_;

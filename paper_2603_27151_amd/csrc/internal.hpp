@@ -32,8 +32,9 @@ void launch_clip(int64_t* tile_start, int64_t n_tiles, int64_t cap, unsigned int
 constexpr unsigned kOverflowBins = 1u;
 constexpr unsigned kOverflowFragments = 2u;
 
-// MLP shapes compiled in: (C, H, NH)
-enum class MlpKind { k8_16_1, k16_32_2, k32_64_2, kNone };
+// MLP shapes compiled in: (C, H, NH); kPaper is the paper form's raster (opacity
+// texture only, the shading MLP deferred)
+enum class MlpKind { k8_16_1, k16_32_2, k32_64_2, kPaper, kNone };
 MlpKind mlp_kind(int n_layers, const int32_t* dims);
 int mlp_params(int n_layers, const int32_t* dims);
 
@@ -211,6 +212,73 @@ void launch_selftest_sigmoid(const float* x, float* y, int64_t n, hipStream_t s)
 void launch_selftest_uniform(uint64_t seed, const uint32_t* pixel, const uint32_t* tri, uint32_t view_id,
                              uint32_t step, float* u, int64_t n, hipStream_t s);
 
+
+// Paper form (Section 3.3; Supplement B.3, B.6): mesh-colour texture assembly,
+// deferred shading, the score term and log p over a fragment list, the
+// winners' backward.
+constexpr int kPMaxLevels = 8;
+struct AssembleArgs {
+    const float* raw[kPMaxLevels];   // learnable level Rmin + l: [T][V(level)][8]
+    float* graw[kPMaxLevels];        // backward: their gradients
+    int Rmin, Rtop, Rmax, T;
+    float* tex_out;                  // forward: [T][V(Rmax)][8]
+    const float* tex;                // backward: the assembled texture and its gradient
+    const float* grad_tex;
+    int accumulate;
+};
+void launch_mc_assemble(const AssembleArgs& a, hipStream_t s);
+size_t mc_assemble_bwd_lds(int Rmin, int Rtop);
+size_t mc_assemble_bwd_lds_cap(size_t lds_limit);
+void launch_mc_assemble_bwd(const AssembleArgs& a, size_t lds_limit, hipStream_t s);
+
+struct PShadeArgs {
+    const ViewDesc* views;
+    int V;
+    int64_t P;
+    const TriRec* recs;
+    const float* tex;
+    const float* mlp;
+    int R;
+    const uint64_t* vis;
+    float* color;
+    Opts o;
+};
+void launch_pshade(const PShadeArgs& a, hipStream_t s);
+
+struct PFragArgs {
+    const FragRec* frags;
+    uint32_t region;
+    const uint32_t* counts;
+    const uint32_t* boff;
+    int n_regions;
+    const float* tex;
+    int R;
+    float* grad_tex;                 // score pass: d / d opacity channel (added to)
+    float* logp;                     // logp pass (zeroed by the caller)
+    int n_blocks;
+};
+void launch_pfrag(const PFragArgs& a, bool logp, hipStream_t s);
+
+struct PWinArgs {
+    const ViewDesc* views;
+    int V;
+    int64_t P;
+    const TriRec* recs;
+    const float* verts;
+    const float* tex;
+    const float* mlp;
+    int R;
+    const uint64_t* vis;
+    const float* grad_color;
+    const float2* edge_w;            // or null
+    float* grad_tex;                 // added to
+    double* gvert;                   // [T, 9] float64 sums (zeroed by the caller)
+    float* mlp_partial;              // [n_blocks * 4, 595]
+    int n_blocks;
+};
+int pwinner_blocks(int num_cus);
+void launch_pwinner_bwd(const PWinArgs& a, hipStream_t s);
+void launch_pvert_finish(const double* g, float* out, int64_t n, bool accumulate, hipStream_t s);
 
 // Adaptive control of primitives.
 constexpr int kEdgeViews = 32;  // views per edge-length launch (kernel argument)

@@ -1,0 +1,641 @@
+// Paper form of the step (Section 3.3; Supplement B.3, B.6): kernels besides
+// the forward raster (which takes the opacity-only policy PaperTex).
+//
+//  assemble      sigmoid(sum of the learnable levels sampled at the finest
+//                grid's vertices), one workgroup per triangle, and its
+//                gradient summed per triangle in LDS;
+//  shade         the deferred colour of every pixel's winner: features of its
+//                micro-triangle, harmonics of the view direction, the MLP on
+//                the vector ALUs in the float32 contract, the RGBA blend;
+//  frag          over a fragment list (the forward's log filtered, or a
+//                replay): the score term of Eq. (9) on the opacity channel, or
+//                log p(f*) of Eq. (6);
+//  winner_bwd    per pixel: the colour path of the winner (the MLP's data
+//                backward on the vector ALUs; its weight gradient, a
+//                contraction over pixels, on the matrix cores), the features'
+//                gradient onto the three grid vertices, and the vertex
+//                gradient through the barycentrics and the edge term in
+//                float64.
+#include "decode_mfma.hpp"
+#include "pform.hpp"
+
+namespace soup {
+
+// ---------------------------------------------------------------------------
+// texture assembly
+// ---------------------------------------------------------------------------
+
+// (i, j) of the finest grid's vertex k (row-major storage): row j starts at
+// j (n + 1) - j (j - 1) / 2; the float estimate of j is corrected exactly.
+__device__ __forceinline__ void mc_ij(int n, int k, int& i, int& j) {
+    const float b = static_cast<float>(2 * n + 3);
+    int jj = static_cast<int>((b - __builtin_sqrtf(b * b - 8.0f * static_cast<float>(k))) * 0.5f);
+    jj = jj < 0 ? 0 : (jj > n ? n : jj);
+    while (jj > 0 && mc_index(n, 0, jj) > k) --jj;
+    while (jj < n && mc_index(n, 0, jj + 1) <= k) ++jj;
+    j = jj;
+    i = k - mc_index(n, 0, jj);
+}
+
+__global__ __launch_bounds__(256) void mc_assemble_kernel(AssembleArgs a) {
+    const int t = blockIdx.x;
+    const int nf = 1 << a.Rmax, Vf = mc_count(a.Rmax);
+    float* out = a.tex_out + static_cast<size_t>(t) * Vf * kPCh;
+    for (int k = threadIdx.x; k < Vf; k += blockDim.x) {
+        int i, j;
+        mc_ij(nf, k, i, j);
+        const float b1 = static_cast<float>(i) / static_cast<float>(nf);
+        const float b2 = static_cast<float>(j) / static_cast<float>(nf);
+        float z[kPCh];
+#pragma unroll
+        for (int c = 0; c < kPCh; ++c) z[c] = 0.0f;
+        for (int R = a.Rmin; R <= a.Rtop; ++R) {
+            const Micro m = micro_of(1 << R, b1, b2);
+            const float4* g = reinterpret_cast<const float4*>(a.raw[R - a.Rmin] + static_cast<size_t>(t) * mc_count(R) * kPCh);
+            float4 v[3][2];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                v[q][0] = g[2 * m.idx[q]];
+                v[q][1] = g[2 * m.idx[q] + 1];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                z[4 * h + 0] = z[4 * h + 0] + mc_mix(m, v[0][h].x, v[1][h].x, v[2][h].x);
+                z[4 * h + 1] = z[4 * h + 1] + mc_mix(m, v[0][h].y, v[1][h].y, v[2][h].y);
+                z[4 * h + 2] = z[4 * h + 2] + mc_mix(m, v[0][h].z, v[1][h].z, v[2][h].z);
+                z[4 * h + 3] = z[4 * h + 3] + mc_mix(m, v[0][h].w, v[1][h].w, v[2][h].w);
+            }
+        }
+        float4* o = reinterpret_cast<float4*>(out + static_cast<size_t>(k) * kPCh);
+        o[0] = make_float4(sigmoid_c(z[0]), sigmoid_c(z[1]), sigmoid_c(z[2]), sigmoid_c(z[3]));
+        o[1] = make_float4(sigmoid_c(z[4]), sigmoid_c(z[5]), sigmoid_c(z[6]), sigmoid_c(z[7]));
+    }
+}
+
+// Gradient of the assembly: d raw[l] (vertex q) += w_q(l) sigmoid'(z) d tex
+// over the finest grid's vertices, with sigmoid' = tex (1 - tex). LDS holds
+// the triangle's level gradients (offsets lofs); without room for them the
+// adds go to global memory directly.
+template <bool LDS_SUM>
+__global__ __launch_bounds__(256) void mc_assemble_bwd_kernel(AssembleArgs a) {
+    extern __shared__ float acc[];
+    const int t = blockIdx.x;
+    const int nf = 1 << a.Rmax, Vf = mc_count(a.Rmax);
+    const int nl = a.Rtop - a.Rmin + 1;
+    int lofs[kPMaxLevels + 1];
+    lofs[0] = 0;
+    for (int l = 0; l < nl; ++l) lofs[l + 1] = lofs[l] + mc_count(a.Rmin + l) * kPCh;
+    if constexpr (LDS_SUM) {
+        for (int e = threadIdx.x; e < lofs[nl]; e += blockDim.x) acc[e] = 0.0f;
+        __syncthreads();
+    }
+    const float* tx = a.tex + static_cast<size_t>(t) * Vf * kPCh;
+    const float* gt = a.grad_tex + static_cast<size_t>(t) * Vf * kPCh;
+    for (int k = threadIdx.x; k < Vf; k += blockDim.x) {
+        int i, j;
+        mc_ij(nf, k, i, j);
+        const float b1 = static_cast<float>(i) / static_cast<float>(nf);
+        const float b2 = static_cast<float>(j) / static_cast<float>(nf);
+        float dz[kPCh];
+        const float4* s4 = reinterpret_cast<const float4*>(tx + static_cast<size_t>(k) * kPCh);
+        const float4* g4 = reinterpret_cast<const float4*>(gt + static_cast<size_t>(k) * kPCh);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float4 s = s4[h], g = g4[h];
+            dz[4 * h + 0] = g.x * s.x * (1.0f - s.x);
+            dz[4 * h + 1] = g.y * s.y * (1.0f - s.y);
+            dz[4 * h + 2] = g.z * s.z * (1.0f - s.z);
+            dz[4 * h + 3] = g.w * s.w * (1.0f - s.w);
+        }
+        for (int l = 0; l < nl; ++l) {
+            const int R = a.Rmin + l;
+            const Micro m = micro_of(1 << R, b1, b2);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (m.w[q] == 0.0f) continue;
+#pragma unroll
+                for (int c = 0; c < kPCh; ++c) {
+                    const float v = m.w[q] * dz[c];
+                    if (v == 0.0f) continue;
+                    if constexpr (LDS_SUM) atomicAdd(&acc[lofs[l] + m.idx[q] * kPCh + c], v);
+                    else atomicAdd(&a.graw[l][(static_cast<size_t>(t) * mc_count(R) + m.idx[q]) * kPCh + c], v);
+                }
+            }
+        }
+    }
+    if constexpr (LDS_SUM) {
+        __syncthreads();
+        for (int l = 0; l < nl; ++l) {
+            const int n = lofs[l + 1] - lofs[l];
+            float* g = a.graw[l] + static_cast<size_t>(t) * n;
+            for (int e = threadIdx.x; e < n; e += blockDim.x) g[e] = (a.accumulate ? g[e] : 0.0f) + acc[lofs[l] + e];
+        }
+    }
+}
+
+// LDS one workgroup of the assembly gradient may take: half the CU's, at most 64 KiB.
+size_t mc_assemble_bwd_lds_cap(size_t lds_limit) { return lds_limit / 2 < 65536 ? lds_limit / 2 : 65536; }
+
+size_t mc_assemble_bwd_lds(int Rmin, int Rtop) {
+    size_t n = 0;
+    for (int R = Rmin; R <= Rtop; ++R) n += static_cast<size_t>(mc_count(R)) * kPCh;
+    return n * sizeof(float);
+}
+
+void launch_mc_assemble(const AssembleArgs& a, hipStream_t s) {
+    if (a.T <= 0) return;
+    hipLaunchKernelGGL(mc_assemble_kernel, dim3(static_cast<unsigned>(a.T)), dim3(256), 0, s, a);
+}
+
+void launch_mc_assemble_bwd(const AssembleArgs& a, size_t lds_limit, hipStream_t s) {
+    if (a.T <= 0) return;
+    const size_t lds = mc_assemble_bwd_lds(a.Rmin, a.Rtop);
+    if (lds <= mc_assemble_bwd_lds_cap(lds_limit)) {
+        hipLaunchKernelGGL(mc_assemble_bwd_kernel<true>, dim3(static_cast<unsigned>(a.T)), dim3(256), lds, s, a);
+    } else {
+        // outputs zeroed by the caller unless accumulating
+        hipLaunchKernelGGL(mc_assemble_bwd_kernel<false>, dim3(static_cast<unsigned>(a.T)), dim3(256), 0, s, a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-pixel helpers
+// ---------------------------------------------------------------------------
+
+// View of global pixel p (views ordered by pix_base).
+__device__ __forceinline__ int view_of_pixel(const ViewDesc* __restrict__ views, int V, int64_t p) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].pix_base <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Workgroups are dealt to the eight XCDs in turn: workgroup b works on block
+// (b % 8) * per + b / 8 of the grid's blocks (a bijection when the grid is a
+// multiple of eight), so that each XCD takes one contiguous eighth of the
+// pixels and a triangle's texture is read into one L2.
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t per = gridDim.x / kXcds;
+    return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+// The forward's perspective-correct barycentrics of triangle record tr at the
+// centre of pixel (x, y): the exact orientation-normalised edge functions,
+// beta_i = (float)E_i |rA|, t_i = beta_i / w_i, then the contract's b1, b2.
+__device__ __forceinline__ void frag_bary(const TriRec& tr, int x, int y, float& b1, float& b2, double (&E)[3]) {
+    const int64_t PX = static_cast<int64_t>(kSnap) * x + kSnap / 2, PY = static_cast<int64_t>(kSnap) * y + kSnap / 2;
+    const double sgn = tr.rA < 0.0f ? -1.0 : 1.0;
+    const float ra = __builtin_fabsf(tr.rA);
+    float t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int ea = i == 2 ? 0 : i + 1, eb = i == 0 ? 2 : (i == 1 ? 0 : 1);
+        const double ex = static_cast<double>(tr.X[eb] - tr.X[ea]), ey = static_cast<double>(tr.Y[eb] - tr.Y[ea]);
+        // every factor is an integer below 2^26: the product and the fused sum are exact
+        E[i] = sgn * __builtin_fma(ex, static_cast<double>(PY - tr.Y[ea]), -(ey * static_cast<double>(PX - tr.X[ea])));
+        t[i] = (static_cast<float>(E[i]) * ra) * tr.iw[i];
+    }
+    persp_from_t(t[0], t[1], t[2], b1, b2);
+}
+
+// The winner's shading inputs: the eight channels of its micro-triangle's
+// three grid vertices (v[q][0..1]) and their interpolation (feat).
+__device__ __forceinline__ void fetch_texel(gfloat* __restrict__ tex, uint32_t tri, int V, const Micro& m,
+                                            float4 (&v)[3][2], float (&feat)[kPCh]) {
+    gfloat4* g = reinterpret_cast<gfloat4*>(tex + static_cast<size_t>(tri) * V * kPCh);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        v[q][0] = g[2 * m.idx[q]];
+        v[q][1] = g[2 * m.idx[q] + 1];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        feat[4 * h + 0] = mc_mix(m, v[0][h].x, v[1][h].x, v[2][h].x);
+        feat[4 * h + 1] = mc_mix(m, v[0][h].y, v[1][h].y, v[2][h].y);
+        feat[4 * h + 2] = mc_mix(m, v[0][h].z, v[1][h].z, v[2][h].z);
+        feat[4 * h + 3] = mc_mix(m, v[0][h].w, v[1][h].w, v[2][h].w);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// deferred shading (forward)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void pshade_kernel(PShadeArgs a) {
+    const int64_t p = static_cast<int64_t>(xcd_block()) * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const uint64_t key = a.vis[p];
+    float* out = a.color + 3 * p;
+    if (key == kBgKey) {
+        out[0] = a.o.bg[0];
+        out[1] = a.o.bg[1];
+        out[2] = a.o.bg[2];
+        return;
+    }
+    const int v = view_of_pixel(a.views, a.V, p);
+    const ViewDesc& vd = a.views[v];
+    const uint32_t local = static_cast<uint32_t>(p - vd.pix_base);
+    const int y = static_cast<int>(local / static_cast<uint32_t>(vd.W));
+    const int x = static_cast<int>(local - static_cast<uint32_t>(y) * static_cast<uint32_t>(vd.W));
+    const uint32_t tri = static_cast<uint32_t>(key);
+    const TriRec tr = a.recs[vd.rec_base + tri];
+    float b1, b2;
+    double E[3];
+    frag_bary(tr, x, y, b1, b2, E);
+    const Micro m = micro_of(1 << a.R, b1, b2);
+    float4 tv[3][2];
+    float feat[kPCh];
+    fetch_texel(as_global(a.tex), tri, mc_count(a.R), m, tv, feat);
+    float in[kPIn];
+#pragma unroll
+    for (int c = 0; c < kPFeat; ++c) in[c] = feat[c];
+    float d[3];
+    view_dir(vd.Mi, vd.W, vd.H, x, y, d);
+    sh2(d, in + kPFeat);
+    cfloat* mp = as_const(a.mlp);
+    float h1[kPHid], h2[kPHid], o[kPOut];
+    dense<kPIn, kPHid, true>(mp + kPW0, mp + kPB0, in, h1);
+    dense<kPHid, kPHid, true>(mp + kPW1, mp + kPB1, h1, h2);
+    dense<kPHid, kPOut, false>(mp + kPW2, mp + kPB2, h2, o);
+    const float A = feat[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float mm = sigmoid_c(o[c]);
+        out[c] = __builtin_fmaf(A, feat[c] - mm, mm);   // A RGB + (1 - A) MLP
+    }
+}
+
+void launch_pshade(const PShadeArgs& a, hipStream_t s) {
+    if (a.P <= 0) return;
+    const int64_t nb = ((a.P + 255) / 256 + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(pshade_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// fragment list: score term (Eq. (9)) or log p(f*) (Eq. (6))
+// ---------------------------------------------------------------------------
+
+template <bool LOGP>
+__global__ __launch_bounds__(256) void pfrag_kernel(PFragArgs a) {
+    __shared__ uint32_t s_boff[kMaxRegions + 1];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i <= a.n_regions; i += blockDim.x) s_boff[i] = a.boff[i];
+    __syncthreads();
+    const uint32_t n_batch = s_boff[a.n_regions];
+    const uint32_t n_waves = gridDim.x * 4;
+    const int n = 1 << a.R, V = mc_count(a.R);
+    gfloat* tex = as_global(a.tex);
+    for (uint32_t bi = blockIdx.x * 4 + w; bi < n_batch; bi += n_waves) {
+        int lo = 0, hi = a.n_regions - 1;   // region: last w with boff[w] <= bi
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_boff[mid] <= bi) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t cr = a.counts[lo];
+        const uint32_t in_region = (bi - s_boff[lo]) * 64u + static_cast<uint32_t>(lane);
+        if (in_region >= (cr < a.region ? cr : a.region)) continue;
+        const FragRec fr = a.frags[static_cast<uint64_t>(lo) * a.region + in_region];
+        const uint32_t tri = fr.p0.y & 0x7FFFFFFFu;
+        const bool win = (fr.p0.y >> 31) != 0u;
+        const float b1 = __uint_as_float(fr.p1.x), b2 = __uint_as_float(fr.p1.y);
+        const Micro m = micro_of(n, b1, b2);
+        gfloat* t = tex + static_cast<size_t>(tri) * V * kPCh + (kPCh - 1);
+        const float alpha = mc_mix(m, t[m.idx[0] * kPCh], t[m.idx[1] * kPCh], t[m.idx[2] * kPCh]);
+        if constexpr (LOGP) {
+            atomicAdd(&a.logp[fr.p0.x], win ? logf(alpha) : log1pf(-alpha));
+        } else {
+            const float gl = __uint_as_float(fr.x.x);
+            if (gl == 0.0f) continue;
+            // d log p / d alpha: 1 / alpha for the winner, -1 / (1 - alpha) in front of it
+            const float da = win ? gl / alpha : -gl / (1.0f - alpha);
+            float* g = a.grad_tex + static_cast<size_t>(tri) * V * kPCh + (kPCh - 1);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (m.w[q] != 0.0f) atomicAdd(&g[m.idx[q] * kPCh], m.w[q] * da);
+        }
+    }
+}
+
+void launch_pfrag(const PFragArgs& a, bool logp, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
+    if (logp) hipLaunchKernelGGL(pfrag_kernel<true>, dim3(a.n_blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(pfrag_kernel<false>, dim3(a.n_blocks), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// winners (backward)
+// ---------------------------------------------------------------------------
+
+constexpr int kPStage = 64 + 4;   // staged row: 64 pixels, padded
+
+// The world-space gradient of the vertices of the winner's triangle from the
+// gradient of its perspective-correct barycentrics (db1, db2) and the edge
+// weights (ex, ey), in float64 at the snapped positions (every edge function
+// an exact integer), with the clip coordinates recomputed in the setup's
+// float32 order.
+__device__ __forceinline__ void vertex_grad(const ViewDesc& vd, const TriRec& tr, const float* __restrict__ vp,
+                                            int px, int py, const double (&E)[3], double db1, double db2, double ex,
+                                            double ey, double (&gw)[9]) {
+    const double inv_a = 1.0 / ((E[0] + E[1]) + E[2]);
+    double fb[3], iwv[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        fb[i] = E[i] * inv_a;
+        iwv[i] = tr.iw[i];
+    }
+    const double tt[3] = {fb[0] * iwv[0], fb[1] * iwv[1], fb[2] * iwv[2]};
+    const double inv_s = 1.0 / ((tt[0] + tt[1]) + tt[2]);
+    const double bb[3] = {tt[0] * inv_s, tt[1] * inv_s, tt[2] * inv_s};
+    const double db[3] = {0.0, db1, db2};
+    const double dot = db[1] * bb[1] + db[2] * bb[2];
+    double dbeta[3], diw[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double dt = (db[i] - dot) * inv_s;
+        dbeta[i] = dt * iwv[i];
+        diw[i] = dt * fb[i];
+    }
+    const int32_t PX = kSnap * px + kSnap / 2, PY = kSnap * py + kSnap / 2;
+    const double Ai = __builtin_fma(static_cast<double>(tr.X[1] - tr.X[0]), static_cast<double>(tr.Y[2] - tr.Y[0]),
+                                    -(static_cast<double>(tr.Y[1] - tr.Y[0]) * static_cast<double>(tr.X[2] - tr.X[0])));
+    const double inv_area = 65536.0 / Ai;   // 1 / (signed 2 x area in px^2)
+    const double inv256 = 1.0 / 256.0;
+    double gsx[3] = {0., 0., 0.}, gsy[3] = {0., 0., 0.};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // beta_i = e_i / area with e_i = edge(v_p, v_q, pixel centre)
+        const int p = i == 2 ? 0 : i + 1, q = i == 0 ? 2 : (i == 1 ? 0 : 1);
+#pragma unroll
+        for (int jv = 0; jv < 3; ++jv) {
+            const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
+            const double dax = static_cast<double>(tr.Y[jp] - tr.Y[jq]) * inv256;
+            const double day = static_cast<double>(tr.X[jq] - tr.X[jp]) * inv256;
+            double dex = 0., dey = 0.;
+            if (jv == p) {
+                dex = static_cast<double>(tr.Y[q] - PY) * inv256;
+                dey = static_cast<double>(PX - tr.X[q]) * inv256;
+            } else if (jv == q) {
+                dex = static_cast<double>(PY - tr.Y[p]) * inv256;
+                dey = static_cast<double>(tr.X[p] - PX) * inv256;
+            }
+            gsx[jv] += dbeta[i] * (dex - fb[i] * dax) * inv_area;
+            gsy[jv] += dbeta[i] * (dey - fb[i] * day) * inv_area;
+        }
+    }
+    // edge term (Section 3.2): the boundaries this pixel occludes move with its
+    // surface point, w beta_i e on the screen position of vertex i
+#pragma unroll
+    for (int jv = 0; jv < 3; ++jv) {
+        gsx[jv] += ex * fb[jv];
+        gsy[jv] += ey * fb[jv];
+    }
+    // screen position (W/2 (c_x / c_w) + W/2, H/2 - H/2 (c_y / c_w)) and 1/w -> clip -> world
+    const double hw = 0.5 * vd.W, hh = 0.5 * vd.H;
+#pragma unroll
+    for (int jv = 0; jv < 3; ++jv) {
+        const float x = vp[3 * jv], y = vp[3 * jv + 1], z = vp[3 * jv + 2];
+        float cc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {   // the setup's transform
+            float acc = vd.M[j * 4 + 3];
+            acc = __builtin_fmaf(vd.M[j * 4 + 0], x, acc);
+            acc = __builtin_fmaf(vd.M[j * 4 + 1], y, acc);
+            acc = __builtin_fmaf(vd.M[j * 4 + 2], z, acc);
+            cc[j] = acc;
+        }
+        const double cx = cc[0], cy = cc[1], iw = 1.0 / static_cast<double>(cc[3]);
+        const double gc0 = gsx[jv] * hw * iw;
+        const double gc1 = -gsy[jv] * hh * iw;
+        const double gc3 = (-gsx[jv] * hw * cx + gsy[jv] * hh * cy - diw[jv]) * (iw * iw);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            gw[3 * jv + k] = static_cast<double>(vd.M[k]) * gc0 + static_cast<double>(vd.M[4 + k]) * gc1 +
+                             static_cast<double>(vd.M[12 + k]) * gc3;
+    }
+}
+
+// One weight-gradient block of the wave's 64 pixels on the matrix cores:
+// D[j][c] += sum over pixels of delta[p][j] act[p][c] (v_mfma_f32_16x16x4f32,
+// K = pixels: step s of lane group grp takes pixel 16 grp + s, so that lane
+// (grp, col) reads 16 consecutive pixels of unit col from the stage), and
+// bsum += the lane's 16 values of delta unit col (the bias gradient).
+__device__ __forceinline__ void wgrad_block(float (*st)[kPIn][kPStage], const float (&act)[kPIn], const float* delta,
+                                            int nd, int lane, f4v& acc, float& bsum) {
+    const int col = lane & 15, grp = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < kPIn; ++u) {
+        st[0][u][lane] = act[u];
+        st[1][u][lane] = u < nd ? delta[u] : 0.0f;
+    }
+    wave_fence();
+    float4 A4[4], B4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        A4[q] = *reinterpret_cast<const float4*>(&st[1][col][16 * grp + 4 * q]);
+        B4[q] = *reinterpret_cast<const float4*>(&st[0][col][16 * grp + 4 * q]);
+    }
+    wave_fence();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        acc = mfma4(A4[q].x, B4[q].x, acc);
+        acc = mfma4(A4[q].y, B4[q].y, acc);
+        acc = mfma4(A4[q].z, B4[q].z, acc);
+        acc = mfma4(A4[q].w, B4[q].w, acc);
+        bsum += (A4[q].x + A4[q].y) + (A4[q].z + A4[q].w);
+    }
+}
+
+__global__ __launch_bounds__(256) void pwinner_bwd_kernel(PWinArgs a) {
+    __shared__ __align__(16) float stage[4][2][kPIn][kPStage];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, col = lane & 15, grp = lane >> 4;
+    float (*st)[kPIn][kPStage] = stage[w];
+    // contiguous runs of 64-pixel batches per wave, the waves of one XCD on adjacent runs
+    const int64_t nbat = (a.P + 63) / 64;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
+    const int64_t wid = static_cast<int64_t>(xcd_block()) * 4 + w;
+    const int64_t bbeg = nbat * wid / nw, bend = nbat * (wid + 1) / nw;
+    const int R = a.R, n = 1 << R, V = mc_count(R);
+    cfloat* mp = as_const(a.mlp);
+    gfloat* tex = as_global(a.tex);
+    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+    float ab0 = 0.f, ab1 = 0.f, ab2 = 0.f;
+    for (int64_t b = bbeg; b < bend; ++b) {
+        const int64_t p = b * 64 + lane;
+        uint64_t key = kBgKey;
+        if (p < a.P) key = a.vis[p];
+        const bool on = key != kBgKey;
+        float gc[3] = {0.f, 0.f, 0.f};
+        float ex = 0.f, ey = 0.f;
+        if (on) {
+            gc[0] = a.grad_color[3 * p];
+            gc[1] = a.grad_color[3 * p + 1];
+            gc[2] = a.grad_color[3 * p + 2];
+            if (a.edge_w) {
+                const float2 e = a.edge_w[p];
+                ex = e.x;
+                ey = e.y;
+            }
+        }
+        const bool cpath = on && (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f);
+        const bool active = cpath || (on && (ex != 0.f || ey != 0.f));
+        int x = 0, y = 0, v = 0;
+        uint32_t tri = 0;
+        TriRec tr{};
+        float b1 = 0.f, b2 = 0.f;
+        double E[3] = {1.0, 0.0, 0.0};
+        Micro m{};
+        float4 tv[3][2];
+        float feat[kPCh];
+        if (active) {
+            v = view_of_pixel(a.views, a.V, p);
+            const ViewDesc& vd = a.views[v];
+            const uint32_t local = static_cast<uint32_t>(p - vd.pix_base);
+            y = static_cast<int>(local / static_cast<uint32_t>(vd.W));
+            x = static_cast<int>(local - static_cast<uint32_t>(y) * static_cast<uint32_t>(vd.W));
+            tri = static_cast<uint32_t>(key);
+            tr = a.recs[vd.rec_base + tri];
+            frag_bary(tr, x, y, b1, b2, E);
+            m = micro_of(n, b1, b2);
+        }
+        // --- colour path: recompute in the forward's arithmetic, then the data backward ---
+        float in[kPIn], h1[kPHid], h2[kPHid], d1[kPHid], d2[kPHid], d3[kPOut];
+        float dfeat[kPFeat];
+#pragma unroll
+        for (int u = 0; u < kPHid; ++u) {
+            in[u] = 0.f;
+            h1[u] = 0.f;
+            h2[u] = 0.f;
+            d1[u] = 0.f;
+            d2[u] = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < kPOut; ++c) d3[c] = 0.f;
+#pragma unroll
+        for (int c = 0; c < kPFeat; ++c) dfeat[c] = 0.f;
+        if (cpath) {
+            const ViewDesc& vd = a.views[v];
+            fetch_texel(tex, tri, V, m, tv, feat);
+#pragma unroll
+            for (int c = 0; c < kPFeat; ++c) in[c] = feat[c];
+            float d[3];
+            view_dir(vd.Mi, vd.W, vd.H, x, y, d);
+            sh2(d, in + kPFeat);
+            float o[kPOut];
+            dense<kPIn, kPHid, true>(mp + kPW0, mp + kPB0, in, h1);
+            dense<kPHid, kPHid, true>(mp + kPW1, mp + kPB1, h1, h2);
+            dense<kPHid, kPOut, false>(mp + kPW2, mp + kPB2, h2, o);
+            const float A = feat[3];
+            float dA = 0.f;
+#pragma unroll
+            for (int c = 0; c < kPOut; ++c) {
+                const float mm = sigmoid_c(o[c]);
+                dfeat[c] = A * gc[c];
+                dA = __builtin_fmaf(gc[c], feat[c] - mm, dA);
+                d3[c] = (1.0f - A) * gc[c] * (mm * (1.0f - mm));
+            }
+            dfeat[3] = dA;
+            // through the output layer and the ReLU gates of the recompute (the forward's own)
+#pragma unroll
+            for (int u = 0; u < kPHid; ++u) {
+                float s = 0.f;
+#pragma unroll
+                for (int c = 0; c < kPOut; ++c) s = __builtin_fmaf(mp[kPW2 + c * kPHid + u], d3[c], s);
+                d2[u] = h2[u] > 0.f ? s : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kPHid; ++u) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < kPHid; ++j) s = __builtin_fmaf(mp[kPW1 + j * kPHid + u], d2[j], s);
+                d1[u] = h1[u] > 0.f ? s : 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < kPFeat; ++c) {
+                float s = 0.f;
+#pragma unroll
+                for (int j = 0; j < kPHid; ++j) s = __builtin_fmaf(mp[kPW0 + j * kPIn + c], d1[j], s);
+                dfeat[c] += s;   // the harmonics have no parameters
+            }
+        }
+        // --- MLP weight gradients over the wave's pixels (lanes without a colour path add zeros) ---
+        if (__ballot(cpath)) {
+            wgrad_block(st, in, d1, kPHid, lane, acc0, ab0);
+            wgrad_block(st, h1, d2, kPHid, lane, acc1, ab1);
+            wgrad_block(st, h2, d3, kPOut, lane, acc2, ab2);
+        }
+        if (!active) continue;
+        // --- features -> the micro-triangle's grid vertices; along (b1, b2) -> the triangle ---
+        float dfu = 0.f, dfv = 0.f;
+        if (cpath) {
+            float* gt = a.grad_tex + static_cast<size_t>(tri) * V * kPCh;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (m.w[q] == 0.0f) continue;
+#pragma unroll
+                for (int c = 0; c < kPFeat; ++c)
+                    if (dfeat[c] != 0.0f) atomicAdd(&gt[m.idx[q] * kPCh + c], m.w[q] * dfeat[c]);
+            }
+            // upright: w = (1 - fu - fv, fu, fv); inverted: w = (fu + fv - 1, 1 - fv, 1 - fu)
+#pragma unroll
+            for (int c = 0; c < kPFeat; ++c) {
+                const float t0 = c < 4 ? (&tv[0][0].x)[c] : (&tv[0][1].x)[c - 4];
+                const float t1 = c < 4 ? (&tv[1][0].x)[c] : (&tv[1][1].x)[c - 4];
+                const float t2 = c < 4 ? (&tv[2][0].x)[c] : (&tv[2][1].x)[c - 4];
+                dfu = __builtin_fmaf(dfeat[c], m.inv ? t0 - t2 : t1 - t0, dfu);
+                dfv = __builtin_fmaf(dfeat[c], m.inv ? t0 - t1 : t2 - t0, dfv);
+            }
+        }
+        double gw[9];
+        vertex_grad(a.views[v], tr, a.verts + static_cast<size_t>(tri) * 9, x, y, E,
+                    static_cast<double>(dfu) * n, static_cast<double>(dfv) * n, ex, ey, gw);
+        double* gv = a.gvert + static_cast<size_t>(tri) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            if (gw[k] != 0.0) atomicAdd(&gv[k], gw[k]);
+    }
+    // the wave's partial row of the MLP gradient (D[4 grp + i][col] of each block)
+    float* row = a.mlp_partial + static_cast<size_t>(blockIdx.x * 4 + w) * kPParams;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        row[kPW0 + (4 * grp + i) * kPIn + col] = acc0[i];
+        row[kPW1 + (4 * grp + i) * kPHid + col] = acc1[i];
+        if (grp == 0 && i < kPOut) row[kPW2 + i * kPHid + col] = acc2[i];
+    }
+    ab0 += __shfl_xor(ab0, 16, 64);
+    ab0 += __shfl_xor(ab0, 32, 64);
+    ab1 += __shfl_xor(ab1, 16, 64);
+    ab1 += __shfl_xor(ab1, 32, 64);
+    ab2 += __shfl_xor(ab2, 16, 64);
+    ab2 += __shfl_xor(ab2, 32, 64);
+    if (grp == 0) {
+        row[kPB0 + col] = ab0;
+        row[kPB1 + col] = ab1;
+        if (col < kPOut) row[kPB2 + col] = ab2;
+    }
+}
+
+int pwinner_blocks(int num_cus) { return ((num_cus * 2 + kXcds - 1) / kXcds) * kXcds; }
+
+void launch_pwinner_bwd(const PWinArgs& a, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
+    hipLaunchKernelGGL(pwinner_bwd_kernel, dim3(static_cast<unsigned>(a.n_blocks)), dim3(256), 0, s, a);
+}
+
+__global__ __launch_bounds__(256) void pvert_finish_kernel(const double* __restrict__ g, float* __restrict__ out,
+                                                           int64_t n, int accumulate) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = static_cast<float>((accumulate ? static_cast<double>(out[i]) : 0.0) + g[i]);
+}
+
+void launch_pvert_finish(const double* g, float* out, int64_t n, bool accumulate, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(pvert_finish_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, g, out, n,
+                       accumulate ? 1 : 0);
+}
+
+}  // namespace soup

@@ -15,6 +15,13 @@ void launch_raster_fwd_k32_64_2_t8(const RasterArgs& a, hipStream_t s);
 void launch_raster_fwd_k32_64_2_t16(const RasterArgs& a, hipStream_t s);
 void launch_raster_fwd_k32_64_2_t32(const RasterArgs& a, hipStream_t s);
 
+void launch_raster_fwd_paper_t8(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_paper_t16(const RasterArgs& a, hipStream_t s);
+void launch_raster_fwd_paper_t32(const RasterArgs& a, hipStream_t s);
+int raster_fwd_per_cu_paper_t8(int region);
+int raster_fwd_per_cu_paper_t16(int region);
+int raster_fwd_per_cu_paper_t32(int region);
+
 int raster_fwd_per_cu_k8_16_1_t8(int region);
 int raster_fwd_per_cu_k8_16_1_t16(int region);
 int raster_fwd_per_cu_k8_16_1_t32(int region);
@@ -42,6 +49,11 @@ void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s) 
             else if (tile == 32) launch_raster_fwd_k32_64_2_t32(a, s);
             else launch_raster_fwd_k32_64_2_t16(a, s);
             break;
+        case MlpKind::kPaper:
+            if (tile == 8) launch_raster_fwd_paper_t8(a, s);
+            else if (tile == 32) launch_raster_fwd_paper_t32(a, s);
+            else launch_raster_fwd_paper_t16(a, s);
+            break;
         default: break;
     }
 }
@@ -55,6 +67,8 @@ int raster_fwd_blocks_per_cu(int tile, MlpKind k, int region) {
             return tile == 8 ? raster_fwd_per_cu_k16_32_2_t8(region) : tile == 32 ? raster_fwd_per_cu_k16_32_2_t32(region) : raster_fwd_per_cu_k16_32_2_t16(region);
         case MlpKind::k32_64_2:
             return tile == 8 ? raster_fwd_per_cu_k32_64_2_t8(region) : tile == 32 ? raster_fwd_per_cu_k32_64_2_t32(region) : raster_fwd_per_cu_k32_64_2_t16(region);
+        case MlpKind::kPaper:
+            return tile == 8 ? raster_fwd_per_cu_paper_t8(region) : tile == 32 ? raster_fwd_per_cu_paper_t32(region) : raster_fwd_per_cu_paper_t16(region);
         default: return 1;
     }
 }

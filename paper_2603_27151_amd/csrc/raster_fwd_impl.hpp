@@ -33,7 +33,7 @@
 // pixel: front-to-back early-out without sorting fragments. The result does
 // not depend on the visiting order (the draws are fixed by Philox), only the
 // amount of work does.
-#include "raster_common.hpp"
+#include "pform.hpp"
 
 namespace soup {
 
@@ -173,31 +173,43 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         int pl = 0;
         bool pass = false;
         float o[4] = {0.f, 0.f, 0.f, 0.f};
-        uint32_t gates[GateWords<S>::kWords];
+        constexpr int GW = GateWords<S>::kWords;
+        uint32_t gates[GW > 0 ? GW : 1];
 #pragma unroll
-        for (int w = 0; w < GateWords<S>::kWords; ++w) gates[w] = 0u;
+        for (int w = 0; w < GW; ++w) gates[w] = 0u;
         if (act) {
             key = L.qkey[lane];
             pl = static_cast<int>(L.qpl[lane]);
             float b1, b2;
             persp_from_t(L.qt[0][lane], L.qt[1][lane], L.qt[2][lane], b1, b2);
             const uint32_t tri = static_cast<uint32_t>(key);
-            const Cell c = cell_of(b1, b2, G);
-            float x[S::C];
-            fetch_feature<S::C>(feats, tri, G, c, x);
-            // an opaque copy of the weight pointer per batch: the compiler may
-            // not hoist the weights' scalar loads out of the traversal loops
-            // (the ReLU gates are kept for the log; forming them costs two
-            // instructions per hidden unit)
-            mlp_logits_gates<S>(as_const(opaque_ptr(mlp_p)), x, o, gates);
             const int blk = pl >> 6, p = pl & 63;
             const int gx = rx + (blk % BR) * 8 + (p & 7), gy = ry + (blk / BR) * 8 + (p >> 3);
-            if (a.o.mode == 0) {
-                const float alpha = sigmoid_c(o[3]);
-                const uint32_t pidx = static_cast<uint32_t>(gy * W + gx);
-                pass = uniform24(a.o.seed, pidx, tri, view_id, a.o.step) < alpha;
+            if constexpr (S::kPaper) {
+                // the opacity texture alone decides the mask (G holds the texture level R)
+                const float alpha = mc_alpha(feats, tri, G, b1, b2);
+                if (a.o.mode == 0) {
+                    const uint32_t pidx = static_cast<uint32_t>(gy * W + gx);
+                    pass = uniform24(a.o.seed, pidx, tri, view_id, a.o.step) < alpha;
+                } else {
+                    pass = alpha > 0.5f;
+                }
             } else {
-                pass = o[3] > 0.0f;
+                const Cell c = cell_of(b1, b2, G);
+                float x[S::C];
+                fetch_feature<S::C>(feats, tri, G, c, x);
+                // an opaque copy of the weight pointer per batch: the compiler may
+                // not hoist the weights' scalar loads out of the traversal loops
+                // (the ReLU gates are kept for the log; forming them costs two
+                // instructions per hidden unit)
+                mlp_logits_gates<S>(as_const(opaque_ptr(mlp_p)), x, o, gates);
+                if (a.o.mode == 0) {
+                    const float alpha = sigmoid_c(o[3]);
+                    const uint32_t pidx = static_cast<uint32_t>(gy * W + gx);
+                    pass = uniform24(a.o.seed, pidx, tri, view_id, a.o.step) < alpha;
+                } else {
+                    pass = o[3] > 0.0f;
+                }
             }
             if (pass) atomicMin(reinterpret_cast<unsigned long long*>(&L.key[pl]), static_cast<unsigned long long>(key));
             if (a.log_frag) {
@@ -206,7 +218,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     const int64_t pg = pix_base + static_cast<int64_t>(gy) * W + gx;
                     a.log_frag[log_base + at] =
                         make_uint4(static_cast<uint32_t>(pg), tri, __float_as_uint(b1), __float_as_uint(b2));
-                    constexpr int GW = GateWords<S>::kWords, AW2 = aux_words(GW) / 2;
+                    constexpr int AW2 = aux_words(GW) / 2;
                     uint2* ax = a.log_aux + (log_base + at) * AW2;
                     ax[0] = make_uint2(static_cast<uint32_t>(key >> 32), static_cast<uint32_t>(v));
 #pragma unroll
@@ -216,9 +228,10 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         }
         if (a.log_frag) log_cursor += static_cast<uint32_t>(n);
         __syncthreads();
-        if (pass && L.key[pl] == key) {
+        if (!S::kPaper && pass && L.key[pl] == key) {
             // the pixel's new best: its colour goes to the output now (a later batch that lowers
-            // the key again writes after this one, behind the workgroup barriers between them)
+            // the key again writes after this one, behind the workgroup barriers between them;
+            // the paper form shades its winners afterwards)
             const int blk = pl >> 6, p = pl & 63;
             const int64_t off = static_cast<int64_t>(ry + (blk / BR) * 8 + (p >> 3)) * W + rx + (blk % BR) * 8 + (p & 7);
             gfloat_w* col = color_base + 3 * off;
@@ -505,7 +518,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     for (int b = 0; b < NB; ++b) {
         if (!oin[b]) continue;
         if (vis_base) vis_base[ooff[b]] = okey[b];
-        if (okey[b] == kBgKey) {   // covered pixels got their colour when their best key was set
+        if (!S::kPaper && okey[b] == kBgKey) {   // covered pixels got their colour when their best key was set
             gfloat_w* col = color_base + 3 * ooff[b];
             col[0] = a.o.bg[0];
             col[1] = a.o.bg[1];

@@ -271,3 +271,95 @@ def adam_step(p, g, m, v, lr: float, t: int, vec: int = 1, beta1: float = 0.9, b
     (v holds one entry per vec-vector)."""
     ctx = ctx or context()
     _lib.soup_adam_step(ctx, p, g, m, v, vec, lr, beta1, beta2, eps, t, stream)
+
+
+# ---------------------------------------------------------------------------
+# Paper form (Section 3.3; Supplement B.3, B.6): mesh-colour texture, opacity
+# outside the MLP, deferred shading
+
+@dataclasses.dataclass
+class PDeviceScene:
+    verts: torch.Tensor        # [T,3,3] float32, cuda
+    tex: torch.Tensor          # [T,V(R),8], activated
+    mlp: torch.Tensor          # [595]
+    R: int
+
+    @staticmethod
+    def from_host(ps, device="cuda") -> "PDeviceScene":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        return PDeviceScene(t(ps.verts), t(ps.tex), t(ps.mlp), int(ps.R))
+
+    @property
+    def T(self) -> int:
+        return int(self.verts.shape[0])
+
+    def c_struct(self) -> _lib.soup_pscene:
+        return _lib.make_pscene(self.verts, self.tex, self.mlp, self.R)
+
+
+def inv_view_proj(views: Views) -> np.ndarray:
+    """Per view the inverse of its view-projection, in float64 rounded once
+    to float32 (the deferred shading's view directions)."""
+    return np.linalg.inv(views.view_proj.astype(np.float64)).astype(np.float32)
+
+
+def pforward(scene: PDeviceScene, views: Views, opts: Opts, minv=None, want_logp: bool = False, ctx=None,
+             stream=None, out=None):
+    """vis [P] int64, color [P,3], logp [P] or None (the paper form)."""
+    ctx = ctx or context()
+    dev = scene.verts.device
+    P = views.pixels
+    if out is not None:
+        vis, color, logp = out
+    else:
+        vis = torch.empty(P, dtype=torch.int64, device=dev)
+        color = torch.empty(P, 3, dtype=torch.float32, device=dev)
+        logp = torch.empty(P, dtype=torch.float32, device=dev) if want_logp else None
+    minv = inv_view_proj(views) if minv is None else minv
+    h = _lib._Holder()
+    _lib.soup_pforward(ctx, scene.c_struct(), views.c_struct(h), minv, opts.c_struct(), vis, color, logp, stream)
+    return vis, color, logp
+
+
+def pbackward(scene: PDeviceScene, views: Views, opts: Opts, vis, color, grad_color, grad_logp=None, minv=None,
+              ctx=None, stream=None, out=None):
+    """(d verts [T,3,3], d tex [T,V,8], d mlp [595]) of the paper form."""
+    ctx = ctx or context()
+    if out is None:
+        gv = torch.empty_like(scene.verts)
+        gt = torch.empty_like(scene.tex)
+        gm = torch.empty_like(scene.mlp)
+    else:
+        gv, gt, gm = out
+    minv = inv_view_proj(views) if minv is None else minv
+    h = _lib._Holder()
+    _lib.soup_pbackward(ctx, scene.c_struct(), views.c_struct(h), minv, opts.c_struct(), vis, color,
+                        grad_color.contiguous(), None if grad_logp is None else grad_logp.contiguous(), gv, gt, gm,
+                        stream)
+    return gv, gt, gm
+
+
+def mc_vertices(R: int) -> int:
+    n = 1 << R
+    return (n + 1) * (n + 2) // 2
+
+
+def mc_assemble(raw: Sequence[torch.Tensor], Rmin: int, Rmax: int, out=None, ctx=None, stream=None):
+    """tex [T,V(Rmax),8] = sigmoid(sum of the learnable levels Rmin.. sampled at the finest vertices)."""
+    ctx = ctx or context()
+    T = int(raw[0].shape[0])
+    tex = out if out is not None else torch.empty(T, mc_vertices(Rmax), 8, dtype=torch.float32,
+                                                  device=raw[0].device)
+    _lib.soup_mc_assemble(ctx, [r.contiguous() for r in raw], Rmin, Rmax, tex, stream)
+    return tex
+
+
+def mc_assemble_bwd(tex, grad_tex, Rmin: int, n_levels: int, Rmax: int, out=None, accumulate: int = 0, ctx=None,
+                    stream=None):
+    ctx = ctx or context()
+    T = int(tex.shape[0])
+    if out is None:
+        out = [torch.empty(T, mc_vertices(Rmin + l), 8, dtype=torch.float32, device=tex.device)
+               for l in range(n_levels)]
+    _lib.soup_mc_assemble_bwd(ctx, tex, grad_tex.contiguous(), Rmin, Rmax, out, accumulate, stream)
+    return out

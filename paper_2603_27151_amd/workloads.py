@@ -212,7 +212,7 @@ def _targets(rng, views):
     return [rng.random((v.height, v.width, 3)).astype(np.float32) for v in views]
 
 
-CONFIG_SEEDS = {"tiny": 1001, "single": 1002, "batched": 1003, "serving": 1004, "large": 1005}
+CONFIG_SEEDS = {"tiny": 1001, "single": 1002, "batched": 1003, "serving": 1004, "large": 1005, "paper": 1006}
 PHILOX_SEEDS = {k: 0x5EED0000 + i + 1 for i, k in enumerate(CONFIG_SEEDS)}
 
 
@@ -372,6 +372,45 @@ def random_levels(rng, T: int, Rmin: int, Rtop: int, Rmax: int, sd: float = 0.5)
     raw = [rng.normal(0.0, sd, (T, mc_vertices(R), PF_CHANNELS)).astype(np.float32)
            for R in range(Rmin, Rtop + 1)]
     return PLevels(raw, Rmin, Rmax)
+
+
+@dataclasses.dataclass
+class PWorkload:
+    """The paper form's training step: a soup, its learnable texture levels
+    Rmin..Rmax-1 accumulated on the level-Rmax grid, the shading MLP, views
+    and targets."""
+    name: str
+    verts: np.ndarray
+    levels: PLevels
+    mlp: np.ndarray
+    views: List[View]
+    seed: int
+    step: int = 0
+    targets: Optional[List[np.ndarray]] = None
+
+    @property
+    def pixels(self) -> int:
+        return int(sum(v.width * v.height for v in self.views))
+
+    @property
+    def T(self) -> int:
+        return int(self.verts.shape[0])
+
+
+def paper(with_targets: bool = True, T: int = 50_000, n_views: int = 4, res: int = 800, Rmin: int = 2,
+          Rmax: int = 5) -> PWorkload:
+    """The paper form at the paper's second training stage (levels 2..4 onto
+    the level-5 grid, 561 vertices per triangle) and its batch of four
+    views, on the batched workload's kind of soup: 50,000 triangles, views of
+    800 x 800 on a sphere of radius 3."""
+    rng = np.random.Generator(np.random.PCG64(CONFIG_SEEDS["paper"]))
+    verts = equilateral_soup(rng, uniform_ball(rng, T))
+    levels = random_levels(rng, T, Rmin, Rmax - 1, Rmax)
+    mlp = random_pscene(rng, verts[:1], 0).mlp
+    eyes = fibonacci_sphere(n_views, 3.0)
+    views = [View(res, res, i, view_proj(eyes[i], res, res)) for i in range(n_views)]
+    t = _targets(rng, views) if with_targets else None
+    return PWorkload("paper", verts, levels, mlp, views, PHILOX_SEEDS["paper"], 0, t)
 
 
 def by_name(name: str, **kw) -> Workload:

@@ -572,3 +572,31 @@ def test_score_estimator_is_unbiased_on_textured_opacity():
     want = exact[..., [0, 1, 2, 3, 7]].ravel()
     assert np.abs(want).max() > 1e-2
     assert np.all(np.abs(sm.mean(0) - want) < 5 * se + 1e-6), np.abs(sm.mean(0) - want) / (se + 1e-12)
+
+
+def test_pixel_entry_points_agree_with_full_image():
+    rng = np.random.default_rng(37)
+    ps = _persp_scene(rng)
+    ps.tex[..., 7] = rng.uniform(0.2, 0.9, ps.tex[..., 7].shape)
+    Wd, Hd = 40, 33
+    M = W.view_proj((0.2, 0.1, 3.0), Wd, Hd)
+    view = W.View(Wd, Hd, 3, M)
+    Minv = W.inv_view_proj(M)
+    o = O.Opts(seed=11, step=2)
+    vis, color, logp, _ = O.pforward(ps, view, Minv, o)
+    xy = np.array([(x, y) for y in range(0, Hd, 4) for x in range(1, Wd, 3)], np.int32)
+    v2, c2, l2 = O.pforward_pixels(ps, view, Minv, o, xy)
+    assert np.array_equal(v2, vis[xy[:, 1], xy[:, 0]])
+    assert np.array_equal(c2, color[xy[:, 1], xy[:, 0]])
+    assert np.array_equal(l2, logp[xy[:, 1], xy[:, 0]])
+    gc = rng.normal(size=(len(xy), 3)).astype(np.float32)
+    gl = rng.normal(size=len(xy)).astype(np.float32)
+    full_gc = np.zeros((Hd, Wd, 3), np.float32)
+    full_gl = np.zeros((Hd, Wd), np.float32)
+    full_gc[xy[:, 1], xy[:, 0]] = gc
+    full_gl[xy[:, 1], xy[:, 0]] = gl
+    a = O.pbackward(ps, view, Minv, o, vis, color, full_gc, full_gl)
+    b = O.pbackward_pixels(ps, view, Minv, o, xy, gc, gl)
+    for x, y in zip(a, b):
+        assert np.allclose(x, y, rtol=1e-12, atol=1e-14 * max(1.0, np.abs(x).max()))
+    assert np.abs(a[0]).max() > 0 and np.abs(a[1]).max() > 0 and np.abs(a[2]).max() > 0
