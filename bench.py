@@ -133,6 +133,124 @@ class Step:
         return g
 
 
+class PStep(Step):
+    """One step of the paper form (Section 3.3; Supplement B.3, B.6) on one
+    stream: soup_mc_assemble (levels Rmin..Rmax-1 onto the level-Rmax grid)
+    -> soup_pforward (opacity-texture mask, deferred shading) ->
+    soup_loss_l1_ssim (the paper's loss) -> soup_pbackward ->
+    soup_mc_assemble_bwd, into preallocated buffers."""
+
+    def __init__(self, R, ctx, wl, target, dev):
+        import torch
+        self.R, self.ctx, self.wl, self.target = R, ctx, wl, target
+        lv = wl.levels
+        self.Rmin, self.Rmax = lv.Rmin, lv.Rmax
+        self.raw = [torch.from_numpy(r).to(dev) for r in lv.raw]
+        self.graw = [torch.empty_like(r) for r in self.raw]
+        T = wl.T
+        tex = torch.empty(T, R.mc_vertices(lv.Rmax), 8, dtype=torch.float32, device=dev)
+        self.ds = R.PDeviceScene(torch.from_numpy(wl.verts).to(dev), tex, torch.from_numpy(wl.mlp).to(dev), lv.Rmax)
+        self.vs = R.Views.from_list(wl.views)
+        self.minv = R.inv_view_proj(self.vs)
+        P = self.vs.pixels
+        self.opts = R.Opts(seed=wl.seed, step=wl.step, reuse_bins=1)
+        self.vis = torch.empty(P, dtype=torch.int64, device=dev)
+        self.color = torch.empty(P, 3, dtype=torch.float32, device=dev)
+        self.loss = torch.empty(1, dtype=torch.float32, device=dev)
+        self.gc = torch.empty(P, 3, dtype=torch.float32, device=dev)
+        self.gl = torch.empty(P, dtype=torch.float32, device=dev)
+        self.gv = torch.empty_like(self.ds.verts)
+        self.gt = torch.empty_like(tex)
+        self.gm = torch.empty_like(self.ds.mlp)
+
+    def __call__(self):
+        R, ctx = self.R, self.ctx
+        R.mc_assemble(self.raw, self.Rmin, self.Rmax, out=self.ds.tex, ctx=ctx)
+        R.pforward(self.ds, self.vs, self.opts, minv=self.minv, ctx=ctx, out=(self.vis, self.color, None))
+        R.loss_l1_ssim(self.color, self.target, self.vs, 0.8, ctx=ctx, out=(self.loss, self.gc, self.gl))
+        R.pbackward(self.ds, self.vs, self.opts, self.vis, self.color, self.gc, self.gl, minv=self.minv, ctx=ctx,
+                    out=(self.gv, self.gt, self.gm))
+        R.mc_assemble_bwd(self.ds.tex, self.gt, self.Rmin, len(self.raw), self.Rmax, out=self.graw, ctx=ctx)
+
+
+def paper_form_bench(args, R, W, dev, timed):
+    """The paper form's training step at the paper's second stage (levels
+    2..4 onto level 5, 561 grid vertices per triangle) on four 800 x 800
+    views of a 50,000-triangle soup: step time, per-kernel times, counts and
+    the roofline of its dominant kernel."""
+    import torch
+    wl = W.paper()
+    target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
+    ctx = R._lib.Ctx(0)
+    ctx.set_tile(16)
+    st = PStep(R, ctx, wl, target, dev)
+    for _ in range(max(2, args.warmup)):
+        st()
+    torch.cuda.synchronize()
+    ctx.set_counting(True)
+    R.pforward(st.ds, st.vs, st.opts, minv=st.minv, ctx=ctx, out=(st.vis, st.color, None))
+    sf = ctx.stats()
+    R.loss_l1_ssim(st.color, st.target, st.vs, 0.8, ctx=ctx, out=(st.loss, st.gc, st.gl))
+    R.pbackward(st.ds, st.vs, st.opts, st.vis, st.color, st.gc, st.gl, minv=st.minv, ctx=ctx,
+                out=(st.gv, st.gt, st.gm))
+    ctx.set_counting(False)
+    torch.cuda.synchronize()
+    P = st.vs.pixels
+    winners = int((st.vis != -1).sum().item())
+    ctx.read_timings()
+    ctx.set_timing(True)
+    eager_ms = timed(st, args.steps)
+    ctx.set_timing(False)
+    kern = ctx.read_timings()
+    # the paper form's kernels under the timing kinds they share with the workloads' form
+    names = {"decode_bwd": "winner_bwd", "grad_reduce": "score", "mlp_reduce": "reduce"}
+    per_kernel = {names.get(k, k): (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
+    ms, graph = eager_ms, False
+    if not args.no_graph:
+        ref = st.vis.clone()
+        g = st.capture(log)
+        g.replay()
+        torch.cuda.synchronize()
+        ctx.check_overflow()
+        if not torch.equal(st.vis, ref):
+            raise RuntimeError("paper-form graph replay changed the visibility buffer")
+        ms = timed(g.replay, args.steps)
+        torch.cuda.synchronize()
+        ctx.check_overflow()
+        ctx.set_static(False)
+        graph = True
+    T, V = wl.T, R.mc_vertices(wl.levels.Rmax)
+    n_raw = sum(int(r.numel()) for r in st.raw)
+    # algorithmic bytes per launch of each kernel (the data it must touch once)
+    bytes_ = {
+        # levels read once, the assembled texture written once
+        "assemble": 4.0 * (n_raw + 8 * T * V),
+        # the texture and its gradient read once, the levels' gradients written once
+        "assemble_bwd": 4.0 * (n_raw + 2 * 8 * T * V),
+        # per pixel: its key in, its colour out; per winner: the record (64 B), the three
+        # grid vertices (96 B) and the view's inverse matrix is cached
+        "shade": 8.0 * P + 12.0 * P + winners * (64.0 + 96.0),
+    }
+    log(f"paper form: {P} pixels, {winners} winners, fwd decodes {sf['decodes']}, eager {eager_ms:.3f} ms, "
+        f"graph {ms:.3f} ms")
+    log("paper form per-kernel avg ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_kernel.items() if v > 0))
+    out = {"workload": f"paper form: {T} triangles, texture levels {wl.levels.Rmin}..{wl.levels.Rtop} onto level "
+                       f"{wl.levels.Rmax} ({V} grid vertices x 8 channels), MLP 16->16->16->3 deferred, "
+                       f"{st.vs.V} views of 800x800, L1 + D-SSIM",
+           "ms_per_step": round(ms, 4), "eager_ms_per_step": round(eager_ms, 4), "hip_graph": graph,
+           "mpixel_s": round(P / (ms * 1e-3) / 1e6, 2), "pixels": P, "winners": winners,
+           "forward_decodes": sf["decodes"], "covered_pixels": sf["covered_pixels"],
+           "kernels_ms": {k: round(v, 4) for k, v in per_kernel.items() if v > 0},
+           "hbm": {k: {"bytes": b, "gb_s": round(b / (per_kernel[kk] * 1e-3) / 1e9, 1),
+                       "frac": round(b / (per_kernel[kk] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                   for k, b in bytes_.items() for kk in [k] if per_kernel.get(kk, 0) > 0}}
+    del st
+    if graph:
+        del g
+    ctx.close()
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +266,7 @@ def parse():
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--skip-adaptive", action="store_true")
     ap.add_argument("--skip-train", action="store_true")
+    ap.add_argument("--skip-paper", action="store_true", help="skip the paper-form step")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first copy this many MiB device to device three times (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -475,6 +594,13 @@ def main():
                    "tiles": {f"{w}x{h}": t for (w, h), t in srv.tile_by_res.items()},
                    "slo_p99_ms": 16.7, **main_st, "sweep": sweep}
 
+    # the paper form (Section 3.3): mesh-colour texture, opacity outside the
+    # MLP, deferred shading; its own step on its own workload
+    paper_form = None
+    if not args.skip_paper:
+        paper_form = paper_form_bench(args, R, W, dev, timed)
+        log("paper form: " + json.dumps(paper_form))
+
     # CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.skip_cpu:
@@ -530,6 +656,7 @@ def main():
         "serving": serving,
         "adaptive": adaptive,
         "train": train,
+        "paper_form": paper_form,
     }
     print(json.dumps(out), flush=True)
 

@@ -139,8 +139,9 @@ enum {
     SOUP_T_TLOSS = 17,   /* L1 + SSIM loss */
     SOUP_T_ADAM = 18,    /* optimiser steps */
     SOUP_T_SHADE = 19,   /* paper form: deferred shading of the winners */
-    SOUP_T_ASSEMBLE = 20, /* paper form: texture assembly and its gradient */
-    SOUP_TIMING_KINDS = 21
+    SOUP_T_ASSEMBLE = 20, /* paper form: texture assembly */
+    SOUP_T_ASSEMBLE_BWD = 21, /* paper form: texture assembly gradient */
+    SOUP_TIMING_KINDS = 22
 };
 soup_status soup_ctx_set_timing(soup_ctx* ctx, int32_t on);
 soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);

@@ -59,7 +59,7 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
-                "adaptive_apply", "train_loss", "adam", "shade", "assemble"]
+                "adaptive_apply", "train_loss", "adam", "shade", "assemble", "assemble_bwd"]
 PMLP_PARAMS = 595
 ACT_REMOVE, ACT_KEEP, ACT_SPLIT0 = 0, 1, 2
 PLAN_PRUNE_ZERO, PLAN_FILL = 1, 2

@@ -1304,8 +1304,8 @@ soup_status soup_mc_assemble_bwd(soup_ctx* c, int32_t T, int32_t Rmin, int32_t R
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     {
-        Timed t(c, SOUP_T_ASSEMBLE, s);
-        if (mc_assemble_bwd_lds(Rmin, Rtop) > mc_assemble_bwd_lds_cap(c->lds_limit) && !accumulate && T > 0)
+        Timed t(c, SOUP_T_ASSEMBLE_BWD, s);
+        if (mc_assemble_bwd_lds(Rmin, Rmax) > mc_assemble_bwd_lds_cap(c->lds_limit) && !accumulate && T > 0)
             for (int l = 0; l <= Rtop - Rmin; ++l)
                 launch_fill_f32(grad_raw[l], static_cast<int64_t>(T) * mc_count(Rmin + l) * kPCh, 0.0f, s);
         launch_mc_assemble_bwd(aa, c->lds_limit, s);

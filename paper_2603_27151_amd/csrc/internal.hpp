@@ -227,7 +227,7 @@ struct AssembleArgs {
     int accumulate;
 };
 void launch_mc_assemble(const AssembleArgs& a, hipStream_t s);
-size_t mc_assemble_bwd_lds(int Rmin, int Rtop);
+size_t mc_assemble_bwd_lds(int Rmin, int Rmax);
 size_t mc_assemble_bwd_lds_cap(size_t lds_limit);
 void launch_mc_assemble_bwd(const AssembleArgs& a, size_t lds_limit, hipStream_t s);
 

@@ -37,15 +37,21 @@ __device__ __forceinline__ void mc_ij(int n, int k, int& i, int& j) {
     i = k - mc_index(n, 0, jj);
 }
 
+// One thread per (triangle, vertex of the finest grid), consecutive threads on
+// consecutive vertices (32-byte records, written coalesced).
 __global__ __launch_bounds__(256) void mc_assemble_kernel(AssembleArgs a) {
-    const int t = blockIdx.x;
     const int nf = 1 << a.Rmax, Vf = mc_count(a.Rmax);
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= static_cast<int64_t>(a.T) * Vf) return;
+    const int t = static_cast<int>(g / Vf);
+    const int k = static_cast<int>(g - static_cast<int64_t>(t) * Vf);
     float* out = a.tex_out + static_cast<size_t>(t) * Vf * kPCh;
-    for (int k = threadIdx.x; k < Vf; k += blockDim.x) {
+    {
         int i, j;
         mc_ij(nf, k, i, j);
-        const float b1 = static_cast<float>(i) / static_cast<float>(nf);
-        const float b2 = static_cast<float>(j) / static_cast<float>(nf);
+        // i / n and j / n (n a power of two: the product by 1 / n is exact)
+        const float b1 = static_cast<float>(i) * (1.0f / static_cast<float>(nf));
+        const float b2 = static_cast<float>(j) * (1.0f / static_cast<float>(nf));
         float z[kPCh];
 #pragma unroll
         for (int c = 0; c < kPCh; ++c) z[c] = 0.0f;
@@ -72,63 +78,100 @@ __global__ __launch_bounds__(256) void mc_assemble_kernel(AssembleArgs a) {
     }
 }
 
-// Gradient of the assembly: d raw[l] (vertex q) += w_q(l) sigmoid'(z) d tex
-// over the finest grid's vertices, with sigmoid' = tex (1 - tex). LDS holds
-// the triangle's level gradients (offsets lofs); without room for them the
-// adds go to global memory directly.
+// Gradient of the assembly. The lookup of level R at the vertices of level
+// Rmax equals prolongation to level R + 1, then R + 2, ..., Rmax (the field of
+// a level is linear on each of its micro-triangles, and every micro-triangle
+// of the next level lies inside one of them; a vertex of level R + 1 is a
+// vertex of level R, weight 1, or the midpoint of an edge, weights 1/2). Its
+// transpose is the restriction chain: with dz = tex (1 - tex) d tex on level
+// Rmax, g_R(I, J) = g_{R+1}(2I, 2J) + 1/2 sum over the six lattice neighbours
+// (2I, 2J) + d, d in +-(1, 0), +-(0, 1), +-(1, -1), that exist. One workgroup
+// per triangle keeps the chain in LDS (two buffers of the largest level) and
+// writes every learnable level; without room for them the adds go to global
+// memory directly, one lookup per level and vertex.
 template <bool LDS_SUM>
 __global__ __launch_bounds__(256) void mc_assemble_bwd_kernel(AssembleArgs a) {
-    extern __shared__ float acc[];
+    extern __shared__ float lds[];
     const int t = blockIdx.x;
     const int nf = 1 << a.Rmax, Vf = mc_count(a.Rmax);
-    const int nl = a.Rtop - a.Rmin + 1;
-    int lofs[kPMaxLevels + 1];
-    lofs[0] = 0;
-    for (int l = 0; l < nl; ++l) lofs[l + 1] = lofs[l] + mc_count(a.Rmin + l) * kPCh;
-    if constexpr (LDS_SUM) {
-        for (int e = threadIdx.x; e < lofs[nl]; e += blockDim.x) acc[e] = 0.0f;
-        __syncthreads();
-    }
     const float* tx = a.tex + static_cast<size_t>(t) * Vf * kPCh;
     const float* gt = a.grad_tex + static_cast<size_t>(t) * Vf * kPCh;
-    for (int k = threadIdx.x; k < Vf; k += blockDim.x) {
-        int i, j;
-        mc_ij(nf, k, i, j);
-        const float b1 = static_cast<float>(i) / static_cast<float>(nf);
-        const float b2 = static_cast<float>(j) / static_cast<float>(nf);
-        float dz[kPCh];
-        const float4* s4 = reinterpret_cast<const float4*>(tx + static_cast<size_t>(k) * kPCh);
-        const float4* g4 = reinterpret_cast<const float4*>(gt + static_cast<size_t>(k) * kPCh);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const float4 s = s4[h], g = g4[h];
-            dz[4 * h + 0] = g.x * s.x * (1.0f - s.x);
-            dz[4 * h + 1] = g.y * s.y * (1.0f - s.y);
-            dz[4 * h + 2] = g.z * s.z * (1.0f - s.z);
-            dz[4 * h + 3] = g.w * s.w * (1.0f - s.w);
+    if constexpr (LDS_SUM) {
+        // level Rmax in the first buffer, the chain's levels then alternate
+        // between a second buffer (levels Rmax - 1, Rmax - 3, ...) and the first
+        float* cur = lds;
+        float* nxt = lds + Vf * kPCh;
+        const float4* tx4 = reinterpret_cast<const float4*>(tx);
+        const float4* gt4 = reinterpret_cast<const float4*>(gt);
+        float4* cur4 = reinterpret_cast<float4*>(cur);
+        for (int e = threadIdx.x; e < Vf * 2; e += blockDim.x) {
+            const float4 s = tx4[e], g = gt4[e];
+            cur4[e] = make_float4(g.x * s.x * (1.0f - s.x), g.y * s.y * (1.0f - s.y), g.z * s.z * (1.0f - s.z),
+                                  g.w * s.w * (1.0f - s.w));
         }
-        for (int l = 0; l < nl; ++l) {
-            const int R = a.Rmin + l;
-            const Micro m = micro_of(1 << R, b1, b2);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                if (m.w[q] == 0.0f) continue;
-#pragma unroll
-                for (int c = 0; c < kPCh; ++c) {
-                    const float v = m.w[q] * dz[c];
-                    if (v == 0.0f) continue;
-                    if constexpr (LDS_SUM) atomicAdd(&acc[lofs[l] + m.idx[q] * kPCh + c], v);
-                    else atomicAdd(&a.graw[l][(static_cast<size_t>(t) * mc_count(R) + m.idx[q]) * kPCh + c], v);
+        __syncthreads();
+        for (int R = a.Rmax;; --R) {
+            if (R <= a.Rtop) {   // a learnable level: out (32 bytes per vertex, 16-byte aligned)
+                const int n4 = mc_count(R) * 2;
+                float4* g = reinterpret_cast<float4*>(a.graw[R - a.Rmin]) + static_cast<size_t>(t) * n4;
+                const float4* c4 = reinterpret_cast<const float4*>(cur);
+                for (int e = threadIdx.x; e < n4; e += blockDim.x) {
+                    float4 v = c4[e];
+                    if (a.accumulate) {
+                        const float4 o = g[e];
+                        v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+                    }
+                    g[e] = v;
                 }
             }
+            if (R == a.Rmin) break;
+            // restrict level R (cur) onto level R - 1 (nxt)
+            const int nc = 1 << (R - 1), nfl = 1 << R, Vc = mc_count(R - 1);
+            for (int e = threadIdx.x; e < Vc * kPCh; e += blockDim.x) {
+                const int q = e / kPCh, c = e - q * kPCh;
+                int I, J;
+                mc_ij(nc, q, I, J);
+                const int i = 2 * I, j = 2 * J;
+                float side = 0.0f;
+                if (i + 1 + j <= nfl) side += cur[mc_index(nfl, i + 1, j) * kPCh + c];
+                if (i > 0) side += cur[mc_index(nfl, i - 1, j) * kPCh + c];
+                if (i + j + 1 <= nfl) side += cur[mc_index(nfl, i, j + 1) * kPCh + c];
+                if (j > 0) side += cur[mc_index(nfl, i, j - 1) * kPCh + c];
+                if (j > 0) side += cur[mc_index(nfl, i + 1, j - 1) * kPCh + c];   // i + 1 + j - 1 <= n always
+                if (i > 0) side += cur[mc_index(nfl, i - 1, j + 1) * kPCh + c];
+                nxt[e] = cur[mc_index(nfl, i, j) * kPCh + c] + 0.5f * side;
+            }
+            __syncthreads();
+            float* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
         }
-    }
-    if constexpr (LDS_SUM) {
-        __syncthreads();
-        for (int l = 0; l < nl; ++l) {
-            const int n = lofs[l + 1] - lofs[l];
-            float* g = a.graw[l] + static_cast<size_t>(t) * n;
-            for (int e = threadIdx.x; e < n; e += blockDim.x) g[e] = (a.accumulate ? g[e] : 0.0f) + acc[lofs[l] + e];
+    } else {
+        const int nl = a.Rtop - a.Rmin + 1;
+        for (int k = threadIdx.x; k < Vf; k += blockDim.x) {
+            int i, j;
+            mc_ij(nf, k, i, j);
+            const float b1 = static_cast<float>(i) * (1.0f / static_cast<float>(nf));
+            const float b2 = static_cast<float>(j) * (1.0f / static_cast<float>(nf));
+            float dz[kPCh];
+#pragma unroll
+            for (int c = 0; c < kPCh; ++c) {
+                const float s = tx[k * kPCh + c];
+                dz[c] = gt[k * kPCh + c] * s * (1.0f - s);
+            }
+            for (int l = 0; l < nl; ++l) {
+                const int R = a.Rmin + l;
+                const Micro m = micro_of(1 << R, b1, b2);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (m.w[q] == 0.0f) continue;
+#pragma unroll
+                    for (int c = 0; c < kPCh; ++c) {
+                        const float v = m.w[q] * dz[c];
+                        if (v != 0.0f) atomicAdd(&a.graw[l][(static_cast<size_t>(t) * mc_count(R) + m.idx[q]) * kPCh + c], v);
+                    }
+                }
+            }
         }
     }
 }
@@ -136,20 +179,21 @@ __global__ __launch_bounds__(256) void mc_assemble_bwd_kernel(AssembleArgs a) {
 // LDS one workgroup of the assembly gradient may take: half the CU's, at most 64 KiB.
 size_t mc_assemble_bwd_lds_cap(size_t lds_limit) { return lds_limit / 2 < 65536 ? lds_limit / 2 : 65536; }
 
-size_t mc_assemble_bwd_lds(int Rmin, int Rtop) {
-    size_t n = 0;
-    for (int R = Rmin; R <= Rtop; ++R) n += static_cast<size_t>(mc_count(R)) * kPCh;
-    return n * sizeof(float);
+// The finest level's gradient and the next coarser one's (every later level fits the first).
+size_t mc_assemble_bwd_lds(int Rmin, int Rmax) {
+    const size_t next = Rmax > Rmin ? static_cast<size_t>(mc_count(Rmax - 1)) : 0;
+    return (static_cast<size_t>(mc_count(Rmax)) + next) * kPCh * sizeof(float);
 }
 
 void launch_mc_assemble(const AssembleArgs& a, hipStream_t s) {
     if (a.T <= 0) return;
-    hipLaunchKernelGGL(mc_assemble_kernel, dim3(static_cast<unsigned>(a.T)), dim3(256), 0, s, a);
+    const int64_t n = static_cast<int64_t>(a.T) * mc_count(a.Rmax);
+    hipLaunchKernelGGL(mc_assemble_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
 }
 
 void launch_mc_assemble_bwd(const AssembleArgs& a, size_t lds_limit, hipStream_t s) {
     if (a.T <= 0) return;
-    const size_t lds = mc_assemble_bwd_lds(a.Rmin, a.Rtop);
+    const size_t lds = mc_assemble_bwd_lds(a.Rmin, a.Rmax);
     if (lds <= mc_assemble_bwd_lds_cap(lds_limit)) {
         hipLaunchKernelGGL(mc_assemble_bwd_kernel<true>, dim3(static_cast<unsigned>(a.T)), dim3(256), lds, s, a);
     } else {
@@ -567,35 +611,58 @@ __global__ __launch_bounds__(256) void pwinner_bwd_kernel(PWinArgs a) {
             wgrad_block(st, h1, d2, kPHid, lane, acc1, ab1);
             wgrad_block(st, h2, d3, kPOut, lane, acc2, ab2);
         }
-        if (!active) continue;
         // --- features -> the micro-triangle's grid vertices; along (b1, b2) -> the triangle ---
-        float dfu = 0.f, dfv = 0.f;
-        if (cpath) {
-            float* gt = a.grad_tex + static_cast<size_t>(tri) * V * kPCh;
+        double gw[9] = {0., 0., 0., 0., 0., 0., 0., 0., 0.};
+        if (active) {
+            float dfu = 0.f, dfv = 0.f;
+            if (cpath) {
+                float* gt = a.grad_tex + static_cast<size_t>(tri) * V * kPCh;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                if (m.w[q] == 0.0f) continue;
+                for (int q = 0; q < 3; ++q) {
+                    if (m.w[q] == 0.0f) continue;
 #pragma unroll
-                for (int c = 0; c < kPFeat; ++c)
-                    if (dfeat[c] != 0.0f) atomicAdd(&gt[m.idx[q] * kPCh + c], m.w[q] * dfeat[c]);
+                    for (int c = 0; c < kPFeat; ++c)
+                        if (dfeat[c] != 0.0f) atomicAdd(&gt[m.idx[q] * kPCh + c], m.w[q] * dfeat[c]);
+                }
+                // upright: w = (1 - fu - fv, fu, fv); inverted: w = (fu + fv - 1, 1 - fv, 1 - fu)
+#pragma unroll
+                for (int c = 0; c < kPFeat; ++c) {
+                    const float t0 = c < 4 ? (&tv[0][0].x)[c] : (&tv[0][1].x)[c - 4];
+                    const float t1 = c < 4 ? (&tv[1][0].x)[c] : (&tv[1][1].x)[c - 4];
+                    const float t2 = c < 4 ? (&tv[2][0].x)[c] : (&tv[2][1].x)[c - 4];
+                    dfu = __builtin_fmaf(dfeat[c], m.inv ? t0 - t2 : t1 - t0, dfu);
+                    dfv = __builtin_fmaf(dfeat[c], m.inv ? t0 - t1 : t2 - t0, dfv);
+                }
             }
-            // upright: w = (1 - fu - fv, fu, fv); inverted: w = (fu + fv - 1, 1 - fv, 1 - fu)
-#pragma unroll
-            for (int c = 0; c < kPFeat; ++c) {
-                const float t0 = c < 4 ? (&tv[0][0].x)[c] : (&tv[0][1].x)[c - 4];
-                const float t1 = c < 4 ? (&tv[1][0].x)[c] : (&tv[1][1].x)[c - 4];
-                const float t2 = c < 4 ? (&tv[2][0].x)[c] : (&tv[2][1].x)[c - 4];
-                dfu = __builtin_fmaf(dfeat[c], m.inv ? t0 - t2 : t1 - t0, dfu);
-                dfv = __builtin_fmaf(dfeat[c], m.inv ? t0 - t1 : t2 - t0, dfv);
-            }
+            vertex_grad(a.views[v], tr, a.verts + static_cast<size_t>(tri) * 9, x, y, E,
+                        static_cast<double>(dfu) * n, static_cast<double>(dfv) * n, ex, ey, gw);
         }
-        double gw[9];
-        vertex_grad(a.views[v], tr, a.verts + static_cast<size_t>(tri) * 9, x, y, E,
-                    static_cast<double>(dfu) * n, static_cast<double>(dfv) * n, ex, ey, gw);
-        double* gv = a.gvert + static_cast<size_t>(tri) * 9;
+        // --- the vertex gradient summed over each run of equal triangles among the
+        // wave's lanes (neighbouring pixels of a row mostly share their winner), one
+        // set of float64 atomics per run ---
+        if (__ballot(active)) {
+            const uint32_t tk = active ? tri : 0xFFFFFFFFu;
+            const uint32_t tp = static_cast<uint32_t>(__shfl_up(static_cast<int>(tk), 1, 64));
+            const bool head = lane == 0 || tp != tk;
+            const uint64_t heads = __ballot(head);
+            double* sd = reinterpret_cast<double*>(&st[0][0][0]);   // [9][64], within the stage
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-            if (gw[k] != 0.0) atomicAdd(&gv[k], gw[k]);
+            for (int k = 0; k < 9; ++k) sd[k * 64 + lane] = gw[k];
+            wave_fence();
+            if (head && active) {
+                const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+                const int end = above ? __builtin_ctzll(above) : 64;
+                double acc[9] = {0., 0., 0., 0., 0., 0., 0., 0., 0.};
+                for (int l = lane; l < end; ++l)
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) acc[k] += sd[k * 64 + l];
+                double* gv = a.gvert + static_cast<size_t>(tri) * 9;
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    if (acc[k] != 0.0) atomicAdd(&gv[k], acc[k]);
+            }
+            wave_fence();
+        }
     }
     // the wave's partial row of the MLP gradient (D[4 grp + i][col] of each block)
     float* row = a.mlp_partial + static_cast<size_t>(blockIdx.x * 4 + w) * kPParams;
