@@ -25,6 +25,12 @@ namespace {
 
 constexpr float kC1 = 0.0001f;  // 0.01^2
 constexpr float kC2 = 0.0009f;  // 0.03^2
+// The window statistics are formed from values shifted by this constant
+// (colours and targets live in [0, 1]): variances and covariances do not
+// change under a shift, and sigma^2 = E[x^2] - mu^2 then cancels far fewer
+// digits in float32 (E[(x - 1/2)^2] <= 1/4 against E[x^2] <= 1). Padding
+// outside the image is the shifted zero, -1/2; the means are shifted back.
+constexpr float kShift = 0.5f;
 
 // Both SSIM passes work on 32 x 8 pixel tiles, one thread per pixel. The
 // tile plus its 5-pixel halo is staged in LDS (zeros outside the image: the
@@ -47,8 +53,8 @@ __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict
         const bool ok = gx >= 0 && gx < W && gy >= 0 && gy < H;
         const int64_t q = ok ? static_cast<int64_t>(gy) * W + gx : 0;
         for (int c = 0; c < 3; ++c) {
-            in[r][cc][c] = ok ? color[q * 3 + c] : 0.0f;
-            in[r][cc][3 + c] = ok ? target[q * 3 + c] : 0.0f;
+            in[r][cc][c] = (ok ? color[q * 3 + c] : 0.0f) - kShift;
+            in[r][cc][3 + c] = (ok ? target[q * 3 + c] : 0.0f) - kShift;
         }
     }
     __syncthreads();
@@ -83,18 +89,20 @@ __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict
         const int64_t p = static_cast<int64_t>(y) * W + x;
         float* st = stats + p * 12;
         for (int c = 0; c < 3; ++c) {
-            const float mx = sm[c], my = sm[3 + c];
-            const float vx = sm[6 + c] - mx * mx, vy = sm[9 + c] - my * my, cxy = sm[12 + c] - mx * my;
+            const float sx = sm[c], sy = sm[3 + c];   // shifted means
+            const float vx = sm[6 + c] - sx * sx, vy = sm[9 + c] - sy * sy, cxy = sm[12 + c] - sx * sy;
+            const float mx = sx + kShift, my = sy + kShift;
             const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
             const float B1 = mx * mx + my * my + kC1, B2 = vx + vy + kC2;
             const float S = (A1 * A2) / (B1 * B2);
             const float dS_dmx = 2.0f * my * A2 / (B1 * B2) - S * 2.0f * mx / B1;
             const float dS_dvx = -S / B2;
             const float dS_dcxy = 2.0f * A1 / (B1 * B2);
-            st[c] = dS_dmx - 2.0f * mx * dS_dvx - my * dS_dcxy;
+            // G1 in shifted coordinates: the gradient pass pairs it with shifted values
+            st[c] = dS_dmx - 2.0f * sx * dS_dvx - sy * dS_dcxy;
             st[3 + c] = dS_dvx;
             st[6 + c] = dS_dcxy;
-            const float d = in[ly + kSsimR][lx + kSsimR][c] - in[ly + kSsimR][lx + kSsimR][3 + c];
+            const float d = color[p * 3 + c] - target[p * 3 + c];
             share += lam * fabsf(d) + (1.0f - lam) * (1.0f - S);
         }
         share *= inv_n;
@@ -160,7 +168,7 @@ __global__ void __launch_bounds__(256) ssim_grad_kernel(const float* __restrict_
         const float a = color[p * 3 + c], b = target[p * 3 + c];
         const float d = a - b;
         const float sgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-        const float dssim = sm[c] + 2.0f * a * sm[3 + c] + b * sm[6 + c];
+        const float dssim = sm[c] + 2.0f * (a - kShift) * sm[3 + c] + (b - kShift) * sm[6 + c];
         grad_color[p * 3 + c] = inv_n * (lam * sgn - (1.0f - lam) * dssim);
     }
 }
