@@ -587,8 +587,21 @@ def main():
             log(f"serving sweep {rate}/s: {sweep[-1]}")
             if st["throughput_rps"] is None or st["throughput_rps"] < 0.9 * rate:
                 break   # saturated
+        # the same arrivals with a memory budget that fits two of the largest requests
+        # (1920x1080 on the 100k-triangle soup), so that admission binds
+        big = max(SV.request_bytes(w, h, sc.T) for w, h in W.SERVING_RES for sc in soups)
+        srv_b = SV.Server(soups, tile=None, n_streams=2, max_batch=16, budget_bytes=2 * big)
+        srv_b.tile_by_res = dict(srv.tile_by_res)
+        SV.run(srv_b, W.serving_requests(200.0, 1.0, seed=98))
+        bind_st = SV.run(srv_b, W.serving_requests(200.0, args.serve_seconds / 2, seed=97))
+        burst = SV.run(srv_b, [W.Request(0.0, r.soup, r.view) for r in W.serving_requests(200.0, 0.5, seed=96)])
+        log(f"serving 200/s, budget of two requests: {bind_st}; burst: {burst}")
+        serving_bind = {"budget_bytes": srv_b.budget, "largest_request_bytes": big, "rate_hz": 200, **bind_st,
+                        "burst_of_100": burst}
+        del srv_b
         serving = {"workload": "4 soups (20k/40k/70k/100k triangles), 8x8x16 features, MLP 16->32->32->4, "
                                "threshold mode, 640x360/1280x720/1920x1080 uniform, Poisson arrivals",
+                   "budget_of_two_requests": serving_bind,
                    "rate_hz": 200, "duration_s": args.serve_seconds, "streams": 2, "max_batch": 16,
                    "budget_fraction": args.serve_budget, "budget_bytes": srv.budget,
                    "tiles": {f"{w}x{h}": t for (w, h), t in srv.tile_by_res.items()},

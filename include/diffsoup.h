@@ -164,6 +164,11 @@ soup_status soup_read_timings(soup_ctx* ctx, double* ms, int64_t* count);
 soup_status soup_ctx_set_static(soup_ctx* ctx, int32_t on);
 soup_status soup_ctx_check(soup_ctx* ctx);
 
+/* Device bytes the context's workspaces hold now (they grow on demand and
+ * are released by soup_ctx_destroy): what a caller that admits work by
+ * memory has to count besides its own buffers. */
+soup_status soup_ctx_workspace_bytes(const soup_ctx* ctx, int64_t* bytes);
+
 /* Enable (1) or disable (0, default) counting of decodes in soup_stats. */
 soup_status soup_ctx_set_counting(soup_ctx* ctx, int32_t on);
 soup_status soup_last_stats(const soup_ctx* ctx, soup_stats* out);

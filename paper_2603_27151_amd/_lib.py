@@ -56,7 +56,8 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings", "soup_ctx_set_static",
            "soup_ctx_check", "soup_coverage_count", "soup_edge_lengths", "soup_adaptive_plan",
            "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step", "soup_loss_l1_ssim_noalloc",
-           "soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd"]
+           "soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd",
+           "soup_ctx_workspace_bytes"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
                 "adaptive_apply", "train_loss", "adam", "shade", "assemble", "assemble_bwd"]
@@ -113,7 +114,9 @@ def lib() -> C.CDLL:
                                  P, P, P, P, P, P, P, P]
     L.soup_mc_assemble.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
     L.soup_mc_assemble_bwd.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_int32, P]
-    for name in ["soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd"]:
+    L.soup_ctx_workspace_bytes.argtypes = [P, C.POINTER(C.c_int64)]
+    for name in ["soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd",
+                 "soup_ctx_workspace_bytes"]:
         getattr(L, name).restype = C.c_int
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
@@ -254,6 +257,11 @@ class Ctx:
         cnt = (C.c_int64 * n)()
         self.check(lib().soup_read_timings(self.p, ms, cnt))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
+
+    def workspace_bytes(self) -> int:
+        n = C.c_int64(0)
+        self.check(lib().soup_ctx_workspace_bytes(self.p, C.byref(n)))
+        return int(n.value)
 
     def stats(self) -> dict:
         s = soup_stats()

@@ -323,7 +323,10 @@ soup_status bin(soup_ctx* c, Plan& p, const Opts& o, hipStream_t s) {
         (st = ensure(c, c->recs, static_cast<size_t>(p.n_recs) * sizeof(TriRec))) ||
         (st = ensure(c, c->tile_count, static_cast<size_t>(p.n_tiles) * 4)) ||
         (st = ensure(c, c->tile_fill, static_cast<size_t>(p.n_tiles) * 4)) ||
-        (st = ensure(c, c->chunk_base, static_cast<size_t>(bin_chunks(p.maxT, chunk)) * p.n_tiles * 4)) ||
+        // per-chunk tile slots exist only for the LDS-histogram chunks (a small render's
+        // one-triangle-per-thread chunks count with global atomics and need none)
+        (st = ensure(c, c->chunk_base,
+                     chunk >= kBinChunk ? static_cast<size_t>(bin_chunks(p.maxT, chunk)) * p.n_tiles * 4 : 0)) ||
         (st = ensure(c, c->tile_start, static_cast<size_t>(p.n_tiles + 1) * 8)) ||
         (st = ensure(c, c->bsum, static_cast<size_t>((p.n_tiles + 1023) / 1024 + 1) * 8)) ||
         (st = ensure(c, c->counters, 128)) || (st = ensure(c, c->flags, 256)) ||
@@ -662,6 +665,20 @@ soup_status soup_ctx_check(soup_ctx* c) {
 soup_status soup_ctx_set_counting(soup_ctx* c, int32_t on) {
     if (!c) return SOUP_ERR_INVALID;
     c->counting = on != 0;
+    return SOUP_OK;
+}
+
+soup_status soup_ctx_workspace_bytes(const soup_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return SOUP_ERR_INVALID;
+    const DevBuf* bufs[] = {&c->views,     &c->scenes,    &c->recs,          &c->tile_count,  &c->tile_fill,
+                            &c->tile_start, &c->bsum,      &c->entries,       &c->edge_w,      &c->partial,
+                            &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
+                            &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
+                            &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff, &c->ssim,
+                            &c->chunk_base, &c->frag_gates, &c->sorted_gates, &c->gvert};
+    int64_t n = 0;
+    for (const DevBuf* b : bufs) n += static_cast<int64_t>(b->bytes);
+    *bytes = n;
     return SOUP_OK;
 }
 

@@ -45,11 +45,15 @@ class Batch:
 
 
 def request_bytes(width: int, height: int, n_tris: int) -> int:
-    """Device bytes a request holds while in flight: its colour output
-    (12 B/px), the per-pixel visibility keys (8 B/px), an allowance for tile
-    lists (16 B/px) and its triangle setup records (64 B per triangle)."""
+    """Device bytes a request needs while in flight, an upper bound: its
+    colour output (12 B/px) and an allowance of 8 B/px for the per-tile
+    counters and offsets and, in large batches, the binning chunks' per-tile
+    slots; 128 B per triangle for its 64-byte setup record and its tile-list
+    entries (the library's workspaces grow with 25% headroom). The GPU tests
+    check it against what a render actually allocates: its colour buffer
+    plus the workspaces of a fresh context."""
     P = int(width) * int(height)
-    return P * (12 + 8 + 16) + int(n_tris) * 64
+    return P * (12 + 8) + int(n_tris) * 128
 
 
 class Scheduler:
@@ -64,6 +68,8 @@ class Scheduler:
         self.queue: collections.deque = collections.deque()
         self.slots: List[Optional[Batch]] = [None] * n_slots
         self.in_use = 0
+        self.peak_in_use = 0          # the largest in_use seen after a launch
+        self.peak_in_flight = 0       # ... and the most requests in flight at once
         self.batches = 0
         self.batch_sizes: List[int] = []
 
@@ -111,6 +117,9 @@ class Scheduler:
                 self.slots[i] = Batch(batch, need, self._launch(i, batch))
                 self.batches += 1
                 self.batch_sizes.append(len(batch))
+                self.peak_in_use = max(self.peak_in_use, self.in_use)
+                self.peak_in_flight = max(self.peak_in_flight,
+                                          sum(len(b.tickets) for b in self.slots if b is not None))
         return finished
 
 
@@ -123,7 +132,8 @@ class Server:
     takes the tile of its largest request."""
 
     def __init__(self, soups, tile: Optional[int] = 16, n_streams: int = 2, max_batch: int = 16,
-                 budget_fraction: float = 0.25, opts=None, keep_colors: bool = False):
+                 budget_fraction: float = 0.25, opts=None, keep_colors: bool = False,
+                 budget_bytes: Optional[int] = None):
         import torch
         from . import _lib
         from . import raster as R
@@ -141,7 +151,7 @@ class Server:
             self.ctxs.append(c)
         self.ctx_tile = [tile if tile is not None else 16] * n_streams
         free, _total = torch.cuda.mem_get_info()
-        self.budget = int(budget_fraction * free)
+        self.budget = int(budget_bytes) if budget_bytes is not None else int(budget_fraction * free)
         self.t0 = time.perf_counter()
         self.sched = Scheduler(n_streams, max_batch, self.budget, self._launch, self._done, self._finish,
                                self.clock)
@@ -216,6 +226,20 @@ class Server:
             for t, c in zip(tickets, handle[1]):
                 t.color = c
 
+    def measure_request(self, soup: int, view) -> int:
+        """Device bytes one render of this request allocates: its colour
+        buffer plus what it grows a fresh context's workspaces to."""
+        torch, R = self.torch, self.R
+        from . import _lib
+        ctx = _lib.Ctx(torch.cuda.current_device())
+        ctx.set_tile(self.tile_for([Ticket(0, soup, view, 0.0, 0)]))
+        c = torch.empty(view.height, view.width, 3, dtype=torch.float32, device="cuda")
+        R.render([self.soups[soup]], R.Views.from_list([view]), self.opts, [c], ctx=ctx)
+        torch.cuda.synchronize()
+        n = ctx.workspace_bytes() + c.numel() * 4
+        ctx.close()
+        return n
+
     def render_alone(self, soup: int, view):
         """One request in its own call (reference for batching invariance)."""
         torch, R = self.torch, self.R
@@ -261,4 +285,6 @@ def run(server: Server, requests: Sequence, warmup_s: float = 0.0) -> Dict:
         "mpixel_s": round(px / dur / 1e6, 1) if dur > 0 else None,
         "batches": len(sizes),
         "mean_batch": round(float(np.mean(sizes)), 2) if sizes else None,
+        "peak_in_use_bytes": sched.peak_in_use,
+        "peak_in_flight": sched.peak_in_flight,
     }

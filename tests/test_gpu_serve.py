@@ -85,3 +85,57 @@ def test_tuned_tiles_keep_results():
     ref = SV.Server(soups, tile=16, n_streams=1, max_batch=1)
     for t in done:
         assert torch.equal(t.color, ref.render_alone(t.soup, t.view)), f"request {t.rid} differs"
+
+
+def test_request_bytes_bounds_what_a_render_allocates():
+    """request_bytes (the admission's per-request charge) against the bytes a
+    render really allocates: its colour buffer plus the workspaces it grows
+    a fresh context to, for every soup and resolution of the workload."""
+    from paper_2603_27151_amd import raster as R
+    from paper_2603_27151_amd import serve as SV
+    soups = [R.DeviceScene.from_host(s) for s in W.serving_soups()]
+    srv = SV.Server(soups, tile=16, n_streams=1, max_batch=1)
+    for soup in range(len(soups)):
+        for (w, h) in W.SERVING_RES:
+            v = W.View(w, h, 3, W.view_proj((0.4, 0.2, 3.0), w, h))
+            actual = srv.measure_request(soup, v)
+            est = srv.need(soup, v)
+            _say(f"soup {soup} ({soups[soup].T} triangles) {w}x{h}: allocated {actual} B, charged {est} B "
+                 f"({actual / est:.2f})")
+            assert actual <= est
+            assert actual >= 0.4 * est
+
+
+def test_admission_budget_binds_and_results_hold():
+    """A budget that fits about two requests: a burst of 24 requests is
+    admitted at most two at a time, the charged bytes in flight never exceed
+    the budget, and every request still equals its lone render."""
+    from paper_2603_27151_amd import raster as R
+    from paper_2603_27151_amd import serve as SV
+    soups = [R.DeviceScene.from_host(s) for s in W.serving_soups()]
+    rng = np.random.default_rng(21)
+    views = []
+    for i in range(24):
+        w, h = W.SERVING_RES[i % 2]                # 640x360 and 1280x720
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        views.append((int(rng.integers(0, len(soups))), W.View(w, h, 500 + i, W.view_proj(3.0 * d, w, h))))
+    needs = [SV.request_bytes(v.width, v.height, soups[s].T) for s, v in views]
+    budget = int(max(needs) * 2.05)
+    srv = SV.Server(soups, tile=16, n_streams=2, max_batch=16, keep_colors=True, budget_bytes=budget)
+    _say(f"case: burst of {len(views)} requests, budget {budget} B, largest request {max(needs)} B")
+    for i, (s, v) in enumerate(views):
+        srv.sched.submit(SV.Ticket(i, s, v, 0.0, srv.need(s, v)))
+    done = []
+    while srv.sched.busy:
+        done += srv.sched.poll()
+        assert srv.sched.in_use <= budget
+    assert len(done) == len(views)
+    sizes = srv.sched.batch_sizes
+    _say(f"batches {len(sizes)}, sizes {sizes}, peak in flight {srv.sched.peak_in_flight}, "
+         f"peak charged {srv.sched.peak_in_use} B")
+    assert srv.sched.peak_in_use <= budget
+    assert 2 <= srv.sched.peak_in_flight <= 3       # about two requests' worth at a time
+    assert len(sizes) > len(views) / 3              # admission split the burst
+    for t in done:
+        assert torch.equal(t.color, srv.render_alone(t.soup, t.view)), f"request {t.rid} differs"

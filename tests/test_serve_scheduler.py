@@ -97,7 +97,7 @@ def test_arrivals_during_a_batch_join_the_next_launch_on_the_other_slot():
 
 
 def test_request_bytes_counts_outputs_and_setup():
-    assert SV.request_bytes(1920, 1080, 100_000) == 1920 * 1080 * 36 + 100_000 * 64
+    assert SV.request_bytes(1920, 1080, 100_000) == 1920 * 1080 * 20 + 100_000 * 128
 
 
 def test_poisson_arrivals_match_the_rate():
