@@ -770,7 +770,7 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
         if (c->frag_regions != nr || c->frag_region == 0)
             return fail(c, SOUP_ERR_CAPACITY, "static mode: no fragment list sized for this call; run it once "
                         "outside static mode");
-        if (want_gates && c->frag_gates.bytes < static_cast<size_t>(c->frag_region) * nr * gw * 4)
+        if (want_gates && c->frag_gates.bytes < static_cast<size_t>(c->frag_region) * nr * gate_stride(gw) * 4)
             return fail(c, SOUP_ERR_CAPACITY, "static mode: no gate list sized for this call; run it once "
                         "outside static mode");
         launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
@@ -785,7 +785,8 @@ soup_status replay(soup_ctx* c, const Plan& p, const RasterArgs& a, const uint64
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (region >= (uint64_t(1) << 31)) return fail(c, SOUP_ERR_CAPACITY, "fragment region too large");
         if ((st = ensure(c, c->frags, static_cast<size_t>(region) * nr * sizeof(FragRec)))) return st;
-        if (want_gates && (st = ensure(c, c->frag_gates, static_cast<size_t>(region) * nr * gw * 4))) return st;
+        if (want_gates && (st = ensure(c, c->frag_gates, static_cast<size_t>(region) * nr * gate_stride(gw) * 4)))
+            return st;
         {
             Timed t(c, SOUP_T_FILL, s);
             launch_fill_i32(reinterpret_cast<int32_t*>(a.work), 1, 0, s);
@@ -993,13 +994,14 @@ soup_status soup_rasterize_bwd(soup_ctx* c, const soup_scene* scene, const soup_
     const int gw = gate_words(p.kind);
     if (!c->frags_gated) {
         // replayed fragments: their ReLU gates from a decode in the forward's arithmetic
-        if ((st = ensure(c, c->frag_gates, static_cast<size_t>(frag_cap) * gw * 4))) return st;
+        if ((st = ensure(c, c->frag_gates, static_cast<size_t>(frag_cap) * gate_stride(gw) * 4))) return st;
         Timed t(c, SOUP_T_REPLAY, s);
         launch_fragment_gates(decode_args(c, p, a), p.kind, static_cast<uint32_t*>(c->frag_gates.p), s);
         c->frags_gated = true;
     }
     if ((st = ensure(c, c->sorted, static_cast<size_t>(frag_cap) * sizeof(FragRec)))) return st;
-    if (c->frags_gated && (st = ensure(c, c->sorted_gates, static_cast<size_t>(frag_cap) * gw * 4))) return st;
+    if (c->frags_gated && (st = ensure(c, c->sorted_gates, static_cast<size_t>(frag_cap) * gate_stride(gw) * 4)))
+        return st;
     {
         Timed t(c, SOUP_T_GRAD, s);
         launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
@@ -1193,12 +1195,20 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
                           c->log_mode == o.mode;
     const int T = scene->T;
     const int64_t n_tex = static_cast<int64_t>(T) * mc_count(scene->R) * kPCh;
-    const int nb = pwinner_blocks(c->num_cus);
-    const int rows = nb * 4;
+    // the triangle-sorted path keeps one triangle's texture gradient per wave in LDS
+    // (18 KB at R = 5); a texture too large for that takes the per-pixel path with
+    // global atomics
+    const bool sorted_path = ptri_bwd_lds(scene->R) <= 65536;
+    const int nb = sorted_path ? ptri_blocks(c->num_cus, scene->R) : pwinner_blocks(c->num_cus);
+    const int rows = sorted_path ? nb : nb * 4;
     if ((st = ensure(c, c->edge_w, static_cast<size_t>(p.n_pix) * sizeof(float2))) ||
         (st = ensure(c, c->partial, static_cast<size_t>(rows) * kPParams * 4)) ||
         (st = ensure(c, c->mlp_mid, static_cast<size_t>(mlp_reduce_mid_rows(rows)) * kPParams * 8)) ||
-        (st = ensure(c, c->gvert, static_cast<size_t>(T) * 9 * sizeof(double))))
+        (st = ensure(c, c->gvert, static_cast<size_t>(T) * 9 * sizeof(double))) ||
+        (st = ensure(c, c->tri_count, static_cast<size_t>(T) * 4)) ||
+        (st = ensure(c, c->tri_fill, static_cast<size_t>(T) * 8)) ||
+        (st = ensure(c, c->tri_off, static_cast<size_t>(T + 1) * 8)) ||
+        (st = ensure(c, c->tri_bsum, static_cast<size_t>((T + 1023) / 1024 + 1) * 8)))
         return st;
     RasterArgs a = raster_args(c, p, o);
     const float2* ew = nullptr;
@@ -1212,26 +1222,73 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
         if (!o.accumulate) launch_fill_f32(grad_tex, n_tex, 0.0f, s);
         launch_fill_i32(static_cast<int32_t*>(c->gvert.p), static_cast<int64_t>(T) * 18, 0, s);
     }
-    if (o.mode == 0 && grad_logp) {
-        // the score term (Eq. (9)): every fragment in front of a winner, and the winner
+    const float* gl = o.mode == 0 ? grad_logp : nullptr;
+    if (sorted_path) {
+        // every winner and, where the pixel carries a score weight, every fragment in
+        // front of it (Eq. (9)), sorted by triangle
         int64_t n_frag = 0, n_batch = 0;
-        if ((st = replay(c, p, a, vis, grad_color, grad_logp, nullptr, false, nullptr, 0, s, &n_frag, &n_batch,
-                         from_log)))
+        if ((st = replay(c, p, a, vis, grad_color, gl, ew, false, static_cast<int32_t*>(c->tri_count.p), T, s,
+                         &n_frag, &n_batch, from_log)))
             return st;
-        Timed t(c, SOUP_T_GRAD, s);
-        PFragArgs fa{};
-        fa.frags = static_cast<FragRec*>(c->frags.p);
-        fa.region = static_cast<uint32_t>(c->frag_region);
-        fa.counts = static_cast<uint32_t*>(c->region_counts.p);
-        fa.boff = static_cast<uint32_t*>(c->region_boff.p);
-        fa.n_regions = c->frag_regions;
-        fa.tex = scene->tex;
-        fa.R = scene->R;
-        fa.grad_tex = grad_tex;
-        fa.n_blocks = decode_blocks(c);
-        launch_pfrag(fa, false, s);
-    }
-    {
+        const int64_t frag_cap = static_cast<int64_t>(c->frag_regions) * static_cast<int64_t>(c->frag_region);
+        if ((st = ensure(c, c->sorted, static_cast<size_t>(frag_cap) * sizeof(FragRec)))) return st;
+        {
+            Timed t(c, SOUP_T_GRAD, s);
+            launch_scan(static_cast<int32_t*>(c->tri_count.p), T, static_cast<int64_t*>(c->tri_bsum.p),
+                        static_cast<int64_t*>(c->tri_off.p), s);
+            launch_fill_i32(static_cast<int32_t*>(c->tri_fill.p), 2 * T, 0, s);
+            PlaceArgs pa{};
+            pa.frags = static_cast<FragRec*>(c->frags.p);
+            pa.region = static_cast<uint32_t>(c->frag_region);
+            pa.counts = static_cast<uint32_t*>(c->region_counts.p);
+            pa.boff = static_cast<uint32_t*>(c->region_boff.p);
+            pa.n_regions = c->frag_regions;
+            pa.tri_off = static_cast<int64_t*>(c->tri_off.p);
+            pa.tri_fill = static_cast<unsigned long long*>(c->tri_fill.p);
+            pa.sorted = static_cast<FragRec*>(c->sorted.p);
+            pa.n_blocks = decode_blocks(c);
+            launch_place(pa, s);
+        }
+        Timed t(c, SOUP_T_BWD, s);
+        PTriArgs ta{};
+        ta.views = a.views;
+        ta.recs = a.recs;
+        ta.verts = scene->verts;
+        ta.tex = scene->tex;
+        ta.mlp = scene->mlp;
+        ta.R = scene->R;
+        ta.T = T;
+        ta.sorted = static_cast<FragRec*>(c->sorted.p);
+        ta.tri_off = static_cast<int64_t*>(c->tri_off.p);
+        ta.grad_color = grad_color;
+        ta.edge_w = ew;
+        ta.score = gl ? 1 : 0;
+        ta.accumulate = o.accumulate;
+        ta.grad_tex = grad_tex;
+        ta.gvert = static_cast<double*>(c->gvert.p);
+        ta.mlp_partial = static_cast<float*>(c->partial.p);
+        ta.n_blocks = nb;
+        launch_ptri_bwd(ta, s);
+    } else {
+        if (gl) {
+            // the score term (Eq. (9)): every fragment in front of a winner, and the winner
+            int64_t n_frag = 0, n_batch = 0;
+            if ((st = replay(c, p, a, vis, grad_color, gl, nullptr, false, nullptr, 0, s, &n_frag, &n_batch,
+                             from_log)))
+                return st;
+            Timed t(c, SOUP_T_GRAD, s);
+            PFragArgs fa{};
+            fa.frags = static_cast<FragRec*>(c->frags.p);
+            fa.region = static_cast<uint32_t>(c->frag_region);
+            fa.counts = static_cast<uint32_t*>(c->region_counts.p);
+            fa.boff = static_cast<uint32_t*>(c->region_boff.p);
+            fa.n_regions = c->frag_regions;
+            fa.tex = scene->tex;
+            fa.R = scene->R;
+            fa.grad_tex = grad_tex;
+            fa.n_blocks = decode_blocks(c);
+            launch_pfrag(fa, false, s);
+        }
         Timed t(c, SOUP_T_BWD, s);
         PWinArgs wa{};
         wa.views = a.views;

@@ -234,7 +234,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             nx = fr.x;
             if (use_gates) {
 #pragma unroll
-                for (int k = 0; k < GW; ++k) ngate[k] = a.sorted_gates[fi * GW + k];
+                for (int k = 0; k < GW; k += 2) {   // 8-byte units of the padded gate record
+                    const uint2 g = reinterpret_cast<const uint2*>(a.sorted_gates)[fi * (gate_stride(GW) / 2) + k / 2];
+                    ngate[k] = g.x;
+                    if (k + 1 < GW) ngate[k + 1] = g.y;
+                }
             }
         }
     };
@@ -818,7 +822,9 @@ __global__ __launch_bounds__(256) void fragment_gates_kernel(DecodeArgs a, uint3
         uint32_t g[GW];
         mlp_logits_gates<S>(as_const(opaque_ptr(a.mlp)), x, o, g);
 #pragma unroll
-        for (int k = 0; k < GW; ++k) gates_out[at * GW + k] = g[k];
+        for (int k = 0; k < GW; k += 2)   // the padded gate record, 8 bytes at a time
+            reinterpret_cast<uint2*>(gates_out)[at * (gate_stride(GW) / 2) + k / 2] =
+                make_uint2(g[k], k + 1 < GW ? g[k + 1] : 0u);
     }
 }
 

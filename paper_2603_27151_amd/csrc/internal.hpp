@@ -67,6 +67,9 @@ struct RasterArgs {
 int gate_words(MlpKind k);
 // Words of one log_aux record: depth bits, view and the gates, rounded up to an even count.
 __host__ __device__ constexpr int aux_words(int gate_words) { return (2 + gate_words + 1) & ~1; }
+// Words per fragment in the gate arrays beside the fragment lists: the gates padded to an
+// even count, so that every copy moves 8-byte units.
+__host__ __device__ constexpr int gate_stride(int gate_words) { return (gate_words + 1) & ~1; }
 
 void launch_raster_fwd(const RasterArgs& a, int tile, MlpKind k, hipStream_t s);
 // Resident single-wave workgroups per CU of the forward kernel for a tile side, MLP shape and
@@ -115,7 +118,8 @@ void launch_replay(const ReplayArgs& a, int tile, hipStream_t s);
 struct CollectArgs {
     const uint4* log_frag;
     const uint2* log_aux;          // aux_words(gate_words) words per logged fragment
-    uint32_t* frag_gates;          // the log's ReLU gates of every kept fragment (same slots as frags), or null
+    uint32_t* frag_gates;          // the log's ReLU gates of every kept fragment (same slots as frags, gate_stride
+                                   // words each), or null
     int gate_words;
     uint32_t log_region;
     const uint32_t* log_counts;    // [log_regions]
@@ -276,6 +280,28 @@ struct PWinArgs {
     float* mlp_partial;              // [n_blocks * 4, 595]
     int n_blocks;
 };
+struct PTriArgs {
+    const ViewDesc* views;
+    const TriRec* recs;
+    const float* verts;
+    const float* tex;
+    const float* mlp;
+    int R;
+    int T;
+    const FragRec* sorted;           // [tri_off[T]] the fragment list sorted by triangle
+    const int64_t* tri_off;          // [T + 1]
+    const float* grad_color;
+    const float2* edge_w;            // or null
+    int score;                       // 1: the score term (mode 0 with score weights)
+    int accumulate;                  // 1: add into grad_tex rows (else they were zero-filled)
+    float* grad_tex;
+    double* gvert;                   // [T, 9] float64 sums (zeroed by the caller)
+    float* mlp_partial;              // [n_blocks, 595]
+    int n_blocks;                    // single-wave workgroups, a multiple of 8
+};
+size_t ptri_bwd_lds(int R);
+int ptri_blocks(int num_cus, int R);
+void launch_ptri_bwd(const PTriArgs& a, hipStream_t s);
 int pwinner_blocks(int num_cus);
 void launch_pwinner_bwd(const PWinArgs& a, hipStream_t s);
 void launch_pvert_finish(const double* g, float* out, int64_t n, bool accumulate, hipStream_t s);

@@ -692,6 +692,274 @@ void launch_pwinner_bwd(const PWinArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(pwinner_bwd_kernel, dim3(static_cast<unsigned>(a.n_blocks)), dim3(256), 0, s, a);
 }
 
+// ---------------------------------------------------------------------------
+// backward over the triangle-sorted fragment list
+// ---------------------------------------------------------------------------
+
+// One wave per workgroup walks a contiguous range of the fragment list sorted
+// by triangle (every winner, and the fragments in front of it where the pixel
+// carries a score weight), 64 fragments per batch, and keeps the gradient of
+// the current triangle's texture (V x 8 floats) and its nine float64 vertex
+// sums in its LDS. Per fragment: its opacity lookup and the score term;
+// per winner also the colour path of pwinner_bwd_kernel (recompute, blend,
+// MLP data backward on the VALU, features onto the three grid vertices, the
+// float64 vertex chain with the edge term) and the MLP weight gradient on the
+// matrix cores. Adds into the row are LDS float atomics (two fragments of a
+// run may share a grid vertex). When the triangle changes, the row's nonzero
+// entries go to HBM: plain stores when the wave holds all of the triangle's
+// fragments, float atomics when the triangle straddles two waves' ranges.
+__global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
+    __shared__ __align__(16) float stage[2][kPIn][kPStage];
+    __shared__ double vsum[9];
+    extern __shared__ __align__(16) float row[];   // [V][8]: the current triangle's texture gradient
+    const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
+    float (*st)[kPIn][kPStage] = stage;
+    const int R = a.R, n = 1 << R, V = mc_count(R), NR = V * kPCh;
+    cfloat* mp = as_const(a.mlp);
+    gfloat* tex = as_global(a.tex);
+    const int64_t E = a.tri_off[a.T];
+    const int64_t nb = (E + 63) / 64;
+    const int64_t nw = gridDim.x;
+    const int64_t wid = xcd_block();
+    const int64_t bbeg = nb * wid / nw, bend = nb * (wid + 1) / nw;
+    const int64_t f0 = bbeg * 64, f1 = bend * 64 < E ? bend * 64 : E;
+    for (int k = lane; k < NR; k += 64) row[k] = 0.0f;
+    if (lane < 9) vsum[lane] = 0.0;
+    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+    float ab0 = 0.f, ab1 = 0.f, ab2 = 0.f;
+    int cur = -1;   // triangle held in the row (wave-uniform)
+    // the row's nonzero entries go out and are cleared
+    auto flush = [&](int t) __attribute__((always_inline)) {
+        wave_fence();
+        const bool owned = a.tri_off[t] >= f0 && a.tri_off[t + 1] <= f1;
+        float* g = a.grad_tex + static_cast<size_t>(t) * NR;
+        for (int k = lane; k < NR; k += 64) {
+            const float v = row[k];
+            if (v != 0.0f) {
+                row[k] = 0.0f;
+                if (owned) g[k] = a.accumulate ? g[k] + v : v;   // the row was zero-filled unless accumulating
+                else atomicAdd(&g[k], v);
+            }
+        }
+        if (lane < 9) {
+            const double v = vsum[lane];
+            vsum[lane] = 0.0;
+            if (v != 0.0) atomicAdd(&a.gvert[static_cast<size_t>(t) * 9 + lane], v);
+        }
+        wave_fence();
+    };
+    for (int64_t b = bbeg; b < bend; ++b) {
+        const int64_t fi = b * 64 + lane;
+        const bool on = fi < E;
+        FragRec fr = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
+        if (on) fr = a.sorted[fi];
+        const uint32_t tri = on ? (fr.p0.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
+        const bool win = on && (fr.p0.y >> 31) != 0u;
+        const float gl = a.score ? __uint_as_float(fr.x.x) : 0.0f;
+        const float b1 = __uint_as_float(fr.p1.x), b2 = __uint_as_float(fr.p1.y);
+        Micro m{};
+        float alpha = 1.0f;
+        if (on) {
+            m = micro_of(n, b1, b2);
+            gfloat* t7 = tex + static_cast<size_t>(tri) * NR + (kPCh - 1);
+            alpha = mc_mix(m, t7[m.idx[0] * kPCh], t7[m.idx[1] * kPCh], t7[m.idx[2] * kPCh]);
+        }
+        // d log p / d alpha: 1 / alpha for the winner, -1 / (1 - alpha) in front of it
+        const float da = gl == 0.0f ? 0.0f : (win ? gl / alpha : -gl / (1.0f - alpha));
+        // --- the winner's colour path ---
+        float gc[3] = {0.f, 0.f, 0.f};
+        float ex = 0.f, ey = 0.f;
+        int x = 0, y = 0, v = 0;
+        if (win) {
+            const uint32_t p = fr.p0.x;
+            gc[0] = a.grad_color[3 * static_cast<size_t>(p)];
+            gc[1] = a.grad_color[3 * static_cast<size_t>(p) + 1];
+            gc[2] = a.grad_color[3 * static_cast<size_t>(p) + 2];
+            if (a.edge_w) {
+                const float2 e = a.edge_w[p];
+                ex = e.x;
+                ey = e.y;
+            }
+            v = static_cast<int>(fr.x.y);
+            const ViewDesc& vd = a.views[v];
+            const uint32_t local = p - static_cast<uint32_t>(vd.pix_base);
+            y = static_cast<int>(local / static_cast<uint32_t>(vd.W));
+            x = static_cast<int>(local - static_cast<uint32_t>(y) * static_cast<uint32_t>(vd.W));
+        }
+        const bool cpath = win && (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f);
+        const bool vpath = cpath || (win && (ex != 0.f || ey != 0.f));
+        float in[kPIn], h1[kPHid], h2[kPHid], d1[kPHid], d2[kPHid], d3[kPOut];
+        float dfeat[kPFeat];
+        float4 tv[3][2];
+#pragma unroll
+        for (int u = 0; u < kPHid; ++u) {
+            in[u] = 0.f;
+            h1[u] = 0.f;
+            h2[u] = 0.f;
+            d1[u] = 0.f;
+            d2[u] = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < kPOut; ++c) d3[c] = 0.f;
+#pragma unroll
+        for (int c = 0; c < kPFeat; ++c) dfeat[c] = 0.f;
+        if (cpath) {
+            const ViewDesc& vd = a.views[v];
+            float feat[kPCh];
+            fetch_texel(tex, tri, V, m, tv, feat);
+#pragma unroll
+            for (int c = 0; c < kPFeat; ++c) in[c] = feat[c];
+            float d[3];
+            view_dir(vd.Mi, vd.W, vd.H, x, y, d);
+            sh2(d, in + kPFeat);
+            float o[kPOut];
+            dense<kPIn, kPHid, true>(mp + kPW0, mp + kPB0, in, h1);
+            dense<kPHid, kPHid, true>(mp + kPW1, mp + kPB1, h1, h2);
+            dense<kPHid, kPOut, false>(mp + kPW2, mp + kPB2, h2, o);
+            const float A = feat[3];
+            float dA = 0.f;
+#pragma unroll
+            for (int c = 0; c < kPOut; ++c) {
+                const float mm = sigmoid_c(o[c]);
+                dfeat[c] = A * gc[c];
+                dA = __builtin_fmaf(gc[c], feat[c] - mm, dA);
+                d3[c] = (1.0f - A) * gc[c] * (mm * (1.0f - mm));
+            }
+            dfeat[3] = dA;
+#pragma unroll
+            for (int u = 0; u < kPHid; ++u) {
+                float sacc = 0.f;
+#pragma unroll
+                for (int c = 0; c < kPOut; ++c) sacc = __builtin_fmaf(mp[kPW2 + c * kPHid + u], d3[c], sacc);
+                d2[u] = h2[u] > 0.f ? sacc : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kPHid; ++u) {
+                float sacc = 0.f;
+#pragma unroll
+                for (int j = 0; j < kPHid; ++j) sacc = __builtin_fmaf(mp[kPW1 + j * kPHid + u], d2[j], sacc);
+                d1[u] = h1[u] > 0.f ? sacc : 0.f;
+            }
+#pragma unroll
+            for (int c = 0; c < kPFeat; ++c) {
+                float sacc = 0.f;
+#pragma unroll
+                for (int j = 0; j < kPHid; ++j) sacc = __builtin_fmaf(mp[kPW0 + j * kPIn + c], d1[j], sacc);
+                dfeat[c] += sacc;
+            }
+        }
+        if (__ballot(cpath)) {
+            wgrad_block(st, in, d1, kPHid, lane, acc0, ab0);
+            wgrad_block(st, h1, d2, kPHid, lane, acc1, ab1);
+            wgrad_block(st, h2, d3, kPOut, lane, acc2, ab2);
+        }
+        // --- the winner's vertex gradient (colour path and edge term), float64 ---
+        double gw[9] = {0., 0., 0., 0., 0., 0., 0., 0., 0.};
+        if (vpath) {
+            float dfu = 0.f, dfv = 0.f;
+            if (cpath) {
+#pragma unroll
+                for (int c = 0; c < kPFeat; ++c) {
+                    const float t0 = c < 4 ? (&tv[0][0].x)[c] : (&tv[0][1].x)[c - 4];
+                    const float t1 = c < 4 ? (&tv[1][0].x)[c] : (&tv[1][1].x)[c - 4];
+                    const float t2 = c < 4 ? (&tv[2][0].x)[c] : (&tv[2][1].x)[c - 4];
+                    dfu = __builtin_fmaf(dfeat[c], m.inv ? t0 - t2 : t1 - t0, dfu);
+                    dfv = __builtin_fmaf(dfeat[c], m.inv ? t0 - t1 : t2 - t0, dfv);
+                }
+            }
+            const ViewDesc& vd = a.views[v];
+            const TriRec tr = a.recs[vd.rec_base + tri];
+            float pb1, pb2;
+            double E3[3];
+            frag_bary(tr, x, y, pb1, pb2, E3);
+            vertex_grad(vd, tr, a.verts + static_cast<size_t>(tri) * 9, x, y, E3, static_cast<double>(dfu) * n,
+                        static_cast<double>(dfv) * n, ex, ey, gw);
+        }
+        // --- into the wave's row, one run of equal triangles at a time ---
+        const uint32_t tp = static_cast<uint32_t>(__shfl_up(static_cast<int>(tri), 1, 64));
+        uint64_t heads = __ballot(lane == 0 || tp != tri);
+        while (heads) {
+            const int h = __builtin_ctzll(heads);
+            heads &= heads - 1;
+            const int t = __builtin_amdgcn_readlane(static_cast<int>(tri), h);
+            if (t < 0) break;   // the sentinel run: empty lanes at the list's end
+            if (t != cur) {
+                if (cur >= 0) flush(cur);
+                cur = t;
+            }
+            const int end = heads ? __builtin_ctzll(heads) : 64;
+            const bool in_run = lane >= h && lane < end;
+            if (in_run) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (m.w[q] == 0.0f) continue;
+                    float* rv = row + m.idx[q] * kPCh;
+                    if (da != 0.0f) atomicAdd(rv + (kPCh - 1), m.w[q] * da);
+                    if (cpath) {
+#pragma unroll
+                        for (int c = 0; c < kPFeat; ++c)
+                            if (dfeat[c] != 0.0f) atomicAdd(rv + c, m.w[q] * dfeat[c]);
+                    }
+                }
+            }
+            if (__ballot(in_run && vpath)) {   // the run's winners: vertex sums over the wave
+                double vv[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) vv[k] = in_run ? gw[k] : 0.0;
+#pragma unroll
+                for (int d = 32; d > 0; d >>= 1)
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) vv[k] += __shfl_xor(vv[k], d, 64);
+                if (lane == 0) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) vsum[k] += vv[k];
+                }
+            }
+            wave_fence();
+        }
+    }
+    if (cur >= 0) flush(cur);
+    // the wave's partial row of the MLP gradient
+    float* prow = a.mlp_partial + static_cast<size_t>(blockIdx.x) * kPParams;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        prow[kPW0 + (4 * grp + i) * kPIn + col] = acc0[i];
+        prow[kPW1 + (4 * grp + i) * kPHid + col] = acc1[i];
+        if (grp == 0 && i < kPOut) prow[kPW2 + i * kPHid + col] = acc2[i];
+    }
+    ab0 += __shfl_xor(ab0, 16, 64);
+    ab0 += __shfl_xor(ab0, 32, 64);
+    ab1 += __shfl_xor(ab1, 16, 64);
+    ab1 += __shfl_xor(ab1, 32, 64);
+    ab2 += __shfl_xor(ab2, 16, 64);
+    ab2 += __shfl_xor(ab2, 32, 64);
+    if (grp == 0) {
+        prow[kPB0 + col] = ab0;
+        prow[kPB1 + col] = ab1;
+        if (col < kPOut) prow[kPB2 + col] = ab2;
+    }
+}
+
+size_t ptri_bwd_lds(int R) { return static_cast<size_t>(mc_count(R)) * kPCh * sizeof(float); }
+
+// As many single-wave workgroups as are resident at once (the LDS row bounds them), a
+// multiple of eight: the wave ranges are static, so a second round of workgroups
+// would double the time.
+int ptri_blocks(int num_cus, int R) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ptri_bwd_kernel, 64, ptri_bwd_lds(R)) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return (num_cus * per_cu / kXcds) * kXcds > 0 ? (num_cus * per_cu / kXcds) * kXcds : kXcds;
+}
+
+void launch_ptri_bwd(const PTriArgs& a, hipStream_t s) {
+    if (a.n_blocks <= 0) return;
+    hipLaunchKernelGGL(ptri_bwd_kernel, dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), ptri_bwd_lds(a.R), s, a);
+}
+
 __global__ __launch_bounds__(256) void pvert_finish_kernel(const double* __restrict__ g, float* __restrict__ out,
                                                            int64_t n, int accumulate) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;

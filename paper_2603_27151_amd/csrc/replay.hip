@@ -320,10 +320,12 @@ __global__ __launch_bounds__(256) void place_kernel(PlaceArgs a) {
             const int64_t dst = win ? a.tri_off[tri] + static_cast<int64_t>(hb & 0xFFFFFFFFull) + w_before
                                     : a.tri_off[tri + 1] - 1 - static_cast<int64_t>(hb >> 32) - ((lane - hl) - w_before);
             a.sorted[dst] = fr;
-            if (a.frag_gates) {
+            if (a.frag_gates) {   // 8-byte units of the padded gate record
                 const uint64_t src = static_cast<uint64_t>(lo) * a.region + in_region;
-                for (int w = 0; w < a.gate_words; ++w)
-                    a.sorted_gates[static_cast<uint64_t>(dst) * a.gate_words + w] = a.frag_gates[src * a.gate_words + w];
+                const int g2 = gate_stride(a.gate_words) / 2;
+                const uint2* gs = reinterpret_cast<const uint2*>(a.frag_gates) + src * g2;
+                uint2* gd = reinterpret_cast<uint2*>(a.sorted_gates) + static_cast<uint64_t>(dst) * g2;
+                for (int w = 0; w < g2; ++w) gd[w] = gs[w];
             }
         }
     }
@@ -384,10 +386,12 @@ __global__ __launch_bounds__(256) void collect_kernel(CollectArgs a) {
         const uint32_t pos = cursor + static_cast<uint32_t>(__popcll(km & lanemask_lt()));
         if (keep && pos < a.region) {
             a.frags[out_base + pos] = fr;
-            if (a.frag_gates) {
+            if (a.frag_gates) {   // the aux record's gates (words 2.., zero-padded to even) as 8-byte units
                 const uint64_t at = static_cast<uint64_t>(lo) * a.log_region + in_region;
-                const uint32_t* g = reinterpret_cast<const uint32_t*>(a.log_aux + at * (aux_words(a.gate_words) / 2)) + 2;
-                for (int w = 0; w < a.gate_words; ++w) a.frag_gates[(out_base + pos) * a.gate_words + w] = g[w];
+                const int g2 = gate_stride(a.gate_words) / 2;
+                const uint2* g = a.log_aux + at * (aux_words(a.gate_words) / 2) + 1;
+                uint2* gd = reinterpret_cast<uint2*>(a.frag_gates) + (out_base + pos) * g2;
+                for (int w = 0; w < g2; ++w) gd[w] = g[w];
             }
         }
         // fragments per triangle, counting only those stored (one atomic per

@@ -103,7 +103,12 @@ def test_paper_forward_matches_oracle(case):
     _say("covered", int((rvis != O.BG_KEY).sum()), "of", rvis.size)
 
 
-@pytest.mark.parametrize("case", CASES[:3], ids=lambda c: f"T{c['T']}R{c['R']}m{c['mode']}v{len(c['sizes'])}")
+# R = 6: a texture row (2,145 vertices x 8 channels) too large for the sorted path's
+# LDS row, so the backward takes the per-pixel path with global atomics
+BWD_CASES = CASES[:3] + [dict(seed=6, T=80, R=6, sizes=[(56, 40)], mode=0)]
+
+
+@pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"T{c['T']}R{c['R']}m{c['mode']}v{len(c['sizes'])}")
 @pytest.mark.parametrize("from_log", [False, True])
 def test_paper_backward_matches_oracle(case, from_log):
     _say("backward", case, "from_log", from_log)
