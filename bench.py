@@ -251,12 +251,47 @@ def paper_form_bench(args, R, W, dev, timed):
     return out
 
 
+def single_view_bench(args, R, W, dev, timed):
+    """The single-view workload as configured (centres in the unit ball, depth
+    complexity 2.97) and with the ball shrunk to a depth complexity of 8 (the
+    figure the configuration quotes; both measured by the oracle's fragment
+    statistics in tests/test_workload_depth.py): autotuned tile, eager and
+    graph-replayed steps."""
+    import torch
+    from paper_2603_27151_amd import autotune
+    out = {}
+    for name, dc in (("single", 2.97), ("single_dc8", 8.0)):
+        wl = W.by_name(name)
+        ds = R.DeviceScene.from_host(wl.scene)
+        vs = R.Views.from_list(wl.views)
+        target = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in wl.targets])).to(dev)
+        ctx = R._lib.Ctx(0)
+        st = Step(R, ctx, ds, vs, target, wl.seed, wl.step)
+        autotune.tune(st, ctx, name + "-" + autotune.signature(ds, vs))
+        for _ in range(max(2, args.warmup)):
+            st()
+        eager = timed(st, max(10, args.steps))
+        g = st.capture(log)
+        g.replay()
+        torch.cuda.synchronize()
+        ctx.check_overflow()
+        ms = timed(g.replay, max(10, args.steps))
+        ctx.check_overflow()
+        ctx.set_static(False)
+        out[name] = {"depth_complexity": dc, "tile": ctx.tile, "ms_per_step": round(ms, 4),
+                     "eager_ms_per_step": round(eager, 4), "mpixel_s": round(vs.pixels / (ms * 1e-3) / 1e6, 1),
+                     "triangles_per_s": round(ds.T / (ms * 1e-3), 1)}
+        del g, st
+        ctx.close()
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched", choices=["batched", "single", "large", "tiny"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "single", "single_dc8", "large", "tiny"])
     ap.add_argument("--tile", type=int, default=0, help="tile side (0: autotuned)")
     ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of HIP-graph replays")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -267,6 +302,7 @@ def parse():
     ap.add_argument("--skip-adaptive", action="store_true")
     ap.add_argument("--skip-train", action="store_true")
     ap.add_argument("--skip-paper", action="store_true", help="skip the paper-form step")
+    ap.add_argument("--skip-single", action="store_true", help="skip the single-view steps")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first copy this many MiB device to device three times (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -607,6 +643,12 @@ def main():
                    "tiles": {f"{w}x{h}": t for (w, h), t in srv.tile_by_res.items()},
                    "slo_p99_ms": 16.7, **main_st, "sweep": sweep}
 
+    # the single-view workload, literal and at depth complexity 8
+    single_view = None
+    if not args.skip_single:
+        single_view = single_view_bench(args, R, W, dev, timed)
+        log("single view: " + json.dumps(single_view))
+
     # the paper form (Section 3.3): mesh-colour texture, opacity outside the
     # MLP, deferred shading; its own step on its own workload
     paper_form = None
@@ -670,6 +712,7 @@ def main():
         "adaptive": adaptive,
         "train": train,
         "paper_form": paper_form,
+        "single_view": single_view,
     }
     print(json.dumps(out), flush=True)
 
