@@ -334,6 +334,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
         }
         float* st = s_stage[w];
         const uint32_t cellw = static_cast<uint32_t>(c.ix) | (static_cast<uint32_t>(c.iy) << 16);
+        // the fragment's triangle and winner bit, 0x7FFFFFFF for an empty lane
+        // (no triangle has that index: T is below 2^31)
+        const uint32_t fkey = on ? fa.y : 0x7FFFFFFFu;
         float my_dfx = 0.0f, my_dfy = 0.0f;   // this lane's fragment: d loss / d (fx, fy), colour logits
         {   // ---- the batch's MLP on the matrix cores, one 16-fragment block at a time ----
             constexpr int CB = MfmaWeights<S>::CB, HB = MfmaWeights<S>::HB;
@@ -347,11 +350,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             float qw[4];
             float qfx = 0.0f, qfy = 0.0f;   // the block fragment's position in its texture cell
             auto gather = [&](int nb) __attribute__((always_inline)) {
-                const int src = 16 * nb + col;
-                const bool on_n = __shfl(static_cast<int>(on), src, 64) != 0;
-                const uint32_t tri_n = static_cast<uint32_t>(__shfl(static_cast<int>(tri), src, 64));
-                const uint32_t cw = static_cast<uint32_t>(__shfl(static_cast<int>(cellw), src, 64));
-                const float fx = __shfl(c.fx, src, 64), fy = __shfl(c.fy, src, 64);
+                const uint32_t key_n = row_bcast(fkey, nb);
+                const uint32_t tri_n = key_n & 0x7FFFFFFFu;
+                const bool on_n = tri_n != 0x7FFFFFFFu;
+                const uint32_t cw = row_bcast(cellw, nb);
+                const float fx = row_bcast(c.fx, nb), fy = row_bcast(c.fy, nb);
                 qfx = fx;
                 qfy = fy;
                 // an empty lane's weights are zero, so that its input is zero
@@ -374,8 +377,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 }
             };
             gather(0);
-            for (int nb = 0; nb < 4; ++nb) {   // fragment 16 nb + col
-                const int src = 16 * nb + col;
+            for (int nb = 0; nb < 4; ++nb) {   // fragment 16 nb + col (lane 16 nb + col holds its record)
                 // inputs, unit-major: channels 16 cb + 4 grp .. + 3 (an empty lane's
                 // weights are zero; channels past C meet zero weights in layer 0)
                 f4v xin[CB];
@@ -411,10 +413,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                     for (int ob = 0; ob < HB; ++ob) {
                         constexpr int kH = S::H;
                         const int b0 = 16 * ob, b1 = kH + 16 * ob;   // first unit of the block, layers 0 and 1
-                        const uint32_t w0 = static_cast<uint32_t>(__shfl(static_cast<int>(gt[b0 >> 5]), src, 64));
+                        const uint32_t w0 = row_bcast(gt[b0 >> 5], nb);
                         gate0[ob] = (w0 >> ((b0 & 31) + 4 * grp)) & 0xFu;
                         if constexpr (S::NH == 2) {
-                            const uint32_t w1 = static_cast<uint32_t>(__shfl(static_cast<int>(gt[b1 >> 5]), src, 64));
+                            const uint32_t w1 = row_bcast(gt[b1 >> 5], nb);
                             gate1[ob] = (w1 >> ((b1 & 31) + 4 * grp)) & 0xFu;
                         }
                     }
@@ -428,8 +430,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 // output layer and the logit gradients (Eq. (9) through the sigmoid for the score term)
                 float dO;   // lane group j: output j of the fragment
                 // an empty fragment has zero colour gradient and score weight, so its dO is zero
-                const bool win_n = __shfl(static_cast<int>(win), src, 64) != 0;
-                const float gl_n = __shfl(__uint_as_float(fb4.x), src, 64);
+                const bool win_n = (row_bcast(fkey, nb) >> 31) != 0;
+                const float gl_n = row_bcast(__uint_as_float(fb4.x), nb);
                 {
                     f4v o = {Wt.bo[lane], 0.f, 0.f, 0.f};
 #pragma unroll
@@ -438,8 +440,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
 #pragma unroll
                         for (int s4 = 0; s4 < 4; ++s4) o = mfma4(wv[s4], hl[ib][s4], o);
                     }
-                    const float g0 = __shfl(__uint_as_float(fb4.y), src, 64), g1 = __shfl(__uint_as_float(fb4.z), src, 64),
-                                g2 = __shfl(__uint_as_float(fb4.w), src, 64);
+                    const float g0 = row_bcast(__uint_as_float(fb4.y), nb), g1 = row_bcast(__uint_as_float(fb4.z), nb),
+                                g2 = row_bcast(__uint_as_float(fb4.w), nb);
                     const float sg = sigmoid_fast(o[0]);
                     float d;
                     if (grp == 3) d = win_n ? gl_n * (1.0f - sg) : -gl_n * sg;
@@ -529,10 +531,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 }
                 // sum over the four lane groups' channels; lane 16 nb + col keeps
                 // the values of its own fragment
-                pfx += __shfl_xor(pfx, 16, 64);
-                pfy += __shfl_xor(pfy, 16, 64);
-                pfx += __shfl_xor(pfx, 32, 64);
-                pfy += __shfl_xor(pfy, 32, 64);
+                pfx = rows_sum(pfx);
+                pfy = rows_sum(pfy);
                 if (grp == nb) {
                     my_dfx = pfx;
                     my_dfy = pfy;
@@ -693,16 +693,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             const int end = heads ? __builtin_ctzll(heads) : 64;
             const bool in_run = lane >= h && lane < end;
             if (__ballot(in_run && win)) {   // the run's winners: vertex gradient summed over the wave
-                double v[9];
+                double v[9], q[3];
 #pragma unroll
                 for (int k = 0; k < 9; ++k) v[k] = in_run ? gw[k] : 0.0;   // gw is zero for fragments in front
-#pragma unroll
-                for (int d = 32; d > 0; d >>= 1)   // the nine sums advance together
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) v[k] += __shfl_xor(v[k], d, 64);
-                if (lane == 0) {
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) vgrid[k] += v[k];
+                wave_sum9(v, q);
+                if ((lane & 15) == 0) {   // row g's first lane: components c, c + 2 (and 4 in row 0)
+                    const int g = lane >> 4, c0 = (g & 1) + 5 * (g >> 1);
+                    vgrid[c0] += q[0];
+                    vgrid[c0 + 2] += q[1];
+                    if (g == 0) vgrid[4] += q[2];
                 }
             }
             constexpr int UF = 4;                          // steps in flight: their staged reads go first

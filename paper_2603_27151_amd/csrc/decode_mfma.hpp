@@ -37,6 +37,96 @@ __device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// ---- cross-lane moves on the vector ALU ----
+// A wave's 64 lanes are four rows of 16. gfx950's row swaps exchange rows
+// between two registers in one VALU instruction, where a general shuffle
+// (ds_bpermute) would go through the LDS pipe and wait for it:
+//   swap16(a, b) -> (a.r0, b.r0, a.r2, b.r2), (a.r1, b.r1, a.r3, b.r3)
+//   swap32(a, b) -> (a.r0, a.r1, b.r0, b.r1), (a.r2, a.r3, b.r2, b.r3)
+// (rX = row X; the lane within the row is kept).
+struct U2 {
+    uint32_t a, b;
+};
+__device__ __forceinline__ U2 swap16(uint32_t a, uint32_t b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    return {static_cast<uint32_t>(r[0]), static_cast<uint32_t>(r[1])};
+}
+__device__ __forceinline__ U2 swap32(uint32_t a, uint32_t b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    return {static_cast<uint32_t>(r[0]), static_cast<uint32_t>(r[1])};
+}
+
+// Row n of x in every row: lane (row g, column c) receives lane 16 n + c.
+// Two swaps; the first is shared by every n (the compiler merges it).
+__device__ __forceinline__ uint32_t row_bcast(uint32_t x, int n) {
+    const U2 h = swap16(x, x);                   // (x0, x0, x2, x2), (x1, x1, x3, x3)
+    const uint32_t y = (n & 1) ? h.b : h.a;
+    const U2 q = swap32(y, y);                   // (y0, y0, y0, y0), (y2, y2, y2, y2)
+    return (n & 2) ? q.b : q.a;
+}
+__device__ __forceinline__ float row_bcast(float x, int n) {
+    return __uint_as_float(row_bcast(__float_as_uint(x), n));
+}
+
+// Sum over the four rows, in every row: (x0 + x1) + (x2 + x3) per column.
+__device__ __forceinline__ float rows_sum(float x) {
+    const U2 h = swap16(__float_as_uint(x), __float_as_uint(x));
+    const float y = __uint_as_float(h.a) + __uint_as_float(h.b);
+    const U2 q = swap32(__float_as_uint(y), __float_as_uint(y));
+    return __uint_as_float(q.a) + __uint_as_float(q.b);
+}
+
+// Doubles through the 32-bit moves, one half at a time.
+__device__ __forceinline__ uint32_t dlo(double v) { return static_cast<uint32_t>(__double_as_longlong(v)); }
+__device__ __forceinline__ uint32_t dhi(double v) { return static_cast<uint32_t>(__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double djoin(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// a over rows {0, 1} + {2, 3} in rows 0 and 1, b likewise in rows 2 and 3.
+__device__ __forceinline__ double pair32(double a, double b) {
+    const U2 l = swap32(dlo(a), dlo(b)), h = swap32(dhi(a), dhi(b));
+    return djoin(l.a, h.a) + djoin(l.b, h.b);
+}
+// a over rows 0 + 1 in row 0 and 2 + 3 in row 2; b likewise in rows 1 and 3.
+__device__ __forceinline__ double pair16(double a, double b) {
+    const U2 l = swap16(dlo(a), dlo(b)), h = swap16(dhi(a), dhi(b));
+    return djoin(l.a, h.a) + djoin(l.b, h.b);
+}
+
+// Lane l + x of the lane's row by a DPP pattern, for both halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(dlo(v)), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(dhi(v)), CTRL, 0xF, 0xF, false);
+    return djoin(static_cast<uint32_t>(lo), static_cast<uint32_t>(hi));
+}
+// Sum over the 16 lanes of each row, in every lane of the row: partners at
+// distance 1 and 2 within quads, then the half-row and row mirrors (lane i
+// with 7 - i, then with 15 - i).
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);   // row_half_mirror
+    v += dpp_d<0x140>(v);   // row_mirror
+    return v;
+}
+
+// Nine per-lane doubles summed over the wave as a transposed reduction
+// (each exchange carries two components): on return, lane 16 g of row g
+// holds the sums of components c = (g & 1) + 5 (g >> 1) in q[0] and c + 2 in
+// q[1], and row 0 that of component 4 in q[2].
+__device__ __forceinline__ void wave_sum9(const double (&v)[9], double (&q)[3]) {
+    double r[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r[k] = pair32(v[k], k + 5 < 9 ? v[k + 5] : 0.0);   // rows 0-1: k, rows 2-3: k + 5
+    q[0] = pair16(r[0], r[1]);   // rows: 0, 1, 5, 6
+    q[1] = pair16(r[2], r[3]);   // rows: 2, 3, 7, 8
+    q[2] = pair16(r[4], 0.0);    // row 0: 4
+#pragma unroll
+    for (int j = 0; j < 3; ++j) q[j] = row16_sum(q[j]);
+}
+
 // Weights and biases of one MLP in the A-operand arrangement, per lane.
 template <class S>
 struct MfmaWeights {
