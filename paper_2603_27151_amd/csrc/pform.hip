@@ -37,8 +37,10 @@ __device__ __forceinline__ void mc_ij(int n, int k, int& i, int& j) {
     i = k - mc_index(n, 0, jj);
 }
 
-// One thread per (triangle, vertex of the finest grid), consecutive threads on
-// consecutive vertices (32-byte records, written coalesced).
+// Fallback for levels too large to stage in LDS: one thread per (triangle,
+// vertex of the finest grid), consecutive threads on consecutive vertices
+// (32-byte records, written coalesced), the three grid vertices of every
+// level gathered from global memory.
 __global__ __launch_bounds__(256) void mc_assemble_kernel(AssembleArgs a) {
     const int nf = 1 << a.Rmax, Vf = mc_count(a.Rmax);
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -78,6 +80,69 @@ __global__ __launch_bounds__(256) void mc_assemble_kernel(AssembleArgs a) {
     }
 }
 
+// TPB consecutive triangles per workgroup: their learnable levels (contiguous
+// per level in global memory) are staged in LDS with coalesced 16-byte loads;
+// then each thread takes one (finest-grid vertex, half of the channels) for
+// all TPB triangles, so the vertex's micro-triangle lookups, which do not
+// depend on the triangle, are computed once. Same arithmetic, in the same
+// order, as the fallback: the results are identical.
+template <int TPB>
+__global__ __launch_bounds__(256) void mc_assemble_lds_kernel(AssembleArgs a) {
+    extern __shared__ float4 st4[];
+    const int t0 = blockIdx.x * TPB;
+    const int nt = a.T - t0 < TPB ? a.T - t0 : TPB;
+    {
+        int off = 0;   // float4 offset of level R's block of TPB triangles
+        for (int R = a.Rmin; R <= a.Rtop; ++R) {
+            const int v2 = mc_count(R) * 2;
+            const float4* src = reinterpret_cast<const float4*>(a.raw[R - a.Rmin]) + static_cast<size_t>(t0) * v2;
+            for (int e = threadIdx.x; e < nt * v2; e += blockDim.x) st4[off + e] = src[e];
+            off += TPB * v2;
+        }
+    }
+    __syncthreads();
+    const int nf = 1 << a.Rmax, Vf = mc_count(a.Rmax);
+    for (int e = threadIdx.x; e < 2 * Vf; e += blockDim.x) {
+        const int k = e >> 1, h = e & 1;
+        int i, j;
+        mc_ij(nf, k, i, j);
+        const float b1 = static_cast<float>(i) * (1.0f / static_cast<float>(nf));
+        const float b2 = static_cast<float>(j) * (1.0f / static_cast<float>(nf));
+        float4 z[TPB];
+#pragma unroll
+        for (int tt = 0; tt < TPB; ++tt) z[tt] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int off = 0;
+        for (int R = a.Rmin; R <= a.Rtop; ++R) {
+            const Micro m = micro_of(1 << R, b1, b2);
+            const int v2 = mc_count(R) * 2;
+#pragma unroll
+            for (int tt = 0; tt < TPB; ++tt) {   // rows past nt hold stale LDS; their results are not stored
+                const float4* g = st4 + off + tt * v2 + h;
+                const float4 v0 = g[2 * m.idx[0]], v1 = g[2 * m.idx[1]], v2v = g[2 * m.idx[2]];
+                z[tt].x = z[tt].x + mc_mix(m, v0.x, v1.x, v2v.x);
+                z[tt].y = z[tt].y + mc_mix(m, v0.y, v1.y, v2v.y);
+                z[tt].z = z[tt].z + mc_mix(m, v0.z, v1.z, v2v.z);
+                z[tt].w = z[tt].w + mc_mix(m, v0.w, v1.w, v2v.w);
+            }
+            off += TPB * v2;
+        }
+#pragma unroll
+        for (int tt = 0; tt < TPB; ++tt) {
+            if (tt < nt) {
+                float4* o = reinterpret_cast<float4*>(a.tex_out) + static_cast<size_t>(t0 + tt) * Vf * 2 + e;
+                *o = make_float4(sigmoid_c(z[tt].x), sigmoid_c(z[tt].y), sigmoid_c(z[tt].z), sigmoid_c(z[tt].w));
+            }
+        }
+    }
+}
+
+// Bytes of the learnable levels of one triangle.
+static size_t mc_levels_bytes(int Rmin, int Rtop) {
+    size_t b = 0;
+    for (int R = Rmin; R <= Rtop; ++R) b += static_cast<size_t>(mc_count(R)) * kPCh * sizeof(float);
+    return b;
+}
+
 // Gradient of the assembly. The lookup of level R at the vertices of level
 // Rmax equals prolongation to level R + 1, then R + 2, ..., Rmax (the field of
 // a level is linear on each of its micro-triangles, and every micro-triangle
@@ -104,10 +169,25 @@ __global__ __launch_bounds__(256) void mc_assemble_bwd_kernel(AssembleArgs a) {
         const float4* tx4 = reinterpret_cast<const float4*>(tx);
         const float4* gt4 = reinterpret_cast<const float4*>(gt);
         float4* cur4 = reinterpret_cast<float4*>(cur);
-        for (int e = threadIdx.x; e < Vf * 2; e += blockDim.x) {
-            const float4 s = tx4[e], g = gt4[e];
-            cur4[e] = make_float4(g.x * s.x * (1.0f - s.x), g.y * s.y * (1.0f - s.y), g.z * s.z * (1.0f - s.z),
-                                  g.w * s.w * (1.0f - s.w));
+        auto dz4 = [](float4 g, float4 s) {
+            return make_float4(g.x * s.x * (1.0f - s.x), g.y * s.y * (1.0f - s.y), g.z * s.z * (1.0f - s.z),
+                               g.w * s.w * (1.0f - s.w));
+        };
+        {   // four loads of each array in flight per thread
+            const int n4 = Vf * 2;
+            int e = threadIdx.x;
+            const int nt = blockDim.x;
+            for (; e + 3 * nt < n4; e += 4 * nt) {
+                float4 sv[4], gv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    sv[u] = tx4[e + u * nt];
+                    gv[u] = gt4[e + u * nt];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) cur4[e + u * nt] = dz4(gv[u], sv[u]);
+            }
+            for (; e < n4; e += nt) cur4[e] = dz4(gt4[e], tx4[e]);
         }
         __syncthreads();
         for (int R = a.Rmax;; --R) {
@@ -125,21 +205,29 @@ __global__ __launch_bounds__(256) void mc_assemble_bwd_kernel(AssembleArgs a) {
                 }
             }
             if (R == a.Rmin) break;
-            // restrict level R (cur) onto level R - 1 (nxt)
+            // restrict level R (cur) onto level R - 1 (nxt): one thread per
+            // (coarse vertex, four channels), the six neighbours in a fixed order
             const int nc = 1 << (R - 1), nfl = 1 << R, Vc = mc_count(R - 1);
-            for (int e = threadIdx.x; e < Vc * kPCh; e += blockDim.x) {
-                const int q = e / kPCh, c = e - q * kPCh;
+            const float4* c4 = reinterpret_cast<const float4*>(cur);
+            float4* n4 = reinterpret_cast<float4*>(nxt);
+            for (int e = threadIdx.x; e < Vc * 2; e += blockDim.x) {
+                const int q = e >> 1, h = e & 1;
                 int I, J;
                 mc_ij(nc, q, I, J);
                 const int i = 2 * I, j = 2 * J;
-                float side = 0.0f;
-                if (i + 1 + j <= nfl) side += cur[mc_index(nfl, i + 1, j) * kPCh + c];
-                if (i > 0) side += cur[mc_index(nfl, i - 1, j) * kPCh + c];
-                if (i + j + 1 <= nfl) side += cur[mc_index(nfl, i, j + 1) * kPCh + c];
-                if (j > 0) side += cur[mc_index(nfl, i, j - 1) * kPCh + c];
-                if (j > 0) side += cur[mc_index(nfl, i + 1, j - 1) * kPCh + c];   // i + 1 + j - 1 <= n always
-                if (i > 0) side += cur[mc_index(nfl, i - 1, j + 1) * kPCh + c];
-                nxt[e] = cur[mc_index(nfl, i, j) * kPCh + c] + 0.5f * side;
+                float4 side = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                auto add = [&](int ii, int jj) __attribute__((always_inline)) {
+                    const float4 v = c4[mc_index(nfl, ii, jj) * 2 + h];
+                    side = make_float4(side.x + v.x, side.y + v.y, side.z + v.z, side.w + v.w);
+                };
+                if (i + 1 + j <= nfl) add(i + 1, j);
+                if (i > 0) add(i - 1, j);
+                if (i + j + 1 <= nfl) add(i, j + 1);
+                if (j > 0) add(i, j - 1);
+                if (j > 0) add(i + 1, j - 1);   // i + 1 + j - 1 <= n always
+                if (i > 0) add(i - 1, j + 1);
+                const float4 c = c4[mc_index(nfl, i, j) * 2 + h];
+                n4[e] = make_float4(c.x + 0.5f * side.x, c.y + 0.5f * side.y, c.z + 0.5f * side.z, c.w + 0.5f * side.w);
             }
             __syncthreads();
             float* tmp = cur;
@@ -187,8 +275,21 @@ size_t mc_assemble_bwd_lds(int Rmin, int Rmax) {
 
 void launch_mc_assemble(const AssembleArgs& a, hipStream_t s) {
     if (a.T <= 0) return;
-    const int64_t n = static_cast<int64_t>(a.T) * mc_count(a.Rmax);
-    hipLaunchKernelGGL(mc_assemble_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
+    // four triangles per workgroup while their levels take at most 32 KiB of
+    // LDS, fewer up to 64 KiB, else the gathering fallback
+    const size_t lb = mc_levels_bytes(a.Rmin, a.Rtop);
+    const int tpb = 4 * lb <= 32768 ? 4 : (2 * lb <= 49152 ? 2 : (lb <= 65536 ? 1 : 0));
+    const unsigned nb = static_cast<unsigned>((a.T + (tpb > 0 ? tpb : 1) - 1) / (tpb > 0 ? tpb : 1));
+    if (tpb == 4) {
+        hipLaunchKernelGGL(mc_assemble_lds_kernel<4>, dim3(nb), dim3(256), 4 * lb, s, a);
+    } else if (tpb == 2) {
+        hipLaunchKernelGGL(mc_assemble_lds_kernel<2>, dim3(nb), dim3(256), 2 * lb, s, a);
+    } else if (tpb == 1) {
+        hipLaunchKernelGGL(mc_assemble_lds_kernel<1>, dim3(nb), dim3(256), lb, s, a);
+    } else {
+        const int64_t n = static_cast<int64_t>(a.T) * mc_count(a.Rmax);
+        hipLaunchKernelGGL(mc_assemble_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a);
+    }
 }
 
 void launch_mc_assemble_bwd(const AssembleArgs& a, size_t lds_limit, hipStream_t s) {
