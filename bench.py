@@ -137,12 +137,14 @@ class PStep(Step):
     """One step of the paper form (Section 3.3; Supplement B.3, B.6) on one
     stream: soup_mc_assemble (levels Rmin..Rmax-1 onto the level-Rmax grid)
     -> soup_pforward (opacity-texture mask, deferred shading) ->
-    soup_loss_l1_ssim (the paper's loss) -> soup_pbackward ->
-    soup_mc_assemble_bwd, into preallocated buffers."""
+    soup_loss_l1_ssim (the paper's loss) -> soup_pbackward_levels (the
+    backward with the assembly's restriction folded in), into preallocated
+    buffers; with fused=False the last call is soup_pbackward followed by
+    soup_mc_assemble_bwd through a texture-sized gradient."""
 
-    def __init__(self, R, ctx, wl, target, dev):
+    def __init__(self, R, ctx, wl, target, dev, fused=True):
         import torch
-        self.R, self.ctx, self.wl, self.target = R, ctx, wl, target
+        self.R, self.ctx, self.wl, self.target, self.fused = R, ctx, wl, target, fused
         lv = wl.levels
         self.Rmin, self.Rmax = lv.Rmin, lv.Rmax
         self.raw = [torch.from_numpy(r).to(dev) for r in lv.raw]
@@ -168,9 +170,17 @@ class PStep(Step):
         R.mc_assemble(self.raw, self.Rmin, self.Rmax, out=self.ds.tex, ctx=ctx)
         R.pforward(self.ds, self.vs, self.opts, minv=self.minv, ctx=ctx, out=(self.vis, self.color, None))
         R.loss_l1_ssim(self.color, self.target, self.vs, 0.8, ctx=ctx, out=(self.loss, self.gc, self.gl))
-        R.pbackward(self.ds, self.vs, self.opts, self.vis, self.color, self.gc, self.gl, minv=self.minv, ctx=ctx,
-                    out=(self.gv, self.gt, self.gm))
-        R.mc_assemble_bwd(self.ds.tex, self.gt, self.Rmin, len(self.raw), self.Rmax, out=self.graw, ctx=ctx)
+        self.backward()
+
+    def backward(self):
+        R, ctx = self.R, self.ctx
+        if self.fused:
+            R.pbackward_levels(self.ds, self.vs, self.opts, self.vis, self.color, self.gc, self.Rmin, len(self.raw),
+                               grad_logp=self.gl, minv=self.minv, ctx=ctx, out=(self.gv, self.graw, self.gm))
+        else:
+            R.pbackward(self.ds, self.vs, self.opts, self.vis, self.color, self.gc, self.gl, minv=self.minv, ctx=ctx,
+                        out=(self.gv, self.gt, self.gm))
+            R.mc_assemble_bwd(self.ds.tex, self.gt, self.Rmin, len(self.raw), self.Rmax, out=self.graw, ctx=ctx)
 
 
 def paper_form_bench(args, R, W, dev, timed):
@@ -191,19 +201,42 @@ def paper_form_bench(args, R, W, dev, timed):
     R.pforward(st.ds, st.vs, st.opts, minv=st.minv, ctx=ctx, out=(st.vis, st.color, None))
     sf = ctx.stats()
     R.loss_l1_ssim(st.color, st.target, st.vs, 0.8, ctx=ctx, out=(st.loss, st.gc, st.gl))
-    R.pbackward(st.ds, st.vs, st.opts, st.vis, st.color, st.gc, st.gl, minv=st.minv, ctx=ctx,
-                out=(st.gv, st.gt, st.gm))
+    st.backward()
     ctx.set_counting(False)
     torch.cuda.synchronize()
     P = st.vs.pixels
     winners = int((st.vis != -1).sum().item())
+    # the paper form's kernels under the timing kinds they share with the workloads' form
+    names = {"decode_bwd": "winner_bwd", "grad_reduce": "score", "mlp_reduce": "reduce"}
+    # the unfused backward (texture gradient through HBM, then the assembly's
+    # backward) for comparison: eager with per-kernel times, and graph replays
+    # (an eager call that synchronises now and then blocks for tens of
+    # milliseconds; replays have no host synchronisation)
+    st.fused = False
+    st()
+    ctx.read_timings()
+    ctx.set_timing(True)
+    unfused_ms = timed(st, args.steps)
+    ctx.set_timing(False)
+    kern_u = ctx.read_timings()
+    per_kernel_u = {names.get(k, k): (v[0] / v[1] if v[1] else 0.0) for k, v in kern_u.items()}
+    unfused_graph_ms = None
+    if not args.no_graph:
+        gu = st.capture(log)
+        gu.replay()
+        torch.cuda.synchronize()
+        ctx.check_overflow()
+        unfused_graph_ms = timed(gu.replay, args.steps)
+        ctx.check_overflow()
+        ctx.set_static(False)
+        del gu
+    st.fused = True
+    st()
     ctx.read_timings()
     ctx.set_timing(True)
     eager_ms = timed(st, args.steps)
     ctx.set_timing(False)
     kern = ctx.read_timings()
-    # the paper form's kernels under the timing kinds they share with the workloads' form
-    names = {"decode_bwd": "winner_bwd", "grad_reduce": "score", "mlp_reduce": "reduce"}
     per_kernel = {names.get(k, k): (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
     ms, graph = eager_ms, False
     if not args.no_graph:
@@ -232,7 +265,7 @@ def paper_form_bench(args, R, W, dev, timed):
         "shade": 8.0 * P + 12.0 * P + winners * (64.0 + 96.0),
     }
     log(f"paper form: {P} pixels, {winners} winners, fwd decodes {sf['decodes']}, eager {eager_ms:.3f} ms, "
-        f"graph {ms:.3f} ms")
+        f"graph {ms:.3f} ms; unfused backward: eager {unfused_ms:.3f} ms, graph {unfused_graph_ms} ms")
     log("paper form per-kernel avg ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_kernel.items() if v > 0))
     out = {"workload": f"paper form: {T} triangles, texture levels {wl.levels.Rmin}..{wl.levels.Rtop} onto level "
                        f"{wl.levels.Rmax} ({V} grid vertices x 8 channels), MLP 16->16->16->3 deferred, "
@@ -241,9 +274,13 @@ def paper_form_bench(args, R, W, dev, timed):
            "mpixel_s": round(P / (ms * 1e-3) / 1e6, 2), "pixels": P, "winners": winners,
            "forward_decodes": sf["decodes"], "covered_pixels": sf["covered_pixels"],
            "kernels_ms": {k: round(v, 4) for k, v in per_kernel.items() if v > 0},
-           "hbm": {k: {"bytes": b, "gb_s": round(b / (per_kernel[kk] * 1e-3) / 1e9, 1),
-                       "frac": round(b / (per_kernel[kk] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
-                   for k, b in bytes_.items() for kk in [k] if per_kernel.get(kk, 0) > 0}}
+           "hbm": {k: {"bytes": b, "gb_s": round(b / (pk[k] * 1e-3) / 1e9, 1),
+                       "frac": round(b / (pk[k] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                   for k, b in bytes_.items() for pk in [per_kernel if per_kernel.get(k, 0) > 0 else per_kernel_u]
+                   if pk.get(k, 0) > 0},
+           "unfused_backward": {"eager_ms_per_step": round(unfused_ms, 4),
+                                "ms_per_step": None if unfused_graph_ms is None else round(unfused_graph_ms, 4),
+                                "kernels_ms": {k: round(v, 4) for k, v in per_kernel_u.items() if v > 0}}}
     del st
     if graph:
         del g

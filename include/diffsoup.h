@@ -370,6 +370,26 @@ soup_status soup_pbackward(soup_ctx* ctx, const soup_pscene* scene, const soup_v
                            float* grad_verts, float* grad_tex, float* grad_mlp, void* stream);
 
 /*
+ * soup_pbackward followed by the assembly's backward (Section 3.3; the
+ * gradient of soup_mc_assemble), in one call: scene->tex must be the
+ * assembly of the learnable levels Rmin..Rtop onto level scene->R, and
+ * grad_raw (host array of Rtop - Rmin + 1 device pointers, [T,V(Rmin + l),8],
+ * 16-byte aligned) receives the gradient of those levels instead of a
+ * gradient of the texture; overwritten, or added into when opts->accumulate
+ * is 1. grad_verts and grad_mlp as in soup_pbackward. Where one triangle's
+ * grids fit the backward's LDS (R <= 5) the restriction to the levels runs
+ * inside it and no texture-sized gradient is written; otherwise the call
+ * uses a context workspace of T * V(R) * 32 bytes. Errors as soup_pbackward,
+ * and SOUP_ERR_INVALID for levels outside 0 <= Rmin <= Rtop <= R or a NULL
+ * level pointer.
+ */
+soup_status soup_pbackward_levels(soup_ctx* ctx, const soup_pscene* scene, const soup_views* views,
+                                  const float* inv_view_proj, const soup_opts* opts, const uint64_t* vis,
+                                  const float* color, const float* grad_color, const float* grad_logp,
+                                  int32_t Rmin, int32_t Rtop, float* grad_verts, float* const* grad_raw,
+                                  float* grad_mlp, void* stream);
+
+/*
  * Multi-resolution texture assembly (Section 3.3): the learnable grids of
  * levels Rmin..Rtop (raw: host array of Rtop - Rmin + 1 device pointers,
  * level Rmin + l at raw[l], [T,V(Rmin + l),8], before the sigmoid) are each

@@ -56,8 +56,8 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_selftest_uniform", "soup_ctx_set_timing", "soup_read_timings", "soup_ctx_set_static",
            "soup_ctx_check", "soup_coverage_count", "soup_edge_lengths", "soup_adaptive_plan",
            "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step", "soup_loss_l1_ssim_noalloc",
-           "soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd",
-           "soup_ctx_workspace_bytes"]
+           "soup_pforward", "soup_pbackward", "soup_pbackward_levels", "soup_mc_assemble",
+           "soup_mc_assemble_bwd", "soup_ctx_workspace_bytes"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
                 "adaptive_apply", "train_loss", "adam", "shade", "assemble", "assemble_bwd"]
@@ -112,11 +112,13 @@ def lib() -> C.CDLL:
                                 P, P, P, P]
     L.soup_pbackward.argtypes = [P, C.POINTER(soup_pscene), C.POINTER(soup_views), P, C.POINTER(soup_opts),
                                  P, P, P, P, P, P, P, P]
+    L.soup_pbackward_levels.argtypes = [P, C.POINTER(soup_pscene), C.POINTER(soup_views), P, C.POINTER(soup_opts),
+                                        P, P, P, P, C.c_int32, C.c_int32, P, P, P, P]
     L.soup_mc_assemble.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
     L.soup_mc_assemble_bwd.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_int32, P]
     L.soup_ctx_workspace_bytes.argtypes = [P, C.POINTER(C.c_int64)]
-    for name in ["soup_pforward", "soup_pbackward", "soup_mc_assemble", "soup_mc_assemble_bwd",
-                 "soup_ctx_workspace_bytes"]:
+    for name in ["soup_pforward", "soup_pbackward", "soup_pbackward_levels", "soup_mc_assemble",
+                 "soup_mc_assemble_bwd", "soup_ctx_workspace_bytes"]:
         getattr(L, name).restype = C.c_int
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
@@ -377,6 +379,21 @@ def soup_pbackward(ctx: Ctx, scene: soup_pscene, views: soup_views, inv_view_pro
     ctx.check(lib().soup_pbackward(ctx.p, C.byref(scene), C.byref(views), mi.ctypes.data_as(C.c_void_p),
                                    C.byref(opts), _ptr(vis), _ptr(color), _ptr(grad_color), _ptr(grad_logp),
                                    _ptr(grad_verts), _ptr(grad_tex), _ptr(grad_mlp), _stream(stream)))
+
+
+def soup_pbackward_levels(ctx: Ctx, scene: soup_pscene, views: soup_views, inv_view_proj, opts: soup_opts, vis,
+                          color, grad_color, grad_logp, Rmin: int, grad_verts, grad_raw: Sequence, grad_mlp,
+                          stream=None):
+    """grad_raw: device tensors of the learnable levels Rmin, Rmin + 1, ..."""
+    mi = np.ascontiguousarray(np.asarray(inv_view_proj, np.float32).reshape(-1, 16))
+    if mi.shape[0] != views.V:
+        raise ValueError("inv_view_proj needs one 4x4 matrix per view")
+    ptrs = (C.c_void_p * len(grad_raw))(*[_ptr(r) for r in grad_raw])
+    Rtop = Rmin + len(grad_raw) - 1
+    ctx.check(lib().soup_pbackward_levels(ctx.p, C.byref(scene), C.byref(views), mi.ctypes.data_as(C.c_void_p),
+                                          C.byref(opts), _ptr(vis), _ptr(color), _ptr(grad_color),
+                                          _ptr(grad_logp), int(Rmin), Rtop, _ptr(grad_verts), ptrs,
+                                          _ptr(grad_mlp), _stream(stream)))
 
 
 def soup_mc_assemble(ctx: Ctx, raw: Sequence, Rmin: int, Rmax: int, tex, stream=None):

@@ -56,6 +56,7 @@ struct soup_ctx {
     bool frags_gated = false;        // the current fragment list carries the forward's gates
     DevBuf ssim;                                      // SSIM statistics of the training loss
     DevBuf gvert;                                     // the paper form's float64 vertex gradient sums
+    DevBuf gtex;                                      // its texture gradient when levels are asked for and the sorted path cannot fold them in
     uint64_t region_hint = 0;        // largest replay-region count of the last call, to size the next
     uint64_t frag_region = 0;        // region size and count of the current fragment list
     int frag_regions = 0;
@@ -589,7 +590,7 @@ void soup_ctx_destroy(soup_ctx* c) {
                       &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                       &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
                       &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff, &c->ssim,
-                      &c->chunk_base, &c->frag_gates, &c->sorted_gates, &c->gvert};
+                      &c->chunk_base, &c->frag_gates, &c->sorted_gates, &c->gvert, &c->gtex};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -675,7 +676,7 @@ soup_status soup_ctx_workspace_bytes(const soup_ctx* c, int64_t* bytes) {
                             &c->counters,   &c->tri_count, &c->tri_fill,      &c->tri_off,     &c->tri_bsum,
                             &c->mlp_mid,    &c->frags,     &c->sorted,        &c->region_counts, &c->region_boff,
                             &c->flags,      &c->log_frag,  &c->log_aux,       &c->log_counts,  &c->log_boff, &c->ssim,
-                            &c->chunk_base, &c->frag_gates, &c->sorted_gates, &c->gvert};
+                            &c->chunk_base, &c->frag_gates, &c->sorted_gates, &c->gvert, &c->gtex};
     int64_t n = 0;
     for (const DevBuf* b : bufs) n += static_cast<int64_t>(b->bytes);
     *bytes = n;
@@ -1168,10 +1169,25 @@ soup_status soup_pforward(soup_ctx* c, const soup_pscene* scene, const soup_view
     return finish_stats(c, s);
 }
 
-soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_views* views, const float* inv_view_proj,
-                           const soup_opts* opts, const uint64_t* vis, const float* color, const float* grad_color,
-                           const float* grad_logp, float* grad_verts, float* grad_tex, float* grad_mlp,
-                           void* stream) {
+static soup_status check_levels(soup_ctx* c, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax) {
+    if (T < 0) return fail(c, SOUP_ERR_INVALID, "T = %d < 0", T);
+    if (Rmin < 0 || Rtop < Rmin || Rmax < Rtop || Rmax > kPMaxR || Rtop - Rmin + 1 > kPMaxLevels)
+        return fail(c, SOUP_ERR_INVALID, "levels Rmin = %d, Rtop = %d, Rmax = %d: need 0 <= Rmin <= Rtop <= Rmax <= %d",
+                    Rmin, Rtop, Rmax, kPMaxR);
+    return SOUP_OK;
+}
+
+// The learnable levels a backward writes instead of the assembled texture's gradient.
+struct LevelsOut {
+    int Rmin, Rtop;
+    float* const* graw;
+};
+
+static soup_status pbackward_impl(soup_ctx* c, const soup_pscene* scene, const soup_views* views,
+                                  const float* inv_view_proj, const soup_opts* opts, const uint64_t* vis,
+                                  const float* color, const float* grad_color, const float* grad_logp,
+                                  float* grad_verts, float* grad_tex, const LevelsOut* lv, float* grad_mlp,
+                                  void* stream) {
     if (!c) return SOUP_ERR_INVALID;
     c->err.clear();
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1180,7 +1196,15 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
     if ((st = plan_paper(c, p, scene, views, inv_view_proj))) return st;
     if ((st = check_opts(c, opts))) return st;
     if (!vis || !color || !grad_color) return fail(c, SOUP_ERR_INVALID, "vis, color and grad_color are required");
-    if (!grad_verts || !grad_tex || !grad_mlp) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
+    if (!grad_verts || !grad_mlp || (!lv && !grad_tex)) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
+    if (lv) {
+        if ((st = check_levels(c, scene->T, lv->Rmin, lv->Rtop, scene->R))) return st;
+        if (scene->T > 0) {
+            if (!lv->graw) return fail(c, SOUP_ERR_INVALID, "grad_raw is NULL");
+            for (int l = 0; l <= lv->Rtop - lv->Rmin; ++l)
+                if (!lv->graw[l]) return fail(c, SOUP_ERR_INVALID, "grad_raw[%d] (level %d) is NULL", l, lv->Rmin + l);
+        }
+    }
     HIP_TRY(c, hipSetDevice(c->device));
     const Opts o = to_opts(opts);
     bool reused = false;
@@ -1199,6 +1223,14 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
     // (18 KB at R = 5); a texture too large for that takes the per-pixel path with
     // global atomics
     const bool sorted_path = ptri_bwd_lds(scene->R) <= 65536;
+    // levels: folded into the sorted path's flush where level R - 1 fits its stage;
+    // otherwise the texture gradient goes to a workspace and through the assembly's
+    // backward
+    const bool fused = lv && sorted_path && ptri_levels_fit(scene->R);
+    if (lv && !fused) {
+        if ((st = ensure(c, c->gtex, static_cast<size_t>(n_tex) * sizeof(float)))) return st;
+        grad_tex = static_cast<float*>(c->gtex.p);
+    }
     const int nb = sorted_path ? ptri_blocks(c->num_cus, scene->R) : pwinner_blocks(c->num_cus);
     const int rows = sorted_path ? nb : nb * 4;
     if ((st = ensure(c, c->edge_w, static_cast<size_t>(p.n_pix) * sizeof(float2))) ||
@@ -1219,7 +1251,13 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
     }
     {
         Timed t(c, SOUP_T_FILL, s);
-        if (!o.accumulate) launch_fill_f32(grad_tex, n_tex, 0.0f, s);
+        if (fused) {
+            if (!o.accumulate)
+                for (int l = 0; l <= lv->Rtop - lv->Rmin; ++l)
+                    launch_fill_f32(lv->graw[l], static_cast<int64_t>(T) * mc_count(lv->Rmin + l) * kPCh, 0.0f, s);
+        } else if (!o.accumulate || lv) {   // the workspace starts from zero
+            launch_fill_f32(grad_tex, n_tex, 0.0f, s);
+        }
         launch_fill_i32(static_cast<int32_t*>(c->gvert.p), static_cast<int64_t>(T) * 18, 0, s);
     }
     const float* gl = o.mode == 0 ? grad_logp : nullptr;
@@ -1263,8 +1301,14 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
         ta.grad_color = grad_color;
         ta.edge_w = ew;
         ta.score = gl ? 1 : 0;
-        ta.accumulate = o.accumulate;
-        ta.grad_tex = grad_tex;
+        ta.accumulate = lv && !fused ? 0 : o.accumulate;
+        ta.grad_tex = fused ? nullptr : grad_tex;
+        if (fused) {
+            ta.levels = 1;
+            ta.Rmin = lv->Rmin;
+            ta.Rtop = lv->Rtop;
+            for (int l = 0; l <= lv->Rtop - lv->Rmin; ++l) ta.graw[l] = lv->graw[l];
+        }
         ta.gvert = static_cast<double*>(c->gvert.p);
         ta.mlp_partial = static_cast<float*>(c->partial.p);
         ta.n_blocks = nb;
@@ -1309,6 +1353,22 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
         launch_pwinner_bwd(wa, s);
     }
     HIP_TRY(c, hipGetLastError());
+    if (lv && !fused) {   // the workspace's texture gradient through the assembly's backward
+        Timed t(c, SOUP_T_ASSEMBLE_BWD, s);
+        AssembleArgs aa{};
+        for (int l = 0; l <= lv->Rtop - lv->Rmin; ++l) aa.graw[l] = lv->graw[l];
+        aa.Rmin = lv->Rmin;
+        aa.Rtop = lv->Rtop;
+        aa.Rmax = scene->R;
+        aa.T = T;
+        aa.tex = scene->tex;
+        aa.grad_tex = grad_tex;
+        aa.accumulate = o.accumulate;
+        if (mc_assemble_bwd_lds(aa.Rmin, aa.Rmax) > mc_assemble_bwd_lds_cap(c->lds_limit) && !o.accumulate && T > 0)
+            for (int l = 0; l <= aa.Rtop - aa.Rmin; ++l)
+                launch_fill_f32(aa.graw[l], static_cast<int64_t>(T) * mc_count(aa.Rmin + l) * kPCh, 0.0f, s);
+        launch_mc_assemble_bwd(aa, c->lds_limit, s);
+    }
     {
         Timed t(c, SOUP_T_REDUCE, s);
         launch_pvert_finish(static_cast<double*>(c->gvert.p), grad_verts, static_cast<int64_t>(T) * 9,
@@ -1320,12 +1380,22 @@ soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_vie
     return finish_stats(c, s, false);
 }
 
-static soup_status check_levels(soup_ctx* c, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax) {
-    if (T < 0) return fail(c, SOUP_ERR_INVALID, "T = %d < 0", T);
-    if (Rmin < 0 || Rtop < Rmin || Rmax < Rtop || Rmax > kPMaxR || Rtop - Rmin + 1 > kPMaxLevels)
-        return fail(c, SOUP_ERR_INVALID, "levels Rmin = %d, Rtop = %d, Rmax = %d: need 0 <= Rmin <= Rtop <= Rmax <= %d",
-                    Rmin, Rtop, Rmax, kPMaxR);
-    return SOUP_OK;
+soup_status soup_pbackward(soup_ctx* c, const soup_pscene* scene, const soup_views* views, const float* inv_view_proj,
+                           const soup_opts* opts, const uint64_t* vis, const float* color, const float* grad_color,
+                           const float* grad_logp, float* grad_verts, float* grad_tex, float* grad_mlp,
+                           void* stream) {
+    return pbackward_impl(c, scene, views, inv_view_proj, opts, vis, color, grad_color, grad_logp, grad_verts, grad_tex,
+                          nullptr, grad_mlp, stream);
+}
+
+soup_status soup_pbackward_levels(soup_ctx* c, const soup_pscene* scene, const soup_views* views,
+                                  const float* inv_view_proj, const soup_opts* opts, const uint64_t* vis,
+                                  const float* color, const float* grad_color, const float* grad_logp,
+                                  int32_t Rmin, int32_t Rtop, float* grad_verts, float* const* grad_raw,
+                                  float* grad_mlp, void* stream) {
+    const LevelsOut lv{Rmin, Rtop, grad_raw};
+    return pbackward_impl(c, scene, views, inv_view_proj, opts, vis, color, grad_color, grad_logp, grad_verts, nullptr,
+                          &lv, grad_mlp, stream);
 }
 
 soup_status soup_mc_assemble(soup_ctx* c, int32_t T, int32_t Rmin, int32_t Rtop, int32_t Rmax, const float* const* raw,

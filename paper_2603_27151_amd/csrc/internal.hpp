@@ -298,8 +298,15 @@ struct PTriArgs {
     double* gvert;                   // [T, 9] float64 sums (zeroed by the caller)
     float* mlp_partial;              // [n_blocks, 595]
     int n_blocks;                    // single-wave workgroups, a multiple of 8
+    // levels = 1: the learnable levels' gradients instead of grad_tex (tex is
+    // their assembly onto level R); graw[l] = level Rmin + l, zero-filled by
+    // the caller unless accumulating
+    int levels;
+    int Rmin, Rtop;
+    float* graw[kPMaxLevels];
 };
 size_t ptri_bwd_lds(int R);
+bool ptri_levels_fit(int R);   // level R - 1 fits the kernel's stage buffer
 int ptri_blocks(int num_cus, int R);
 void launch_ptri_bwd(const PTriArgs& a, hipStream_t s);
 int pwinner_blocks(int num_cus);

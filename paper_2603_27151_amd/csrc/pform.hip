@@ -809,6 +809,19 @@ void launch_pwinner_bwd(const PWinArgs& a, hipStream_t s) {
 // run may share a grid vertex). When the triangle changes, the row's nonzero
 // entries go to HBM: plain stores when the wave holds all of the triangle's
 // fragments, float atomics when the triangle straddles two waves' ranges.
+//
+// LEVELS: the gradient of the learnable levels instead of the assembled
+// texture's (the assembly's backward folded in). Every add into the row is
+// multiplied by tex (1 - tex) at its grid vertex (the sigmoid's derivative;
+// the texels are the ones the fragment's lookups already read), so the row
+// holds the gradient of the level-R sum; when the triangle changes, the
+// restriction chain (the transpose of the lookups at the level-R vertices:
+// the coincident vertex with weight 1, the six lattice neighbours with 1/2)
+// runs in LDS, level R - 1 in the stage buffer (free between batches), level
+// R - 2 back in the row, and so on, and each learnable level goes out. The
+// restriction is linear, so a triangle split between two waves restricts
+// each part and adds them.
+template <bool LEVELS>
 __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
     __shared__ __align__(16) float stage[2][kPIn][kPStage];
     __shared__ double vsum[9];
@@ -829,17 +842,78 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
     f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
     float ab0 = 0.f, ab1 = 0.f, ab2 = 0.f;
     int cur = -1;   // triangle held in the row (wave-uniform)
+    // level L's gradient (n floats at src) out to its grid rows: plain stores
+    // when the wave owns the triangle, else atomics of the nonzero entries
+    auto put = [&](float* __restrict__ g, const float* src, int nf4, bool owned) __attribute__((always_inline)) {
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        float4* g4 = reinterpret_cast<float4*>(g);
+        for (int k = lane; k < nf4; k += 64) {
+            float4 v = s4[k];
+            if (owned) {
+                if (a.accumulate) {   // the outputs were zero-filled unless accumulating
+                    const float4 o = g4[k];
+                    v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+                }
+                g4[k] = v;
+            } else {
+                if (v.x != 0.0f) atomicAdd(&g[4 * k], v.x);
+                if (v.y != 0.0f) atomicAdd(&g[4 * k + 1], v.y);
+                if (v.z != 0.0f) atomicAdd(&g[4 * k + 2], v.z);
+                if (v.w != 0.0f) atomicAdd(&g[4 * k + 3], v.w);
+            }
+        }
+    };
     // the row's nonzero entries go out and are cleared
     auto flush = [&](int t) __attribute__((always_inline)) {
         wave_fence();
         const bool owned = a.tri_off[t] >= f0 && a.tri_off[t + 1] <= f1;
-        float* g = a.grad_tex + static_cast<size_t>(t) * NR;
-        for (int k = lane; k < NR; k += 64) {
-            const float v = row[k];
-            if (v != 0.0f) {
-                row[k] = 0.0f;
-                if (owned) g[k] = a.accumulate ? g[k] + v : v;   // the row was zero-filled unless accumulating
-                else atomicAdd(&g[k], v);
+        if constexpr (LEVELS) {
+            float* cur_l = row;
+            float* nxt_l = &st[0][0][0];
+            for (int L = R;; --L) {
+                const int VL = mc_count(L);
+                if (L <= a.Rtop) put(a.graw[L - a.Rmin] + static_cast<size_t>(t) * VL * kPCh, cur_l, VL * 2, owned);
+                if (L == a.Rmin) break;
+                // level L onto level L - 1: lane per (coarse vertex, four channels)
+                const int nc = 1 << (L - 1), nfl = 1 << L, Vc = mc_count(L - 1);
+                const float4* c4 = reinterpret_cast<const float4*>(cur_l);
+                float4* n4 = reinterpret_cast<float4*>(nxt_l);
+                for (int e = lane; e < Vc * 2; e += 64) {
+                    const int q = e >> 1, h = e & 1;
+                    int I, J;
+                    mc_ij(nc, q, I, J);
+                    const int i = 2 * I, j = 2 * J;
+                    float4 side = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    auto add = [&](int ii, int jj) __attribute__((always_inline)) {
+                        const float4 v = c4[mc_index(nfl, ii, jj) * 2 + h];
+                        side = make_float4(side.x + v.x, side.y + v.y, side.z + v.z, side.w + v.w);
+                    };
+                    if (i + 1 + j <= nfl) add(i + 1, j);
+                    if (i > 0) add(i - 1, j);
+                    if (i + j + 1 <= nfl) add(i, j + 1);
+                    if (j > 0) add(i, j - 1);
+                    if (j > 0) add(i + 1, j - 1);
+                    if (i > 0) add(i - 1, j + 1);
+                    const float4 c = c4[mc_index(nfl, i, j) * 2 + h];
+                    n4[e] = make_float4(c.x + 0.5f * side.x, c.y + 0.5f * side.y, c.z + 0.5f * side.z,
+                                        c.w + 0.5f * side.w);
+                }
+                wave_fence();
+                float* tmp = cur_l;
+                cur_l = nxt_l;
+                nxt_l = tmp;
+            }
+            float4* r4 = reinterpret_cast<float4*>(row);
+            for (int k = lane; k < NR / 4; k += 64) r4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        } else {
+            float* g = a.grad_tex + static_cast<size_t>(t) * NR;
+            for (int k = lane; k < NR; k += 64) {
+                const float v = row[k];
+                if (v != 0.0f) {
+                    row[k] = 0.0f;
+                    if (owned) g[k] = a.accumulate ? g[k] + v : v;   // the row was zero-filled unless accumulating
+                    else atomicAdd(&g[k], v);
+                }
             }
         }
         if (lane < 9) {
@@ -860,10 +934,13 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
         const float b1 = __uint_as_float(fr.p1.x), b2 = __uint_as_float(fr.p1.y);
         Micro m{};
         float alpha = 1.0f;
+        float s7[3] = {0.f, 0.f, 0.f};   // the opacity texels of the three grid vertices
         if (on) {
             m = micro_of(n, b1, b2);
             gfloat* t7 = tex + static_cast<size_t>(tri) * NR + (kPCh - 1);
-            alpha = mc_mix(m, t7[m.idx[0] * kPCh], t7[m.idx[1] * kPCh], t7[m.idx[2] * kPCh]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) s7[q] = t7[m.idx[q] * kPCh];
+            alpha = mc_mix(m, s7[0], s7[1], s7[2]);
         }
         // d log p / d alpha: 1 / alpha for the winner, -1 / (1 - alpha) in front of it
         const float da = gl == 0.0f ? 0.0f : (win ? gl / alpha : -gl / (1.0f - alpha));
@@ -995,11 +1072,16 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
                 for (int q = 0; q < 3; ++q) {
                     if (m.w[q] == 0.0f) continue;
                     float* rv = row + m.idx[q] * kPCh;
-                    if (da != 0.0f) atomicAdd(rv + (kPCh - 1), m.w[q] * da);
+                    // LEVELS: times the sigmoid's derivative at the grid vertex
+                    const float w7 = LEVELS ? m.w[q] * (s7[q] * (1.0f - s7[q])) : m.w[q];
+                    if (da != 0.0f) atomicAdd(rv + (kPCh - 1), w7 * da);
                     if (cpath) {
 #pragma unroll
-                        for (int c = 0; c < kPFeat; ++c)
-                            if (dfeat[c] != 0.0f) atomicAdd(rv + c, m.w[q] * dfeat[c]);
+                        for (int c = 0; c < kPFeat; ++c) {
+                            const float tq = c < 4 ? (&tv[q][0].x)[c] : (&tv[q][1].x)[c - 4];
+                            const float wc = LEVELS ? m.w[q] * (tq * (1.0f - tq)) : m.w[q];
+                            if (dfeat[c] != 0.0f) atomicAdd(rv + c, wc * dfeat[c]);
+                        }
                     }
                 }
             }
@@ -1048,7 +1130,7 @@ size_t ptri_bwd_lds(int R) { return static_cast<size_t>(mc_count(R)) * kPCh * si
 // would double the time.
 int ptri_blocks(int num_cus, int R) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ptri_bwd_kernel, 64, ptri_bwd_lds(R)) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ptri_bwd_kernel<true>, 64, ptri_bwd_lds(R)) != hipSuccess ||
         per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 1;
@@ -1056,9 +1138,16 @@ int ptri_blocks(int num_cus, int R) {
     return (num_cus * per_cu / kXcds) * kXcds > 0 ? (num_cus * per_cu / kXcds) * kXcds : kXcds;
 }
 
+bool ptri_levels_fit(int R) { return R < 1 || static_cast<size_t>(mc_count(R - 1)) * kPCh <= 2 * kPIn * kPStage; }
+
 void launch_ptri_bwd(const PTriArgs& a, hipStream_t s) {
     if (a.n_blocks <= 0) return;
-    hipLaunchKernelGGL(ptri_bwd_kernel, dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), ptri_bwd_lds(a.R), s, a);
+    if (a.levels)
+        hipLaunchKernelGGL(ptri_bwd_kernel<true>, dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), ptri_bwd_lds(a.R),
+                           s, a);
+    else
+        hipLaunchKernelGGL(ptri_bwd_kernel<false>, dim3(static_cast<unsigned>(a.n_blocks)), dim3(64), ptri_bwd_lds(a.R),
+                           s, a);
 }
 
 __global__ __launch_bounds__(256) void pvert_finish_kernel(const double* __restrict__ g, float* __restrict__ out,

@@ -339,6 +339,27 @@ def pbackward(scene: PDeviceScene, views: Views, opts: Opts, vis, color, grad_co
     return gv, gt, gm
 
 
+def pbackward_levels(scene: PDeviceScene, views: Views, opts: Opts, vis, color, grad_color, Rmin: int,
+                     n_levels: int, grad_logp=None, minv=None, ctx=None, stream=None, out=None):
+    """(d verts [T,3,3], [d level Rmin + l, [T,V,8], for l < n_levels], d mlp [595]) of the paper
+    form, scene.tex being the assembly of those levels onto level scene.R."""
+    ctx = ctx or context()
+    T = scene.T
+    if out is None:
+        gv = torch.empty_like(scene.verts)
+        gr = [torch.empty(T, mc_vertices(Rmin + l), 8, dtype=torch.float32, device=scene.tex.device)
+              for l in range(n_levels)]
+        gm = torch.empty_like(scene.mlp)
+    else:
+        gv, gr, gm = out
+    minv = inv_view_proj(views) if minv is None else minv
+    h = _lib._Holder()
+    _lib.soup_pbackward_levels(ctx, scene.c_struct(), views.c_struct(h), minv, opts.c_struct(), vis, color,
+                               grad_color.contiguous(), None if grad_logp is None else grad_logp.contiguous(), Rmin,
+                               gv, gr, gm, stream)
+    return gv, gr, gm
+
+
 def mc_vertices(R: int) -> int:
     n = 1 << R
     return (n + 1) * (n + 2) // 2

@@ -149,6 +149,78 @@ def test_paper_backward_matches_oracle(case, from_log):
                     tag="gpu-paper")
 
 
+# (seed, T, R, Rmin, Rtop, view sizes, from_log): the paper's levels 2..4 onto 5;
+# the finest grid learnable too; one level; R = 6, whose sorted path does not
+# exist, through the texture-gradient workspace and the assembly's backward
+LEVEL_CASES = [
+    dict(seed=21, T=300, R=5, Rmin=2, Rtop=4, sizes=[(64, 64), (13, 40), (1, 1)], from_log=False),
+    dict(seed=22, T=400, R=3, Rmin=0, Rtop=3, sizes=[(97, 61)], from_log=True),
+    dict(seed=23, T=200, R=2, Rmin=1, Rtop=1, sizes=[(48, 40)], from_log=False),
+    dict(seed=24, T=80, R=6, Rmin=3, Rtop=5, sizes=[(56, 40)], from_log=False),
+]
+
+
+@pytest.mark.parametrize("case", LEVEL_CASES, ids=lambda c: f"R{c['R']}L{c['Rmin']}-{c['Rtop']}")
+def test_paper_levels_backward_matches_oracle(case):
+    """soup_pbackward_levels against the oracle's backward followed by its
+    assembly backward, on a texture assembled from random levels; then with
+    accumulate = 1. Many fragments per wave in the first case put triangles
+    on both sides of wave boundaries (the restricted parts are added)."""
+    _say("levels backward", case)
+    R = _R()
+    rng = np.random.default_rng(case["seed"])
+    ps = _soup(case["seed"], case["T"], case["R"])
+    lv = W.random_levels(rng, case["T"], case["Rmin"], case["Rtop"], case["R"], sd=1.0)
+    ps.tex = O.mc_assemble(lv.raw, case["Rmin"], case["R"])
+    views = _views(case["sizes"])
+    o = O.Opts(seed=0xBEEF + case["seed"], step=5, mode=0)
+    ds = R.PDeviceScene.from_host(ps)
+    rv = R.Views.from_list(views)
+    ro = R.Opts(seed=o.seed, step=5, mode=0, reuse_bins=1 if case["from_log"] else 0)
+    vis, col, _ = R.pforward(ds, rv, ro)
+    P = rv.pixels
+    gc = rng.normal(size=(P, 3)).astype(np.float32)
+    gl = rng.normal(size=P).astype(np.float32)
+    n_lv = case["Rtop"] - case["Rmin"] + 1
+    gv, gr, gm = R.pbackward_levels(ds, rv, ro, vis, col, torch.from_numpy(gc).cuda(), case["Rmin"], n_lv,
+                                    grad_logp=torch.from_numpy(gl).cuda())
+    torch.cuda.synchronize()
+    T, V = ps.tex.shape[0], ps.tex.shape[1]
+    out = (np.zeros((T, 3, 3)), np.zeros((T, V, 8)), np.zeros(O.pmlp_params()))
+    off = 0
+    vis_h, col_h = _u64(vis), col.cpu().numpy()
+    for v in views:
+        n = v.width * v.height
+        O.pbackward(ps, v, W.inv_view_proj(v.M), o, vis_h[off:off + n].reshape(v.height, v.width),
+                    col_h[off:off + n].reshape(v.height, v.width, 3), gc[off:off + n].reshape(v.height, v.width, 3),
+                    gl[off:off + n].reshape(v.height, v.width), out=out)
+        off += n
+    ref_lv = O.mc_assemble_bwd(ps.tex, out[1].astype(np.float32), case["Rmin"], n_lv, case["R"])
+    names = ["verts"] + [f"level{case['Rmin'] + l}" for l in range(n_lv)] + ["mlp"]
+    PT.assert_grads([gv.cpu().numpy()] + [g.cpu().numpy() for g in gr] + [gm.cpu().numpy()],
+                    [out[0]] + list(ref_lv) + [out[2]], names=names, tag="gpu-paper")
+    ro2 = R.Opts(seed=o.seed, step=5, mode=0, accumulate=1)
+    gv2, gr2, gm2 = R.pbackward_levels(ds, rv, ro2, vis, col, torch.from_numpy(gc).cuda(), case["Rmin"], n_lv,
+                                       grad_logp=torch.from_numpy(gl).cuda(),
+                                       out=(gv.clone(), [g.clone() for g in gr], gm.clone()))
+    torch.cuda.synchronize()
+    PT.assert_grads([gv2.cpu().numpy()] + [g.cpu().numpy() for g in gr2] + [gm2.cpu().numpy()],
+                    [2 * out[0]] + [2 * x for x in ref_lv] + [2 * out[2]], names=[n + "+" for n in names],
+                    tag="gpu-paper")
+
+
+def test_paper_levels_backward_rejects_bad_levels():
+    from paper_2603_27151_amd import _lib
+    R = _R()
+    ps = _soup(5, 10, 3)
+    ds = R.PDeviceScene.from_host(ps)
+    rv = R.Views.from_list(_views([(8, 8)]))
+    vis, col, _ = R.pforward(ds, rv, R.Opts())
+    gc = torch.zeros(rv.pixels, 3, device="cuda")
+    with pytest.raises(_lib.SoupError):   # Rtop above the scene's level
+        R.pbackward_levels(ds, rv, R.Opts(), vis, col, gc, 2, 3)
+
+
 def test_paper_opacity_one_is_a_z_buffer_and_blend_limits():
     """Opacity 1 everywhere: the winner is the nearest covering fragment
     whatever the draws (two seeds give the same buffer); A = 1 gives the RGB
