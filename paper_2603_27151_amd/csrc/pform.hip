@@ -820,15 +820,41 @@ void launch_pwinner_bwd(const PWinArgs& a, hipStream_t s) {
 // runs in LDS, level R - 1 in the stage buffer (free between batches), level
 // R - 2 back in the row, and so on, and each learnable level goes out. The
 // restriction is linear, so a triangle split between two waves restricts
-// each part and adds them.
+// each part and adds them. The seven fine-grid indices of every coarse
+// vertex are tabulated once per workgroup (a neighbour outside the grid
+// points at a zero vertex one past the level's last), so a restriction step
+// is one table read and seven 16-byte reads per (vertex, four channels).
+constexpr int kPTabMax = 153 + 45 + 15 + 6 + 1;   // coarse vertices of levels 4..0 (the sorted path has R <= 5)
 template <bool LEVELS>
 __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
     __shared__ __align__(16) float stage[2][kPIn][kPStage];
     __shared__ double vsum[9];
-    extern __shared__ __align__(16) float row[];   // [V][8]: the current triangle's texture gradient
+    __shared__ uint4 s_tab[LEVELS ? kPTabMax : 1];   // per coarse vertex: centre, six neighbours (16-bit)
+    extern __shared__ __align__(16) float row[];   // [V + 1][8]: the current triangle's texture gradient, a zero vertex
     const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
     float (*st)[kPIn][kPStage] = stage;
     const int R = a.R, n = 1 << R, V = mc_count(R), NR = V * kPCh;
+    if constexpr (LEVELS) {   // the restriction tables of levels R - 1 down to Rmin, in that order
+        int off = 0;
+        for (int L = R; L > a.Rmin; --L) {
+            const int nc = 1 << (L - 1), nfl = 1 << L, Vc = mc_count(L - 1), Vfl = mc_count(L);
+            for (int q = lane; q < Vc; q += 64) {
+                int I, J;
+                mc_ij(nc, q, I, J);
+                const int i = 2 * I, j = 2 * J;
+                const uint32_t z = static_cast<uint32_t>(Vfl);   // the zero vertex
+                const uint32_t c = mc_index(nfl, i, j);
+                const uint32_t n1 = i + 1 + j <= nfl ? mc_index(nfl, i + 1, j) : z;
+                const uint32_t n2 = i > 0 ? mc_index(nfl, i - 1, j) : z;
+                const uint32_t n3 = i + j + 1 <= nfl ? mc_index(nfl, i, j + 1) : z;
+                const uint32_t n4 = j > 0 ? mc_index(nfl, i, j - 1) : z;
+                const uint32_t n5 = j > 0 ? mc_index(nfl, i + 1, j - 1) : z;   // i + 1 + j - 1 <= n always
+                const uint32_t n6 = i > 0 ? mc_index(nfl, i - 1, j + 1) : z;
+                s_tab[off + q] = make_uint4(c | (n1 << 16), n2 | (n3 << 16), n4 | (n5 << 16), n6);
+            }
+            off += Vc;
+        }
+    }
     cfloat* mp = as_const(a.mlp);
     gfloat* tex = as_global(a.tex);
     const int64_t E = a.tri_off[a.T];
@@ -837,7 +863,7 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
     const int64_t wid = xcd_block();
     const int64_t bbeg = nb * wid / nw, bend = nb * (wid + 1) / nw;
     const int64_t f0 = bbeg * 64, f1 = bend * 64 < E ? bend * 64 : E;
-    for (int k = lane; k < NR; k += 64) row[k] = 0.0f;
+    for (int k = lane; k < NR + kPCh; k += 64) row[k] = 0.0f;
     if (lane < 9) vsum[lane] = 0.0;
     f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
     float ab0 = 0.f, ab1 = 0.f, ab2 = 0.f;
@@ -870,49 +896,58 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
         if constexpr (LEVELS) {
             float* cur_l = row;
             float* nxt_l = &st[0][0][0];
+            int off = 0;
             for (int L = R;; --L) {
                 const int VL = mc_count(L);
                 if (L <= a.Rtop) put(a.graw[L - a.Rmin] + static_cast<size_t>(t) * VL * kPCh, cur_l, VL * 2, owned);
                 if (L == a.Rmin) break;
-                // level L onto level L - 1: lane per (coarse vertex, four channels)
-                const int nc = 1 << (L - 1), nfl = 1 << L, Vc = mc_count(L - 1);
+                // level L onto level L - 1: lane per (coarse vertex, four channels); the
+                // neighbours in a fixed order, an absent one read as the zero vertex
+                const int Vc = mc_count(L - 1);
                 const float4* c4 = reinterpret_cast<const float4*>(cur_l);
                 float4* n4 = reinterpret_cast<float4*>(nxt_l);
                 for (int e = lane; e < Vc * 2; e += 64) {
-                    const int q = e >> 1, h = e & 1;
-                    int I, J;
-                    mc_ij(nc, q, I, J);
-                    const int i = 2 * I, j = 2 * J;
-                    float4 side = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    auto add = [&](int ii, int jj) __attribute__((always_inline)) {
-                        const float4 v = c4[mc_index(nfl, ii, jj) * 2 + h];
-                        side = make_float4(side.x + v.x, side.y + v.y, side.z + v.z, side.w + v.w);
-                    };
-                    if (i + 1 + j <= nfl) add(i + 1, j);
-                    if (i > 0) add(i - 1, j);
-                    if (i + j + 1 <= nfl) add(i, j + 1);
-                    if (j > 0) add(i, j - 1);
-                    if (j > 0) add(i + 1, j - 1);
-                    if (i > 0) add(i - 1, j + 1);
-                    const float4 c = c4[mc_index(nfl, i, j) * 2 + h];
-                    n4[e] = make_float4(c.x + 0.5f * side.x, c.y + 0.5f * side.y, c.z + 0.5f * side.z,
-                                        c.w + 0.5f * side.w);
+                    const uint4 ix = s_tab[off + (e >> 1)];
+                    const int h = e & 1;
+                    const float4 c = c4[(ix.x & 0xFFFFu) * 2 + h];
+                    const float4 v1 = c4[(ix.x >> 16) * 2 + h], v2 = c4[(ix.y & 0xFFFFu) * 2 + h];
+                    const float4 v3 = c4[(ix.y >> 16) * 2 + h], v4 = c4[(ix.z & 0xFFFFu) * 2 + h];
+                    const float4 v5 = c4[(ix.z >> 16) * 2 + h], v6 = c4[ix.w * 2 + h];
+                    const float4 sd = make_float4(((((v1.x + v2.x) + v3.x) + v4.x) + v5.x) + v6.x,
+                                                  ((((v1.y + v2.y) + v3.y) + v4.y) + v5.y) + v6.y,
+                                                  ((((v1.z + v2.z) + v3.z) + v4.z) + v5.z) + v6.z,
+                                                  ((((v1.w + v2.w) + v3.w) + v4.w) + v5.w) + v6.w);
+                    n4[e] = make_float4(c.x + 0.5f * sd.x, c.y + 0.5f * sd.y, c.z + 0.5f * sd.z, c.w + 0.5f * sd.w);
                 }
+                if (lane < 2) n4[Vc * 2 + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // level L - 1's zero vertex
+                off += Vc;
                 wave_fence();
                 float* tmp = cur_l;
                 cur_l = nxt_l;
                 nxt_l = tmp;
             }
-            float4* r4 = reinterpret_cast<float4*>(row);
-            for (int k = lane; k < NR / 4; k += 64) r4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float4* r4 = reinterpret_cast<float4*>(row);   // the row and its zero vertex
+            for (int k = lane; k < (NR + kPCh) / 4; k += 64) r4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         } else {
+            float4* r4 = reinterpret_cast<float4*>(row);
+            float4* g4 = reinterpret_cast<float4*>(a.grad_tex + static_cast<size_t>(t) * NR);
             float* g = a.grad_tex + static_cast<size_t>(t) * NR;
-            for (int k = lane; k < NR; k += 64) {
-                const float v = row[k];
-                if (v != 0.0f) {
-                    row[k] = 0.0f;
-                    if (owned) g[k] = a.accumulate ? g[k] + v : v;   // the row was zero-filled unless accumulating
-                    else atomicAdd(&g[k], v);
+            for (int k = lane; k < NR / 4; k += 64) {
+                float4 v = r4[k];
+                if (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) {
+                    r4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if (owned) {   // the texture gradient was zero-filled unless accumulating
+                        if (a.accumulate) {
+                            const float4 o = g4[k];
+                            v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+                        }
+                        g4[k] = v;
+                    } else {
+                        if (v.x != 0.0f) atomicAdd(&g[4 * k], v.x);
+                        if (v.y != 0.0f) atomicAdd(&g[4 * k + 1], v.y);
+                        if (v.z != 0.0f) atomicAdd(&g[4 * k + 2], v.z);
+                        if (v.w != 0.0f) atomicAdd(&g[4 * k + 3], v.w);
+                    }
                 }
             }
         }
@@ -1123,7 +1158,7 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
     }
 }
 
-size_t ptri_bwd_lds(int R) { return static_cast<size_t>(mc_count(R)) * kPCh * sizeof(float); }
+size_t ptri_bwd_lds(int R) { return static_cast<size_t>(mc_count(R) + 1) * kPCh * sizeof(float); }
 
 // As many single-wave workgroups as are resident at once (the LDS row bounds them), a
 // multiple of eight: the wave ranges are static, so a second round of workgroups
@@ -1138,7 +1173,10 @@ int ptri_blocks(int num_cus, int R) {
     return (num_cus * per_cu / kXcds) * kXcds > 0 ? (num_cus * per_cu / kXcds) * kXcds : kXcds;
 }
 
-bool ptri_levels_fit(int R) { return R < 1 || static_cast<size_t>(mc_count(R - 1)) * kPCh <= 2 * kPIn * kPStage; }
+bool ptri_levels_fit(int R) {
+    // level R - 1 and its zero vertex in the stage buffer; the tables of levels R - 1.. (R <= 5)
+    return R < 1 || (R <= 5 && static_cast<size_t>(mc_count(R - 1) + 1) * kPCh <= 2 * kPIn * kPStage);
+}
 
 void launch_ptri_bwd(const PTriArgs& a, hipStream_t s) {
     if (a.n_blocks <= 0) return;
