@@ -868,13 +868,16 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
     f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
     float ab0 = 0.f, ab1 = 0.f, ab2 = 0.f;
     int cur = -1;   // triangle held in the row (wave-uniform)
+    // whether the wave holds all of the current triangle's fragments, loaded
+    // when the triangle becomes current (its flush needs it)
+    bool cur_owned = false;
     // level L's gradient (n floats at src) out to its grid rows: plain stores
-    // when the wave owns the triangle, else atomics of the nonzero entries
+    // when the wave owns the triangle, else atomics of the nonzero entries;
+    // two rows per lane and step, their LDS reads issued together
     auto put = [&](float* __restrict__ g, const float* src, int nf4, bool owned) __attribute__((always_inline)) {
         const float4* s4 = reinterpret_cast<const float4*>(src);
         float4* g4 = reinterpret_cast<float4*>(g);
-        for (int k = lane; k < nf4; k += 64) {
-            float4 v = s4[k];
+        auto out1 = [&](int k, float4 v) __attribute__((always_inline)) {
             if (owned) {
                 if (a.accumulate) {   // the outputs were zero-filled unless accumulating
                     const float4 o = g4[k];
@@ -887,12 +890,19 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
                 if (v.z != 0.0f) atomicAdd(&g[4 * k + 2], v.z);
                 if (v.w != 0.0f) atomicAdd(&g[4 * k + 3], v.w);
             }
+        };
+        int k = lane;
+        for (; k + 64 < nf4; k += 128) {
+            const float4 v0 = s4[k], v1 = s4[k + 64];
+            out1(k, v0);
+            out1(k + 64, v1);
         }
+        if (k < nf4) out1(k, s4[k]);
     };
     // the row's nonzero entries go out and are cleared
     auto flush = [&](int t) __attribute__((always_inline)) {
         wave_fence();
-        const bool owned = a.tri_off[t] >= f0 && a.tri_off[t + 1] <= f1;
+        const bool owned = cur_owned;
         if constexpr (LEVELS) {
             float* cur_l = row;
             float* nxt_l = &st[0][0][0];
@@ -906,8 +916,7 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
                 const int Vc = mc_count(L - 1);
                 const float4* c4 = reinterpret_cast<const float4*>(cur_l);
                 float4* n4 = reinterpret_cast<float4*>(nxt_l);
-                for (int e = lane; e < Vc * 2; e += 64) {
-                    const uint4 ix = s_tab[off + (e >> 1)];
+                auto one = [&](int e, uint4 ix) __attribute__((always_inline)) {
                     const int h = e & 1;
                     const float4 c = c4[(ix.x & 0xFFFFu) * 2 + h];
                     const float4 v1 = c4[(ix.x >> 16) * 2 + h], v2 = c4[(ix.y & 0xFFFFu) * 2 + h];
@@ -918,7 +927,14 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
                                                   ((((v1.z + v2.z) + v3.z) + v4.z) + v5.z) + v6.z,
                                                   ((((v1.w + v2.w) + v3.w) + v4.w) + v5.w) + v6.w);
                     n4[e] = make_float4(c.x + 0.5f * sd.x, c.y + 0.5f * sd.y, c.z + 0.5f * sd.z, c.w + 0.5f * sd.w);
+                };
+                int e = lane;
+                for (; e + 64 < Vc * 2; e += 128) {   // two items per step: both table reads first
+                    const uint4 i0 = s_tab[off + (e >> 1)], i1 = s_tab[off + ((e + 64) >> 1)];
+                    one(e, i0);
+                    one(e + 64, i1);
                 }
+                if (e < Vc * 2) one(e, s_tab[off + (e >> 1)]);
                 if (lane < 2) n4[Vc * 2 + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // level L - 1's zero vertex
                 off += Vc;
                 wave_fence();
@@ -1099,6 +1115,7 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
             if (t != cur) {
                 if (cur >= 0) flush(cur);
                 cur = t;
+                cur_owned = a.tri_off[t] >= f0 && a.tri_off[t + 1] <= f1;
             }
             const int end = heads ? __builtin_ctzll(heads) : 64;
             const bool in_run = lane >= h && lane < end;
@@ -1121,16 +1138,15 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
                 }
             }
             if (__ballot(in_run && vpath)) {   // the run's winners: vertex sums over the wave
-                double vv[9];
+                double vv[9], q[3];
 #pragma unroll
                 for (int k = 0; k < 9; ++k) vv[k] = in_run ? gw[k] : 0.0;
-#pragma unroll
-                for (int d = 32; d > 0; d >>= 1)
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) vv[k] += __shfl_xor(vv[k], d, 64);
-                if (lane == 0) {
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) vsum[k] += vv[k];
+                wave_sum9(vv, q);
+                if ((lane & 15) == 0) {   // row g's first lane: components c, c + 2 (and 4 in row 0)
+                    const int g = lane >> 4, c0 = (g & 1) + 5 * (g >> 1);
+                    vsum[c0] += q[0];
+                    vsum[c0 + 2] += q[1];
+                    if (g == 0) vsum[4] += q[2];
                 }
             }
             wave_fence();
