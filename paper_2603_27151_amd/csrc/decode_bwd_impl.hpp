@@ -433,16 +433,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                 const bool win_n = (row_bcast(fkey, nb) >> 31) != 0;
                 const float gl_n = row_bcast(__uint_as_float(fb4.x), nb);
                 {
-                    f4v o = {Wt.bo[lane], 0.f, 0.f, 0.f};
+                    // lane group g: outputs 0..3 summed over its own units 16 ib + 4 g + s
+                    f4v pr = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int ib = 0; ib < HB; ++ib) {
                         const f4v wv = Wt.lo[ib][lane];
 #pragma unroll
-                        for (int s4 = 0; s4 < 4; ++s4) o = mfma4(wv[s4], hl[ib][s4], o);
+                        for (int s4 = 0; s4 < 4; ++s4) pr = mfma4x4(wv[s4], hl[ib][s4], pr);
                     }
+                    // the four lane groups' parts summed, output g to lane group g
+                    const float og = pair16f(pair32f(pr[0], pr[2]), pair32f(pr[1], pr[3])) + Wt.bo[lane];
                     const float g0 = row_bcast(__uint_as_float(fb4.y), nb), g1 = row_bcast(__uint_as_float(fb4.z), nb),
                                 g2 = row_bcast(__uint_as_float(fb4.w), nb);
-                    const float sg = sigmoid_fast(o[0]);
+                    const float sg = sigmoid_fast(og);
                     float d;
                     if (grp == 3) d = win_n ? gl_n * (1.0f - sg) : -gl_n * sg;
                     else d = win_n ? (grp == 0 ? g0 : (grp == 1 ? g1 : g2)) * sg * (1.0f - sg) : 0.0f;

@@ -13,9 +13,15 @@
 // the B operand of step s is then register s of the previous layer's D, so
 // layers chain without moving data between lanes, and the A operand is the
 // weight W[16 ob + col][16 ib + 4 grp + s] (pre-arranged in LDS, four steps
-// per 16-byte read). The output layer puts output j on row 4 j of a padded
-// 16-row block, so that lane group j holds output j of every fragment, which
-// is exactly the B operand of the first backward product (K = the 4 outputs).
+// per 16-byte read). The output layer (four outputs) runs on
+// v_mfma_f32_4x4x1f32, sixteen independent 4x4 blocks of four lanes each
+// (lane 4b + j supplies A[j][0] and B[0][j] of block b and holds D[i][j] in
+// register i): block b's lanes share one lane group, so its B operand is the
+// hidden units 16 ib + 4 grp + s of four fragments and its A operand the four
+// outputs' weights of those units; the four lane groups' partial sums are
+// then summed across rows with row swaps so that lane group j ends with
+// output j of every fragment, which is exactly the B operand of the first
+// backward product (K = the 4 outputs).
 // Weight gradients contract over fragments, the other index; activations and
 // deltas are staged through LDS as rows, 16 fragments at a time.
 //
@@ -35,6 +41,9 @@ constexpr int kRowPad = 4;
 
 __device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma4x4(float a, float b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
 // ---- cross-lane moves on the vector ALU ----
@@ -74,6 +83,17 @@ __device__ __forceinline__ float rows_sum(float x) {
     const float y = __uint_as_float(h.a) + __uint_as_float(h.b);
     const U2 q = swap32(__float_as_uint(y), __float_as_uint(y));
     return __uint_as_float(q.a) + __uint_as_float(q.b);
+}
+
+// a over rows {0, 1} + {2, 3} in rows 0 and 1, b likewise in rows 2 and 3.
+__device__ __forceinline__ float pair32f(float a, float b) {
+    const U2 r = swap32(__float_as_uint(a), __float_as_uint(b));
+    return __uint_as_float(r.a) + __uint_as_float(r.b);
+}
+// a over rows 0 + 1 in row 0 and 2 + 3 in row 2; b likewise in rows 1 and 3.
+__device__ __forceinline__ float pair16f(float a, float b) {
+    const U2 r = swap16(__float_as_uint(a), __float_as_uint(b));
+    return __uint_as_float(r.a) + __uint_as_float(r.b);
 }
 
 // Doubles through the 32-bit moves, one half at a time.
@@ -135,7 +155,7 @@ struct MfmaWeights {
     static constexpr int MB = S::NH == 2 ? HB : 1;
     f4v l0[HB][CB][64];      // W0[16 ob + col][16 ib + 4 grp + s]
     f4v l1[MB][MB][64];      // W1[16 ob + col][16 ib + 4 grp + s]
-    f4v lo[HB][64];          // padded output block: row 4 j = W_out[j][16 ib + 4 grp + s]
+    f4v lo[HB][64];          // W_out[lane & 3][16 ib + 4 grp + s]: A operand of the 4x4x1 output products
     float loT[HB][64];       // W_out[grp][16 ob + col]
     f4v l1T[MB][MB][64];     // W1[16 ib + 4 grp + s][16 ob + col]
     f4v l0T[CB][HB][64];     // W0[16 ib + 4 grp + s][16 cb + col]
@@ -172,7 +192,7 @@ struct MfmaWeights {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int k = 16 * b + 4 * grp + s;
-                v[s] = (col & 3) == 0 ? WO[(col >> 2) * S::H + k] : 0.0f;
+                v[s] = WO[(l & 3) * S::H + k];
                 bb[s] = B0[16 * b + 4 * grp + s];
             }
             lo[b][l] = v;
