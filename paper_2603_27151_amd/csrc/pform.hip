@@ -974,41 +974,87 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
         }
         wave_fence();
     };
-    for (int64_t b = bbeg; b < bend; ++b) {
+    // Memory is pipelined across batches: a batch's records are loaded two
+    // batches ahead, and its per-fragment loads (the opacity texels; for a
+    // winner its eight-channel texels, colour gradient and edge weights) are
+    // issued before the previous batch's adds into the row and its flush, so
+    // that their latency falls behind that work.
+    struct Pre {
+        FragRec fr;
+        bool on;
+        Micro m;
+        float s7[3];        // the opacity texels of the micro-triangle's vertices
+        float gc[3];        // the winner's colour gradient
+        float ex, ey;       // ... and its pixel's edge weights
+        float4 tv[3][2];    // ... and its eight-channel texels
+    };
+    auto load_rec = [&](int64_t b, FragRec& fr) __attribute__((always_inline)) {
         const int64_t fi = b * 64 + lane;
-        const bool on = fi < E;
-        FragRec fr = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
-        if (on) fr = a.sorted[fi];
+        fr = {make_uint2(0u, 0u), make_uint2(0u, 0u), make_uint2(0u, 0u)};
+        if (b < bend && fi < E) fr = a.sorted[fi];
+    };
+    auto issue = [&](const FragRec& fr, int64_t b, Pre& P) __attribute__((always_inline)) {
+        P.fr = fr;
+        P.on = b < bend && b * 64 + lane < E;
+        P.m = Micro{};
+        P.ex = P.ey = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            P.s7[q] = 0.f;
+            P.gc[q] = 0.f;
+        }
+        if (P.on) {
+            const uint32_t tri = fr.p0.y & 0x7FFFFFFFu;
+            P.m = micro_of(n, __uint_as_float(fr.p1.x), __uint_as_float(fr.p1.y));
+            gfloat* t7 = tex + static_cast<size_t>(tri) * NR + (kPCh - 1);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) P.s7[q] = t7[P.m.idx[q] * kPCh];
+            if (fr.p0.y >> 31) {   // a winner
+                const uint32_t p = fr.p0.x;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) P.gc[c] = a.grad_color[3 * static_cast<size_t>(p) + c];
+                if (a.edge_w) {
+                    const float2 e = a.edge_w[p];
+                    P.ex = e.x;
+                    P.ey = e.y;
+                }
+                gfloat4* g = reinterpret_cast<gfloat4*>(tex + static_cast<size_t>(tri) * NR);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    P.tv[q][0] = g[2 * P.m.idx[q]];
+                    P.tv[q][1] = g[2 * P.m.idx[q] + 1];
+                }
+            }
+        }
+    };
+    Pre nx;
+    FragRec rec1;
+    {
+        FragRec rec0;
+        load_rec(bbeg, rec0);
+        issue(rec0, bbeg, nx);
+        load_rec(bbeg + 1, rec1);
+    }
+    for (int64_t b = bbeg; b < bend; ++b) {
+        const Pre P = nx;       // this batch's records and loads
+        FragRec rec2;           // the records two batches ahead
+        load_rec(b + 2, rec2);
+        const FragRec& fr = P.fr;
+        const bool on = P.on;
         const uint32_t tri = on ? (fr.p0.y & 0x7FFFFFFFu) : 0xFFFFFFFFu;
         const bool win = on && (fr.p0.y >> 31) != 0u;
         const float gl = a.score ? __uint_as_float(fr.x.x) : 0.0f;
-        const float b1 = __uint_as_float(fr.p1.x), b2 = __uint_as_float(fr.p1.y);
-        Micro m{};
-        float alpha = 1.0f;
-        float s7[3] = {0.f, 0.f, 0.f};   // the opacity texels of the three grid vertices
-        if (on) {
-            m = micro_of(n, b1, b2);
-            gfloat* t7 = tex + static_cast<size_t>(tri) * NR + (kPCh - 1);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) s7[q] = t7[m.idx[q] * kPCh];
-            alpha = mc_mix(m, s7[0], s7[1], s7[2]);
-        }
+        const Micro& m = P.m;
+        const float(&s7)[3] = P.s7;
+        const float alpha = on ? mc_mix(m, s7[0], s7[1], s7[2]) : 1.0f;
         // d log p / d alpha: 1 / alpha for the winner, -1 / (1 - alpha) in front of it
         const float da = gl == 0.0f ? 0.0f : (win ? gl / alpha : -gl / (1.0f - alpha));
         // --- the winner's colour path ---
-        float gc[3] = {0.f, 0.f, 0.f};
-        float ex = 0.f, ey = 0.f;
+        const float(&gc)[3] = P.gc;
+        const float ex = P.ex, ey = P.ey;
         int x = 0, y = 0, v = 0;
         if (win) {
             const uint32_t p = fr.p0.x;
-            gc[0] = a.grad_color[3 * static_cast<size_t>(p)];
-            gc[1] = a.grad_color[3 * static_cast<size_t>(p) + 1];
-            gc[2] = a.grad_color[3 * static_cast<size_t>(p) + 2];
-            if (a.edge_w) {
-                const float2 e = a.edge_w[p];
-                ex = e.x;
-                ey = e.y;
-            }
             v = static_cast<int>(fr.x.y);
             const ViewDesc& vd = a.views[v];
             const uint32_t local = p - static_cast<uint32_t>(vd.pix_base);
@@ -1017,9 +1063,19 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
         }
         const bool cpath = win && (gc[0] != 0.f || gc[1] != 0.f || gc[2] != 0.f);
         const bool vpath = cpath || (win && (ex != 0.f || ey != 0.f));
+        // the winner's setup record and vertices, for its vertex chain after the MLP
+        TriRec tr{};
+        float vx[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vx[k] = 0.f;
+        if (vpath) {
+            tr = a.recs[a.views[v].rec_base + tri];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) vx[k] = a.verts[static_cast<size_t>(tri) * 9 + k];
+        }
+        const float4(&tv)[3][2] = P.tv;
         float in[kPIn], h1[kPHid], h2[kPHid], d1[kPHid], d2[kPHid], d3[kPOut];
         float dfeat[kPFeat];
-        float4 tv[3][2];
 #pragma unroll
         for (int u = 0; u < kPHid; ++u) {
             in[u] = 0.f;
@@ -1035,7 +1091,13 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
         if (cpath) {
             const ViewDesc& vd = a.views[v];
             float feat[kPCh];
-            fetch_texel(tex, tri, V, m, tv, feat);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {   // the texels' interpolation, as fetch_texel
+                feat[4 * h + 0] = mc_mix(m, tv[0][h].x, tv[1][h].x, tv[2][h].x);
+                feat[4 * h + 1] = mc_mix(m, tv[0][h].y, tv[1][h].y, tv[2][h].y);
+                feat[4 * h + 2] = mc_mix(m, tv[0][h].z, tv[1][h].z, tv[2][h].z);
+                feat[4 * h + 3] = mc_mix(m, tv[0][h].w, tv[1][h].w, tv[2][h].w);
+            }
 #pragma unroll
             for (int c = 0; c < kPFeat; ++c) in[c] = feat[c];
             float d[3];
@@ -1097,13 +1159,14 @@ __global__ __launch_bounds__(64) void ptri_bwd_kernel(PTriArgs a) {
                 }
             }
             const ViewDesc& vd = a.views[v];
-            const TriRec tr = a.recs[vd.rec_base + tri];
             float pb1, pb2;
             double E3[3];
             frag_bary(tr, x, y, pb1, pb2, E3);
-            vertex_grad(vd, tr, a.verts + static_cast<size_t>(tri) * 9, x, y, E3, static_cast<double>(dfu) * n,
-                        static_cast<double>(dfv) * n, ex, ey, gw);
+            vertex_grad(vd, tr, vx, x, y, E3, static_cast<double>(dfu) * n, static_cast<double>(dfv) * n, ex, ey, gw);
         }
+        // the next batch's loads go out before this batch's adds and flush
+        issue(rec1, b + 1, nx);
+        rec1 = rec2;
         // --- into the wave's row, one run of equal triangles at a time ---
         const uint32_t tp = static_cast<uint32_t>(__shfl_up(static_cast<int>(tri), 1, 64));
         uint64_t heads = __ballot(lane == 0 || tp != tri);
