@@ -322,3 +322,21 @@ def test_paper_step_at_full_size_on_sampled_pixels():
         for r, x in zip(refs, a):
             r += x
     PT.assert_grads(gpu, refs, names=("verts", "tex", "mlp"), tag="gpu-paper")
+    # the bench's own backward: the levels' gradients straight from the sorted pass,
+    # against the oracle's assembly backward of its texture gradient (on the
+    # triangles that the sampled pixels reach; every other row must stay zero)
+    Rmin, n_lv = wl.levels.Rmin, len(wl.levels.raw)
+    gv, glv, gm = R.pbackward_levels(ds, rv, ro, vis, col, torch.from_numpy(gc).cuda(), Rmin, n_lv,
+                                     grad_logp=torch.from_numpy(gl).cuda())
+    torch.cuda.synchronize()
+    touched = np.nonzero(np.abs(refs[1]).reshape(wl.T, -1).max(1) > 0)[0]
+    _say("levels backward: triangles reached by the sampled pixels", len(touched))
+    ref_lv = O.mc_assemble_bwd(tex_h[touched], refs[1][touched].astype(np.float32), Rmin, n_lv, wl.levels.Rmax)
+    glv = [g.cpu().numpy() for g in glv]
+    PT.assert_grads([gv.cpu().numpy()] + [g[touched] for g in glv] + [gm.cpu().numpy()],
+                    [refs[0]] + list(ref_lv) + [refs[2]],
+                    names=["verts"] + [f"level{Rmin + l}" for l in range(n_lv)] + ["mlp"], tag="gpu-paper")
+    rest = np.ones(wl.T, bool)
+    rest[touched] = False
+    for g in glv:
+        assert not np.any(g[rest]), "a level gradient row outside the sampled pixels' triangles is not zero"
