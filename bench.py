@@ -35,6 +35,8 @@ import numpy as np  # noqa: E402
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published fp32 vector peak (packed FMA)
 PEAK_HBM_GBS = 8000.0
+# non-packed fp32 FMA: 256 CUs x 4 SIMD16 x 16 lanes x 2 FLOP x 2.4 GHz (the library disables packed fp32)
+PEAK_FP32_NON_PACKED_TFLOPS = 78.6
 
 
 def mlp_macs(dims):
@@ -288,6 +290,64 @@ def paper_form_bench(args, R, W, dev, timed):
     return out
 
 
+def ceilings_bench(R, dev):
+    """Measured ceilings on this GPU (the library's probe kernels, HIP events,
+    best of several launches): HBM copy and read of 1 GiB, scattered float
+    atomics, the non-packed float32 FMA rate and the float32 matrix-core
+    rate, beside the published peaks."""
+    import torch
+    from paper_2603_27151_amd import _lib
+    ctx = _lib.Ctx(0)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def best_ms(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    out = {}
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    ms = best_ms(lambda: _lib.soup_probe_copy(ctx, src, dst))
+    out["hbm_copy"] = {"bytes": 2 * nbytes, "ms": round(ms, 4), "gb_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(2 * nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    partial = torch.empty(n_cu * 64, dtype=torch.float32, device=dev)   # 64 workgroups per CU
+    ms = best_ms(lambda: _lib.soup_probe_read(ctx, src, partial))
+    out["hbm_read"] = {"bytes": nbytes, "ms": round(ms, 4), "gb_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    del src, dst
+    slots = torch.zeros(1 << 26, dtype=torch.float32, device=dev)   # 256 MB: beyond the caches
+    n_ops = 1 << 28
+    ms = best_ms(lambda: _lib.soup_probe_atomic(ctx, slots, n_ops), reps=3)
+    out["f32_atomics_scattered"] = {"ops": n_ops, "slots": int(slots.numel()), "ms": round(ms, 4),
+                                    "gops": round(n_ops / (ms * 1e-3) / 1e9, 2)}
+    del slots
+    threads = n_cu * 4 * 8 * 64          # eight waves per SIMD
+    iters = 8192
+    o = torch.empty(threads, dtype=torch.float32, device=dev)
+    ms = best_ms(lambda: _lib.soup_probe_fma(ctx, o, iters))
+    tf = 16.0 * iters * threads / (ms * 1e-3) / 1e12
+    out["valu_fp32_fma"] = {"ms": round(ms, 4), "tflops": round(tf, 2),
+                            "frac_of_non_packed": round(tf / PEAK_FP32_NON_PACKED_TFLOPS, 4),
+                            "frac_of_published": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4)}
+    threads = n_cu * 4 * 2 * 64          # two waves per SIMD
+    o = torch.empty(threads, dtype=torch.float32, device=dev)
+    ms = best_ms(lambda: _lib.soup_probe_mfma(ctx, o, iters))
+    tf = 8192.0 * iters * (threads // 64) / (ms * 1e-3) / 1e12
+    out["mfma_fp32"] = {"ms": round(ms, 4), "tflops": round(tf, 2), "frac_of_published": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4)}
+    ctx.close()
+    return out
+
+
 def single_view_bench(args, R, W, dev, timed):
     """The single-view workload as configured (centres in the unit ball, depth
     complexity 2.97) and with the ball shrunk to a depth complexity of 8 (the
@@ -340,6 +400,7 @@ def parse():
     ap.add_argument("--skip-train", action="store_true")
     ap.add_argument("--skip-paper", action="store_true", help="skip the paper-form step")
     ap.add_argument("--skip-single", action="store_true", help="skip the single-view steps")
+    ap.add_argument("--skip-ceilings", action="store_true", help="skip the measured ceilings")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first copy this many MiB device to device three times (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -693,6 +754,14 @@ def main():
         paper_form = paper_form_bench(args, R, W, dev, timed)
         log("paper form: " + json.dumps(paper_form))
 
+    # measured ceilings of this GPU (probe kernels beside the published peaks)
+    ceilings = None
+    if not args.skip_ceilings:
+        ceilings = ceilings_bench(R, dev)
+        log("ceilings: " + json.dumps(ceilings))
+        roofline["measured_peak_mfma_fp32"] = ceilings["mfma_fp32"]["tflops"]
+        roofline["frac_of_measured_peak"] = round(roofline["achieved"] / ceilings["mfma_fp32"]["tflops"], 4)
+
     # CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.skip_cpu:
@@ -750,6 +819,7 @@ def main():
         "train": train,
         "paper_form": paper_form,
         "single_view": single_view,
+        "ceilings": ceilings,
     }
     print(json.dumps(out), flush=True)
 

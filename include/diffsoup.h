@@ -470,6 +470,33 @@ soup_status soup_selftest_uniform(soup_ctx* ctx, uint64_t seed, const uint32_t* 
                                   const uint32_t* tri, uint32_t view_id, uint32_t step,
                                   float* u, int64_t n, void* stream);
 
+/*
+ * Measured ceilings: kernels of known work that a caller times on `stream`
+ * to put the method's kernels on a measured roofline beside the published
+ * peaks (they compute nothing of the method). Each leaves a result that can
+ * be checked exactly. Device buffers, 16-byte aligned where noted; errors
+ * SOUP_ERR_INVALID for bad arguments.
+ *   soup_probe_copy:   dst = src, `bytes` (a multiple of 16) read and written.
+ *   soup_probe_read:   reads `bytes` of src (a multiple of 16); partial
+ *                      [n_partial] receives per-workgroup sums of its floats
+ *                      (min(bytes / 4096, n_partial) of them, rounded up,
+ *                      are written).
+ *   soup_probe_atomic: n_ops float atomic adds of 1 into slots [n_slots],
+ *                      op k to slot (k * 2654435761) mod n_slots (scattered).
+ *   soup_probe_fma:    n_threads (a multiple of 256) threads each run eight
+ *                      independent chains of iters float32 FMAs (2^20 at most):
+ *                      16 iters n_threads FLOP; out [n_threads] = 8 iters + 28.
+ *   soup_probe_mfma:   n_threads / 64 waves each run four independent chains
+ *                      of iters v_mfma_f32_16x16x4f32 (2^18 at most): 8192
+ *                      iters n_threads / 64 FLOP; out [n_threads] = 64 iters.
+ */
+soup_status soup_probe_copy(soup_ctx* ctx, const void* src, void* dst, int64_t bytes, void* stream);
+soup_status soup_probe_read(soup_ctx* ctx, const void* src, int64_t bytes, float* partial, int64_t n_partial,
+                            void* stream);
+soup_status soup_probe_atomic(soup_ctx* ctx, float* slots, int64_t n_slots, int64_t n_ops, void* stream);
+soup_status soup_probe_fma(soup_ctx* ctx, float* out, int64_t n_threads, int32_t iters, void* stream);
+soup_status soup_probe_mfma(soup_ctx* ctx, float* out, int64_t n_threads, int32_t iters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,7 +57,8 @@ EXPORTS = ["soup_ctx_create", "soup_ctx_destroy", "soup_last_error", "soup_ctx_s
            "soup_ctx_check", "soup_coverage_count", "soup_edge_lengths", "soup_adaptive_plan",
            "soup_adaptive_apply", "soup_loss_l1_ssim", "soup_adam_step", "soup_loss_l1_ssim_noalloc",
            "soup_pforward", "soup_pbackward", "soup_pbackward_levels", "soup_mc_assemble",
-           "soup_mc_assemble_bwd", "soup_ctx_workspace_bytes"]
+           "soup_mc_assemble_bwd", "soup_ctx_workspace_bytes", "soup_probe_copy", "soup_probe_read",
+           "soup_probe_atomic", "soup_probe_fma", "soup_probe_mfma"]
 TIMING_KINDS = ["setup", "scan", "scatter", "sort", "raster_fwd", "decode_bwd", "edge", "vertex_chain",
                 "mlp_reduce", "logp", "loss", "fill", "replay", "grad_reduce", "coverage", "edge_lengths",
                 "adaptive_apply", "train_loss", "adam", "shade", "assemble", "assemble_bwd"]
@@ -117,8 +118,14 @@ def lib() -> C.CDLL:
     L.soup_mc_assemble.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
     L.soup_mc_assemble_bwd.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_int32, P]
     L.soup_ctx_workspace_bytes.argtypes = [P, C.POINTER(C.c_int64)]
+    L.soup_probe_copy.argtypes = [P, P, P, C.c_int64, P]
+    L.soup_probe_read.argtypes = [P, P, C.c_int64, P, C.c_int64, P]
+    L.soup_probe_atomic.argtypes = [P, P, C.c_int64, C.c_int64, P]
+    L.soup_probe_fma.argtypes = [P, P, C.c_int64, C.c_int32, P]
+    L.soup_probe_mfma.argtypes = [P, P, C.c_int64, C.c_int32, P]
     for name in ["soup_pforward", "soup_pbackward", "soup_pbackward_levels", "soup_mc_assemble",
-                 "soup_mc_assemble_bwd", "soup_ctx_workspace_bytes"]:
+                 "soup_mc_assemble_bwd", "soup_ctx_workspace_bytes", "soup_probe_copy", "soup_probe_read",
+                 "soup_probe_atomic", "soup_probe_fma", "soup_probe_mfma"]:
         getattr(L, name).restype = C.c_int
     for name in ["soup_ctx_create", "soup_ctx_set_tile", "soup_ctx_set_counting", "soup_last_stats",
                  "soup_rasterize_fwd", "soup_rasterize_bwd", "soup_render", "soup_loss_l2",
@@ -410,3 +417,26 @@ def soup_mc_assemble_bwd(ctx: Ctx, tex, grad_tex, Rmin: int, Rmax: int, grad_raw
     Rtop = Rmin + len(grad_raw) - 1
     ctx.check(lib().soup_mc_assemble_bwd(ctx.p, int(tex.shape[0]), int(Rmin), Rtop, int(Rmax), _ptr(tex),
                                          _ptr(grad_tex), ptrs, int(accumulate), _stream(stream)))
+
+
+# measured ceilings (kernels of known work; the caller times them on `stream`)
+def soup_probe_copy(ctx: Ctx, src, dst, stream=None):
+    ctx.check(lib().soup_probe_copy(ctx.p, _ptr(src), _ptr(dst), int(src.numel() * src.element_size()),
+                                    _stream(stream)))
+
+
+def soup_probe_read(ctx: Ctx, src, partial, stream=None):
+    ctx.check(lib().soup_probe_read(ctx.p, _ptr(src), int(src.numel() * src.element_size()), _ptr(partial),
+                                    int(partial.numel()), _stream(stream)))
+
+
+def soup_probe_atomic(ctx: Ctx, slots, n_ops: int, stream=None):
+    ctx.check(lib().soup_probe_atomic(ctx.p, _ptr(slots), int(slots.numel()), int(n_ops), _stream(stream)))
+
+
+def soup_probe_fma(ctx: Ctx, out, iters: int, stream=None):
+    ctx.check(lib().soup_probe_fma(ctx.p, _ptr(out), int(out.numel()), int(iters), _stream(stream)))
+
+
+def soup_probe_mfma(ctx: Ctx, out, iters: int, stream=None):
+    ctx.check(lib().soup_probe_mfma(ctx.p, _ptr(out), int(out.numel()), int(iters), _stream(stream)))

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libdiffsoup.so")
-SOURCES = ['fwd_k8_16_1_t8.hip', 'fwd_k8_16_1_t16.hip', 'fwd_k8_16_1_t32.hip', 'fwd_k16_32_2_t8.hip', 'fwd_k16_32_2_t16.hip', 'fwd_k16_32_2_t32.hip', 'fwd_k32_64_2_t8.hip', 'fwd_k32_64_2_t16.hip', 'fwd_k32_64_2_t32.hip', 'dbwd_k8_16_1.hip', 'dbwd_k16_32_2.hip', 'dbwd_k32_64_2.hip', 'fwd_paper_t8.hip', 'fwd_paper_t16.hip', 'fwd_paper_t32.hip'] + ["api.hip", "pform.hip", "bin.hip", "replay.hip", "raster_fwd.hip", "raster_bwd.hip", "adaptive.hip", "train.hip"]
+SOURCES = ['fwd_k8_16_1_t8.hip', 'fwd_k8_16_1_t16.hip', 'fwd_k8_16_1_t32.hip', 'fwd_k16_32_2_t8.hip', 'fwd_k16_32_2_t16.hip', 'fwd_k16_32_2_t32.hip', 'fwd_k32_64_2_t8.hip', 'fwd_k32_64_2_t16.hip', 'fwd_k32_64_2_t32.hip', 'dbwd_k8_16_1.hip', 'dbwd_k16_32_2.hip', 'dbwd_k32_64_2.hip', 'fwd_paper_t8.hip', 'fwd_paper_t16.hip', 'fwd_paper_t32.hip'] + ["api.hip", "pform.hip", "bin.hip", "replay.hip", "raster_fwd.hip", "raster_bwd.hip", "adaptive.hip", "train.hip", "probe.hip"]
 ARCH = os.environ.get("SOUP_OFFLOAD_ARCH", "gfx950")
 
 

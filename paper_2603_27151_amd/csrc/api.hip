@@ -1688,3 +1688,69 @@ soup_status soup_selftest_uniform(soup_ctx* c, uint64_t seed, const uint32_t* pi
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// measured ceilings
+// ---------------------------------------------------------------------------
+
+soup_status soup_probe_copy(soup_ctx* c, const void* src, void* dst, int64_t bytes, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (bytes < 0 || bytes % 16 != 0 || (bytes > 0 && (!src || !dst)) ||
+        ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) != 0)
+        return fail(c, SOUP_ERR_INVALID, "probe_copy: need 16-byte aligned buffers and a multiple of 16 bytes");
+    HIP_TRY(c, hipSetDevice(c->device));
+    soup::launch_probe_copy(static_cast<const float4*>(src), static_cast<float4*>(dst), bytes / 16, c->num_cus,
+                            static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_probe_read(soup_ctx* c, const void* src, int64_t bytes, float* partial, int64_t n_partial,
+                            void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (bytes < 0 || bytes % 16 != 0 || (bytes > 0 && (!src || !partial)) || n_partial < 1 ||
+        (reinterpret_cast<uintptr_t>(src) & 15) != 0)
+        return fail(c, SOUP_ERR_INVALID, "probe_read: need a 16-byte aligned buffer, a multiple of 16 bytes and "
+                    "n_partial >= 1");
+    HIP_TRY(c, hipSetDevice(c->device));
+    soup::launch_probe_read(static_cast<const float4*>(src), bytes / 16, partial, n_partial,
+                            static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_probe_atomic(soup_ctx* c, float* slots, int64_t n_slots, int64_t n_ops, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (n_slots < 1 || n_ops < 0 || !slots) return fail(c, SOUP_ERR_INVALID, "probe_atomic: bad arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    soup::launch_probe_atomic(slots, n_slots, n_ops, c->num_cus, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_probe_fma(soup_ctx* c, float* out, int64_t n_threads, int32_t iters, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (!out || n_threads < 256 || n_threads % 256 != 0 || n_threads / 256 > INT32_MAX || iters < 0 ||
+        iters > (1 << 20))
+        return fail(c, SOUP_ERR_INVALID, "probe_fma: n_threads a positive multiple of 256, 0 <= iters <= 2^20");
+    HIP_TRY(c, hipSetDevice(c->device));
+    soup::launch_probe_fma(out, n_threads, iters, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}
+
+soup_status soup_probe_mfma(soup_ctx* c, float* out, int64_t n_threads, int32_t iters, void* stream) {
+    if (!c) return SOUP_ERR_INVALID;
+    c->err.clear();
+    if (!out || n_threads < 256 || n_threads % 256 != 0 || n_threads / 256 > INT32_MAX || iters < 0 ||
+        iters > (1 << 18))
+        return fail(c, SOUP_ERR_INVALID, "probe_mfma: n_threads a positive multiple of 256, 0 <= iters <= 2^18");
+    HIP_TRY(c, hipSetDevice(c->device));
+    soup::launch_probe_mfma(out, n_threads, iters, static_cast<hipStream_t>(stream));
+    HIP_TRY(c, hipGetLastError());
+    return SOUP_OK;
+}

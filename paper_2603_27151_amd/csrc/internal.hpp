@@ -307,6 +307,13 @@ struct PTriArgs {
 };
 size_t ptri_bwd_lds(int R);
 bool ptri_levels_fit(int R);   // level R - 1 fits the kernel's stage buffer
+
+// measured ceilings (probe.hip)
+void launch_probe_copy(const float4* src, float4* dst, int64_t n, int num_cus, hipStream_t s);
+void launch_probe_read(const float4* src, int64_t n, float* partial, int64_t n_partial, hipStream_t s);
+void launch_probe_atomic(float* slots, int64_t n_slots, int64_t n_ops, int num_cus, hipStream_t s);
+void launch_probe_fma(float* out, int64_t n_threads, int iters, hipStream_t s);
+void launch_probe_mfma(float* out, int64_t n_threads, int iters, hipStream_t s);
 int ptri_blocks(int num_cus, int R);
 void launch_ptri_bwd(const PTriArgs& a, hipStream_t s);
 int pwinner_blocks(int num_cus);

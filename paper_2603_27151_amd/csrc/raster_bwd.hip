@@ -165,23 +165,56 @@ void launch_mlp_reduce(const float* partial, int n_rows, int n_params, double* m
 // L2 loss and contract self-tests
 // ---------------------------------------------------------------------------
 
+// Per pixel: d = colour - target, g_C = 2 d / (3P), g_L = |d|^2 / (3P) (its
+// share of the mean), loss += g_L. Four pixels (48 bytes of each input) per
+// thread and step with 16-byte loads and stores when every array is 16-byte
+// aligned; the pixels past the last group of four (and unaligned arrays) one
+// at a time.
 __global__ __launch_bounds__(256) void loss_l2_kernel(const float* __restrict__ color, const float* __restrict__ target,
                                                       int64_t P, float* __restrict__ gc, float* __restrict__ gl,
-                                                      float* __restrict__ loss) {
+                                                      float* __restrict__ loss, int vec4) {
     __shared__ float red[4];
     const float inv = 1.0f / (3.0f * static_cast<float>(P));
     float part = 0.0f;
-    for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < P;
-         p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        float s = 0.0f;
+    const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    const int64_t P4 = vec4 ? P / 4 : 0;
+    for (int64_t q = tid; q < P4; q += stride) {
+        const float4* c4 = reinterpret_cast<const float4*>(color) + 3 * q;
+        const float4* t4 = reinterpret_cast<const float4*>(target) + 3 * q;
+        const float4 a0 = c4[0], a1 = c4[1], a2 = c4[2];
+        const float4 b0 = t4[0], b1 = t4[1], b2 = t4[2];
+        const float cv[12] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w};
+        const float tv[12] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w, b2.x, b2.y, b2.z, b2.w};
+        float g[12], l[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float sq = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float d = cv[3 * k + c] - tv[3 * k + c];
+                g[3 * k + c] = 2.0f * d * inv;
+                sq = __builtin_fmaf(d, d, sq);
+            }
+            l[k] = sq * inv;
+            part += sq * inv;
+        }
+        float4* g4 = reinterpret_cast<float4*>(gc) + 3 * q;
+        g4[0] = make_float4(g[0], g[1], g[2], g[3]);
+        g4[1] = make_float4(g[4], g[5], g[6], g[7]);
+        g4[2] = make_float4(g[8], g[9], g[10], g[11]);
+        reinterpret_cast<float4*>(gl)[q] = make_float4(l[0], l[1], l[2], l[3]);
+    }
+    for (int64_t p = 4 * P4 + tid; p < P; p += stride) {
+        float sq = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float d = color[3 * p + c] - target[3 * p + c];
             gc[3 * p + c] = 2.0f * d * inv;
-            s = __builtin_fmaf(d, d, s);
+            sq = __builtin_fmaf(d, d, sq);
         }
-        gl[p] = s * inv;
-        part += s * inv;
+        gl[p] = sq * inv;
+        part += sq * inv;
     }
     if (loss) {
 #pragma unroll
@@ -196,9 +229,13 @@ void launch_loss_l2(const float* color, const float* target, int64_t P, float* g
                     hipStream_t s) {
     if (P <= 0) return;
     if (loss) launch_fill_f32(loss, 1, 0.0f, s);
-    int64_t g = (P + 255) / 256;
+    const uintptr_t al = reinterpret_cast<uintptr_t>(color) | reinterpret_cast<uintptr_t>(target) |
+                         reinterpret_cast<uintptr_t>(gc) | reinterpret_cast<uintptr_t>(gl);
+    const int vec4 = (al & 15) == 0 ? 1 : 0;
+    int64_t g = ((vec4 ? (P + 3) / 4 : P) + 255) / 256;
     if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(loss_l2_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, color, target, P, gc, gl, loss);
+    hipLaunchKernelGGL(loss_l2_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, color, target, P, gc, gl, loss,
+                       vec4);
 }
 
 __global__ void selftest_sigmoid_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n) {
