@@ -152,11 +152,65 @@ struct LayerAcc {
     }
 };
 
+// The output layer's weight gradient dW[4][DIN] += sum_f d_f a_f^T on
+// v_mfma_f32_4x4x1f32: block b (lanes 4b .. 4b + 3) accumulates the 4 x 4
+// tile of units 4 (b % 8) .. + 3 over the fragments of half b / 8 of the 16
+// staged rows, one fragment per product (A = the fragment's four output
+// deltas, B = its four units); the two halves are added at the end. The
+// bias gradient as in LayerAcc (output grp in element 0 of lane group grp).
+template <int DIN>
+struct OutAcc {
+    static_assert(DIN == 32, "the tiles cover 32 input units");
+    f4v w;
+    f4v bs[1];
+    __device__ __forceinline__ void zero() {
+        w = f4v{0.f, 0.f, 0.f, 0.f};
+        bs[0] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    __device__ __forceinline__ void add_bias(const f4v (&d)[1]) { bs[0][0] += d[0][0]; }
+    __device__ __forceinline__ void accumulate(const float* __restrict__ in, const float* __restrict__ d, int lane) {
+        const int x = lane & 3, t = (lane >> 2) & 7, half = lane >> 5;
+        float av[8], bv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int f = 8 * half + k;
+            av[k] = d[f * (4 + kRowPad) + x];
+            bv[k] = in[f * (DIN + kRowPad) + 4 * t + x];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w = mfma4x4(av[k], bv[k], w);
+    }
+    __device__ __forceinline__ void store(float* __restrict__ row, int w_off, int b_off, int lane) const {
+        // lanes 0..31 (the first half) add the second half's tiles
+        f4v s;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = pair32f(w[i], w[i]);
+        if (lane < 32) {
+            const int t = lane >> 2, j = lane & 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) row[w_off + i * DIN + 4 * t + j] = s[i];
+        }
+        f4v v = bs[0];
+#pragma unroll
+        for (int sh = 1; sh < 16; sh <<= 1) v[0] += __shfl_xor(v[0], sh, 64);
+        if ((lane & 15) == 0) row[b_off + (lane >> 4)] = v[0];
+    }
+};
+
+template <class S, bool OUT4 = (S::H == 32)>
+struct OutAccOf {
+    using type = LayerAcc<S::H, 4, true>;
+};
+template <class S>
+struct OutAccOf<S, true> {
+    using type = OutAcc<S::H>;
+};
+
 template <class S>
 struct MlpGrad {
     LayerAcc<S::C, S::H> l0;
     LayerAcc<S::H, S::H> mid[S::NH > 1 ? S::NH - 1 : 1];
-    LayerAcc<S::H, 4, true> out;
+    typename OutAccOf<S>::type out;
 };
 
 template <class S, bool LOGP>
