@@ -12,7 +12,9 @@
 //  * ssim_grad_kernel: dL/dC = lambda sign(C - T) / (3P) minus
 //    (1 - lambda) / (3P) times the window sums of G1, G2, G3 around p.
 //    One thread per pixel of a 32 x 8 tile; the window is applied as two
-//    11-tap passes over an LDS copy of the tile and its halo.
+//    11-tap passes over an LDS copy of the tile and its halo, columns first
+//    (the halo's 42 columns for the tile's 8 rows, two rows per thread from
+//    their 12 shared input rows), then rows (the tile's 32 columns).
 //  * adam_kernel: Adam (vec = 1) or VectorAdam (vec = 3: one second moment
 //    per 3-vector from its squared norm), one thread per vector.
 #include <hip/hip_runtime.h>
@@ -34,17 +36,21 @@ constexpr float kShift = 0.5f;
 
 // Both SSIM passes work on 32 x 8 pixel tiles, one thread per pixel. The
 // tile plus its 5-pixel halo is staged in LDS (zeros outside the image: the
-// zero padding of the definition), filtered along rows for the tile's
-// columns, then along columns: 22 taps per map instead of 121.
+// zero padding of the definition) and filtered along columns for the tile's
+// rows over the halo's columns (a thread takes two output rows of one
+// column, whose windows share 10 of their 12 input rows), then along rows:
+// 22 taps per map instead of 121. Columns first: for a tile wider than
+// tall the first pass covers 42 x 8 positions instead of 18 x 32.
 constexpr int kTW = 32, kTH = 8;
 constexpr int kHW = kTW + 2 * kSsimR, kHH = kTH + 2 * kSsimR;
+static_assert(kTH % 2 == 0, "the column pass takes output rows in pairs");
 
 __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict__ color,
                                                          const float* __restrict__ target, int W, int H, float lam,
                                                          float inv_n, SsimWindow win, float* __restrict__ stats,
                                                          float* __restrict__ grad_logp, float* __restrict__ loss) {
     __shared__ float in[kHH][kHW][6];   // colour rgb, target rgb
-    __shared__ float hs[kHH][kTW][15];  // row sums: x, y, x^2, y^2, xy per channel
+    __shared__ float vs[kTH][15][kHW];  // column sums: x, y, x^2, y^2, xy per channel
     __shared__ float part[4];
     const int tx0 = blockIdx.x * kTW, ty0 = blockIdx.y * kTH;
     for (int i = threadIdx.x; i < kHH * kHW; i += blockDim.x) {
@@ -58,22 +64,39 @@ __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kHH * kTW; i += blockDim.x) {
-        const int r = i / kTW, col = i % kTW;
-        float acc[15];
-        for (int j = 0; j < 15; ++j) acc[j] = 0.0f;
-        for (int k = 0; k <= 2 * kSsimR; ++k) {
-            const float w = win.g[k];
+    // columns: output rows 2 pr and 2 pr + 1 of halo column cc, from input
+    // rows 2 pr .. 2 pr + 11 (row 2 pr + k is tap k of the first, k - 1 of the second)
+    for (int i = threadIdx.x; i < kHW * (kTH / 2); i += blockDim.x) {
+        const int cc = i % kHW, pr = i / kHW;
+        float a0[15], a1[15];
+        for (int j = 0; j < 15; ++j) {
+            a0[j] = 0.0f;
+            a1[j] = 0.0f;
+        }
+        for (int k = 0; k <= 2 * kSsimR + 1; ++k) {
+            const float* px = in[2 * pr + k][cc];
+            float v[15];
             for (int c = 0; c < 3; ++c) {
-                const float a = in[r][col + k][c], b = in[r][col + k][3 + c];
-                acc[c] += w * a;
-                acc[3 + c] += w * b;
-                acc[6 + c] += w * (a * a);
-                acc[9 + c] += w * (b * b);
-                acc[12 + c] += w * (a * b);
+                const float a = px[c], b = px[3 + c];
+                v[c] = a;
+                v[3 + c] = b;
+                v[6 + c] = a * a;
+                v[9 + c] = b * b;
+                v[12 + c] = a * b;
+            }
+            if (k <= 2 * kSsimR) {
+                const float w = win.g[k];
+                for (int j = 0; j < 15; ++j) a0[j] += w * v[j];
+            }
+            if (k >= 1) {
+                const float w = win.g[k - 1];
+                for (int j = 0; j < 15; ++j) a1[j] += w * v[j];
             }
         }
-        for (int j = 0; j < 15; ++j) hs[r][col][j] = acc[j];
+        for (int j = 0; j < 15; ++j) {
+            vs[2 * pr][j][cc] = a0[j];
+            vs[2 * pr + 1][j][cc] = a1[j];
+        }
     }
     __syncthreads();
     const int lx = threadIdx.x % kTW, ly = threadIdx.x / kTW;
@@ -84,7 +107,7 @@ __global__ void __launch_bounds__(256) ssim_stats_kernel(const float* __restrict
         for (int j = 0; j < 15; ++j) sm[j] = 0.0f;
         for (int k = 0; k <= 2 * kSsimR; ++k) {
             const float w = win.g[k];
-            for (int j = 0; j < 15; ++j) sm[j] += w * hs[ly + k][lx][j];
+            for (int j = 0; j < 15; ++j) sm[j] += w * vs[ly][j][lx + k];
         }
         const int64_t p = static_cast<int64_t>(y) * W + x;
         float* st = stats + p * 12;
@@ -120,7 +143,7 @@ __global__ void __launch_bounds__(256) ssim_grad_kernel(const float* __restrict_
                                                         float inv_n, SsimWindow win, const float* __restrict__ stats,
                                                         float* __restrict__ grad_color) {
     __shared__ float in[kHH][kHW][9];   // G1, G2, G3 per channel (zero outside the image)
-    __shared__ float hs[kHH][kTW][9];
+    __shared__ float vs[kTH][9][kHW];   // their column sums
     const int tx0 = blockIdx.x * kTW, ty0 = blockIdx.y * kTH;
     for (int i = threadIdx.x; i < kHH * kHW; i += blockDim.x) {
         const int r = i / kHW, cc = i % kHW;
@@ -143,15 +166,28 @@ __global__ void __launch_bounds__(256) ssim_grad_kernel(const float* __restrict_
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kHH * kTW; i += blockDim.x) {
-        const int r = i / kTW, col = i % kTW;
-        float acc[9];
-        for (int j = 0; j < 9; ++j) acc[j] = 0.0f;
-        for (int k = 0; k <= 2 * kSsimR; ++k) {
-            const float w = win.g[k];
-            for (int j = 0; j < 9; ++j) acc[j] += w * in[r][col + k][j];
+    for (int i = threadIdx.x; i < kHW * (kTH / 2); i += blockDim.x) {   // columns, two output rows each
+        const int cc = i % kHW, pr = i / kHW;
+        float a0[9], a1[9];
+        for (int j = 0; j < 9; ++j) {
+            a0[j] = 0.0f;
+            a1[j] = 0.0f;
         }
-        for (int j = 0; j < 9; ++j) hs[r][col][j] = acc[j];
+        for (int k = 0; k <= 2 * kSsimR + 1; ++k) {
+            const float* px = in[2 * pr + k][cc];
+            if (k <= 2 * kSsimR) {
+                const float w = win.g[k];
+                for (int j = 0; j < 9; ++j) a0[j] += w * px[j];
+            }
+            if (k >= 1) {
+                const float w = win.g[k - 1];
+                for (int j = 0; j < 9; ++j) a1[j] += w * px[j];
+            }
+        }
+        for (int j = 0; j < 9; ++j) {
+            vs[2 * pr][j][cc] = a0[j];
+            vs[2 * pr + 1][j][cc] = a1[j];
+        }
     }
     __syncthreads();
     const int lx = threadIdx.x % kTW, ly = threadIdx.x / kTW;
@@ -161,7 +197,7 @@ __global__ void __launch_bounds__(256) ssim_grad_kernel(const float* __restrict_
     for (int j = 0; j < 9; ++j) sm[j] = 0.0f;
     for (int k = 0; k <= 2 * kSsimR; ++k) {
         const float w = win.g[k];
-        for (int j = 0; j < 9; ++j) sm[j] += w * hs[ly + k][lx][j];
+        for (int j = 0; j < 9; ++j) sm[j] += w * vs[ly][j][lx + k];
     }
     const int64_t p = static_cast<int64_t>(y) * W + x;
     for (int c = 0; c < 3; ++c) {
