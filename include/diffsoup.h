@@ -363,6 +363,7 @@ soup_status soup_pforward(soup_ctx* ctx, const soup_pscene* scene, const soup_vi
  *   f in front:  score -g_L / (1 - alpha_f) on its opacity channel;
  *   the score term moves no vertex; the edge term as in soup_rasterize_bwd.
  * Floating-point sums use atomics (order-dependent, about 1e-6 relative).
+ * For an empty soup (T = 0) grad_verts and grad_tex may be NULL.
  */
 soup_status soup_pbackward(soup_ctx* ctx, const soup_pscene* scene, const soup_views* views,
                            const float* inv_view_proj, const soup_opts* opts, const uint64_t* vis,

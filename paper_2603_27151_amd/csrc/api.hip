@@ -1196,7 +1196,9 @@ static soup_status pbackward_impl(soup_ctx* c, const soup_pscene* scene, const s
     if ((st = plan_paper(c, p, scene, views, inv_view_proj))) return st;
     if ((st = check_opts(c, opts))) return st;
     if (!vis || !color || !grad_color) return fail(c, SOUP_ERR_INVALID, "vis, color and grad_color are required");
-    if (!grad_verts || !grad_mlp || (!lv && !grad_tex)) return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
+    // an empty soup has empty vertex and texture gradients (their pointers may be NULL)
+    if (!grad_mlp || (scene->T > 0 && (!grad_verts || (!lv && !grad_tex))))
+        return fail(c, SOUP_ERR_INVALID, "gradient outputs are required");
     if (lv) {
         if ((st = check_levels(c, scene->T, lv->Rmin, lv->Rtop, scene->R))) return st;
         if (scene->T > 0) {

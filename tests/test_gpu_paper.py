@@ -108,7 +108,7 @@ def test_paper_forward_matches_oracle(case):
 
 # R = 6: a texture row (2,145 vertices x 8 channels) too large for the sorted path's
 # LDS row, so the backward takes the per-pixel path with global atomics
-BWD_CASES = CASES[:3] + [dict(seed=6, T=80, R=6, sizes=[(56, 40)], mode=0)]
+BWD_CASES = CASES + [dict(seed=6, T=80, R=6, sizes=[(56, 40)], mode=0)]   # CASES[3]: an empty soup
 
 
 @pytest.mark.parametrize("case", BWD_CASES, ids=lambda c: f"T{c['T']}R{c['R']}m{c['mode']}v{len(c['sizes'])}")
@@ -157,6 +157,8 @@ LEVEL_CASES = [
     dict(seed=22, T=400, R=3, Rmin=0, Rtop=3, sizes=[(97, 61)], from_log=True),
     dict(seed=23, T=200, R=2, Rmin=1, Rtop=1, sizes=[(48, 40)], from_log=False),
     dict(seed=24, T=80, R=6, Rmin=3, Rtop=5, sizes=[(56, 40)], from_log=False),
+    dict(seed=25, T=150, R=3, Rmin=3, Rtop=3, sizes=[(40, 30)], from_log=False),   # the finest level alone
+    dict(seed=26, T=0, R=5, Rmin=2, Rtop=4, sizes=[(16, 9)], from_log=False),      # an empty soup
 ]
 
 
