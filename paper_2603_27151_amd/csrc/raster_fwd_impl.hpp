@@ -37,25 +37,40 @@
 
 namespace soup {
 
+// A slice pair's geometry, one 16-byte aligned record (five 16-byte reads).
+struct alignas(16) PairGeo {
+    double e0[3];        // orientation-normalised edge functions at the block's first pixel centre
+    int32_t ndx[3];      // ... whose steps per pixel are -256 ndy in x and 256 ndx in y
+    int32_t ndy[3];
+    float z[3];          // vertex depths
+    float iw[3];         // 1 / w at the vertices
+    float ra;            // 1 / |2 x area|
+    float pad;
+};
+// A slice pair's run of combinations: coverage mask, list entry, first combination, block.
+struct alignas(8) PairMeta {
+    uint32_t mlo, mhi;
+    uint32_t ent_lo, ent_hi;
+    int32_t off, blk;
+};
+
 // LDS of one wave owning NB 8x8 blocks.
 template <int NB>
 struct FwdWaveLds {
     // the current slice: (triangle, block) pairs that cover a pixel of their block
-    double e0[3][64];    // orientation-normalised edge functions at the block's first pixel centre
-    int32_t ndx[3][64];  // ... whose steps per pixel are -256 ndy in x and 256 ndx in y
-    int32_t ndy[3][64];
-    float z[3][64];      // vertex depths
-    float iw[3][64];     // 1 / w at the vertices
-    float ra[64];        // 1 / |2 x area|
+    PairGeo geo[64];
+    PairMeta meta[64];
     // (triangle, block) pairs waiting for the coverage step, in list order: a ring of
     // kRing slots (at most 63 wait when a scan of 64 entries appends up to 64 NB more)
     static constexpr int kRing = 64 * (NB + 1);
     uint32_t ptri[kRing];
     uint8_t pblk[kRing];
-    // candidate queue (below 64 waiting, plus up to 64 from each of two pairs)
-    uint64_t qkey[192];
-    float qt[3][192];    // beta_i / w_i (the decode forms the perspective-correct barycentrics)
-    uint16_t qpl[192];   // pixel of the region: block * 64 + pixel of the block
+    // candidate queue: a fragment round starts with fewer than 64 waiting (64
+    // are decoded first) and adds at most 64, one per lane
+    static constexpr int kQueue = 128;
+    uint64_t qkey[kQueue];
+    float qt[3][kQueue];    // beta_i / w_i (the decode forms the perspective-correct barycentrics)
+    uint16_t qpl[kQueue];   // pixel of the region: block * 64 + pixel of the block
     // the region's pixels: current best key (their colours go straight to the output)
     uint64_t key[64 * NB];
     // per round of the fragment step: the slice pair whose run of combinations starts here
@@ -320,29 +335,25 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             const int c = base + lane;
             const bool valid = c < n_comb;
             const int j = valid ? (h > carry ? h : carry) : 0;
-            // its pixel: the k-th covered pixel of the pair, k its rank in the pair's run (every
-            // lane takes part in the shuffles: a lane reading an inactive lane gets no value)
-            const int offj = __shfl(off, j, 64);
-            const uint32_t mjl = static_cast<uint32_t>(__shfl(static_cast<int>(mlo), j, 64));
-            const uint32_t mjh = static_cast<uint32_t>(__shfl(static_cast<int>(mhi), j, 64));
-            const int p = select_bit(mjl, mjh, valid ? c - offj : 0);
-            const int bj = __shfl(cblk, j, 64);
-            const uint64_t zk =
-                (static_cast<uint64_t>(static_cast<uint32_t>(__shfl(static_cast<int>(cent >> 32), j, 64))) << 32) |
-                static_cast<uint32_t>(__shfl(static_cast<int>(cent), j, 64));
+            // its pixel: the k-th covered pixel of the pair, k its rank in the pair's run
+            const PairMeta mj = L.meta[j];
+            const PairGeo gj = L.geo[j];
+            const int p = select_bit(mj.mlo, mj.mhi, valid ? c - mj.off : 0);
+            const int bj = mj.blk;
+            const uint64_t zk = (static_cast<uint64_t>(mj.ent_hi) << 32) | mj.ent_lo;
             const uint64_t kp = L.key[bj * 64 + p];   // the pixel's best key as of the last decode batch
             const double px = static_cast<double>(p & 7), py = static_cast<double>(p >> 3);
             Frag f;
             double e[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {   // exact: every term is an integer below 2^51
-                const double t = __builtin_fma(py, static_cast<double>(L.ndx[i][j]), -(px * static_cast<double>(L.ndy[i][j])));
-                e[i] = __builtin_fma(static_cast<double>(kSnap), t, L.e0[i][j]);
+                const double t = __builtin_fma(py, static_cast<double>(gj.ndx[i]), -(px * static_cast<double>(gj.ndy[i])));
+                e[i] = __builtin_fma(static_cast<double>(kSnap), t, gj.e0[i]);
             }
-            const float ra = L.ra[j];
+            const float ra = gj.ra;
 #pragma unroll
             for (int i = 0; i < 3; ++i) f.beta[i] = static_cast<float>(e[i]) * ra;
-            float z = __builtin_fmaf(f.beta[2], L.z[2][j], __builtin_fmaf(f.beta[1], L.z[1][j], f.beta[0] * L.z[0][j]));
+            float z = __builtin_fmaf(f.beta[2], gj.z[2], __builtin_fmaf(f.beta[1], gj.z[1], f.beta[0] * gj.z[0]));
             if (!(z > 0.0f)) z = 0.0f;
             if (z > 1.0f) z = 1.0f;
             f.key = (static_cast<uint64_t>(__float_as_uint(z)) << 32) | static_cast<uint32_t>(zk);
@@ -352,7 +363,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                 const int pos = qn + __popcll(m & lanemask_lt());
                 L.qkey[pos] = f.key;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) L.qt[i][pos] = f.beta[i] * L.iw[i][j];
+                for (int i = 0; i < 3; ++i) L.qt[i][pos] = f.beta[i] * gj.iw[i];
                 L.qpl[pos] = static_cast<uint16_t>(bj * 64 + p);
             }
             qn += __popcll(m);
@@ -433,24 +444,28 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                     atomicOr(&L.cov[2 * cblk + 1], mhi);
                 }
                 if ((mlo | mhi) != 0) {
+                    PairGeo g;
 #pragma unroll
                     for (int e = 0; e < 3; ++e) {
-                        L.e0[e][lane] = e0[e];
-                        L.ndx[e][lane] = nx[e];
-                        L.ndy[e][lane] = ny[e];
+                        g.e0[e] = e0[e];
+                        g.ndx[e] = nx[e];
+                        g.ndy[e] = ny[e];
                     }
-                    L.z[0][lane] = __uint_as_float(q1.z);
-                    L.z[1][lane] = __uint_as_float(q1.w);
-                    L.z[2][lane] = __uint_as_float(q2.x);
-                    L.iw[0][lane] = __uint_as_float(q2.y);
-                    L.iw[1][lane] = __uint_as_float(q2.z);
-                    L.iw[2][lane] = __uint_as_float(q2.w);
-                    L.ra[lane] = __builtin_fabsf(rA);
+                    g.z[0] = __uint_as_float(q1.z);
+                    g.z[1] = __uint_as_float(q1.w);
+                    g.z[2] = __uint_as_float(q2.x);
+                    g.iw[0] = __uint_as_float(q2.y);
+                    g.iw[1] = __uint_as_float(q2.z);
+                    g.iw[2] = __uint_as_float(q2.w);
+                    g.ra = __builtin_fabsf(rA);
+                    g.pad = 0.0f;
+                    L.geo[lane] = g;
                 }
             }
             cnt = __popc(mlo) + __popc(mhi);
             const int incl = wave_incl_scan_i32(cnt);
             off = incl - cnt;
+            L.meta[lane] = PairMeta{mlo, mhi, static_cast<uint32_t>(cent), static_cast<uint32_t>(cent >> 32), off, cblk};
             n_comb = __builtin_amdgcn_readlane(incl, 63);
             rnd = 0;
             n_rnd = (n_comb + 63) >> 6;
