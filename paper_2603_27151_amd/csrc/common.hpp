@@ -189,12 +189,13 @@ struct MlpShape {
     __host__ __device__ static constexpr int b_off(int l) { return w_off(l) + dout(l) * din(l); }
 };
 
-// Texture position of perspective-correct barycentrics (b1, b2) on a G x G
-// grid: vertex 0 -> (0,0), vertex 1 -> (G-1,0), vertex 2 -> (0,G-1).
 // Orders one wave's LDS accesses for the compiler only: a wave's LDS
 // operations execute in issue order, so a lane's read sees another lane's
 // earlier write of the same wave without a wait.
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Texture position of perspective-correct barycentrics (b1, b2) on a G x G
+// grid: vertex 0 -> (0,0), vertex 1 -> (G-1,0), vertex 2 -> (0,G-1).
 
 struct Cell {
     int ix, iy;

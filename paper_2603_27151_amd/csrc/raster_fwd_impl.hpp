@@ -6,7 +6,8 @@
 // (16x16 pixels, four 8x8 blocks, or a single 8x8 block when a call has too
 // few 16x16 regions to fill the GPU), taken from a counter (persistent, the
 // next region fetched while the current one runs),
-// so no barrier ever waits for another wave. It walks the tile's triangle
+// so no barrier ever waits for another wave (the wave's LDS accesses are
+// ordered by wavefront-scope fences, which wait on nothing). It walks the tile's triangle
 // list (sorted by a lower bound of their depth) in three steps, all in one
 // loop with uniform control flow:
 //  - scan, lanes over list entries: each entry whose bounding box touches a
@@ -182,7 +183,10 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
 
     // decode a batch of n queued candidates, one per lane
     auto run_batch = [&](int n) __attribute__((always_inline)) {
-        __syncthreads();
+        // the colour stores below may overwrite a pixel's colour from an earlier
+        // batch: those stores complete first (the only wait on global memory
+        // that the LDS ordering of this kernel needs)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         const bool act = lane < n;
         uint64_t key = 0;
         int pl = 0;
@@ -242,11 +246,11 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             }
         }
         if (a.log_frag) log_cursor += static_cast<uint32_t>(n);
-        __syncthreads();
+        wave_fence();
         if (!S::kPaper && pass && L.key[pl] == key) {
             // the pixel's new best: its colour goes to the output now (a later batch that lowers
-            // the key again writes after this one, behind the workgroup barriers between them;
-            // the paper form shades its winners afterwards)
+            // the key again writes after this one, behind the release fence that opens that
+            // batch; the paper form shades its winners afterwards)
             const int blk = pl >> 6, p = pl & 63;
             const int64_t off = static_cast<int64_t>(ry + (blk / BR) * 8 + (p >> 3)) * W + rx + (blk % BR) * 8 + (p & 7);
             gfloat_w* col = color_base + 3 * off;
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             col[2] = sigmoid_c(o[2]);
         }
         if (a.counter && lane == 0) atomicAdd(a.counter, static_cast<unsigned long long>(n));
-        __syncthreads();
+        wave_fence();
         wmax = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
                 kept += __popcll(m);
             }
             qn = kept;
-            __syncthreads();
+            wave_fence();
             continue;
         }
         if (rnd < n_rnd) {
@@ -326,9 +330,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             ++rnd;
             // the pair of a combination: the last pair whose run starts at or before it
             L.head[lane] = -1;
-            __syncthreads();
+            wave_fence();
             if (cnt > 0 && off >= base && off < base + 64) L.head[off - base] = lane;
-            __syncthreads();
+            wave_fence();
             const uint64_t before = __ballot(cnt > 0 && off < base);
             const int carry = before ? 63 - __builtin_clzll(before) : -1;
             const int h = wave_scan_dpp(L.head[lane], -1, [](int x, int y) { return x > y ? x : y; });
@@ -472,7 +476,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             ph += n;
             if (ph >= kRing) ph -= kRing;
             pn -= n;
-            __syncthreads();
+            wave_fence();
             continue;
         }
         // ---- scan the next 64 list entries: lane = entry ----
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
         }
         pn += __builtin_amdgcn_readlane(incl, 63);
         c0 += 64;
-        __syncthreads();
+        wave_fence();
     }
     // every read first, then the stores (a wait for a read issued between
     // stores would also wait for the stores)
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             col[2] = a.o.bg[2];
         }
     }
-    __syncthreads();
+    wave_fence();
     }   // regions
     if (a.log_counts && lane == 0) a.log_counts[blockIdx.x] = log_cursor;
 }
