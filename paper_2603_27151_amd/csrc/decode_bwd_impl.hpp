@@ -658,28 +658,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                                             -(static_cast<double>(Yv[1] - Yv[0]) * static_cast<double>(Xv[2] - Xv[0])));
             const double inv_area = 65536.0 * rcp64(Ai);   // 1 / (signed 2 x area in px^2)
             const double inv256 = 1.0 / 256.0;
-            double gsx[3] = {0., 0., 0.}, gsy[3] = {0., 0., 0.};
+            // beta_i = e_i / area, e_i = edge(v_p(i), v_q(i), pixel centre) with edge i
+            // joining vertices p(i) = i + 1 and q(i) = i + 2 (mod 3). Vertex jv moves
+            // e_i only for the two edges it belongs to (i = jv + 2 as p, i = jv + 1 as
+            // q), and the area as a whole; so d beta . dbeta / d(vertex jv) is
+            // (sum over those two edges of dbeta_i de_i - d area . sb) / area with
+            // sb = sum_i dbeta_i beta_i.
+            double sb = 0.0;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int p = i == 2 ? 0 : i + 1, qq = i == 0 ? 2 : (i == 1 ? 0 : 1);
-                // beta_i = e_i / area with e_i = edge(v_p, v_q, pixel centre)
-                const double bi = fb[i];
+            for (int i = 0; i < 3; ++i) sb = __builtin_fma(dbeta[i], fb[i], sb);
+            double gsx[3], gsy[3];
 #pragma unroll
-                for (int jv = 0; jv < 3; ++jv) {
-                    const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
-                    const double dax = static_cast<double>(Yv[jp] - Yv[jq]) * inv256;
-                    const double day = static_cast<double>(Xv[jq] - Xv[jp]) * inv256;
-                    double dex = 0., dey = 0.;
-                    if (jv == p) {
-                        dex = static_cast<double>(Yv[qq] - PY) * inv256;
-                        dey = static_cast<double>(PX - Xv[qq]) * inv256;
-                    } else if (jv == qq) {
-                        dex = static_cast<double>(PY - Yv[p]) * inv256;
-                        dey = static_cast<double>(Xv[p] - PX) * inv256;
-                    }
-                    gsx[jv] += dbeta[i] * (dex - bi * dax) * inv_area;
-                    gsy[jv] += dbeta[i] * (dey - bi * day) * inv_area;
-                }
+            for (int jv = 0; jv < 3; ++jv) {
+                const int jp = jv == 2 ? 0 : jv + 1, jq = jv == 0 ? 2 : (jv == 1 ? 0 : 1);
+                const double dax = static_cast<double>(Yv[jp] - Yv[jq]) * inv256;
+                const double day = static_cast<double>(Xv[jq] - Xv[jp]) * inv256;
+                // edge ip has jv as its first vertex (its other one is jp), edge iq as its second (other: jq)
+                const int ip = jv == 0 ? 2 : jv - 1, iq = jv == 2 ? 0 : jv + 1;
+                const double ex_p = static_cast<double>(Yv[jp] - PY) * inv256, ey_p = static_cast<double>(PX - Xv[jp]) * inv256;
+                const double ex_q = static_cast<double>(PY - Yv[jq]) * inv256, ey_q = static_cast<double>(Xv[jq] - PX) * inv256;
+                gsx[jv] = (__builtin_fma(dbeta[ip], ex_p, dbeta[iq] * ex_q) - dax * sb) * inv_area;
+                gsy[jv] = (__builtin_fma(dbeta[ip], ey_p, dbeta[iq] * ey_q) - day * sb) * inv_area;
             }
             // edge term (Section 3.2): the boundaries this pixel occludes move
             // with its surface point, w beta_i e on the screen position of vertex i
