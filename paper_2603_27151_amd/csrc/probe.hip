@@ -1,4 +1,4 @@
-// Measured ceilings of the machine, for the rooflines the kernels are judged
+// Measured ceilings of the machine, for the rooflines the kernels are measured
 // against: a streaming copy and a streaming read of HBM, float atomics to
 // scattered global addresses, the vector ALU's float32 FMA rate (non-packed,
 // as the library is built) and the matrix cores' float32 rate
