@@ -77,6 +77,33 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
+def test_bench_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    # roofline.traffic comes from the committed FETCH_SIZE / WRITE_SIZE summary, scaled by
+    # its copy calibration, and only while the kernel sources hash to the recorded value
+    # and the workload and tile side are the profiled ones
+    sys.path.insert(0, ROOT)
+    import bench
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_batched.txt").write_text(
+        "# a summary\ncsrc_sha1: 0123456789abcdef\nworkload: batched\ntile: 16\n"
+        "fetch_scale: 2.0\nwrite_scale: 1.0\ndecode_bwd.fetch_kb: 1000\ndecode_bwd.write_kb: 300\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "csrc_sha1", lambda: "0123456789abcdef")
+    assert bench.measured_traffic("decode_bwd", "batched", 16) == 1000 * 1024 * 2 + 300 * 1024
+    assert bench.measured_traffic("raster_fwd", "batched", 16) is None      # not in the summary
+    assert bench.measured_traffic("decode_bwd", "large", 16) is None        # another workload
+    assert bench.measured_traffic("decode_bwd", "batched", 8) is None       # another tile side
+    monkeypatch.setattr(bench, "csrc_sha1", lambda: "fedcba9876543210")
+    assert bench.measured_traffic("decode_bwd", "batched", 16) is None      # the kernels changed
+
+
+def test_bench_source_hash_follows_the_kernel_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.csrc_sha1()
+    assert re.fullmatch(r"[0-9a-f]{16}", h) and bench.csrc_sha1() == h
+
+
 def test_generators_are_deterministic_and_shaped():
     from paper_2603_27151_amd import workloads as W
     a, b = W.tiny(), W.tiny()
