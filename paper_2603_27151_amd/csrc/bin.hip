@@ -7,10 +7,10 @@
 // scan:    exclusive scan of the per-tile counts -> per-tile list offsets.
 // scatter: per (view, triangle): writes (zmin << 32 | tri) into the list of
 //          every tile its bounding box touches.
-// sort:    sorts each tile's list ascending (a wave ranks a short list; a
-//          workgroup sorts a long one bitonic in LDS, in blocks of kSortBlock
-//          entries), so that the raster can walk triangles front to back and
-//          stop early.
+// sort:    sorts each tile's list ascending (a wave sorts a short list
+//          bitonic in registers; a workgroup sorts a long one bitonic in LDS,
+//          in blocks of kSortBlock entries), so that the raster can walk
+//          triangles front to back and stop early.
 #include "internal.hpp"
 
 namespace soup {
@@ -168,41 +168,58 @@ __global__ __launch_bounds__(256) void scatter_kernel(const ViewDesc* __restrict
     }
 }
 
-// Rank sort of a short list by one wave: every key is distinct (its low half
-// is the triangle, listed once per tile), so entry i belongs at position
-// #{j : key_j < key_i}. R = entries per lane (n <= 64 R).
+// Bitonic sort of a short list by one wave, held in registers: entry e =
+// 64 r + lane is register r of its lane (R = entries per lane, n <= 64 R; the
+// slots past n hold the largest key and stay at the end). A compare-exchange
+// at distance j pairs e with e ^ j: between lanes for j < 64, between two
+// registers of one lane for j >= 64. Entry e keeps the smaller key when it is
+// the lower of its pair in an ascending run (e & k == 0) or the upper of its
+// pair in a descending one.
 template <int R>
-__device__ __forceinline__ void wave_rank_sort(uint64_t* __restrict__ list, int n) {
+__device__ __forceinline__ void wave_bitonic_sort(uint64_t* __restrict__ list, int n) {
     const int lane = lane_id();
-    uint64_t k[R];
-    int rank[R];
+    constexpr int N = 64 * R;
+    uint64_t v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        k[r] = 64 * r + lane < n ? list[64 * r + lane] : kBgKey;
-        rank[r] = 0;
-    }
+    for (int r = 0; r < R; ++r) v[r] = 64 * r + lane < n ? list[64 * r + lane] : kBgKey;
 #pragma unroll
-    for (int r2 = 0; r2 < R; ++r2) {
-        const int cnt = min(64, n - 64 * r2);
-        for (int l = 0; l < cnt; ++l) {
-            const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(k[r2]), l));
-            const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(k[r2] >> 32), l));
-            const uint64_t kj = (static_cast<uint64_t>(hi) << 32) | lo;
+    for (int k = 2; k <= N; k <<= 1) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) rank[r] += kj < k[r] ? 1 : 0;
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int jr = j >> 6;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & jr) continue;   // the pair (r, r + jr), seen from its lower register
+                    const int e = 64 * r + lane;
+                    const uint64_t a = v[r], b = v[r | jr];
+                    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    const bool up = (e & k) == 0;
+                    v[r] = up ? lo : hi;
+                    v[r | jr] = up ? hi : lo;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int e = 64 * r + lane;
+                    const uint64_t b = static_cast<uint64_t>(__shfl_xor(static_cast<long long>(v[r]), j, 64));
+                    const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+                    const uint64_t a = v[r];
+                    v[r] = keep_min ? (a < b ? a : b) : (a < b ? b : a);
+                }
+            }
         }
     }
-    // every read above has completed before these writes (the ranks depend on all of them)
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        if (64 * r + lane < n) list[rank[r]] = k[r];
+        if (64 * r + lane < n) list[64 * r + lane] = v[r];
 }
 
 constexpr int kWaveSortMax = 256;   // longest list sorted by one wave
 
 // Workgroup b owns tiles b + i * gridDim.x, i = 0..3 (strided, so that the
 // long lists of a crowded screen region spread over many workgroups). A list
-// of at most kWaveSortMax entries is rank-sorted by the wave of its tile;
+// of at most kWaveSortMax entries is sorted by the wave of its tile;
 // longer lists are then sorted by the whole workgroup, bitonic in LDS, in
 // blocks of kSortBlock.
 __global__ __launch_bounds__(256) void sort_kernel(const int64_t* __restrict__ tile_start, int64_t n_tiles,
@@ -215,9 +232,9 @@ __global__ __launch_bounds__(256) void sort_kernel(const int64_t* __restrict__ t
         if (tile < n_tiles) {
             const int64_t beg = tile_start[tile];
             const int n = static_cast<int>(min<int64_t>(tile_start[tile + 1] - beg, kWaveSortMax + 1));
-            if (n > 1 && n <= 64) wave_rank_sort<1>(entries + beg, n);
-            else if (n > 64 && n <= 128) wave_rank_sort<2>(entries + beg, n);
-            else if (n > 128 && n <= kWaveSortMax) wave_rank_sort<4>(entries + beg, n);
+            if (n > 1 && n <= 64) wave_bitonic_sort<1>(entries + beg, n);
+            else if (n > 64 && n <= 128) wave_bitonic_sort<2>(entries + beg, n);
+            else if (n > 128 && n <= kWaveSortMax) wave_bitonic_sort<4>(entries + beg, n);
         }
     }
     for (int i = 0; i < 4; ++i) {
