@@ -227,6 +227,25 @@ def test_tile_list_longer_than_sort_block():
         _fwd_bwd_case(wl, tile=tile, check_bwd=(tile == 16))
 
 
+@pytest.mark.parametrize("T", [63, 64, 65, 127, 128, 129, 255, 256, 257])
+def test_tile_lists_at_the_wave_sort_sizes(T):
+    """T large triangles cover every pixel of a 32x32 view, so every tile list
+    holds exactly T entries: the sizes around the one-wave sorts' 64, 128 and
+    256 entries and the workgroup sort past them. With a low opacity every pixel
+    walks deep into its list, and its early exit trusts the sorted order."""
+    wl = W.tiny()
+    rng = np.random.default_rng(4000 + T)
+    centres = W.uniform_ball(rng, T, 0.5)
+    ang = rng.uniform(0.0, 2.0 * np.pi, T)[:, None] + np.array([0.0, 2.0 * np.pi / 3.0, 4.0 * np.pi / 3.0])
+    verts = np.stack([4.0 * np.cos(ang), 4.0 * np.sin(ang), rng.uniform(-0.2, 0.2, (T, 3))], axis=2)
+    verts = (verts + centres[:, None, :]).astype(np.float32)
+    wl.scene = W.random_scene(rng, verts, 4, 8, [8, 16, 4])
+    wl.scene.mlp[-1] = -3.0          # opacity bias: about one fragment in twenty passes
+    wl.views = [W.View(32, 32, 5, W.view_proj((0.0, 0.0, 3.0), 32, 32))]
+    wl.targets = None
+    _fwd_bwd_case(wl, tile=16, check_bwd=(T in (64, 257)))
+
+
 def test_empty_and_culled_scenes():
     R = _raster()
     wl = W.tiny()
