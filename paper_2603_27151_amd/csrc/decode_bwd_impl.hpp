@@ -433,8 +433,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
             gather(0);
             // While a wave runs its chains of products it issues ahead of the other
             // wave of its SIMD, whose LDS and VALU work then fills the gaps between
-            // them (decode 2.96 -> 2.92 ms); the default priority returns after the MLP.
-            __builtin_amdgcn_s_setprio(1);
+            // them: priority 2 for the MLP, 1 for the grid adds, the default for the
+            // vertex chain and the record loads (decode 2.95 -> 2.91 ms).
+            __builtin_amdgcn_s_setprio(2);
             for (int nb = 0; nb < 4; ++nb) {   // fragment 16 nb + col (lane 16 nb + col holds its record)
                 // inputs, unit-major: channels 16 cb + 4 grp .. + 3 (an empty lane's
                 // weights are zero; channels past C meet zero weights in layer 0)
@@ -719,6 +720,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void d
                                      static_cast<double>(vd.M[12 + k]) * gc3;
             }
         }
+        __builtin_amdgcn_s_setprio(1);
         // --- sum into the wave's grid, one run of equal triangles at a time ---
         // The feature gradients are staged (row = fragment) and added one
         // fragment per step with the wave's lanes spread over (corner,

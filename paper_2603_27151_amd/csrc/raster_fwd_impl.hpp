@@ -139,8 +139,9 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
     if (lane == 0) next = atomicAdd(a.work, 1u);
     // The walk's scan, coverage and fragment steps wait on memory and LDS; at a
     // raised priority they issue ahead of the other waves' decode batches, long
-    // runs of VALU work that then fill the gaps (a batch drops back to the
-    // default priority; forward 2.26 -> 2.23 ms)
+    // runs of VALU work that then fill the gaps: priority 2 for the scan and the
+    // fragment step, 1 for the coverage step, the default for a decode batch
+    // (forward 2.26 -> 2.22 ms)
     __builtin_amdgcn_s_setprio(1);
 
     for (;;) {   // persistent: regions from a counter
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             continue;
         }
         if (rnd < n_rnd) {
+            __builtin_amdgcn_s_setprio(2);
             // ---- fragments of 64 covered (pair, pixel) combinations, in slice order:
             // lane = combination ----
             const int base = 64 * rnd;
@@ -381,6 +383,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             continue;
         }
         if (pn >= 64 || (listed && pn > 0)) {
+            __builtin_amdgcn_s_setprio(1);
             // ---- coverage of up to 64 waiting pairs: lane = (triangle, block) ----
             const int n = pn < 64 ? pn : 64;
             cent = kBgKey;
@@ -486,6 +489,7 @@ __global__ __launch_bounds__(64, 3) void raster_fwd_kernel(RasterArgs a) {
             wave_fence();
             continue;
         }
+        __builtin_amdgcn_s_setprio(2);
         // ---- scan the next 64 list entries: lane = entry ----
         if (c0 >= end || remaining_min(a.entries, beg, c0, end) >= wmax) {
             listed = true;
